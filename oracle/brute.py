@@ -1,0 +1,205 @@
+"""NumPy brute force for tiny problems: the oracle's own check.
+
+Test infrastructure only.  Written independently of ``sisso_oracle.c``: it
+builds every feature as an expression string and a NumPy value vector level
+by level (Sec. 2.1, eq. feature-exp), ranks all of them with
+``numpy.corrcoef`` (Sec. 2.2, eq. sis-weight / sis-method), and fits every
+t-subset with ``numpy.linalg.lstsq`` on [1, F_T] (Sec. 2.3, eq. residual).
+It follows the same written readings as the oracle (numbering, validity,
+duplicate classes, tie rules) so the two can be compared id by id.
+"""
+from __future__ import annotations
+
+import itertools
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+_UNARY = {
+    "sq": (lambda a: a * a, lambda a: True, "({})^2"),
+    "cube": (lambda a: a * a * a, lambda a: True, "({})^3"),
+    "sqrt": (np.sqrt, lambda a: np.all(a >= 0), "sqrt({})"),
+    "inv": (lambda a: 1.0 / a, lambda a: np.all(a != 0), "1/({})"),
+    "exp": (np.exp, lambda a: True, "exp({})"),
+    "nexp": (lambda a: np.exp(-a), lambda a: True, "exp(-{})"),
+    "log": (np.log, lambda a: np.all(a > 0), "ln({})"),
+    "sin": (np.sin, lambda a: True, "sin({})"),
+}
+_BINARY = {"add": "+", "sub": "-", "mul": "*", "div": "/"}
+
+
+def _ok(v: np.ndarray) -> bool:
+    if not np.all(np.isfinite(v)) or np.any(np.abs(v) > 1e15):
+        return False
+    sd = np.sqrt(np.mean((v - v.mean()) ** 2))
+    return bool(sd != 0 and sd > 1e-6 * abs(v.mean()))
+
+
+def _bin(op, a, b):
+    with np.errstate(all="ignore"):
+        if op == "add":
+            return a + b, True
+        if op == "sub":
+            return a - b, True
+        if op == "mul":
+            return a * b, True
+        return a / b, bool(np.all(b != 0))
+
+
+def _slots(binary):
+    out = []
+    for op in binary:
+        out.append((op, False))
+        if op == "div":
+            out.append((op, True))
+    return out
+
+
+def enumerate_space(X: np.ndarray, unary: Sequence[str], binary: Sequence[str], levels: int,
+                    rect: bool = False):
+    """All features in canonical order: list of (expr, values, valid)."""
+    n, d = X.shape
+    feats: List[Tuple[str, np.ndarray, bool]] = []
+    for i in range(d):
+        v = X[:, i].astype(np.float64)
+        feats.append((f"x{i}", v, _ok(v)))
+    sizes = [0, d]            # P_{-1}, P_0
+    slots = _slots(binary)
+
+    def unary_feat(a, op):
+        fn, dom, fmt = _UNARY[op]
+        ea, va, oka = feats[a]
+        if not oka:
+            return (fmt.format(ea), np.full(n, np.nan), False)
+        with np.errstate(all="ignore"):
+            if not dom(va):
+                return (fmt.format(ea), np.full(n, np.nan), False)
+            v = fn(va)
+        return (fmt.format(ea), v, _ok(v))
+
+    def binary_feat(l, r, op):
+        el, vl, okl = feats[l]
+        er, vr, okr = feats[r]
+        e = f"({el}{_BINARY[op]}{er})"
+        if not (okl and okr):
+            return (e, np.full(n, np.nan), False)
+        v, dom = _bin(op, vl, vr)
+        if not dom:
+            return (e, np.full(n, np.nan), False)
+        return (e, v, _ok(v))
+
+    for _ in range(levels):
+        lo, hi = sizes[-2], sizes[-1]
+        new = []
+        for a in range(lo, hi):
+            for op in unary:
+                new.append(unary_feat(a, op))
+        for j in range(lo, hi):
+            for i in range(j):
+                for op, rev in slots:
+                    new.append(binary_feat(i, j, op) if rev else binary_feat(j, i, op))
+        feats.extend(new)
+        sizes.append(len(feats))
+    if rect:
+        lo, hi = sizes[-2], sizes[-1]
+        new = []
+        for u in range(lo, hi):
+            for op in unary:
+                new.append(unary_feat(u, op))
+        for u in range(lo, hi):
+            for v in range(0, lo):
+                for op, rev in slots:
+                    new.append(binary_feat(v, u, op) if rev else binary_feat(u, v, op))
+        feats.extend(new)
+    return feats
+
+
+def abs_corr(f, r) -> float:
+    return float(abs(np.corrcoef(f, r)[0, 1]))
+
+
+def sis(feats, r, keep: int, exclude=()):
+    ex = set(int(e) for e in exclude)
+    cand = [(abs_corr(v, r), i) for i, (_, v, ok) in enumerate(feats) if ok and i not in ex]
+    cand.sort(key=lambda t: (-t[0], t[1]))
+    cand = cand[:keep]
+    return np.array([i for _, i in cand], dtype=np.int64), np.array([s for s, _ in cand])
+
+
+def dedup(feats, list_ids, list_scores, prev, k):
+    ids = list(prev) + list(list_ids)
+    m = len(ids)
+    label = list(range(m))
+
+    def find(a):
+        while label[a] != a:
+            a = label[a]
+        return a
+
+    for i in range(m):
+        for j in range(i + 1, m):
+            if 1.0 - abs_corr(feats[ids[i]][1], feats[ids[j]][1]) <= 1e-9:
+                a, b = find(i), find(j)
+                if a != b:
+                    label[max(a, b)] = min(a, b)
+    comps = {}
+    for i in range(m):
+        comps.setdefault(find(i), []).append(i)
+    classes = []
+    for members in comps.values():
+        if any(i < len(prev) for i in members):
+            continue
+        rep = min(ids[i] for i in members)
+        sc = max(list_scores[i - len(prev)] for i in members)
+        classes.append((sc, rep))
+    classes.sort(key=lambda t: (-t[0], t[1]))
+    return [rep for _, rep in classes[:k]], [sc for sc, _ in classes[:k]], len(classes)
+
+
+def l0(F: np.ndarray, y: np.ndarray, D: int):
+    """All D-subsets of the columns of F with lstsq on [1, F_T].  Tie band
+    1e-12 * S_yy, lexicographically first tuple; near-singular tuples (the
+    smallest eigenvalue of their correlation matrix <= 1e-10) skipped."""
+    n, m = F.shape
+    syy = float(np.sum((y - y.mean()) ** 2))
+    res = []
+    for tup in itertools.combinations(range(m), D):
+        Ft = F[:, tup]
+        Z = (Ft - Ft.mean(0)) / np.sqrt(np.sum((Ft - Ft.mean(0)) ** 2, axis=0))
+        if np.min(np.linalg.eigvalsh(Z.T @ Z)) <= 1e-10:
+            continue
+        A = np.column_stack([np.ones(n), Ft])
+        c, *_ = np.linalg.lstsq(A, y, rcond=None)
+        sse = float(np.sum((y - A @ c) ** 2))
+        res.append((sse, tup, c))
+    smin = min(r[0] for r in res)
+    for sse, tup, c in res:                       # combinations are lexicographic
+        if sse <= smin + 1e-12 * syy:
+            return tup, sse, c, len(res)
+    raise AssertionError
+
+
+def fit(X, y, unary, binary, levels, rect, k, dmax, keep0=None):
+    """Brute-force SISSO loop (same readings as the oracle)."""
+    feats = enumerate_space(X, unary, binary, levels, rect)
+    keep0 = 2 * k if keep0 is None else keep0
+    sub: List[int] = []
+    r = np.asarray(y, dtype=np.float64).copy()
+    out = []
+    for t in range(1, dmax + 1):
+        keep = keep0
+        while True:
+            li, ls = sis(feats, r, keep, exclude=sub)
+            new, nsc, ncls = dedup(feats, li, ls, sub, k)
+            if len(new) >= k or len(li) < keep or keep >= 4096:
+                break
+            keep = min(2 * keep, 4096)
+        sub = sub + list(new)
+        order = sorted(sub)
+        F = np.column_stack([feats[i][1] for i in order])
+        tup, sse, c, nfit = l0(F, y, t)
+        best = [order[i] for i in tup]
+        r = y - np.column_stack([np.ones(len(y)), F[:, list(tup)]]) @ c
+        out.append(dict(list_ids=li, list_scores=ls, sub_ids=np.array(sub), best_ids=best,
+                        coef=c, sse=sse, exprs=[feats[i][0] for i in best]))
+    return out

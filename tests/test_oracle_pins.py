@@ -1,0 +1,328 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the
+paper's worked expansion example, closed-form counts and the paper's count
+bound, textbook correlation and least squares (NumPy), invariances, and an
+independently written NumPy brute force on tiny inputs.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brute as B
+from oracle import oracle as O
+from paper_2410_01752_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------- expansion
+
+def test_paper_worked_example_counts_and_values():
+    """Sec. 2.1 worked example: d = 2, O = {I, +, x} -> |phi_1| = 4,
+    |phi_2| = 14, and the 10 new features are exactly the paper's list."""
+    sp = O.Space(2, [], ["add", "mul"], 2)
+    assert (sp.pool(0), sp.pool(1), sp.pool(2)) == (2, 4, 14)
+    # the paper's bound: d_l <= m_u d_{l-1} + (m_bs/2 + m_bns) d_{l-1}(d_{l-1}-1)
+    mu, mbs, mbns = 1, 2, 0         # identity counted as the unary operator
+    b1 = mu * 2 + (mbs / 2 + mbns) * 2 * 1
+    b2 = mu * 4 + (mbs / 2 + mbns) * 4 * 3
+    assert (b1, b2) == (4, 16)
+    assert sp.pool(1) == b1 and sp.pool(2) < b2
+    lines = [l.strip() for l in open(os.path.join(GOLDEN, "paper_example_rung2.txt"))
+             if l.strip() and not l.startswith("#")]
+    assert len(lines) == 10
+    rng = np.random.default_rng(0)
+    X = rng.uniform(1.0, 2.0, size=(7, 2))
+    x1, x2 = X[:, 0], X[:, 1]
+    paper = sorted(tuple(np.round(eval(e, {"x1": x1, "x2": x2}), 12)) for e in lines)
+    V, ok = sp.eval(X, range(4, 14))
+    assert ok.all()
+    ours = sorted(tuple(np.round(V[:, i], 12)) for i in range(10))
+    assert ours == paper
+    # phi_1 = {x1, x2, x1 + x2, x1 x2}
+    V1, _ = sp.eval(X, range(4))
+    got = sorted(tuple(np.round(V1[:, i], 12)) for i in range(4))
+    want = sorted(tuple(np.round(v, 12)) for v in (x1, x2, x1 + x2, x1 * x2))
+    assert got == want
+
+
+def _closed_form(d, U, slots, levels, rect):
+    p = [0, d]                        # p_{-1}, p_0
+    for _ in range(levels):
+        lo, hi = p[-2], p[-1]
+        p.append(hi + U * (hi - lo) + slots * (math.comb(hi, 2) - math.comb(lo, 2)))
+    total = p[-1]
+    if rect:
+        nl = p[-1] - p[-2]
+        total += U * nl + slots * nl * p[-2]
+    return p[1:], total
+
+
+@pytest.mark.parametrize("d,ops,levels,rect", [
+    (5, I.OPS1, 2, False), (10, I.FULL, 2, False), (20, I.OPS1, 2, True),
+    (12, I.FULL, 2, False), (30, I.OPS1, 2, True), (3, I.OPS1, 3, False),
+    (4, {"unary": [], "binary": ["mul"]}, 2, True), (6, {"unary": ["log"], "binary": []}, 2, False)])
+def test_counts_closed_form_and_bound(d, ops, levels, rect):
+    sp = O.Space(d, ops["unary"], ops["binary"], levels, rect)
+    U = len(ops["unary"])
+    slots = sum(2 if b == "div" else 1 for b in ops["binary"])
+    pools, total = _closed_form(d, U, slots, levels, rect)
+    assert [sp.pool(l) for l in range(levels + 1)] == pools
+    assert sp.total == total
+    mbs = sum(b in ("add", "mul") for b in ops["binary"])
+    mbns = sum(b in ("sub", "div") for b in ops["binary"])
+    for l in range(1, levels + 1):
+        prev = sp.pool(l - 1)
+        assert sp.pool(l) <= (U + 1) * prev + (mbs / 2 + mbns) * prev * (prev - 1)
+
+
+def test_sizes_of_the_workloads():
+    # sizes quoted for the configurations (rung-3 slice ~1.4e10 candidates)
+    assert O.Space(20, I.OPS1["unary"], I.OPS1["binary"], 2, True).total == 13_667_146_300
+    assert O.Space(10, I.FULL["unary"], I.FULL["binary"], 2).total == 249_805
+
+
+def test_decode_structure_tiny():
+    ops = I.OPS1
+    sp = O.Space(3, ops["unary"], ops["binary"], 2, True)
+    p0, p1, p2 = sp.pool(0), sp.pool(1), sp.pool(2)
+    seen = set()
+    for fid in range(sp.total):
+        op, l, r = sp.decode(fid)
+        key = (op, l, r) if op >= 0 else ("x", fid)
+        assert key not in seen
+        seen.add(key)
+        if fid < p0:
+            assert op == -1
+            continue
+        lev = 1 if fid < p1 else 2 if fid < p2 else 3
+        lo_new = {1: 0, 2: p0, 3: p1}[lev]
+        hi_new = {1: p0, 2: p1, 3: p2}[lev]
+        if op >= 4:                                  # unary on a newest operand
+            assert lo_new <= l < hi_new and r == -1
+        else:
+            newer, older = (l, r) if (op != 3 or l > r) else (r, l)
+            assert lo_new <= newer < hi_new and older < newer
+            if lev == 3:
+                assert older < p1
+    assert len(seen) == sp.total
+
+
+def test_values_match_brute_force_rung3_slice():
+    p = I.tiny(3, n=9, d=3)
+    feats = B.enumerate_space(p.X, p.unary, p.binary, 2, True)
+    sp = O.Space(3, p.unary, p.binary, 2, True)
+    assert len(feats) == sp.total
+    V, ok = sp.eval(p.X, np.arange(sp.total))
+    okb = np.array([f[2] for f in feats])
+    assert np.array_equal(ok, okb)
+    Vb = np.column_stack([f[1] for f in feats])
+    assert np.allclose(V[:, ok], Vb[:, ok], rtol=1e-13, atol=0)
+
+
+def test_validity_rules():
+    """Domain violations, non-finite or > 1e15 values and near-constant
+    features are invalid, and so are their children."""
+    X = np.array([[1.0, -1.0, 3.0, 1e8], [2.0, 2.0, 3.0, 2e8], [4.0, 0.5, 3.0, 3e8],
+                  [3.0, 1.5, 3.0, 4e8]])
+    sp = O.Space(4, ["sqrt", "inv", "log", "cube"], ["div", "mul"], 1)
+    V, ok = sp.eval(X, range(sp.total))
+    names = {sp.decode(fid): bool(ok[fid]) for fid in range(sp.total)}
+    assert ok[0] and ok[1] and not ok[2] and ok[3]          # x2 is constant
+    assert not names[(6, 1, -1)]                            # sqrt(x1), x1 < 0
+    assert not names[(10, 1, -1)]                           # log(x1), x1 <= 0
+    assert names[(6, 0, -1)] and names[(7, 1, -1)]          # sqrt(x0), 1/x1 fine
+    assert not names[(5, 3, -1)]                            # (x3)^3 > 1e15
+    assert names[(5, 0, -1)]
+    assert not names[(2, 2, 0)]                             # constant operand
+    assert names[(2, 3, 1)] and names[(3, 3, 1)]            # x3*x1, x3/x1
+    # a zero divisor makes the quotient invalid
+    X2 = X.copy(); X2[2, 1] = 0.0
+    V2, ok2 = sp.eval(X2, range(sp.total))
+    names2 = {sp.decode(fid): bool(ok2[fid]) for fid in range(sp.total)}
+    assert not names2[(3, 3, 1)] and names2[(3, 1, 3)] and not names2[(7, 1, -1)]
+
+
+# -------------------------------------------------------------------- SIS
+
+def test_score_is_abs_pearson_and_invariant():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        f = rng.lognormal(size=40)
+        r = rng.normal(size=40) + 0.3 * f
+        s = O.abs_corr(f, r)
+        assert abs(s - abs(np.corrcoef(f, r)[0, 1])) < 1e-14
+        a, b, c, e = rng.normal(size=4)
+        assert abs(O.abs_corr(a * f + b, r) - s) < 1e-12
+        assert abs(O.abs_corr(f, c * r + e) - s) < 1e-12
+        perm = rng.permutation(40)
+        assert abs(O.abs_corr(f[perm], r[perm]) - s) < 1e-12
+    assert abs(O.abs_corr(f, f) - 1.0) < 1e-15
+
+
+def test_sis_matches_full_sort_and_invariances():
+    p = I.tiny(7, n=15, d=3)
+    feats = B.enumerate_space(p.X, p.unary, p.binary, 2)
+    sp = O.Space(3, p.unary, p.binary, 2)
+    ids, sc = sp.sis(p.X, p.y, 40)
+    bi, bs = B.sis(feats, p.y, 40)
+    assert np.allclose(sc, bs, atol=1e-12)
+    # ids agree except for the order of exact-value duplicates (equal scores)
+    for a, b, s in zip(ids, bi, sc):
+        if a != b:
+            assert abs(sp.score_range(p.X, p.y, a, a + 1)[0] -
+                       sp.score_range(p.X, p.y, b, b + 1)[0]) < 1e-12
+    ids2, sc2 = sp.sis(p.X, -2.5 * p.y + 7.0, 40)
+    assert np.allclose(sc2, sc, atol=1e-12)
+    perm = np.random.default_rng(1).permutation(15)
+    ids3, sc3 = sp.sis(p.X[perm], p.y[perm], 40)
+    assert np.allclose(sc3, sc, atol=1e-12)
+    # exclusion removes exactly the excluded ids
+    ex = ids[:5]
+    ids4, _ = sp.sis(p.X, p.y, 40, exclude=ex)
+    assert not set(ex) & set(ids4)
+    assert list(ids4[:30]) == [i for i in ids if i not in set(ex)][:30]
+
+
+def test_dedup_classes_explicit_duplicates():
+    """(x0 x1)/x2 and x0 (x1/x2) are the same feature; (x0 + x1) - x1 is x0."""
+    p = I.tiny(11, n=20, d=3)
+    sp = O.Space(3, [], ["add", "sub", "mul", "div"], 2)
+    X = p.X
+    x0, x1, x2 = X[:, 0], X[:, 1], X[:, 2]
+    V, ok = sp.eval(X, range(sp.total))
+    def find(v):
+        return [i for i in range(sp.total) if ok[i] and np.allclose(V[:, i], v, rtol=1e-12)]
+    dup_a = find(x0 * x1 / x2)
+    dup_b = find(x0)
+    assert len(dup_a) >= 2 and len(dup_b) >= 2
+    target = 2.0 * x0 * x1 / x2 + 0.1 * np.sin(np.arange(20))
+    ids, sc = sp.sis(X, target, 60)
+    new, nsc, ncls = sp.dedup(X, ids, sc, [], 10)
+    nb, nbs, nbc = B.dedup(B.enumerate_space(X, [], ["add", "sub", "mul", "div"], 2), ids, sc, [], 10)
+    assert list(new) == list(nb) and ncls == nbc
+    assert new[0] == min(i for i in dup_a if i in set(ids))
+    # a previous-subspace member drops its whole class
+    new2, _, _ = sp.dedup(X, ids, sc, [dup_a[-1]], 10)
+    assert not set(new2) & set(dup_a)
+
+
+# --------------------------------------------------------------------- SO
+
+def _rand_F(seed, n=30, m=8):
+    rng = np.random.default_rng(seed)
+    F = rng.lognormal(size=(n, m))
+    y = 1.5 * F[:, 2] - 0.7 * F[:, 5] + 0.2 * rng.normal(size=n)
+    return F, y
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_l0_matches_lstsq_brute_force(D):
+    for seed in range(4):
+        F, y = _rand_F(seed)
+        res = O.l0(F, y, D)
+        tup, sse, c, nfit = B.l0(F, y, D)
+        assert tuple(res.best) == tup
+        assert abs(res.sse - sse) <= 1e-10 * max(sse, 1e-300) + 1e-12
+        assert np.allclose(res.coef, c, rtol=1e-9, atol=1e-10)
+        assert res.n_tuples == math.comb(F.shape[1], D)
+
+
+def test_l0_closed_forms_and_invariants():
+    F, y = _rand_F(9, n=40, m=10)
+    syy = np.sum((y - y.mean()) ** 2)
+    r1 = O.l0(F, y, 1)
+    rho = max(abs(np.corrcoef(F[:, j], y)[0, 1]) for j in range(10))
+    assert abs(r1.sse - syy * (1 - rho ** 2)) < 1e-10 * syy
+    prev = np.inf
+    for D in (1, 2, 3, 4):
+        r = O.l0(F, y, D)
+        assert r.sse <= prev + 1e-12 * syy
+        prev = r.sse
+        # residual orthogonal to 1 and to every selected column
+        res = y - r.coef[0] - F[:, r.best] @ r.coef[1:]
+        assert abs(res.sum()) < 1e-9 * np.abs(y).sum()
+        for j in r.best:
+            assert abs(res @ (F[:, j] - F[:, j].mean())) < 1e-8 * np.linalg.norm(F[:, j]) * np.linalg.norm(y)
+        assert abs(np.sum(res ** 2) - r.sse) < 1e-9 * syy
+
+
+def test_l0_noise_free_planted_exact():
+    rng = np.random.default_rng(2)
+    F = rng.uniform(1, 3, size=(25, 9))
+    y = 4.0 - 2.0 * F[:, 1] + 3.0 * F[:, 7]
+    r = O.l0(F, y, 2)
+    syy = np.sum((y - y.mean()) ** 2)
+    assert list(r.best) == [1, 7]
+    assert r.sse <= 1e-24 * syy * 25
+    assert np.allclose(r.coef, [4.0, -2.0, 3.0], rtol=1e-10, atol=1e-10)
+
+
+def test_l0_singular_tuples_skipped():
+    rng = np.random.default_rng(4)
+    a, b = rng.uniform(1, 2, size=(2, 20))
+    F = np.column_stack([a, b, a + b, rng.uniform(1, 2, size=20)])
+    y = a + 0.5 * F[:, 3] + 0.01 * rng.normal(size=20)
+    r = O.l0(F, y, 3)
+    assert r.n_singular == 1                     # (a, b, a+b)
+    tup, sse, c, nfit = B.l0(F, y, 3)
+    assert tuple(r.best) == tup
+
+
+# --------------------------------------------------------------- pipeline
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_fit_matches_brute_force(seed):
+    p = I.tiny(seed, n=12, d=3, k=5, dmax=3)
+    ro = O.fit(p.X, p.y, p.unary, p.binary, 2, False, p.k, p.dmax)
+    rb = B.fit(p.X, p.y, p.unary, p.binary, 2, False, p.k, p.dmax)
+    for a, b in zip(ro, rb):
+        assert list(a.sub_ids) == list(b["sub_ids"])
+        assert list(a.best_ids) == list(b["best_ids"])
+        assert abs(a.sse - b["sse"]) <= 1e-10 * b["sse"] + 1e-14
+        assert np.allclose(a.list_scores, b["list_scores"], atol=1e-12)
+
+
+def test_fit_rung3_slice_matches_brute_force():
+    p = I.tiny(21, n=10, d=2, k=4, dmax=2)
+    ro = O.fit(p.X, p.y, p.unary, p.binary, 2, True, p.k, p.dmax)
+    rb = B.fit(p.X, p.y, p.unary, p.binary, 2, True, p.k, p.dmax)
+    for a, b in zip(ro, rb):
+        assert list(a.sub_ids) == list(b["sub_ids"])
+        assert list(a.best_ids) == list(b["best_ids"])
+
+
+def test_c1_recovers_planted_terms():
+    """y = 3 x0 x1/x2 + 0.5 x3^2 + N(0, 0.01^2): the 2-term model is the
+    planted pair with coefficients 3 and 0.5 and RMSE at the noise level."""
+    p = I.config1()
+    ro = O.fit(p.X, p.y, p.unary, p.binary, 2, False, p.k, p.dmax)
+    st = ro[1]
+    sp = O.Space(5, p.unary, p.binary, 2)
+    V, _ = sp.eval(p.X, st.best_ids)
+    planted = [I.eval_tree(t, p.X) for t in p.planted]
+    # each selected feature equals one planted term (up to rounding)
+    match = {}
+    for a in range(2):
+        for b in range(2):
+            if abs(np.corrcoef(V[:, a], planted[b])[0, 1]) > 1 - 1e-12:
+                match[a] = b
+    assert sorted(match.values()) == [0, 1]
+    coefs = {match[a]: st.coef[1 + a] for a in range(2)}
+    assert abs(coefs[0] - 3.0) < 0.01 and abs(coefs[1] - 0.5) < 0.01
+    assert 0.005 < st.rmse < 0.015
+    assert ro[0].sse >= st.sse
+
+
+def test_noise_free_single_term_recovered_exactly():
+    rng = np.random.default_rng(8)
+    X = rng.uniform(0.5, 5.0, size=(30, 4))
+    y = 2.5 * X[:, 0] * X[:, 3] / X[:, 1] - 1.0
+    ro = O.fit(X, y, I.OPS1["unary"], I.OPS1["binary"], 2, False, 10, 1)
+    syy = np.sum((y - y.mean()) ** 2)
+    assert ro[0].sse <= 1e-26 * syy * 30
+    assert abs(ro[0].coef[1] - 2.5) < 1e-10 and abs(ro[0].coef[0] + 1.0) < 1e-9
