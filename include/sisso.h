@@ -1,0 +1,300 @@
+/*
+ * sisso.h -- C ABI of the SISSO hot path on MI355X (gfx950).
+ *
+ * The library implements the data-parallel core of SISSO (sure independence
+ * screening + sparsifying operator), following Sec. 2 of "TorchSISSO"
+ * (arXiv 2410.01752):
+ *
+ *   feature expansion   Sec. 2.1, eq. feature-exp  -> sisso_materialize_pools,
+ *                                                     sisso_materialize_ids
+ *   SIS screening       Sec. 2.2, eq. sis-weight,
+ *                       eq. sis-method              -> sisso_prepare_residual,
+ *                                                     sisso_expand_score,
+ *                                                     sisso_topk
+ *   subspace update     Sec. 2.3, eq. subspace-expansion
+ *                       (duplicate features, Sec. 2.1 remark that some
+ *                       combinations are not unique) -> sisso_subspace_update
+ *   SO (l0 search)      Sec. 2.3, eq. residual      -> sisso_l0_search
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers unless marked [host].  Device
+ *     arrays are column-major: element (s, j) of an n x m matrix with leading
+ *     dimension ld is at base[j*ld + s]; ld >= n.
+ *   - The caller owns every buffer, the workspace and the stream.  The
+ *     library allocates no device memory inside these calls and keeps no
+ *     pointer after the call's work on `stream` completes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue asynchronous work and return without synchronising;
+ *     outputs are valid once the stream passes the call.
+ *   - Every call validates its arguments on the host before enqueueing
+ *     anything and returns a status; it never aborts, throws or prints.
+ *     A launch failure reported by the HIP runtime returns SISSO_E_DEVICE.
+ *   - Feature ids are canonical 64-bit integers (numbering below).  Scores are
+ *     |Pearson correlation| in [0, 1].  Invalid features never appear in a
+ *     screened list.
+ *
+ * Canonical feature numbering (the "space").  P_0 = the d base features,
+ * ids 0..d-1.  Level l (1 <= l <= levels) appends N_l to the pool,
+ * P_l = P_{l-1} ++ N_l, with N_{l-1} = ids [p_{l-2}, p_{l-1}) (p_{-1} = 0):
+ *   1. for each a in N_{l-1} ascending, for each unary op in list order: op(a);
+ *   2. for each unordered pair i < j with j in N_{l-1}, ordered by (j, i),
+ *      for each binary slot: ADD, SUB, MUL give op(P[j], P[i]); DIV gives
+ *      P[j] / P[i], then P[i] / P[j].
+ * Pairs are never a feature with itself and need an operand new at the
+ * previous level, which reproduces the paper's worked example of Sec. 2.1
+ * (|phi_1| = 4, |phi_2| = 14 for d = 2 and {I, +, x}).  If `rect` is set, the
+ * SIS space adds the one-sided slice of the next level: for each u in N_L,
+ * each unary op(u); then for each u in N_L, each v in P_{L-1}, each binary
+ * slot: op(u, v) (DIV: u/v then v/u).
+ *
+ * Validity: a feature is invalid if an operand is invalid, a domain is
+ * violated (sqrt of a negative, log of a non-positive, division by zero,
+ * 1/0), a value is non-finite or exceeds 1e15 in magnitude, it is
+ * near-constant (population sd <= 1e-6 |mean|, or sd == 0), or it is a sum
+ * or difference that cancels (sd <= 1e-5 x the larger root-mean-square of
+ * its operands: an identity that is zero or constant in exact arithmetic).
+ */
+#ifndef SISSO_H
+#define SISSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SISSO_OK = 0,
+    SISSO_E_NULL = 1,        /* a required pointer is NULL                       */
+    SISSO_E_SHAPE = 2,       /* n, ld, m, d or another size is out of range       */
+    SISSO_E_RANGE = 3,       /* an id, a range or k is outside the space         */
+    SISSO_E_WORKSPACE = 4,   /* the workspace is smaller than its size query     */
+    SISSO_E_UNSUPPORTED = 5, /* a valid request this build does not implement    */
+    SISSO_E_DEVICE = 6,      /* the HIP runtime reported an error                */
+    SISSO_E_NUMERIC = 7      /* e.g. a constant residual (nothing to screen)     */
+} sisso_status;
+
+/* Operator codes.  Binary: 0..3, unary: 4..11 (exp(-x) is NEXP). */
+typedef enum {
+    SISSO_ADD = 0, SISSO_SUB = 1, SISSO_MUL = 2, SISSO_DIV = 3,
+    SISSO_SQ = 4, SISSO_CUBE = 5, SISSO_SQRT = 6, SISSO_INV = 7,
+    SISSO_EXP = 8, SISSO_NEXP = 9, SISSO_LOG = 10, SISSO_SIN = 11
+} sisso_op;
+
+#define SISSO_MAX_UNARY 8
+#define SISSO_MAX_BINARY 4
+#define SISSO_MAX_LEVELS 2
+#define SISSO_MAX_N 65536          /* samples per problem                    */
+#define SISSO_MAX_KEEP 2048        /* screened-list length per call          */
+#define SISSO_MAX_SUBSPACE 1024    /* |S_t|                                  */
+#define SISSO_MAX_D 3              /* terms per SO model                     */
+
+/* Feature space description (host struct).  Fill d, levels, rect and the
+ * operator lists, then call sisso_space_init, which validates them and fills
+ * the derived counts.  Paper: Sec. 2.1, eq. feature-exp and the count bound
+ * that follows it. */
+typedef struct {
+    int32_t d;                         /* base features, >= 1                  */
+    int32_t levels;                    /* full levels stored as pools, 1..2    */
+    int32_t rect;                      /* 1: add the one-sided next-level slice */
+    int32_t n_unary, n_binary;
+    int32_t unary[SISSO_MAX_UNARY];    /* sisso_op codes 4..11, distinct       */
+    int32_t binary[SISSO_MAX_BINARY];  /* sisso_op codes 0..3, distinct        */
+    /* filled by sisso_space_init: */
+    int32_t n_slots;                   /* binary slots per pair (DIV counts 2) */
+    int32_t slot_op[2 * SISSO_MAX_BINARY], slot_rev[2 * SISSO_MAX_BINARY];
+    int64_t pool[SISSO_MAX_LEVELS + 1];/* pool[l] = |P_l|                      */
+    int64_t rect_unary, rect_binary;   /* sizes of the slice's two blocks      */
+    int64_t total;                     /* size of the SIS space                */
+} sisso_space;
+
+/* Per pool column statistics written by sisso_materialize_pools (device,
+ * one record per column).  All values are taken from the FP64 column. */
+typedef struct {
+    float mean;      /* mean                                                   */
+    float sd;        /* population standard deviation                          */
+    float mean_rcp;  /* mean of 1/f (inf if the column has a zero)             */
+    float maxabs;    /* max |f|                                                */
+    float minabs;    /* min |f| (0 => the column has a zero)                    */
+    float minval;    /* min f                                                  */
+    float valid;     /* 1 = valid feature, 0 = invalid                         */
+    float rms;       /* root-mean-square sqrt(mean f^2)                        */
+} sisso_colstat;
+
+/* Validate a space and fill its derived fields [host].  Errors:
+ * SISSO_E_NULL, SISSO_E_SHAPE (d < 1, levels outside 1..2, rect without a
+ * level, operator lists too long or with wrong or repeated codes),
+ * SISSO_E_RANGE (total size overflows 2^62). */
+sisso_status sisso_space_init(sisso_space *space);
+
+/* Structure of feature `id` [host]: op code (-1 for a base feature) and
+ * operand ids (-1 when absent; for unary ops *right = -1).  Errors:
+ * SISSO_E_NULL, SISSO_E_RANGE (id outside [0, total)). */
+sisso_status sisso_decode(const sisso_space *space, int64_t id, int32_t *op, int64_t *left,
+                          int64_t *right);
+
+/* Evaluate the pool columns P_levels (ids [0, pool[levels])) in FP64 from X
+ * and store them rounded to FP32 with their statistics (Sec. 2.1,
+ * eq. feature-exp; step "operand pools" of the path).
+ *   X        n x d FP64, leading dim ldx >= n.
+ *   pool32   n x pool[levels] FP32 output, leading dim ld32 >= n, ld32 % 4 == 0.
+ *   pool1_64 n x pool[1] FP64 output (level-1 values, kept for FP64
+ *            re-evaluation by sisso_materialize_ids), leading dim ld64 >= n.
+ *   stats    pool[levels] records output.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE (n < 2, n > SISSO_MAX_N, bad ld). */
+sisso_status sisso_materialize_pools(const sisso_space *space, const double *X, int32_t n,
+                                     int32_t ldx, float *pool32, int64_t ld32, double *pool1_64,
+                                     int64_t ld64, sisso_colstat *stats, void *stream);
+
+/* Evaluate arbitrary features (any id of the space) in FP64 (Sec. 2.1).
+ *   pool1_64, stats  the FP64 level-1 pool and the column statistics written
+ *                    by sisso_materialize_pools (operand values and validity).
+ *   ids              count ids (device); ids outside [0, total) give invalid
+ *                    columns, so a screened list padded with sentinels is fine.
+ *   out              n x count FP64 output (leading dim ldo); invalid columns
+ *                    are filled with NaN.  valid: count int32 flags (1/0).
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE. */
+sisso_status sisso_materialize_ids(const sisso_space *space, int32_t n, const double *pool1_64,
+                                   int64_t ld64, const sisso_colstat *stats, const int64_t *ids,
+                                   int32_t count, double *out, int32_t ldo, int32_t *valid,
+                                   void *stream);
+
+/* Residual record used by the screening kernels (device, 4 doubles). */
+typedef struct {
+    double sum_r32;   /* sum of the FP32 centred residual values            */
+    double s_rr;      /* sum of squares about their mean                    */
+    double mean_r;    /* mean of the FP64 residual before centring          */
+    double n;         /* number of samples                                  */
+} sisso_resid_info;
+
+/* Centre a FP64 residual (or the target y) and round it to FP32 for
+ * screening (Sec. 2.2: SIS of the target at t = 1, of the best residual
+ * r_t* afterwards, eq. subspace-expansion).
+ *   r      n FP64 input.  r32: n FP32 output (padded samples untouched).
+ *   info   one sisso_resid_info output.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE. */
+sisso_status sisso_prepare_residual(const double *r, int32_t n, float *r32,
+                                    sisso_resid_info *info, void *stream);
+
+/* Screening precision. */
+typedef enum { SISSO_FP32 = 0, SISSO_BF16 = 1 } sisso_precision;
+
+/* Arguments of one screening pass. */
+typedef struct {
+    int32_t n;                    /* samples                                     */
+    const float *pool32;          /* pool columns (sisso_materialize_pools)      */
+    int64_t ld32;
+    const sisso_colstat *stats;   /* their statistics                            */
+    const float *r32;             /* centred FP32 residual (sisso_prepare_residual) */
+    const sisso_resid_info *info; /* its record                                  */
+    const int64_t *exclude;       /* sorted ascending ids never admitted, or NULL */
+    int32_t n_exclude;
+    int32_t keep;                 /* list length K', 1..SISSO_MAX_KEEP           */
+    int32_t precision;            /* SISSO_FP32 (SISSO_BF16: see below)          */
+    int32_t grid;                 /* persistent blocks per launch, 0 = default   */
+    int32_t tile;                 /* tile-shape variant, 0 = default             */
+    int32_t list_base;            /* first list slot this call writes: 0 starts a
+                                     new pass (resets the workspace); > 0 appends
+                                     to the lists of earlier calls of the pass   */
+} sisso_score_args;
+
+/* Workspace of a screening pass: per-block candidate lists plus a header.
+ * The size depends on keep and on the launch shape of the call. */
+size_t sisso_score_workspace_size(const sisso_space *space, const sisso_score_args *args);
+
+/* Reset a workspace header (fill kernel on `stream`).  sisso_expand_score
+ * with list_base == 0 does this itself. */
+sisso_status sisso_score_reset(void *ws, size_t ws_bytes, void *stream);
+
+/* Number of per-block lists one sisso_expand_score call over
+ * [cand_begin, cand_end) writes [host]; a pass split into several calls over
+ * disjoint ranges sets each call's list_base to the sum of the earlier calls'
+ * counts.  Returns -1 on invalid arguments. */
+int32_t sisso_expand_score_lists(const sisso_space *space, const sisso_score_args *args,
+                                 int64_t cand_begin, int64_t cand_end);
+
+/* Score every feature with id in [cand_begin, cand_end) against the residual
+ * and keep, per block, the best `keep` valid ones (score desc, id asc),
+ * admitting only candidates not in `exclude` (Sec. 2.2, eq. sis-weight and
+ * eq. sis-method).  Pool columns are scored from their stored FP32 values;
+ * the slice features op(u, v) are generated in registers from the stored
+ * operand columns and never written to memory.  Several calls may feed one
+ * workspace (e.g. disjoint ranges); sisso_topk then merges them.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE, SISSO_E_RANGE (empty or outside
+ * [0, total) range, keep outside 1..SISSO_MAX_KEEP), SISSO_E_WORKSPACE (also
+ * when list_base plus this call's lists exceeds the workspace's capacity),
+ * SISSO_E_UNSUPPORTED (precision other than SISSO_FP32 in this entry point). */
+sisso_status sisso_expand_score(const sisso_space *space, const sisso_score_args *args,
+                                int64_t cand_begin, int64_t cand_end, void *ws, size_t ws_bytes,
+                                void *stream);
+
+/* Merge the workspace's per-block lists into the global best k (score desc,
+ * id asc) (Sec. 2.2, eq. sis-method).  out_ids / out_scores: k entries;
+ * out_count: number written (< k when fewer valid features exist).
+ * Deterministic: identical for any grid or tile choice.
+ * Errors: SISSO_E_NULL, SISSO_E_RANGE (k < 1 or k larger than the keep the
+ * workspace was filled with). */
+sisso_status sisso_topk(const void *ws, size_t ws_bytes, int32_t k, int64_t *out_ids,
+                        float *out_scores, int32_t *out_count, void *stream);
+
+/* Subspace update (Sec. 2.3, eq. subspace-expansion, with the duplicate
+ * rule for non-unique features of Sec. 2.1).  Inputs: the screened list
+ * (count ids, FP64 columns cand (n x count, ldc) with validity), the current
+ * subspace (m_prev FP64 columns sub (n x m_prev, leading dim lds) and their
+ * ids sub_ids), and the FP64 residual r the list was screened against.
+ * Duplicate classes are the connected components of 1 - |corr| <= 1e-9 over
+ * list + subspace; classes touching the subspace are dropped; each remaining
+ * class is represented by its smallest id and scored by the largest FP64
+ * |corr| of its members; the best k classes (score desc, id asc) are
+ * appended to the subspace (ids to sub_ids[m_prev..], columns to sub).
+ * *n_new (device int32) receives the number appended (<= k) and *n_classes
+ * the number of surviving classes.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE (m_prev + k > SISSO_MAX_SUBSPACE,
+ * count > SISSO_MAX_KEEP). */
+size_t sisso_subspace_workspace_size(int32_t n, int32_t count, int32_t m_prev);
+sisso_status sisso_subspace_update(const double *cand, int32_t ldc, const int64_t *cand_ids,
+                                   const int32_t *cand_valid, const int32_t *count_dev,
+                                   int32_t count_max, const double *r, int32_t n, double *sub,
+                                   int32_t lds, int64_t *sub_ids, int32_t m_prev, int32_t k,
+                                   int32_t *n_new, int32_t *n_classes, void *ws, size_t ws_bytes,
+                                   void *stream);
+
+/* SO: exhaustive l0 search (Sec. 2.3, eq. residual read with an inverse;
+ * all C(m, D) models, best by residual norm).  F: n x m FP64 columns (ld)
+ * whose order must be ascending in feature id (ties are broken towards the
+ * lexicographically smallest position tuple among models whose SSE is within
+ * 1e-12 * S_yy of the minimum).  The intercept is fitted and not counted in
+ * D.  Columns are centred and scaled, their FP64 correlation Gram is formed
+ * on the device, and every tuple is solved by an incremental Cholesky
+ * factorisation; tuples with a pivot <= singular_tol are skipped.
+ * Outputs (device): out_tuple D int32 positions (ascending), out_sse[0],
+ * out_coef D + 1 doubles (intercept first), out_resid n doubles (y - fit),
+ * out_stats 4 doubles (rmse, r2, tuples evaluated, tuples skipped).
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE (D outside 1..SISSO_MAX_D, m < D,
+ * m > SISSO_MAX_SUBSPACE), SISSO_E_WORKSPACE.  If every tuple is singular
+ * the stats record tuples skipped == tuples evaluated and out_sse = +inf. */
+size_t sisso_l0_workspace_size(int32_t m, int32_t n, int32_t D);
+sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, const double *y,
+                             int32_t D, double singular_tol, int32_t *out_tuple, double *out_sse,
+                             double *out_coef, double *out_resid, double *out_stats, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/* Gather columns: dst[:, i] = src[:, perm[i]] for i < m (FP64), with ids.
+ * Used to put a subspace in ascending id order before sisso_l0_search.
+ * perm_out (device, m int32) receives the permutation that sorts ids. */
+sisso_status sisso_sort_subspace(const double *src, int32_t lds, const int64_t *ids, int32_t m,
+                                 int32_t n, double *dst, int32_t ldd, int64_t *ids_sorted,
+                                 int32_t *perm_out, void *stream);
+
+/* Human-readable name of a status. */
+const char *sisso_status_string(sisso_status status);
+
+/* Library version string. */
+const char *sisso_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SISSO_H */

@@ -5,8 +5,10 @@ builds every feature as an expression string and a NumPy value vector level
 by level (Sec. 2.1, eq. feature-exp), ranks all of them with
 ``numpy.corrcoef`` (Sec. 2.2, eq. sis-weight / sis-method), and fits every
 t-subset with ``numpy.linalg.lstsq`` on [1, F_T] (Sec. 2.3, eq. residual).
-It follows the same written readings as the oracle (numbering, validity,
-duplicate classes, tie rules) so the two can be compared id by id.
+It follows the same written readings as the oracle (numbering, validity --
+including the rule that a sum or difference cancelling to sd <= 1e-5 of its
+operands' root-mean-square is invalid --, duplicate classes, tie rules) so the
+two can be compared id by id.
 """
 from __future__ import annotations
 
@@ -86,7 +88,11 @@ def enumerate_space(X: np.ndarray, unary: Sequence[str], binary: Sequence[str], 
         v, dom = _bin(op, vl, vr)
         if not dom:
             return (e, np.full(n, np.nan), False)
-        return (e, v, _ok(v))
+        ok = _ok(v)
+        if ok and op in ("add", "sub"):
+            scale = max(np.sqrt(np.mean(vl ** 2)), np.sqrt(np.mean(vr ** 2)))
+            ok = bool(np.sqrt(np.mean((v - v.mean()) ** 2)) > 1e-5 * scale)
+        return (e, v, ok)
 
     for _ in range(levels):
         lo, hi = sizes[-2], sizes[-1]

@@ -34,8 +34,11 @@
  *     v/u).
  *   - validity: a feature is invalid if an operand is invalid, a domain is
  *     violated (sqrt of a negative, log of a non-positive, division by zero,
- *     1/0), a value is non-finite or exceeds 1e15 in magnitude, or the
- *     feature is near-constant (sd <= 1e-6 |mean| or sd == 0).
+ *     1/0), a value is non-finite or exceeds 1e15 in magnitude, the feature
+ *     is near-constant (sd <= 1e-6 |mean| or sd == 0), or it is a sum or
+ *     difference that cancels (sd <= 1e-5 x the larger root-mean-square of
+ *     its two operands): such a feature is an identity that is zero or
+ *     constant in exact arithmetic and carries only rounding noise.
  *   - score = |Pearson correlation| (standardised features; the variance
  *     convention cancels).  Ties ordered by (score desc, id asc).
  *   - duplicates: classes = connected components of 1 - |corr| <= 1e-9 over
@@ -60,6 +63,7 @@ enum { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQ = 4, OP_CUBE = 5,
 #define OR_MAX_LEVELS 4
 #define VALUE_CAP 1e15
 #define CONST_REL 1e-6
+#define CANCEL_REL 1e-5
 #define DUP_TOL 1e-9
 #define PIVOT_TOL 1e-10
 #define TIE_REL 1e-12
@@ -212,6 +216,22 @@ static int apply_op(int op, const double *a, const double *b, double *out, int n
 
 /* Evaluate feature `id` on the n samples of X (column-major, leading dim
  * ldx).  Returns 1 if valid, 0 if invalid (out is then unspecified). */
+static double rms(const double *f, int n)
+{
+    double a = 0.0;
+    for (int s = 0; s < n; s++) a += f[s] * f[s];
+    return sqrt(a / n);
+}
+
+static double sd_of(const double *f, int n)
+{
+    double m = 0.0, ss = 0.0;
+    for (int s = 0; s < n; s++) m += f[s];
+    m /= n;
+    for (int s = 0; s < n; s++) ss += (f[s] - m) * (f[s] - m);
+    return sqrt(ss / n);
+}
+
 static int eval_rec(const or_space *s, const double *X, int n, int ldx, int64_t id, double *out)
 {
     int32_t op; int64_t l, r;
@@ -226,6 +246,10 @@ static int eval_rec(const or_space *s, const double *X, int n, int ldx, int64_t 
     if (ok && b) ok = eval_rec(s, X, n, ldx, r, b);
     if (ok) ok = apply_op(op, a, b, out, n);
     if (ok) ok = check_values(out, n);
+    if (ok && (op == OP_ADD || op == OP_SUB)) {
+        const double ra = rms(a, n), rb = rms(b, n);
+        if (sd_of(out, n) <= CANCEL_REL * (ra > rb ? ra : rb)) ok = 0;
+    }
     free(a); free(b);
     return ok;
 }

@@ -1,0 +1,140 @@
+"""ctypes binding of libsisso.so (the C ABI declared in include/sisso.h).
+
+Argument marshalling only: torch tensors are passed as device pointers and
+the current torch stream as the HIP stream.  Every computation happens in the
+library's HIP kernels.  Loading fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libsisso.so")
+
+OPCODE = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sq": 4, "cube": 5, "sqrt": 6,
+          "inv": 7, "exp": 8, "nexp": 9, "log": 10, "sin": 11}
+OPNAME = {v: k for k, v in OPCODE.items()}
+
+MAX_UNARY, MAX_BINARY, MAX_LEVELS = 8, 4, 2
+MAX_N, MAX_KEEP, MAX_SUBSPACE, MAX_D = 65536, 2048, 1024, 3
+FP32, BF16 = 0, 1
+
+
+class SissoError(RuntimeError):
+    pass
+
+
+class Space(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("levels", ctypes.c_int32), ("rect", ctypes.c_int32),
+                ("n_unary", ctypes.c_int32), ("n_binary", ctypes.c_int32),
+                ("unary", ctypes.c_int32 * MAX_UNARY), ("binary", ctypes.c_int32 * MAX_BINARY),
+                ("n_slots", ctypes.c_int32),
+                ("slot_op", ctypes.c_int32 * (2 * MAX_BINARY)),
+                ("slot_rev", ctypes.c_int32 * (2 * MAX_BINARY)),
+                ("pool", ctypes.c_int64 * (MAX_LEVELS + 1)),
+                ("rect_unary", ctypes.c_int64), ("rect_binary", ctypes.c_int64),
+                ("total", ctypes.c_int64)]
+
+
+class ScoreArgs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("pool32", ctypes.c_void_p), ("ld32", ctypes.c_int64),
+                ("stats", ctypes.c_void_p), ("r32", ctypes.c_void_p), ("info", ctypes.c_void_p),
+                ("exclude", ctypes.c_void_p), ("n_exclude", ctypes.c_int32),
+                ("keep", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("list_base", ctypes.c_int32)]
+
+
+COLSTAT_FLOATS = 8      # sisso_colstat: 8 floats
+RESID_DOUBLES = 4       # sisso_resid_info: 4 doubles
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise SissoError(f"libsisso.so not found at {LIBPATH}; build it with "
+                         "`python -m paper_2410_01752_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIBPATH)
+    sp = ctypes.POINTER(Space)
+    ap = ctypes.POINTER(ScoreArgs)
+    sig = {
+        "sisso_space_init": (_i32, [sp]),
+        "sisso_decode": (_i32, [sp, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                                ctypes.POINTER(_i64)]),
+        "sisso_materialize_pools": (_i32, [sp, _vp, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _vp]),
+        "sisso_materialize_ids": (_i32, [sp, _i32, _vp, _i64, _vp, _vp, _i32, _vp, _i32, _vp, _vp]),
+        "sisso_prepare_residual": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+        "sisso_score_workspace_size": (_sz, [sp, ap]),
+        "sisso_score_reset": (_i32, [_vp, _sz, _vp]),
+        "sisso_expand_score": (_i32, [sp, ap, _i64, _i64, _vp, _sz, _vp]),
+        "sisso_expand_score_lists": (_i32, [sp, ap, _i64, _i64]),
+        "sisso_topk": (_i32, [_vp, _sz, _i32, _vp, _vp, _vp, _vp]),
+        "sisso_subspace_workspace_size": (_sz, [_i32, _i32, _i32]),
+        "sisso_subspace_update": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp,
+                                         _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+        "sisso_l0_workspace_size": (_sz, [_i32, _i32, _i32]),
+        "sisso_l0_search": (_i32, [_vp, _i32, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
+                                   _vp, _vp, _vp, _sz, _vp]),
+        "sisso_sort_subspace": (_i32, [_vp, _i32, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
+        "sisso_status_string": (ctypes.c_char_p, [_i32]),
+        "sisso_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "sisso_materialize_ids",
+            "sisso_prepare_residual", "sisso_score_workspace_size", "sisso_score_reset",
+            "sisso_expand_score", "sisso_expand_score_lists", "sisso_topk", "sisso_subspace_workspace_size",
+            "sisso_subspace_update", "sisso_l0_workspace_size", "sisso_l0_search",
+            "sisso_sort_subspace", "sisso_status_string", "sisso_version"]
+
+
+def check(status: int, what: str = ""):
+    if status != 0:
+        msg = lib().sisso_status_string(status).decode()
+        raise SissoError(f"{what}: status {status} ({msg})")
+
+
+def ptr(t) -> int:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def stream_handle(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def make_space(d: int, unary, binary, levels: int, rect: bool) -> Space:
+    s = Space()
+    s.d, s.levels, s.rect = d, levels, int(rect)
+    s.n_unary, s.n_binary = len(unary), len(binary)
+    for i, o in enumerate(unary):
+        s.unary[i] = OPCODE[o]
+    for i, o in enumerate(binary):
+        s.binary[i] = OPCODE[o]
+    check(lib().sisso_space_init(ctypes.byref(s)), "sisso_space_init")
+    return s
+
+
+def decode(space: Space, fid: int):
+    op = _i32(); l = _i64(); r = _i64()
+    check(lib().sisso_decode(ctypes.byref(space), fid, ctypes.byref(op), ctypes.byref(l),
+                             ctypes.byref(r)), "sisso_decode")
+    return op.value, l.value, r.value

@@ -1,0 +1,351 @@
+// l0.hip -- the sparsifying operator: exhaustive least squares over every
+// D-subset of the subspace (Sec. 2.3, eq. residual, read with an inverse; the
+// best model minimises the residual norm over all C(m, D) models).
+//
+// Columns and y are centred (the intercept is fitted and not counted in D) and
+// columns are scaled to unit norm; their FP64 correlation Gram C and
+// beta = Z^T y~ are formed once.  A tuple's SSE then follows from an
+// incremental Cholesky factorisation of C restricted to the tuple:
+//   D = 1: SSE = S_yy - b_i^2
+//   D = 2: L22 = sqrt(1 - C_ij^2), z2 = (b_j - C_ij b_i) / L22,
+//          SSE = S_yy - b_i^2 - z2^2
+//   D = 3: L32 = (C_jl - C_il C_ij) / L22, q = 1 - C_il^2 - L32^2,
+//          tau = b_l - C_il b_i - L32 z2, SSE = S_yy - b_i^2 - z2^2 - tau^2 / q
+// A tuple whose pivot (L22^2 or q) is <= singular_tol is skipped.
+// Pass 1 finds the minimum SSE; pass 2 the lexicographically first tuple whose
+// SSE is within 1e-12 S_yy of it (columns arrive in ascending id order).
+#include "linalg.hpp"
+
+namespace sisso {
+
+struct L0Ws {
+    double *Z;         // n x m standardised
+    double *C;         // m x m correlation Gram
+    double *beta;      // m
+    double *mean;      // m
+    double *norm;      // m
+    double *yt;        // n centred y
+    double *scal;      // [0] ybar, [1] syy
+    unsigned long long *best;   // [0] min SSE bits, [1] lex key
+    unsigned long long *skipped;
+    int ldz;
+};
+
+__host__ __device__ inline size_t l0_ws_bytes(int m, int n)
+{
+    const size_t ldz = (size_t)((n + 3) & ~3);
+    size_t b = ldz * m * 8 + (size_t)m * m * 8 + 3 * (size_t)m * 8 + ldz * 8 + 4 * 8 + 4 * 8;
+    return (b + 255) & ~(size_t)255;
+}
+
+__host__ __device__ inline L0Ws l0_ws_view(void *ws, int m, int n)
+{
+    L0Ws w;
+    w.ldz = (n + 3) & ~3;
+    char *p = (char *)ws;
+    w.Z = (double *)p; p += (size_t)w.ldz * m * 8;
+    w.C = (double *)p; p += (size_t)m * m * 8;
+    w.beta = (double *)p; p += (size_t)m * 8;
+    w.mean = (double *)p; p += (size_t)m * 8;
+    w.norm = (double *)p; p += (size_t)m * 8;
+    w.yt = (double *)p; p += (size_t)w.ldz * 8;
+    w.scal = (double *)p; p += 4 * 8;
+    w.best = (unsigned long long *)p; p += 2 * 8;
+    w.skipped = (unsigned long long *)p;
+    return w;
+}
+
+__global__ void __launch_bounds__(256) k_l0_y(const double *__restrict__ y, int n, L0Ws w)
+{
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) s += y[t];
+    const double ym = block_sum(s, red) / n;
+    double ss = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double e = y[t] - ym;
+        w.yt[t] = e;
+        ss += e * e;
+    }
+    const double syy = block_sum(ss, red);
+    if (threadIdx.x == 0) {
+        w.scal[0] = ym;
+        w.scal[1] = syy;
+        w.best[0] = 0x7FF0000000000000ull;   // +inf
+        w.best[1] = ~0ull;
+        *w.skipped = 0ull;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_l0_columns(const double *__restrict__ F, int ld, int n, L0Ws w)
+{
+    __shared__ double red[16];
+    const int j = blockIdx.x;
+    double *z = w.Z + (size_t)j * w.ldz;
+    standardize_column(F + (size_t)j * ld, n, z, &w.mean[j], &w.norm[j], nullptr, red);
+    double d = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) d += z[t] * w.yt[t];
+    const double b = block_sum(d, red);
+    if (threadIdx.x == 0) w.beta[j] = b;
+}
+
+__global__ void __launch_bounds__(256) k_l0_gram(int m, int n, L0Ws w)
+{
+    __shared__ double As[kGK][kGT + 1];
+    __shared__ double Bs[kGK][kGT + 1];
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    if (bj > bi) return;
+    double acc[2][2];
+    gemm_tile_tn(w.Z, m, w.Z, m, n, w.ldz, bi, bj, acc, As, Bs);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int i = bi * kGT + ty * 2 + a, j = bj * kGT + tx * 2 + b;
+            if (i < m && j < m && j <= i) {
+                const double v = i == j ? 1.0 : acc[a][b];
+                w.C[(size_t)i * m + j] = v;
+                w.C[(size_t)j * m + i] = v;
+            }
+        }
+}
+
+__device__ __forceinline__ unsigned long long sse_bits(double sse)
+{
+    return (unsigned long long)__double_as_longlong(sse > 0.0 ? sse : 0.0);
+}
+
+// Enumerate tuples with first index i = blockIdx.x.  PASS 0: minimum SSE;
+// PASS 1: smallest lexicographic key (i, j, l) with SSE <= band.
+template <int D, int PASS>
+__global__ void __launch_bounds__(256) k_l0_enum(int m, double tol, L0Ws w)
+{
+    __shared__ double inv22[SISSO_MAX_SUBSPACE], z2s[SISSO_MAX_SUBSPACE];
+    __shared__ unsigned long long red64[4];
+    __shared__ unsigned long long skip_s;
+    const int i = blockIdx.x;
+    const double syy = w.scal[1];
+    const double bi = w.beta[i];
+    const double base = syy - bi * bi;
+    double band = 0.0;
+    if (PASS == 1) band = __longlong_as_double((long long)w.best[0]) + kTieRel * syy;
+    unsigned long long mine = PASS == 0 ? 0x7FF0000000000000ull : ~0ull;
+    unsigned long long nskip = 0;
+    if (threadIdx.x == 0) skip_s = 0;
+    if (D == 1) {
+        if (threadIdx.x == 0) {
+            const unsigned long long sb = sse_bits(base);
+            if (PASS == 0) mine = sb;
+            else if (__longlong_as_double((long long)sb) <= band) mine = (unsigned long long)i;
+        }
+    } else {
+        const double *Ci = w.C + (size_t)i * m;
+        // per-j quantities of the pair (i, j)
+        for (int j = i + 1 + threadIdx.x; j < m; j += blockDim.x) {
+            const double cij = Ci[j];
+            const double p2 = fma(-cij, cij, 1.0);
+            if (p2 > tol) {
+                const double l22 = sqrt(p2);
+                inv22[j] = 1.0 / l22;
+                z2s[j] = (w.beta[j] - cij * bi) / l22;
+            } else {
+                inv22[j] = 0.0;     // singular pair
+                z2s[j] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (D == 2) {
+            for (int j = i + 1 + threadIdx.x; j < m; j += blockDim.x) {
+                if (inv22[j] == 0.0) { nskip++; continue; }
+                const double z2 = z2s[j];
+                const double sse = fma(-z2, z2, base);
+                const unsigned long long sb = sse_bits(sse);
+                if (PASS == 0) { if (sb < mine) mine = sb; }
+                else if (__longlong_as_double((long long)sb) <= band) {
+                    const unsigned long long key = (unsigned long long)i * m + j;
+                    if (key < mine) mine = key;
+                }
+            }
+        } else {
+            for (int l = i + 2 + threadIdx.x; l < m; l += blockDim.x) {
+                const double cil = Ci[l];
+                const double bl = w.beta[l];
+                const double r1 = fma(-cil, cil, 1.0);
+                const double t1 = fma(-cil, bi, bl);
+                for (int j = i + 1; j < l; ++j) {
+                    const double iv = inv22[j];
+                    if (iv == 0.0) { nskip++; continue; }
+                    const double cij = Ci[j];
+                    const double cjl = w.C[(size_t)j * m + l];
+                    const double l32 = fma(-cil, cij, cjl) * iv;
+                    const double q = fma(-l32, l32, r1);
+                    if (!(q > tol)) { nskip++; continue; }
+                    const double z2 = z2s[j];
+                    const double tau = fma(-l32, z2, t1);
+                    const double sse = fma(-z2, z2, base) - tau * tau / q;
+                    const unsigned long long sb = sse_bits(sse);
+                    if (PASS == 0) { if (sb < mine) mine = sb; }
+                    else if (__longlong_as_double((long long)sb) <= band) {
+                        const unsigned long long key = ((unsigned long long)i * m + j) * m + l;
+                        if (key < mine) mine = key;
+                    }
+                }
+            }
+        }
+    }
+    // block min, then global atomic min
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(mine, o, 64);
+        mine = other < mine ? other : mine;
+    }
+    if (PASS == 0 && nskip) atomicAdd(&skip_s, nskip);
+    if ((threadIdx.x & 63) == 0) red64[threadIdx.x >> 6] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long v = red64[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) v = red64[q] < v ? red64[q] : v;
+        atomicMin(&w.best[PASS], v);
+        if (PASS == 0 && skip_s) atomicAdd(w.skipped, skip_s);
+    }
+}
+
+// Decode the best tuple, solve for the coefficients, form the residual.
+__global__ void __launch_bounds__(256) k_l0_finish(const double *__restrict__ F, int ld, int n, int m, int D,
+                                                   const double *__restrict__ y, double n_tuples, L0Ws w,
+                                                   int32_t *__restrict__ out_tuple, double *__restrict__ out_sse,
+                                                   double *__restrict__ out_coef, double *__restrict__ out_resid,
+                                                   double *__restrict__ out_stats)
+{
+    __shared__ int tup[SISSO_MAX_D];
+    __shared__ double coef[SISSO_MAX_D + 1];
+    __shared__ double sse_chosen;
+    __shared__ int found;
+    __shared__ double red[16];
+    if (threadIdx.x == 0) {
+        const unsigned long long key = w.best[1];
+        found = key != ~0ull;
+        if (found) {
+            unsigned long long k = key;
+            for (int a = D - 1; a >= 0; --a) { tup[a] = (int)(k % (unsigned long long)m); k /= (unsigned long long)m; }
+            // normal equations on the unit-diagonal system, Cholesky (D <= 3)
+            double A[SISSO_MAX_D][SISSO_MAX_D], b[SISSO_MAX_D], L[SISSO_MAX_D][SISSO_MAX_D], zz[SISSO_MAX_D], c[SISSO_MAX_D];
+            for (int a = 0; a < D; ++a) {
+                b[a] = w.beta[tup[a]];
+                for (int q = 0; q < D; ++q) A[a][q] = w.C[(size_t)tup[a] * m + tup[q]];
+            }
+            for (int a = 0; a < D; ++a) {
+                for (int q = 0; q <= a; ++q) {
+                    double s = A[a][q];
+                    for (int p = 0; p < q; ++p) s -= L[a][p] * L[q][p];
+                    if (a == q) L[a][a] = sqrt(s > 0.0 ? s : 0.0);
+                    else L[a][q] = s / L[q][q];
+                }
+            }
+            for (int a = 0; a < D; ++a) {
+                double s = b[a];
+                for (int p = 0; p < a; ++p) s -= L[a][p] * zz[p];
+                zz[a] = s / L[a][a];
+            }
+            for (int a = D - 1; a >= 0; --a) {
+                double s = zz[a];
+                for (int p = a + 1; p < D; ++p) s -= L[p][a] * c[p];
+                c[a] = s / L[a][a];
+            }
+            double fit = 0.0;
+            for (int a = 0; a < D; ++a) fit += zz[a] * zz[a];
+            const double e = w.scal[1] - fit;
+            sse_chosen = e > 0.0 ? e : 0.0;            // SSE of the chosen tuple
+            double icpt = w.scal[0];
+            for (int a = 0; a < D; ++a) {
+                const double ca = c[a] / w.norm[tup[a]];
+                coef[1 + a] = ca;
+                icpt -= ca * w.mean[tup[a]];
+            }
+            coef[0] = icpt;
+        }
+    }
+    __syncthreads();
+    if (!found) {
+        for (int t = threadIdx.x; t < n; t += blockDim.x) out_resid[t] = y[t];
+        if (threadIdx.x == 0) {
+            for (int a = 0; a < D; ++a) out_tuple[a] = -1;
+            for (int a = 0; a <= D; ++a) out_coef[a] = 0.0;
+            out_sse[0] = INFINITY;
+            out_stats[0] = NAN; out_stats[1] = NAN;
+            out_stats[2] = n_tuples; out_stats[3] = (double)*w.skipped;
+        }
+        return;
+    }
+    double ss = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        double yh = coef[0];
+        for (int a = 0; a < D; ++a) yh = fma(coef[1 + a], F[(size_t)tup[a] * ld + t], yh);
+        const double r = y[t] - yh;
+        out_resid[t] = r;
+        ss += r * r;
+    }
+    const double sst = block_sum(ss, red);
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < D; ++a) out_tuple[a] = tup[a];
+        for (int a = 0; a <= D; ++a) out_coef[a] = coef[a];
+        const double sse = sse_chosen;
+        out_sse[0] = sse;
+        out_stats[0] = sqrt(sst / n);
+        out_stats[1] = 1.0 - sse / w.scal[1];
+        out_stats[2] = n_tuples;
+        out_stats[3] = (double)*w.skipped;
+    }
+}
+
+}  // namespace sisso
+
+using namespace sisso;
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" size_t sisso_l0_workspace_size(int32_t m, int32_t n, int32_t D)
+{
+    if (m < 1 || n < 2 || D < 1) return 0;
+    return l0_ws_bytes(m, n);
+}
+
+static double n_choose(int m, int D)
+{
+    double r = 1.0;
+    for (int a = 0; a < D; ++a) r = r * (m - a) / (a + 1);
+    return r;
+}
+
+extern "C" sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, const double *y,
+                                        int32_t D, double singular_tol, int32_t *out_tuple, double *out_sse,
+                                        double *out_coef, double *out_resid, double *out_stats, void *ws,
+                                        size_t ws_bytes, void *stream)
+{
+    if (!F || !y || !out_tuple || !out_sse || !out_coef || !out_resid || !out_stats || !ws) return SISSO_E_NULL;
+    if (D < 1 || D > SISSO_MAX_D || m < D || m > SISSO_MAX_SUBSPACE || n < 2 || n > SISSO_MAX_N || ld < n)
+        return SISSO_E_SHAPE;
+    if (!(singular_tol >= 0.0) || singular_tol >= 1.0) return SISSO_E_RANGE;
+    if (ws_bytes < l0_ws_bytes(m, n)) return SISSO_E_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    L0Ws w = l0_ws_view(ws, m, n);
+    hipLaunchKernelGGL(k_l0_y, dim3(1), dim3(256), 0, st, y, n, w);
+    hipLaunchKernelGGL(k_l0_columns, dim3(m), dim3(256), 0, st, F, ld, n, w);
+    const int tiles = (m + kGT - 1) / kGT;
+    hipLaunchKernelGGL(k_l0_gram, dim3(tiles, tiles), dim3(256), 0, st, m, n, w);
+    const int gb = D == 1 ? m : m - D + 1;
+    if (D == 1) {
+        hipLaunchKernelGGL((k_l0_enum<1, 0>), dim3(gb), dim3(64), 0, st, m, singular_tol, w);
+        hipLaunchKernelGGL((k_l0_enum<1, 1>), dim3(gb), dim3(64), 0, st, m, singular_tol, w);
+    } else if (D == 2) {
+        hipLaunchKernelGGL((k_l0_enum<2, 0>), dim3(gb), dim3(256), 0, st, m, singular_tol, w);
+        hipLaunchKernelGGL((k_l0_enum<2, 1>), dim3(gb), dim3(256), 0, st, m, singular_tol, w);
+    } else {
+        hipLaunchKernelGGL((k_l0_enum<3, 0>), dim3(gb), dim3(256), 0, st, m, singular_tol, w);
+        hipLaunchKernelGGL((k_l0_enum<3, 1>), dim3(gb), dim3(256), 0, st, m, singular_tol, w);
+    }
+    hipLaunchKernelGGL(k_l0_finish, dim3(1), dim3(256), 0, st, F, ld, n, m, D, y, n_choose(m, D), w, out_tuple,
+                       out_sse, out_coef, out_resid, out_stats);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}

@@ -1,0 +1,280 @@
+// materialize.hip -- operand pools and FP64 feature evaluation.
+//
+// Feature expansion (Sec. 2.1, eq. feature-exp): the pool levels P_0, P_1,
+// P_2 are evaluated in FP64 from the base features, one block per column,
+// and stored column-major in FP32 (the screening operands) together with
+// per-column statistics.  Level-1 values are also kept in FP64 so that any
+// feature of the space (pool or one-sided slice) can be re-evaluated exactly
+// in FP64 for the subspace and the SO step.
+#include "common.hpp"
+
+namespace sisso {
+
+struct BlockStats {
+    double red[16];
+    float fmx[16], fmn[16], fmv[16];
+    int bad[16];
+};
+
+__device__ inline void block_minmax(float &mx, float &mn, float &mv, int &bad, BlockStats &bs)
+{
+    mx = wave_max(mx); mn = wave_min(mn); mv = wave_min(mv); bad = wave_or(bad);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { bs.fmx[w] = mx; bs.fmn[w] = mn; bs.fmv[w] = mv; bs.bad[w] = bad; }
+    __syncthreads();
+    for (int i = 0; i < nw; ++i) {
+        mx = fmaxf(mx, bs.fmx[i]); mn = fminf(mn, bs.fmn[i]); mv = fminf(mv, bs.fmv[i]);
+        bad |= bs.bad[i];
+    }
+}
+
+// One level of the pool: columns [c_begin, c_end).  Level 0 copies the base
+// features.  Operands of levels >= 1 are read from the FP64 level-1 pool.
+__global__ void __launch_bounds__(256) k_pool_level(sisso_space s, const double *__restrict__ X,
+                                                    int n, int ldx, float *__restrict__ pool32,
+                                                    int64_t ld32, double *__restrict__ p1,
+                                                    int64_t ld64, sisso_colstat *__restrict__ stats,
+                                                    int64_t c_begin, int64_t c_end)
+{
+    __shared__ BlockStats bs;
+    for (int64_t c = c_begin + blockIdx.x; c < c_end; c += gridDim.x) {
+        int op;
+        int64_t a, b;
+        decode_id(s, c, &op, &a, &b);
+        bool opok = true;
+        if (op >= 0) {
+            opok = stats[a].valid != 0.0f;
+            if (b >= 0) opok = opok && stats[b].valid != 0.0f;
+        }
+        const double *A = op < 0 ? X + (size_t)c * ldx : p1 + (size_t)a * ld64;
+        const double *B = (op >= 0 && b >= 0) ? p1 + (size_t)b * ld64 : nullptr;
+        // pass 1: values, domain, magnitude, sums
+        double sum = 0.0, sa2 = 0.0, sb2 = 0.0;
+        int bad = opok ? 0 : 1;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            bool ok = true;
+            const double x = A[t], y = B ? B[t] : 0.0;
+            const double f = op < 0 ? x : apply64(op, x, y, ok);
+            if (!ok || !(fabs(f) <= kValueCap)) bad = 1;   // also catches NaN
+            sum += f;
+            sa2 += x * x;
+            sb2 += y * y;
+        }
+        const double mean = block_sum(sum, bs.red) / n;
+        const double ra = sqrt(block_sum(sa2, bs.red) / n), rb = sqrt(block_sum(sb2, bs.red) / n);
+        // pass 2: sum of squares, extremes, reciprocal mean, stores
+        double ss = 0.0, srcp = 0.0, sf2 = 0.0;
+        float mx = 0.0f, mn = INFINITY, mv = INFINITY;
+        float *out32 = pool32 + (size_t)c * ld32;
+        double *out64 = (c < s.pool[1 < s.levels ? 1 : s.levels]) ? p1 + (size_t)c * ld64 : nullptr;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            bool ok = true;
+            const double f = op < 0 ? A[t] : apply64(op, A[t], B ? B[t] : 0.0, ok);
+            const double e = f - mean;
+            ss += e * e;
+            sf2 += f * f;
+            srcp += 1.0 / f;
+            const float af = (float)fabs(f);
+            mx = fmaxf(mx, af); mn = fminf(mn, af); mv = fminf(mv, (float)f);
+            out32[t] = (float)f;
+            if (out64) out64[t] = f;
+        }
+        for (int64_t t = n + threadIdx.x; t < ld32; t += blockDim.x) out32[t] = 0.0f;
+        const double sst = block_sum(ss, bs.red);
+        const double mrcp = block_sum(srcp, bs.red) / n;
+        const double msq = block_sum(sf2, bs.red) / n;
+        block_minmax(mx, mn, mv, bad, bs);
+        if (threadIdx.x == 0) {
+            const double sd = sqrt(sst / n);
+            bool valid = !bad && sd != 0.0 && sd > kConstRel * fabs(mean);
+            if (op == SISSO_ADD || op == SISSO_SUB) valid = valid && sd > kCancelRel * fmax(ra, rb);
+            sisso_colstat st;
+            st.mean = (float)mean;
+            st.sd = (float)sd;
+            st.mean_rcp = mn > 0.0f ? (float)mrcp : INFINITY;
+            st.maxabs = mx;
+            st.minabs = mn;
+            st.minval = mv;
+            st.valid = valid ? 1.0f : 0.0f;
+            st.rms = (float)sqrt(msq);
+            stats[c] = st;
+        }
+        __syncthreads();
+    }
+}
+
+// One operand of a feature, evaluated from the FP64 level-1 pool: a pool-1
+// column, or a level-2 column op(P1[a], P1[b]).
+struct Node {
+    int op;          // -1: leaf P1[a]
+    int64_t a, b;
+};
+
+__device__ inline Node make_node(const sisso_space &s, int64_t id)
+{
+    Node nd;
+    if (id < s.pool[1]) { nd.op = -1; nd.a = id; nd.b = -1; return nd; }
+    int op;
+    int64_t a, b;
+    decode_id(s, id, &op, &a, &b);
+    nd.op = op; nd.a = a; nd.b = b;
+    return nd;
+}
+
+__device__ __forceinline__ double eval_node(const Node &nd, const double *p1, int64_t ld64, int t,
+                                            bool &ok)
+{
+    const double x = p1[(size_t)nd.a * ld64 + t];
+    if (nd.op < 0) return x;
+    const double y = nd.b >= 0 ? p1[(size_t)nd.b * ld64 + t] : 0.0;
+    return apply64(nd.op, x, y, ok);
+}
+
+// FP64 values of arbitrary features, one block per id.
+__global__ void __launch_bounds__(256) k_eval_ids(sisso_space s, int n, const double *__restrict__ p1,
+                                                  int64_t ld64, const sisso_colstat *__restrict__ stats,
+                                                  const int64_t *__restrict__ ids, int count,
+                                                  double *__restrict__ out, int ldo,
+                                                  int32_t *__restrict__ valid)
+{
+    __shared__ BlockStats bs;
+    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        const int64_t id = ids[q];
+        double *o = out + (size_t)q * ldo;
+        if (id < 0 || id >= s.total) {
+            for (int t = threadIdx.x; t < n; t += blockDim.x) o[t] = NAN;
+            if (threadIdx.x == 0) valid[q] = 0;
+            continue;
+        }
+        int top = -1;
+        Node L, R;
+        bool opok = true;
+        R.op = -1; R.a = -1; R.b = -1;
+        if (id < s.pool[s.levels]) {
+            L = make_node(s, id);
+            opok = stats[id].valid != 0.0f;   // pool columns: decided at materialisation
+        } else {
+            int64_t u, v;
+            decode_id(s, id, &top, &u, &v);
+            L = make_node(s, u);
+            opok = stats[u].valid != 0.0f;
+            if (v >= 0) { R = make_node(s, v); opok = opok && stats[v].valid != 0.0f; }
+        }
+        double sum = 0.0, sa2 = 0.0, sb2 = 0.0;
+        int bad = opok ? 0 : 1;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            bool ok = true;
+            double f = eval_node(L, p1, ld64, t, ok);
+            if (top >= 0) {
+                const double g = R.a >= 0 ? eval_node(R, p1, ld64, t, ok) : 0.0;
+                sa2 += f * f;
+                sb2 += g * g;
+                f = apply64(top, f, g, ok);
+            }
+            if (!ok || !(fabs(f) <= kValueCap)) bad = 1;
+            o[t] = f;
+            sum += f;
+        }
+        const double mean = block_sum(sum, bs.red) / n;
+        const double ra = sqrt(block_sum(sa2, bs.red) / n), rb = sqrt(block_sum(sb2, bs.red) / n);
+        double ss = 0.0;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            const double e = o[t] - mean;
+            ss += e * e;
+        }
+        const double sst = block_sum(ss, bs.red);
+        float mx = 0, mn = 0, mv = 0;
+        block_minmax(mx, mn, mv, bad, bs);
+        const double sd = sqrt(sst / n);
+        bool ok = !bad && sd != 0.0 && sd > kConstRel * fabs(mean);
+        if (top == SISSO_ADD || top == SISSO_SUB) ok = ok && sd > kCancelRel * fmax(ra, rb);
+        if (!ok)
+            for (int t = threadIdx.x; t < n; t += blockDim.x) o[t] = NAN;
+        if (threadIdx.x == 0) valid[q] = ok ? 1 : 0;
+        __syncthreads();
+    }
+}
+
+// Centre a residual, round it to FP32 and record its sums (one block).
+__global__ void __launch_bounds__(1024) k_prepare_residual(const double *__restrict__ r, int n,
+                                                           float *__restrict__ r32,
+                                                           sisso_resid_info *__restrict__ info)
+{
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) s += r[t];
+    const double mean = block_sum(s, red) / n;
+    double s32 = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const float v = (float)(r[t] - mean);
+        r32[t] = v;
+        s32 += (double)v;
+    }
+    const double sum32 = block_sum(s32, red);
+    const double m32 = sum32 / n;
+    double ss = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double e = (double)r32[t] - m32;
+        ss += e * e;
+    }
+    const double srr = block_sum(ss, red);
+    if (threadIdx.x == 0) {
+        info->sum_r32 = sum32;
+        info->s_rr = srr;
+        info->mean_r = mean;
+        info->n = (double)n;
+    }
+}
+
+}  // namespace sisso
+
+using namespace sisso;
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" sisso_status sisso_materialize_pools(const sisso_space *space, const double *X, int32_t n,
+                                                int32_t ldx, float *pool32, int64_t ld32,
+                                                double *pool1_64, int64_t ld64, sisso_colstat *stats,
+                                                void *stream)
+{
+    if (!space || !X || !pool32 || !pool1_64 || !stats) return SISSO_E_NULL;
+    if (space->total <= 0 || space->levels < 1 || space->levels > SISSO_MAX_LEVELS) return SISSO_E_SHAPE;
+    if (n < 2 || n > SISSO_MAX_N || ldx < n || ld32 < n || (ld32 % 4) != 0 || ld64 < n)
+        return SISSO_E_SHAPE;
+    hipStream_t st = as_stream(stream);
+    for (int lev = 0; lev <= space->levels; ++lev) {
+        const int64_t lo = lev == 0 ? 0 : space->pool[lev - 1], hi = space->pool[lev];
+        const int64_t cols = hi - lo;
+        const int grid = (int)(cols < 65536 ? cols : 65536);
+        hipLaunchKernelGGL(k_pool_level, dim3(grid), dim3(256), 0, st, *space, X, n, ldx, pool32, ld32,
+                           pool1_64, ld64, stats, lo, hi);
+        if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
+    }
+    return SISSO_OK;
+}
+
+extern "C" sisso_status sisso_materialize_ids(const sisso_space *space, int32_t n,
+                                              const double *pool1_64, int64_t ld64,
+                                              const sisso_colstat *stats, const int64_t *ids,
+                                              int32_t count, double *out, int32_t ldo,
+                                              int32_t *valid, void *stream)
+{
+    if (!space || !pool1_64 || !stats || !ids || !out || !valid) return SISSO_E_NULL;
+    if (space->total <= 0 || n < 2 || n > SISSO_MAX_N || ld64 < n || ldo < n || count < 0)
+        return SISSO_E_SHAPE;
+    if (count == 0) return SISSO_OK;
+    const int grid = count < 4096 ? count : 4096;
+    hipLaunchKernelGGL(k_eval_ids, dim3(grid), dim3(256), 0, as_stream(stream), *space, n, pool1_64,
+                       ld64, stats, ids, count, out, ldo, valid);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_prepare_residual(const double *r, int32_t n, float *r32,
+                                               sisso_resid_info *info, void *stream)
+{
+    if (!r || !r32 || !info) return SISSO_E_NULL;
+    if (n < 2 || n > SISSO_MAX_N) return SISSO_E_SHAPE;
+    hipLaunchKernelGGL(k_prepare_residual, dim3(1), dim3(1024), 0, as_stream(stream), r, n, r32, info);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}

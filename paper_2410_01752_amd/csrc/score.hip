@@ -1,0 +1,894 @@
+// score.hip -- SIS screening: |Pearson correlation| of every candidate with
+// the residual and a deterministic grid-wide top-K' (Sec. 2.2, eq. sis-weight
+// and eq. sis-method).
+//
+// Per candidate f and centred FP32 residual r the kernels accumulate, with a
+// per-candidate shift c (the candidate's value at sample 0),
+//     A = sum (f - c),   B = sum (f - c)^2,   C = sum (f - c) r
+// and score = |C - A R1/n| / sqrt((B - A^2/n) S_rr), where R1 = sum r and
+// S_rr = sum (r - R1/n)^2 come from sisso_prepare_residual.  Partial sums run
+// in FP32 over short sample chunks and are carried in FP64.
+//
+// Two kernels cover the space:
+//   k_score_columns  stored pool columns (one wave per column, HBM-bound),
+//                    plus the one-sided slice's unary block on the newest
+//                    pool level, evaluated while the column streams by;
+//   k_score_rect     the slice's binary block op(u, v): a block owns a tile of
+//                    newest-level operands u and sweeps every v tile of the
+//                    previous pool, staging sample chunks of both through LDS
+//                    and evaluating all binary slots in registers.  Slice
+//                    candidates are never written to memory.
+// Every block keeps its best K' candidates (score desc, id asc) in LDS and
+// writes them to its list slot of the workspace; sisso_topk merges the lists.
+#include "common.hpp"
+
+namespace sisso {
+
+// ------------------------------------------------------------- workspace
+
+constexpr int kHistBins = 4096;
+constexpr int kFinalCap = 8192;
+
+struct WsHeader {
+    unsigned gthr;          // grid-wide admission bound (float bits)
+    int keep;               // list length
+    int n_lists;            // lists written by the last sisso_expand_score
+    int status;             // 0 ok; 1 = tie overflow in sisso_topk
+    unsigned prefix;        // radix select state
+    int need;
+    int total;              // entries considered by the select
+    int n_gt, n_eq;         // gather counters
+    int lists_cap;          // list slots the workspace was laid out for
+    int pad[6];
+    unsigned hist[kHistBins];
+};
+
+struct WsView {
+    WsHeader *h;
+    float *sc;              // n_lists x keep
+    int64_t *id;
+    float *fin_sc;          // kFinalCap gather buffer
+    int64_t *fin_id;
+};
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__host__ __device__ inline size_t ws_bytes_for(int lists, int keep)
+{
+    size_t b = align256(sizeof(WsHeader));
+    b += align256((size_t)lists * keep * sizeof(float));
+    b += align256((size_t)lists * keep * sizeof(int64_t));
+    b += align256((size_t)kFinalCap * sizeof(float));
+    b += align256((size_t)kFinalCap * sizeof(int64_t));
+    return b;
+}
+
+__host__ __device__ inline WsView ws_view(void *ws, int lists, int keep)
+{
+    char *p = (char *)ws;
+    WsView v;
+    v.h = (WsHeader *)p;
+    p += align256(sizeof(WsHeader));
+    v.sc = (float *)p;
+    p += align256((size_t)lists * keep * sizeof(float));
+    v.id = (int64_t *)p;
+    p += align256((size_t)lists * keep * sizeof(int64_t));
+    v.fin_sc = (float *)p;
+    p += align256((size_t)kFinalCap * sizeof(float));
+    v.fin_id = (int64_t *)p;
+    return v;
+}
+
+__global__ void k_ws_reset(WsHeader *h, int keep, int n_lists, int lists_cap)
+{
+    if (threadIdx.x == 0) {
+        h->gthr = 0u;
+        h->keep = keep;
+        h->n_lists = n_lists;
+        h->lists_cap = lists_cap;
+        h->status = 0;
+    }
+}
+
+__global__ void k_ws_append(WsHeader *h, int n_lists)
+{
+    if (threadIdx.x == 0) h->n_lists = n_lists;
+}
+
+__device__ __forceinline__ WsView ws_view_dev(void *ws)
+{
+    const WsHeader *h = (const WsHeader *)ws;
+    return ws_view(ws, h->lists_cap, h->keep);
+}
+
+// Scores of a candidate from its shifted sums.  Returns -1 when the FP32
+// statistics show a non-positive or near-constant variance.
+__device__ __forceinline__ float score_from_sums(double A, double B, double C, double shift, double n,
+                                                 double R1, double Srr)
+{
+    const double var = B - A * (A / n);
+    if (!(var > 0.0)) return -1.0f;
+    const double mean = shift + A / n;
+    if (!(sqrt(var / n) > kConstRel * fabs(mean))) return -1.0f;
+    const double cov = C - A * (R1 / n);
+    double s = fabs(cov) / sqrt(var * Srr);
+    if (!(s <= 1.0)) s = (s > 1.0) ? 1.0 : -1.0;   // rounding above 1, or NaN
+    return (float)s;
+}
+
+// ------------------------------------------------------ pool columns kernel
+
+constexpr int kColWaves = 4;       // waves per block
+constexpr int kColBatch = 16;      // columns per wave between list merges
+
+template <int NU>
+__global__ void __launch_bounds__(256) k_score_columns(
+    sisso_space s, int n, const float *__restrict__ pool32, int64_t ld32,
+    const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
+    const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl,
+    int64_t c_lo, int64_t c_hi, int64_t id_begin, int64_t id_end, int list_base, void *ws,
+    int lists_total, int keep, int cap)
+{
+    extern __shared__ unsigned char smem[];
+    WsView W = ws_view(ws, lists_total, keep);
+    float *lsc = (float *)smem;
+    int64_t *lid = (int64_t *)(smem + cap * sizeof(float));
+    __shared__ int lcnt;
+    __shared__ float lthr;
+    constexpr int PER = 1 + NU;
+    __shared__ float st_sc[kColWaves * kColBatch * PER];
+    __shared__ int64_t st_id[kColWaves * kColBatch * PER];
+    BlockList L{lsc, lid, &lcnt, &lthr, cap, keep};
+    list_init(L);
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int Lv = s.levels;
+    const int64_t newlo = s.pool[Lv - 1], pL = s.pool[Lv];
+    const bool rect = s.rect != 0;
+    const int nu = rect ? s.n_unary : 0;
+    int uop[NU > 0 ? NU : 1];
+#pragma unroll
+    for (int o = 0; o < (NU > 0 ? NU : 1); ++o) uop[o] = (o < nu) ? s.unary[o] : 0;
+    const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
+    const int per_batch = kColWaves * kColBatch;
+    const int64_t ncols = c_hi - c_lo;
+    constexpr int NC = (kColWaves * kColBatch * PER + 255) / 256;
+
+    for (int64_t b0 = (int64_t)blockIdx.x * per_batch; b0 < ncols; b0 += (int64_t)gridDim.x * per_batch) {
+        for (int j = 0; j < kColBatch; ++j) {
+            const int slot_base = (w * kColBatch + j) * PER;
+            const int64_t c = c_lo + b0 + w * kColBatch + j;
+            float scs[PER];
+#pragma unroll
+            for (int o = 0; o < PER; ++o) scs[o] = -1.0f;
+            if (c < c_hi) {
+                const sisso_colstat st = stats[c];
+                const float *col = pool32 + (size_t)c * ld32;
+                const float f0 = st.mean;            // shift of the stored column
+                float a0 = 0.f, b0s = 0.f, c0 = 0.f;
+                float au[NU > 0 ? NU : 1], bu[NU > 0 ? NU : 1], cu[NU > 0 ? NU : 1], sh[NU > 0 ? NU : 1];
+                int badu = 0;
+#pragma unroll
+                for (int o = 0; o < (NU > 0 ? NU : 1); ++o) au[o] = bu[o] = cu[o] = sh[o] = 0.f;
+                const bool do_unary = NU > 0 && rect && c >= newlo;
+                if (do_unary) {
+                    // shift of each unary candidate: its mean over the first 256 samples
+                    const int t = lane * 4;
+                    float4 fv = make_float4(0, 0, 0, 0);
+                    if (t < n) fv = *reinterpret_cast<const float4 *>(col + t);
+                    const float fa[4] = {fv.x, fv.y, fv.z, fv.w};
+                    const int cnt = n < 256 ? n : 256;
+#pragma unroll
+                    for (int o = 0; o < NU; ++o) {
+                        float acc = 0.f;
+                        if (o < nu) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (t + e < n) {
+                                    const float h = unary32(uop[o], fa[e]);
+                                    acc += fabsf(h) <= 1e15f ? h : 0.f;
+                                }
+                        }
+                        sh[o] = (float)(wave_sum((double)acc) / cnt);
+                    }
+                }
+                for (int t = lane * 4; t < n; t += 256) {
+                    const float4 fv = *reinterpret_cast<const float4 *>(col + t);
+                    const float4 rv = *reinterpret_cast<const float4 *>(r32 + t);
+                    const float fa[4] = {fv.x, fv.y, fv.z, fv.w};
+                    const float ra[4] = {rv.x, rv.y, rv.z, rv.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (t + e < n) {
+                            const float g = fa[e] - f0;
+                            a0 += g; b0s = fmaf(g, g, b0s); c0 = fmaf(g, ra[e], c0);
+                            if (do_unary) {
+#pragma unroll
+                                for (int o = 0; o < NU; ++o) {
+                                    if (o < nu) {
+                                        const float h = unary32(uop[o], fa[e]);
+                                        badu |= (!(fabsf(h) <= 1e15f)) << o;
+                                        const float gu = h - sh[o];
+                                        au[o] += gu; bu[o] = fmaf(gu, gu, bu[o]); cu[o] = fmaf(gu, ra[e], cu[o]);
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+                const double A = wave_sum((double)a0), B = wave_sum((double)b0s), C = wave_sum((double)c0);
+                if (st.valid != 0.0f && c >= id_begin && c < id_end)
+                    scs[0] = score_from_sums(A, B, C, (double)f0, nd, R1, Srr);
+                if (do_unary) {
+                    badu = wave_or(badu);
+#pragma unroll
+                    for (int o = 0; o < NU; ++o) {
+                        if (o < nu) {
+                            const double Au = wave_sum((double)au[o]), Bu = wave_sum((double)bu[o]),
+                                         Cu = wave_sum((double)cu[o]);
+                            float bound;
+                            const bool dom = unary_domain_bound(uop[o], st, &bound);
+                            const int64_t uid = pL + (c - newlo) * nu + o;
+                            if (st.valid != 0.0f && dom && !((badu >> o) & 1) && uid >= id_begin &&
+                                uid < id_end)
+                                scs[1 + o] = score_from_sums(Au, Bu, Cu, (double)sh[o], nd, R1, Srr);
+                        }
+                    }
+                }
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int o = 0; o < PER; ++o) {
+                    st_sc[slot_base + o] = scs[o];
+                    st_id[slot_base + o] = o == 0 ? c : pL + (c - newlo) * nu + (o - 1);
+                }
+            }
+        }
+        __syncthreads();
+        float osc[NC];
+        int64_t oid[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int e = threadIdx.x + q * 256;
+            osc[q] = e < kColWaves * kColBatch * PER ? st_sc[e] : -1.0f;
+            oid[q] = e < kColWaves * kColBatch * PER ? st_id[e] : INT64_MAX;
+        }
+        list_offer<NC>(L, osc, oid, &W.h->gthr, excl, n_excl);
+        __syncthreads();
+    }
+    const int list = list_base + blockIdx.x;
+    list_flush(L, &W.h->gthr, W.sc + (size_t)list * keep, W.id + (size_t)list * keep);
+}
+
+// --------------------------------------------------------- binary slice
+
+constexpr int kSC = 32;            // samples per LDS chunk
+
+template <int RU, int RV>
+struct RectCfg {
+    static constexpr int TU = 16 * RU, TV = 16 * RV;
+    static constexpr int TUP = TU + 4, TVP = TV + 4;
+    static constexpr int BUF = kSC * (3 * TUP + 3 * TVP) + kSC;   // floats per buffer
+};
+
+// Result slot of each of the five binary forms (ADD, SUB, MUL, u/v, v/u) in
+// the pair's slot list, or -1 if the op is not in the operator set.
+struct FormSlots {
+    int slot[5];
+};
+
+template <int RU, int RV>
+__global__ void __launch_bounds__(256) k_score_rect(
+    sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
+    const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
+    const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl,
+    int64_t ut_lo, int64_t ut_hi, int64_t id_begin, int64_t id_end, int list_base, void *ws,
+    int lists_total, int keep, int cap)
+{
+    using Cfg = RectCfg<RU, RV>;
+    constexpr int TU = Cfg::TU, TV = Cfg::TV, TUP = Cfg::TUP, TVP = Cfg::TVP;
+    extern __shared__ unsigned char smem[];
+    float *buf0 = (float *)smem;
+    float *buf1 = buf0 + Cfg::BUF;
+    float *lsc = buf1 + Cfg::BUF;
+    int64_t *lid = (int64_t *)(lsc + cap);
+    __shared__ int lcnt;
+    __shared__ float lthr;
+    WsView W = ws_view(ws, lists_total, keep);
+    BlockList L{lsc, lid, &lcnt, &lthr, cap, keep};
+    list_init(L);
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int Lv = s.levels;
+    const int64_t vcount = s.pool[Lv - 1];          // v in P_{L-1}
+    const int64_t ulo = s.pool[Lv - 1], uhi = s.pool[Lv];
+    const int64_t binbase = s.pool[Lv] + s.rect_unary;
+    const int S = s.n_slots;
+    const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
+    const int nch = (n + kSC - 1) / kSC;
+    const int64_t nvt = (vcount + TV - 1) / TV;
+
+    // staging roles: 256 threads load TU (then TV) columns x kSC samples as float4
+    const int scol = tid / (kSC / 4), squad = tid % (kSC / 4);
+
+    for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
+        const int64_t u0 = ulo + ut * TU;
+        // staging column of U for this thread (TU * kSC / 4 == 256 when RU == 2)
+        const int64_t su = u0 + (scol < TU ? scol : 0);
+        const bool su_ok = scol < TU && su < uhi;
+        const sisso_colstat sust = stats[su_ok ? su : ulo];
+        // per-thread operand statistics (compute role)
+        float ufo[RU], urf[RU], umx[RU], umn[RU], urm[RU];
+        bool uval[RU];
+        int64_t uidx[RU];
+#pragma unroll
+        for (int a = 0; a < RU; ++a) {
+            const int64_t u = u0 + ty * RU + a;
+            uval[a] = u < uhi;
+            const sisso_colstat st = stats[uval[a] ? u : ulo];
+            uval[a] = uval[a] && st.valid != 0.0f;
+            ufo[a] = st.mean; urf[a] = st.mean_rcp; umx[a] = st.maxabs; umn[a] = st.minabs;
+            urm[a] = st.rms;
+            uidx[a] = u - ulo;
+        }
+        for (int64_t vt = 0; vt < nvt; ++vt) {
+            const int64_t v0 = vt * TV;
+            const int64_t sv = v0 + (scol < TV ? scol : 0);
+            const bool sv_ok = scol < TV && sv < vcount;
+            const sisso_colstat svst = stats[sv_ok ? sv : 0];
+            float vfo[RV], vrf[RV], vmx[RV], vmn[RV], vrm[RV];
+            bool vval[RV];
+#pragma unroll
+            for (int b = 0; b < RV; ++b) {
+                const int64_t v = v0 + tx * RV + b;
+                vval[b] = v < vcount;
+                const sisso_colstat st = stats[vval[b] ? v : 0];
+                vval[b] = vval[b] && st.valid != 0.0f;
+                vfo[b] = st.mean; vrf[b] = st.mean_rcp; vmx[b] = st.maxabs; vmn[b] = st.minabs;
+                vrm[b] = st.rms;
+            }
+            // shift constants of the multiplicative forms (set by the pilot
+            // below); sums and differences use the operands' exact means
+            float cm[RU][RV], c3[RU][RV], c4[RU][RV];
+            double dA[RU][RV][5], dB[RU][RV][5], dC[RU][RV][5];
+            float fA[RU][RV][5], fB[RU][RV][5], fC[RU][RV][5];
+#pragma unroll
+            for (int a = 0; a < RU; ++a)
+#pragma unroll
+                for (int b = 0; b < RV; ++b)
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) {
+                        dA[a][b][k] = dB[a][b][k] = dC[a][b][k] = 0.0;
+                        fA[a][b][k] = fB[a][b][k] = fC[a][b][k] = 0.0f;
+                    }
+
+            // register prefetch of one chunk
+            float4 pu = make_float4(0, 0, 0, 0), pv = make_float4(0, 0, 0, 0), pr = make_float4(0, 0, 0, 0);
+            auto load_chunk = [&](int ch) {
+                const int t0 = ch * kSC + squad * 4;
+                pu = make_float4(0, 0, 0, 0);
+                pv = make_float4(0, 0, 0, 0);
+                if (t0 < n) {
+                    if (su_ok) pu = *reinterpret_cast<const float4 *>(pool32 + (size_t)su * ld32 + t0);
+                    if (sv_ok) pv = *reinterpret_cast<const float4 *>(pool32 + (size_t)sv * ld32 + t0);
+                }
+                if (tid < kSC / 4) {
+                    const int tr = ch * kSC + tid * 4;
+                    pr = tr < n ? *reinterpret_cast<const float4 *>(r32 + tr) : make_float4(0, 0, 0, 0);
+                }
+            };
+            auto store_chunk = [&](float *bf) {
+                float *Ur = bf, *Us = Ur + kSC * TUP, *Uq = Us + kSC * TUP;
+                float *Vr = Uq + kSC * TUP, *Vs = Vr + kSC * TVP, *Vq = Vs + kSC * TVP;
+                float *R = Vq + kSC * TVP;
+                const float uv[4] = {pu.x, pu.y, pu.z, pu.w};
+                const float vv[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int srow = squad * 4 + e;
+                    if (scol < TU) {
+                        Ur[srow * TUP + scol] = uv[e];
+                        Us[srow * TUP + scol] = uv[e] - sust.mean;
+                        Uq[srow * TUP + scol] = __builtin_amdgcn_rcpf(uv[e]);
+                    }
+                    if (scol < TV) {
+                        Vr[srow * TVP + scol] = vv[e];
+                        Vs[srow * TVP + scol] = vv[e] - svst.mean;
+                        Vq[srow * TVP + scol] = __builtin_amdgcn_rcpf(vv[e]);
+                    }
+                }
+                if (tid < kSC / 4) {
+                    R[tid * 4 + 0] = pr.x; R[tid * 4 + 1] = pr.y;
+                    R[tid * 4 + 2] = pr.z; R[tid * 4 + 3] = pr.w;
+                }
+            };
+
+            __syncthreads();
+            load_chunk(0);
+            store_chunk(buf0);
+            __syncthreads();
+            {
+                // pilot: shift of the multiplicative forms = their mean over the
+                // first chunk, so that B - A^2/n does not cancel
+                const float *Ur = buf0, *Uq = Ur + 2 * kSC * TUP;
+                const float *Vr = Uq + kSC * TUP, *Vq = Vr + 2 * kSC * TVP;
+                const int c0 = n < kSC ? n : kSC;
+                float pm[RU][RV], p3[RU][RV], p4[RU][RV];
+#pragma unroll
+                for (int a = 0; a < RU; ++a)
+#pragma unroll
+                    for (int b = 0; b < RV; ++b) pm[a][b] = p3[a][b] = p4[a][b] = 0.0f;
+                for (int t = 0; t < c0; ++t) {
+#pragma unroll
+                    for (int a = 0; a < RU; ++a)
+#pragma unroll
+                        for (int b = 0; b < RV; ++b) {
+                            const float ur = Ur[t * TUP + ty * RU + a], uq = Uq[t * TUP + ty * RU + a];
+                            const float vr = Vr[t * TVP + tx * RV + b], vq = Vq[t * TVP + tx * RV + b];
+                            pm[a][b] = fmaf(ur, vr, pm[a][b]);
+                            p3[a][b] = fmaf(ur, vq, p3[a][b]);
+                            p4[a][b] = fmaf(vr, uq, p4[a][b]);
+                        }
+                }
+                const float inv = 1.0f / (float)c0;
+#pragma unroll
+                for (int a = 0; a < RU; ++a)
+#pragma unroll
+                    for (int b = 0; b < RV; ++b) {
+                        cm[a][b] = pm[a][b] * inv;
+                        c3[a][b] = p3[a][b] * inv;
+                        c4[a][b] = p4[a][b] * inv;
+                    }
+            }
+            for (int ch = 0; ch < nch; ++ch) {
+                float *bf = (ch & 1) ? buf1 : buf0;
+                if (ch + 1 < nch) load_chunk(ch + 1);
+                const float *Ur = bf, *Us = Ur + kSC * TUP, *Uq = Us + kSC * TUP;
+                const float *Vr = Uq + kSC * TUP, *Vs = Vr + kSC * TVP, *Vq = Vs + kSC * TVP;
+                const float *R = Vq + kSC * TVP;
+                const int cnt = (n - ch * kSC) < kSC ? (n - ch * kSC) : kSC;
+                auto step = [&](int t) {
+                    float ur[RU], us[RU], uq[RU], vr[RV], vs[RV], vq[RV];
+#pragma unroll
+                    for (int a = 0; a < RU; ++a) {
+                        ur[a] = Ur[t * TUP + ty * RU + a];
+                        us[a] = Us[t * TUP + ty * RU + a];
+                        uq[a] = Uq[t * TUP + ty * RU + a];
+                    }
+#pragma unroll
+                    for (int b = 0; b < RV; ++b) {
+                        vr[b] = Vr[t * TVP + tx * RV + b];
+                        vs[b] = Vs[t * TVP + tx * RV + b];
+                        vq[b] = Vq[t * TVP + tx * RV + b];
+                    }
+                    const float r = R[t];
+#pragma unroll
+                    for (int a = 0; a < RU; ++a)
+#pragma unroll
+                        for (int b = 0; b < RV; ++b) {
+                            float g[5];
+                            g[0] = us[a] + vs[b];
+                            g[1] = us[a] - vs[b];
+                            g[2] = fmaf(ur[a], vr[b], -cm[a][b]);
+                            g[3] = fmaf(ur[a], vq[b], -c3[a][b]);
+                            g[4] = fmaf(vr[b], uq[a], -c4[a][b]);
+#pragma unroll
+                            for (int k = 0; k < 5; ++k) {
+                                fA[a][b][k] += g[k];
+                                fB[a][b][k] = fmaf(g[k], g[k], fB[a][b][k]);
+                                fC[a][b][k] = fmaf(g[k], r, fC[a][b][k]);
+                            }
+                        }
+                };
+                if (cnt == kSC) {
+#pragma unroll 4
+                    for (int t = 0; t < kSC; ++t) step(t);
+                } else {
+                    for (int t = 0; t < cnt; ++t) step(t);
+                }
+                // carry the chunk's FP32 partial sums in FP64
+#pragma unroll
+                for (int a = 0; a < RU; ++a)
+#pragma unroll
+                    for (int b = 0; b < RV; ++b)
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) {
+                            dA[a][b][k] += (double)fA[a][b][k];
+                            dB[a][b][k] += (double)fB[a][b][k];
+                            dC[a][b][k] += (double)fC[a][b][k];
+                            fA[a][b][k] = fB[a][b][k] = fC[a][b][k] = 0.0f;
+                        }
+                if (ch + 1 < nch) store_chunk((ch & 1) ? buf0 : buf1);
+                __syncthreads();
+            }
+
+            // scores, validity and ids of the tile's candidates
+            float osc[RU * RV * 5];
+            int64_t oid[RU * RV * 5];
+#pragma unroll
+            for (int a = 0; a < RU; ++a)
+#pragma unroll
+                for (int b = 0; b < RV; ++b) {
+                    const int64_t v = v0 + tx * RV + b;
+                    const bool ok = uval[a] && vval[b];
+                    const double shifts[5] = {(double)ufo[a] + (double)vfo[b], (double)ufo[a] - (double)vfo[b],
+                                              (double)cm[a][b], (double)c3[a][b], (double)c4[a][b]};
+                    const float bnd[5] = {umx[a] + vmx[b], umx[a] + vmx[b], umx[a] * vmx[b],
+                                          vmn[b] > 0.f ? umx[a] / vmn[b] : INFINITY,
+                                          umn[a] > 0.f ? vmx[b] / umn[a] : INFINITY};
+                    const bool dom[5] = {true, true, true, vmn[b] > 0.f, umn[a] > 0.f};
+                    int need = 0;
+#pragma unroll
+                    for (int k = 0; k < 5; ++k)
+                        if (ok && dom[k] && fs.slot[k] >= 0 && !(bnd[k] <= kCapSafe)) need |= 1 << k;
+                    int over = 0;
+                    if (need) {
+                        // exact per-sample magnitude check (rare)
+                        const int64_t u = u0 + ty * RU + a;
+                        const float *cu = pool32 + (size_t)u * ld32, *cv = pool32 + (size_t)v * ld32;
+                        for (int t = 0; t < n; ++t) {
+                            const float x = cu[t], y = cv[t];
+                            const float fv[5] = {x + y, x - y, x * y, x * __builtin_amdgcn_rcpf(y),
+                                                 y * __builtin_amdgcn_rcpf(x)};
+#pragma unroll
+                            for (int k = 0; k < 5; ++k)
+                                if (((need >> k) & 1) && !(fabsf(fv[k]) <= 1e15f)) over |= 1 << k;
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) {
+                        const int e = (a * RV + b) * 5 + k;
+                        float sc = -1.0f;
+                        int64_t fid = INT64_MAX;
+                        if (fs.slot[k] >= 0 && ok && dom[k] && !((over >> k) & 1)) {
+                            fid = binbase + (uidx[a] * vcount + v) * S + fs.slot[k];
+                            if (fid >= id_begin && fid < id_end) {
+                                sc = score_from_sums(dA[a][b][k], dB[a][b][k], dC[a][b][k], shifts[k], nd,
+                                                     R1, Srr);
+                                if (k < 2) {
+                                    // a sum or difference that cancels to rounding noise
+                                    const double var = dB[a][b][k] - dA[a][b][k] * (dA[a][b][k] / nd);
+                                    const double scale = fmax((double)urm[a], (double)vrm[b]);
+                                    if (!(sqrt(fmax(var, 0.0) / nd) > kCancelRel * scale)) sc = -1.0f;
+                                }
+                            }
+                        }
+                        osc[e] = sc;
+                        oid[e] = fid;
+                    }
+                }
+            list_offer<RU * RV * 5>(L, osc, oid, &W.h->gthr, excl, n_excl);
+        }
+    }
+    const int list = list_base + blockIdx.x;
+    list_flush(L, &W.h->gthr, W.sc + (size_t)list * keep, W.id + (size_t)list * keep);
+}
+
+// ----------------------------------------------------------------- top-k
+
+__device__ __forceinline__ bool considered(float sc, unsigned g)
+{
+    return sc >= 0.0f && __float_as_uint(sc) >= g;
+}
+
+__global__ void k_tk_init(WsHeader *h, int k)
+{
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h->hist[i] = 0u;
+    if (threadIdx.x == 0) {
+        h->prefix = 0u; h->need = k; h->total = 0; h->n_gt = 0; h->n_eq = 0; h->status = 0;
+    }
+}
+
+// pass 0: bits [31:20]; pass 1: bits [19:8] under prefix; pass 2: bits [7:0].
+__global__ void __launch_bounds__(256) k_tk_hist(void *ws, int pass)
+{
+    __shared__ unsigned hist[kHistBins];
+    WsView W = ws_view_dev(ws);
+    const int keep = W.h->keep;
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const unsigned g = W.h->gthr, pre = W.h->prefix;
+    const int64_t M = (int64_t)W.h->n_lists * keep;
+    unsigned cnt = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x) {
+        const float sc = W.sc[e];
+        if (!considered(sc, g)) continue;
+        const unsigned u = __float_as_uint(sc);
+        unsigned bin;
+        if (pass == 0) { bin = u >> 20; cnt++; }
+        else if (pass == 1) { if ((u >> 20) != (pre >> 20)) continue; bin = (u >> 8) & 0xFFFu; }
+        else { if ((u >> 8) != (pre >> 8)) continue; bin = u & 0xFFu; }
+        atomicAdd(&hist[bin], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+        if (hist[i]) atomicAdd(&W.h->hist[i], hist[i]);
+    if (pass == 0 && cnt) atomicAdd(&W.h->total, (int)cnt);
+}
+
+__global__ void k_tk_select(WsHeader *h, int pass)
+{
+    // single thread scan from the top bin; then clear the histogram
+    if (threadIdx.x == 0) {
+        const int bins = pass == 2 ? 256 : kHistBins;
+        const int shift = pass == 0 ? 20 : (pass == 1 ? 8 : 0);
+        int need = h->need;
+        if (pass == 0 && h->total <= need) {
+            h->need = -1;       // take everything that is considered
+        } else if (need > 0) {
+            int b = bins - 1;
+            for (; b > 0; --b) {
+                const int c = (int)h->hist[b];
+                if (c >= need) break;
+                need -= c;
+            }
+            h->prefix |= ((unsigned)b) << shift;
+            h->need = need;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h->hist[i] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_tk_gather(void *ws)
+{
+    WsView W = ws_view_dev(ws);
+    const int keep = W.h->keep;
+    const unsigned g = W.h->gthr, sstar = W.h->prefix;
+    const bool all = W.h->need < 0;
+    const int64_t M = (int64_t)W.h->n_lists * keep;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x) {
+        const float sc = W.sc[e];
+        if (!considered(sc, g)) continue;
+        const unsigned u = __float_as_uint(sc);
+        if (all || u >= sstar) {
+            const int slot = atomicAdd(&W.h->n_gt, 1);
+            if (slot < kFinalCap) { W.fin_sc[slot] = sc; W.fin_id[slot] = W.id[e]; }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_tk_final(void *ws, int k, int64_t *__restrict__ out_ids,
+                                                   float *__restrict__ out_sc, int32_t *out_count)
+{
+    extern __shared__ unsigned char smem[];
+    WsView W = ws_view_dev(ws);
+    if (k > W.h->keep) {
+        // k larger than the list length the workspace was filled with
+        for (int i = threadIdx.x; i < k; i += blockDim.x) { out_ids[i] = INT64_MAX; out_sc[i] = -1.0f; }
+        if (threadIdx.x == 0) { *out_count = 0; W.h->status = 2; }
+        return;
+    }
+    const int m = W.h->n_gt;
+    const int cap = next_pow2(m < kFinalCap ? (m > 1 ? m : 2) : kFinalCap);
+    float *sc = (float *)smem;
+    int64_t *id = (int64_t *)(smem + kFinalCap * sizeof(float));
+    for (int i = threadIdx.x; i < cap; i += blockDim.x) {
+        sc[i] = i < m && i < kFinalCap ? W.fin_sc[i] : -1.0f;
+        id[i] = i < m && i < kFinalCap ? W.fin_id[i] : INT64_MAX;
+    }
+    __syncthreads();
+    bitonic_sort_keys(sc, id, cap);
+    int valid = m < kFinalCap ? m : kFinalCap;
+    const int take = valid < k ? valid : k;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        out_ids[i] = i < take ? id[i] : INT64_MAX;
+        out_sc[i] = i < take ? sc[i] : -1.0f;
+    }
+    if (threadIdx.x == 0) {
+        *out_count = take;
+        if (m > kFinalCap) W.h->status = 1;
+    }
+}
+
+}  // namespace sisso
+
+// ------------------------------------------------------------------ C ABI
+
+using namespace sisso;
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+constexpr int kMaxColGrid = 2048;
+constexpr int kMaxRectGrid = 1024;
+
+struct Plan {
+    int64_t c_lo = 0, c_hi = 0;       // columns for k_score_columns
+    int64_t ut_lo = 0, ut_hi = 0;     // u tiles for k_score_rect
+    int g_cols = 0, g_rect = 0;
+    int ru = 2, rv = 2;
+};
+
+int rect_tu(int ru) { return 16 * ru; }
+
+int max_col_grid(const sisso_score_args *a) { return a->grid > 0 ? a->grid : kMaxColGrid; }
+int max_rect_grid(const sisso_score_args *a) { return a->grid > 0 ? a->grid : kMaxRectGrid; }
+
+void tile_shape(const sisso_score_args *a, int *ru, int *rv)
+{
+    switch (a->tile) {
+    case 1: *ru = 2; *rv = 1; break;
+    case 2: *ru = 1; *rv = 2; break;
+    default: *ru = 2; *rv = 2; break;
+    }
+}
+
+Plan make_plan(const sisso_space *s, const sisso_score_args *a, int64_t begin, int64_t end)
+{
+    Plan p;
+    tile_shape(a, &p.ru, &p.rv);
+    const int L = s->levels;
+    const int64_t pL = s->pool[L], newlo = s->pool[L - 1];
+    // pool columns in range
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    if (begin < pL) { lo = begin; hi = end < pL ? end : pL; }
+    // unary slice ids -> their N_L columns
+    if (s->rect && s->n_unary > 0) {
+        const int64_t ub = pL, ue = pL + s->rect_unary;
+        const int64_t b = begin > ub ? begin : ub, e = end < ue ? end : ue;
+        if (b < e) {
+            const int64_t cl = newlo + (b - pL) / s->n_unary;
+            const int64_t ch = newlo + (e - 1 - pL) / s->n_unary + 1;
+            lo = lo < cl ? lo : cl;
+            hi = hi > ch ? hi : ch;
+        }
+    }
+    if (lo < hi) {
+        p.c_lo = lo; p.c_hi = hi;
+        const int64_t batches = (hi - lo + kColWaves * kColBatch - 1) / (kColWaves * kColBatch);
+        p.g_cols = (int)(batches < max_col_grid(a) ? batches : max_col_grid(a));
+    }
+    if (s->rect) {
+        const int64_t bb = pL + s->rect_unary, be = s->total;
+        const int64_t b = begin > bb ? begin : bb, e = end < be ? end : be;
+        if (b < e) {
+            const int64_t per_u = newlo * s->n_slots;
+            const int64_t ul = (b - bb) / per_u, uh = (e - 1 - bb) / per_u + 1;
+            const int tu = rect_tu(p.ru);
+            p.ut_lo = ul / tu;
+            p.ut_hi = (uh + tu - 1) / tu;
+            const int64_t tiles = p.ut_hi - p.ut_lo;
+            p.g_rect = (int)(tiles < max_rect_grid(a) ? tiles : max_rect_grid(a));
+        }
+    }
+    return p;
+}
+
+int lists_capacity(const sisso_space *s, const sisso_score_args *a)
+{
+    const Plan p = make_plan(s, a, 0, s->total);
+    return p.g_cols + p.g_rect;
+}
+
+int list_cap(int keep) { return next_pow2(keep + 256); }
+
+size_t rect_smem(int ru, int rv, int cap)
+{
+    int buf = 0;
+    if (ru == 2 && rv == 2) buf = RectCfg<2, 2>::BUF;
+    else if (ru == 2 && rv == 1) buf = RectCfg<2, 1>::BUF;
+    else buf = RectCfg<1, 2>::BUF;
+    return (size_t)2 * buf * sizeof(float) + (size_t)cap * (sizeof(float) + sizeof(int64_t));
+}
+
+}  // namespace
+
+extern "C" size_t sisso_score_workspace_size(const sisso_space *space, const sisso_score_args *args)
+{
+    if (!space || !args || args->keep < 1 || args->keep > SISSO_MAX_KEEP || space->total <= 0) return 0;
+    return ws_bytes_for(lists_capacity(space, args), args->keep);
+}
+
+extern "C" int32_t sisso_expand_score_lists(const sisso_space *space, const sisso_score_args *args,
+                                            int64_t cand_begin, int64_t cand_end)
+{
+    if (!space || !args || space->total <= 0 || cand_begin < 0 || cand_end > space->total ||
+        cand_begin >= cand_end || args->tile < 0 || args->tile > 2 || args->grid < 0)
+        return -1;
+    const Plan p = make_plan(space, args, cand_begin, cand_end);
+    return p.g_cols + p.g_rect;
+}
+
+extern "C" sisso_status sisso_score_reset(void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ws) return SISSO_E_NULL;
+    if (ws_bytes < sizeof(WsHeader)) return SISSO_E_WORKSPACE;
+    hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(64), 0, as_stream(stream), (WsHeader *)ws, 1, 0, 0);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso_score_args *args,
+                                           int64_t cand_begin, int64_t cand_end, void *ws,
+                                           size_t ws_bytes, void *stream)
+{
+    if (!space || !args || !ws || !args->pool32 || !args->stats || !args->r32 || !args->info)
+        return SISSO_E_NULL;
+    if (args->n_exclude > 0 && !args->exclude) return SISSO_E_NULL;
+    if (space->total <= 0 || space->levels < 1 || space->levels > SISSO_MAX_LEVELS) return SISSO_E_SHAPE;
+    if (args->n < 2 || args->n > SISSO_MAX_N || args->ld32 < args->n || (args->ld32 % 4) != 0 ||
+        args->n_exclude < 0)
+        return SISSO_E_SHAPE;
+    if (args->keep < 1 || args->keep > SISSO_MAX_KEEP) return SISSO_E_RANGE;
+    if (cand_begin < 0 || cand_end > space->total || cand_begin >= cand_end) return SISSO_E_RANGE;
+    if (args->precision != SISSO_FP32) return SISSO_E_UNSUPPORTED;
+    if (args->tile < 0 || args->tile > 2 || args->grid < 0) return SISSO_E_RANGE;
+    const int lists = lists_capacity(space, args);
+    if (ws_bytes < ws_bytes_for(lists, args->keep)) return SISSO_E_WORKSPACE;
+    if (space->rect && space->pool[space->levels - 1] < 1) return SISSO_E_SHAPE;
+
+    const Plan p = make_plan(space, args, cand_begin, cand_end);
+    if (args->list_base < 0 || args->list_base + p.g_cols + p.g_rect > lists) return SISSO_E_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    const int keep = args->keep, cap = list_cap(keep);
+    const int base = args->list_base;
+    if (base == 0)
+        hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(64), 0, st, (WsHeader *)ws, keep, p.g_cols + p.g_rect, lists);
+    else
+        hipLaunchKernelGGL(k_ws_append, dim3(1), dim3(64), 0, st, (WsHeader *)ws, base + p.g_cols + p.g_rect);
+    if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
+    const size_t lsmem = (size_t)cap * (sizeof(float) + sizeof(int64_t));
+    if (p.g_cols > 0) {
+        const int nu = space->rect ? space->n_unary : 0;
+        if (nu == 0)
+            hipLaunchKernelGGL(k_score_columns<0>, dim3(p.g_cols), dim3(256), lsmem, st, *space, args->n,
+                               args->pool32, args->ld32, args->stats, args->r32, args->info, args->exclude,
+                               args->n_exclude, p.c_lo, p.c_hi, cand_begin, cand_end, base, ws, lists, keep, cap);
+        else if (nu <= 3)
+            hipLaunchKernelGGL(k_score_columns<3>, dim3(p.g_cols), dim3(256), lsmem, st, *space, args->n,
+                               args->pool32, args->ld32, args->stats, args->r32, args->info, args->exclude,
+                               args->n_exclude, p.c_lo, p.c_hi, cand_begin, cand_end, base, ws, lists, keep, cap);
+        else
+            hipLaunchKernelGGL(k_score_columns<8>, dim3(p.g_cols), dim3(256), lsmem, st, *space, args->n,
+                               args->pool32, args->ld32, args->stats, args->r32, args->info, args->exclude,
+                               args->n_exclude, p.c_lo, p.c_hi, cand_begin, cand_end, base, ws, lists, keep, cap);
+        if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
+    }
+    if (p.g_rect > 0) {
+        FormSlots fs;
+        for (int k = 0; k < 5; ++k) fs.slot[k] = -1;
+        for (int sl = 0; sl < space->n_slots; ++sl) {
+            const int op = space->slot_op[sl], rev = space->slot_rev[sl];
+            const int form = op == SISSO_DIV ? (rev ? 4 : 3) : op;
+            fs.slot[form] = sl;
+        }
+        const size_t smem = rect_smem(p.ru, p.rv, cap);
+        auto launch = [&](auto kern) -> sisso_status {
+            if (!allow_dynamic_lds(kern, smem)) return SISSO_E_UNSUPPORTED;
+            hipLaunchKernelGGL(kern, dim3(p.g_rect), dim3(256), smem, st, *space, fs, args->n, args->pool32,
+                               args->ld32, args->stats, args->r32, args->info, args->exclude, args->n_exclude,
+                               p.ut_lo, p.ut_hi, cand_begin, cand_end, base + p.g_cols, ws, lists, keep, cap);
+            return SISSO_OK;
+        };
+        sisso_status rs;
+        if (p.ru == 2 && p.rv == 2) rs = launch(k_score_rect<2, 2>);
+        else if (p.ru == 2 && p.rv == 1) rs = launch(k_score_rect<2, 1>);
+        else rs = launch(k_score_rect<1, 2>);
+        if (rs != SISSO_OK) return rs;
+        if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
+    }
+    return SISSO_OK;
+}
+
+extern "C" sisso_status sisso_topk(const void *ws_c, size_t ws_bytes, int32_t k, int64_t *out_ids,
+                                   float *out_scores, int32_t *out_count, void *stream)
+{
+    void *ws = const_cast<void *>(ws_c);
+    if (!ws || !out_ids || !out_scores || !out_count) return SISSO_E_NULL;
+    if (k < 1 || k > SISSO_MAX_KEEP) return SISSO_E_RANGE;
+    if (ws_bytes < ws_bytes_for(0, 1)) return SISSO_E_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    WsHeader *h = (WsHeader *)ws;
+    hipLaunchKernelGGL(k_tk_init, dim3(1), dim3(256), 0, st, h, k);
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_tk_hist, dim3(512), dim3(256), 0, st, ws, pass);
+        hipLaunchKernelGGL(k_tk_select, dim3(1), dim3(256), 0, st, h, pass);
+    }
+    hipLaunchKernelGGL(k_tk_gather, dim3(512), dim3(256), 0, st, ws);
+    const size_t smem = (size_t)kFinalCap * (sizeof(float) + sizeof(int64_t));
+    if (!allow_dynamic_lds(k_tk_final, smem)) return SISSO_E_UNSUPPORTED;
+    hipLaunchKernelGGL(k_tk_final, dim3(1), dim3(1024), smem, st, ws, k, out_ids, out_scores, out_count);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}

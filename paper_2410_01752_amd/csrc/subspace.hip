@@ -1,0 +1,320 @@
+// subspace.hip -- subspace update S_t = S_{t-1} u SIS(r) (Sec. 2.3,
+// eq. subspace-expansion) with the duplicate rule for non-unique features
+// (Sec. 2.1: some combinations are not unique).
+//
+// The screened list is re-scored in FP64 (|corr| of the FP64 feature with the
+// FP64 residual).  Duplicate classes are the connected components of
+// 1 - |corr(f, g)| <= 1e-9 over list + current subspace; a class touching the
+// subspace is dropped; a class is represented by its smallest id and scored by
+// its best member; the best k classes (score desc, id asc) are appended.
+#include "linalg.hpp"
+
+namespace sisso {
+
+constexpr int kEdgeCap = 1 << 20;
+
+struct SubWs {
+    double *Z;        // n x nodes, standardised (ld = ldz)
+    double *zr;       // standardised residual
+    double *score;    // FP64 score per node (candidates)
+    int *ok;          // per node
+    int2 *edges;
+    int *n_edges;
+    int ldz;
+};
+
+__host__ __device__ inline size_t sub_ws_bytes(int n, int nodes)
+{
+    const size_t ldz = (size_t)((n + 3) & ~3);
+    size_t b = 0;
+    b += ldz * nodes * sizeof(double);
+    b += ldz * sizeof(double);
+    b += (size_t)nodes * sizeof(double);
+    b += (size_t)nodes * sizeof(int);
+    b = (b + 255) & ~(size_t)255;
+    b += (size_t)kEdgeCap * sizeof(int2);
+    b += 256;
+    return b;
+}
+
+__host__ __device__ inline SubWs sub_ws_view(void *ws, int n, int nodes)
+{
+    SubWs w;
+    w.ldz = (n + 3) & ~3;
+    char *p = (char *)ws;
+    w.Z = (double *)p; p += (size_t)w.ldz * nodes * sizeof(double);
+    w.zr = (double *)p; p += (size_t)w.ldz * sizeof(double);
+    w.score = (double *)p; p += (size_t)nodes * sizeof(double);
+    w.ok = (int *)p; p += (size_t)nodes * sizeof(int);
+    size_t off = (size_t)(p - (char *)ws);
+    off = (off + 255) & ~(size_t)255;
+    p = (char *)ws + off;
+    w.edges = (int2 *)p; p += (size_t)kEdgeCap * sizeof(int2);
+    w.n_edges = (int *)p;
+    return w;
+}
+
+__global__ void __launch_bounds__(256) k_sub_resid(const double *__restrict__ r, int n, SubWs w)
+{
+    __shared__ double red[16];
+    standardize_column(r, n, w.zr, nullptr, nullptr, nullptr, red);
+    if (threadIdx.x == 0) *w.n_edges = 0;
+}
+
+// node q < m_prev: subspace column; else candidate q - m_prev.
+__global__ void __launch_bounds__(256) k_sub_standardize(const double *__restrict__ sub, int lds, int m_prev,
+                                                         const double *__restrict__ cand, int ldc,
+                                                         const int32_t *__restrict__ cvalid,
+                                                         const int32_t *__restrict__ count_dev, int n, SubWs w)
+{
+    __shared__ double red[16];
+    const int q = blockIdx.x;
+    const bool is_c = q >= m_prev;
+    const int ci = q - m_prev;
+    const double *x = is_c ? cand + (size_t)ci * ldc : sub + (size_t)q * lds;
+    double *z = w.Z + (size_t)q * w.ldz;
+    int ok_live = 1;
+    if (is_c) ok_live = (ci < *count_dev) && cvalid[ci] != 0;
+    if (!ok_live) {
+        for (int t = threadIdx.x; t < n; t += blockDim.x) z[t] = 0.0;
+        if (threadIdx.x == 0) { w.ok[q] = 0; w.score[q] = -1.0; }
+        return;
+    }
+    int okc;
+    __shared__ int okc_s;
+    standardize_column(x, n, z, nullptr, nullptr, &okc_s, red);
+    okc = okc_s;
+    double d = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) d += z[t] * w.zr[t];
+    const double dot = block_sum(d, red);
+    if (threadIdx.x == 0) {
+        w.ok[q] = okc;
+        w.score[q] = okc ? fabs(dot) : -1.0;
+    }
+}
+
+// Duplicate edges between candidate rows and all earlier nodes.
+__global__ void __launch_bounds__(256) k_sub_edges(int m_prev, int nodes, int n, SubWs w)
+{
+    __shared__ double As[kGK][kGT + 1];
+    __shared__ double Bs[kGK][kGT + 1];
+    const int bi = blockIdx.y, bj = blockIdx.x;     // rows: nodes, cols: nodes
+    if (bj > bi) return;                              // only j <= i tiles
+    if ((bi + 1) * kGT <= m_prev) return;             // rows all subspace members
+    double acc[2][2];
+    gemm_tile_tn(w.Z, nodes, w.Z, nodes, n, w.ldz, bi, bj, acc, As, Bs);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int i = bi * kGT + ty * 2 + a, j = bj * kGT + tx * 2 + b;
+            if (i < nodes && j < i && i >= m_prev && w.ok[i] && w.ok[j] && 1.0 - fabs(acc[a][b]) <= kDupTol) {
+                const int e = atomicAdd(w.n_edges, 1);
+                if (e < kEdgeCap) w.edges[e] = make_int2(i, j);
+            }
+        }
+}
+
+__device__ __forceinline__ bool rank64_before(double sa, int64_t ia, double sb, int64_t ib)
+{
+    return sa > sb || (sa == sb && ia < ib);
+}
+
+// Components, classes, ranking and the new members (one block).
+__global__ void __launch_bounds__(1024) k_sub_classes(int m_prev, int nodes, const int64_t *__restrict__ cand_ids,
+                                                      int64_t *__restrict__ sub_ids, int k, int32_t *n_new,
+                                                      int32_t *n_classes, int *__restrict__ new_src, SubWs w)
+{
+    extern __shared__ unsigned char smem[];
+    int *label = (int *)smem;                                   // nodes
+    unsigned long long *rep = (unsigned long long *)(label + ((nodes + 1) & ~1));   // min id per root
+    unsigned long long *best = rep + nodes;                     // max score bits per root
+    double *ksc = (double *)(best + nodes);                     // class list (pow2)
+    int64_t *kid = (int64_t *)(ksc + next_pow2(nodes));
+    __shared__ int changed, ncls;
+    const int ne = min(*w.n_edges, kEdgeCap);
+    for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
+        label[i] = i;
+        rep[i] = ~0ull;
+        best[i] = 0ull;
+    }
+    __syncthreads();
+    // min-label propagation over the edges until stable
+    for (;;) {
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+            const int2 ed = w.edges[e];
+            const int la = label[ed.x], lb = label[ed.y];
+            if (la != lb) {
+                const int m = la < lb ? la : lb;
+                atomicMin(&label[ed.x], m);
+                atomicMin(&label[ed.y], m);
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        // pointer jumping
+        for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
+            int l = label[i];
+            while (label[l] != l) l = label[l];
+            if (l != label[i]) { atomicMin(&label[i], l); }
+        }
+        __syncthreads();
+        if (!changed) break;
+        __syncthreads();
+    }
+    // per root: min candidate id and max FP64 score over valid candidates
+    for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
+        if (i >= m_prev && w.ok[i]) {
+            const int r = label[i];
+            atomicMin(&rep[r], (unsigned long long)cand_ids[i - m_prev]);
+            atomicMax(&best[r], (unsigned long long)__double_as_longlong(w.score[i]));
+        }
+    }
+    if (threadIdx.x == 0) ncls = 0;
+    __syncthreads();
+    // surviving classes: roots not touching the subspace (min label >= m_prev)
+    for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
+        if (label[i] == i && i >= m_prev && rep[i] != ~0ull) {
+            const int q = atomicAdd(&ncls, 1);
+            ksc[q] = __longlong_as_double((long long)best[i]);
+            kid[q] = (int64_t)rep[i];
+        }
+    }
+    __syncthreads();
+    const int nc = ncls;
+    const int cap = next_pow2(nc > 1 ? nc : 2);
+    for (int i = nc + threadIdx.x; i < cap; i += blockDim.x) { ksc[i] = -1.0; kid[i] = INT64_MAX; }
+    __syncthreads();
+    for (int size = 2; size <= cap; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < (cap >> 1); t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1)), j = i + stride;
+                const bool up = (i & size) == 0;
+                if (rank64_before(ksc[j], kid[j], ksc[i], kid[i]) == up) {
+                    const double ts = ksc[i]; ksc[i] = ksc[j]; ksc[j] = ts;
+                    const int64_t ti = kid[i]; kid[i] = kid[j]; kid[j] = ti;
+                }
+            }
+            __syncthreads();
+        }
+    const int take = nc < k ? nc : k;
+    // source candidate of each new member: the candidate whose id is the rep
+    for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
+        if (i >= m_prev && w.ok[i]) {
+            const int64_t id = cand_ids[i - m_prev];
+            // binary search is not possible (ksc order); scan the taken list
+            for (int q = 0; q < take; ++q)
+                if (kid[q] == id) new_src[q] = i - m_prev;
+        }
+    }
+    for (int q = threadIdx.x; q < take; q += blockDim.x) sub_ids[m_prev + q] = kid[q];
+    if (threadIdx.x == 0) { *n_new = take; *n_classes = nc; }
+}
+
+__global__ void __launch_bounds__(256) k_sub_gather(const double *__restrict__ cand, int ldc,
+                                                    const int *__restrict__ new_src, const int32_t *__restrict__ n_new,
+                                                    int n, double *__restrict__ sub, int lds, int m_prev)
+{
+    const int q = blockIdx.x;
+    if (q >= *n_new) return;
+    const double *src = cand + (size_t)new_src[q] * ldc;
+    double *dst = sub + (size_t)(m_prev + q) * lds;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
+}
+
+// Sort ids ascending (one block) and record the permutation.
+__global__ void __launch_bounds__(1024) k_sort_ids(const int64_t *__restrict__ ids, int m, int64_t *__restrict__ ids_sorted,
+                                                   int32_t *__restrict__ perm)
+{
+    __shared__ int64_t key[SISSO_MAX_SUBSPACE];
+    __shared__ int pos[SISSO_MAX_SUBSPACE];
+    const int cap = next_pow2(m > 1 ? m : 2);
+    for (int i = threadIdx.x; i < cap; i += blockDim.x) {
+        key[i] = i < m ? ids[i] : INT64_MAX;
+        pos[i] = i;
+    }
+    __syncthreads();
+    for (int size = 2; size <= cap; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < (cap >> 1); t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1)), j = i + stride;
+                const bool up = (i & size) == 0;
+                const bool j_first = key[j] < key[i] || (key[j] == key[i] && pos[j] < pos[i]);
+                if (j_first == up) {
+                    const int64_t tk = key[i]; key[i] = key[j]; key[j] = tk;
+                    const int tp = pos[i]; pos[i] = pos[j]; pos[j] = tp;
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) { ids_sorted[i] = key[i]; perm[i] = pos[i]; }
+}
+
+__global__ void __launch_bounds__(256) k_gather_perm(const double *__restrict__ src, int lds,
+                                                     const int32_t *__restrict__ perm, int n,
+                                                     double *__restrict__ dst, int ldd)
+{
+    const int q = blockIdx.x;
+    const double *s = src + (size_t)perm[q] * lds;
+    double *d = dst + (size_t)q * ldd;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) d[t] = s[t];
+}
+
+}  // namespace sisso
+
+using namespace sisso;
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" size_t sisso_subspace_workspace_size(int32_t n, int32_t count, int32_t m_prev)
+{
+    if (n < 2 || count < 0 || m_prev < 0) return 0;
+    return sub_ws_bytes(n, m_prev + count) + (size_t)SISSO_MAX_SUBSPACE * sizeof(int) + 256;
+}
+
+extern "C" sisso_status sisso_subspace_update(const double *cand, int32_t ldc, const int64_t *cand_ids,
+                                              const int32_t *cand_valid, const int32_t *count_dev,
+                                              int32_t count_max, const double *r, int32_t n, double *sub,
+                                              int32_t lds, int64_t *sub_ids, int32_t m_prev, int32_t k,
+                                              int32_t *n_new, int32_t *n_classes, void *ws, size_t ws_bytes,
+                                              void *stream)
+{
+    if (!cand || !cand_ids || !cand_valid || !count_dev || !r || !sub || !sub_ids || !n_new || !n_classes || !ws)
+        return SISSO_E_NULL;
+    if (n < 2 || n > SISSO_MAX_N || ldc < n || lds < n || count_max < 1 || count_max > SISSO_MAX_KEEP ||
+        m_prev < 0 || k < 1 || m_prev + k > SISSO_MAX_SUBSPACE)
+        return SISSO_E_SHAPE;
+    const int nodes = m_prev + count_max;
+    if (ws_bytes < sisso_subspace_workspace_size(n, count_max, m_prev)) return SISSO_E_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    SubWs w = sub_ws_view(ws, n, nodes);
+    int *new_src = (int *)((char *)ws + sub_ws_bytes(n, nodes));
+    hipLaunchKernelGGL(k_sub_resid, dim3(1), dim3(256), 0, st, r, n, w);
+    hipLaunchKernelGGL(k_sub_standardize, dim3(nodes), dim3(256), 0, st, sub, lds, m_prev, cand, ldc, cand_valid,
+                       count_dev, n, w);
+    const int tiles = (nodes + kGT - 1) / kGT;
+    hipLaunchKernelGGL(k_sub_edges, dim3(tiles, tiles), dim3(256), 0, st, m_prev, nodes, n, w);
+    const size_t smem = (size_t)((nodes + 1) & ~1) * sizeof(int) + (size_t)nodes * 2 * sizeof(unsigned long long) +
+                        (size_t)next_pow2(nodes) * (sizeof(double) + sizeof(int64_t));
+    if (smem > 160 * 1024) return SISSO_E_SHAPE;
+    if (!allow_dynamic_lds(k_sub_classes, smem)) return SISSO_E_UNSUPPORTED;
+    hipLaunchKernelGGL(k_sub_classes, dim3(1), dim3(1024), smem, st, m_prev, nodes, cand_ids, sub_ids, k, n_new,
+                       n_classes, new_src, w);
+    hipLaunchKernelGGL(k_sub_gather, dim3(k), dim3(256), 0, st, cand, ldc, new_src, n_new, n, sub, lds, m_prev);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_sort_subspace(const double *src, int32_t lds, const int64_t *ids, int32_t m,
+                                            int32_t n, double *dst, int32_t ldd, int64_t *ids_sorted,
+                                            int32_t *perm_out, void *stream)
+{
+    if (!src || !ids || !dst || !ids_sorted || !perm_out) return SISSO_E_NULL;
+    if (m < 1 || m > SISSO_MAX_SUBSPACE || n < 1 || lds < n || ldd < n) return SISSO_E_SHAPE;
+    hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_sort_ids, dim3(1), dim3(1024), 0, st, ids, m, ids_sorted, perm_out);
+    hipLaunchKernelGGL(k_gather_perm, dim3(m), dim3(256), 0, st, src, lds, perm_out, n, dst, ldd);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}

@@ -1,0 +1,250 @@
+"""SISSO fit driver on MI355X: the loop of Sec. 2.3 over the C ABI.
+
+For t = 1..D (eq. subspace-expansion):
+    r    = y (t = 1) or the residual of the best (t-1)-term model
+    SIS  : sisso_prepare_residual -> sisso_expand_score -> sisso_topk
+    S_t  : sisso_materialize_ids (FP64) -> sisso_subspace_update
+    SO   : sisso_sort_subspace -> sisso_l0_search (best t-term model, residual)
+Every step runs in the library's kernels; this module only allocates device
+buffers with torch, passes pointers and reads back the small per-t results.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class StepResult:
+    t: int
+    list_ids: np.ndarray         # screened list before duplicate removal
+    list_scores: np.ndarray      # FP32 screening scores
+    sub_ids: np.ndarray          # S_t in insertion order
+    best_ids: np.ndarray         # ascending ids of the best t-term model
+    coef: np.ndarray             # intercept first, then per best id
+    sse: float
+    rmse: float
+    r2: float
+    n_tuples: int
+    n_skipped: int
+    keep: int
+    n_classes: int
+
+
+def _round_up(x: int, m: int) -> int:
+    return (x + m - 1) // m * m
+
+
+class Engine:
+    """Device state of one SISSO problem: base features, pools, subspace."""
+
+    def __init__(self, X: np.ndarray, y: np.ndarray, unary: Sequence[str], binary: Sequence[str],
+                 levels: int, rect: bool = False, device: str = "cuda:0"):
+        L.lib()
+        self.dev = torch.device(device)
+        X = np.asarray(X, dtype=np.float64)
+        self.n, self.d = X.shape
+        n = self.n
+        if n < 2 or n > L.MAX_N:
+            raise L.SissoError(f"n = {n} outside 2..{L.MAX_N}")
+        self.space = L.make_space(self.d, list(unary), list(binary), levels, rect)
+        self.levels, self.rect = levels, rect
+        self.ld32 = _round_up(n, 64)
+        self.ld64 = n
+        self.X = torch.from_numpy(np.ascontiguousarray(X.T)).to(self.dev)
+        self.y = torch.from_numpy(np.ascontiguousarray(y, dtype=np.float64)).to(self.dev)
+        pL, p1 = self.space.pool[levels], self.space.pool[1]
+        self.pool32 = torch.empty(pL * self.ld32, dtype=torch.float32, device=self.dev)
+        self.pool1 = torch.empty(p1 * self.ld64, dtype=torch.float64, device=self.dev)
+        self.stats = torch.empty(pL * L.COLSTAT_FLOATS, dtype=torch.float32, device=self.dev)
+        L.check(L.lib().sisso_materialize_pools(
+            ctypes.byref(self.space), L.ptr(self.X), n, n, L.ptr(self.pool32), self.ld32,
+            L.ptr(self.pool1), self.ld64, L.ptr(self.stats), L.stream_handle(self.dev)),
+            "sisso_materialize_pools")
+        self.r32 = torch.zeros(self.ld32, dtype=torch.float32, device=self.dev)
+        self.info = torch.zeros(L.RESID_DOUBLES, dtype=torch.float64, device=self.dev)
+        self._ws: Dict[str, torch.Tensor] = {}
+
+    # ---------------------------------------------------------------- utils
+    @property
+    def total(self) -> int:
+        return int(self.space.total)
+
+    def _workspace(self, name: str, nbytes: int) -> torch.Tensor:
+        t = self._ws.get(name)
+        if t is None or t.numel() < nbytes:
+            t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.dev)
+            self._ws[name] = t
+        return t
+
+    def stream(self) -> int:
+        return L.stream_handle(self.dev)
+
+    def decode(self, fid: int):
+        return L.decode(self.space, int(fid))
+
+    def expr(self, fid: int) -> str:
+        """Readable expression of a feature id."""
+        op, l, r = self.decode(fid)
+        if op < 0:
+            return f"x{fid}"
+        name = L.OPNAME[op]
+        if op <= 3:
+            sym = {"add": "+", "sub": "-", "mul": "*", "div": "/"}[name]
+            return f"({self.expr(l)}{sym}{self.expr(r)})"
+        return f"{name}({self.expr(l)})"
+
+    # ----------------------------------------------------------------- SIS
+    def prepare_residual(self, r64: torch.Tensor):
+        L.check(L.lib().sisso_prepare_residual(L.ptr(r64), self.n, L.ptr(self.r32), L.ptr(self.info),
+                                               self.stream()), "sisso_prepare_residual")
+
+    def score_args(self, keep: int, exclude: Optional[torch.Tensor] = None, grid: int = 0,
+                   tile: int = 0, precision: int = L.FP32) -> L.ScoreArgs:
+        a = L.ScoreArgs()
+        a.n, a.pool32, a.ld32 = self.n, L.ptr(self.pool32), self.ld32
+        a.stats, a.r32, a.info = L.ptr(self.stats), L.ptr(self.r32), L.ptr(self.info)
+        a.exclude = L.ptr(exclude) if exclude is not None and exclude.numel() else None
+        a.n_exclude = int(exclude.numel()) if exclude is not None else 0
+        a.keep, a.precision, a.grid, a.tile = keep, precision, grid, tile
+        return a
+
+    def binary_base(self) -> int:
+        """First id of the one-sided slice's binary block (total if none)."""
+        s = self.space
+        return int(s.pool[self.levels] + s.rect_unary) if self.rect else self.total
+
+    def screen(self, r64: torch.Tensor, keep: int, exclude: Optional[torch.Tensor] = None,
+               begin: int = 0, end: Optional[int] = None, grid: int = 0, tile: int = 0,
+               k: Optional[int] = None, events: Optional[dict] = None):
+        """SIS over ids [begin, end): returns device tensors (ids, scores, count).
+
+        The pass is issued as one sisso_expand_score call per block of the
+        space (stored pool + unary slice, then the binary slice) feeding one
+        workspace; `events`, if given, collects (start, end) CUDA events per
+        call, recorded on the stream the kernels run on."""
+        end = self.total if end is None else end
+        self.prepare_residual(r64)
+        a = self.score_args(keep, exclude, grid, tile)
+        nbytes = L.lib().sisso_score_workspace_size(ctypes.byref(self.space), ctypes.byref(a))
+        if nbytes == 0:
+            raise L.SissoError("sisso_score_workspace_size: invalid arguments")
+        ws = self._workspace("score", nbytes)
+        st = self.stream()
+        bb = self.binary_base()
+        parts = [("pool", begin, min(end, bb)), ("binary", max(begin, bb), end)]
+        base = 0
+        for name, b, e in parts:
+            if b >= e:
+                continue
+            a.list_base = base
+            if events is not None:
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record()
+            L.check(L.lib().sisso_expand_score(ctypes.byref(self.space), ctypes.byref(a), b, e,
+                                               L.ptr(ws), ws.numel(), st), "sisso_expand_score")
+            if events is not None:
+                ev1.record()
+                events.setdefault(name, []).append((ev0, ev1))
+            base += L.lib().sisso_expand_score_lists(ctypes.byref(self.space), ctypes.byref(a), b, e)
+        k = keep if k is None else k
+        ids = torch.empty(k, dtype=torch.int64, device=self.dev)
+        sc = torch.empty(k, dtype=torch.float32, device=self.dev)
+        cnt = torch.empty(1, dtype=torch.int32, device=self.dev)
+        if events is not None:
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+        L.check(L.lib().sisso_topk(L.ptr(ws), ws.numel(), k, L.ptr(ids), L.ptr(sc), L.ptr(cnt), st),
+                "sisso_topk")
+        if events is not None:
+            ev1.record()
+            events.setdefault("topk", []).append((ev0, ev1))
+        return ids, sc, cnt
+
+    def materialize(self, ids: torch.Tensor):
+        """FP64 values (count x n, row q = feature ids[q]) and validity."""
+        count = ids.numel()
+        out = torch.empty(count * self.n, dtype=torch.float64, device=self.dev)
+        valid = torch.empty(count, dtype=torch.int32, device=self.dev)
+        L.check(L.lib().sisso_materialize_ids(ctypes.byref(self.space), self.n, L.ptr(self.pool1),
+                                              self.ld64, L.ptr(self.stats), L.ptr(ids), count,
+                                              L.ptr(out), self.n, L.ptr(valid), self.stream()),
+                "sisso_materialize_ids")
+        return out.view(count, self.n), valid
+
+    # ----------------------------------------------------------------- fit
+    def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10,
+            grid: int = 0, tile: int = 0, timings: Optional[dict] = None) -> List[StepResult]:
+        n, dev, st = self.n, self.dev, self.stream()
+        keep0 = min(2 * k if keep0 is None else keep0, L.MAX_KEEP)
+        if dmax < 1 or dmax > L.MAX_D or k * dmax > L.MAX_SUBSPACE:
+            raise L.SissoError("dmax or k out of range")
+        sub = torch.empty(L.MAX_SUBSPACE * n, dtype=torch.float64, device=dev)
+        sub_ids = torch.empty(L.MAX_SUBSPACE, dtype=torch.int64, device=dev)
+        fsorted = torch.empty(L.MAX_SUBSPACE * n, dtype=torch.float64, device=dev)
+        ids_sorted = torch.empty(L.MAX_SUBSPACE, dtype=torch.int64, device=dev)
+        perm = torch.empty(L.MAX_SUBSPACE, dtype=torch.int32, device=dev)
+        n_new = torch.zeros(1, dtype=torch.int32, device=dev)
+        n_cls = torch.zeros(1, dtype=torch.int32, device=dev)
+        tup = torch.empty(L.MAX_D, dtype=torch.int32, device=dev)
+        sse = torch.empty(1, dtype=torch.float64, device=dev)
+        coef = torch.empty(L.MAX_D + 1, dtype=torch.float64, device=dev)
+        resid = torch.empty(n, dtype=torch.float64, device=dev)
+        stats = torch.empty(4, dtype=torch.float64, device=dev)
+        out: List[StepResult] = []
+        m = 0
+        r = self.y
+        for t in range(1, dmax + 1):
+            keep = keep0
+            exclude = ids_sorted[:m] if m else None
+            while True:
+                ids, sc, cnt = self.screen(r, keep, exclude, grid=grid, tile=tile, events=timings)
+                cand, valid = self.materialize(ids)
+                nb = L.lib().sisso_subspace_workspace_size(n, keep, m)
+                ws2 = self._workspace("sub", nb)
+                L.check(L.lib().sisso_subspace_update(
+                    L.ptr(cand), n, L.ptr(ids), L.ptr(valid), L.ptr(cnt), keep, L.ptr(r), n,
+                    L.ptr(sub), n, L.ptr(sub_ids), m, k, L.ptr(n_new), L.ptr(n_cls), L.ptr(ws2),
+                    ws2.numel(), st), "sisso_subspace_update")
+                nn, nc, ct = int(n_new.item()), int(n_cls.item()), int(cnt.item())
+                if nn >= k or ct < keep or keep >= L.MAX_KEEP:
+                    break
+                keep = min(2 * keep, L.MAX_KEEP)
+            list_ids = ids[:ct].cpu().numpy()
+            list_sc = sc[:ct].cpu().numpy()
+            m += nn
+            if m < t:
+                break
+            L.check(L.lib().sisso_sort_subspace(L.ptr(sub), n, L.ptr(sub_ids), m, n, L.ptr(fsorted), n,
+                                                L.ptr(ids_sorted), L.ptr(perm), st), "sisso_sort_subspace")
+            nb = L.lib().sisso_l0_workspace_size(m, n, t)
+            ws3 = self._workspace("l0", nb)
+            if timings is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+            L.check(L.lib().sisso_l0_search(L.ptr(fsorted), m, n, n, L.ptr(self.y), t, singular_tol,
+                                            L.ptr(tup), L.ptr(sse), L.ptr(coef), L.ptr(resid),
+                                            L.ptr(stats), L.ptr(ws3), ws3.numel(), st),
+                    "sisso_l0_search")
+            if timings is not None:
+                e1.record()
+                timings.setdefault(f"l0_D{t}", []).append((e0, e1))
+                timings.setdefault("so_m", []).append(m)
+            tp = tup[:t].cpu().numpy()
+            srt = ids_sorted[:m].cpu().numpy()
+            stt = stats.cpu().numpy()
+            best = srt[tp] if (tp >= 0).all() else np.full(t, -1)
+            out.append(StepResult(t, list_ids, list_sc, sub_ids[:m].cpu().numpy(), best,
+                                  coef[:t + 1].cpu().numpy(), float(sse.item()), float(stt[0]),
+                                  float(stt[1]), int(stt[2]), int(stt[3]), keep, nc))
+            r = resid.clone()
+        return out

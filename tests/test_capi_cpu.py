@@ -1,0 +1,111 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2410_01752_amd import _lib as L
+from paper_2410_01752_amd import inputs as I
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "sisso.h")).read()
+    return sorted(set(re.findall(r"\b(sisso_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTED) <= set(names)
+    assert lib.sisso_version().decode().startswith("sisso-mi355x")
+
+
+def test_space_init_validation():
+    s = L.Space()
+    s.d, s.levels, s.rect, s.n_unary, s.n_binary = 0, 2, 0, 0, 1
+    s.binary[0] = 2
+    assert L.lib().sisso_space_init(ctypes.byref(s)) == 2          # d < 1
+    s.d, s.levels = 3, 3
+    assert L.lib().sisso_space_init(ctypes.byref(s)) == 2          # levels > 2
+    s.levels, s.n_binary = 2, 2
+    s.binary[0] = s.binary[1] = 2
+    assert L.lib().sisso_space_init(ctypes.byref(s)) == 2          # repeated op
+    s.binary[1] = 7
+    assert L.lib().sisso_space_init(ctypes.byref(s)) == 2          # unary code as binary
+    assert L.lib().sisso_space_init(None) == 1
+
+
+@pytest.mark.parametrize("d,ops,levels,rect", [
+    (5, I.OPS1, 2, False), (10, I.FULL, 2, False), (20, I.OPS1, 2, True), (30, I.OPS1, 2, True),
+    (3, I.OPS1, 2, True), (2, {"unary": [], "binary": ["add", "mul"]}, 2, False),
+    (4, I.FULL, 1, True), (6, {"unary": ["log", "sin"], "binary": ["div"]}, 2, True)])
+def test_space_counts_and_decode_match_oracle(d, ops, levels, rect):
+    s = L.make_space(d, ops["unary"], ops["binary"], levels, rect)
+    o = O.Space(d, ops["unary"], ops["binary"], levels, rect)
+    assert s.total == o.total
+    for l in range(levels + 1):
+        assert s.pool[l] == o.pool(l)
+    rng = np.random.default_rng(d)
+    ids = list(range(min(o.total, 2000))) + [int(v) for v in rng.integers(0, o.total, 2000)]
+    ids += [o.total - 1, int(s.pool[levels]) - 1, int(s.pool[levels])] if o.total > s.pool[levels] else []
+    for fid in ids:
+        assert L.decode(s, fid) == o.decode(fid), fid
+
+
+def test_decode_ids_above_2_32():
+    s = L.make_space(20, I.OPS1["unary"], I.OPS1["binary"], 2, True)
+    o = O.Space(20, I.OPS1["unary"], I.OPS1["binary"], 2, True)
+    for fid in [2 ** 32, 2 ** 32 + 12345, 2 ** 33 + 7, s.total - 5]:
+        assert L.decode(s, fid) == o.decode(fid)
+    with pytest.raises(L.SissoError):
+        L.decode(s, s.total)
+
+
+def test_argument_errors_before_launch():
+    lib = L.lib()
+    s = L.make_space(5, I.OPS1["unary"], I.OPS1["binary"], 2, False)
+    a = L.ScoreArgs()
+    a.n, a.keep = 50, 40
+    # null pointers
+    assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 0, 10, None, 0, None) == 1
+    assert lib.sisso_topk(None, 0, 5, None, None, None, None) == 1
+    assert lib.sisso_materialize_pools(ctypes.byref(s), None, 50, 50, None, 64, None, 50, None, None) == 1
+    assert lib.sisso_l0_search(None, 10, 10, 10, None, 2, 1e-10, None, None, None, None, None, None, 0, None) == 1
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    # shapes
+    assert lib.sisso_materialize_pools(ctypes.byref(s), fake, 1, 1, fake, 4, fake, 1, fake, None) == 2
+    assert lib.sisso_materialize_pools(ctypes.byref(s), fake, 50, 50, fake, 50, fake, 50, fake, None) == 2  # ld32 % 4
+    assert lib.sisso_l0_search(fake, 2, 10, 10, fake, 3, 1e-10, fake, fake, fake, fake, fake, fake, 1 << 20,
+                               None) == 2                                              # m < D
+    assert lib.sisso_l0_search(fake, 10, 10, 10, fake, 4, 1e-10, fake, fake, fake, fake, fake, fake, 1 << 20,
+                               None) == 2                                              # D > 3
+    assert lib.sisso_l0_search(fake, 10, 10, 10, fake, 2, 1e-10, fake, fake, fake, fake, fake, fake, 8,
+                               None) == 4                                              # workspace
+    assert lib.sisso_prepare_residual(fake, 1, fake, fake, None) == 2
+    # ranges
+    a.pool32 = a.stats = a.r32 = a.info = 0x1000
+    a.ld32 = 64
+    ws = lib.sisso_score_workspace_size(ctypes.byref(s), ctypes.byref(a))
+    assert ws > 0
+    assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 5, 5, fake, ws, None) == 3     # empty
+    assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 0, s.total + 1, fake, ws, None) == 3
+    assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 0, 10, fake, ws - 1, None) == 4
+    a.keep = 0
+    assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 0, 10, fake, ws, None) == 3
+    a.keep, a.precision = 40, 7
+    assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 0, 10, fake, ws, None) == 5
+    assert lib.sisso_topk(fake, ws, 0, fake, fake, fake, None) == 3
+    assert lib.sisso_subspace_update(fake, 50, fake, fake, fake, 40, fake, 50, fake, 50, fake, 1020, 20,
+                                     fake, fake, fake, 1 << 30, None) == 2             # m_prev + k > 1024
+    assert lib.sisso_sort_subspace(fake, 50, fake, 0, 50, fake, 50, fake, fake, None) == 2
+    for st in range(8):
+        assert lib.sisso_status_string(st)

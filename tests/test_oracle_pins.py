@@ -326,3 +326,23 @@ def test_noise_free_single_term_recovered_exactly():
     syy = np.sum((y - y.mean()) ** 2)
     assert ro[0].sse <= 1e-26 * syy * 30
     assert abs(ro[0].coef[1] - 2.5) < 1e-10 and abs(ro[0].coef[0] + 1.0) < 1e-9
+
+
+def test_cancelling_sum_or_difference_is_invalid():
+    """sqrt(x1^2) - x1 is identically zero: invalid although its FP64 rounding
+    noise is not constant; a genuine difference of close features stays."""
+    rng = np.random.default_rng(6)
+    X = rng.uniform(0.5, 5.0, size=(40, 2))
+    sp = O.Space(2, ["sq", "sqrt"], ["sub", "add"], 2, True)
+    names = {}
+    for fid in range(sp.total):
+        names[sp.decode(fid)] = fid
+    sq1 = names[(4, 1, -1)]                   # x1^2 (level 1)
+    root = names[(6, sq1, -1)]                # sqrt(x1^2) (level 2, == x1)
+    bad = names[(1, root, 1)]                 # sqrt(x1^2) - x1 (slice)
+    good = names[(1, root, 0)]                # sqrt(x1^2) - x0
+    V, ok = sp.eval(X, [root, bad, good])
+    assert ok[0] and not ok[1] and ok[2]
+    assert np.max(np.abs(V[:, 0] - X[:, 1])) < 1e-14
+    feats = B.enumerate_space(X, ["sq", "sqrt"], ["sub", "add"], 2, True)
+    assert feats[root][2] and not feats[bad][2] and feats[good][2]
