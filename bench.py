@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--keep0", type=int, default=0,
+                    help="screened-list length before duplicate removal (k + slack); 0 = 2k, "
+                         "or 1024 for the rung-3 workload")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
 
 
@@ -89,10 +94,21 @@ def main():
     print(f"[bench] workload {args.workload} n={n} d={p.X.shape[1]} k={p.k} D={p.dmax}", file=sys.stderr,
           flush=True)
 
+    keep0 = args.keep0 or (1024 if p.rect else 2 * p.k)
+
     def one_step(timings=None):
         eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
-        res = eng.fit(p.k, p.dmax, grid=args.grid, tile=args.tile, timings=timings)
+        res = eng.fit(p.k, p.dmax, keep0=keep0, grid=args.grid, tile=args.tile, timings=timings)
         return eng, res
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("[bench] copy calibration: 3 x 1 GiB device copies", file=sys.stderr, flush=True)
 
     for w in range(args.warmup):
         one_step()
@@ -169,7 +185,8 @@ def main():
         "sis_pool_pass_ms": (sum(pool_ms) / len(pool_ms)) if pool_ms else None,
         "topk_ms": (sum(ev_ms("topk")) / len(ev_ms("topk"))) if ev_ms("topk") else None,
         "roofline": roof,
-        "fit": {"rmse": [r.rmse for r in last], "best_ids": [list(map(int, r.best_ids)) for r in last]},
+        "fit": {"rmse": [r.rmse for r in last], "best_ids": [list(map(int, r.best_ids)) for r in last],
+                "keep": [r.keep for r in last], "keep0": keep0},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -273,6 +273,7 @@ template <int NC>
 __device__ inline void list_offer(BlockList &L, const float (&sc)[NC], const int64_t (&id)[NC],
                                   unsigned *gthr, const int64_t *excl, int n_excl)
 {
+#pragma unroll
     for (int q = 0; q < NC; ++q) {
         __syncthreads();
         const int c = *L.cnt;

@@ -351,7 +351,9 @@ __global__ void __launch_bounds__(256) k_score_rect(
             // shift constants of the multiplicative forms (set by the pilot
             // below); sums and differences use the operands' exact means
             float cm[RU][RV], c3[RU][RV], c4[RU][RV];
-            double dA[RU][RV][5], dB[RU][RV][5], dC[RU][RV][5];
+            // A stays small (the shifts are means) and is kept in FP32; B and C
+            // are carried in FP64 across chunks
+            double dB[RU][RV][5], dC[RU][RV][5];
             float fA[RU][RV][5], fB[RU][RV][5], fC[RU][RV][5];
 #pragma unroll
             for (int a = 0; a < RU; ++a)
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(256) k_score_rect(
                 for (int b = 0; b < RV; ++b)
 #pragma unroll
                     for (int k = 0; k < 5; ++k) {
-                        dA[a][b][k] = dB[a][b][k] = dC[a][b][k] = 0.0;
+                        dB[a][b][k] = dC[a][b][k] = 0.0;
                         fA[a][b][k] = fB[a][b][k] = fC[a][b][k] = 0.0f;
                     }
 
@@ -494,10 +496,9 @@ __global__ void __launch_bounds__(256) k_score_rect(
                     for (int b = 0; b < RV; ++b)
 #pragma unroll
                         for (int k = 0; k < 5; ++k) {
-                            dA[a][b][k] += (double)fA[a][b][k];
                             dB[a][b][k] += (double)fB[a][b][k];
                             dC[a][b][k] += (double)fC[a][b][k];
-                            fA[a][b][k] = fB[a][b][k] = fC[a][b][k] = 0.0f;
+                            fB[a][b][k] = fC[a][b][k] = 0.0f;
                         }
                 if (ch + 1 < nch) store_chunk((ch & 1) ? buf0 : buf1);
                 __syncthreads();
@@ -544,11 +545,11 @@ __global__ void __launch_bounds__(256) k_score_rect(
                         if (fs.slot[k] >= 0 && ok && dom[k] && !((over >> k) & 1)) {
                             fid = binbase + (uidx[a] * vcount + v) * S + fs.slot[k];
                             if (fid >= id_begin && fid < id_end) {
-                                sc = score_from_sums(dA[a][b][k], dB[a][b][k], dC[a][b][k], shifts[k], nd,
+                                sc = score_from_sums((double)fA[a][b][k], dB[a][b][k], dC[a][b][k], shifts[k], nd,
                                                      R1, Srr);
                                 if (k < 2) {
                                     // a sum or difference that cancels to rounding noise
-                                    const double var = dB[a][b][k] - dA[a][b][k] * (dA[a][b][k] / nd);
+                                    const double var = dB[a][b][k] - (double)fA[a][b][k] * ((double)fA[a][b][k] / nd);
                                     const double scale = fmax((double)urm[a], (double)vrm[b]);
                                     if (!(sqrt(fmax(var, 0.0) / nd) > kCancelRel * scale)) sc = -1.0f;
                                 }
