@@ -229,6 +229,31 @@ sisso_status sisso_expand_score(const sisso_space *space, const sisso_score_args
                                 int64_t cand_begin, int64_t cand_end, void *ws, size_t ws_bytes,
                                 void *stream);
 
+/* BF16 screening of the one-sided slice's binary block (spec form of
+ * Sec. 2.2's screening on matrix cores).  With centred operands the sums of
+ * every form op(u, v) are contractions over the samples; twelve GEMMs per tile
+ * of (u, v) pairs run on BF16 MFMA with FP32 accumulation and give approximate
+ * scores.  The best `band` candidates by BF16 score are then rescored exactly
+ * with the FP32 path's arithmetic and written as per-block lists into `ws`
+ * (list_base as in sisso_expand_score), so sisso_topk returns FP32 scores.
+ *   ops       u-side BF16 operands from sisso_prepare_bf16 (size from
+ *             sisso_bf16_operands_size; residual-independent, once per problem).
+ *   bws       per-call workspace (size from sisso_bf16_workspace_size).
+ *   band      candidates rescored, keep <= band <= SISSO_MAX_KEEP.
+ * [cand_begin, cand_end) must lie in the binary block of the slice.  The
+ * recall of the band against the FP32 screening is measured by the tests.
+ * Errors: as sisso_expand_score; SISSO_E_UNSUPPORTED without a slice. */
+size_t sisso_bf16_operands_size(const sisso_space *space, int32_t n);
+sisso_status sisso_prepare_bf16(const sisso_space *space, const sisso_score_args *args, void *ops,
+                                size_t ops_bytes, void *stream);
+size_t sisso_bf16_workspace_size(const sisso_space *space, const sisso_score_args *args, int32_t band);
+int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_score_args *args,
+                                      int32_t band);
+sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score_args *args,
+                                     const void *ops, size_t ops_bytes, int32_t band,
+                                     int64_t cand_begin, int64_t cand_end, void *bws, size_t bws_bytes,
+                                     void *ws, size_t ws_bytes, void *stream);
+
 /* Merge the workspace's per-block lists into the global best k (score desc,
  * id asc) (Sec. 2.2, eq. sis-method).  out_ids / out_scores: k entries;
  * out_count: number written (< k when fewer valid features exist).

@@ -87,6 +87,11 @@ def lib():
         "sisso_l0_search": (_i32, [_vp, _i32, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
                                    _vp, _vp, _vp, _sz, _vp]),
         "sisso_sort_subspace": (_i32, [_vp, _i32, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
+        "sisso_bf16_operands_size": (_sz, [sp, _i32]),
+        "sisso_prepare_bf16": (_i32, [sp, ap, _vp, _sz, _vp]),
+        "sisso_bf16_workspace_size": (_sz, [sp, ap, _i32]),
+        "sisso_expand_score_bf16_lists": (_i32, [sp, ap, _i32]),
+        "sisso_expand_score_bf16": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _vp, _sz, _vp]),
         "sisso_status_string": (ctypes.c_char_p, [_i32]),
         "sisso_version": (ctypes.c_char_p, []),
     }
@@ -102,7 +107,9 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_prepare_residual", "sisso_score_workspace_size", "sisso_score_reset",
             "sisso_expand_score", "sisso_expand_score_lists", "sisso_topk", "sisso_subspace_workspace_size",
             "sisso_subspace_update", "sisso_l0_workspace_size", "sisso_l0_search",
-            "sisso_sort_subspace", "sisso_status_string", "sisso_version"]
+            "sisso_sort_subspace", "sisso_bf16_operands_size", "sisso_prepare_bf16",
+            "sisso_bf16_workspace_size", "sisso_expand_score_bf16_lists", "sisso_expand_score_bf16",
+            "sisso_status_string", "sisso_version"]
 
 
 def check(status: int, what: str = ""):

@@ -1,0 +1,634 @@
+// bf16.hip -- BF16 MFMA screening of the one-sided rung-3 slice, followed by
+// an exact FP32 rescore of a band of candidates around the cutoff (Sec. 2.2,
+// eq. sis-weight: the correlation of every candidate with the residual).
+//
+// With centred operands u~ = u - mean(u), z~ = 1/u - mean(1/u) and
+// v~ = v - mean(v), w~ = 1/v - mean(1/v), the sums a score needs are
+// contractions over the samples.  For u * v, with h = uv - mean(u) mean(v)
+// = u~v~ + mean(v) u~ + mean(u) v~:
+//   sum h      = G[U~, V~]
+//   sum h r    = G[U~, V~ r] + mean(v) sum u~ r + mean(u) sum v~ r
+//   sum h^2    = G[U~^2, V~ (V~ + 2 mean(v))] + 2 mean(u) G[U~, V~ (V~ + mean(v))]
+//                + mean(v)^2 sum u~^2 + mean(u)^2 sum v~^2
+// and likewise u/v (with W~) and v/u (with Z~ against V~); u + v and u - v
+// need only G[U~, V~].  Twelve GEMMs over a tile of (u, v) pairs, with the
+// per-column terms folded into the v-side operands, give all five forms.
+// They run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation; sums of single
+// columns are exact (FP64).  The BF16 scores only select a band; every
+// candidate of the band is rescored with the plain FP32 kernel's arithmetic
+// (shared functions), so reported scores are the FP32 path's scores.
+#include "screen.hpp"
+
+namespace sisso {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kUVar = 4;      // U~, U~^2, Z~, Z~^2
+constexpr int kVVar = 8;      // V~, V~ r, P, Q, W~, W~ r, Pw, Qw
+constexpr int kBT = 64;       // (u, v) pairs per block side: 2 x 2 waves of 32 x 32
+constexpr int kKC = 16;       // samples per LDS stage (one MFMA k-step)
+constexpr int kKP = kKC + 8;  // padded LDS row (bf16)
+constexpr int kNG = 12;       // GEMMs per tile
+
+// GEMM g multiplies u-side variant A(g) with v-side variant B(g):
+//   g:  0   1    2   3   4   5    6    7   8   9    10   11
+//   A:  U~  U~   U~2 U~  U~  U~   U~2  U~  Z~  Z~   Z~2  Z~
+//   B:  V~  V~r  P   Q   W~  W~r  Pw   Qw  V~  V~r  P    Q
+
+__host__ __device__ inline size_t align256b(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// u-side operand buffer: [kUVar][ucols][ldb] bf16, then ucols float4 sums.
+struct BfOps {
+    __bf16 *U;
+    float4 *usum;     // mean(u), mean(1/u), sum u~^2, sum z~^2
+};
+__host__ __device__ inline size_t bf_ops_bytes(int64_t ucols, int64_t ldb)
+{
+    return align256b((size_t)kUVar * ucols * ldb * sizeof(__bf16)) + align256b((size_t)ucols * sizeof(float4));
+}
+__host__ __device__ inline BfOps bf_ops_view(void *p, int64_t ucols, int64_t ldb)
+{
+    BfOps o;
+    o.U = (__bf16 *)p;
+    o.usum = (float4 *)((char *)p + align256b((size_t)kUVar * ucols * ldb * sizeof(__bf16)));
+    return o;
+}
+
+// per-pass BF16 workspace: v-side operands and sums, u-side residual sums,
+// band lists (a screening workspace of its own) and the band ids.
+struct BfWs {
+    __bf16 *V;        // [kVVar][vcols][ldb]
+    float4 *vsum;     // 2 per column: (mean v, mean 1/v, sum v~^2, sum w~^2), (sum v~ r, sum w~ r, rms, 0)
+    float2 *ures;     // per u column: sum u~ r, sum z~ r
+    int64_t *band_ids;
+    float *band_sc;
+    int32_t *band_cnt;
+    void *lists;      // screening workspace of the BF16 lists
+};
+__host__ __device__ inline size_t bf_ws_bytes(int64_t ucols, int64_t vcols, int64_t ldb, int band, int lists, int keep)
+{
+    size_t b = align256b((size_t)kVVar * vcols * ldb * sizeof(__bf16));
+    b += align256b((size_t)vcols * 2 * sizeof(float4));
+    b += align256b((size_t)ucols * sizeof(float2));
+    b += align256b((size_t)band * sizeof(int64_t)) + align256b((size_t)band * sizeof(float)) + 256;
+    b += ws_bytes_for(lists, keep);
+    return b;
+}
+__host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols, int64_t ldb, int band)
+{
+    BfWs w;
+    char *c = (char *)p;
+    w.V = (__bf16 *)c; c += align256b((size_t)kVVar * vcols * ldb * sizeof(__bf16));
+    w.vsum = (float4 *)c; c += align256b((size_t)vcols * 2 * sizeof(float4));
+    w.ures = (float2 *)c; c += align256b((size_t)ucols * sizeof(float2));
+    w.band_ids = (int64_t *)c; c += align256b((size_t)band * sizeof(int64_t));
+    w.band_sc = (float *)c; c += align256b((size_t)band * sizeof(float));
+    w.band_cnt = (int32_t *)c; c += 256;
+    w.lists = c;
+    return w;
+}
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// ---------------------------------------------------------------- operands
+
+// u side (newest pool level), independent of the residual.  One wave per column.
+__global__ void __launch_bounds__(256) k_bf16_u_prep(int n, const float *__restrict__ pool32, int64_t ld32,
+                                                     const sisso_colstat *__restrict__ stats, int64_t col0,
+                                                     int64_t ucols, int64_t ldb, BfOps ops)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c = wave; c < ucols; c += nw) {
+        const sisso_colstat st = stats[col0 + c];
+        const float *col = pool32 + (size_t)(col0 + c) * ld32;
+        const float mu = st.mean, mz = st.mean_rcp;
+        const bool zok = st.minabs > 0.0f;
+        double suu = 0.0, szz = 0.0;
+        for (int64_t t = lane; t < ldb; t += 64) {
+            float uu = 0.f, zz = 0.f;
+            if (t < n) {
+                const float x = col[t];
+                uu = x - mu;
+                zz = zok ? __builtin_amdgcn_rcpf(x) - mz : 0.f;
+                suu += (double)uu * uu;
+                szz += (double)zz * zz;
+            }
+            ops.U[((size_t)0 * ucols + c) * ldb + t] = to_bf16(uu);
+            ops.U[((size_t)1 * ucols + c) * ldb + t] = to_bf16(uu * uu);
+            ops.U[((size_t)2 * ucols + c) * ldb + t] = to_bf16(zz);
+            ops.U[((size_t)3 * ucols + c) * ldb + t] = to_bf16(zz * zz);
+        }
+        suu = wave_sum(suu);
+        szz = wave_sum(szz);
+        if (lane == 0) ops.usum[c] = make_float4(mu, mz, (float)suu, (float)szz);
+    }
+}
+
+// u side, per residual: sum u~ r and sum z~ r.
+__global__ void __launch_bounds__(256) k_bf16_u_resid(int n, const float *__restrict__ pool32, int64_t ld32,
+                                                      const sisso_colstat *__restrict__ stats, int64_t col0,
+                                                      int64_t ucols, const float *__restrict__ r32,
+                                                      float2 *__restrict__ ures)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c = wave; c < ucols; c += nw) {
+        const sisso_colstat st = stats[col0 + c];
+        const float *col = pool32 + (size_t)(col0 + c) * ld32;
+        const bool zok = st.minabs > 0.0f;
+        float sur = 0.f, szr = 0.f;
+        for (int t = lane; t < n; t += 64) {
+            const float x = col[t], r = r32[t];
+            sur = fmaf(x - st.mean, r, sur);
+            if (zok) szr = fmaf(__builtin_amdgcn_rcpf(x) - st.mean_rcp, r, szr);
+        }
+        const double a = wave_sum((double)sur), b = wave_sum((double)szr);
+        if (lane == 0) ures[c] = make_float2((float)a, (float)b);
+    }
+}
+
+// v side (previous pool), per residual: eight variants and the column sums.
+__global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restrict__ pool32, int64_t ld32,
+                                                     const sisso_colstat *__restrict__ stats, int64_t vcols,
+                                                     int64_t ldb, const float *__restrict__ r32, BfWs w)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c = wave; c < vcols; c += nw) {
+        const sisso_colstat st = stats[c];
+        const float *col = pool32 + (size_t)c * ld32;
+        const float mv = st.mean, mw = st.mean_rcp;
+        const bool wok = st.minabs > 0.0f;
+        double svv = 0.0, sww = 0.0, svr = 0.0, swr = 0.0;
+        for (int64_t t = lane; t < ldb; t += 64) {
+            float vv = 0.f, ww = 0.f, r = 0.f;
+            if (t < n) {
+                const float x = col[t];
+                r = r32[t];
+                vv = x - mv;
+                ww = wok ? __builtin_amdgcn_rcpf(x) - mw : 0.f;
+                svv += (double)vv * vv;
+                sww += (double)ww * ww;
+                svr += (double)vv * r;
+                swr += (double)ww * r;
+            }
+            const float var[kVVar] = {vv, vv * r, vv * (vv + 2.f * mv), vv * (vv + mv),
+                                      ww, ww * r, ww * (ww + 2.f * mw), ww * (ww + mw)};
+#pragma unroll
+            for (int q = 0; q < kVVar; ++q) w.V[((size_t)q * vcols + c) * ldb + t] = to_bf16(var[q]);
+        }
+        svv = wave_sum(svv); sww = wave_sum(sww); svr = wave_sum(svr); swr = wave_sum(swr);
+        if (lane == 0) {
+            w.vsum[2 * c] = make_float4(mv, mw, (float)svv, (float)sww);
+            w.vsum[2 * c + 1] = make_float4((float)svr, (float)swr, st.rms, 0.f);
+        }
+    }
+}
+
+// -------------------------------------------------------------- screening
+
+__global__ void __launch_bounds__(256) k_score_rect_bf16(
+    sisso_space s, FormSlots fs, int n, int64_t ldb, const __bf16 *__restrict__ U,
+    const float4 *__restrict__ usum, const __bf16 *__restrict__ V, const float4 *__restrict__ vsum,
+    const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
+    const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
+    int64_t ut_hi, int64_t id_begin, int64_t id_end, void *lws, int lists_total, int keep, int cap)
+{
+    extern __shared__ unsigned char smem[];
+    constexpr int ASZ = kUVar * kBT * kKP, BSZ = kVVar * kBT * kKP;
+    __bf16 *const sbase = reinterpret_cast<__bf16 *>(smem);
+    float *lsc = (float *)((__bf16 *)smem + 2 * (ASZ + BSZ));
+    int64_t *lid = (int64_t *)(lsc + cap);
+    __shared__ int lcnt;
+    __shared__ float lthr;
+    WsView W = ws_view(lws, lists_total, keep);
+    BlockList Lst{lsc, lid, &lcnt, &lthr, cap, keep};
+    list_init(Lst);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wu = w & 1, wv = w >> 1;
+    const int Lv = s.levels;
+    const int64_t vcount = s.pool[Lv - 1], ulo = s.pool[Lv - 1], ucols = s.pool[Lv] - ulo;
+    const int64_t binbase = s.pool[Lv] + s.rect_unary;
+    const int S = s.n_slots;
+    const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
+    const int nch = (n + kKC - 1) / kKC;
+    const int64_t nvt = (vcount + kBT - 1) / kBT;
+
+    for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
+        const int64_t u0 = ut * kBT;   // index into the newest level
+        for (int64_t vt = 0; vt < nvt; ++vt) {
+            const int64_t v0 = vt * kBT;
+            f32x16 acc[kNG];
+#pragma unroll
+            for (int g = 0; g < kNG; ++g)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
+            // staging: A = kUVar x 64 columns x 16 samples (512 x 16 B, 2 per thread),
+            // B = kVVar x 64 x 16 (1024 x 16 B, 4 per thread)
+            uint4 pa[2], pb[4];
+            auto load_chunk = [&](int ch) {
+                const int64_t k0 = (int64_t)ch * kKC;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
+                    const int64_t c = u0 + col;
+                    pa[q] = c < ucols ? *reinterpret_cast<const uint4 *>(U + ((size_t)var * ucols + c) * ldb + k0 + part * 8)
+                                      : make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
+                    const int64_t c = v0 + col;
+                    pb[q] = c < vcount ? *reinterpret_cast<const uint4 *>(V + ((size_t)var * vcount + c) * ldb + k0 + part * 8)
+                                       : make_uint4(0, 0, 0, 0);
+                }
+            };
+            auto store_chunk = [&](int b) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
+                    *reinterpret_cast<uint4 *>((sbase + b * (ASZ + BSZ)) + (var * kBT + col) * kKP + part * 8) = pa[q];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
+                    *reinterpret_cast<uint4 *>((sbase + b * (ASZ + BSZ) + ASZ) + (var * kBT + col) * kKP + part * 8) = pb[q];
+                }
+            };
+            __syncthreads();
+            load_chunk(0);
+            store_chunk(0);
+            __syncthreads();
+            for (int ch = 0; ch < nch; ++ch) {
+                const int b = ch & 1;
+                if (ch + 1 < nch) load_chunk(ch + 1);
+#pragma unroll
+                for (int kk = 0; kk < kKC / 16; ++kk) {
+                    const int koff = kk * 16 + (lane >> 5) * 8;
+                    bf16x8 af[kUVar], bfr[kVVar];
+#pragma unroll
+                    for (int a = 0; a < kUVar; ++a)
+                        af[a] = *reinterpret_cast<const bf16x8 *>((sbase + b * (ASZ + BSZ)) + (a * kBT + wu * 32 + (lane & 31)) * kKP + koff);
+#pragma unroll
+                    for (int q = 0; q < kVVar; ++q)
+                        bfr[q] = *reinterpret_cast<const bf16x8 *>((sbase + b * (ASZ + BSZ) + ASZ) + (q * kBT + wv * 32 + (lane & 31)) * kKP + koff);
+                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[0], acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[1], acc[1], 0, 0, 0);
+                    acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1], bfr[2], acc[2], 0, 0, 0);
+                    acc[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[3], acc[3], 0, 0, 0);
+                    acc[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[4], acc[4], 0, 0, 0);
+                    acc[5] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[5], acc[5], 0, 0, 0);
+                    acc[6] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1], bfr[6], acc[6], 0, 0, 0);
+                    acc[7] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[7], acc[7], 0, 0, 0);
+                    acc[8] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[2], bfr[0], acc[8], 0, 0, 0);
+                    acc[9] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[2], bfr[1], acc[9], 0, 0, 0);
+                    acc[10] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[3], bfr[2], acc[10], 0, 0, 0);
+                    acc[11] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[2], bfr[3], acc[11], 0, 0, 0);
+                }
+                if (ch + 1 < nch) store_chunk(b ^ 1);
+                __syncthreads();
+            }
+
+            // epilogue: lane holds column j = lane % 32 and rows
+            // i = 8 (r / 4) + 4 (lane / 32) + (r % 4) of each 32 x 32 result
+            const int j = lane & 31;
+            const int64_t v = v0 + wv * 32 + j;
+            const bool vin = v < vcount;
+            const sisso_colstat vst = stats[vin ? v : 0];
+            const float4 vs0 = vsum[2 * (vin ? v : 0)], vs1 = vsum[2 * (vin ? v : 0) + 1];
+            const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w, Svr = vs1.x, Swr = vs1.y, vrm = vs1.z;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t uix = u0 + wu * 32 + i;
+                const bool uin = uix < ucols;
+                const sisso_colstat ust = stats[ulo + (uin ? uix : 0)];
+                const float4 us = usum[uin ? uix : 0];
+                const float2 ur = ures[uin ? uix : 0];
+                const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w, Sur = ur.x, Szr = ur.y;
+                const bool ok = uin && vin && ust.valid != 0.0f && vst.valid != 0.0f;
+                const float fn = (float)n, rr = (float)(R1 / nd);
+                const float g0 = acc[0][r];
+                float cov[5], var[5];
+                var[0] = Suu + Svv + 2.0f * g0;                     // u + v
+                var[1] = Suu + Svv - 2.0f * g0;                     // u - v
+                cov[0] = Sur + Svr;
+                cov[1] = Sur - Svr;
+                {                                                   // u v
+                    const float s1 = g0;
+                    const float s2 = acc[2][r] + 2.0f * mu * acc[3][r] + mv * mv * Suu + mu * mu * Svv;
+                    var[2] = s2 - s1 * s1 / fn;
+                    cov[2] = acc[1][r] + mv * Sur + mu * Svr - s1 * rr;
+                }
+                {                                                   // u / v
+                    const float s1 = acc[4][r];
+                    const float s2 = acc[6][r] + 2.0f * mu * acc[7][r] + mw * mw * Suu + mu * mu * Sww;
+                    var[3] = s2 - s1 * s1 / fn;
+                    cov[3] = acc[5][r] + mw * Sur + mu * Swr - s1 * rr;
+                }
+                {                                                   // v / u
+                    const float s1 = acc[8][r];
+                    const float s2 = acc[10][r] + 2.0f * mz * acc[11][r] + mv * mv * Szz + mz * mz * Svv;
+                    var[4] = s2 - s1 * s1 / fn;
+                    cov[4] = acc[9][r] + mv * Szr + mz * Svr - s1 * rr;
+                }
+                const bool dom[5] = {true, true, true, vst.minabs > 0.f, ust.minabs > 0.f};
+                const float scale = fmaxf(ust.rms, vrm);
+                float sc[5];
+                int64_t fid[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    sc[k] = -1.0f;
+                    fid[k] = INT64_MAX;
+                    if (ok && dom[k] && fs.slot[k] >= 0) {
+                        fid[k] = binbase + (uix * vcount + v) * S + fs.slot[k];
+                        if (fid[k] >= id_begin && fid[k] < id_end && var[k] > 0.0f) {
+                            float q = fabsf(cov[k]) * __builtin_amdgcn_rsqf(var[k] * (float)Srr);
+                            sc[k] = q <= 1.0f ? q : (q > 1.0f ? 1.0f : -1.0f);
+                            // clear cancellation of a sum or difference (the exact
+                            // rule is applied by the rescore)
+                            if (k < 2 && !(sqrtf(var[k] / fn) > 1e-2f * scale)) sc[k] = -1.0f;
+                        }
+                    }
+                }
+                // insert this row's candidates: all five forms at once when the list
+                // has room for a full row of the block, else form by form with merges
+                __syncthreads();
+                const int c = *Lst.cnt;
+                __syncthreads();
+                if (c + 5 * (int)blockDim.x <= Lst.cap) {
+                    const float t = fmaxf(*Lst.thr, load_gthr(&W.h->gthr));
+#pragma unroll
+                    for (int k = 0; k < 5; ++k)
+                        if (sc[k] >= 0.0f && sc[k] >= t && (n_excl == 0 || !in_sorted_ids(excl, n_excl, fid[k]))) {
+                            const int slot = atomicAdd(Lst.cnt, 1);
+                            Lst.sc[slot] = sc[k];
+                            Lst.id[slot] = fid[k];
+                        }
+                } else {
+                    list_offer<5>(Lst, sc, fid, &W.h->gthr, excl, n_excl);
+                }
+            }
+        }
+    }
+    list_flush(Lst, &W.h->gthr, W.sc + (size_t)blockIdx.x * keep, W.id + (size_t)blockIdx.x * keep);
+}
+
+// --------------------------------------------------------------- rescore
+
+// Exact FP32 score of every band id, with the plain kernel's arithmetic: the
+// same staged values, pilot shifts, chunked FP32 partial sums carried in FP64
+// and validity rules.  One thread per candidate.
+__global__ void __launch_bounds__(256) k_rescore_ids(sisso_space s, FormSlots fs, int n,
+                                                     const float *__restrict__ pool32, int64_t ld32,
+                                                     const sisso_colstat *__restrict__ stats,
+                                                     const float *__restrict__ r32,
+                                                     const sisso_resid_info *__restrict__ info,
+                                                     const int64_t *__restrict__ ids, const int32_t *__restrict__ count,
+                                                     const int64_t *__restrict__ excl, int n_excl, int list_base,
+                                                     void *ws, int lists_total, int keep, int cap)
+{
+    extern __shared__ unsigned char smem[];
+    float *lsc = (float *)smem;
+    int64_t *lid = (int64_t *)(smem + cap * sizeof(float));
+    __shared__ int lcnt;
+    __shared__ float lthr;
+    WsView W = ws_view(ws, lists_total, keep);
+    BlockList L{lsc, lid, &lcnt, &lthr, cap, keep};
+    list_init(L);
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    float osc[1] = {-1.0f};
+    int64_t oid[1] = {INT64_MAX};
+    const int Lv = s.levels;
+    const int64_t binbase = s.pool[Lv] + s.rect_unary;
+    if (q < *count) {
+        const int64_t id = ids[q];
+        if (id >= binbase && id < s.total) {
+            const int64_t loc = id - binbase, vcount = s.pool[Lv - 1];
+            const int slot = (int)(loc % s.n_slots);
+            const int64_t pair = loc / s.n_slots;
+            const int64_t u = s.pool[Lv - 1] + pair / vcount, v = pair % vcount;
+            int k = -1;
+            for (int f = 0; f < 5; ++f)
+                if (fs.slot[f] == slot) k = f;
+            const sisso_colstat ust = stats[u], vst = stats[v];
+            if (k >= 0 && ust.valid != 0.0f && vst.valid != 0.0f) {
+                const float *cu = pool32 + (size_t)u * ld32, *cv = pool32 + (size_t)v * ld32;
+                const int c0 = n < kSC ? n : kSC;
+                float pm = 0.f, p3 = 0.f, p4 = 0.f;
+                for (int t = 0; t < c0; ++t) {
+                    const float ur = cu[t], vr = cv[t];
+                    const float uq = __builtin_amdgcn_rcpf(ur), vq = __builtin_amdgcn_rcpf(vr);
+                    pm = fmaf(ur, vr, pm);
+                    p3 = fmaf(ur, vq, p3);
+                    p4 = fmaf(vr, uq, p4);
+                }
+                const float inv = 1.0f / (float)c0;
+                const float cm = pm * inv, c3 = p3 * inv, c4 = p4 * inv;
+                float fA = 0.f, fB = 0.f, fC = 0.f;
+                double dB = 0.0, dC = 0.0;
+                for (int t0 = 0; t0 < n; t0 += kSC) {
+                    const int te = t0 + kSC < n ? t0 + kSC : n;
+                    for (int t = t0; t < te; ++t) {
+                        const float ur = cu[t], vr = cv[t];
+                        const float us = ur - ust.mean, vs = vr - vst.mean;
+                        const float uq = __builtin_amdgcn_rcpf(ur), vq = __builtin_amdgcn_rcpf(vr);
+                        const float g = binary_form(k, ur, us, uq, vr, vs, vq, cm, c3, c4);
+                        fA += g;
+                        fB = fmaf(g, g, fB);
+                        fC = fmaf(g, r32[t], fC);
+                    }
+                    dB += (double)fB;
+                    dC += (double)fC;
+                    fB = fC = 0.0f;
+                }
+                const double shifts[5] = {(double)ust.mean + (double)vst.mean, (double)ust.mean - (double)vst.mean,
+                                          (double)cm, (double)c3, (double)c4};
+                osc[0] = form_score(k, fA, dB, dC, shifts[k], cu, cv, n, ust.maxabs, ust.minabs, ust.rms,
+                                    vst.maxabs, vst.minabs, vst.rms, (double)n, info->sum_r32, info->s_rr);
+                oid[0] = id;
+            }
+        }
+    }
+    list_offer<1>(L, osc, oid, &W.h->gthr, excl, n_excl);
+    const int list = list_base + blockIdx.x;
+    list_flush(L, &W.h->gthr, W.sc + (size_t)list * keep, W.id + (size_t)list * keep);
+}
+
+__global__ void k_bf_append(WsHeader *h, int n_lists)
+{
+    if (threadIdx.x == 0) h->n_lists = n_lists;
+}
+
+__global__ void k_bf_reset(WsHeader *h, int keep, int n_lists, int lists_cap)
+{
+    if (threadIdx.x == 0) {
+        h->gthr = 0u; h->keep = keep; h->n_lists = n_lists; h->lists_cap = lists_cap; h->status = 0;
+    }
+}
+
+}  // namespace sisso
+
+using namespace sisso;
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int64_t ldb_of(int n) { return ((int64_t)n + 63) / 64 * 64; }
+
+FormSlots form_slots(const sisso_space *space)
+{
+    FormSlots fs;
+    for (int k = 0; k < 5; ++k) fs.slot[k] = -1;
+    for (int sl = 0; sl < space->n_slots; ++sl) {
+        const int op = space->slot_op[sl], rev = space->slot_rev[sl];
+        fs.slot[op == SISSO_DIV ? (rev ? 4 : 3) : op] = sl;
+    }
+    return fs;
+}
+
+struct BfPlan {
+    int64_t ut_lo = 0, ut_hi = 0;
+    int grid = 0;
+};
+
+constexpr int kMaxBfGrid = 1024;
+
+BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end)
+{
+    BfPlan p;
+    const int L = s->levels;
+    const int64_t bb = s->pool[L] + s->rect_unary, be = s->total;
+    const int64_t b = begin > bb ? begin : bb, e = end < be ? end : be;
+    if (b >= e) return p;
+    const int64_t per_u = s->pool[L - 1] * s->n_slots;
+    const int64_t ul = (b - bb) / per_u, uh = (e - 1 - bb) / per_u + 1;
+    p.ut_lo = ul / kBT;
+    p.ut_hi = (uh + kBT - 1) / kBT;
+    const int64_t tiles = p.ut_hi - p.ut_lo;
+    p.grid = (int)(tiles < kMaxBfGrid ? tiles : kMaxBfGrid);
+    return p;
+}
+
+int bf_lists_cap(const sisso_space *s) { return bf_plan(s, 0, s->total).grid; }
+
+int bf_list_cap(int keep) { return next_pow2(keep + 256); }
+
+bool space_ok(const sisso_space *s)
+{
+    return s && s->total > 0 && s->rect && s->levels >= 1 && s->levels <= SISSO_MAX_LEVELS &&
+           s->pool[s->levels - 1] > 0;
+}
+
+}  // namespace
+
+extern "C" size_t sisso_bf16_operands_size(const sisso_space *space, int32_t n)
+{
+    if (!space_ok(space) || n < 2 || n > SISSO_MAX_N) return 0;
+    const int64_t ucols = space->pool[space->levels] - space->pool[space->levels - 1];
+    return bf_ops_bytes(ucols, ldb_of(n));
+}
+
+extern "C" sisso_status sisso_prepare_bf16(const sisso_space *space, const sisso_score_args *args, void *ops,
+                                           size_t ops_bytes, void *stream)
+{
+    if (!space || !args || !ops || !args->pool32 || !args->stats) return SISSO_E_NULL;
+    if (!space_ok(space)) return SISSO_E_UNSUPPORTED;
+    if (args->n < 2 || args->n > SISSO_MAX_N || args->ld32 < args->n || (args->ld32 % 4) != 0) return SISSO_E_SHAPE;
+    if (ops_bytes < sisso_bf16_operands_size(space, args->n)) return SISSO_E_WORKSPACE;
+    const int L = space->levels;
+    const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, ldb = ldb_of(args->n);
+    const BfOps o = bf_ops_view(ops, ucols, ldb);
+    const int64_t blocks = (ucols + 3) / 4;
+    hipLaunchKernelGGL(k_bf16_u_prep, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, as_stream(stream),
+                       args->n, args->pool32, args->ld32, args->stats, col0, ucols, ldb, o);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" size_t sisso_bf16_workspace_size(const sisso_space *space, const sisso_score_args *args, int32_t band)
+{
+    if (!space_ok(space) || !args || args->n < 2 || band < 1 || band > SISSO_MAX_KEEP) return 0;
+    const int L = space->levels;
+    const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
+    return bf_ws_bytes(ucols, vcols, ldb_of(args->n), band, bf_lists_cap(space), band);
+}
+
+extern "C" int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_score_args *args,
+                                                 int32_t band)
+{
+    (void)space;
+    (void)args;
+    if (band < 1 || band > SISSO_MAX_KEEP) return -1;
+    return (band + 255) / 256;
+}
+
+extern "C" sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score_args *args,
+                                                const void *ops, size_t ops_bytes, int32_t band, int64_t cand_begin,
+                                                int64_t cand_end, void *bws, size_t bws_bytes, void *ws,
+                                                size_t ws_bytes, void *stream)
+{
+    if (!space || !args || !ops || !bws || !ws || !args->pool32 || !args->stats || !args->r32 || !args->info)
+        return SISSO_E_NULL;
+    if (args->n_exclude > 0 && !args->exclude) return SISSO_E_NULL;
+    if (!space_ok(space)) return SISSO_E_UNSUPPORTED;
+    const int n = args->n;
+    if (n < 2 || n > SISSO_MAX_N || args->ld32 < n || (args->ld32 % 4) != 0 || args->n_exclude < 0)
+        return SISSO_E_SHAPE;
+    if (args->keep < 1 || args->keep > SISSO_MAX_KEEP || band < args->keep || band > SISSO_MAX_KEEP) return SISSO_E_RANGE;
+    const int L = space->levels;
+    const int64_t bb = space->pool[L] + space->rect_unary;
+    if (cand_begin < bb || cand_end > space->total || cand_begin >= cand_end) return SISSO_E_RANGE;
+    if (ops_bytes < sisso_bf16_operands_size(space, n)) return SISSO_E_WORKSPACE;
+    if (bws_bytes < sisso_bf16_workspace_size(space, args, band)) return SISSO_E_WORKSPACE;
+    const int lists_main = score_lists_capacity(space, args);
+    const int n_resc = (band + 255) / 256;
+    if (ws_bytes < ws_bytes_for(lists_main, args->keep)) return SISSO_E_WORKSPACE;
+    if (args->list_base < 0 || args->list_base + n_resc > lists_main) return SISSO_E_WORKSPACE;
+
+    hipStream_t st = as_stream(stream);
+    const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
+    const int64_t ldb = ldb_of(n);
+    const BfOps o = bf_ops_view(const_cast<void *>(ops), ucols, ldb);
+    BfWs w = bf_ws_view(bws, ucols, vcols, ldb, band);
+    const FormSlots fs = form_slots(space);
+    // residual-dependent operands
+    const int64_t vb = (vcols + 3) / 4, ub = (ucols + 3) / 4;
+    hipLaunchKernelGGL(k_bf16_v_prep, dim3((unsigned)(vb < 65536 ? vb : 65536)), dim3(256), 0, st, n, args->pool32,
+                       args->ld32, args->stats, vcols, ldb, args->r32, w);
+    hipLaunchKernelGGL(k_bf16_u_resid, dim3((unsigned)(ub < 65536 ? ub : 65536)), dim3(256), 0, st, n, args->pool32,
+                       args->ld32, args->stats, col0, ucols, args->r32, w.ures);
+    // BF16 screen -> band lists
+    const BfPlan p = bf_plan(space, cand_begin, cand_end);
+    const int keep_b = band;   // every block keeps the whole band: the grid-wide bound stays valid
+    const int cap_b = bf_list_cap(keep_b);
+    const int lcap = bf_lists_cap(space);
+    hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
+    if (p.grid > 0) {
+        const size_t smem = (size_t)2 * (kUVar + kVVar) * kBT * kKP * sizeof(__bf16) +
+                            (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
+        if (!allow_dynamic_lds(k_score_rect_bf16, smem)) return SISSO_E_UNSUPPORTED;
+        hipLaunchKernelGGL(k_score_rect_bf16, dim3(p.grid), dim3(256), smem, st, *space, fs, n, ldb, o.U, o.usum, w.V,
+                           w.vsum, w.ures, args->stats, args->info, args->exclude, args->n_exclude, p.ut_lo, p.ut_hi,
+                           cand_begin, cand_end, w.lists, lcap, keep_b, cap_b);
+    }
+    sisso_status rs = topk_launch(w.lists, band, w.band_ids, w.band_sc, w.band_cnt, st, false);
+    if (rs != SISSO_OK) return rs;
+    // exact FP32 rescore of the band into the main workspace
+    const int keep = args->keep, cap = next_pow2(keep + 256);
+    if (args->list_base == 0)
+        hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)ws, keep, n_resc, lists_main);
+    else
+        hipLaunchKernelGGL(k_bf_append, dim3(1), dim3(64), 0, st, (WsHeader *)ws, args->list_base + n_resc);
+    const size_t smem = (size_t)cap * (sizeof(float) + sizeof(int64_t));
+    hipLaunchKernelGGL(k_rescore_ids, dim3(n_resc), dim3(256), smem, st, *space, fs, n, args->pool32, args->ld32,
+                       args->stats, args->r32, args->info, w.band_ids, w.band_cnt, args->exclude, args->n_exclude,
+                       args->list_base, ws, lists_main, keep, cap);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}

@@ -20,64 +20,9 @@
 //                    candidates are never written to memory.
 // Every block keeps its best K' candidates (score desc, id asc) in LDS and
 // writes them to its list slot of the workspace; sisso_topk merges the lists.
-#include "common.hpp"
+#include "screen.hpp"
 
 namespace sisso {
-
-// ------------------------------------------------------------- workspace
-
-constexpr int kHistBins = 4096;
-constexpr int kFinalCap = 8192;
-
-struct WsHeader {
-    unsigned gthr;          // grid-wide admission bound (float bits)
-    int keep;               // list length
-    int n_lists;            // lists written by the last sisso_expand_score
-    int status;             // 0 ok; 1 = tie overflow in sisso_topk
-    unsigned prefix;        // radix select state
-    int need;
-    int total;              // entries considered by the select
-    int n_gt, n_eq;         // gather counters
-    int lists_cap;          // list slots the workspace was laid out for
-    int pad[6];
-    unsigned hist[kHistBins];
-};
-
-struct WsView {
-    WsHeader *h;
-    float *sc;              // n_lists x keep
-    int64_t *id;
-    float *fin_sc;          // kFinalCap gather buffer
-    int64_t *fin_id;
-};
-
-constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-__host__ __device__ inline size_t ws_bytes_for(int lists, int keep)
-{
-    size_t b = align256(sizeof(WsHeader));
-    b += align256((size_t)lists * keep * sizeof(float));
-    b += align256((size_t)lists * keep * sizeof(int64_t));
-    b += align256((size_t)kFinalCap * sizeof(float));
-    b += align256((size_t)kFinalCap * sizeof(int64_t));
-    return b;
-}
-
-__host__ __device__ inline WsView ws_view(void *ws, int lists, int keep)
-{
-    char *p = (char *)ws;
-    WsView v;
-    v.h = (WsHeader *)p;
-    p += align256(sizeof(WsHeader));
-    v.sc = (float *)p;
-    p += align256((size_t)lists * keep * sizeof(float));
-    v.id = (int64_t *)p;
-    p += align256((size_t)lists * keep * sizeof(int64_t));
-    v.fin_sc = (float *)p;
-    p += align256((size_t)kFinalCap * sizeof(float));
-    v.fin_id = (int64_t *)p;
-    return v;
-}
 
 __global__ void k_ws_reset(WsHeader *h, int keep, int n_lists, int lists_cap)
 {
@@ -93,27 +38,6 @@ __global__ void k_ws_reset(WsHeader *h, int keep, int n_lists, int lists_cap)
 __global__ void k_ws_append(WsHeader *h, int n_lists)
 {
     if (threadIdx.x == 0) h->n_lists = n_lists;
-}
-
-__device__ __forceinline__ WsView ws_view_dev(void *ws)
-{
-    const WsHeader *h = (const WsHeader *)ws;
-    return ws_view(ws, h->lists_cap, h->keep);
-}
-
-// Scores of a candidate from its shifted sums.  Returns -1 when the FP32
-// statistics show a non-positive or near-constant variance.
-__device__ __forceinline__ float score_from_sums(double A, double B, double C, double shift, double n,
-                                                 double R1, double Srr)
-{
-    const double var = B - A * (A / n);
-    if (!(var > 0.0)) return -1.0f;
-    const double mean = shift + A / n;
-    if (!(sqrt(var / n) > kConstRel * fabs(mean))) return -1.0f;
-    const double cov = C - A * (R1 / n);
-    double s = fabs(cov) / sqrt(var * Srr);
-    if (!(s <= 1.0)) s = (s > 1.0) ? 1.0 : -1.0;   // rounding above 1, or NaN
-    return (float)s;
 }
 
 // ------------------------------------------------------ pool columns kernel
@@ -262,19 +186,12 @@ __global__ void __launch_bounds__(256) k_score_columns(
 
 // --------------------------------------------------------- binary slice
 
-constexpr int kSC = 32;            // samples per LDS chunk
 
 template <int RU, int RV>
 struct RectCfg {
     static constexpr int TU = 16 * RU, TV = 16 * RV;
     static constexpr int TUP = TU + 4, TVP = TV + 4;
     static constexpr int BUF = kSC * (3 * TUP + 3 * TVP) + kSC;   // floats per buffer
-};
-
-// Result slot of each of the five binary forms (ADD, SUB, MUL, u/v, v/u) in
-// the pair's slot list, or -1 if the op is not in the operator set.
-struct FormSlots {
-    int slot[5];
 };
 
 template <int RU, int RV>
@@ -470,11 +387,10 @@ __global__ void __launch_bounds__(256) k_score_rect(
 #pragma unroll
                         for (int b = 0; b < RV; ++b) {
                             float g[5];
-                            g[0] = us[a] + vs[b];
-                            g[1] = us[a] - vs[b];
-                            g[2] = fmaf(ur[a], vr[b], -cm[a][b]);
-                            g[3] = fmaf(ur[a], vq[b], -c3[a][b]);
-                            g[4] = fmaf(vr[b], uq[a], -c4[a][b]);
+#pragma unroll
+                            for (int k = 0; k < 5; ++k)
+                                g[k] = binary_form(k, ur[a], us[a], uq[a], vr[b], vs[b], vq[b], cm[a][b],
+                                                   c3[a][b], c4[a][b]);
 #pragma unroll
                             for (int k = 0; k < 5; ++k) {
                                 fA[a][b][k] += g[k];
@@ -515,45 +431,19 @@ __global__ void __launch_bounds__(256) k_score_rect(
                     const bool ok = uval[a] && vval[b];
                     const double shifts[5] = {(double)ufo[a] + (double)vfo[b], (double)ufo[a] - (double)vfo[b],
                                               (double)cm[a][b], (double)c3[a][b], (double)c4[a][b]};
-                    const float bnd[5] = {umx[a] + vmx[b], umx[a] + vmx[b], umx[a] * vmx[b],
-                                          vmn[b] > 0.f ? umx[a] / vmn[b] : INFINITY,
-                                          umn[a] > 0.f ? vmx[b] / umn[a] : INFINITY};
-                    const bool dom[5] = {true, true, true, vmn[b] > 0.f, umn[a] > 0.f};
-                    int need = 0;
-#pragma unroll
-                    for (int k = 0; k < 5; ++k)
-                        if (ok && dom[k] && fs.slot[k] >= 0 && !(bnd[k] <= kCapSafe)) need |= 1 << k;
-                    int over = 0;
-                    if (need) {
-                        // exact per-sample magnitude check (rare)
-                        const int64_t u = u0 + ty * RU + a;
-                        const float *cu = pool32 + (size_t)u * ld32, *cv = pool32 + (size_t)v * ld32;
-                        for (int t = 0; t < n; ++t) {
-                            const float x = cu[t], y = cv[t];
-                            const float fv[5] = {x + y, x - y, x * y, x * __builtin_amdgcn_rcpf(y),
-                                                 y * __builtin_amdgcn_rcpf(x)};
-#pragma unroll
-                            for (int k = 0; k < 5; ++k)
-                                if (((need >> k) & 1) && !(fabsf(fv[k]) <= 1e15f)) over |= 1 << k;
-                        }
-                    }
+                    const int64_t u = u0 + ty * RU + a;
+                    const float *cu = pool32 + (size_t)(ok ? u : 0) * ld32;
+                    const float *cv = pool32 + (size_t)(ok ? v : 0) * ld32;
 #pragma unroll
                     for (int k = 0; k < 5; ++k) {
                         const int e = (a * RV + b) * 5 + k;
                         float sc = -1.0f;
                         int64_t fid = INT64_MAX;
-                        if (fs.slot[k] >= 0 && ok && dom[k] && !((over >> k) & 1)) {
+                        if (fs.slot[k] >= 0 && ok) {
                             fid = binbase + (uidx[a] * vcount + v) * S + fs.slot[k];
-                            if (fid >= id_begin && fid < id_end) {
-                                sc = score_from_sums((double)fA[a][b][k], dB[a][b][k], dC[a][b][k], shifts[k], nd,
-                                                     R1, Srr);
-                                if (k < 2) {
-                                    // a sum or difference that cancels to rounding noise
-                                    const double var = dB[a][b][k] - (double)fA[a][b][k] * ((double)fA[a][b][k] / nd);
-                                    const double scale = fmax((double)urm[a], (double)vrm[b]);
-                                    if (!(sqrt(fmax(var, 0.0) / nd) > kCancelRel * scale)) sc = -1.0f;
-                                }
-                            }
+                            if (fid >= id_begin && fid < id_end)
+                                sc = form_score(k, fA[a][b][k], dB[a][b][k], dC[a][b][k], shifts[k], cu, cv, n,
+                                                umx[a], umn[a], urm[a], vmx[b], vmn[b], vrm[b], nd, R1, Srr);
                         }
                         osc[e] = sc;
                         oid[e] = fid;
@@ -650,12 +540,13 @@ __global__ void __launch_bounds__(256) k_tk_gather(void *ws)
     }
 }
 
-__global__ void __launch_bounds__(1024) k_tk_final(void *ws, int k, int64_t *__restrict__ out_ids,
-                                                   float *__restrict__ out_sc, int32_t *out_count)
+__global__ void __launch_bounds__(1024) k_tk_final(void *ws, int k, int allow_above_keep,
+                                                   int64_t *__restrict__ out_ids, float *__restrict__ out_sc,
+                                                   int32_t *out_count)
 {
     extern __shared__ unsigned char smem[];
     WsView W = ws_view_dev(ws);
-    if (k > W.h->keep) {
+    if (k > kFinalCap || (!allow_above_keep && k > W.h->keep)) {
         // k larger than the list length the workspace was filled with
         for (int i = threadIdx.x; i < k; i += blockDim.x) { out_ids[i] = INT64_MAX; out_sc[i] = -1.0f; }
         if (threadIdx.x == 0) { *out_count = 0; W.h->status = 2; }
@@ -761,7 +652,9 @@ Plan make_plan(const sisso_space *s, const sisso_score_args *a, int64_t begin, i
 int lists_capacity(const sisso_space *s, const sisso_score_args *a)
 {
     const Plan p = make_plan(s, a, 0, s->total);
-    return p.g_cols + p.g_rect;
+    // the binary block's lists come from k_score_rect, or from the exact rescore
+    // of a BF16 band (at most kFinalCap / 256 lists)
+    return p.g_cols + (p.g_rect > kFinalCap / 256 ? p.g_rect : kFinalCap / 256);
 }
 
 int list_cap(int keep) { return next_pow2(keep + 256); }
@@ -776,6 +669,10 @@ size_t rect_smem(int ru, int rv, int cap)
 }
 
 }  // namespace
+
+namespace sisso {
+int score_lists_capacity(const sisso_space *s, const sisso_score_args *a) { return lists_capacity(s, a); }
+}  // namespace sisso
 
 extern "C" size_t sisso_score_workspace_size(const sisso_space *space, const sisso_score_args *args)
 {
@@ -873,14 +770,13 @@ extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso
     return SISSO_OK;
 }
 
-extern "C" sisso_status sisso_topk(const void *ws_c, size_t ws_bytes, int32_t k, int64_t *out_ids,
-                                   float *out_scores, int32_t *out_count, void *stream)
+namespace sisso {
+// Top-k merge of a screening workspace.  With allow_above_keep, k may exceed the
+// per-block list length (up to the gather buffer): the result is then the best k
+// of the union of the lists, which is what a screening band needs.
+sisso_status topk_launch(void *ws, int k, int64_t *out_ids, float *out_scores, int32_t *out_count,
+                         hipStream_t st, bool allow_above_keep)
 {
-    void *ws = const_cast<void *>(ws_c);
-    if (!ws || !out_ids || !out_scores || !out_count) return SISSO_E_NULL;
-    if (k < 1 || k > SISSO_MAX_KEEP) return SISSO_E_RANGE;
-    if (ws_bytes < ws_bytes_for(0, 1)) return SISSO_E_WORKSPACE;
-    hipStream_t st = as_stream(stream);
     WsHeader *h = (WsHeader *)ws;
     hipLaunchKernelGGL(k_tk_init, dim3(1), dim3(256), 0, st, h, k);
     for (int pass = 0; pass < 3; ++pass) {
@@ -890,6 +786,18 @@ extern "C" sisso_status sisso_topk(const void *ws_c, size_t ws_bytes, int32_t k,
     hipLaunchKernelGGL(k_tk_gather, dim3(512), dim3(256), 0, st, ws);
     const size_t smem = (size_t)kFinalCap * (sizeof(float) + sizeof(int64_t));
     if (!allow_dynamic_lds(k_tk_final, smem)) return SISSO_E_UNSUPPORTED;
-    hipLaunchKernelGGL(k_tk_final, dim3(1), dim3(1024), smem, st, ws, k, out_ids, out_scores, out_count);
+    hipLaunchKernelGGL(k_tk_final, dim3(1), dim3(1024), smem, st, ws, k, allow_above_keep ? 1 : 0, out_ids,
+                       out_scores, out_count);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+}  // namespace sisso
+
+extern "C" sisso_status sisso_topk(const void *ws_c, size_t ws_bytes, int32_t k, int64_t *out_ids,
+                                   float *out_scores, int32_t *out_count, void *stream)
+{
+    void *ws = const_cast<void *>(ws_c);
+    if (!ws || !out_ids || !out_scores || !out_count) return SISSO_E_NULL;
+    if (k < 1 || k > SISSO_MAX_KEEP) return SISSO_E_RANGE;
+    if (ws_bytes < ws_bytes_for(0, 1)) return SISSO_E_WORKSPACE;
+    return topk_launch(ws, k, out_ids, out_scores, out_count, as_stream(stream), false);
 }

@@ -67,6 +67,7 @@ class Engine:
             ctypes.byref(self.space), L.ptr(self.X), n, n, L.ptr(self.pool32), self.ld32,
             L.ptr(self.pool1), self.ld64, L.ptr(self.stats), L.stream_handle(self.dev)),
             "sisso_materialize_pools")
+        self.bf16_ops: Optional[torch.Tensor] = None
         self.r32 = torch.zeros(self.ld32, dtype=torch.float32, device=self.dev)
         self.info = torch.zeros(L.RESID_DOUBLES, dtype=torch.float64, device=self.dev)
         self._ws: Dict[str, torch.Tensor] = {}
@@ -120,9 +121,22 @@ class Engine:
         s = self.space
         return int(s.pool[self.levels] + s.rect_unary) if self.rect else self.total
 
+    def prepare_bf16(self):
+        """BF16 operands of the slice's newest-level side (once per problem)."""
+        if self.bf16_ops is not None:
+            return
+        nb = L.lib().sisso_bf16_operands_size(ctypes.byref(self.space), self.n)
+        if nb == 0:
+            raise L.SissoError("BF16 screening needs a space with the rung-3 slice")
+        self.bf16_ops = torch.empty(nb, dtype=torch.uint8, device=self.dev)
+        a = self.score_args(1)
+        L.check(L.lib().sisso_prepare_bf16(ctypes.byref(self.space), ctypes.byref(a), L.ptr(self.bf16_ops),
+                                           nb, self.stream()), "sisso_prepare_bf16")
+
     def screen(self, r64: torch.Tensor, keep: int, exclude: Optional[torch.Tensor] = None,
                begin: int = 0, end: Optional[int] = None, grid: int = 0, tile: int = 0,
-               k: Optional[int] = None, events: Optional[dict] = None):
+               k: Optional[int] = None, events: Optional[dict] = None, precision: str = "fp32",
+               band: int = 0):
         """SIS over ids [begin, end): returns device tensors (ids, scores, count).
 
         The pass is issued as one sisso_expand_score call per block of the
@@ -140,6 +154,10 @@ class Engine:
         bb = self.binary_base()
         parts = [("pool", begin, min(end, bb)), ("binary", max(begin, bb), end)]
         base = 0
+        use_bf16 = precision == "bf16" and self.rect
+        if use_bf16:
+            self.prepare_bf16()
+            band = max(min(band or 4 * keep, L.MAX_KEEP), keep)
         for name, b, e in parts:
             if b >= e:
                 continue
@@ -148,12 +166,21 @@ class Engine:
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev1 = torch.cuda.Event(enable_timing=True)
                 ev0.record()
-            L.check(L.lib().sisso_expand_score(ctypes.byref(self.space), ctypes.byref(a), b, e,
-                                               L.ptr(ws), ws.numel(), st), "sisso_expand_score")
+            if name == "binary" and use_bf16:
+                nb = L.lib().sisso_bf16_workspace_size(ctypes.byref(self.space), ctypes.byref(a), band)
+                bws = self._workspace("bf16", nb)
+                L.check(L.lib().sisso_expand_score_bf16(
+                    ctypes.byref(self.space), ctypes.byref(a), L.ptr(self.bf16_ops), self.bf16_ops.numel(),
+                    band, b, e, L.ptr(bws), bws.numel(), L.ptr(ws), ws.numel(), st), "sisso_expand_score_bf16")
+                nl = L.lib().sisso_expand_score_bf16_lists(ctypes.byref(self.space), ctypes.byref(a), band)
+            else:
+                L.check(L.lib().sisso_expand_score(ctypes.byref(self.space), ctypes.byref(a), b, e,
+                                                   L.ptr(ws), ws.numel(), st), "sisso_expand_score")
+                nl = L.lib().sisso_expand_score_lists(ctypes.byref(self.space), ctypes.byref(a), b, e)
             if events is not None:
                 ev1.record()
                 events.setdefault(name, []).append((ev0, ev1))
-            base += L.lib().sisso_expand_score_lists(ctypes.byref(self.space), ctypes.byref(a), b, e)
+            base += nl
         k = keep if k is None else k
         ids = torch.empty(k, dtype=torch.int64, device=self.dev)
         sc = torch.empty(k, dtype=torch.float32, device=self.dev)
@@ -182,7 +209,8 @@ class Engine:
 
     # ----------------------------------------------------------------- fit
     def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10,
-            grid: int = 0, tile: int = 0, timings: Optional[dict] = None) -> List[StepResult]:
+            grid: int = 0, tile: int = 0, timings: Optional[dict] = None, precision: str = "fp32",
+            band: int = 0) -> List[StepResult]:
         n, dev, st = self.n, self.dev, self.stream()
         keep0 = min(2 * k if keep0 is None else keep0, L.MAX_KEEP)
         if dmax < 1 or dmax > L.MAX_D or k * dmax > L.MAX_SUBSPACE:
@@ -206,7 +234,8 @@ class Engine:
             keep = keep0
             exclude = ids_sorted[:m] if m else None
             while True:
-                ids, sc, cnt = self.screen(r, keep, exclude, grid=grid, tile=tile, events=timings)
+                ids, sc, cnt = self.screen(r, keep, exclude, grid=grid, tile=tile, events=timings,
+                                           precision=precision, band=band)
                 cand, valid = self.materialize(ids)
                 nb = L.lib().sisso_subspace_workspace_size(n, keep, m)
                 ws2 = self._workspace("sub", nb)

@@ -1,0 +1,105 @@
+"""BF16-MFMA screening with FP32 band rescore, against the plain FP32 path.
+
+Recall of the BF16 form's top-K' against the FP32 form's top-K' must be
+>= 0.99 (ids missing from the BF16 list may only be FP32 near-ties of the
+cutoff beyond that), and every score the BF16 form returns is the FP32
+path's score of that id, bit for bit (the band is rescored with the FP32
+kernel's arithmetic).  The FP32 path itself is checked against the oracle in
+test_gpu_parity.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2410_01752_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _engine(p):
+    from paper_2410_01752_amd.fit import Engine
+    return Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
+
+
+def _both(eng, r, keep, band, begin=None, end=None):
+    r64 = torch.as_tensor(r, dtype=torch.float64, device=eng.dev)
+    begin = eng.binary_base() if begin is None else begin
+    out = {}
+    for prec in ("fp32", "bf16"):
+        ids, sc, cnt = eng.screen(r64, keep, None, begin=begin, end=end, precision=prec, band=band)
+        torch.cuda.synchronize()
+        c = int(cnt.item())
+        out[prec] = (ids[:c].cpu().numpy(), sc[:c].cpu().numpy())
+    return out
+
+
+def recall_of(out, tol=1e-6):
+    """Top-K' recall of the BF16 form against the FP32 form.  A FP32 member that
+    the BF16 list lacks counts as found when its score is within tol of the
+    cutoff: such candidates tie with the cutoff (typically duplicate features
+    with bit-identical scores) and either choice is a valid top-K'."""
+    fi, fs = out["fp32"]
+    bi, bs = out["bf16"]
+    got = set(bi.tolist())
+    cutoff = fs[-1]
+    found = sum(1 for i, s in zip(fi.tolist(), fs.tolist()) if i in got or s <= cutoff + tol)
+    raw = sum(1 for i in fi.tolist() if i in got)
+    return found / len(fi), raw / len(fi)
+
+
+def _check(out, keep, min_recall=0.99):
+    fi, fs = out["fp32"]
+    bi, bs = out["bf16"]
+    assert len(bi) == len(fi)
+    fmap = dict(zip(fi.tolist(), fs.tolist()))
+    bmap = dict(zip(bi.tolist(), bs.tolist()))
+    for i in bmap:
+        if i in fmap:
+            assert bmap[i] == fmap[i], (i, bmap[i], fmap[i])        # bit-identical rescore
+    # the BF16 list is sorted and never ranks below the FP32 cutoff
+    assert np.all(np.diff(bs) <= 0) and bs[-1] >= fs[-1] - 1e-6
+    recall, raw = recall_of(out)
+    print(f"  recall {recall:.4f} (raw {raw:.4f}, {len(fi)} kept)", flush=True)
+    assert recall >= min_recall
+    return recall
+
+
+def test_bf16_recall_rung3_small():
+    p = I.tiny(9, n=300, d=6, dist="lognormal", rect=True)
+    print("[bf16] n=300 d=6 full binary block", flush=True)
+    eng = _engine(p)
+    _check(_both(eng, p.y, 500, 2000), 500)
+
+
+def test_bf16_recall_c3_slice():
+    """n = 2000, d = 20: 1024 operands u of the binary block (5.3e6 candidates)."""
+    p = I.config3()
+    print("[bf16] C3 slice", flush=True)
+    eng = _engine(p)
+    sp = O.Space(20, p.unary, p.binary, 2, True)
+    bb = eng.binary_base()
+    per_u = sp.pool(1) * 5
+    out = _both(eng, p.y, 400, 1600, begin=bb + 2000 * per_u, end=bb + 3024 * per_u)
+    _check(out, 400)
+
+
+def test_bf16_rescored_scores_match_oracle():
+    """The rescored list of the BF16 form is FP32-exact: within 1e-6 of the oracle."""
+    p = I.tiny(9, n=300, d=6, dist="lognormal", rect=True)
+    eng = _engine(p)
+    sp = O.Space(6, p.unary, p.binary, 2, True)
+    out = _both(eng, p.y, 300, 1200)
+    bi, bs = out["bf16"]
+    ref = np.array([sp.score_range(p.X, p.y, int(i), int(i) + 1)[0] for i in bi[:120]])
+    assert np.max(np.abs(ref - bs[:120])) <= 1e-6
+
+
+def test_bf16_fit_matches_fp32_fit():
+    p = I.tiny(5, n=200, d=5, dist="lognormal", rect=True, k=8, dmax=3)
+    eng = _engine(p)
+    a = eng.fit(p.k, p.dmax, precision="fp32")
+    b = eng.fit(p.k, p.dmax, precision="bf16", band=0)
+    for x, y in zip(a, b):
+        assert list(x.best_ids) == list(y.best_ids)
+        assert abs(x.rmse - y.rmse) <= 1e-9 * x.rmse
