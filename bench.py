@@ -13,6 +13,12 @@ screening, top-k, FP64 subspace update and the l0 search.  Inputs are
 resident in HBM before the timed region.  `value` is SIS candidates scored per
 second of step time; SO tuples per second are reported beside it.
 
+Screening forms: before the timed steps the binary rung-3 block is screened
+once against y with the plain FP32 form and with the BF16-MFMA form (band
+rescored in FP32); their times, the BF16 form's speedup and its top-K'
+recall against the FP32 form are reported under "forms".  The timed steps
+use the BF16 form when that recall is >= 0.99, else the FP32 form.
+
 Prints one JSON line (see the fields below).  `--gpus N` with N > 1 exits:
 this build measures one GPU.
 """
@@ -48,6 +54,11 @@ def parse():
     ap.add_argument("--keep0", type=int, default=0,
                     help="screened-list length before duplicate removal (k + slack); 0 = 2k, "
                          "or 1024 for the rung-3 workload")
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16"],
+                    help="screening form of the rung-3 slice; auto = BF16 when its recall against the "
+                         "FP32 form, measured in this run, is >= 0.99")
+    ap.add_argument("--band", type=int, default=2048, help="BF16 form: candidates rescored in FP32")
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16 vs FP32 recall check")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -79,6 +90,20 @@ def cpu_baseline(p, budget_s: float):
                       f"binary rung-3 block) scored in FP64, one thread, {dt:.1f} s"}
 
 
+MI355X_BF16_TFLOPS = 2500.0               # dense MFMA
+GEMMS_PER_PAIR = 12                       # BF16 form: 12 contractions over the samples per (u, v) pair
+
+
+def recall_of(fi, fs, bi, tol=1e-6):
+    """Tie-aware top-K' recall of a form against the FP32 form (a missing FP32
+    member within tol of the cutoff ties with it and counts as found)."""
+    got = set(bi.tolist())
+    cutoff = fs[-1]
+    found = sum(1 for i, sc in zip(fi.tolist(), fs.tolist()) if i in got or sc <= cutoff + tol)
+    raw = sum(1 for i in fi.tolist() if i in got)
+    return found / len(fi), raw / len(fi)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -91,15 +116,10 @@ def main():
     p = {"C3": I.config3, "C2": I.config2, "C1": I.config1}[args.workload]()
     dev = torch.device("cuda:0")
     n = p.X.shape[0]
-    print(f"[bench] workload {args.workload} n={n} d={p.X.shape[1]} k={p.k} D={p.dmax}", file=sys.stderr,
-          flush=True)
-
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    log(f"workload {args.workload} n={n} d={p.X.shape[1]} k={p.k} D={p.dmax}")
     keep0 = args.keep0 or (1024 if p.rect else 2 * p.k)
-
-    def one_step(timings=None):
-        eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
-        res = eng.fit(p.k, p.dmax, keep0=keep0, grid=args.grid, tile=args.tile, timings=timings)
-        return eng, res
+    band = args.band
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -108,46 +128,93 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        print("[bench] copy calibration: 3 x 1 GiB device copies", file=sys.stderr, flush=True)
+        log("copy calibration: 3 x 1 GiB device copies")
+
+    def ev_ms(tm, name):
+        return [a.elapsed_time(b) for a, b in tm.get(name, [])]
+
+    # ---- forms: BF16 against plain FP32 on the first residual (y)
+    forms = {}
+    prec = args.precision
+    if p.rect and prec in ("auto", "bf16") and not args.no_forms:
+        eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
+        y64 = eng.y
+        out = {}
+        for form in ("fp32", "bf16", "bf16"):       # BF16 twice: the first call prepares operands
+            tm = {}
+            ids, sc, cnt = eng.screen(y64, keep0, None, precision=form, band=band, events=tm)
+            torch.cuda.synchronize()
+            c = int(cnt.item())
+            out[form] = (ids[:c].cpu().numpy(), sc[:c].cpu().numpy(), tm)
+        fi, fs, tf = out["fp32"]
+        bi, bs, tb = out["bf16"]
+        rec, raw = recall_of(fi, fs, bi)
+        fp32_ms = sum(ev_ms(tf, "binary"))
+        bf16_ms = sum(ev_ms(tb, "binary"))
+        forms = {"fp32": {"binary_block_ms": fp32_ms, "k_score_rect_ms": fp32_ms},
+                 "bf16": {"binary_block_ms": bf16_ms, "k_score_rect_bf16_ms": sum(ev_ms(tb, "bf16_screen")),
+                          "operand_prep_ms": sum(ev_ms(tb, "bf16_residual")),
+                          "band_rescore_ms": sum(ev_ms(tb, "bf16_rescore")), "band": band,
+                          "recall": rec, "recall_raw": raw, "speedup_vs_fp32": fp32_ms / bf16_ms,
+                          "keep": keep0}}
+        log(f"forms: fp32 {fp32_ms:.1f} ms, bf16 {bf16_ms:.1f} ms, recall {rec:.4f} (raw {raw:.4f})")
+        if prec == "auto":
+            prec = "bf16" if rec >= 0.99 else "fp32"
+        del eng
+        torch.cuda.empty_cache()
+    elif prec == "auto":
+        prec = "fp32"
+
+    def one_step(timings=None):
+        eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
+        res = eng.fit(p.k, p.dmax, keep0=keep0, grid=args.grid, tile=args.tile, timings=timings,
+                      precision=prec, band=band)
+        return eng, res
 
     for w in range(args.warmup):
         one_step()
         torch.cuda.synchronize()
-        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        log(f"warmup {w + 1}/{args.warmup} done")
 
     timings = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
-    for s in range(args.steps):
+    for st in range(args.steps):
         eng, res = one_step(timings)
         results.append(res)
         torch.cuda.synchronize()
-        print(f"[bench] step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        log(f"step {st + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
 
-    def ev_ms(name):
-        return [a.elapsed_time(b) for a, b in timings.get(name, [])]
-
     total = eng.total
     bb = eng.binary_base()
     n_bin = total - bb
-    passes_per_step = sum(1 for _ in ev_ms("pool")) / args.steps
+    passes_per_step = len(ev_ms(timings, "pool")) / args.steps if ev_ms(timings, "pool") else \
+        len(ev_ms(timings, "binary")) / args.steps
     cands_per_step = passes_per_step * total
     value = cands_per_step / (wall / args.steps)
-    so_tuples = sum(math.comb(200 * t if args.workload == "C3" else p.k * t, t)
-                    for t in range(1, p.dmax + 1))
-    l0_ms = sum(sum(ev_ms(f"l0_D{t}")) for t in range(1, p.dmax + 1)) / args.steps
-    so_ms_d3 = sum(ev_ms(f"l0_D{p.dmax}")) / max(1, len(ev_ms(f"l0_D{p.dmax}")))
+    l0_ms = sum(sum(ev_ms(timings, f"l0_D{t}")) for t in range(1, p.dmax + 1)) / args.steps
+    d3 = ev_ms(timings, f"l0_D{p.dmax}")
+    so_ms_d3 = sum(d3) / max(1, len(d3))
     so_m = timings.get("so_m", [0])
     dmax_tuples = math.comb(so_m[p.dmax - 1] if len(so_m) >= p.dmax else p.k * p.dmax, p.dmax)
-
-    bin_ms = ev_ms("binary")
-    pool_ms = ev_ms("pool")
-    if n_bin > 0 and bin_ms:
-        kernel_ms = sum(bin_ms) / len(bin_ms)
+    pool_ms = ev_ms(timings, "pool")
+    if n_bin > 0 and prec == "bf16":
+        ks = ev_ms(timings, "bf16_screen")
+        kernel_ms = sum(ks) / len(ks)
+        pairs = n_bin // eng.space.n_slots
+        flops = 2.0 * GEMMS_PER_PAIR * n * pairs
+        achieved = flops / (kernel_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "k_score_rect_bf16", "achieved": achieved,
+                "peak": MI355X_BF16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MI355X_BF16_TFLOPS,
+                "traffic": None, "avg_launch_ms": kernel_ms, "units_per_launch": pairs,
+                "per_unit": f"{GEMMS_PER_PAIR} GEMMs x 2 flops x n={n} samples per (u, v) pair"}
+    elif n_bin > 0:
+        kb = ev_ms(timings, "binary")
+        kernel_ms = sum(kb) / len(kb)
         flops = FLOPS_PER_CAND_SAMPLE * n * n_bin
         achieved = flops / (kernel_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": "k_score_rect", "achieved": achieved,
@@ -163,35 +230,40 @@ def main():
                 "peak": MI355X_HBM_GBS, "unit": "GB/s", "frac": achieved / MI355X_HBM_GBS,
                 "traffic": None, "avg_launch_ms": kernel_ms, "units_per_launch": total,
                 "per_unit": f"4 bytes x n={n} samples per stored column"}
+    if "fp32" in forms and n_bin > 0:
+        fms = forms["fp32"]["k_score_rect_ms"]
+        forms["fp32"]["roofline_frac"] = FLOPS_PER_CAND_SAMPLE * n * n_bin / (fms * 1e-3) / 1e12 / \
+            MI355X_FP32_NONPACKED_TFLOPS
 
     last = results[-1]
     out = {
         "metric": "SIS candidates scored/s + SO tuples/s at rung 3; learned/BF16 vs plain @99% recall",
         "value": value, "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if prec == "bf16" else "f32",
+        "data": "synthetic",
         "config": {"workload": {"C3": "rung-3 SISSO fit: n=2000, d=20 LogNormal(0,0.5), ops {+,-,*,/,^2,sqrt,1/x}, "
                                       "pool levels 0-2 + one-sided rung-3 slice (13,667,146,300 candidates), "
-                                      "k=200, D=1..3, FP32 screening, FP64 SO",
+                                      "k=200, D=1..3, FP64 SO",
                                 "C2": "rung-2 SISSO fit: n=500, d=10, full operator set, k=100, D=1..3",
                                 "C1": "rung-2 SISSO fit: n=50, d=5, k=20, D=1..2"}[args.workload],
-                   "n": n, "d": p.X.shape[1], "candidates_per_pass": total, "k": p.k, "D": p.dmax},
+                   "n": n, "d": p.X.shape[1], "candidates_per_pass": total, "k": p.k, "D": p.dmax,
+                   "screening_form": prec, "keep0": keep0, "band": band if prec == "bf16" else None},
         "sis_passes_per_step": passes_per_step,
         "sis_candidates_per_step": cands_per_step,
         "so_tuples_per_s": dmax_tuples / (so_ms_d3 * 1e-3) if so_ms_d3 > 0 else None,
         "so_tuples_D3": dmax_tuples,
         "so_ms_per_step": l0_ms,
-        "sis_binary_kernel_ms": kernel_ms,
         "sis_pool_pass_ms": (sum(pool_ms) / len(pool_ms)) if pool_ms else None,
-        "topk_ms": (sum(ev_ms("topk")) / len(ev_ms("topk"))) if ev_ms("topk") else None,
+        "topk_ms": (sum(ev_ms(timings, "topk")) / len(ev_ms(timings, "topk"))) if ev_ms(timings, "topk") else None,
         "roofline": roof,
+        "forms": forms,
         "fit": {"rmse": [r.rmse for r in last], "best_ids": [list(map(int, r.best_ids)) for r in last],
-                "keep": [r.keep for r in last], "keep0": keep0},
+                "keep": [r.keep for r in last]},
     }
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cb = cpu_baseline(p, args.cpu_seconds)
-        out["cpu_baseline"] = cb
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out))
 
 

@@ -249,6 +249,17 @@ sisso_status sisso_prepare_bf16(const sisso_space *space, const sisso_score_args
 size_t sisso_bf16_workspace_size(const sisso_space *space, const sisso_score_args *args, int32_t band);
 int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_score_args *args,
                                       int32_t band);
+/* The three steps of sisso_expand_score_bf16, for callers that time or
+ * overlap them: the residual-dependent operands (v side and the u side's
+ * residual sums), the MFMA screen into the band lists of `bws`, and the band
+ * top-k plus exact FP32 rescore into `ws`. */
+sisso_status sisso_bf16_residual(const sisso_space *space, const sisso_score_args *args, int32_t band,
+                                 void *bws, size_t bws_bytes, void *stream);
+sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_score_args *args, const void *ops,
+                               size_t ops_bytes, int32_t band, int64_t cand_begin, int64_t cand_end,
+                               void *bws, size_t bws_bytes, void *stream);
+sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso_score_args *args, int32_t band,
+                                void *bws, size_t bws_bytes, void *ws, size_t ws_bytes, void *stream);
 sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score_args *args,
                                      const void *ops, size_t ops_bytes, int32_t band,
                                      int64_t cand_begin, int64_t cand_end, void *bws, size_t bws_bytes,

@@ -92,6 +92,9 @@ def lib():
         "sisso_bf16_workspace_size": (_sz, [sp, ap, _i32]),
         "sisso_expand_score_bf16_lists": (_i32, [sp, ap, _i32]),
         "sisso_expand_score_bf16": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _vp, _sz, _vp]),
+        "sisso_bf16_residual": (_i32, [sp, ap, _i32, _vp, _sz, _vp]),
+        "sisso_bf16_screen": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _vp]),
+        "sisso_bf16_rescore": (_i32, [sp, ap, _i32, _vp, _sz, _vp, _sz, _vp]),
         "sisso_status_string": (ctypes.c_char_p, [_i32]),
         "sisso_version": (ctypes.c_char_p, []),
     }
@@ -109,6 +112,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_subspace_update", "sisso_l0_workspace_size", "sisso_l0_search",
             "sisso_sort_subspace", "sisso_bf16_operands_size", "sisso_prepare_bf16",
             "sisso_bf16_workspace_size", "sisso_expand_score_bf16_lists", "sisso_expand_score_bf16",
+            "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore",
             "sisso_status_string", "sisso_version"]
 
 

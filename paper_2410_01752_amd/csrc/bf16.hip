@@ -13,7 +13,11 @@
 // and likewise u/v (with W~) and v/u (with Z~ against V~); u + v and u - v
 // need only G[U~, V~].  Twelve GEMMs over a tile of (u, v) pairs, with the
 // per-column terms folded into the v-side operands, give all five forms.
-// They run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation; sums of single
+// They run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Every operand
+// is stored as two BF16 parts, x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
+// and each product is hi*hi + hi*lo + lo*hi: BF16 alone (8-bit mantissa) cannot
+// resolve forms whose centred terms cancel (ratios of strongly related operands,
+// e.g. (x0 x1 x2)/(x0 x1)), the split form keeps about 16 bits.  Sums of single
 // columns are exact (FP64).  The BF16 scores only select a band; every
 // candidate of the band is rescored with the plain FP32 kernel's arithmetic
 // (shared functions), so reported scores are the FP32 path's scores.
@@ -26,6 +30,7 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int kUVar = 4;      // U~, U~^2, Z~, Z~^2
 constexpr int kVVar = 8;      // V~, V~ r, P, Q, W~, W~ r, Pw, Qw
+constexpr int kSplit = 2;     // BF16 parts per operand (hi, lo)
 constexpr int kBT = 64;       // (u, v) pairs per block side: 2 x 2 waves of 32 x 32
 constexpr int kKC = 16;       // samples per LDS stage (one MFMA k-step)
 constexpr int kKP = kKC + 8;  // padded LDS row (bf16)
@@ -38,27 +43,28 @@ constexpr int kNG = 12;       // GEMMs per tile
 
 __host__ __device__ inline size_t align256b(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// u-side operand buffer: [kUVar][ucols][ldb] bf16, then ucols float4 sums.
+// u-side operand buffer: [kUVar * kSplit][ucols][ldb] bf16 (variant-major,
+// hi then lo), then ucols float4 sums.
 struct BfOps {
     __bf16 *U;
     float4 *usum;     // mean(u), mean(1/u), sum u~^2, sum z~^2
 };
 __host__ __device__ inline size_t bf_ops_bytes(int64_t ucols, int64_t ldb)
 {
-    return align256b((size_t)kUVar * ucols * ldb * sizeof(__bf16)) + align256b((size_t)ucols * sizeof(float4));
+    return align256b((size_t)kUVar * kSplit * ucols * ldb * sizeof(__bf16)) + align256b((size_t)ucols * sizeof(float4));
 }
 __host__ __device__ inline BfOps bf_ops_view(void *p, int64_t ucols, int64_t ldb)
 {
     BfOps o;
     o.U = (__bf16 *)p;
-    o.usum = (float4 *)((char *)p + align256b((size_t)kUVar * ucols * ldb * sizeof(__bf16)));
+    o.usum = (float4 *)((char *)p + align256b((size_t)kUVar * kSplit * ucols * ldb * sizeof(__bf16)));
     return o;
 }
 
 // per-pass BF16 workspace: v-side operands and sums, u-side residual sums,
 // band lists (a screening workspace of its own) and the band ids.
 struct BfWs {
-    __bf16 *V;        // [kVVar][vcols][ldb]
+    __bf16 *V;        // [kVVar * kSplit][vcols][ldb]
     float4 *vsum;     // 2 per column: (mean v, mean 1/v, sum v~^2, sum w~^2), (sum v~ r, sum w~ r, rms, 0)
     float2 *ures;     // per u column: sum u~ r, sum z~ r
     int64_t *band_ids;
@@ -68,7 +74,7 @@ struct BfWs {
 };
 __host__ __device__ inline size_t bf_ws_bytes(int64_t ucols, int64_t vcols, int64_t ldb, int band, int lists, int keep)
 {
-    size_t b = align256b((size_t)kVVar * vcols * ldb * sizeof(__bf16));
+    size_t b = align256b((size_t)kVVar * kSplit * vcols * ldb * sizeof(__bf16));
     b += align256b((size_t)vcols * 2 * sizeof(float4));
     b += align256b((size_t)ucols * sizeof(float2));
     b += align256b((size_t)band * sizeof(int64_t)) + align256b((size_t)band * sizeof(float)) + 256;
@@ -79,7 +85,7 @@ __host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols
 {
     BfWs w;
     char *c = (char *)p;
-    w.V = (__bf16 *)c; c += align256b((size_t)kVVar * vcols * ldb * sizeof(__bf16));
+    w.V = (__bf16 *)c; c += align256b((size_t)kVVar * kSplit * vcols * ldb * sizeof(__bf16));
     w.vsum = (float4 *)c; c += align256b((size_t)vcols * 2 * sizeof(float4));
     w.ures = (float2 *)c; c += align256b((size_t)ucols * sizeof(float2));
     w.band_ids = (int64_t *)c; c += align256b((size_t)band * sizeof(int64_t));
@@ -90,6 +96,17 @@ __host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols
 }
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// Store x as its two BF16 parts: variant q of a (variant, column) matrix with
+// kSplit parts per variant, hi at part 0 and lo at part 1.
+__device__ __forceinline__ void store_split(__bf16 *base, int q, int64_t cols, int64_t c, int64_t ldb, int64_t t,
+                                            float x)
+{
+    const __bf16 hi = to_bf16(x);
+    const __bf16 lo = to_bf16(x - (float)hi);
+    base[((size_t)(q * kSplit + 0) * cols + c) * ldb + t] = hi;
+    base[((size_t)(q * kSplit + 1) * cols + c) * ldb + t] = lo;
+}
 
 // ---------------------------------------------------------------- operands
 
@@ -116,10 +133,10 @@ __global__ void __launch_bounds__(256) k_bf16_u_prep(int n, const float *__restr
                 suu += (double)uu * uu;
                 szz += (double)zz * zz;
             }
-            ops.U[((size_t)0 * ucols + c) * ldb + t] = to_bf16(uu);
-            ops.U[((size_t)1 * ucols + c) * ldb + t] = to_bf16(uu * uu);
-            ops.U[((size_t)2 * ucols + c) * ldb + t] = to_bf16(zz);
-            ops.U[((size_t)3 * ucols + c) * ldb + t] = to_bf16(zz * zz);
+            store_split(ops.U, 0, ucols, c, ldb, t, uu);
+            store_split(ops.U, 1, ucols, c, ldb, t, uu * uu);
+            store_split(ops.U, 2, ucols, c, ldb, t, zz);
+            store_split(ops.U, 3, ucols, c, ldb, t, zz * zz);
         }
         suu = wave_sum(suu);
         szz = wave_sum(szz);
@@ -180,7 +197,7 @@ __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restr
             const float var[kVVar] = {vv, vv * r, vv * (vv + 2.f * mv), vv * (vv + mv),
                                       ww, ww * r, ww * (ww + 2.f * mw), ww * (ww + mw)};
 #pragma unroll
-            for (int q = 0; q < kVVar; ++q) w.V[((size_t)q * vcols + c) * ldb + t] = to_bf16(var[q]);
+            for (int q = 0; q < kVVar; ++q) store_split(w.V, q, vcols, c, ldb, t, var[q]);
         }
         svv = wave_sum(svv); sww = wave_sum(sww); svr = wave_sum(svr); swr = wave_sum(swr);
         if (lane == 0) {
@@ -200,9 +217,11 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     int64_t ut_hi, int64_t id_begin, int64_t id_end, void *lws, int lists_total, int keep, int cap)
 {
     extern __shared__ unsigned char smem[];
-    constexpr int ASZ = kUVar * kBT * kKP, BSZ = kVVar * kBT * kKP;
-    __bf16 *const sbase = reinterpret_cast<__bf16 *>(smem);
-    float *lsc = (float *)((__bf16 *)smem + 2 * (ASZ + BSZ));
+    constexpr int AV = kUVar * kSplit, BV = kVVar * kSplit;   // staged matrices per side
+    constexpr int ASZ = AV * kBT * kKP, BSZ = BV * kBT * kKP;
+    __bf16 *const sA = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *const sB = sA + ASZ;
+    float *lsc = (float *)(sB + BSZ);
     int64_t *lid = (int64_t *)(lsc + cap);
     __shared__ int lcnt;
     __shared__ float lthr;
@@ -219,6 +238,8 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
     const int nch = (n + kKC - 1) / kKC;
     const int64_t nvt = (vcount + kBT - 1) / kBT;
+    constexpr int NA = AV * kBT * (kKC / 8) / 256;   // 16-byte pieces per thread, A side
+    constexpr int NB = BV * kBT * (kKC / 8) / 256;   // and B side
 
     for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
         const int64_t u0 = ut * kBT;   // index into the newest level
@@ -229,70 +250,61 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
             for (int g = 0; g < kNG; ++g)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
-            // staging: A = kUVar x 64 columns x 16 samples (512 x 16 B, 2 per thread),
-            // B = kVVar x 64 x 16 (1024 x 16 B, 4 per thread)
-            uint4 pa[2], pb[4];
+            uint4 pa[NA], pb[NB];
             auto load_chunk = [&](int ch) {
                 const int64_t k0 = (int64_t)ch * kKC;
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < NA; ++q) {
                     const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
                     const int64_t c = u0 + col;
                     pa[q] = c < ucols ? *reinterpret_cast<const uint4 *>(U + ((size_t)var * ucols + c) * ldb + k0 + part * 8)
                                       : make_uint4(0, 0, 0, 0);
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < NB; ++q) {
                     const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
                     const int64_t c = v0 + col;
                     pb[q] = c < vcount ? *reinterpret_cast<const uint4 *>(V + ((size_t)var * vcount + c) * ldb + k0 + part * 8)
                                        : make_uint4(0, 0, 0, 0);
                 }
             };
-            auto store_chunk = [&](int b) {
+            auto store_chunk = [&]() {
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < NA; ++q) {
                     const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
-                    *reinterpret_cast<uint4 *>((sbase + b * (ASZ + BSZ)) + (var * kBT + col) * kKP + part * 8) = pa[q];
+                    *reinterpret_cast<uint4 *>(sA + (var * kBT + col) * kKP + part * 8) = pa[q];
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < NB; ++q) {
                     const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
-                    *reinterpret_cast<uint4 *>((sbase + b * (ASZ + BSZ) + ASZ) + (var * kBT + col) * kKP + part * 8) = pb[q];
+                    *reinterpret_cast<uint4 *>(sB + (var * kBT + col) * kKP + part * 8) = pb[q];
                 }
             };
-            __syncthreads();
             load_chunk(0);
-            store_chunk(0);
-            __syncthreads();
             for (int ch = 0; ch < nch; ++ch) {
-                const int b = ch & 1;
-                if (ch + 1 < nch) load_chunk(ch + 1);
-#pragma unroll
-                for (int kk = 0; kk < kKC / 16; ++kk) {
-                    const int koff = kk * 16 + (lane >> 5) * 8;
-                    bf16x8 af[kUVar], bfr[kVVar];
-#pragma unroll
-                    for (int a = 0; a < kUVar; ++a)
-                        af[a] = *reinterpret_cast<const bf16x8 *>((sbase + b * (ASZ + BSZ)) + (a * kBT + wu * 32 + (lane & 31)) * kKP + koff);
-#pragma unroll
-                    for (int q = 0; q < kVVar; ++q)
-                        bfr[q] = *reinterpret_cast<const bf16x8 *>((sbase + b * (ASZ + BSZ) + ASZ) + (q * kBT + wv * 32 + (lane & 31)) * kKP + koff);
-                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[0], acc[0], 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[1], acc[1], 0, 0, 0);
-                    acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1], bfr[2], acc[2], 0, 0, 0);
-                    acc[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[3], acc[3], 0, 0, 0);
-                    acc[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[4], acc[4], 0, 0, 0);
-                    acc[5] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[5], acc[5], 0, 0, 0);
-                    acc[6] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[1], bfr[6], acc[6], 0, 0, 0);
-                    acc[7] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[0], bfr[7], acc[7], 0, 0, 0);
-                    acc[8] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[2], bfr[0], acc[8], 0, 0, 0);
-                    acc[9] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[2], bfr[1], acc[9], 0, 0, 0);
-                    acc[10] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[3], bfr[2], acc[10], 0, 0, 0);
-                    acc[11] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[2], bfr[3], acc[11], 0, 0, 0);
-                }
-                if (ch + 1 < nch) store_chunk(b ^ 1);
+                __syncthreads();                      // the previous chunk's fragments are read
+                store_chunk();
                 __syncthreads();
+                if (ch + 1 < nch) load_chunk(ch + 1); // in flight during the MFMAs
+                const int koff = (lane >> 5) * 8;
+                bf16x8 af[AV], bfr[BV];
+#pragma unroll
+                for (int a = 0; a < AV; ++a)
+                    af[a] = *reinterpret_cast<const bf16x8 *>(sA + (a * kBT + wu * 32 + (lane & 31)) * kKP + koff);
+#pragma unroll
+                for (int q = 0; q < BV; ++q)
+                    bfr[q] = *reinterpret_cast<const bf16x8 *>(sB + (q * kBT + wv * 32 + (lane & 31)) * kKP + koff);
+                // GEMM g: u-side variant GA[g], v-side variant GB[g]; terms hi*hi, hi*lo, lo*hi
+                constexpr int GA[kNG] = {0, 0, 1, 0, 0, 0, 1, 0, 2, 2, 3, 2};
+                constexpr int GB[kNG] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3};
+#pragma unroll
+                for (int term = 0; term < 3; ++term) {
+                    const int pa_ = term == 2 ? 1 : 0, pb_ = term == 1 ? 1 : 0;
+#pragma unroll
+                    for (int g = 0; g < kNG; ++g)
+                        acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[GA[g] * kSplit + pa_],
+                                                                         bfr[GB[g] * kSplit + pb_], acc[g], 0, 0, 0);
+                }
             }
 
             // epilogue: lane holds column j = lane % 32 and rows
@@ -569,58 +581,93 @@ extern "C" int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const
     return (band + 255) / 256;
 }
 
-extern "C" sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score_args *args,
-                                                const void *ops, size_t ops_bytes, int32_t band, int64_t cand_begin,
-                                                int64_t cand_end, void *bws, size_t bws_bytes, void *ws,
-                                                size_t ws_bytes, void *stream)
+namespace {
+
+sisso_status bf_check(const sisso_space *space, const sisso_score_args *args, int32_t band, size_t bws_bytes)
 {
-    if (!space || !args || !ops || !bws || !ws || !args->pool32 || !args->stats || !args->r32 || !args->info)
-        return SISSO_E_NULL;
+    if (!space || !args || !args->pool32 || !args->stats || !args->r32 || !args->info) return SISSO_E_NULL;
     if (args->n_exclude > 0 && !args->exclude) return SISSO_E_NULL;
     if (!space_ok(space)) return SISSO_E_UNSUPPORTED;
     const int n = args->n;
     if (n < 2 || n > SISSO_MAX_N || args->ld32 < n || (args->ld32 % 4) != 0 || args->n_exclude < 0)
         return SISSO_E_SHAPE;
-    if (args->keep < 1 || args->keep > SISSO_MAX_KEEP || band < args->keep || band > SISSO_MAX_KEEP) return SISSO_E_RANGE;
-    const int L = space->levels;
+    if (args->keep < 1 || args->keep > SISSO_MAX_KEEP || band < args->keep || band > SISSO_MAX_KEEP)
+        return SISSO_E_RANGE;
+    if (bws_bytes < sisso_bf16_workspace_size(space, args, band)) return SISSO_E_WORKSPACE;
+    return SISSO_OK;
+}
+
+}  // namespace
+
+extern "C" sisso_status sisso_bf16_residual(const sisso_space *space, const sisso_score_args *args, int32_t band,
+                                            void *bws, size_t bws_bytes, void *stream)
+{
+    if (!bws) return SISSO_E_NULL;
+    const sisso_status c = bf_check(space, args, band, bws_bytes);
+    if (c != SISSO_OK) return c;
+    hipStream_t st = as_stream(stream);
+    const int L = space->levels, n = args->n;
+    const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
+    const int64_t ldb = ldb_of(n);
+    BfWs w = bf_ws_view(bws, ucols, vcols, ldb, band);
+    const int64_t vb = (vcols + 3) / 4, ub = (ucols + 3) / 4;
+    hipLaunchKernelGGL(k_bf16_v_prep, dim3((unsigned)(vb < 65536 ? vb : 65536)), dim3(256), 0, st, n, args->pool32,
+                       args->ld32, args->stats, vcols, ldb, args->r32, w);
+    hipLaunchKernelGGL(k_bf16_u_resid, dim3((unsigned)(ub < 65536 ? ub : 65536)), dim3(256), 0, st, n, args->pool32,
+                       args->ld32, args->stats, col0, ucols, args->r32, w.ures);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_score_args *args, const void *ops,
+                                          size_t ops_bytes, int32_t band, int64_t cand_begin, int64_t cand_end,
+                                          void *bws, size_t bws_bytes, void *stream)
+{
+    if (!ops || !bws) return SISSO_E_NULL;
+    const sisso_status c = bf_check(space, args, band, bws_bytes);
+    if (c != SISSO_OK) return c;
+    const int L = space->levels, n = args->n;
     const int64_t bb = space->pool[L] + space->rect_unary;
     if (cand_begin < bb || cand_end > space->total || cand_begin >= cand_end) return SISSO_E_RANGE;
     if (ops_bytes < sisso_bf16_operands_size(space, n)) return SISSO_E_WORKSPACE;
-    if (bws_bytes < sisso_bf16_workspace_size(space, args, band)) return SISSO_E_WORKSPACE;
-    const int lists_main = score_lists_capacity(space, args);
-    const int n_resc = (band + 255) / 256;
-    if (ws_bytes < ws_bytes_for(lists_main, args->keep)) return SISSO_E_WORKSPACE;
-    if (args->list_base < 0 || args->list_base + n_resc > lists_main) return SISSO_E_WORKSPACE;
-
     hipStream_t st = as_stream(stream);
     const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
     const int64_t ldb = ldb_of(n);
     const BfOps o = bf_ops_view(const_cast<void *>(ops), ucols, ldb);
     BfWs w = bf_ws_view(bws, ucols, vcols, ldb, band);
     const FormSlots fs = form_slots(space);
-    // residual-dependent operands
-    const int64_t vb = (vcols + 3) / 4, ub = (ucols + 3) / 4;
-    hipLaunchKernelGGL(k_bf16_v_prep, dim3((unsigned)(vb < 65536 ? vb : 65536)), dim3(256), 0, st, n, args->pool32,
-                       args->ld32, args->stats, vcols, ldb, args->r32, w);
-    hipLaunchKernelGGL(k_bf16_u_resid, dim3((unsigned)(ub < 65536 ? ub : 65536)), dim3(256), 0, st, n, args->pool32,
-                       args->ld32, args->stats, col0, ucols, args->r32, w.ures);
-    // BF16 screen -> band lists
     const BfPlan p = bf_plan(space, cand_begin, cand_end);
     const int keep_b = band;   // every block keeps the whole band: the grid-wide bound stays valid
     const int cap_b = bf_list_cap(keep_b);
     const int lcap = bf_lists_cap(space);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)2 * (kUVar + kVVar) * kBT * kKP * sizeof(__bf16) +
+        const size_t smem = (size_t)(kUVar + kVVar) * kSplit * kBT * kKP * sizeof(__bf16) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16, smem)) return SISSO_E_UNSUPPORTED;
         hipLaunchKernelGGL(k_score_rect_bf16, dim3(p.grid), dim3(256), smem, st, *space, fs, n, ldb, o.U, o.usum, w.V,
                            w.vsum, w.ures, args->stats, args->info, args->exclude, args->n_exclude, p.ut_lo, p.ut_hi,
                            cand_begin, cand_end, w.lists, lcap, keep_b, cap_b);
     }
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso_score_args *args, int32_t band,
+                                           void *bws, size_t bws_bytes, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!bws || !ws) return SISSO_E_NULL;
+    const sisso_status c = bf_check(space, args, band, bws_bytes);
+    if (c != SISSO_OK) return c;
+    const int lists_main = score_lists_capacity(space, args);
+    const int n_resc = (band + 255) / 256;
+    if (ws_bytes < ws_bytes_for(lists_main, args->keep)) return SISSO_E_WORKSPACE;
+    if (args->list_base < 0 || args->list_base + n_resc > lists_main) return SISSO_E_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    const int L = space->levels, n = args->n;
+    const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
+    BfWs w = bf_ws_view(bws, ucols, vcols, ldb_of(n), band);
+    const FormSlots fs = form_slots(space);
     sisso_status rs = topk_launch(w.lists, band, w.band_ids, w.band_sc, w.band_cnt, st, false);
     if (rs != SISSO_OK) return rs;
-    // exact FP32 rescore of the band into the main workspace
     const int keep = args->keep, cap = next_pow2(keep + 256);
     if (args->list_base == 0)
         hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)ws, keep, n_resc, lists_main);
@@ -631,4 +678,16 @@ extern "C" sisso_status sisso_expand_score_bf16(const sisso_space *space, const 
                        args->stats, args->r32, args->info, w.band_ids, w.band_cnt, args->exclude, args->n_exclude,
                        args->list_base, ws, lists_main, keep, cap);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score_args *args,
+                                                const void *ops, size_t ops_bytes, int32_t band, int64_t cand_begin,
+                                                int64_t cand_end, void *bws, size_t bws_bytes, void *ws,
+                                                size_t ws_bytes, void *stream)
+{
+    sisso_status st = sisso_bf16_residual(space, args, band, bws, bws_bytes, stream);
+    if (st != SISSO_OK) return st;
+    st = sisso_bf16_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, bws, bws_bytes, stream);
+    if (st != SISSO_OK) return st;
+    return sisso_bf16_rescore(space, args, band, bws, bws_bytes, ws, ws_bytes, stream);
 }

@@ -169,9 +169,24 @@ class Engine:
             if name == "binary" and use_bf16:
                 nb = L.lib().sisso_bf16_workspace_size(ctypes.byref(self.space), ctypes.byref(a), band)
                 bws = self._workspace("bf16", nb)
-                L.check(L.lib().sisso_expand_score_bf16(
-                    ctypes.byref(self.space), ctypes.byref(a), L.ptr(self.bf16_ops), self.bf16_ops.numel(),
-                    band, b, e, L.ptr(bws), bws.numel(), L.ptr(ws), ws.numel(), st), "sisso_expand_score_bf16")
+                sp_, a_ = ctypes.byref(self.space), ctypes.byref(a)
+                steps = [("bf16_residual", lambda: L.lib().sisso_bf16_residual(sp_, a_, band, L.ptr(bws),
+                                                                              bws.numel(), st)),
+                         ("bf16_screen", lambda: L.lib().sisso_bf16_screen(
+                             sp_, a_, L.ptr(self.bf16_ops), self.bf16_ops.numel(), band, b, e, L.ptr(bws),
+                             bws.numel(), st)),
+                         ("bf16_rescore", lambda: L.lib().sisso_bf16_rescore(sp_, a_, band, L.ptr(bws),
+                                                                            bws.numel(), L.ptr(ws), ws.numel(),
+                                                                            st))]
+                for sname, call in steps:
+                    if events is not None:
+                        s0 = torch.cuda.Event(enable_timing=True)
+                        s1 = torch.cuda.Event(enable_timing=True)
+                        s0.record()
+                    L.check(call(), "sisso_" + sname)
+                    if events is not None:
+                        s1.record()
+                        events.setdefault(sname, []).append((s0, s1))
                 nl = L.lib().sisso_expand_score_bf16_lists(ctypes.byref(self.space), ctypes.byref(a), band)
             else:
                 L.check(L.lib().sisso_expand_score(ctypes.byref(self.space), ctypes.byref(a), b, e,
