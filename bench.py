@@ -59,6 +59,7 @@ def parse():
                          "FP32 form, measured in this run, is >= 0.99")
     ap.add_argument("--band", type=int, default=2048, help="BF16 form: candidates rescored in FP32")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 vs FP32 recall check")
+    ap.add_argument("--no-autotune", action="store_true", help="use the library's default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -165,9 +166,21 @@ def main():
     elif prec == "auto":
         prec = "fp32"
 
+    # ---- autotuned launch shape of the slice kernel for the chosen form
+    tile, grid, tuned = args.tile, args.grid, None
+    if p.rect and not args.no_autotune and not (args.tile or args.grid):
+        from paper_2410_01752_amd import autotune as AT
+        eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
+        ch = AT.tune_engine(eng, form=prec, keep=keep0, band=band, sample_tiles=1024)
+        tile, grid = ch.tile, ch.grid
+        tuned = {"tile": tile, "grid": grid, "sample_ms": ch.ms, "timings_ms": ch.timings}
+        log(f"autotune {prec}: tile {tile} grid {grid}")
+        del eng
+        torch.cuda.empty_cache()
+
     def one_step(timings=None):
         eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
-        res = eng.fit(p.k, p.dmax, keep0=keep0, grid=args.grid, tile=args.tile, timings=timings,
+        res = eng.fit(p.k, p.dmax, keep0=keep0, grid=grid, tile=tile, timings=timings,
                       precision=prec, band=band)
         return eng, res
 
@@ -258,6 +271,7 @@ def main():
         "topk_ms": (sum(ev_ms(timings, "topk")) / len(ev_ms(timings, "topk"))) if ev_ms(timings, "topk") else None,
         "roofline": roof,
         "forms": forms,
+        "autotune": tuned,
         "fit": {"rmse": [r.rmse for r in last], "best_ids": [list(map(int, r.best_ids)) for r in last],
                 "keep": [r.keep for r in last]},
     }

@@ -103,3 +103,19 @@ def test_bf16_fit_matches_fp32_fit():
     for x, y in zip(a, b):
         assert list(x.best_ids) == list(y.best_ids)
         assert abs(x.rmse - y.rmse) <= 1e-9 * x.rmse
+
+
+def test_autotuned_shapes_give_identical_results(tmp_path):
+    from paper_2410_01752_amd import autotune as A
+    p = I.tiny(9, n=300, d=6, dist="lognormal", rect=True)
+    eng = _engine(p)
+    cache = A.Cache(str(tmp_path / "at.json"))
+    for form in ("fp32", "bf16"):
+        ch = A.tune_engine(eng, form=form, keep=300, band=1200, sample_tiles=64, cache=cache)
+        assert cache.get(A.cache_key(*A.device_key(), "k_score_rect_bf16" if form == "bf16" else "k_score_rect",
+                                     form, eng.n)) is not None
+        r64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+        a = eng.screen(r64, 300, None, precision=form, band=1200)
+        b = eng.screen(r64, 300, None, precision=form, band=1200, tile=ch.tile, grid=ch.grid)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
