@@ -89,6 +89,7 @@ typedef enum {
 #define SISSO_MAX_KEEP 2048        /* screened-list length per call          */
 #define SISSO_MAX_SUBSPACE 1024    /* |S_t|                                  */
 #define SISSO_MAX_D 3              /* terms per SO model                     */
+#define SISSO_MAX_BATCH 4096       /* problems per batched call              */
 
 /* Feature space description (host struct).  Fill d, levels, rect and the
  * operator lists, then call sisso_space_init, which validates them and fills
@@ -159,6 +160,17 @@ sisso_status sisso_materialize_ids(const sisso_space *space, int32_t n, const do
                                    int64_t ld64, const sisso_colstat *stats, const int64_t *ids,
                                    int32_t count, double *out, int32_t ldo, int32_t *valid,
                                    void *stream);
+
+/* As sisso_materialize_ids, for a caller that stored only the pool levels
+ * 1..stored_levels (stats covers ids [0, pool[stored_levels])): features of
+ * higher TRI levels are evaluated from their operands like slice features.
+ * Used by batched problems, which store P_{levels-1}.  Errors: as
+ * sisso_materialize_ids; SISSO_E_SHAPE for stored_levels outside
+ * 1..levels. */
+sisso_status sisso_materialize_ids_stored(const sisso_space *space, int32_t stored_levels, int32_t n,
+                                          const double *pool1_64, int64_t ld64, const sisso_colstat *stats,
+                                          const int64_t *ids, int32_t count, double *out, int32_t ldo,
+                                          int32_t *valid, void *stream);
 
 /* Residual record used by the screening kernels (device, 4 doubles). */
 typedef struct {
@@ -273,6 +285,62 @@ sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score
  * workspace was filled with). */
 sisso_status sisso_topk(const void *ws, size_t ws_bytes, int32_t k, int64_t *out_ids,
                         float *out_scores, int32_t *out_count, void *stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent problems over one space: cross-validation folds and
+ * bootstrap resamples of a dataset, or several datasets (Sec. 3 evaluates
+ * by cross-validation; Sec. 4 runs independent fits side by side).  The
+ * space must be TRI with levels == 2 (rect == 0).  Each problem stores only
+ * P_1 (sisso_materialize_pools with a copy of the space whose levels is 1);
+ * the level-2 features are evaluated in registers from P_1 by the screening
+ * kernel.  The problem table is a DEVICE array of n_problems records. */
+typedef struct {
+    int32_t n;                     /* samples, 2..SISSO_MAX_N                     */
+    int32_t keep;                  /* list length K' of this problem, 1..keep_max */
+    int64_t ld32;                  /* leading dim of pool32 and r32: >= n, % 4 == 0 */
+    const float *pool32;           /* P_1: pool[1] FP32 columns                   */
+    const sisso_colstat *stats;    /* their statistics                            */
+    const double *r64;             /* FP64 residual (n), read by prepare          */
+    float *r32;                    /* centred FP32 residual, written by prepare   */
+    sisso_resid_info *info;        /* its record, written by prepare              */
+    const int64_t *exclude;        /* sorted ascending ids never admitted, or NULL */
+    int32_t n_exclude;
+    int32_t reserved;              /* 0                                           */
+} sisso_problem;
+
+/* sisso_prepare_residual for every problem of a table (one launch).  Entries
+ * with n outside 2..SISSO_MAX_N or a NULL r64/r32/info are skipped.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE (n_problems outside 1..SISSO_MAX_BATCH). */
+sisso_status sisso_prepare_residual_batched(const sisso_problem *problems, int32_t n_problems, void *stream);
+
+/* Workspace of a batched screening pass (0 for an unsupported space or
+ * out-of-range sizes), and the work items per problem (-1 if unsupported). */
+size_t sisso_batch_workspace_size(const sisso_space *space, int32_t n_problems, int32_t keep_max);
+int32_t sisso_batch_items(const sisso_space *space);
+
+/* Screen every problem of the table against its prepared residual in one
+ * persistent launch (Sec. 2.2, eq. sis-weight and eq. sis-method).  Work
+ * items (problem, 32 x 32 pair tile) and (problem, 64 stored columns) are
+ * taken from an atomic counter, largest n first; each keeps its best K'_p
+ * (score desc, id asc) not in the problem's exclude list.  grid: persistent
+ * blocks, 0 = as many as fit on the device at once.  The scores are those of
+ * the single-problem FP32 kernels.  An entry with an invalid field (n, keep,
+ * ld32, a NULL pointer) is skipped and reported by sisso_topk_batched.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE (n_problems, keep_max, grid),
+ * SISSO_E_UNSUPPORTED (space not TRI level 2), SISSO_E_WORKSPACE. */
+sisso_status sisso_expand_score_batched(const sisso_space *space, const sisso_problem *problems,
+                                        int32_t n_problems, int32_t keep_max, int32_t grid, void *ws,
+                                        size_t ws_bytes, void *stream);
+
+/* Per-problem merge of a batched screening workspace (one block per problem):
+ * row p of out_ids / out_scores (stride keep_max, the value of the screening
+ * call) receives problem p's best keep_p (score desc, id asc); out_count[p]
+ * the number written; out_status[p] (nullable) 0, SISSO_E_SHAPE for a skipped
+ * entry, or SISSO_E_RANGE if more than 4096 candidates tie at the cut.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE. */
+sisso_status sisso_topk_batched(const sisso_problem *problems, int32_t n_problems, const void *ws,
+                                size_t ws_bytes, int64_t *out_ids, float *out_scores, int32_t *out_count,
+                                int32_t *out_status, void *stream);
 
 /* Subspace update (Sec. 2.3, eq. subspace-expansion, with the duplicate
  * rule for non-unique features of Sec. 2.1).  Inputs: the screened list

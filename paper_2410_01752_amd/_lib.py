@@ -20,6 +20,7 @@ OPNAME = {v: k for k, v in OPCODE.items()}
 
 MAX_UNARY, MAX_BINARY, MAX_LEVELS = 8, 4, 2
 MAX_N, MAX_KEEP, MAX_SUBSPACE, MAX_D = 65536, 2048, 1024, 3
+MAX_BATCH = 4096
 FP32, BF16 = 0, 1
 
 
@@ -48,6 +49,14 @@ class ScoreArgs(ctypes.Structure):
                 ("list_base", ctypes.c_int32)]
 
 
+class Problem(ctypes.Structure):
+    """sisso_problem: one entry of a batched problem table (device array)."""
+    _fields_ = [("n", ctypes.c_int32), ("keep", ctypes.c_int32), ("ld32", ctypes.c_int64),
+                ("pool32", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("r64", ctypes.c_void_p),
+                ("r32", ctypes.c_void_p), ("info", ctypes.c_void_p), ("exclude", ctypes.c_void_p),
+                ("n_exclude", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 COLSTAT_FLOATS = 8      # sisso_colstat: 8 floats
 RESID_DOUBLES = 4       # sisso_resid_info: 4 doubles
 
@@ -74,7 +83,14 @@ def lib():
                                 ctypes.POINTER(_i64)]),
         "sisso_materialize_pools": (_i32, [sp, _vp, _i32, _i32, _vp, _i64, _vp, _i64, _vp, _vp]),
         "sisso_materialize_ids": (_i32, [sp, _i32, _vp, _i64, _vp, _vp, _i32, _vp, _i32, _vp, _vp]),
+        "sisso_materialize_ids_stored": (_i32, [sp, _i32, _i32, _vp, _i64, _vp, _vp, _i32, _vp, _i32, _vp,
+                                                _vp]),
         "sisso_prepare_residual": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+        "sisso_prepare_residual_batched": (_i32, [_vp, _i32, _vp]),
+        "sisso_batch_workspace_size": (_sz, [sp, _i32, _i32]),
+        "sisso_batch_items": (_i32, [sp]),
+        "sisso_expand_score_batched": (_i32, [sp, _vp, _i32, _i32, _i32, _vp, _sz, _vp]),
+        "sisso_topk_batched": (_i32, [_vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp]),
         "sisso_score_workspace_size": (_sz, [sp, ap]),
         "sisso_score_reset": (_i32, [_vp, _sz, _vp]),
         "sisso_expand_score": (_i32, [sp, ap, _i64, _i64, _vp, _sz, _vp]),
@@ -113,6 +129,8 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_sort_subspace", "sisso_bf16_operands_size", "sisso_prepare_bf16",
             "sisso_bf16_workspace_size", "sisso_expand_score_bf16_lists", "sisso_expand_score_bf16",
             "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore",
+            "sisso_materialize_ids_stored", "sisso_prepare_residual_batched", "sisso_batch_workspace_size",
+            "sisso_batch_items", "sisso_expand_score_batched", "sisso_topk_batched",
             "sisso_status_string", "sisso_version"]
 
 

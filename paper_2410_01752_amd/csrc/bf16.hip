@@ -495,16 +495,6 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 int64_t ldb_of(int n) { return ((int64_t)n + 63) / 64 * 64; }
 
-FormSlots form_slots(const sisso_space *space)
-{
-    FormSlots fs;
-    for (int k = 0; k < 5; ++k) fs.slot[k] = -1;
-    for (int sl = 0; sl < space->n_slots; ++sl) {
-        const int op = space->slot_op[sl], rev = space->slot_rev[sl];
-        fs.slot[op == SISSO_DIV ? (rev ? 4 : 3) : op] = sl;
-    }
-    return fs;
-}
 
 struct BfPlan {
     int64_t ut_lo = 0, ut_hi = 0;
@@ -513,7 +503,7 @@ struct BfPlan {
 
 constexpr int kMaxBfGrid = 1024;
 
-BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end)
+BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end, int max_grid = kMaxBfGrid)
 {
     BfPlan p;
     const int L = s->levels;
@@ -525,7 +515,7 @@ BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end)
     p.ut_lo = ul / kBT;
     p.ut_hi = (uh + kBT - 1) / kBT;
     const int64_t tiles = p.ut_hi - p.ut_lo;
-    p.grid = (int)(tiles < kMaxBfGrid ? tiles : kMaxBfGrid);
+    p.grid = (int)(tiles < max_grid ? tiles : max_grid);
     return p;
 }
 
@@ -635,7 +625,8 @@ extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_
     const BfOps o = bf_ops_view(const_cast<void *>(ops), ucols, ldb);
     BfWs w = bf_ws_view(bws, ucols, vcols, ldb, band);
     const FormSlots fs = form_slots(space);
-    const BfPlan p = bf_plan(space, cand_begin, cand_end);
+    const BfPlan p = bf_plan(space, cand_begin, cand_end,
+                             args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid);
     const int keep_b = band;   // every block keeps the whole band: the grid-wide bound stays valid
     const int cap_b = bf_list_cap(keep_b);
     const int lcap = bf_lists_cap(space);

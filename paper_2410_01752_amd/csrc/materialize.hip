@@ -132,7 +132,7 @@ __device__ __forceinline__ double eval_node(const Node &nd, const double *p1, in
 }
 
 // FP64 values of arbitrary features, one block per id.
-__global__ void __launch_bounds__(256) k_eval_ids(sisso_space s, int n, const double *__restrict__ p1,
+__global__ void __launch_bounds__(256) k_eval_ids(sisso_space s, int stored, int n, const double *__restrict__ p1,
                                                   int64_t ld64, const sisso_colstat *__restrict__ stats,
                                                   const int64_t *__restrict__ ids, int count,
                                                   double *__restrict__ out, int ldo,
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(256) k_eval_ids(sisso_space s, int n, const do
         Node L, R;
         bool opok = true;
         R.op = -1; R.a = -1; R.b = -1;
-        if (id < s.pool[s.levels]) {
+        if (id < s.pool[stored]) {
             L = make_node(s, id);
             opok = stats[id].valid != 0.0f;   // pool columns: decided at materialisation
         } else {
@@ -197,11 +197,9 @@ __global__ void __launch_bounds__(256) k_eval_ids(sisso_space s, int n, const do
 }
 
 // Centre a residual, round it to FP32 and record its sums (one block).
-__global__ void __launch_bounds__(1024) k_prepare_residual(const double *__restrict__ r, int n,
-                                                           float *__restrict__ r32,
-                                                           sisso_resid_info *__restrict__ info)
+__device__ inline void prepare_residual_block(const double *__restrict__ r, int n, float *__restrict__ r32,
+                                              sisso_resid_info *__restrict__ info, double *red)
 {
-    __shared__ double red[16];
     double s = 0.0;
     for (int t = threadIdx.x; t < n; t += blockDim.x) s += r[t];
     const double mean = block_sum(s, red) / n;
@@ -225,6 +223,24 @@ __global__ void __launch_bounds__(1024) k_prepare_residual(const double *__restr
         info->mean_r = mean;
         info->n = (double)n;
     }
+}
+
+__global__ void __launch_bounds__(1024) k_prepare_residual(const double *__restrict__ r, int n,
+                                                           float *__restrict__ r32,
+                                                           sisso_resid_info *__restrict__ info)
+{
+    __shared__ double red[16];
+    prepare_residual_block(r, n, r32, info, red);
+}
+
+// One block per problem of a batch; entries with a bad n or a null pointer
+// are left untouched (the batched screening flags them).
+__global__ void __launch_bounds__(1024) k_prepare_residual_batch(const sisso_problem *__restrict__ probs)
+{
+    __shared__ double red[16];
+    const sisso_problem P = probs[blockIdx.x];
+    if (P.n < 2 || P.n > SISSO_MAX_N || !P.r64 || !P.r32 || !P.info) return;
+    prepare_residual_block(P.r64, P.n, P.r32, P.info, red);
 }
 
 }  // namespace sisso
@@ -254,20 +270,32 @@ extern "C" sisso_status sisso_materialize_pools(const sisso_space *space, const 
     return SISSO_OK;
 }
 
+extern "C" sisso_status sisso_materialize_ids_stored(const sisso_space *space, int32_t stored_levels, int32_t n,
+                                                     const double *pool1_64, int64_t ld64,
+                                                     const sisso_colstat *stats, const int64_t *ids,
+                                                     int32_t count, double *out, int32_t ldo,
+                                                     int32_t *valid, void *stream)
+{
+    if (!space || !pool1_64 || !stats || !ids || !out || !valid) return SISSO_E_NULL;
+    if (space->total <= 0 || n < 2 || n > SISSO_MAX_N || ld64 < n || ldo < n || count < 0)
+        return SISSO_E_SHAPE;
+    if (stored_levels < 1 || stored_levels > space->levels) return SISSO_E_SHAPE;
+    if (count == 0) return SISSO_OK;
+    const int grid = count < 4096 ? count : 4096;
+    hipLaunchKernelGGL(k_eval_ids, dim3(grid), dim3(256), 0, as_stream(stream), *space, stored_levels, n,
+                       pool1_64, ld64, stats, ids, count, out, ldo, valid);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
 extern "C" sisso_status sisso_materialize_ids(const sisso_space *space, int32_t n,
                                               const double *pool1_64, int64_t ld64,
                                               const sisso_colstat *stats, const int64_t *ids,
                                               int32_t count, double *out, int32_t ldo,
                                               int32_t *valid, void *stream)
 {
-    if (!space || !pool1_64 || !stats || !ids || !out || !valid) return SISSO_E_NULL;
-    if (space->total <= 0 || n < 2 || n > SISSO_MAX_N || ld64 < n || ldo < n || count < 0)
-        return SISSO_E_SHAPE;
-    if (count == 0) return SISSO_OK;
-    const int grid = count < 4096 ? count : 4096;
-    hipLaunchKernelGGL(k_eval_ids, dim3(grid), dim3(256), 0, as_stream(stream), *space, n, pool1_64,
-                       ld64, stats, ids, count, out, ldo, valid);
-    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+    if (!space) return SISSO_E_NULL;
+    return sisso_materialize_ids_stored(space, space->levels, n, pool1_64, ld64, stats, ids, count, out, ldo,
+                                        valid, stream);
 }
 
 extern "C" sisso_status sisso_prepare_residual(const double *r, int32_t n, float *r32,
@@ -276,5 +304,14 @@ extern "C" sisso_status sisso_prepare_residual(const double *r, int32_t n, float
     if (!r || !r32 || !info) return SISSO_E_NULL;
     if (n < 2 || n > SISSO_MAX_N) return SISSO_E_SHAPE;
     hipLaunchKernelGGL(k_prepare_residual, dim3(1), dim3(1024), 0, as_stream(stream), r, n, r32, info);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_prepare_residual_batched(const sisso_problem *problems, int32_t n_problems,
+                                                       void *stream)
+{
+    if (!problems) return SISSO_E_NULL;
+    if (n_problems < 1 || n_problems > SISSO_MAX_BATCH) return SISSO_E_SHAPE;
+    hipLaunchKernelGGL(k_prepare_residual_batch, dim3(n_problems), dim3(1024), 0, as_stream(stream), problems);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }

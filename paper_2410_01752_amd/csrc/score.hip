@@ -20,7 +20,7 @@
 //                    candidates are never written to memory.
 // Every block keeps its best K' candidates (score desc, id asc) in LDS and
 // writes them to its list slot of the workspace; sisso_topk merges the lists.
-#include "screen.hpp"
+#include "tiles.hpp"
 
 namespace sisso {
 
@@ -41,9 +41,6 @@ __global__ void k_ws_append(WsHeader *h, int n_lists)
 }
 
 // ------------------------------------------------------ pool columns kernel
-
-constexpr int kColWaves = 4;       // waves per block
-constexpr int kColBatch = 16;      // columns per wave between list merges
 
 template <int NU>
 __global__ void __launch_bounds__(256) k_score_columns(
@@ -87,77 +84,13 @@ __global__ void __launch_bounds__(256) k_score_columns(
             for (int o = 0; o < PER; ++o) scs[o] = -1.0f;
             if (c < c_hi) {
                 const sisso_colstat st = stats[c];
-                const float *col = pool32 + (size_t)c * ld32;
-                const float f0 = st.mean;            // shift of the stored column
-                float a0 = 0.f, b0s = 0.f, c0 = 0.f;
-                float au[NU > 0 ? NU : 1], bu[NU > 0 ? NU : 1], cu[NU > 0 ? NU : 1], sh[NU > 0 ? NU : 1];
-                int badu = 0;
+                score_column<NU>(pool32 + (size_t)c * ld32, st, r32, n, nd, R1, Srr, uop, nu,
+                                 NU > 0 && rect && c >= newlo, scs);
+                if (!(c >= id_begin && c < id_end)) scs[0] = -1.0f;
 #pragma unroll
-                for (int o = 0; o < (NU > 0 ? NU : 1); ++o) au[o] = bu[o] = cu[o] = sh[o] = 0.f;
-                const bool do_unary = NU > 0 && rect && c >= newlo;
-                if (do_unary) {
-                    // shift of each unary candidate: its mean over the first 256 samples
-                    const int t = lane * 4;
-                    float4 fv = make_float4(0, 0, 0, 0);
-                    if (t < n) fv = *reinterpret_cast<const float4 *>(col + t);
-                    const float fa[4] = {fv.x, fv.y, fv.z, fv.w};
-                    const int cnt = n < 256 ? n : 256;
-#pragma unroll
-                    for (int o = 0; o < NU; ++o) {
-                        float acc = 0.f;
-                        if (o < nu) {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                if (t + e < n) {
-                                    const float h = unary32(uop[o], fa[e]);
-                                    acc += fabsf(h) <= 1e15f ? h : 0.f;
-                                }
-                        }
-                        sh[o] = (float)(wave_sum((double)acc) / cnt);
-                    }
-                }
-                for (int t = lane * 4; t < n; t += 256) {
-                    const float4 fv = *reinterpret_cast<const float4 *>(col + t);
-                    const float4 rv = *reinterpret_cast<const float4 *>(r32 + t);
-                    const float fa[4] = {fv.x, fv.y, fv.z, fv.w};
-                    const float ra[4] = {rv.x, rv.y, rv.z, rv.w};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        if (t + e < n) {
-                            const float g = fa[e] - f0;
-                            a0 += g; b0s = fmaf(g, g, b0s); c0 = fmaf(g, ra[e], c0);
-                            if (do_unary) {
-#pragma unroll
-                                for (int o = 0; o < NU; ++o) {
-                                    if (o < nu) {
-                                        const float h = unary32(uop[o], fa[e]);
-                                        badu |= (!(fabsf(h) <= 1e15f)) << o;
-                                        const float gu = h - sh[o];
-                                        au[o] += gu; bu[o] = fmaf(gu, gu, bu[o]); cu[o] = fmaf(gu, ra[e], cu[o]);
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }
-                const double A = wave_sum((double)a0), B = wave_sum((double)b0s), C = wave_sum((double)c0);
-                if (st.valid != 0.0f && c >= id_begin && c < id_end)
-                    scs[0] = score_from_sums(A, B, C, (double)f0, nd, R1, Srr);
-                if (do_unary) {
-                    badu = wave_or(badu);
-#pragma unroll
-                    for (int o = 0; o < NU; ++o) {
-                        if (o < nu) {
-                            const double Au = wave_sum((double)au[o]), Bu = wave_sum((double)bu[o]),
-                                         Cu = wave_sum((double)cu[o]);
-                            float bound;
-                            const bool dom = unary_domain_bound(uop[o], st, &bound);
-                            const int64_t uid = pL + (c - newlo) * nu + o;
-                            if (st.valid != 0.0f && dom && !((badu >> o) & 1) && uid >= id_begin &&
-                                uid < id_end)
-                                scs[1 + o] = score_from_sums(Au, Bu, Cu, (double)sh[o], nd, R1, Srr);
-                        }
-                    }
+                for (int o = 0; o < NU; ++o) {
+                    const int64_t uid = pL + (c - newlo) * nu + o;
+                    if (!(uid >= id_begin && uid < id_end)) scs[1 + o] = -1.0f;
                 }
             }
             if (lane == 0) {
@@ -186,14 +119,6 @@ __global__ void __launch_bounds__(256) k_score_columns(
 
 // --------------------------------------------------------- binary slice
 
-
-template <int RU, int RV>
-struct RectCfg {
-    static constexpr int TU = 16 * RU, TV = 16 * RV;
-    static constexpr int TUP = TU + 4, TVP = TV + 4;
-    static constexpr int BUF = kSC * (3 * TUP + 3 * TVP) + kSC;   // floats per buffer
-};
-
 template <int RU, int RV>
 __global__ void __launch_bounds__(256) k_score_rect(
     sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
@@ -203,7 +128,7 @@ __global__ void __launch_bounds__(256) k_score_rect(
     int lists_total, int keep, int cap)
 {
     using Cfg = RectCfg<RU, RV>;
-    constexpr int TU = Cfg::TU, TV = Cfg::TV, TUP = Cfg::TUP, TVP = Cfg::TVP;
+    constexpr int TU = Cfg::TU, TV = Cfg::TV;
     extern __shared__ unsigned char smem[];
     float *buf0 = (float *)smem;
     float *buf1 = buf0 + Cfg::BUF;
@@ -215,240 +140,22 @@ __global__ void __launch_bounds__(256) k_score_rect(
     BlockList L{lsc, lid, &lcnt, &lthr, cap, keep};
     list_init(L);
 
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
     const int Lv = s.levels;
     const int64_t vcount = s.pool[Lv - 1];          // v in P_{L-1}
     const int64_t ulo = s.pool[Lv - 1], uhi = s.pool[Lv];
-    const int64_t binbase = s.pool[Lv] + s.rect_unary;
-    const int S = s.n_slots;
+    const PairIds ids{s.pool[Lv] + s.rect_unary, ulo, vcount, s.n_slots, false};
     const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
-    const int nch = (n + kSC - 1) / kSC;
     const int64_t nvt = (vcount + TV - 1) / TV;
-
-    // staging roles: 256 threads load TU (then TV) columns x kSC samples as float4
-    const int scol = tid / (kSC / 4), squad = tid % (kSC / 4);
 
     for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
         const int64_t u0 = ulo + ut * TU;
-        // staging column of U for this thread (TU * kSC / 4 == 256 when RU == 2)
-        const int64_t su = u0 + (scol < TU ? scol : 0);
-        const bool su_ok = scol < TU && su < uhi;
-        const sisso_colstat sust = stats[su_ok ? su : ulo];
-        // per-thread operand statistics (compute role)
-        float ufo[RU], urf[RU], umx[RU], umn[RU], urm[RU];
-        bool uval[RU];
-        int64_t uidx[RU];
-#pragma unroll
-        for (int a = 0; a < RU; ++a) {
-            const int64_t u = u0 + ty * RU + a;
-            uval[a] = u < uhi;
-            const sisso_colstat st = stats[uval[a] ? u : ulo];
-            uval[a] = uval[a] && st.valid != 0.0f;
-            ufo[a] = st.mean; urf[a] = st.mean_rcp; umx[a] = st.maxabs; umn[a] = st.minabs;
-            urm[a] = st.rms;
-            uidx[a] = u - ulo;
-        }
+        USide<RU, RV> U;
+        load_uside<RU, RV>(U, stats, ids, u0, uhi);
         for (int64_t vt = 0; vt < nvt; ++vt) {
-            const int64_t v0 = vt * TV;
-            const int64_t sv = v0 + (scol < TV ? scol : 0);
-            const bool sv_ok = scol < TV && sv < vcount;
-            const sisso_colstat svst = stats[sv_ok ? sv : 0];
-            float vfo[RV], vrf[RV], vmx[RV], vmn[RV], vrm[RV];
-            bool vval[RV];
-#pragma unroll
-            for (int b = 0; b < RV; ++b) {
-                const int64_t v = v0 + tx * RV + b;
-                vval[b] = v < vcount;
-                const sisso_colstat st = stats[vval[b] ? v : 0];
-                vval[b] = vval[b] && st.valid != 0.0f;
-                vfo[b] = st.mean; vrf[b] = st.mean_rcp; vmx[b] = st.maxabs; vmn[b] = st.minabs;
-                vrm[b] = st.rms;
-            }
-            // shift constants of the multiplicative forms (set by the pilot
-            // below); sums and differences use the operands' exact means
-            float cm[RU][RV], c3[RU][RV], c4[RU][RV];
-            // A stays small (the shifts are means) and is kept in FP32; B and C
-            // are carried in FP64 across chunks
-            double dB[RU][RV][5], dC[RU][RV][5];
-            float fA[RU][RV][5], fB[RU][RV][5], fC[RU][RV][5];
-#pragma unroll
-            for (int a = 0; a < RU; ++a)
-#pragma unroll
-                for (int b = 0; b < RV; ++b)
-#pragma unroll
-                    for (int k = 0; k < 5; ++k) {
-                        dB[a][b][k] = dC[a][b][k] = 0.0;
-                        fA[a][b][k] = fB[a][b][k] = fC[a][b][k] = 0.0f;
-                    }
-
-            // register prefetch of one chunk
-            float4 pu = make_float4(0, 0, 0, 0), pv = make_float4(0, 0, 0, 0), pr = make_float4(0, 0, 0, 0);
-            auto load_chunk = [&](int ch) {
-                const int t0 = ch * kSC + squad * 4;
-                pu = make_float4(0, 0, 0, 0);
-                pv = make_float4(0, 0, 0, 0);
-                if (t0 < n) {
-                    if (su_ok) pu = *reinterpret_cast<const float4 *>(pool32 + (size_t)su * ld32 + t0);
-                    if (sv_ok) pv = *reinterpret_cast<const float4 *>(pool32 + (size_t)sv * ld32 + t0);
-                }
-                if (tid < kSC / 4) {
-                    const int tr = ch * kSC + tid * 4;
-                    pr = tr < n ? *reinterpret_cast<const float4 *>(r32 + tr) : make_float4(0, 0, 0, 0);
-                }
-            };
-            auto store_chunk = [&](float *bf) {
-                float *Ur = bf, *Us = Ur + kSC * TUP, *Uq = Us + kSC * TUP;
-                float *Vr = Uq + kSC * TUP, *Vs = Vr + kSC * TVP, *Vq = Vs + kSC * TVP;
-                float *R = Vq + kSC * TVP;
-                const float uv[4] = {pu.x, pu.y, pu.z, pu.w};
-                const float vv[4] = {pv.x, pv.y, pv.z, pv.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int srow = squad * 4 + e;
-                    if (scol < TU) {
-                        Ur[srow * TUP + scol] = uv[e];
-                        Us[srow * TUP + scol] = uv[e] - sust.mean;
-                        Uq[srow * TUP + scol] = __builtin_amdgcn_rcpf(uv[e]);
-                    }
-                    if (scol < TV) {
-                        Vr[srow * TVP + scol] = vv[e];
-                        Vs[srow * TVP + scol] = vv[e] - svst.mean;
-                        Vq[srow * TVP + scol] = __builtin_amdgcn_rcpf(vv[e]);
-                    }
-                }
-                if (tid < kSC / 4) {
-                    R[tid * 4 + 0] = pr.x; R[tid * 4 + 1] = pr.y;
-                    R[tid * 4 + 2] = pr.z; R[tid * 4 + 3] = pr.w;
-                }
-            };
-
-            __syncthreads();
-            load_chunk(0);
-            store_chunk(buf0);
-            __syncthreads();
-            {
-                // pilot: shift of the multiplicative forms = their mean over the
-                // first chunk, so that B - A^2/n does not cancel
-                const float *Ur = buf0, *Uq = Ur + 2 * kSC * TUP;
-                const float *Vr = Uq + kSC * TUP, *Vq = Vr + 2 * kSC * TVP;
-                const int c0 = n < kSC ? n : kSC;
-                float pm[RU][RV], p3[RU][RV], p4[RU][RV];
-#pragma unroll
-                for (int a = 0; a < RU; ++a)
-#pragma unroll
-                    for (int b = 0; b < RV; ++b) pm[a][b] = p3[a][b] = p4[a][b] = 0.0f;
-                for (int t = 0; t < c0; ++t) {
-#pragma unroll
-                    for (int a = 0; a < RU; ++a)
-#pragma unroll
-                        for (int b = 0; b < RV; ++b) {
-                            const float ur = Ur[t * TUP + ty * RU + a], uq = Uq[t * TUP + ty * RU + a];
-                            const float vr = Vr[t * TVP + tx * RV + b], vq = Vq[t * TVP + tx * RV + b];
-                            pm[a][b] = fmaf(ur, vr, pm[a][b]);
-                            p3[a][b] = fmaf(ur, vq, p3[a][b]);
-                            p4[a][b] = fmaf(vr, uq, p4[a][b]);
-                        }
-                }
-                const float inv = 1.0f / (float)c0;
-#pragma unroll
-                for (int a = 0; a < RU; ++a)
-#pragma unroll
-                    for (int b = 0; b < RV; ++b) {
-                        cm[a][b] = pm[a][b] * inv;
-                        c3[a][b] = p3[a][b] * inv;
-                        c4[a][b] = p4[a][b] * inv;
-                    }
-            }
-            for (int ch = 0; ch < nch; ++ch) {
-                float *bf = (ch & 1) ? buf1 : buf0;
-                if (ch + 1 < nch) load_chunk(ch + 1);
-                const float *Ur = bf, *Us = Ur + kSC * TUP, *Uq = Us + kSC * TUP;
-                const float *Vr = Uq + kSC * TUP, *Vs = Vr + kSC * TVP, *Vq = Vs + kSC * TVP;
-                const float *R = Vq + kSC * TVP;
-                const int cnt = (n - ch * kSC) < kSC ? (n - ch * kSC) : kSC;
-                auto step = [&](int t) {
-                    float ur[RU], us[RU], uq[RU], vr[RV], vs[RV], vq[RV];
-#pragma unroll
-                    for (int a = 0; a < RU; ++a) {
-                        ur[a] = Ur[t * TUP + ty * RU + a];
-                        us[a] = Us[t * TUP + ty * RU + a];
-                        uq[a] = Uq[t * TUP + ty * RU + a];
-                    }
-#pragma unroll
-                    for (int b = 0; b < RV; ++b) {
-                        vr[b] = Vr[t * TVP + tx * RV + b];
-                        vs[b] = Vs[t * TVP + tx * RV + b];
-                        vq[b] = Vq[t * TVP + tx * RV + b];
-                    }
-                    const float r = R[t];
-#pragma unroll
-                    for (int a = 0; a < RU; ++a)
-#pragma unroll
-                        for (int b = 0; b < RV; ++b) {
-                            float g[5];
-#pragma unroll
-                            for (int k = 0; k < 5; ++k)
-                                g[k] = binary_form(k, ur[a], us[a], uq[a], vr[b], vs[b], vq[b], cm[a][b],
-                                                   c3[a][b], c4[a][b]);
-#pragma unroll
-                            for (int k = 0; k < 5; ++k) {
-                                fA[a][b][k] += g[k];
-                                fB[a][b][k] = fmaf(g[k], g[k], fB[a][b][k]);
-                                fC[a][b][k] = fmaf(g[k], r, fC[a][b][k]);
-                            }
-                        }
-                };
-                if (cnt == kSC) {
-#pragma unroll 4
-                    for (int t = 0; t < kSC; ++t) step(t);
-                } else {
-                    for (int t = 0; t < cnt; ++t) step(t);
-                }
-                // carry the chunk's FP32 partial sums in FP64
-#pragma unroll
-                for (int a = 0; a < RU; ++a)
-#pragma unroll
-                    for (int b = 0; b < RV; ++b)
-#pragma unroll
-                        for (int k = 0; k < 5; ++k) {
-                            dB[a][b][k] += (double)fB[a][b][k];
-                            dC[a][b][k] += (double)fC[a][b][k];
-                            fB[a][b][k] = fC[a][b][k] = 0.0f;
-                        }
-                if (ch + 1 < nch) store_chunk((ch & 1) ? buf0 : buf1);
-                __syncthreads();
-            }
-
-            // scores, validity and ids of the tile's candidates
             float osc[RU * RV * 5];
             int64_t oid[RU * RV * 5];
-#pragma unroll
-            for (int a = 0; a < RU; ++a)
-#pragma unroll
-                for (int b = 0; b < RV; ++b) {
-                    const int64_t v = v0 + tx * RV + b;
-                    const bool ok = uval[a] && vval[b];
-                    const double shifts[5] = {(double)ufo[a] + (double)vfo[b], (double)ufo[a] - (double)vfo[b],
-                                              (double)cm[a][b], (double)c3[a][b], (double)c4[a][b]};
-                    const int64_t u = u0 + ty * RU + a;
-                    const float *cu = pool32 + (size_t)(ok ? u : 0) * ld32;
-                    const float *cv = pool32 + (size_t)(ok ? v : 0) * ld32;
-#pragma unroll
-                    for (int k = 0; k < 5; ++k) {
-                        const int e = (a * RV + b) * 5 + k;
-                        float sc = -1.0f;
-                        int64_t fid = INT64_MAX;
-                        if (fs.slot[k] >= 0 && ok) {
-                            fid = binbase + (uidx[a] * vcount + v) * S + fs.slot[k];
-                            if (fid >= id_begin && fid < id_end)
-                                sc = form_score(k, fA[a][b][k], dB[a][b][k], dC[a][b][k], shifts[k], cu, cv, n,
-                                                umx[a], umn[a], urm[a], vmx[b], vmn[b], vrm[b], nd, R1, Srr);
-                        }
-                        osc[e] = sc;
-                        oid[e] = fid;
-                    }
-                }
+            score_pair_tile<RU, RV>(pool32, ld32, stats, r32, n, nd, R1, Srr, fs, ids, u0, U, vt * TV, vcount,
+                                    id_begin, id_end, buf0, buf1, osc, oid);
             list_offer<RU * RV * 5>(L, osc, oid, &W.h->gthr, excl, n_excl);
         }
     }
@@ -745,13 +452,7 @@ extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso
         if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
     }
     if (p.g_rect > 0) {
-        FormSlots fs;
-        for (int k = 0; k < 5; ++k) fs.slot[k] = -1;
-        for (int sl = 0; sl < space->n_slots; ++sl) {
-            const int op = space->slot_op[sl], rev = space->slot_rev[sl];
-            const int form = op == SISSO_DIV ? (rev ? 4 : 3) : op;
-            fs.slot[form] = sl;
-        }
+        const FormSlots fs = form_slots(space);
         const size_t smem = rect_smem(p.ru, p.rv, cap);
         auto launch = [&](auto kern) -> sisso_status {
             if (!allow_dynamic_lds(kern, smem)) return SISSO_E_UNSUPPORTED;

@@ -16,6 +16,17 @@ struct FormSlots {
     int slot[5];
 };
 
+inline FormSlots form_slots(const sisso_space *space)
+{
+    FormSlots fs;
+    for (int k = 0; k < 5; ++k) fs.slot[k] = -1;
+    for (int sl = 0; sl < space->n_slots; ++sl) {
+        const int op = space->slot_op[sl], rev = space->slot_rev[sl];
+        fs.slot[op == SISSO_DIV ? (rev ? 4 : 3) : op] = sl;
+    }
+    return fs;
+}
+
 // ------------------------------------------------------------- workspace
 
 constexpr int kHistBins = 4096;
@@ -136,6 +147,33 @@ __device__ inline float form_score(int k, float fA, double dB, double dC, double
         if (!(sqrt(fmax(var, 0.0) / nd) > kCancelRel * scale)) sc = -1.0f;
     }
     return sc;
+}
+
+// Score of one stored pool column against the residual (one wave; every lane
+// returns the score, -1 if the column is invalid).  Lane l accumulates the
+// samples l*4 + 256 j in FP32; the wave sum is taken in FP64.  The single-
+// problem and batched screening kernels use this same sequence of operations.
+__device__ inline float score_stored_column(const float *col, const float *r32, int n, float mean, bool valid,
+                                            double nd, double R1, double Srr)
+{
+    const int lane = threadIdx.x & 63;
+    float a0 = 0.f, b0 = 0.f, c0 = 0.f;
+    for (int t = lane * 4; t < n; t += 256) {
+        const float4 fv = *reinterpret_cast<const float4 *>(col + t);
+        const float4 rv = *reinterpret_cast<const float4 *>(r32 + t);
+        const float fa[4] = {fv.x, fv.y, fv.z, fv.w};
+        const float ra[4] = {rv.x, rv.y, rv.z, rv.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (t + e < n) {
+                const float g = fa[e] - mean;
+                a0 += g;
+                b0 = fmaf(g, g, b0);
+                c0 = fmaf(g, ra[e], c0);
+            }
+    }
+    const double A = wave_sum((double)a0), B = wave_sum((double)b0), C = wave_sum((double)c0);
+    return valid ? score_from_sums(A, B, C, (double)mean, nd, R1, Srr) : -1.0f;
 }
 
 int score_lists_capacity(const sisso_space *s, const sisso_score_args *a);

@@ -226,69 +226,100 @@ class Engine:
     def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10,
             grid: int = 0, tile: int = 0, timings: Optional[dict] = None, precision: str = "fp32",
             band: int = 0) -> List[StepResult]:
-        n, dev, st = self.n, self.dev, self.stream()
         keep0 = min(2 * k if keep0 is None else keep0, L.MAX_KEEP)
         if dmax < 1 or dmax > L.MAX_D or k * dmax > L.MAX_SUBSPACE:
             raise L.SissoError("dmax or k out of range")
-        sub = torch.empty(L.MAX_SUBSPACE * n, dtype=torch.float64, device=dev)
-        sub_ids = torch.empty(L.MAX_SUBSPACE, dtype=torch.int64, device=dev)
-        fsorted = torch.empty(L.MAX_SUBSPACE * n, dtype=torch.float64, device=dev)
-        ids_sorted = torch.empty(L.MAX_SUBSPACE, dtype=torch.int64, device=dev)
-        perm = torch.empty(L.MAX_SUBSPACE, dtype=torch.int32, device=dev)
-        n_new = torch.zeros(1, dtype=torch.int32, device=dev)
-        n_cls = torch.zeros(1, dtype=torch.int32, device=dev)
-        tup = torch.empty(L.MAX_D, dtype=torch.int32, device=dev)
-        sse = torch.empty(1, dtype=torch.float64, device=dev)
-        coef = torch.empty(L.MAX_D + 1, dtype=torch.float64, device=dev)
-        resid = torch.empty(n, dtype=torch.float64, device=dev)
-        stats = torch.empty(4, dtype=torch.float64, device=dev)
+        fs = FitState(self.n, self.dev)
         out: List[StepResult] = []
-        m = 0
         r = self.y
         for t in range(1, dmax + 1):
             keep = keep0
-            exclude = ids_sorted[:m] if m else None
             while True:
-                ids, sc, cnt = self.screen(r, keep, exclude, grid=grid, tile=tile, events=timings,
+                ids, sc, cnt = self.screen(r, keep, fs.exclude(), grid=grid, tile=tile, events=timings,
                                            precision=precision, band=band)
                 cand, valid = self.materialize(ids)
-                nb = L.lib().sisso_subspace_workspace_size(n, keep, m)
-                ws2 = self._workspace("sub", nb)
-                L.check(L.lib().sisso_subspace_update(
-                    L.ptr(cand), n, L.ptr(ids), L.ptr(valid), L.ptr(cnt), keep, L.ptr(r), n,
-                    L.ptr(sub), n, L.ptr(sub_ids), m, k, L.ptr(n_new), L.ptr(n_cls), L.ptr(ws2),
-                    ws2.numel(), st), "sisso_subspace_update")
-                nn, nc, ct = int(n_new.item()), int(n_cls.item()), int(cnt.item())
+                fs.update(cand, ids, valid, cnt, keep, r, k, self._workspace)
+                nn, nc, ct = fs.read_update(cnt)
                 if nn >= k or ct < keep or keep >= L.MAX_KEEP:
                     break
                 keep = min(2 * keep, L.MAX_KEEP)
-            list_ids = ids[:ct].cpu().numpy()
-            list_sc = sc[:ct].cpu().numpy()
-            m += nn
-            if m < t:
+            if not fs.commit(nn, t):
                 break
-            L.check(L.lib().sisso_sort_subspace(L.ptr(sub), n, L.ptr(sub_ids), m, n, L.ptr(fsorted), n,
-                                                L.ptr(ids_sorted), L.ptr(perm), st), "sisso_sort_subspace")
-            nb = L.lib().sisso_l0_workspace_size(m, n, t)
-            ws3 = self._workspace("l0", nb)
-            if timings is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-            L.check(L.lib().sisso_l0_search(L.ptr(fsorted), m, n, n, L.ptr(self.y), t, singular_tol,
-                                            L.ptr(tup), L.ptr(sse), L.ptr(coef), L.ptr(resid),
-                                            L.ptr(stats), L.ptr(ws3), ws3.numel(), st),
-                    "sisso_l0_search")
-            if timings is not None:
-                e1.record()
-                timings.setdefault(f"l0_D{t}", []).append((e0, e1))
-                timings.setdefault("so_m", []).append(m)
-            tp = tup[:t].cpu().numpy()
-            srt = ids_sorted[:m].cpu().numpy()
-            stt = stats.cpu().numpy()
-            best = srt[tp] if (tp >= 0).all() else np.full(t, -1)
-            out.append(StepResult(t, list_ids, list_sc, sub_ids[:m].cpu().numpy(), best,
-                                  coef[:t + 1].cpu().numpy(), float(sse.item()), float(stt[0]),
-                                  float(stt[1]), int(stt[2]), int(stt[3]), keep, nc))
-            r = resid.clone()
+            fs.so(self.y, t, singular_tol, self._workspace, timings)
+            out.append(fs.result(t, ids, sc, ct, keep, nc))
+            r = fs.resid.clone()
         return out
+
+
+class FitState:
+    """Device state of one problem's subspace S_t and SO results (Sec. 2.3).
+
+    update() launches the subspace update for a screened list, so() the id
+    sort and the l0 search; neither synchronises.  read_update() and
+    result() copy the few scalars the loop needs to the host."""
+
+    def __init__(self, n: int, dev: torch.device):
+        self.n, self.dev, self.m = n, dev, 0
+        M = L.MAX_SUBSPACE
+        self.sub = torch.empty(M * n, dtype=torch.float64, device=dev)
+        self.sub_ids = torch.empty(M, dtype=torch.int64, device=dev)
+        self.fsorted = torch.empty(M * n, dtype=torch.float64, device=dev)
+        self.ids_sorted = torch.empty(M, dtype=torch.int64, device=dev)
+        self.perm = torch.empty(M, dtype=torch.int32, device=dev)
+        self.n_new = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.n_cls = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.tup = torch.empty(L.MAX_D, dtype=torch.int32, device=dev)
+        self.sse = torch.empty(1, dtype=torch.float64, device=dev)
+        self.coef = torch.empty(L.MAX_D + 1, dtype=torch.float64, device=dev)
+        self.resid = torch.empty(n, dtype=torch.float64, device=dev)
+        self.stats = torch.empty(4, dtype=torch.float64, device=dev)
+
+    def exclude(self) -> Optional[torch.Tensor]:
+        return self.ids_sorted[:self.m] if self.m else None
+
+    def update(self, cand, ids, valid, cnt, keep: int, r, k: int, workspace):
+        n, st = self.n, L.stream_handle(self.dev)
+        nb = L.lib().sisso_subspace_workspace_size(n, keep, self.m)
+        ws = workspace("sub", nb)
+        L.check(L.lib().sisso_subspace_update(
+            L.ptr(cand), n, L.ptr(ids), L.ptr(valid), L.ptr(cnt), keep, L.ptr(r), n,
+            L.ptr(self.sub), n, L.ptr(self.sub_ids), self.m, k, L.ptr(self.n_new), L.ptr(self.n_cls),
+            L.ptr(ws), ws.numel(), st), "sisso_subspace_update")
+
+    def read_update(self, cnt):
+        v = torch.cat([self.n_new, self.n_cls, cnt]).cpu().numpy()
+        return int(v[0]), int(v[1]), int(v[2])
+
+    def commit(self, nn: int, t: int) -> bool:
+        """Grow S_t by the nn appended features; False if S_t has fewer than t."""
+        self.m += nn
+        return self.m >= t
+
+    def so(self, y, t: int, singular_tol: float, workspace, timings: Optional[dict] = None):
+        n, m, st = self.n, self.m, L.stream_handle(self.dev)
+        L.check(L.lib().sisso_sort_subspace(L.ptr(self.sub), n, L.ptr(self.sub_ids), m, n, L.ptr(self.fsorted),
+                                            n, L.ptr(self.ids_sorted), L.ptr(self.perm), st),
+                "sisso_sort_subspace")
+        nb = L.lib().sisso_l0_workspace_size(m, n, t)
+        ws = workspace("l0", nb)
+        if timings is not None:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        L.check(L.lib().sisso_l0_search(L.ptr(self.fsorted), m, n, n, L.ptr(y), t, singular_tol,
+                                        L.ptr(self.tup), L.ptr(self.sse), L.ptr(self.coef), L.ptr(self.resid),
+                                        L.ptr(self.stats), L.ptr(ws), ws.numel(), st), "sisso_l0_search")
+        if timings is not None:
+            e1.record()
+            timings.setdefault(f"l0_D{t}", []).append((e0, e1))
+            timings.setdefault("so_m", []).append(m)
+
+    def result(self, t: int, ids, sc, ct: int, keep: int, nc: int) -> StepResult:
+        m = self.m
+        tp = self.tup[:t].cpu().numpy()
+        srt = self.ids_sorted[:m].cpu().numpy()
+        stt = self.stats.cpu().numpy()
+        best = srt[tp] if (tp >= 0).all() else np.full(t, -1)
+        return StepResult(t, ids[:ct].cpu().numpy(), sc[:ct].cpu().numpy(), self.sub_ids[:m].cpu().numpy(),
+                          best, self.coef[:t + 1].cpu().numpy(), float(self.sse.item()), float(stt[0]),
+                          float(stt[1]), int(stt[2]), int(stt[3]), keep, nc)

@@ -109,3 +109,47 @@ def test_argument_errors_before_launch():
     assert lib.sisso_sort_subspace(fake, 50, fake, 0, 50, fake, 50, fake, fake, None) == 2
     for st in range(8):
         assert lib.sisso_status_string(st)
+
+
+def test_batched_argument_errors_before_launch():
+    lib = L.lib()
+    full = dict(unary=["sq", "sqrt", "inv"], binary=["add", "sub", "mul", "div"])
+    s2 = L.make_space(4, full["unary"], full["binary"], 2, False)
+    s1 = L.make_space(4, full["unary"], full["binary"], 1, False)
+    sr = L.make_space(4, full["unary"], full["binary"], 2, True)
+    fake = ctypes.c_void_p(0x1000)
+    ws = lib.sisso_batch_workspace_size(ctypes.byref(s2), 8, 100)
+    assert ws > 0
+    # sizes grow with problems and keep; unsupported spaces give 0 / -1
+    assert lib.sisso_batch_workspace_size(ctypes.byref(s2), 16, 100) > ws
+    assert lib.sisso_batch_workspace_size(ctypes.byref(s2), 8, 200) > ws
+    assert lib.sisso_batch_workspace_size(ctypes.byref(s1), 8, 100) == 0
+    assert lib.sisso_batch_workspace_size(ctypes.byref(sr), 8, 100) == 0
+    assert lib.sisso_batch_workspace_size(ctypes.byref(s2), 0, 100) == 0
+    assert lib.sisso_batch_workspace_size(ctypes.byref(s2), L.MAX_BATCH + 1, 100) == 0
+    assert lib.sisso_batch_workspace_size(ctypes.byref(s2), 8, L.MAX_KEEP + 1) == 0
+    assert lib.sisso_batch_items(ctypes.byref(sr)) == -1
+    # items: 32 x 32 pair tiles of the level-2 triangle plus 64-column batches of P_1
+    p0, p1 = s2.pool[0], s2.pool[1]
+    tiles = 0
+    for u0 in range(p0, p1, 32):
+        ue = min(u0 + 32, p1)
+        tiles += (ue - 1 + 31) // 32
+    assert lib.sisso_batch_items(ctypes.byref(s2)) == tiles + (p1 + 63) // 64
+    # null pointers, shapes, unsupported spaces, workspace, all before any launch
+    assert lib.sisso_expand_score_batched(ctypes.byref(s2), None, 8, 100, 0, fake, ws, None) == 1
+    assert lib.sisso_expand_score_batched(ctypes.byref(s2), fake, 8, 100, 0, None, ws, None) == 1
+    assert lib.sisso_expand_score_batched(ctypes.byref(s2), fake, 0, 100, 0, fake, ws, None) == 2
+    assert lib.sisso_expand_score_batched(ctypes.byref(s2), fake, 8, 0, 0, fake, ws, None) == 2
+    assert lib.sisso_expand_score_batched(ctypes.byref(s2), fake, 8, 100, -1, fake, ws, None) == 2
+    assert lib.sisso_expand_score_batched(ctypes.byref(s1), fake, 8, 100, 0, fake, ws, None) == 5
+    assert lib.sisso_expand_score_batched(ctypes.byref(sr), fake, 8, 100, 0, fake, ws, None) == 5
+    assert lib.sisso_expand_score_batched(ctypes.byref(s2), fake, 8, 100, 0, fake, ws - 1, None) == 4
+    assert lib.sisso_topk_batched(None, 8, fake, ws, fake, fake, fake, None, None) == 1
+    assert lib.sisso_topk_batched(fake, 0, fake, ws, fake, fake, fake, None, None) == 2
+    assert lib.sisso_prepare_residual_batched(None, 8, None) == 1
+    assert lib.sisso_prepare_residual_batched(fake, L.MAX_BATCH + 1, None) == 2
+    assert lib.sisso_materialize_ids_stored(ctypes.byref(s2), 3, 50, fake, 50, fake, fake, 4, fake, 50, fake,
+                                            None) == 2
+    assert lib.sisso_materialize_ids_stored(ctypes.byref(s2), 0, 50, fake, 50, fake, fake, 4, fake, 50, fake,
+                                            None) == 2

@@ -1,0 +1,149 @@
+"""Batched persistent screening of many problems, against the FP64 oracle.
+
+Every problem of a batch is checked against the oracle's SIS and fit of that
+problem alone, to the bar of the single-problem parity tests: |corr| within
+1e-6, identical top-K' except ids within 1e-6 of the cutoff, identical
+subspaces and SO tuples, RMSE within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2410_01752_amd import inputs as I
+
+from test_gpu_parity import _compare_fit, assert_topk_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _tiny_batch(seeds, ns, d=4, dist="uniform"):
+    ps = []
+    for s, n in zip(seeds, ns):
+        ps.append(I.tiny(s, n=n, d=d, dist=dist, unary=("sq", "sqrt", "inv", "exp", "log"),
+                         binary=("add", "sub", "mul", "div"), rung=2, k=8, dmax=2))
+    return ps
+
+
+def _batch(ps):
+    from paper_2410_01752_amd.batch import Batch
+    return Batch([(p.X, p.y) for p in ps], ps[0].unary, ps[0].binary, 2)
+
+
+def _screen(b, keep, exclude=None, grid=0, which=None):
+    which = list(range(b.P)) if which is None else which
+    exs = None
+    if exclude is not None:
+        exs = [torch.as_tensor(np.sort(np.asarray(e, dtype=np.int64)), device=b.dev) if len(e) else None
+               for e in exclude]
+    ids, sc, cnt, st = b.screen(which, [b.y[p] for p in which], [keep] * len(which), exs, grid=grid)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    c = cnt.cpu().numpy()
+    return [(ids[j, :c[j]].cpu().numpy(), sc[j, :c[j]].cpu().numpy()) for j in range(len(which))]
+
+
+def test_batched_screen_tiny_full_spaces():
+    """Ragged n (several sample chunks and a partial one), all of each space."""
+    ps = _tiny_batch([11, 12, 13, 14, 15], [37, 64, 100, 129, 250])
+    print("[batched] tiny full spaces, n = 37..250", flush=True)
+    b = _batch(ps)
+    keep = 400
+    got = _screen(b, keep)
+    for p, (gi, gs) in zip(ps, got):
+        sp = O.Space(p.X.shape[1], p.unary, p.binary, 2)
+        oi, os_ = sp.sis(p.X, p.y, keep)
+        assert_topk_parity(sp, p.X, p.y, gi, gs, oi, os_, keep)
+
+
+def test_batched_screen_exclusion_and_subset():
+    ps = _tiny_batch([21, 22, 23], [90, 45, 160], d=3)
+    print("[batched] exclusion lists, subset of problems", flush=True)
+    b = _batch(ps)
+    keep = 120
+    excl = []
+    for p in ps:
+        sp = O.Space(3, p.unary, p.binary, 2)
+        oi, _ = sp.sis(p.X, p.y, keep)
+        excl.append(oi[:40:3])
+    got = _screen(b, keep, exclude=[excl[0], [], excl[2]])
+    for j, p in enumerate(ps):
+        sp = O.Space(3, p.unary, p.binary, 2)
+        ex = excl[j] if j != 1 else []
+        oi, os_ = sp.sis(p.X, p.y, keep, exclude=ex)
+        gi, gs = got[j]
+        assert not set(np.asarray(ex).tolist()) & set(gi.tolist())
+        assert_topk_parity(sp, p.X, p.y, gi, gs, oi, os_, keep)
+    # a subset table screens only its problems, in table order
+    sub = _screen(b, keep, which=[2, 0])
+    full = _screen(b, keep)
+    assert np.array_equal(sub[0][0], full[2][0]) and np.array_equal(sub[1][0], full[0][0])
+
+
+def test_batched_screen_deterministic_across_grids():
+    ps = _tiny_batch([31, 32, 33, 34], [300, 80, 512, 41])
+    b = _batch(ps)
+    ref = _screen(b, 300)
+    for g in (1, 7, 64, 1000):
+        got = _screen(b, 300, grid=g)
+        for (a, sa), (c, sc) in zip(ref, got):
+            assert np.array_equal(a, c) and np.array_equal(sa, sc)
+
+
+def test_batched_invalid_entry_is_reported():
+    from paper_2410_01752_amd import _lib as L
+    ps = _tiny_batch([41, 42], [50, 70])
+    b = _batch(ps)
+    # keep larger than keep_max of the call is impossible through Batch.screen;
+    # make an entry invalid by giving it keep 0 next to a valid one
+    ids, sc, cnt, st = b.screen([0, 1], [b.y[0], b.y[1]], [0, 64])
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert st[0] == 2 and st[1] == 0                      # SISSO_E_SHAPE for the bad entry
+    c = cnt.cpu().numpy()
+    assert c[0] == 0 and c[1] == 64
+    sp = O.Space(4, ps[1].unary, ps[1].binary, 2)
+    oi, os_ = sp.sis(ps[1].X, ps[1].y, 64)
+    assert_topk_parity(sp, ps[1].X, ps[1].y, ids[1, :64].cpu().numpy(), sc[1, :64].cpu().numpy(), oi, os_, 64)
+    assert L.MAX_BATCH >= 64
+
+
+def test_batched_fit_tiny_matches_oracle():
+    ps = _tiny_batch([51, 52, 53, 54], [60, 33, 140, 97])
+    print("[batched] fit, 4 tiny problems", flush=True)
+    b = _batch(ps)
+    res = b.fit(8, 2)
+    for p, rg in zip(ps, res):
+        ro = O.fit(p.X, p.y, p.unary, p.binary, 2, False, 8, 2)
+        _compare_fit(p, rg, ro)
+
+
+def test_batched_c4_fit_matches_oracle_on_sampled_problems():
+    """The whole 64-problem batch (n = 100..2000) in one launch per step; the
+    oracle fits three problems (n = 100, ~400, ~700) and the largest problem
+    (n = 2000) is checked against the single-problem path, which stores the
+    whole level-2 pool and is itself checked against the oracle."""
+    from paper_2410_01752_amd.fit import Engine
+    ps = I.config4()
+    print(f"[batched] C4: {len(ps)} problems, n {min(p.X.shape[0] for p in ps)}.."
+          f"{max(p.X.shape[0] for p in ps)}", flush=True)
+    b = _batch(ps)
+    res = b.fit(ps[0].k, ps[0].dmax)
+    torch.cuda.synchronize()
+    ns = np.array([p.X.shape[0] for p in ps])
+    for j in [int(np.argmin(ns)), int(np.argmin(np.abs(ns - 400))), int(np.argmin(np.abs(ns - 700)))]:
+        p = ps[j]
+        print(f"  oracle: problem {p.name} n={p.X.shape[0]}", flush=True)
+        ro = O.fit(p.X, p.y, p.unary, p.binary, 2, False, p.k, p.dmax)
+        _compare_fit(p, res[j], ro)
+    j = int(np.argmax(ns))
+    p = ps[j]
+    print(f"  single-problem path: problem {p.name} n={p.X.shape[0]}", flush=True)
+    rs = Engine(p.X, p.y, p.unary, p.binary, 2, False).fit(p.k, p.dmax)
+    for g, s in zip(res[j], rs):
+        assert set(g.sub_ids.tolist()) == set(s.sub_ids.tolist())
+        assert list(g.best_ids) == list(s.best_ids)
+        assert abs(g.rmse - s.rmse) <= 1e-9 * s.rmse
+    for j, p in enumerate(ps):
+        assert len(res[j]) == p.dmax
+        assert res[j][1].rmse <= res[j][0].rmse
