@@ -267,3 +267,30 @@ def problem_by_name(name: str) -> Problem:
 def eval_tree(tree, X: np.ndarray) -> np.ndarray:
     """Values of a planted tree (used by recovery checks)."""
     return _eval_tree(tree, X)
+
+
+def mlp_init(seed: int, hidden: int = 256, k_in: int = 144) -> dict:
+    """Initial weights of the proposal network (seeded): He-uniform first layer,
+    zero biases, uniform second layer scaled by 1/sqrt(hidden)."""
+    rng = np.random.default_rng(seed)
+    lim = float(np.sqrt(6.0 / k_in))
+    return {"W1": rng.uniform(-lim, lim, size=(hidden, k_in)), "b1": np.zeros(hidden),
+            "w2": rng.uniform(-1.0, 1.0, size=hidden) / np.sqrt(hidden), "b2": np.zeros(1)}
+
+
+def mlp_batch(seed: int, batch: int, k_in: int = 144, e_op: int = 64) -> tuple:
+    """Random network inputs shaped like candidate encodings (one-hot blocks,
+    statistics in [-1, 1], a one-hot form), targets in [0, 3] and weights."""
+    rng = np.random.default_rng(seed)
+    X = np.zeros((batch, k_in))
+    for side in range(2):
+        o = side * e_op
+        for slot in range(3):
+            X[np.arange(batch), o + slot * 14 + rng.integers(0, 14, batch)] = 1.0
+        X[:, o + 42:o + 53] = rng.uniform(-1.0, 1.0, size=(batch, 11))
+        X[:, o + 53:o + 55] = rng.integers(0, 2, size=(batch, 2))
+        X[:, o + 55] = 1.0
+    X[np.arange(batch), 2 * e_op + rng.integers(0, 5, batch)] = 1.0
+    t = rng.uniform(0.0, 3.0, batch)
+    w = rng.uniform(0.5, 2.0, batch)
+    return X, t, w
