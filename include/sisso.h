@@ -342,6 +342,104 @@ sisso_status sisso_topk_batched(const sisso_problem *problems, int32_t n_problem
                                 size_t ws_bytes, int64_t *out_ids, float *out_scores, int32_t *out_count,
                                 int32_t *out_status, void *stream);
 
+/* ---------------------------------------------------------- learned proposal
+ * A two-layer network (144 inputs, 256 ReLU units, one output) ranks the
+ * candidates op(u, v) of the one-sided slice's binary block so that only the
+ * top fraction is scored exactly (an addition to the screening of Sec. 2.2,
+ * which scores every candidate).  Input of candidate (u, v, form):
+ * [enc(u) | enc(v) | onehot(form) | 0], form 0..4 = u+v, u-v, u*v, u/v, v/u.
+ * enc(x) (SISSO_ENC values per pool column) holds one-hot classes of x's
+ * operator and of its operands and statistics of x against the residual:
+ *   [0,14) [14,28) [28,42): class of x's operator, left and right operand
+ *           (0 base feature, 1 + op code, 13 none);
+ *   42 corr(x,r), 43 |corr(x,r)|, 44 corr(1/x,r), 45 corr(log|x|,r),
+ *   46 corr(x^2,r), 47 |corr(1/x,r)|, 48 |corr(log|x|,r)|,
+ *   49 clip(log10(sd/|mean|),-4,4)/4, 50 clip(skewness,-10,10)/10,
+ *   51 clip(log10|mean|,-6,6)/6, 52 clip(log10 sd,-6,6)/6, 53 [min > 0],
+ *   54 [x has a zero], 55 1, [56,64) 0; undefined or non-finite values 0.
+ * Parameters: one FP32 array of SISSO_MLP_PARAMS values, W1 (256 x 144,
+ * row-major) | b1 (256) | w2 (256) | b2 (1).  The products with W1 use BF16
+ * operands (inputs and W1 rounded to nearest even) on matrix cores with FP32
+ * accumulation. */
+#define SISSO_ENC 64
+#define SISSO_MLP_IN 144
+#define SISSO_MLP_HIDDEN 256
+#define SISSO_MLP_PARAMS (256 * 144 + 256 + 256 + 1)
+#define SISSO_MLP_TABLES (5 * 256 + 256 + 1)
+
+int32_t sisso_mlp_param_count(void);
+int32_t sisso_mlp_table_count(void);
+
+/* Encodings of pool columns [c_begin, c_end) against the prepared residual of
+ * args (n, pool32, ld32, stats, r32, info): enc receives (c_end - c_begin)
+ * rows of SISSO_ENC FP32 values.  Errors: SISSO_E_NULL, SISSO_E_SHAPE,
+ * SISSO_E_RANGE (columns outside the stored pool). */
+sisso_status sisso_encode_operands(const sisso_space *space, const sisso_score_args *args, int64_t c_begin,
+                                   int64_t c_end, float *enc, void *stream);
+
+/* Network inputs (count x SISSO_MLP_IN, FP32 row-major) of slice binary ids,
+ * from an encoding table of every stored column (row c = column c); an id
+ * outside the binary block gives a zero row.  Errors: SISSO_E_NULL,
+ * SISSO_E_UNSUPPORTED (no slice), SISSO_E_SHAPE. */
+sisso_status sisso_candidate_inputs(const sisso_space *space, const float *enc, const int64_t *ids, int32_t count,
+                                    float *X, void *stream);
+
+/* Exact FP32 scores of slice binary ids (the screening kernels' arithmetic;
+ * -1 for an invalid candidate or an id outside the block).  Used to label
+ * training examples.  Errors: as sisso_candidate_inputs. */
+sisso_status sisso_score_ids(const sisso_space *space, const sisso_score_args *args, const int64_t *ids,
+                             int32_t count, float *out_scores, void *stream);
+
+/* Forward pass on a batch X (batch x SISSO_MLP_IN): Z (batch x 256) = X W1^T
+ * + b1 (pre-activations), s (batch) = w2 . relu(Z) + b2. */
+sisso_status sisso_mlp_forward(const float *params, const float *X, int32_t batch, float *Z, float *s,
+                               void *stream);
+
+/* Backward pass of the weighted loss sum_i w_i (s_i - t_i)^2 / sum_i w_i for
+ * the forward results Z, s: grads (SISSO_MLP_PARAMS, layout of params) and
+ * *loss (device, nullable).  ws: sisso_mlp_workspace_size(batch) bytes.
+ * The rounding of X and W1 to BF16 is passed through unchanged. */
+size_t sisso_mlp_workspace_size(int32_t batch);
+sisso_status sisso_mlp_backward(const float *params, const float *X, const float *Z, const float *s,
+                                const float *t, const float *w, int32_t batch, float *grads, float *loss, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* Adam update of count parameters with bias-corrected moments m, v (step >= 1
+ * is the update's number).  Errors: SISSO_E_NULL, SISSO_E_SHAPE. */
+sisso_status sisso_adam_step(float *params, const float *grads, float *m, float *v, int64_t count, int32_t step,
+                             float lr, float beta1, float beta2, float eps, void *stream);
+
+/* First-layer parts for factorised scoring: out (rows x 256) = enc W1[:, side
+ * block]^T, side 0 = the u block (columns 0..63), 1 = the v block (64..127). */
+sisso_status sisso_mlp_parts(const float *params, const float *enc, int64_t rows, int32_t side, float *out,
+                             void *stream);
+/* Tables of the factorised score (SISSO_MLP_TABLES floats): per form the
+ * BF16-rounded W1 column 128 + form plus b1, then w2, then b2. */
+sisso_status sisso_mlp_tables(const float *params, float *tables, void *stream);
+
+/* Network scores of slice binary ids from the parts (Au: rows per u - pool[L-1]
+ * of N_L, Bv: rows per v of P_{L-1}); -inf outside the block.  Same value as
+ * the pruned screening kernel computes. */
+sisso_status sisso_mlp_score_ids(const sisso_space *space, const float *Au, const float *Bv, const float *tables,
+                                 const int64_t *ids, int32_t count, float *out, void *stream);
+
+/* *out_value (device) = the q-th largest of x[0..count) (NaN lowest). */
+sisso_status sisso_select_kth(const float *x, int32_t count, int32_t q, float *out_value, void *stream);
+
+/* Pruned screening of the slice's binary block over [cand_begin, cand_end):
+ * candidates whose network score is >= *tau (device) are scored exactly and
+ * enter the per-block lists of ws as in sisso_expand_score (list_base, grid
+ * and keep of args; sisso_topk merges).  *kept (device, nullable) is
+ * increased by the number of candidates scored exactly.  Exact scores are
+ * bit-identical to those of sisso_expand_score.  Errors: as
+ * sisso_expand_score; SISSO_E_UNSUPPORTED without a slice. */
+int32_t sisso_expand_score_pruned_lists(const sisso_space *space, const sisso_score_args *args, int64_t cand_begin,
+                                        int64_t cand_end);
+sisso_status sisso_expand_score_pruned(const sisso_space *space, const sisso_score_args *args, const float *Au,
+                                       const float *Bv, const float *tables, const float *tau, int64_t cand_begin,
+                                       int64_t cand_end, void *ws, size_t ws_bytes, unsigned long long *kept,
+                                       void *stream);
+
 /* Subspace update (Sec. 2.3, eq. subspace-expansion, with the duplicate
  * rule for non-unique features of Sec. 2.1).  Inputs: the screened list
  * (count ids, FP64 columns cand (n x count, ldc) with validity), the current

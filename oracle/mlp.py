@@ -31,7 +31,8 @@ op(a[, b]) of lower-level features):
     55  1
     [56, 64)  0
 A correlation with a constant or undefined transform (zero in x for 1/x and
-log|x|) is 0.  corr is Pearson's correlation; the population moments are
+log|x|) is 0, and so is any statistic that is not finite (a column with an
+overflowing value).  corr is Pearson's correlation; the population moments are
 taken about the exact mean (two passes).
 """
 from __future__ import annotations
@@ -89,6 +90,7 @@ def operand_stats(x: np.ndarray, r: np.ndarray) -> np.ndarray:
     out[11] = 1.0 if x.min() > 0.0 else 0.0
     out[12] = 1.0 if has_zero else 0.0
     out[13] = 1.0
+    out[~np.isfinite(out)] = 0.0
     return out
 
 

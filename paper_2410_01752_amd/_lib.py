@@ -21,6 +21,9 @@ OPNAME = {v: k for k, v in OPCODE.items()}
 MAX_UNARY, MAX_BINARY, MAX_LEVELS = 8, 4, 2
 MAX_N, MAX_KEEP, MAX_SUBSPACE, MAX_D = 65536, 2048, 1024, 3
 MAX_BATCH = 4096
+ENC, MLP_IN, MLP_HIDDEN = 64, 144, 256
+MLP_PARAMS = 256 * 144 + 256 + 256 + 1
+MLP_TABLES = 5 * 256 + 256 + 1
 FP32, BF16 = 0, 1
 
 
@@ -111,6 +114,22 @@ def lib():
         "sisso_bf16_residual": (_i32, [sp, ap, _i32, _vp, _sz, _vp]),
         "sisso_bf16_screen": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _vp]),
         "sisso_bf16_rescore": (_i32, [sp, ap, _i32, _vp, _sz, _vp, _sz, _vp]),
+        "sisso_mlp_param_count": (_i32, []),
+        "sisso_mlp_table_count": (_i32, []),
+        "sisso_encode_operands": (_i32, [sp, ap, _i64, _i64, _vp, _vp]),
+        "sisso_candidate_inputs": (_i32, [sp, _vp, _vp, _i32, _vp, _vp]),
+        "sisso_score_ids": (_i32, [sp, ap, _vp, _i32, _vp, _vp]),
+        "sisso_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
+        "sisso_mlp_workspace_size": (_sz, [_i32]),
+        "sisso_mlp_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+        "sisso_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, _vp]),
+        "sisso_mlp_parts": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
+        "sisso_mlp_tables": (_i32, [_vp, _vp, _vp]),
+        "sisso_mlp_score_ids": (_i32, [sp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
+        "sisso_select_kth": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+        "sisso_expand_score_pruned_lists": (_i32, [sp, ap, _i64, _i64]),
+        "sisso_expand_score_pruned": (_i32, [sp, ap, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _sz, _vp, _vp]),
         "sisso_status_string": (ctypes.c_char_p, [_i32]),
         "sisso_version": (ctypes.c_char_p, []),
     }
@@ -131,6 +150,10 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore",
             "sisso_materialize_ids_stored", "sisso_prepare_residual_batched", "sisso_batch_workspace_size",
             "sisso_batch_items", "sisso_expand_score_batched", "sisso_topk_batched",
+            "sisso_mlp_param_count", "sisso_mlp_table_count", "sisso_encode_operands", "sisso_candidate_inputs",
+            "sisso_score_ids", "sisso_mlp_forward", "sisso_mlp_workspace_size", "sisso_mlp_backward",
+            "sisso_adam_step", "sisso_mlp_parts", "sisso_mlp_tables", "sisso_mlp_score_ids", "sisso_select_kth",
+            "sisso_expand_score_pruned_lists", "sisso_expand_score_pruned",
             "sisso_status_string", "sisso_version"]
 
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsisso.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["capi.hip", "materialize.hip", "score.hip", "bf16.hip", "batched.hip", "subspace.hip", "l0.hip"]
+SOURCES = ["capi.hip", "materialize.hip", "score.hip", "bf16.hip", "batched.hip", "learned.hip", "subspace.hip", "l0.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -21,7 +21,7 @@
 // columns are exact (FP64).  The BF16 scores only select a band; every
 // candidate of the band is rescored with the plain FP32 kernel's arithmetic
 // (shared functions), so reported scores are the FP32 path's scores.
-#include "screen.hpp"
+#include "tiles.hpp"
 
 namespace sisso {
 
@@ -417,56 +417,10 @@ __global__ void __launch_bounds__(256) k_rescore_ids(sisso_space s, FormSlots fs
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     float osc[1] = {-1.0f};
     int64_t oid[1] = {INT64_MAX};
-    const int Lv = s.levels;
-    const int64_t binbase = s.pool[Lv] + s.rect_unary;
     if (q < *count) {
         const int64_t id = ids[q];
-        if (id >= binbase && id < s.total) {
-            const int64_t loc = id - binbase, vcount = s.pool[Lv - 1];
-            const int slot = (int)(loc % s.n_slots);
-            const int64_t pair = loc / s.n_slots;
-            const int64_t u = s.pool[Lv - 1] + pair / vcount, v = pair % vcount;
-            int k = -1;
-            for (int f = 0; f < 5; ++f)
-                if (fs.slot[f] == slot) k = f;
-            const sisso_colstat ust = stats[u], vst = stats[v];
-            if (k >= 0 && ust.valid != 0.0f && vst.valid != 0.0f) {
-                const float *cu = pool32 + (size_t)u * ld32, *cv = pool32 + (size_t)v * ld32;
-                const int c0 = n < kSC ? n : kSC;
-                float pm = 0.f, p3 = 0.f, p4 = 0.f;
-                for (int t = 0; t < c0; ++t) {
-                    const float ur = cu[t], vr = cv[t];
-                    const float uq = __builtin_amdgcn_rcpf(ur), vq = __builtin_amdgcn_rcpf(vr);
-                    pm = fmaf(ur, vr, pm);
-                    p3 = fmaf(ur, vq, p3);
-                    p4 = fmaf(vr, uq, p4);
-                }
-                const float inv = 1.0f / (float)c0;
-                const float cm = pm * inv, c3 = p3 * inv, c4 = p4 * inv;
-                float fA = 0.f, fB = 0.f, fC = 0.f;
-                double dB = 0.0, dC = 0.0;
-                for (int t0 = 0; t0 < n; t0 += kSC) {
-                    const int te = t0 + kSC < n ? t0 + kSC : n;
-                    for (int t = t0; t < te; ++t) {
-                        const float ur = cu[t], vr = cv[t];
-                        const float us = ur - ust.mean, vs = vr - vst.mean;
-                        const float uq = __builtin_amdgcn_rcpf(ur), vq = __builtin_amdgcn_rcpf(vr);
-                        const float g = binary_form(k, ur, us, uq, vr, vs, vq, cm, c3, c4);
-                        fA += g;
-                        fB = fmaf(g, g, fB);
-                        fC = fmaf(g, r32[t], fC);
-                    }
-                    dB += (double)fB;
-                    dC += (double)fC;
-                    fB = fC = 0.0f;
-                }
-                const double shifts[5] = {(double)ust.mean + (double)vst.mean, (double)ust.mean - (double)vst.mean,
-                                          (double)cm, (double)c3, (double)c4};
-                osc[0] = form_score(k, fA, dB, dC, shifts[k], cu, cv, n, ust.maxabs, ust.minabs, ust.rms,
-                                    vst.maxabs, vst.minabs, vst.rms, (double)n, info->sum_r32, info->s_rr);
-                oid[0] = id;
-            }
-        }
+        const float sc = score_slice_id(s, fs, n, pool32, ld32, stats, r32, info, id);
+        if (sc >= 0.0f) { osc[0] = sc; oid[0] = id; }
     }
     list_offer<1>(L, osc, oid, &W.h->gthr, excl, n_excl);
     const int list = list_base + blockIdx.x;

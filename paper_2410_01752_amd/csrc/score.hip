@@ -379,6 +379,15 @@ size_t rect_smem(int ru, int rv, int cap)
 
 namespace sisso {
 int score_lists_capacity(const sisso_space *s, const sisso_score_args *a) { return lists_capacity(s, a); }
+
+bool ws_begin_call(void *ws, int keep, int base, int lists_this_call, int lists_cap, hipStream_t st)
+{
+    if (base == 0)
+        hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(64), 0, st, (WsHeader *)ws, keep, lists_this_call, lists_cap);
+    else
+        hipLaunchKernelGGL(k_ws_append, dim3(1), dim3(64), 0, st, (WsHeader *)ws, base + lists_this_call);
+    return hipGetLastError() == hipSuccess;
+}
 }  // namespace sisso
 
 extern "C" size_t sisso_score_workspace_size(const sisso_space *space, const sisso_score_args *args)

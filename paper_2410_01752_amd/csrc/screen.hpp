@@ -177,6 +177,10 @@ __device__ inline float score_stored_column(const float *col, const float *r32, 
 }
 
 int score_lists_capacity(const sisso_space *s, const sisso_score_args *a);
+
+// Header bookkeeping of one screening call writing lists_this_call lists from
+// slot `base` on: base 0 starts a pass (reset), base > 0 appends.
+bool ws_begin_call(void *ws, int keep, int base, int lists_this_call, int lists_cap, hipStream_t st);
 sisso_status topk_launch(void *ws, int k, int64_t *out_ids, float *out_scores, int32_t *out_count,
                          hipStream_t st, bool allow_above_keep);
 

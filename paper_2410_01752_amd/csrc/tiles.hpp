@@ -369,4 +369,61 @@ __device__ __forceinline__ void score_pair_tile(
         }
 }
 
+// Exact FP32 score of one candidate of the one-sided slice's binary block,
+// by one thread, with the pair-tile kernel's sequence of operations (pilot
+// over the first chunk, FP32 chunk sums carried in FP64), so the value is
+// bit-identical to the tile kernel's.  -1 for an invalid candidate or an id
+// outside the binary block.
+__device__ inline float score_slice_id(const sisso_space &s, const FormSlots &fs, int n,
+                                       const float *__restrict__ pool32, int64_t ld32,
+                                       const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
+                                       const sisso_resid_info *__restrict__ info, int64_t id)
+{
+    const int Lv = s.levels;
+    const int64_t binbase = s.pool[Lv] + s.rect_unary;
+    if (!s.rect || id < binbase || id >= s.total) return -1.0f;
+    const int64_t loc = id - binbase, vcount = s.pool[Lv - 1];
+    const int slot = (int)(loc % s.n_slots);
+    const int64_t pair = loc / s.n_slots;
+    const int64_t u = s.pool[Lv - 1] + pair / vcount, v = pair % vcount;
+    int k = -1;
+    for (int f = 0; f < 5; ++f)
+        if (fs.slot[f] == slot) k = f;
+    const sisso_colstat ust = stats[u], vst = stats[v];
+    if (k < 0 || ust.valid == 0.0f || vst.valid == 0.0f) return -1.0f;
+    const float *cu = pool32 + (size_t)u * ld32, *cv = pool32 + (size_t)v * ld32;
+    const int c0 = n < kSC ? n : kSC;
+    float pm = 0.f, p3 = 0.f, p4 = 0.f;
+    for (int t = 0; t < c0; ++t) {
+        const float ur = cu[t], vr = cv[t];
+        const float uq = __builtin_amdgcn_rcpf(ur), vq = __builtin_amdgcn_rcpf(vr);
+        pm = fmaf(ur, vr, pm);
+        p3 = fmaf(ur, vq, p3);
+        p4 = fmaf(vr, uq, p4);
+    }
+    const float inv = 1.0f / (float)c0;
+    const float cm = pm * inv, c3 = p3 * inv, c4 = p4 * inv;
+    float fA = 0.f, fB = 0.f, fC = 0.f;
+    double dB = 0.0, dC = 0.0;
+    for (int t0 = 0; t0 < n; t0 += kSC) {
+        const int te = t0 + kSC < n ? t0 + kSC : n;
+        for (int t = t0; t < te; ++t) {
+            const float ur = cu[t], vr = cv[t];
+            const float us = ur - ust.mean, vs = vr - vst.mean;
+            const float uq = __builtin_amdgcn_rcpf(ur), vq = __builtin_amdgcn_rcpf(vr);
+            const float g = binary_form(k, ur, us, uq, vr, vs, vq, cm, c3, c4);
+            fA += g;
+            fB = fmaf(g, g, fB);
+            fC = fmaf(g, r32[t], fC);
+        }
+        dB += (double)fB;
+        dC += (double)fC;
+        fB = fC = 0.0f;
+    }
+    const double shifts[5] = {(double)ust.mean + (double)vst.mean, (double)ust.mean - (double)vst.mean,
+                              (double)cm, (double)c3, (double)c4};
+    return form_score(k, fA, dB, dC, shifts[k], cu, cv, n, ust.maxabs, ust.minabs, ust.rms, vst.maxabs, vst.minabs,
+                      vst.rms, (double)n, info->sum_r32, info->s_rr);
+}
+
 }  // namespace sisso

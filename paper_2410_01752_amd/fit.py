@@ -155,6 +155,9 @@ class Engine:
         parts = [("pool", begin, min(end, bb)), ("binary", max(begin, bb), end)]
         base = 0
         use_bf16 = precision == "bf16" and self.rect
+        use_learned = precision == "learned" and self.rect
+        if use_learned and getattr(self, "pruner", None) is None:
+            raise L.SissoError("learned screening needs a pruner (Engine.set_pruner)")
         if use_bf16:
             self.prepare_bf16()
             band = max(min(band or 4 * keep, L.MAX_KEEP), keep)
@@ -166,7 +169,25 @@ class Engine:
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev1 = torch.cuda.Event(enable_timing=True)
                 ev0.record()
-            if name == "binary" and use_bf16:
+            if name == "binary" and use_learned:
+                pr, (frac, n_sample, seed) = self.pruner, self.pruner_cfg
+                steps = [("learned_prepare", lambda: pr.prepare(r64)),
+                         ("learned_threshold", lambda: pr.threshold(frac, n_sample, seed)),
+                         ("learned_screen", lambda: pr.screen_binary(a, ws, b, e))]
+                nl = 0
+                for sname, call in steps:
+                    if events is not None:
+                        s0 = torch.cuda.Event(enable_timing=True)
+                        s1 = torch.cuda.Event(enable_timing=True)
+                        s0.record()
+                    res = call()
+                    if events is not None:
+                        s1.record()
+                        events.setdefault(sname, []).append((s0, s1))
+                    if sname == "learned_screen":
+                        nl = res
+                # the residual was re-prepared by the encoder; the lists are complete
+            elif name == "binary" and use_bf16:
                 nb = L.lib().sisso_bf16_workspace_size(ctypes.byref(self.space), ctypes.byref(a), band)
                 bws = self._workspace("bf16", nb)
                 sp_, a_ = ctypes.byref(self.space), ctypes.byref(a)
@@ -222,6 +243,12 @@ class Engine:
                 "sisso_materialize_ids")
         return out.view(count, self.n), valid
 
+    def set_pruner(self, pruner, frac: float = 0.05, n_sample: int = 1 << 20, seed: int = 0):
+        """Learned screening of the slice's binary block (precision="learned"):
+        only candidates the network ranks in the top `frac` are scored exactly."""
+        self.pruner = pruner
+        self.pruner_cfg = (frac, n_sample, seed)
+
     # ----------------------------------------------------------------- fit
     def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10,
             grid: int = 0, tile: int = 0, timings: Optional[dict] = None, precision: str = "fp32",
@@ -232,6 +259,7 @@ class Engine:
         fs = FitState(self.n, self.dev)
         out: List[StepResult] = []
         r = self.y
+        self.residuals = [self.y]
         for t in range(1, dmax + 1):
             keep = keep0
             while True:
@@ -248,6 +276,7 @@ class Engine:
             fs.so(self.y, t, singular_tol, self._workspace, timings)
             out.append(fs.result(t, ids, sc, ct, keep, nc))
             r = fs.resid.clone()
+            self.residuals.append(r)
         return out
 
 

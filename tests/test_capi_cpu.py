@@ -153,3 +153,41 @@ def test_batched_argument_errors_before_launch():
                                             None) == 2
     assert lib.sisso_materialize_ids_stored(ctypes.byref(s2), 0, 50, fake, 50, fake, fake, 4, fake, 50, fake,
                                             None) == 2
+
+
+def test_learned_argument_errors_before_launch():
+    lib = L.lib()
+    sr = L.make_space(4, ["sq", "sqrt", "inv"], ["add", "sub", "mul", "div"], 2, True)
+    st = L.make_space(4, ["sq", "sqrt", "inv"], ["add", "sub", "mul", "div"], 2, False)
+    fake = ctypes.c_void_p(0x1000)
+    a = L.ScoreArgs()
+    a.n, a.keep, a.ld32 = 50, 40, 64
+    a.pool32 = a.stats = a.r32 = a.info = 0x1000
+    assert lib.sisso_mlp_param_count() == L.MLP_PARAMS and lib.sisso_mlp_table_count() == L.MLP_TABLES
+    assert lib.sisso_encode_operands(ctypes.byref(sr), ctypes.byref(a), 0, 10, None, None) == 1
+    assert lib.sisso_encode_operands(ctypes.byref(sr), ctypes.byref(a), 5, 5, fake, None) == 3
+    assert lib.sisso_encode_operands(ctypes.byref(sr), ctypes.byref(a), 0, sr.pool[2] + 1, fake, None) == 3
+    assert lib.sisso_candidate_inputs(ctypes.byref(st), fake, fake, 4, fake, None) == 5       # no slice
+    assert lib.sisso_score_ids(ctypes.byref(st), ctypes.byref(a), fake, 4, fake, None) == 5
+    assert lib.sisso_score_ids(ctypes.byref(sr), ctypes.byref(a), fake, -1, fake, None) == 2
+    assert lib.sisso_mlp_forward(None, fake, 4, fake, fake, None) == 1
+    assert lib.sisso_mlp_forward(fake, fake, 0, fake, fake, None) == 2
+    assert lib.sisso_mlp_workspace_size(0) == 0 and lib.sisso_mlp_workspace_size(64) > 0
+    assert lib.sisso_mlp_backward(fake, fake, fake, fake, fake, fake, 64, fake, None, fake, 16, None) == 4
+    assert lib.sisso_adam_step(fake, fake, fake, fake, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == 2
+    assert lib.sisso_adam_step(fake, fake, fake, fake, 10, 1, 1e-3, 1.0, 0.999, 1e-8, None) == 2
+    assert lib.sisso_mlp_parts(fake, fake, 0, 0, fake, None) == 2
+    assert lib.sisso_mlp_parts(fake, fake, 10, 2, fake, None) == 2
+    assert lib.sisso_select_kth(fake, 10, 11, fake, None) == 3
+    assert lib.sisso_select_kth(fake, 10, 0, fake, None) == 3
+    ws = lib.sisso_score_workspace_size(ctypes.byref(sr), ctypes.byref(a))
+    bb = sr.pool[2] + sr.rect_unary
+    assert lib.sisso_expand_score_pruned(ctypes.byref(st), ctypes.byref(a), fake, fake, fake, fake, 0, 10, fake,
+                                         ws, None, None) == 5
+    assert lib.sisso_expand_score_pruned(ctypes.byref(sr), ctypes.byref(a), fake, fake, fake, fake, bb, bb, fake,
+                                         ws, None, None) == 3
+    assert lib.sisso_expand_score_pruned(ctypes.byref(sr), ctypes.byref(a), fake, fake, fake, fake, bb,
+                                         sr.total, fake, ws - 1, None, None) == 4
+    assert lib.sisso_expand_score_pruned(ctypes.byref(sr), ctypes.byref(a), None, fake, fake, fake, bb,
+                                         sr.total, fake, ws, None, None) == 1
+    assert lib.sisso_expand_score_pruned_lists(ctypes.byref(sr), ctypes.byref(a), bb, sr.total) > 0

@@ -1,0 +1,296 @@
+"""Learned proposal on the GPU against the FP64 reference (oracle/mlp.py).
+
+Network: forward values within 1e-4, gradients within 2e-2 relative (the
+weight gradient's products run on BF16 matrix cores), Adam within 1e-6.
+Encodings: operator classes exact, statistics within 2e-4 of the FP64 ones.
+Pruned screening: with every candidate kept it equals exhaustive FP32
+screening bit for bit; with a threshold it equals the exact top-K' of the
+candidates whose network score passes.  Training: a network trained on the
+GPU ranks held-out problems' top candidates better than the best operand
+correlation and than random selection at the same budget.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_2410_01752_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2410_01752_amd import _lib as L
+    return L
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda:0")
+
+
+def _engine(p):
+    from paper_2410_01752_amd.fit import Engine
+    return Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
+
+
+# ------------------------------------------------------------------ network
+
+def test_mlp_forward_backward_adam_match_oracle():
+    from paper_2410_01752_amd import learned as LN
+    L = _lib()
+    lib = L.lib()
+    batch = 300                                   # several 64-row tiles and a ragged one
+    X, t, w = I.mlp_batch(17, batch)
+    P = I.mlp_init(18)
+    P["b1"] = np.random.default_rng(1).uniform(-0.3, 0.3, M.HIDDEN)
+    P["b2"] = np.array([0.25])
+    flat = LN.flatten_params(P)
+    Pr = LN.unflatten_params(flat)                # the FP32-rounded weights both sides use
+    dP, dX, dt, dw = _dev(flat), _dev(X), _dev(t), _dev(w)
+    Z = torch.empty(batch * 256, dtype=torch.float32, device="cuda:0")
+    s = torch.empty(batch, dtype=torch.float32, device="cuda:0")
+    st = L.stream_handle(torch.device("cuda:0"))
+    L.check(lib.sisso_mlp_forward(L.ptr(dP), L.ptr(dX), batch, L.ptr(Z), L.ptr(s), st), "forward")
+    G = torch.empty_like(dP)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda:0")
+    ws = torch.empty(lib.sisso_mlp_workspace_size(batch), dtype=torch.uint8, device="cuda:0")
+    L.check(lib.sisso_mlp_backward(L.ptr(dP), L.ptr(dX), L.ptr(Z), L.ptr(s), L.ptr(dt), L.ptr(dw), batch, L.ptr(G),
+                                   L.ptr(loss), L.ptr(ws), ws.numel(), st), "backward")
+    torch.cuda.synchronize()
+    z_o, _, s_o = M.forward(X, Pr)
+    lo, g_o, _ = M.loss_and_grad(X, t, w, Pr)
+    Zg = Z.view(batch, 256).cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(Zg - z_o)) <= 1e-4
+    assert np.max(np.abs(s.cpu().numpy() - s_o)) <= 1e-4
+    assert math.isclose(float(loss.item()), lo, rel_tol=1e-5)
+    g = LN.unflatten_params(G.cpu().numpy())
+    for k in ("b1", "w2", "b2"):
+        err = np.linalg.norm(g[k] - g_o[k]) / max(np.linalg.norm(g_o[k]), 1e-30)
+        assert err <= 1e-4, (k, err)
+    errW = np.linalg.norm(g["W1"] - g_o["W1"]) / np.linalg.norm(g_o["W1"])
+    print(f"  dW1 relative error {errW:.2e}", flush=True)
+    assert errW <= 2e-2
+    # the relu pattern (structure) is the same where the oracle's z is clear of 0
+    clear = np.abs(z_o) > 1e-3
+    assert np.array_equal((Zg > 0)[clear], (z_o > 0)[clear])
+    # Adam: one step from zero moments on the GPU's gradient
+    Mm, Vv = torch.zeros_like(dP), torch.zeros_like(dP)
+    P0 = dP.clone()
+    L.check(lib.sisso_adam_step(L.ptr(dP), L.ptr(G), L.ptr(Mm), L.ptr(Vv), dP.numel(), 1, 1e-3, 0.9, 0.999, 1e-8,
+                                st), "adam")
+    torch.cuda.synchronize()
+    gz = {k: np.zeros_like(v) for k, v in g.items()}
+    pn, _, _ = M.adam_step(LN.unflatten_params(P0.cpu().numpy()), g, gz, gz, 1, lr=1e-3)
+    got = LN.unflatten_params(dP.cpu().numpy())
+    for k in pn:
+        assert np.max(np.abs(got[k] - pn[k])) <= 1e-6, k
+
+
+# ----------------------------------------------------------------- encoding
+
+def _tiny_rect():
+    return I.tiny(9, n=300, d=5, dist="lognormal", rect=True)
+
+
+def test_encodings_match_oracle():
+    from paper_2410_01752_amd import learned as LN
+    p = _tiny_rect()
+    eng = _engine(p)
+    r64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+    enc = LN.encode(eng, r64)
+    torch.cuda.synchronize()
+    enc = enc.cpu().numpy()
+    sp = O.Space(5, p.unary, p.binary, 2, True)
+    pL = sp.pool(2)
+    rng = np.random.default_rng(4)
+    cols = np.unique(np.concatenate([np.arange(min(pL, 200)), rng.integers(0, pL, 400)]))
+    V, ok = sp.eval(p.X, cols)
+    for j, c in enumerate(cols):
+        cls = M.tree_classes(sp, int(c))
+        ref = M.encode(cls, M.operand_stats(V[:, j], p.y) if ok[j] else np.zeros(14))
+        assert np.array_equal(enc[c, :42], ref[:42]), c              # classes exact
+        if ok[j]:
+            err = np.abs(enc[c, 42:56] - ref[42:56])
+            assert err.max() <= 2e-4, (c, err.argmax(), enc[c, 42:56], ref[42:56])
+        assert np.all(enc[c, 56:] == 0)
+
+
+def test_candidate_inputs_and_exact_id_scores():
+    from paper_2410_01752_amd import learned as LN
+    p = _tiny_rect()
+    eng = _engine(p)
+    r64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+    enc = LN.encode(eng, r64)
+    ids = LN.sample_ids(eng, 3000, 5)
+    dids = torch.from_numpy(ids).to(eng.dev)
+    X = LN.inputs(eng, enc, dids)
+    sc = LN.score_ids(eng, dids)
+    # the same ids through the exhaustive kernel: bit-identical scores
+    bb = eng.binary_base()
+    full_ids, full_sc, cnt = eng.screen(r64, 2048, None, begin=bb)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    fmap = dict(zip(full_ids[:c].cpu().numpy().tolist(), full_sc[:c].cpu().numpy().tolist()))
+    X, sc, enc = X.cpu().numpy(), sc.cpu().numpy(), enc.cpu().numpy()
+    sp = O.Space(5, p.unary, p.binary, 2, True)
+    hit = 0
+    for q, i in enumerate(ids.tolist()):
+        op, l, r = sp.decode(i)
+        if i in fmap:
+            assert sc[q] == np.float32(fmap[i])
+            hit += 1
+        # layout: [enc(u) | enc(v) | onehot(form) | 0]; u is the newer operand
+        u, v = (l, r) if l > r else (r, l)
+        form = {0: 0, 1: 1, 2: 2}.get(op, 3 if l == u else 4)
+        assert np.array_equal(X[q, :64], enc[u]) and np.array_equal(X[q, 64:128], enc[v])
+        assert X[q, 128 + form] == 1.0 and X[q, 128:144].sum() == 1.0
+    # exact scores against the oracle (1e-6), invalid ones flagged
+    o = np.array([sp.score_range(p.X, p.y, i, i + 1)[0] for i in ids[:400].tolist()])
+    okm = np.isfinite(o)
+    assert np.all(sc[:400][~okm] < 0)
+    assert np.max(np.abs(sc[:400][okm] - o[okm])) <= 1e-6
+
+
+# ------------------------------------------------------------------ pruning
+
+def _pruner(eng, seed=21):
+    from paper_2410_01752_amd import learned as LN
+    P = I.mlp_init(seed)
+    P["b1"] = np.random.default_rng(seed).uniform(-0.2, 0.2, M.HIDDEN)
+    return LN.Pruner(eng, LN.flatten_params(P))
+
+
+def _screen_learned(eng, r64, keep, frac=None, tau=None, exclude=None):
+    pr = eng.pruner
+    if tau is not None:
+        eng.pruner_cfg = (1.0, 1 << 10, 0)
+        ids, sc, cnt = _screen_with_fixed_tau(eng, r64, keep, tau, exclude)
+    else:
+        ids, sc, cnt = eng.screen(r64, keep, exclude, begin=eng.binary_base(), precision="learned")
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    return ids[:c].cpu().numpy(), sc[:c].cpu().numpy()
+
+
+def _screen_with_fixed_tau(eng, r64, keep, tau, exclude):
+    """Pruned screening of the binary block at a given threshold."""
+    import ctypes
+    L = _lib()
+    pr = eng.pruner
+    pr.prepare(r64)
+    pr.set_threshold(tau)
+    a = eng.score_args(keep, exclude)
+    nb = L.lib().sisso_score_workspace_size(ctypes.byref(eng.space), ctypes.byref(a))
+    ws = torch.empty(nb, dtype=torch.uint8, device=eng.dev)
+    a.list_base = 0
+    pr.screen_binary(a, ws, eng.binary_base(), eng.total)
+    ids = torch.empty(keep, dtype=torch.int64, device=eng.dev)
+    sc = torch.empty(keep, dtype=torch.float32, device=eng.dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=eng.dev)
+    L.check(L.lib().sisso_topk(L.ptr(ws), ws.numel(), keep, L.ptr(ids), L.ptr(sc), L.ptr(cnt), eng.stream()), "topk")
+    return ids, sc, cnt
+
+
+def test_pruned_keep_all_equals_exhaustive():
+    p = I.tiny(12, n=333, d=5, dist="lognormal", rect=True)
+    eng = _engine(p)
+    eng.set_pruner(_pruner(eng))
+    r64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+    keep = 700
+    gi, gs = _screen_learned(eng, r64, keep, tau=-float("inf"))
+    ids, sc, cnt = eng.screen(r64, keep, None, begin=eng.binary_base())
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    assert np.array_equal(gi, ids[:c].cpu().numpy()) and np.array_equal(gs, sc[:c].cpu().numpy())
+    assert int(eng.pruner.kept.item()) == eng.total - eng.binary_base()
+
+
+def test_pruned_threshold_keeps_exactly_the_passing_candidates():
+    from paper_2410_01752_amd import learned as LN
+    p = I.tiny(13, n=150, d=4, dist="lognormal", rect=True)
+    eng = _engine(p)
+    pr = _pruner(eng, 33)
+    eng.set_pruner(pr)
+    r64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+    bb, tot = eng.binary_base(), eng.total
+    all_ids = torch.arange(bb, tot, dtype=torch.int64, device=eng.dev)
+    pr.prepare(r64)
+    net = pr.net_scores(all_ids).cpu().numpy()
+    # the network scores against the FP64 reference on a sample
+    enc = pr.enc.cpu().numpy()
+    Pn = LN.unflatten_params(pr.P.cpu().numpy())
+    sp = O.Space(4, p.unary, p.binary, 2, True)
+    rng = np.random.default_rng(2)
+    for q in rng.integers(0, tot - bb, 200):
+        i = bb + int(q)
+        op, l, r = sp.decode(i)
+        u, v = (l, r) if l > r else (r, l)
+        form = {0: 0, 1: 1, 2: 2}.get(op, 3 if l == u else 4)
+        ref = M.score_factorised(enc[u], enc[v], form, Pn)
+        assert abs(net[q] - ref) <= 1e-3 * max(1.0, abs(ref)), (i, net[q], ref)
+    tau = float(np.quantile(net, 0.9))
+    keep = 300
+    gi, gs = _screen_learned(eng, r64, keep, tau=tau)
+    # reference: exact FP32 scores of every passing candidate, best keep by (score desc, id asc)
+    eng.prepare_residual(r64)
+    passing = all_ids[torch.from_numpy(net >= np.float32(tau)).to(eng.dev)]
+    ex = LN.score_ids(eng, passing).cpu().numpy()
+    pid = passing.cpu().numpy()
+    okm = ex >= 0
+    order = np.lexsort((pid[okm], -ex[okm]))[:keep]
+    assert np.array_equal(gi, pid[okm][order]) and np.array_equal(gs, ex[okm][order])
+    assert int(pr.kept.item()) == len(pid)
+
+
+# ------------------------------------------------------------------ training
+
+def _train_problems(seeds, d=6, n=400):
+    return [I.config3(seed=s, n=n, d=d) for s in seeds]
+
+
+def test_trained_network_beats_operand_heuristic_and_random():
+    """Train on 3 small rung-3 problems (two residuals each); on 2 held-out
+    problems compare, at a 10% budget, the recall of the exhaustive top-K' by
+    the network, by max(|corr(u, r)|, |corr(v, r)|), and by chance (10%)."""
+    from paper_2410_01752_amd import learned as LN
+    Xs, ts, ws = [], [], []
+    for p in _train_problems([601, 602, 603]):
+        eng = _engine(p)
+        eng.fit(20, 1)
+        for ri, r in enumerate(eng.residuals[:2]):
+            ids, sc = LN.capture(eng, r, top=1024, n_sample=1 << 15, seed=ri)
+            X, t, w = LN.dataset(eng, r, ids, sc)
+            Xs.append(X); ts.append(t); ws.append(w)
+    X, t, w = torch.cat(Xs), torch.cat(ts), torch.cat(ws)
+    params, log = LN.train(X, t, w, LN.flatten_params(I.mlp_init(7)), steps=600, batch=2048, lr=2e-3, seed=1)
+    print(f"  trained on {X.shape[0]} examples: loss {log.losses[0]:.4f} -> {log.losses[-1]:.4f}", flush=True)
+    assert log.losses[-1] < 0.5 * log.losses[0]
+    frac, keep = 0.10, 256
+    rec_net, rec_heur = [], []
+    for p in _train_problems([611, 612]):
+        eng = _engine(p)
+        r64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+        ref_ids, ref_sc, cnt = eng.screen(r64, keep, None, begin=eng.binary_base())
+        c = int(cnt.item())
+        ref_ids, ref_sc = ref_ids[:c], ref_sc[:c].cpu().numpy()
+        pr = LN.Pruner(eng, params)
+        eng.set_pruner(pr, frac=frac, n_sample=1 << 16, seed=3)
+        gi, gs, gc = eng.screen(r64, keep, None, begin=eng.binary_base(), precision="learned")
+        torch.cuda.synchronize()
+        rec_net.append(LN.recall_of(ref_ids.cpu().numpy(), ref_sc, gi[:int(gc.item())].cpu().numpy()))
+        # heuristic: max operand |corr| >= its own (1 - frac) quantile on a sample
+        enc = pr.enc.cpu().numpy()
+        sp = O.Space(p.X.shape[1], p.unary, p.binary, 2, True)
+
+        def heur(i):
+            _, l, r = sp.decode(int(i))
+            return max(enc[l, 43], enc[r, 43])
+        samp = LN.sample_ids(eng, 20000, 9)
+        th = np.quantile([heur(i) for i in samp], 1 - frac)
+        rec_heur.append(np.mean([heur(i) >= th for i in ref_ids.cpu().numpy()]))
+    print(f"  recall at {frac:.0%}: network {rec_net}, heuristic {rec_heur}, random {frac}", flush=True)
+    assert np.mean(rec_net) > np.mean(rec_heur)
+    assert np.mean(rec_net) > 3 * frac
