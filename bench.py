@@ -14,10 +14,17 @@ resident in HBM before the timed region.  `value` is SIS candidates scored per
 second of step time; SO tuples per second are reported beside it.
 
 Screening forms: before the timed steps the binary rung-3 block is screened
-once against y with the plain FP32 form and with the BF16-MFMA form (band
-rescored in FP32); their times, the BF16 form's speedup and its top-K'
-recall against the FP32 form are reported under "forms".  The timed steps
-use the BF16 form when that recall is >= 0.99, else the FP32 form.
+once against y with the plain FP32 form, the BF16-MFMA form (band rescored in
+FP32) and the learned form (a network trained here, on the GPU, on eight
+smaller seeded rung-3 problems, keeps the top 2% for exact FP32 scoring);
+their times, speedups over FP32 and top-K' recall against the FP32 form are
+reported under "forms".  The timed steps use the fastest form whose recall
+is >= 0.99.
+
+Batched problems: after the timed steps, the 64-problem cross-validation /
+bootstrap batch (n = 100..2000, d = 12, rung 2, k = 50, D = 1..2) is fitted
+with one persistent screening launch per step; its time and rates are
+reported under "batched".
 
 Prints one JSON line (see the fields below).  `--gpus N` with N > 1 exits:
 this build measures one GPU.
@@ -39,6 +46,88 @@ sys.path.insert(0, ROOT)
 MI355X_HBM_GBS = 8000.0
 MI355X_FP32_NONPACKED_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FLOPS_PER_CAND_SAMPLE = 6               # generate + add + 2 FMA (sum, sum of squares, cross)
+NET_FLOPS_PER_CAND = 4 * 256            # per hidden unit: two adds, max, FMA into the score
+BATCH_FLOPS_PER_CAND_SAMPLE = 6
+
+
+def train_proposal(args, log):
+    """Train the proposal network on the GPU (capture + Adam), seeded."""
+    import torch
+    from paper_2410_01752_amd import inputs as I
+    from paper_2410_01752_amd import learned as LN
+    from paper_2410_01752_amd.fit import Engine
+    t0 = time.perf_counter()
+    Xs, ts, ws = [], [], []
+    seeds = list(range(501, 509))
+    for s in seeds:
+        q = I.config3(seed=s, n=2000, d=12)
+        e = Engine(q.X, q.y, q.unary, q.binary, q.rung, q.rect)
+        e.fit(q.k, 1)
+        for ri, r in enumerate(e.residuals[:2]):
+            ids, sc = LN.capture(e, r, top=2048, n_sample=1 << 17, seed=ri)
+            X, t, w = LN.dataset(e, r, ids, sc)
+            Xs.append(X); ts.append(t); ws.append(w)
+        del e
+        torch.cuda.empty_cache()
+    X, t, w = torch.cat(Xs), torch.cat(ts), torch.cat(ws)
+    del Xs, ts, ws
+    cap_s = time.perf_counter() - t0
+    params, tl = LN.train(X, t, w, LN.flatten_params(I.mlp_init(7)), steps=args.learned_steps, batch=4096,
+                          lr=1e-3, seed=1, log_every=max(1, args.learned_steps // 6))
+    info = {"data": f"seeded rung-3 problems {seeds[0]}-{seeds[-1]} (n=2000, d=12, LogNormal(0,0.5)), "
+                    "residuals y and r_1; exhaustive top 2048 + 2^17 uniform ids each",
+            "examples": int(X.shape[0]), "steps": args.learned_steps, "batch": 4096, "capture_s": cap_s,
+            "train_ms": tl.ms, "loss": tl.losses}
+    log(f"proposal trained: {X.shape[0]} examples, loss {tl.losses[0]:.4f} -> {tl.losses[-1]:.4f}, "
+        f"{tl.ms:.0f} ms")
+    del X, t, w
+    torch.cuda.empty_cache()
+    return params, info
+
+
+def batched_fit(log):
+    """The 64-problem CV / bootstrap batch: one persistent screening launch per step."""
+    import torch
+    from paper_2410_01752_amd import inputs as I
+    from paper_2410_01752_amd.batch import Batch
+    ps = I.config4()
+
+    def step(tm=None):
+        b = Batch([(q.X, q.y) for q in ps], ps[0].unary, ps[0].binary, 2)
+        res = b.fit(ps[0].k, ps[0].dmax, timings=tm)
+        return b, res
+
+    step()
+    torch.cuda.synchronize()
+    tm = {}
+    t0 = time.perf_counter()
+    b, res = step(tm)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sc = [a.elapsed_time(c) for a, c in tm.get("batch_screen", [])]
+    tk = [a.elapsed_time(c) for a, c in tm.get("batch_topk", [])]
+    total = b.total
+    sum_n = sum(b.n)
+    passes = len(sc)
+    # roofline over the launches that screened every problem (one per t)
+    full = [i for i, s in enumerate(tm.get("batch_screen_sum_n", [])) if s == sum_n]
+    flops = BATCH_FLOPS_PER_CAND_SAMPLE * sum_n * total
+    kern_ms = sum(sc[i] for i in full) / max(1, len(full))
+    info = {"workload": "64 SISSO fits (8 datasets x 5 CV folds + 3 bootstraps), n=100..2000, d=12 "
+                        "U(0.1,10), full operator set, rung 2 (482,031 candidates each), k=50, D=1..2",
+            "problems": len(ps), "sum_n": sum_n, "ms_per_step": wall * 1e3,
+            "screen_launches": passes, "screen_ms": sc, "topk_ms": tk,
+            "screen_launch_sum_n": tm.get("batch_screen_sum_n", []),
+            "screen_launch_problems": tm.get("batch_screen_problems", []),
+            "candidates_per_s": sum(tm.get("batch_screen_problems", [])) * total / wall,
+            "roofline": {"bound": "alu", "kernel": "k_score_batch", "achieved": flops / (kern_ms * 1e-3) / 1e12,
+                         "peak": MI355X_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flops / (kern_ms * 1e-3) / 1e12 / MI355X_FP32_NONPACKED_TFLOPS,
+                         "per_unit": f"{BATCH_FLOPS_PER_CAND_SAMPLE} flops per (candidate, sample), "
+                                     f"{total} candidates x sum_n={sum_n} per launch"},
+            "rmse_D2": [r[-1].rmse for r in res[:4]]}
+    log(f"batched: {len(ps)} problems, {wall * 1e3:.1f} ms per step, screen {kern_ms:.2f} ms per launch")
+    return info
 
 
 def parse():
@@ -53,8 +142,13 @@ def parse():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--keep0", type=int, default=0,
                     help="screened-list length before duplicate removal (k + slack); 0 = 2k, "
-                         "or 1024 for the rung-3 workload")
-    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16"],
+                         "or 2048 for the rung-3 workload (no re-screening when duplicates crowd the list)")
+    ap.add_argument("--learned-frac", type=float, default=0.02,
+                    help="learned form: fraction of the binary block scored exactly")
+    ap.add_argument("--learned-steps", type=int, default=3000, help="training steps of the proposal network")
+    ap.add_argument("--no-learned", action="store_true", help="skip training and the learned form")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem fit")
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16", "learned"],
                     help="screening form of the rung-3 slice; auto = BF16 when its recall against the "
                          "FP32 form, measured in this run, is >= 0.99")
     ap.add_argument("--band", type=int, default=2048, help="BF16 form: candidates rescored in FP32")
@@ -119,7 +213,7 @@ def main():
     n = p.X.shape[0]
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
     log(f"workload {args.workload} n={n} d={p.X.shape[1]} k={p.k} D={p.dmax}")
-    keep0 = args.keep0 or (1024 if p.rect else 2 * p.k)
+    keep0 = args.keep0 or (2048 if p.rect else 2 * p.k)
     band = args.band
 
     if args.copy_calibration:
@@ -134,41 +228,66 @@ def main():
     def ev_ms(tm, name):
         return [a.elapsed_time(b) for a, b in tm.get(name, [])]
 
-    # ---- forms: BF16 against plain FP32 on the first residual (y)
+    # ---- forms on the first residual (y): plain FP32, BF16 MFMA + band rescore, learned proposal
     forms = {}
     prec = args.precision
-    if p.rect and prec in ("auto", "bf16") and not args.no_forms:
+    learned_params = None
+    if p.rect and not args.no_learned and prec in ("auto", "learned"):
+        learned_params, forms["learned_training"] = train_proposal(args, log)
+    if p.rect and not args.no_forms:
+        from paper_2410_01752_amd import learned as LN
         eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
         y64 = eng.y
-        out = {}
-        for form in ("fp32", "bf16", "bf16"):       # BF16 twice: the first call prepares operands
-            tm = {}
-            ids, sc, cnt = eng.screen(y64, keep0, None, precision=form, band=band, events=tm)
-            torch.cuda.synchronize()
+        bb = eng.binary_base()
+
+        def run(form, reps=1):
+            for _ in range(reps):
+                tm = {}
+                ids, sc, cnt = eng.screen(y64, keep0, None, begin=bb, precision=form, band=band, events=tm)
+                torch.cuda.synchronize()
             c = int(cnt.item())
-            out[form] = (ids[:c].cpu().numpy(), sc[:c].cpu().numpy(), tm)
-        fi, fs, tf = out["fp32"]
-        bi, bs, tb = out["bf16"]
-        rec, raw = recall_of(fi, fs, bi)
+            return ids[:c].cpu().numpy(), sc[:c].cpu().numpy(), tm
+
+        fi, fs, tf = run("fp32")
         fp32_ms = sum(ev_ms(tf, "binary"))
-        bf16_ms = sum(ev_ms(tb, "binary"))
-        forms = {"fp32": {"binary_block_ms": fp32_ms, "k_score_rect_ms": fp32_ms},
-                 "bf16": {"binary_block_ms": bf16_ms, "k_score_rect_bf16_ms": sum(ev_ms(tb, "bf16_screen")),
-                          "operand_prep_ms": sum(ev_ms(tb, "bf16_residual")),
-                          "band_rescore_ms": sum(ev_ms(tb, "bf16_rescore")), "band": band,
-                          "recall": rec, "recall_raw": raw, "speedup_vs_fp32": fp32_ms / bf16_ms,
-                          "keep": keep0}}
-        log(f"forms: fp32 {fp32_ms:.1f} ms, bf16 {bf16_ms:.1f} ms, recall {rec:.4f} (raw {raw:.4f})")
+        forms["fp32"] = {"binary_block_ms": fp32_ms, "k_score_rect_ms": fp32_ms, "recall": 1.0, "keep": keep0}
+        log(f"forms: fp32 {fp32_ms:.1f} ms")
+        if prec in ("auto", "bf16"):
+            bi, bs, tb = run("bf16", reps=2)             # the first call prepares the BF16 operands
+            rec, raw = recall_of(fi, fs, bi)
+            bf16_ms = sum(ev_ms(tb, "binary"))
+            forms["bf16"] = {"binary_block_ms": bf16_ms, "k_score_rect_bf16_ms": sum(ev_ms(tb, "bf16_screen")),
+                             "operand_prep_ms": sum(ev_ms(tb, "bf16_residual")),
+                             "band_rescore_ms": sum(ev_ms(tb, "bf16_rescore")), "band": band,
+                             "recall": rec, "recall_raw": raw, "speedup_vs_fp32": fp32_ms / bf16_ms, "keep": keep0}
+            log(f"forms: bf16 {bf16_ms:.1f} ms, recall {rec:.4f} (raw {raw:.4f})")
+        if learned_params is not None:
+            pr = LN.Pruner(eng, learned_params)
+            eng.set_pruner(pr, frac=args.learned_frac, n_sample=1 << 20, seed=3)
+            li, ls, tl = run("learned", reps=2)
+            rec, raw = recall_of(fi, fs, li)
+            l_ms = sum(ev_ms(tl, "binary"))
+            forms["learned"] = {"binary_block_ms": l_ms, "k_score_pruned_ms": sum(ev_ms(tl, "learned_screen")),
+                                "encode_and_parts_ms": sum(ev_ms(tl, "learned_prepare")),
+                                "threshold_ms": sum(ev_ms(tl, "learned_threshold")),
+                                "budget_frac": args.learned_frac,
+                                "kept_frac": int(pr.kept.item()) / max(1, eng.total - bb),
+                                "recall": rec, "recall_raw": raw, "speedup_vs_fp32": fp32_ms / l_ms, "keep": keep0}
+            log(f"forms: learned {l_ms:.1f} ms, recall {rec:.4f} (raw {raw:.4f})")
         if prec == "auto":
-            prec = "bf16" if rec >= 0.99 else "fp32"
+            ok = {f: v["binary_block_ms"] for f, v in forms.items()
+                  if f in ("fp32", "bf16", "learned") and v["recall"] >= 0.99}
+            prec = min(ok, key=ok.get)
         del eng
         torch.cuda.empty_cache()
     elif prec == "auto":
         prec = "fp32"
+    if prec == "learned" and learned_params is None:
+        learned_params, forms["learned_training"] = train_proposal(args, log)
 
     # ---- autotuned launch shape of the slice kernel for the chosen form
     tile, grid, tuned = args.tile, args.grid, None
-    if p.rect and not args.no_autotune and not (args.tile or args.grid):
+    if p.rect and prec in ("fp32", "bf16") and not args.no_autotune and not (args.tile or args.grid):
         from paper_2410_01752_amd import autotune as AT
         eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
         ch = AT.tune_engine(eng, form=prec, keep=keep0, band=band, sample_tiles=1024)
@@ -180,6 +299,9 @@ def main():
 
     def one_step(timings=None):
         eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
+        if prec == "learned":
+            from paper_2410_01752_amd import learned as LN
+            eng.set_pruner(LN.Pruner(eng, learned_params), frac=args.learned_frac, n_sample=1 << 20, seed=3)
         res = eng.fit(p.k, p.dmax, keep0=keep0, grid=grid, tile=tile, timings=timings,
                       precision=prec, band=band)
         return eng, res
@@ -215,7 +337,19 @@ def main():
     so_m = timings.get("so_m", [0])
     dmax_tuples = math.comb(so_m[p.dmax - 1] if len(so_m) >= p.dmax else p.k * p.dmax, p.dmax)
     pool_ms = ev_ms(timings, "pool")
-    if n_bin > 0 and prec == "bf16":
+    if n_bin > 0 and prec == "learned":
+        ks = ev_ms(timings, "learned_screen")
+        kernel_ms = sum(ks) / len(ks)
+        kept = forms.get("learned", {}).get("kept_frac", args.learned_frac) * n_bin
+        flops = NET_FLOPS_PER_CAND * n_bin + FLOPS_PER_CAND_SAMPLE * n * kept
+        achieved = flops / (kernel_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_score_pruned", "achieved": achieved,
+                "peak": MI355X_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / MI355X_FP32_NONPACKED_TFLOPS, "traffic": None,
+                "avg_launch_ms": kernel_ms, "units_per_launch": n_bin,
+                "per_unit": f"{NET_FLOPS_PER_CAND} network flops per candidate + {FLOPS_PER_CAND_SAMPLE} flops "
+                            f"x n={n} per exactly scored candidate ({kept:.3g} per launch)"}
+    elif n_bin > 0 and prec == "bf16":
         ks = ev_ms(timings, "bf16_screen")
         kernel_ms = sum(ks) / len(ks)
         pairs = n_bin // eng.space.n_slots
@@ -261,7 +395,8 @@ def main():
                                 "C2": "rung-2 SISSO fit: n=500, d=10, full operator set, k=100, D=1..3",
                                 "C1": "rung-2 SISSO fit: n=50, d=5, k=20, D=1..2"}[args.workload],
                    "n": n, "d": p.X.shape[1], "candidates_per_pass": total, "k": p.k, "D": p.dmax,
-                   "screening_form": prec, "keep0": keep0, "band": band if prec == "bf16" else None},
+                   "screening_form": prec, "keep0": keep0, "band": band if prec == "bf16" else None,
+                   "learned_frac": args.learned_frac if prec == "learned" else None},
         "sis_passes_per_step": passes_per_step,
         "sis_candidates_per_step": cands_per_step,
         "so_tuples_per_s": dmax_tuples / (so_ms_d3 * 1e-3) if so_ms_d3 > 0 else None,
@@ -275,6 +410,8 @@ def main():
         "fit": {"rmse": [r.rmse for r in last], "best_ids": [list(map(int, r.best_ids)) for r in last],
                 "keep": [r.keep for r in last]},
     }
+    if not args.no_batched:
+        out["batched"] = batched_fit(log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)

@@ -134,6 +134,8 @@ class Batch:
             events.setdefault("batch_prepare", []).append((ev[0], ev[1]))
             events.setdefault("batch_screen", []).append((ev[1], ev[2]))
             events.setdefault("batch_topk", []).append((ev[2], ev[3]))
+            events.setdefault("batch_screen_sum_n", []).append(sum(self.n[p] for p in which))
+            events.setdefault("batch_screen_problems", []).append(len(which))
         return ids.view(P, keep_max), sc.view(P, keep_max), cnt, status
 
     def materialize(self, p: int, ids: torch.Tensor):
