@@ -27,6 +27,8 @@ namespace sisso {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kUVar = 4;      // U~, U~^2, Z~, Z~^2
 constexpr int kVVar = 8;      // V~, V~ r, P, Q, W~, W~ r, Pw, Qw
@@ -43,28 +45,21 @@ constexpr int kNG = 12;       // GEMMs per tile
 
 __host__ __device__ inline size_t align256b(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// u-side operand buffer: [kUVar * kSplit][ucols][ldb] bf16 (variant-major,
-// hi then lo), then ucols float4 sums.
+// u-side per-column constants (residual-independent, once per problem).
 struct BfOps {
-    __bf16 *U;
     float4 *usum;     // mean(u), mean(1/u), sum u~^2, sum z~^2
 };
-__host__ __device__ inline size_t bf_ops_bytes(int64_t ucols, int64_t ldb)
-{
-    return align256b((size_t)kUVar * kSplit * ucols * ldb * sizeof(__bf16)) + align256b((size_t)ucols * sizeof(float4));
-}
-__host__ __device__ inline BfOps bf_ops_view(void *p, int64_t ucols, int64_t ldb)
+__host__ __device__ inline size_t bf_ops_bytes(int64_t ucols) { return align256b((size_t)ucols * sizeof(float4)); }
+__host__ __device__ inline BfOps bf_ops_view(void *p)
 {
     BfOps o;
-    o.U = (__bf16 *)p;
-    o.usum = (float4 *)((char *)p + align256b((size_t)kUVar * kSplit * ucols * ldb * sizeof(__bf16)));
+    o.usum = (float4 *)p;
     return o;
 }
 
-// per-pass BF16 workspace: v-side operands and sums, u-side residual sums,
-// band lists (a screening workspace of its own) and the band ids.
+// per-pass BF16 workspace: v-side column sums, u-side residual sums, band
+// lists (a screening workspace of its own) and the band ids.
 struct BfWs {
-    __bf16 *V;        // [kVVar * kSplit][vcols][ldb]
     float4 *vsum;     // 2 per column: (mean v, mean 1/v, sum v~^2, sum w~^2), (sum v~ r, sum w~ r, rms, 0)
     float2 *ures;     // per u column: sum u~ r, sum z~ r
     int64_t *band_ids;
@@ -72,20 +67,18 @@ struct BfWs {
     int32_t *band_cnt;
     void *lists;      // screening workspace of the BF16 lists
 };
-__host__ __device__ inline size_t bf_ws_bytes(int64_t ucols, int64_t vcols, int64_t ldb, int band, int lists, int keep)
+__host__ __device__ inline size_t bf_ws_bytes(int64_t ucols, int64_t vcols, int band, int lists, int keep)
 {
-    size_t b = align256b((size_t)kVVar * kSplit * vcols * ldb * sizeof(__bf16));
-    b += align256b((size_t)vcols * 2 * sizeof(float4));
+    size_t b = align256b((size_t)vcols * 2 * sizeof(float4));
     b += align256b((size_t)ucols * sizeof(float2));
     b += align256b((size_t)band * sizeof(int64_t)) + align256b((size_t)band * sizeof(float)) + 256;
     b += ws_bytes_for(lists, keep);
     return b;
 }
-__host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols, int64_t ldb, int band)
+__host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols, int band)
 {
     BfWs w;
     char *c = (char *)p;
-    w.V = (__bf16 *)c; c += align256b((size_t)kVVar * kSplit * vcols * ldb * sizeof(__bf16));
     w.vsum = (float4 *)c; c += align256b((size_t)vcols * 2 * sizeof(float4));
     w.ures = (float2 *)c; c += align256b((size_t)ucols * sizeof(float2));
     w.band_ids = (int64_t *)c; c += align256b((size_t)band * sizeof(int64_t));
@@ -97,23 +90,13 @@ __host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 
-// Store x as its two BF16 parts: variant q of a (variant, column) matrix with
-// kSplit parts per variant, hi at part 0 and lo at part 1.
-__device__ __forceinline__ void store_split(__bf16 *base, int q, int64_t cols, int64_t c, int64_t ldb, int64_t t,
-                                            float x)
-{
-    const __bf16 hi = to_bf16(x);
-    const __bf16 lo = to_bf16(x - (float)hi);
-    base[((size_t)(q * kSplit + 0) * cols + c) * ldb + t] = hi;
-    base[((size_t)(q * kSplit + 1) * cols + c) * ldb + t] = lo;
-}
-
 // ---------------------------------------------------------------- operands
 
-// u side (newest pool level), independent of the residual.  One wave per column.
+// u side (newest pool level), independent of the residual: the column
+// constants of the centred variants.  One wave per column.
 __global__ void __launch_bounds__(256) k_bf16_u_prep(int n, const float *__restrict__ pool32, int64_t ld32,
                                                      const sisso_colstat *__restrict__ stats, int64_t col0,
-                                                     int64_t ucols, int64_t ldb, BfOps ops)
+                                                     int64_t ucols, BfOps ops)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -124,19 +107,12 @@ __global__ void __launch_bounds__(256) k_bf16_u_prep(int n, const float *__restr
         const float mu = st.mean, mz = st.mean_rcp;
         const bool zok = st.minabs > 0.0f;
         double suu = 0.0, szz = 0.0;
-        for (int64_t t = lane; t < ldb; t += 64) {
-            float uu = 0.f, zz = 0.f;
-            if (t < n) {
-                const float x = col[t];
-                uu = x - mu;
-                zz = zok ? __builtin_amdgcn_rcpf(x) - mz : 0.f;
-                suu += (double)uu * uu;
-                szz += (double)zz * zz;
-            }
-            store_split(ops.U, 0, ucols, c, ldb, t, uu);
-            store_split(ops.U, 1, ucols, c, ldb, t, uu * uu);
-            store_split(ops.U, 2, ucols, c, ldb, t, zz);
-            store_split(ops.U, 3, ucols, c, ldb, t, zz * zz);
+        for (int t = lane; t < n; t += 64) {
+            const float x = col[t];
+            const float uu = x - mu;
+            const float zz = zok ? __builtin_amdgcn_rcpf(x) - mz : 0.f;
+            suu += (double)uu * uu;
+            szz += (double)zz * zz;
         }
         suu = wave_sum(suu);
         szz = wave_sum(szz);
@@ -168,10 +144,10 @@ __global__ void __launch_bounds__(256) k_bf16_u_resid(int n, const float *__rest
     }
 }
 
-// v side (previous pool), per residual: eight variants and the column sums.
+// v side (previous pool), per residual: the column sums.
 __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restrict__ pool32, int64_t ld32,
                                                      const sisso_colstat *__restrict__ stats, int64_t vcols,
-                                                     int64_t ldb, const float *__restrict__ r32, BfWs w)
+                                                     const float *__restrict__ r32, BfWs w)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -182,22 +158,14 @@ __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restr
         const float mv = st.mean, mw = st.mean_rcp;
         const bool wok = st.minabs > 0.0f;
         double svv = 0.0, sww = 0.0, svr = 0.0, swr = 0.0;
-        for (int64_t t = lane; t < ldb; t += 64) {
-            float vv = 0.f, ww = 0.f, r = 0.f;
-            if (t < n) {
-                const float x = col[t];
-                r = r32[t];
-                vv = x - mv;
-                ww = wok ? __builtin_amdgcn_rcpf(x) - mw : 0.f;
-                svv += (double)vv * vv;
-                sww += (double)ww * ww;
-                svr += (double)vv * r;
-                swr += (double)ww * r;
-            }
-            const float var[kVVar] = {vv, vv * r, vv * (vv + 2.f * mv), vv * (vv + mv),
-                                      ww, ww * r, ww * (ww + 2.f * mw), ww * (ww + mw)};
-#pragma unroll
-            for (int q = 0; q < kVVar; ++q) store_split(w.V, q, vcols, c, ldb, t, var[q]);
+        for (int t = lane; t < n; t += 64) {
+            const float x = col[t], r = r32[t];
+            const float vv = x - mv;
+            const float ww = wok ? __builtin_amdgcn_rcpf(x) - mw : 0.f;
+            svv += (double)vv * vv;
+            sww += (double)ww * ww;
+            svr += (double)vv * r;
+            swr += (double)ww * r;
         }
         svv = wave_sum(svv); sww = wave_sum(sww); svr = wave_sum(svr); swr = wave_sum(swr);
         if (lane == 0) {
@@ -210,8 +178,8 @@ __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restr
 // -------------------------------------------------------------- screening
 
 __global__ void __launch_bounds__(256) k_score_rect_bf16(
-    sisso_space s, FormSlots fs, int n, int64_t ldb, const __bf16 *__restrict__ U,
-    const float4 *__restrict__ usum, const __bf16 *__restrict__ V, const float4 *__restrict__ vsum,
+    sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
+    const float *__restrict__ r32, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
     const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
     int64_t ut_hi, int64_t id_begin, int64_t id_end, void *lws, int lists_total, int keep, int cap)
@@ -238,55 +206,89 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
     const int nch = (n + kKC - 1) / kKC;
     const int64_t nvt = (vcount + kBT - 1) / kBT;
-    constexpr int NA = AV * kBT * (kKC / 8) / 256;   // 16-byte pieces per thread, A side
-    constexpr int NB = BV * kBT * (kKC / 8) / 256;   // and B side
+    // staging role: column scol of the u and v tiles, samples 4 squad .. 4 squad + 3 of a chunk
+    const int scol = tid >> 2, squad = tid & 3;
 
     for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
         const int64_t u0 = ut * kBT;   // index into the newest level
+        const int64_t su = u0 + scol;
+        const bool su_ok = su < ucols;
+        const float4 us_c = usum[su_ok ? su : 0];
+        const float smu = us_c.x, smz = us_c.y;
+        const bool szok = su_ok && stats[ulo + su].minabs > 0.0f;
+        const float *ucol = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
         for (int64_t vt = 0; vt < nvt; ++vt) {
             const int64_t v0 = vt * kBT;
+            const int64_t sv = v0 + scol;
+            const bool sv_ok = sv < vcount;
+            const float4 vs_c = vsum[2 * (sv_ok ? sv : 0)];
+            const float smv = vs_c.x, smw = vs_c.y;
+            const bool swok = sv_ok && stats[sv_ok ? sv : 0].minabs > 0.0f;
+            const float *vcol = pool32 + (size_t)(sv_ok ? sv : 0) * ld32;
             f32x16 acc[kNG];
 #pragma unroll
             for (int g = 0; g < kNG; ++g)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
-            uint4 pa[NA], pb[NB];
+            // raw FP32 operands and residual of one chunk (register prefetch); the
+            // centred variants and their BF16 hi/lo parts are formed when staged
+            float4 pu, pv, pr;
             auto load_chunk = [&](int ch) {
-                const int64_t k0 = (int64_t)ch * kKC;
-#pragma unroll
-                for (int q = 0; q < NA; ++q) {
-                    const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
-                    const int64_t c = u0 + col;
-                    pa[q] = c < ucols ? *reinterpret_cast<const uint4 *>(U + ((size_t)var * ucols + c) * ldb + k0 + part * 8)
-                                      : make_uint4(0, 0, 0, 0);
-                }
-#pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
-                    const int64_t c = v0 + col;
-                    pb[q] = c < vcount ? *reinterpret_cast<const uint4 *>(V + ((size_t)var * vcount + c) * ldb + k0 + part * 8)
-                                       : make_uint4(0, 0, 0, 0);
-                }
+                const int t0 = ch * kKC + squad * 4;
+                pu = su_ok && t0 < n ? *reinterpret_cast<const float4 *>(ucol + t0) : make_float4(0, 0, 0, 0);
+                pv = sv_ok && t0 < n ? *reinterpret_cast<const float4 *>(vcol + t0) : make_float4(0, 0, 0, 0);
+                pr = t0 < n ? *reinterpret_cast<const float4 *>(r32 + t0) : make_float4(0, 0, 0, 0);
             };
-            auto store_chunk = [&]() {
+            auto store_chunk = [&](int ch) {
+                const int t0 = ch * kKC + squad * 4;
+                const float xu[4] = {pu.x, pu.y, pu.z, pu.w};
+                const float xv[4] = {pv.x, pv.y, pv.z, pv.w};
+                const float xr[4] = {pr.x, pr.y, pr.z, pr.w};
+                float ua[kUVar][4], va[kVVar][4];
 #pragma unroll
-                for (int q = 0; q < NA; ++q) {
-                    const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
-                    *reinterpret_cast<uint4 *>(sA + (var * kBT + col) * kKP + part * 8) = pa[q];
+                for (int e = 0; e < 4; ++e) {
+                    const bool live = t0 + e < n;
+                    const float uu = live && su_ok ? xu[e] - smu : 0.f;
+                    const float zz = live && szok ? __builtin_amdgcn_rcpf(xu[e]) - smz : 0.f;
+                    ua[0][e] = uu; ua[1][e] = uu * uu; ua[2][e] = zz; ua[3][e] = zz * zz;
+                    const float vv = live && sv_ok ? xv[e] - smv : 0.f;
+                    const float ww = live && swok ? __builtin_amdgcn_rcpf(xv[e]) - smw : 0.f;
+                    const float r = live ? xr[e] : 0.f;
+                    va[0][e] = vv; va[1][e] = vv * r; va[2][e] = vv * (vv + 2.f * smv); va[3][e] = vv * (vv + smv);
+                    va[4][e] = ww; va[5][e] = ww * r; va[6][e] = ww * (ww + 2.f * smw); va[7][e] = ww * (ww + smw);
                 }
+                auto put = [&](__bf16 *base, int var, const float (&x)[4]) {
+                    // hi = bf16(x), lo = bf16(x - hi), two values per conversion
+                    const bf16x2 h01 = __builtin_convertvector((f32x2){x[0], x[1]}, bf16x2);
+                    const bf16x2 h23 = __builtin_convertvector((f32x2){x[2], x[3]}, bf16x2);
+                    const bf16x2 l01 = __builtin_convertvector(
+                        (f32x2){x[0] - (float)h01[0], x[1] - (float)h01[1]}, bf16x2);
+                    const bf16x2 l23 = __builtin_convertvector(
+                        (f32x2){x[2] - (float)h23[0], x[3] - (float)h23[1]}, bf16x2);
+                    uint2 ph, pl;
+                    __builtin_memcpy(&ph.x, &h01, 4);
+                    __builtin_memcpy(&ph.y, &h23, 4);
+                    __builtin_memcpy(&pl.x, &l01, 4);
+                    __builtin_memcpy(&pl.y, &l23, 4);
+                    *reinterpret_cast<uint2 *>(base + ((var * kSplit + 0) * kBT + scol) * kKP + squad * 4) = ph;
+                    *reinterpret_cast<uint2 *>(base + ((var * kSplit + 1) * kBT + scol) * kKP + squad * 4) = pl;
+                };
 #pragma unroll
-                for (int q = 0; q < NB; ++q) {
-                    const int idx = q * 256 + tid, var = idx >> 7, col = (idx & 127) >> 1, part = idx & 1;
-                    *reinterpret_cast<uint4 *>(sB + (var * kBT + col) * kKP + part * 8) = pb[q];
-                }
+                for (int q = 0; q < kUVar; ++q) put(sA, q, ua[q]);
+#pragma unroll
+                for (int q = 0; q < kVVar; ++q) put(sB, q, va[q]);
             };
+            // software pipeline: the MFMAs of chunk ch run from fragments held in
+            // registers while the same waves form and stage chunk ch + 1
+            constexpr int GA[kNG] = {0, 0, 1, 0, 0, 0, 1, 0, 2, 2, 3, 2};
+            constexpr int GB[kNG] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3};
+            const int koff = (lane >> 5) * 8;
+            __syncthreads();                          // the previous tile's fragments are read
             load_chunk(0);
+            store_chunk(0);
+            __syncthreads();
+            if (nch > 1) load_chunk(1);
             for (int ch = 0; ch < nch; ++ch) {
-                __syncthreads();                      // the previous chunk's fragments are read
-                store_chunk();
-                __syncthreads();
-                if (ch + 1 < nch) load_chunk(ch + 1); // in flight during the MFMAs
-                const int koff = (lane >> 5) * 8;
                 bf16x8 af[AV], bfr[BV];
 #pragma unroll
                 for (int a = 0; a < AV; ++a)
@@ -294,9 +296,8 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
 #pragma unroll
                 for (int q = 0; q < BV; ++q)
                     bfr[q] = *reinterpret_cast<const bf16x8 *>(sB + (q * kBT + wv * 32 + (lane & 31)) * kKP + koff);
+                __syncthreads();                      // every wave holds chunk ch: LDS is free
                 // GEMM g: u-side variant GA[g], v-side variant GB[g]; terms hi*hi, hi*lo, lo*hi
-                constexpr int GA[kNG] = {0, 0, 1, 0, 0, 0, 1, 0, 2, 2, 3, 2};
-                constexpr int GB[kNG] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3};
 #pragma unroll
                 for (int term = 0; term < 3; ++term) {
                     const int pa_ = term == 2 ? 1 : 0, pb_ = term == 1 ? 1 : 0;
@@ -304,6 +305,11 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                     for (int g = 0; g < kNG; ++g)
                         acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[GA[g] * kSplit + pa_],
                                                                          bfr[GB[g] * kSplit + pb_], acc[g], 0, 0, 0);
+                }
+                if (ch + 1 < nch) {
+                    store_chunk(ch + 1);              // VALU work beside the MFMAs above
+                    __syncthreads();
+                    if (ch + 2 < nch) load_chunk(ch + 2);
                 }
             }
 
@@ -447,8 +453,6 @@ namespace {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-int64_t ldb_of(int n) { return ((int64_t)n + 63) / 64 * 64; }
-
 
 struct BfPlan {
     int64_t ut_lo = 0, ut_hi = 0;
@@ -489,7 +493,7 @@ extern "C" size_t sisso_bf16_operands_size(const sisso_space *space, int32_t n)
 {
     if (!space_ok(space) || n < 2 || n > SISSO_MAX_N) return 0;
     const int64_t ucols = space->pool[space->levels] - space->pool[space->levels - 1];
-    return bf_ops_bytes(ucols, ldb_of(n));
+    return bf_ops_bytes(ucols);
 }
 
 extern "C" sisso_status sisso_prepare_bf16(const sisso_space *space, const sisso_score_args *args, void *ops,
@@ -500,11 +504,11 @@ extern "C" sisso_status sisso_prepare_bf16(const sisso_space *space, const sisso
     if (args->n < 2 || args->n > SISSO_MAX_N || args->ld32 < args->n || (args->ld32 % 4) != 0) return SISSO_E_SHAPE;
     if (ops_bytes < sisso_bf16_operands_size(space, args->n)) return SISSO_E_WORKSPACE;
     const int L = space->levels;
-    const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, ldb = ldb_of(args->n);
-    const BfOps o = bf_ops_view(ops, ucols, ldb);
+    const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0;
+    const BfOps o = bf_ops_view(ops);
     const int64_t blocks = (ucols + 3) / 4;
     hipLaunchKernelGGL(k_bf16_u_prep, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, as_stream(stream),
-                       args->n, args->pool32, args->ld32, args->stats, col0, ucols, ldb, o);
+                       args->n, args->pool32, args->ld32, args->stats, col0, ucols, o);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 
@@ -513,7 +517,7 @@ extern "C" size_t sisso_bf16_workspace_size(const sisso_space *space, const siss
     if (!space_ok(space) || !args || args->n < 2 || band < 1 || band > SISSO_MAX_KEEP) return 0;
     const int L = space->levels;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
-    return bf_ws_bytes(ucols, vcols, ldb_of(args->n), band, bf_lists_cap(space), band);
+    return bf_ws_bytes(ucols, vcols, band, bf_lists_cap(space), band);
 }
 
 extern "C" int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_score_args *args,
@@ -552,11 +556,10 @@ extern "C" sisso_status sisso_bf16_residual(const sisso_space *space, const siss
     hipStream_t st = as_stream(stream);
     const int L = space->levels, n = args->n;
     const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
-    const int64_t ldb = ldb_of(n);
-    BfWs w = bf_ws_view(bws, ucols, vcols, ldb, band);
+    BfWs w = bf_ws_view(bws, ucols, vcols, band);
     const int64_t vb = (vcols + 3) / 4, ub = (ucols + 3) / 4;
     hipLaunchKernelGGL(k_bf16_v_prep, dim3((unsigned)(vb < 65536 ? vb : 65536)), dim3(256), 0, st, n, args->pool32,
-                       args->ld32, args->stats, vcols, ldb, args->r32, w);
+                       args->ld32, args->stats, vcols, args->r32, w);
     hipLaunchKernelGGL(k_bf16_u_resid, dim3((unsigned)(ub < 65536 ? ub : 65536)), dim3(256), 0, st, n, args->pool32,
                        args->ld32, args->stats, col0, ucols, args->r32, w.ures);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
@@ -575,9 +578,8 @@ extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_
     if (ops_bytes < sisso_bf16_operands_size(space, n)) return SISSO_E_WORKSPACE;
     hipStream_t st = as_stream(stream);
     const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
-    const int64_t ldb = ldb_of(n);
-    const BfOps o = bf_ops_view(const_cast<void *>(ops), ucols, ldb);
-    BfWs w = bf_ws_view(bws, ucols, vcols, ldb, band);
+    const BfOps o = bf_ops_view(const_cast<void *>(ops));
+    BfWs w = bf_ws_view(bws, ucols, vcols, band);
     const FormSlots fs = form_slots(space);
     const BfPlan p = bf_plan(space, cand_begin, cand_end,
                              args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid);
@@ -589,8 +591,8 @@ extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_
         const size_t smem = (size_t)(kUVar + kVVar) * kSplit * kBT * kKP * sizeof(__bf16) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16, smem)) return SISSO_E_UNSUPPORTED;
-        hipLaunchKernelGGL(k_score_rect_bf16, dim3(p.grid), dim3(256), smem, st, *space, fs, n, ldb, o.U, o.usum, w.V,
-                           w.vsum, w.ures, args->stats, args->info, args->exclude, args->n_exclude, p.ut_lo, p.ut_hi,
+        hipLaunchKernelGGL(k_score_rect_bf16, dim3(p.grid), dim3(256), smem, st, *space, fs, n, args->pool32,
+                           args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info, args->exclude, args->n_exclude, p.ut_lo, p.ut_hi,
                            cand_begin, cand_end, w.lists, lcap, keep_b, cap_b);
     }
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
@@ -609,7 +611,7 @@ extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso
     hipStream_t st = as_stream(stream);
     const int L = space->levels, n = args->n;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
-    BfWs w = bf_ws_view(bws, ucols, vcols, ldb_of(n), band);
+    BfWs w = bf_ws_view(bws, ucols, vcols, band);
     const FormSlots fs = form_slots(space);
     sisso_status rs = topk_launch(w.lists, band, w.band_ids, w.band_sc, w.band_cnt, st, false);
     if (rs != SISSO_OK) return rs;
