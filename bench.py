@@ -16,7 +16,7 @@ second of step time; SO tuples per second are reported beside it.
 Screening forms: before the timed steps the binary rung-3 block is screened
 once against y with the plain FP32 form, the BF16-MFMA form (band rescored in
 FP32) and the learned form (a network trained here, on the GPU, on eight
-smaller seeded rung-3 problems, keeps the top 2% for exact FP32 scoring);
+smaller seeded rung-3 problems, keeps the top 1% for exact FP32 scoring);
 their times, speedups over FP32 and top-K' recall against the FP32 form are
 reported under "forms".  The timed steps use the fastest form whose recall
 is >= 0.99.
@@ -48,6 +48,18 @@ MI355X_FP32_NONPACKED_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x
 FLOPS_PER_CAND_SAMPLE = 6               # generate + add + 2 FMA (sum, sum of squares, cross)
 NET_FLOPS_PER_CAND = 4 * 256            # per hidden unit: two adds, max, FMA into the score
 BATCH_FLOPS_PER_CAND_SAMPLE = 6
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when no summary for this kernel and workload exists."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    return d.get("hbm_bytes_per_launch")
 
 
 def train_proposal(args, log):
@@ -143,7 +155,7 @@ def parse():
     ap.add_argument("--keep0", type=int, default=0,
                     help="screened-list length before duplicate removal (k + slack); 0 = 2k, "
                          "or 2048 for the rung-3 workload (no re-screening when duplicates crowd the list)")
-    ap.add_argument("--learned-frac", type=float, default=0.02,
+    ap.add_argument("--learned-frac", type=float, default=0.01,
                     help="learned form: fraction of the binary block scored exactly")
     ap.add_argument("--learned-steps", type=int, default=3000, help="training steps of the proposal network")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned form")
@@ -377,6 +389,9 @@ def main():
                 "peak": MI355X_HBM_GBS, "unit": "GB/s", "frac": achieved / MI355X_HBM_GBS,
                 "traffic": None, "avg_launch_ms": kernel_ms, "units_per_launch": total,
                 "per_unit": f"4 bytes x n={n} samples per stored column"}
+    roof["traffic"] = measured_traffic(roof["kernel"], args.workload)
+    if roof["traffic"] is not None:
+        roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     if "fp32" in forms and n_bin > 0:
         fms = forms["fp32"]["k_score_rect_ms"]
         forms["fp32"]["roofline_frac"] = FLOPS_PER_CAND_SAMPLE * n * n_bin / (fms * 1e-3) / 1e12 / \

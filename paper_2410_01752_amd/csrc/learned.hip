@@ -36,7 +36,8 @@ constexpr int kH = 256;                                 // hidden units
 constexpr int kOffB1 = kH * kIn, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH;
 constexpr int kParams = kOffB2 + 1;
 constexpr int kTab = 5 * kH + kH + 1;                   // c_form rows, w2, b2
-constexpr int kPS = kH + 4;                             // LDS row stride of A / B rows
+constexpr int kPS = kH + 4;                             // row stride of FP32 rows
+constexpr int kPH = kH / 2 + 4;                         // LDS row stride of A / B rows (FP16 pairs)
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
@@ -398,15 +399,31 @@ __global__ void __launch_bounds__(256) k_mlp_tables(const float *__restrict__ P,
     if (j == 0) tab[6 * kH] = P[kOffB2];
 }
 
-// Network score of one candidate from its parts, in the fused kernel's order.
+// The network score is evaluated in packed FP16 (two hidden units per
+// instruction): the FP32 parts are rounded toward zero to FP16 pairs, then per
+// pair t = a + b, z = t + c_form, h = max(z, 0), and the FP32 score accumulates
+// h . w2 with a two-term dot product, pairs in ascending order.  The sampler
+// and the pruned kernel perform this same instruction sequence per candidate.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef __fp16 hp2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ h2 to_h2(float a, float b) { return __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(a, b)); }
+
+__device__ __forceinline__ float net_step(h2 a, h2 b, h2 c, h2 w, float acc)
+{
+    const h2 z = (a + b) + c;
+    const h2 h = __builtin_elementwise_max(z, (h2){(_Float16)0.0f, (_Float16)0.0f});
+    return __builtin_amdgcn_fdot2(__builtin_bit_cast(hp2, h), __builtin_bit_cast(hp2, w), acc, false);
+}
+
+// Network score of one candidate from its FP32 parts (sampler order).
 __device__ __forceinline__ float net_score(const float *__restrict__ a, const float *__restrict__ b,
                                            const float *__restrict__ c, const float *__restrict__ w2, float b2)
 {
     float acc = 0.f;
-    for (int j = 0; j < kH; ++j) {
-        const float z = (a[j] + b[j]) + c[j];
-        acc = fmaf(fmaxf(z, 0.f), w2[j], acc);
-    }
+    for (int j = 0; j < kH; j += 2)
+        acc = net_step(to_h2(a[j], a[j + 1]), to_h2(b[j], b[j + 1]), to_h2(c[j], c[j + 1]), to_h2(w2[j], w2[j + 1]),
+                       acc);
     return acc + b2;
 }
 
@@ -496,7 +513,7 @@ constexpr int kVS = 256;                      // v operands per work item
 constexpr int kKeptCap = 8192;                // kept-list entries per block
 constexpr int kSP = 32 + kVS + 4;             // LDS row stride of the staged chunk
 constexpr int kStageFloats = kSC * kSP + kSC; // staged u/v values + r
-constexpr int kRegion = kStageFloats > 32 * kPS ? kStageFloats : 32 * kPS;
+constexpr int kRegion = kStageFloats > 32 * kPH ? kStageFloats : 32 * kPH;   // floats (a pair is 4 bytes)
 
 template <int KPT>
 __global__ void __launch_bounds__(256) k_score_pruned(
@@ -508,21 +525,28 @@ __global__ void __launch_bounds__(256) k_score_pruned(
     void *ws, int lists_total, int keep, int cap, unsigned long long *__restrict__ kept_total)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    float *sA = (float *)smem;                 // 32 x kPS
-    float *sR = sA + 32 * kPS;                 // B rows of a sub-tile, or the staged chunk
-    float *sC = sR + kRegion;                  // 5 x kH form rows, then w2
-    unsigned short *kl = (unsigned short *)(sC + 6 * kH);
+    h2 *sA = (h2 *)smem;                       // 32 x kPH pairs
+    float *sR = (float *)(sA + 32 * kPH);      // B rows of a sub-tile (pairs), or the staged chunk
+    h2 *sB = (h2 *)sR;
+    h2 *sC = (h2 *)(sR + kRegion);             // 5 x kH/2 form rows, then w2
+    unsigned short *kl = (unsigned short *)(sC + 3 * kH);
     float *lsc = (float *)(kl + kKeptCap);
     int64_t *lid = (int64_t *)(lsc + cap);
-    __shared__ int lcnt, nkept;
+    __shared__ int lcnt, nkept, nuc, nvc;
     __shared__ float lthr;
+    // operand columns referenced by the kept list (bitmaps), and their compact
+    // staging order: u columns first, then v columns
+    __shared__ unsigned ubits, vbits[kVS / 32], vpre[kVS / 32];
+    __shared__ unsigned char umap[32], vmap[kVS];
+    __shared__ short clist[32 + kVS];
     WsView W = ws_view(ws, lists_total, keep);
     BlockList L{lsc, lid, &lcnt, &lthr, cap, keep};
     list_init(L);
 
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    for (int e = tid; e < 6 * kH; e += 256) sC[e] = tab[e];
-    if (tid == 0) nkept = 0;
+    for (int e = tid; e < 3 * kH; e += 256) sC[e] = to_h2(tab[2 * e], tab[2 * e + 1]);
+    if (tid == 0) { nkept = 0; ubits = 0u; }
+    if (tid < kVS / 32) vbits[tid] = 0u;
     const float b2 = tab[6 * kH], tau = *tau_p;
     const int Lv = s.levels;
     const int64_t vcount = s.pool[Lv - 1], ulo = s.pool[Lv - 1], uhi = s.pool[Lv];
@@ -536,6 +560,28 @@ __global__ void __launch_bounds__(256) k_score_pruned(
     // exact FP32 scores of the kept list of item (u0, vb, ve)
     auto exact = [&](int64_t u0, int64_t vb, int64_t ve) {
         const int nk = nkept;
+        // compact staging order of the referenced columns
+        if (tid == 0) {
+            unsigned acc = __popc(ubits);
+            nuc = (int)acc;
+            for (int w = 0; w < kVS / 32; ++w) { vpre[w] = acc; acc += __popc(vbits[w]); }
+            nvc = (int)acc - nuc;
+        }
+        __syncthreads();
+        if (tid < 32) {
+            const unsigned below = ubits & ((1u << tid) - 1u);
+            umap[tid] = (unsigned char)__popc(below);
+            if ((ubits >> tid) & 1u) clist[__popc(below)] = (short)tid;
+        }
+        if (tid < kVS) {
+            const int w = tid >> 5, b = tid & 31;
+            const unsigned below = vbits[w] & ((1u << b) - 1u);
+            const int rank = (int)vpre[w] + __popc(below);          // includes the u columns
+            vmap[tid] = (unsigned char)(rank - nuc);
+            if ((vbits[w] >> b) & 1u) clist[rank] = (short)(32 + tid);
+        }
+        __syncthreads();
+        const int ncols = nuc + nvc;
         if (tid == 0) kept_local += (unsigned long long)nk;
         float *St = sR;
         const float *Rr = sR + kSC * kSP;
@@ -559,8 +605,9 @@ __global__ void __launch_bounds__(256) k_score_pruned(
                 //   k < 2:  (x - mean_u) +- (y - mean_v)   (x = u, y = v)
                 //   k >= 2: fma(x, y', -c), (x, y') = (u, v), (u, 1/v), (v, 1/u) for k = 2, 3, 4
                 const bool sw = kf[i] == 4;
-                ax[i] = sw ? 32 + vl[i] : ul[i];
-                ay[i] = sw ? ul[i] : 32 + vl[i];
+                const int cu = umap[ul[i]], cv = nuc + vmap[vl[i]];
+                ax[i] = sw ? cv : cu;
+                ay[i] = sw ? cu : cv;
                 rc[i] = kf[i] >= 3;
                 ad[i] = kf[i] < 2;
                 sg[i] = kf[i] == 1 ? -1.0f : 1.0f;
@@ -585,8 +632,11 @@ __global__ void __launch_bounds__(256) k_score_pruned(
                     const int e = q * 256 + tid, col = e >> 3, quad = e & 7;
                     const int t0 = ch * kSC + quad * 4;
                     int64_t c = -1;
-                    if (col < 32) { if (u0 + col < uhi) c = u0 + col; }
-                    else if (col < 32 + kVS) { if (vb + (col - 32) < ve) c = vb + (col - 32); }
+                    if (col < ncols) {
+                        const int src = clist[col];
+                        if (src < 32) { if (u0 + src < uhi) c = u0 + src; }
+                        else if (vb + (src - 32) < ve) c = vb + (src - 32);
+                    }
                     pf[q] = (c >= 0 && t0 < n) ? *reinterpret_cast<const float4 *>(pool32 + (size_t)c * ld32 + t0)
                                                : make_float4(0, 0, 0, 0);
                 }
@@ -599,7 +649,7 @@ __global__ void __launch_bounds__(256) k_score_pruned(
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     const int e = q * 256 + tid, col = e >> 3, quad = e & 7;
-                    if (col < 32 + kVS) {
+                    if (col < ncols) {
                         St[(quad * 4 + 0) * kSP + col] = pf[q].x;
                         St[(quad * 4 + 1) * kSP + col] = pf[q].y;
                         St[(quad * 4 + 2) * kSP + col] = pf[q].z;
@@ -684,7 +734,8 @@ __global__ void __launch_bounds__(256) k_score_pruned(
             list_offer<KPT>(L, osc, oid, &W.h->gthr, excl, n_excl);
         }
         __syncthreads();
-        if (tid == 0) nkept = 0;
+        if (tid == 0) { nkept = 0; ubits = 0u; }
+        if (tid < kVS / 32) vbits[tid] = 0u;
         __syncthreads();
     };
 
@@ -699,7 +750,8 @@ __global__ void __launch_bounds__(256) k_score_pruned(
             const int64_t u = u0 + row;
             const float4 val = u < uhi ? reinterpret_cast<const float4 *>(Au + (size_t)(u - ulo) * kH)[q]
                                        : make_float4(0, 0, 0, 0);
-            *reinterpret_cast<float4 *>(sA + row * kPS + q * 4) = val;
+            sA[row * kPH + 2 * q] = to_h2(val.x, val.y);
+            sA[row * kPH + 2 * q + 1] = to_h2(val.z, val.w);
         }
         for (int64_t v0 = vb; v0 < ve; v0 += 32) {
             if (nkept > kKeptCap - 32 * 32 * 5) exact(u0, vb, ve);   // uniform: read after a barrier
@@ -709,7 +761,8 @@ __global__ void __launch_bounds__(256) k_score_pruned(
                 const int64_t v = v0 + row;
                 const float4 val = v < ve ? reinterpret_cast<const float4 *>(Bv + (size_t)v * kH)[q]
                                           : make_float4(0, 0, 0, 0);
-                *reinterpret_cast<float4 *>(sR + row * kPS + q * 4) = val;
+                sB[row * kPH + 2 * q] = to_h2(val.x, val.y);
+                sB[row * kPH + 2 * q + 1] = to_h2(val.z, val.w);
             }
             __syncthreads();
             float acc[2][2][5];
@@ -719,32 +772,28 @@ __global__ void __launch_bounds__(256) k_score_pruned(
                 for (int b = 0; b < 2; ++b)
 #pragma unroll
                     for (int k = 0; k < 5; ++k) acc[a][b][k] = 0.f;
-            for (int j = 0; j < kH; j += 4) {
-                const float4 A0 = *reinterpret_cast<const float4 *>(sA + (2 * ty) * kPS + j);
-                const float4 A1 = *reinterpret_cast<const float4 *>(sA + (2 * ty + 1) * kPS + j);
-                const float4 B0 = *reinterpret_cast<const float4 *>(sR + (2 * tx) * kPS + j);
-                const float4 B1 = *reinterpret_cast<const float4 *>(sR + (2 * tx + 1) * kPS + j);
-                const float4 w4 = *reinterpret_cast<const float4 *>(sC + 5 * kH + j);
-                float4 c4[5];
+            for (int jp = 0; jp < kH / 2; jp += 4) {
+                // four hidden-unit pairs of both u rows, both v rows, every form and w2
+                h2 A[2][4], B[2][4], C[5][4], Wv[4];
 #pragma unroll
-                for (int k = 0; k < 5; ++k) c4[k] = *reinterpret_cast<const float4 *>(sC + k * kH + j);
-                const float av[2][4] = {{A0.x, A0.y, A0.z, A0.w}, {A1.x, A1.y, A1.z, A1.w}};
-                const float bv[2][4] = {{B0.x, B0.y, B0.z, B0.w}, {B1.x, B1.y, B1.z, B1.w}};
-                const float wv[4] = {w4.x, w4.y, w4.z, w4.w};
+                for (int q = 0; q < 4; ++q) {
+                    A[0][q] = sA[(2 * ty) * kPH + jp + q];
+                    A[1][q] = sA[(2 * ty + 1) * kPH + jp + q];
+                    B[0][q] = sB[(2 * tx) * kPH + jp + q];
+                    B[1][q] = sB[(2 * tx + 1) * kPH + jp + q];
+                    Wv[q] = sC[5 * (kH / 2) + jp + q];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
+                    for (int k = 0; k < 5; ++k) C[k][q] = sC[k * (kH / 2) + jp + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) {
-                            const float t = av[a][e] + bv[b][e];
+                        for (int b = 0; b < 2; ++b)
 #pragma unroll
-                            for (int k = 0; k < 5; ++k) {
-                                const float ck = e == 0 ? c4[k].x : e == 1 ? c4[k].y : e == 2 ? c4[k].z : c4[k].w;
-                                acc[a][b][k] = fmaf(fmaxf(t + ck, 0.f), wv[e], acc[a][b][k]);
-                            }
-                        }
-                }
+                            for (int k = 0; k < 5; ++k)
+                                acc[a][b][k] = net_step(A[a][q], B[b][q], C[k][q], Wv[q], acc[a][b][k]);
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -758,6 +807,8 @@ __global__ void __launch_bounds__(256) k_score_pruned(
                         const int64_t fid = binbase + ((u - ulo) * vcount + v) * S + fs.slot[k];
                         if (fid < id_begin || fid >= id_end) continue;
                         const int slot = atomicAdd(&nkept, 1);
+                        atomicOr(&ubits, 1u << (2 * ty + a));
+                        atomicOr(&vbits[(int)(v - vb) >> 5], 1u << ((int)(v - vb) & 31));
                         kl[slot] = (unsigned short)((2 * ty + a) | ((int)(v - vb) << 5) | (k << 13));
                     }
                 }
@@ -798,7 +849,7 @@ constexpr int kPrunedKPT = 4;
 
 size_t pruned_smem(int cap)
 {
-    return (size_t)(32 * kPS + kRegion + 6 * kH) * sizeof(float) + (size_t)kKeptCap * sizeof(unsigned short) +
+    return (size_t)(32 * kPH + kRegion + 3 * kH) * sizeof(float) + (size_t)kKeptCap * sizeof(unsigned short) +
            (size_t)cap * (sizeof(float) + sizeof(int64_t));
 }
 
