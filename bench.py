@@ -229,13 +229,15 @@ def main():
     band = args.band
 
     if args.copy_calibration:
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB (a copy through
+        # the shader engines, so that rocprofv3 counters see it as a kernel)
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-        log("copy calibration: 3 x 1 GiB device copies")
+        log("copy calibration: 3 x 1 GiB elementwise copies")
 
     def ev_ms(tm, name):
         return [a.elapsed_time(b) for a, b in tm.get(name, [])]
