@@ -426,6 +426,15 @@ sisso_status sisso_mlp_score_ids(const sisso_space *space, const float *Au, cons
 /* *out_value (device) = the q-th largest of x[0..count) (NaN lowest). */
 sisso_status sisso_select_kth(const float *x, int32_t count, int32_t q, float *out_value, void *stream);
 
+/* Reliability of the proposal on a residual: given exact scores and network
+ * scores of the same uniform id sample, out[0] (device int32) receives the
+ * number of sample ids with exact score >= *exact_thr (e.g. the sample's 64th
+ * best, from sisso_select_kth) and out[1] how many of them have a network
+ * score >= *net_thr (the pruning threshold): out[1] / out[0] estimates the
+ * recall of the pruned screening for the top of the distribution. */
+sisso_status sisso_count_pass(const float *exact, const float *net, int32_t count, const float *exact_thr,
+                              const float *net_thr, int32_t *out, void *stream);
+
 /* Pruned screening of the slice's binary block over [cand_begin, cand_end):
  * candidates whose network score is >= *tau (device) are scored exactly and
  * enter the per-block lists of ws as in sisso_expand_score (list_base, grid

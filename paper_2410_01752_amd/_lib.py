@@ -129,6 +129,7 @@ def lib():
         "sisso_mlp_score_ids": (_i32, [sp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
         "sisso_select_kth": (_i32, [_vp, _i32, _i32, _vp, _vp]),
         "sisso_expand_score_pruned_lists": (_i32, [sp, ap, _i64, _i64]),
+        "sisso_count_pass": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
         "sisso_expand_score_pruned": (_i32, [sp, ap, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _sz, _vp, _vp]),
         "sisso_status_string": (ctypes.c_char_p, [_i32]),
         "sisso_version": (ctypes.c_char_p, []),
@@ -153,7 +154,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_mlp_param_count", "sisso_mlp_table_count", "sisso_encode_operands", "sisso_candidate_inputs",
             "sisso_score_ids", "sisso_mlp_forward", "sisso_mlp_workspace_size", "sisso_mlp_backward",
             "sisso_adam_step", "sisso_mlp_parts", "sisso_mlp_tables", "sisso_mlp_score_ids", "sisso_select_kth",
-            "sisso_expand_score_pruned_lists", "sisso_expand_score_pruned",
+            "sisso_expand_score_pruned_lists", "sisso_expand_score_pruned", "sisso_count_pass",
             "sisso_status_string", "sisso_version"]
 
 

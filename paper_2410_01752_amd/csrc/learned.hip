@@ -451,6 +451,30 @@ __global__ void __launch_bounds__(256) k_mlp_score_ids(sisso_space s, FormSlots 
     out[q] = sc;
 }
 
+// Tail agreement of the proposal on a uniform sample: out[0] = number of
+// sample ids whose exact score is >= *exact_thr, out[1] = how many of those
+// have a network score >= *net_thr (one block; deterministic integer counts).
+__global__ void __launch_bounds__(1024) k_count_pass(const float *__restrict__ exact, const float *__restrict__ net,
+                                                     int count, const float *__restrict__ exact_thr,
+                                                     const float *__restrict__ net_thr, int32_t *__restrict__ out)
+{
+    __shared__ int c0, c1;
+    if (threadIdx.x == 0) { c0 = 0; c1 = 0; }
+    __syncthreads();
+    const float te = *exact_thr, tn = *net_thr;
+    int a = 0, b = 0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        if (exact[i] >= te && exact[i] >= 0.0f) {
+            ++a;
+            if (net[i] >= tn) ++b;
+        }
+    }
+    atomicAdd(&c0, a);
+    atomicAdd(&c1, b);
+    __syncthreads();
+    if (threadIdx.x == 0) { out[0] = c0; out[1] = c1; }
+}
+
 // Order-preserving key of a float (NaN lowest).
 __device__ __forceinline__ unsigned fkey(float f)
 {
@@ -1047,5 +1071,15 @@ extern "C" sisso_status sisso_expand_score_pruned(const sisso_space *space, cons
                        args->n, args->pool32, args->ld32, args->stats, args->r32, args->info, args->exclude,
                        args->n_exclude, Au, Bv, tables, tau, p.ut_lo, p.ut_hi, cand_begin, cand_end, args->list_base,
                        ws, lists, args->keep, cap, kept);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_count_pass(const float *exact, const float *net, int32_t count, const float *exact_thr,
+                                         const float *net_thr, int32_t *out, void *stream)
+{
+    if (!exact || !net || !exact_thr || !net_thr || !out) return SISSO_E_NULL;
+    if (count < 1) return SISSO_E_SHAPE;
+    hipLaunchKernelGGL(k_count_pass, dim3(1), dim3(1024), 0, as_stream(stream), exact, net, count, exact_thr, net_thr,
+                       out);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }

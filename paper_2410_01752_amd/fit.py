@@ -169,12 +169,12 @@ class Engine:
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev1 = torch.cuda.Event(enable_timing=True)
                 ev0.record()
+            fallback = None
             if name == "binary" and use_learned:
                 pr, (frac, n_sample, seed) = self.pruner, self.pruner_cfg
                 steps = [("learned_prepare", lambda: pr.prepare(r64)),
                          ("learned_threshold", lambda: pr.threshold(frac, n_sample, seed)),
-                         ("learned_screen", lambda: pr.screen_binary(a, ws, b, e))]
-                nl = 0
+                         ("learned_check", lambda: pr.tail_recall(seed=seed + 1))]
                 for sname, call in steps:
                     if events is not None:
                         s0 = torch.cuda.Event(enable_timing=True)
@@ -184,10 +184,25 @@ class Engine:
                     if events is not None:
                         s1.record()
                         events.setdefault(sname, []).append((s0, s1))
-                    if sname == "learned_screen":
-                        nl = res
-                # the residual was re-prepared by the encoder; the lists are complete
-            elif name == "binary" and use_bf16:
+                tail_n, tail_pass = res
+                self.learned_log.append((tail_n, tail_pass))
+                if tail_n > 0 and tail_pass < self.pruner_min_recall * tail_n:
+                    # the proposal does not rank this residual's top: screen exhaustively
+                    fallback = self.pruner_fallback
+                    self.prepare_residual(r64)
+                    if fallback == "bf16":
+                        self.prepare_bf16()
+                        band = max(min(band or 4 * keep, L.MAX_KEEP), keep)
+                else:
+                    if events is not None:
+                        s0 = torch.cuda.Event(enable_timing=True)
+                        s1 = torch.cuda.Event(enable_timing=True)
+                        s0.record()
+                    nl = pr.screen_binary(a, ws, b, e)
+                    if events is not None:
+                        s1.record()
+                        events.setdefault("learned_screen", []).append((s0, s1))
+            if name == "binary" and (use_bf16 or fallback == "bf16"):
                 nb = L.lib().sisso_bf16_workspace_size(ctypes.byref(self.space), ctypes.byref(a), band)
                 bws = self._workspace("bf16", nb)
                 sp_, a_ = ctypes.byref(self.space), ctypes.byref(a)
@@ -209,7 +224,7 @@ class Engine:
                         s1.record()
                         events.setdefault(sname, []).append((s0, s1))
                 nl = L.lib().sisso_expand_score_bf16_lists(ctypes.byref(self.space), ctypes.byref(a), band)
-            else:
+            elif not (name == "binary" and use_learned and fallback is None):
                 L.check(L.lib().sisso_expand_score(ctypes.byref(self.space), ctypes.byref(a), b, e,
                                                    L.ptr(ws), ws.numel(), st), "sisso_expand_score")
                 nl = L.lib().sisso_expand_score_lists(ctypes.byref(self.space), ctypes.byref(a), b, e)
@@ -243,11 +258,18 @@ class Engine:
                 "sisso_materialize_ids")
         return out.view(count, self.n), valid
 
-    def set_pruner(self, pruner, frac: float = 0.05, n_sample: int = 1 << 20, seed: int = 0):
+    def set_pruner(self, pruner, frac: float = 0.05, n_sample: int = 1 << 20, seed: int = 0,
+                   min_recall: float = 0.99, fallback: str = "fp32"):
         """Learned screening of the slice's binary block (precision="learned"):
-        only candidates the network ranks in the top `frac` are scored exactly."""
+        only candidates the network ranks in the top `frac` are scored exactly.
+        Before each pass the proposal's recall of the exact top of a uniform
+        sample is measured; below `min_recall` the pass screens exhaustively
+        with the `fallback` form ("fp32" or "bf16")."""
         self.pruner = pruner
         self.pruner_cfg = (frac, n_sample, seed)
+        self.pruner_min_recall = min_recall
+        self.pruner_fallback = fallback
+        self.learned_log = []
 
     # ----------------------------------------------------------------- fit
     def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10,

@@ -174,6 +174,7 @@ class Pruner:
     def prepare(self, r64: torch.Tensor):
         """Encodings and first-layer parts for residual r64."""
         eng, lib, st = self.eng, L.lib(), self.eng.stream()
+        self._r64 = r64
         self.enc = encode(eng, r64)
         L.check(lib.sisso_mlp_parts(L.ptr(self.P), L.ptr(self.enc[self.ulo:]), self.uhi - self.ulo, 0,
                                     L.ptr(self.Au), st), "sisso_mlp_parts")
@@ -195,6 +196,23 @@ class Pruner:
         L.check(L.lib().sisso_select_kth(L.ptr(sc), n_sample, q, L.ptr(self.tau), self.eng.stream()),
                 "sisso_select_kth")
         return self.tau
+
+    def tail_recall(self, n_sample: int = 1 << 18, top: int = 64, seed: int = 1) -> Tuple[int, int]:
+        """(n, passing): of the `top` best exactly scored ids of a uniform
+        sample, how many pass the current threshold (needs prepare and a
+        threshold).  passing / n estimates the recall of the pruned pass."""
+        eng, lib, st = self.eng, L.lib(), self.eng.stream()
+        ids = torch.from_numpy(sample_ids(eng, n_sample, seed)).to(eng.dev)
+        eng.prepare_residual(self._r64)
+        ex = score_ids(eng, ids)
+        net = self.net_scores(ids)
+        thr = torch.empty(1, dtype=torch.float32, device=eng.dev)
+        L.check(lib.sisso_select_kth(L.ptr(ex), n_sample, top, L.ptr(thr), st), "sisso_select_kth")
+        out = torch.zeros(2, dtype=torch.int32, device=eng.dev)
+        L.check(lib.sisso_count_pass(L.ptr(ex), L.ptr(net), n_sample, L.ptr(thr), L.ptr(self.tau), L.ptr(out), st),
+                "sisso_count_pass")
+        o = out.cpu().numpy()
+        return int(o[0]), int(o[1])
 
     def set_threshold(self, value: float):
         self.tau.fill_(value)

@@ -279,7 +279,7 @@ def test_trained_network_beats_operand_heuristic_and_random():
         c = int(cnt.item())
         ref_ids, ref_sc = ref_ids[:c], ref_sc[:c].cpu().numpy()
         pr = LN.Pruner(eng, params)
-        eng.set_pruner(pr, frac=frac, n_sample=1 << 16, seed=3)
+        eng.set_pruner(pr, frac=frac, n_sample=1 << 16, seed=3, min_recall=0.0)   # measure the network itself
         gi, gs, gc = eng.screen(r64, keep, None, begin=eng.binary_base(), precision="learned")
         torch.cuda.synchronize()
         rec_net.append(LN.recall_of(ref_ids.cpu().numpy(), ref_sc, gi[:int(gc.item())].cpu().numpy()))
@@ -296,3 +296,22 @@ def test_trained_network_beats_operand_heuristic_and_random():
     print(f"  recall at {frac:.0%}: network {rec_net}, heuristic {rec_heur}, random {frac}", flush=True)
     assert np.mean(rec_net) > np.mean(rec_heur)
     assert np.mean(rec_net) > 3 * frac
+
+
+def test_learned_falls_back_when_the_proposal_misses_the_top():
+    """An untrained network ranks at random: the tail check detects it and the
+    pass is screened exhaustively (the result equals plain FP32 screening)."""
+    p = I.tiny(14, n=200, d=5, dist="lognormal", rect=True)
+    eng = _engine(p)
+    eng.set_pruner(_pruner(eng, 44), frac=0.02, n_sample=1 << 14, seed=5, min_recall=0.99)
+    r64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+    keep = 300
+    gi, gs, gc = eng.screen(r64, keep, None, begin=eng.binary_base(), precision="learned")
+    fi, fs, fc = eng.screen(r64, keep, None, begin=eng.binary_base(), precision="fp32")
+    torch.cuda.synchronize()
+    n, passing = eng.learned_log[-1]
+    print(f"  tail check: {passing}/{n} pass", flush=True)
+    assert n > 0 and passing < 0.99 * n
+    c = int(fc.item())
+    assert int(gc.item()) == c
+    assert torch.equal(gi[:c], fi[:c]) and torch.equal(gs[:c], fs[:c])
