@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(256) k_score_batch(sisso_space s, FormSlots fs
     using Cfg = RectCfg<2, 2>;
     constexpr int PER = 1 + NU;
     constexpr int NC = (kBatchCols * PER + 255) / 256;
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     float *buf0 = (float *)smem;
     float *buf1 = buf0 + Cfg::BUF;
     float *lsc = buf1 + Cfg::BUF;
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(1024) k_topk_batch(const sisso_problem *__rest
     __shared__ unsigned hist[kHistBins];
     __shared__ unsigned s_prefix;
     __shared__ int s_need, s_total, s_m;
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     float *fsc = (float *)smem;
     int64_t *fid = (int64_t *)(smem + kBatchFinalCap * sizeof(float));
 

@@ -35,7 +35,10 @@ constexpr int kVVar = 8;      // V~, V~ r, P, Q, W~, W~ r, Pw, Qw
 constexpr int kSplit = 2;     // BF16 parts per operand (hi, lo)
 constexpr int kBT = 64;       // (u, v) pairs per block side: 2 x 2 waves of 32 x 32
 constexpr int kKC = 16;       // samples per LDS stage (one MFMA k-step)
-constexpr int kKP = kKC + 8;  // padded LDS row (bf16)
+constexpr int kKR = kKC;       // bf16 per LDS row: one chunk of samples of one column
+constexpr int kPlane = kBT * kKR;                   // bf16 per staged plane (64 columns)
+constexpr int kPA = kUVar * kSplit, kPB = kVVar * kSplit;   // staged planes per side
+constexpr int kStage = (kPA + kPB) * kPlane;        // bf16 per staging buffer
 constexpr int kNG = 12;       // GEMMs per tile
 
 // GEMM g multiplies u-side variant A(g) with v-side variant B(g):
@@ -89,6 +92,16 @@ __host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols
 }
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// Element offset of samples k .. k + 3 (k % 4 == 0) of column `row` in a staged
+// plane.  The two 8-sample halves of a row are swapped on rows whose bits 2 and
+// 3 differ, so that the fragment reads (16 bytes of 32 consecutive rows) and
+// the staging stores (8 bytes, 4 columns x 4 quads per 16 lanes) fall into
+// distinct banks.
+__device__ __forceinline__ int lds_off(int row, int k)
+{
+    return row * kKR + (k ^ ((((row >> 2) ^ (row >> 3)) & 1) << 3));
+}
 
 // ---------------------------------------------------------------- operands
 
@@ -184,12 +197,9 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
     int64_t ut_hi, int64_t id_begin, int64_t id_end, void *lws, int lists_total, int keep, int cap)
 {
-    extern __shared__ unsigned char smem[];
-    constexpr int AV = kUVar * kSplit, BV = kVVar * kSplit;   // staged matrices per side
-    constexpr int ASZ = AV * kBT * kKP, BSZ = BV * kBT * kKP;
-    __bf16 *const sA = reinterpret_cast<__bf16 *>(smem);
-    __bf16 *const sB = sA + ASZ;
-    float *lsc = (float *)(sB + BSZ);
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // two staging buffers
+    float *lsc = (float *)(stage + 2 * kStage);
     int64_t *lid = (int64_t *)(lsc + cap);
     __shared__ int lcnt;
     __shared__ float lthr;
@@ -208,6 +218,11 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     const int64_t nvt = (vcount + kBT - 1) / kBT;
     // staging role: column scol of the u and v tiles, samples 4 squad .. 4 squad + 3 of a chunk
     const int scol = tid >> 2, squad = tid & 3;
+    const int tmax = ((n - 1) >> 2) << 2;        // last 4-aligned sample start: loads stay inside the column
+    const int sto = lds_off(scol, squad * 4);     // staging store offset within a plane
+    // fragment role: lane reads 8 samples (koff ..) of row lane % 32 of its wave's 32-row half
+    const int koff = (lane >> 5) * 8;
+    const int fa = lds_off(wu * 32 + (lane & 31), koff), fb = lds_off(wv * 32 + (lane & 31), koff);
 
     for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
         const int64_t u0 = ut * kBT;   // index into the newest level
@@ -215,7 +230,6 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
         const bool su_ok = su < ucols;
         const float4 us_c = usum[su_ok ? su : 0];
         const float smu = us_c.x, smz = us_c.y;
-        const bool szok = su_ok && stats[ulo + su].minabs > 0.0f;
         const float *ucol = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
         for (int64_t vt = 0; vt < nvt; ++vt) {
             const int64_t v0 = vt * kBT;
@@ -223,23 +237,27 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
             const bool sv_ok = sv < vcount;
             const float4 vs_c = vsum[2 * (sv_ok ? sv : 0)];
             const float smv = vs_c.x, smw = vs_c.y;
-            const bool swok = sv_ok && stats[sv_ok ? sv : 0].minabs > 0.0f;
             const float *vcol = pool32 + (size_t)(sv_ok ? sv : 0) * ld32;
             f32x16 acc[kNG];
 #pragma unroll
             for (int g = 0; g < kNG; ++g)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
-            // raw FP32 operands and residual of one chunk (register prefetch); the
-            // centred variants and their BF16 hi/lo parts are formed when staged
+            // Raw FP32 values of one chunk are loaded two chunks ahead into
+            // registers; the centred variants and their BF16 hi/lo parts are formed
+            // and stored into the other staging buffer while the MFMAs of the
+            // current chunk run.  Out-of-range columns stage finite values of
+            // column 0 (their rows and columns are dropped by the epilogue); a
+            // zero in a column gives infinite reciprocal variants, which reach
+            // only the accumulators of the form whose domain excludes it.
             float4 pu, pv, pr;
-            auto load_chunk = [&](int ch) {
-                const int t0 = ch * kKC + squad * 4;
-                pu = su_ok && t0 < n ? *reinterpret_cast<const float4 *>(ucol + t0) : make_float4(0, 0, 0, 0);
-                pv = sv_ok && t0 < n ? *reinterpret_cast<const float4 *>(vcol + t0) : make_float4(0, 0, 0, 0);
-                pr = t0 < n ? *reinterpret_cast<const float4 *>(r32 + t0) : make_float4(0, 0, 0, 0);
+            auto load_chunk = [&](int ch, float4 &xu4, float4 &xv4, float4 &xr4) {
+                const int t0 = min(ch * kKC + squad * 4, tmax);
+                xu4 = *reinterpret_cast<const float4 *>(ucol + t0);
+                xv4 = *reinterpret_cast<const float4 *>(vcol + t0);
+                xr4 = *reinterpret_cast<const float4 *>(r32 + t0);
             };
-            auto store_chunk = [&](int ch) {
+            auto store_chunk = [&](int ch, __bf16 *buf, bool tail) {
                 const int t0 = ch * kKC + squad * 4;
                 const float xu[4] = {pu.x, pu.y, pu.z, pu.w};
                 const float xv[4] = {pv.x, pv.y, pv.z, pv.w};
@@ -247,17 +265,18 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                 float ua[kUVar][4], va[kVVar][4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const bool live = t0 + e < n;
-                    const float uu = live && su_ok ? xu[e] - smu : 0.f;
-                    const float zz = live && szok ? __builtin_amdgcn_rcpf(xu[e]) - smz : 0.f;
+                    const float ru = __builtin_amdgcn_rcpf(xu[e]), rv = __builtin_amdgcn_rcpf(xv[e]);
+                    float uu = xu[e] - smu, zz = ru - smz, vv = xv[e] - smv, ww = rv - smw, r = xr[e];
+                    if (tail) {                       // samples past n contribute nothing
+                        const bool live = t0 + e < n;
+                        uu = live ? uu : 0.f; zz = live ? zz : 0.f;
+                        vv = live ? vv : 0.f; ww = live ? ww : 0.f; r = live ? r : 0.f;
+                    }
                     ua[0][e] = uu; ua[1][e] = uu * uu; ua[2][e] = zz; ua[3][e] = zz * zz;
-                    const float vv = live && sv_ok ? xv[e] - smv : 0.f;
-                    const float ww = live && swok ? __builtin_amdgcn_rcpf(xv[e]) - smw : 0.f;
-                    const float r = live ? xr[e] : 0.f;
                     va[0][e] = vv; va[1][e] = vv * r; va[2][e] = vv * (vv + 2.f * smv); va[3][e] = vv * (vv + smv);
                     va[4][e] = ww; va[5][e] = ww * r; va[6][e] = ww * (ww + 2.f * smw); va[7][e] = ww * (ww + smw);
                 }
-                auto put = [&](__bf16 *base, int var, const float (&x)[4]) {
+                auto put = [&](__bf16 *plane, const float (&x)[4]) {
                     // hi = bf16(x), lo = bf16(x - hi), two values per conversion
                     const bf16x2 h01 = __builtin_convertvector((f32x2){x[0], x[1]}, bf16x2);
                     const bf16x2 h23 = __builtin_convertvector((f32x2){x[2], x[3]}, bf16x2);
@@ -270,34 +289,24 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                     __builtin_memcpy(&ph.y, &h23, 4);
                     __builtin_memcpy(&pl.x, &l01, 4);
                     __builtin_memcpy(&pl.y, &l23, 4);
-                    *reinterpret_cast<uint2 *>(base + ((var * kSplit + 0) * kBT + scol) * kKP + squad * 4) = ph;
-                    *reinterpret_cast<uint2 *>(base + ((var * kSplit + 1) * kBT + scol) * kKP + squad * 4) = pl;
+                    *reinterpret_cast<uint2 *>(plane + sto) = ph;
+                    *reinterpret_cast<uint2 *>(plane + kPlane + sto) = pl;
                 };
 #pragma unroll
-                for (int q = 0; q < kUVar; ++q) put(sA, q, ua[q]);
+                for (int q = 0; q < kUVar; ++q) put(buf + (q * kSplit) * kPlane, ua[q]);
 #pragma unroll
-                for (int q = 0; q < kVVar; ++q) put(sB, q, va[q]);
+                for (int q = 0; q < kVVar; ++q) put(buf + (kPA + q * kSplit) * kPlane, va[q]);
             };
-            // software pipeline: the MFMAs of chunk ch run from fragments held in
-            // registers while the same waves form and stage chunk ch + 1
+            // GEMM g: u-side variant GA[g], v-side variant GB[g]; terms hi*hi, hi*lo, lo*hi
             constexpr int GA[kNG] = {0, 0, 1, 0, 0, 0, 1, 0, 2, 2, 3, 2};
             constexpr int GB[kNG] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3};
-            const int koff = (lane >> 5) * 8;
-            __syncthreads();                          // the previous tile's fragments are read
-            load_chunk(0);
-            store_chunk(0);
-            __syncthreads();
-            if (nch > 1) load_chunk(1);
-            for (int ch = 0; ch < nch; ++ch) {
-                bf16x8 af[AV], bfr[BV];
+            auto mfma_chunk = [&](const __bf16 *buf) {
+                bf16x8 af[kPA], bfr[kPB];
 #pragma unroll
-                for (int a = 0; a < AV; ++a)
-                    af[a] = *reinterpret_cast<const bf16x8 *>(sA + (a * kBT + wu * 32 + (lane & 31)) * kKP + koff);
+                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const bf16x8 *>(buf + a * kPlane + fa);
 #pragma unroll
-                for (int q = 0; q < BV; ++q)
-                    bfr[q] = *reinterpret_cast<const bf16x8 *>(sB + (q * kBT + wv * 32 + (lane & 31)) * kKP + koff);
-                __syncthreads();                      // every wave holds chunk ch: LDS is free
-                // GEMM g: u-side variant GA[g], v-side variant GB[g]; terms hi*hi, hi*lo, lo*hi
+                for (int q = 0; q < kPB; ++q)
+                    bfr[q] = *reinterpret_cast<const bf16x8 *>(buf + (kPA + q) * kPlane + fb);
 #pragma unroll
                 for (int term = 0; term < 3; ++term) {
                     const int pa_ = term == 2 ? 1 : 0, pb_ = term == 1 ? 1 : 0;
@@ -306,12 +315,41 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                         acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[GA[g] * kSplit + pa_],
                                                                          bfr[GB[g] * kSplit + pb_], acc[g], 0, 0, 0);
                 }
-                if (ch + 1 < nch) {
-                    store_chunk(ch + 1);              // VALU work beside the MFMAs above
-                    __syncthreads();
-                    if (ch + 2 < nch) load_chunk(ch + 2);
+            };
+            // interleave: fragment reads first, then each MFMA followed by a share of
+            // the staging work of the next chunk (VALU and LDS stores)
+            auto interleave = [&]() {
+                __builtin_amdgcn_sched_group_barrier(0x100, kPA + kPB, 0);   // LDS reads
+                __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);           // global loads
+#pragma unroll
+                for (int i = 0; i < 3 * kNG; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);       // VALU
+                    if (i % 3 == 2) __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);   // LDS stores
                 }
+            };
+            __syncthreads();                          // the previous tile's fragment reads are done
+            load_chunk(0, pu, pv, pr);
+            store_chunk(0, stage, nch == 1);
+            load_chunk(1, pu, pv, pr);
+            __syncthreads();
+            int ch = 0;
+            for (; ch + 2 < nch; ++ch) {              // chunk ch + 1 is full
+                float4 qu, qv, qr;
+                load_chunk(ch + 2, qu, qv, qr);
+                mfma_chunk(stage + (ch & 1) * kStage);
+                store_chunk(ch + 1, stage + ((ch + 1) & 1) * kStage, false);
+                interleave();
+                pu = qu; pv = qv; pr = qr;
+                __syncthreads();
             }
+            if (ch + 1 < nch) {                       // chunk ch + 1 is the last one
+                mfma_chunk(stage + (ch & 1) * kStage);
+                store_chunk(ch + 1, stage + ((ch + 1) & 1) * kStage, true);
+                __syncthreads();
+                ++ch;
+            }
+            mfma_chunk(stage + (ch & 1) * kStage);
 
             // epilogue: lane holds column j = lane % 32 and rows
             // i = 8 (r / 4) + 4 (lane / 32) + (r % 4) of each 32 x 32 result
@@ -412,7 +450,7 @@ __global__ void __launch_bounds__(256) k_rescore_ids(sisso_space s, FormSlots fs
                                                      const int64_t *__restrict__ excl, int n_excl, int list_base,
                                                      void *ws, int lists_total, int keep, int cap)
 {
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     float *lsc = (float *)smem;
     int64_t *lid = (int64_t *)(smem + cap * sizeof(float));
     __shared__ int lcnt;
@@ -588,7 +626,7 @@ extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_
     const int lcap = bf_lists_cap(space);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)(kUVar + kVVar) * kSplit * kBT * kKP * sizeof(__bf16) +
+        const size_t smem = (size_t)2 * kStage * sizeof(__bf16) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16, smem)) return SISSO_E_UNSUPPORTED;
         hipLaunchKernelGGL(k_score_rect_bf16, dim3(p.grid), dim3(256), smem, st, *space, fs, n, args->pool32,

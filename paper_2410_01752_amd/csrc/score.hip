@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_score_columns(
     int64_t c_lo, int64_t c_hi, int64_t id_begin, int64_t id_end, int list_base, void *ws,
     int lists_total, int keep, int cap)
 {
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     WsView W = ws_view(ws, lists_total, keep);
     float *lsc = (float *)smem;
     int64_t *lid = (int64_t *)(smem + cap * sizeof(float));
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) k_score_rect(
 {
     using Cfg = RectCfg<RU, RV>;
     constexpr int TU = Cfg::TU, TV = Cfg::TV;
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     float *buf0 = (float *)smem;
     float *buf1 = buf0 + Cfg::BUF;
     float *lsc = buf1 + Cfg::BUF;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(1024) k_tk_final(void *ws, int k, int allow_ab
                                                    int64_t *__restrict__ out_ids, float *__restrict__ out_sc,
                                                    int32_t *out_count)
 {
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     WsView W = ws_view_dev(ws);
     if (k > kFinalCap || (!allow_above_keep && k > W.h->keep)) {
         // k larger than the list length the workspace was filled with

@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(1024) k_sub_classes(int m_prev, int nodes, con
                                                       int64_t *__restrict__ sub_ids, int k, int32_t *n_new,
                                                       int32_t *n_classes, int *__restrict__ new_src, SubWs w)
 {
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     int *label = (int *)smem;                                   // nodes
     unsigned long long *rep = (unsigned long long *)(label + ((nodes + 1) & ~1));   // min id per root
     unsigned long long *best = rep + nodes;                     // max score bits per root
