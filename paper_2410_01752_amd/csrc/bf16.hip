@@ -201,6 +201,9 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // two staging buffers
     float *lsc = (float *)(stage + 2 * kStage);
     int64_t *lid = (int64_t *)(lsc + cap);
+    // u-tile column constants for the epilogue: (mean u, mean 1/u, sum u~^2,
+    // sum z~^2) and (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero)
+    float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBT;
     __shared__ int lcnt;
     __shared__ float lthr;
     WsView W = ws_view(lws, lists_total, keep);
@@ -231,6 +234,16 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
         const float4 us_c = usum[su_ok ? su : 0];
         const float smu = us_c.x, smz = us_c.y;
         const float *ucol = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
+        // (the previous tile's epilogue has passed a barrier after its last read)
+        if (tid < kBT) {
+            const int64_t x = u0 + tid;
+            const bool in = x < ucols;
+            const sisso_colstat cs = stats[ulo + (in ? x : 0)];
+            const float2 b = ures[in ? x : 0];
+            ucon_a[tid] = usum[in ? x : 0];
+            ucon_b[tid] = make_float4(b.x, b.y, cs.rms,
+                                      (in && cs.valid != 0.0f ? 1.0f : 0.0f) + (cs.minabs > 0.0f ? 2.0f : 0.0f));
+        }
         for (int64_t vt = 0; vt < nvt; ++vt) {
             const int64_t v0 = vt * kBT;
             const int64_t sv = v0 + scol;
@@ -359,17 +372,15 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
             const sisso_colstat vst = stats[vin ? v : 0];
             const float4 vs0 = vsum[2 * (vin ? v : 0)], vs1 = vsum[2 * (vin ? v : 0) + 1];
             const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w, Svr = vs1.x, Swr = vs1.y, vrm = vs1.z;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            const float fn = (float)n, rr = (float)(R1 / nd);
+            // approximate scores of the five forms of row r of this lane
+            auto row_scores = [&](int r, float (&sc)[5], int64_t (&fid)[5]) {
                 const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int64_t uix = u0 + wu * 32 + i;
-                const bool uin = uix < ucols;
-                const sisso_colstat ust = stats[ulo + (uin ? uix : 0)];
-                const float4 us = usum[uin ? uix : 0];
-                const float2 ur = ures[uin ? uix : 0];
-                const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w, Sur = ur.x, Szr = ur.y;
-                const bool ok = uin && vin && ust.valid != 0.0f && vst.valid != 0.0f;
-                const float fn = (float)n, rr = (float)(R1 / nd);
+                const float4 us = ucon_a[wu * 32 + i], ub = ucon_b[wu * 32 + i];
+                const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w, Sur = ub.x, Szr = ub.y;
+                const int uflags = (int)ub.w;
+                const bool ok = (uflags & 1) && vin && vst.valid != 0.0f;
                 const float g0 = acc[0][r];
                 float cov[5], var[5];
                 var[0] = Suu + Svv + 2.0f * g0;                     // u + v
@@ -394,10 +405,8 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                     var[4] = s2 - s1 * s1 / fn;
                     cov[4] = acc[9][r] + mv * Szr + mz * Svr - s1 * rr;
                 }
-                const bool dom[5] = {true, true, true, vst.minabs > 0.f, ust.minabs > 0.f};
-                const float scale = fmaxf(ust.rms, vrm);
-                float sc[5];
-                int64_t fid[5];
+                const bool dom[5] = {true, true, true, vst.minabs > 0.f, (uflags & 2) != 0};
+                const float scale = fmaxf(ub.z, vrm);
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
                     sc[k] = -1.0f;
@@ -413,6 +422,27 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                         }
                     }
                 }
+            };
+            // Count this lane's candidates at or above the admission bound (the
+            // bounds only rise, so a stale read admits more, never fewer).  Once
+            // the lists are full almost no tile has one, and the tile is done
+            // after a single barrier.
+            const float tb = fmaxf(*Lst.thr, load_gthr(&W.h->gthr));
+            int mine = 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                float sc[5];
+                int64_t fid[5];
+                row_scores(r, sc, fid);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) mine += (sc[k] >= 0.0f && sc[k] >= tb) ? 1 : 0;
+            }
+            if (!__syncthreads_or(mine)) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                float sc[5];
+                int64_t fid[5];
+                row_scores(r, sc, fid);
                 // insert this row's candidates: all five forms at once when the list
                 // has room for a full row of the block, else form by form with merges
                 __syncthreads();
@@ -626,7 +656,7 @@ extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_
     const int lcap = bf_lists_cap(space);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)2 * kStage * sizeof(__bf16) +
+        const size_t smem = (size_t)2 * kStage * sizeof(__bf16) + 2 * kBT * sizeof(float4) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16, smem)) return SISSO_E_UNSUPPORTED;
         hipLaunchKernelGGL(k_score_rect_bf16, dim3(p.grid), dim3(256), smem, st, *space, fs, n, args->pool32,
