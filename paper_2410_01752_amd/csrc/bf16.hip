@@ -204,10 +204,11 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     // u-tile column constants for the epilogue: (mean u, mean 1/u, sum u~^2,
     // sum z~^2) and (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero)
     float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBT;
-    __shared__ int lcnt;
+    __shared__ int lcnt, lpend;
     __shared__ float lthr;
     WsView W = ws_view(lws, lists_total, keep);
     BlockList Lst{lsc, lid, &lcnt, &lthr, cap, keep};
+    if (threadIdx.x == 0) lpend = 0;
     list_init(Lst);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -234,7 +235,7 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
         const float4 us_c = usum[su_ok ? su : 0];
         const float smu = us_c.x, smz = us_c.y;
         const float *ucol = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
-        // (the previous tile's epilogue has passed a barrier after its last read)
+        __syncthreads();                              // the previous tile's epilogue reads are done
         if (tid < kBT) {
             const int64_t x = u0 + tid;
             const bool in = x < ucols;
@@ -342,6 +343,7 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                 }
             };
             __syncthreads();                          // the previous tile's fragment reads are done
+            if (tid == 0) lpend = 0;                  // every thread has read the previous total
             load_chunk(0, pu, pv, pr);
             store_chunk(0, stage, nch == 1);
             load_chunk(1, pu, pv, pr);
@@ -424,27 +426,60 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                 }
             };
             // Count this lane's candidates at or above the admission bound (the
-            // bounds only rise, so a stale read admits more, never fewer).  Once
-            // the lists are full almost no tile has one, and the tile is done
-            // after a single barrier.
+            // bounds only rise, so a stale read admits more, never fewer) and
+            // not excluded, and the block's total.  When they all fit into the
+            // list, every thread reserves its slots with one atomic and writes
+            // them: no per-row barriers.
             const float tb = fmaxf(*Lst.thr, load_gthr(&W.h->gthr));
+            auto admit = [&](float sc, int64_t id) {
+                return sc >= 0.0f && sc >= tb && (n_excl == 0 || !in_sorted_ids(excl, n_excl, id));
+            };
             int mine = 0;
+            unsigned rows = 0;                        // bit r: row r has an admitted candidate
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 float sc[5];
                 int64_t fid[5];
                 row_scores(r, sc, fid);
+                int c = 0;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) mine += (sc[k] >= 0.0f && sc[k] >= tb) ? 1 : 0;
+                for (int k = 0; k < 5; ++k) c += admit(sc[k], fid[k]) ? 1 : 0;
+                mine += c;
+                rows |= (c ? 1u : 0u) << r;
             }
-            if (!__syncthreads_or(mine)) continue;
+            if (mine) atomicAdd(&lpend, mine);
+            __syncthreads();
+            const int total = lpend;                  // reset after the next barrier
+            if (total == 0) continue;
+            if (*Lst.cnt + total > Lst.cap) {
+                list_merge(Lst, &W.h->gthr);          // block-uniform: ends with a barrier
+            }
+            if (*Lst.cnt + total <= Lst.cap) {
+                if (mine) {
+                    int slot = atomicAdd(Lst.cnt, mine);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        if (!((rows >> r) & 1u)) continue;
+                        float sc[5];
+                        int64_t fid[5];
+                        row_scores(r, sc, fid);
+#pragma unroll
+                        for (int k = 0; k < 5; ++k)
+                            if (admit(sc[k], fid[k])) {
+                                Lst.sc[slot] = sc[k];
+                                Lst.id[slot] = fid[k];
+                                ++slot;
+                            }
+                    }
+                }
+                continue;
+            }
+            // the list is filling: row by row, merging as needed
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 float sc[5];
                 int64_t fid[5];
                 row_scores(r, sc, fid);
-                // insert this row's candidates: all five forms at once when the list
-                // has room for a full row of the block, else form by form with merges
                 __syncthreads();
                 const int c = *Lst.cnt;
                 __syncthreads();
