@@ -204,7 +204,9 @@ typedef struct {
     int32_t n_exclude;
     int32_t keep;                 /* list length K', 1..SISSO_MAX_KEEP           */
     int32_t precision;            /* SISSO_FP32 (SISSO_BF16: see below)          */
-    int32_t grid;                 /* persistent blocks per launch, 0 = default   */
+    int32_t grid;                 /* persistent blocks of the binary block's
+                                     kernels, 0 = default (the stored-column pass
+                                     always uses its own default)                */
     int32_t tile;                 /* tile-shape variant, 0 = default             */
     int32_t list_base;            /* first list slot this call writes: 0 starts a
                                      new pass (resets the workspace); > 0 appends

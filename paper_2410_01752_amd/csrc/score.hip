@@ -75,23 +75,54 @@ __global__ void __launch_bounds__(256) k_score_columns(
     const int64_t ncols = c_hi - c_lo;
     constexpr int NC = (kColWaves * kColBatch * PER + 255) / 256;
 
+    // n <= 256 kColRegs: the residual stays in registers and each column is
+    // loaded whole, one column ahead of the one being scored
+    const bool regs = n <= 256 * kColRegs;
+    float4 rv[kColRegs], cur[kColRegs], nxt[kColRegs];
+    auto load_col = [&](int64_t c, float4 (&dst)[kColRegs]) {
+        const float *col = pool32 + (size_t)c * ld32;
+#pragma unroll
+        for (int k = 0; k < kColRegs; ++k) {
+            const int t = lane * 4 + 256 * k;
+            dst[k] = t < n ? *reinterpret_cast<const float4 *>(col + t) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    if (regs) {
+#pragma unroll
+        for (int k = 0; k < kColRegs; ++k) {
+            const int t = lane * 4 + 256 * k;
+            rv[k] = t < n ? *reinterpret_cast<const float4 *>(r32 + t) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+
     for (int64_t b0 = (int64_t)blockIdx.x * per_batch; b0 < ncols; b0 += (int64_t)gridDim.x * per_batch) {
+        const int64_t cw = c_lo + b0 + w * kColBatch;     // this wave's first column
+        if (regs && cw < c_hi) load_col(cw, cur);
         for (int j = 0; j < kColBatch; ++j) {
             const int slot_base = (w * kColBatch + j) * PER;
-            const int64_t c = c_lo + b0 + w * kColBatch + j;
+            const int64_t c = cw + j;
             float scs[PER];
 #pragma unroll
             for (int o = 0; o < PER; ++o) scs[o] = -1.0f;
+            if (regs && c + 1 < c_hi && j + 1 < kColBatch) load_col(c + 1, nxt);
             if (c < c_hi) {
                 const sisso_colstat st = stats[c];
-                score_column<NU>(pool32 + (size_t)c * ld32, st, r32, n, nd, R1, Srr, uop, nu,
-                                 NU > 0 && rect && c >= newlo, scs);
+                if (regs)
+                    score_column_regs<NU, kColRegs>(cur, rv, st, n, nd, R1, Srr, uop, nu,
+                                                    NU > 0 && rect && c >= newlo, scs);
+                else
+                    score_column<NU>(pool32 + (size_t)c * ld32, st, r32, n, nd, R1, Srr, uop, nu,
+                                     NU > 0 && rect && c >= newlo, scs);
                 if (!(c >= id_begin && c < id_end)) scs[0] = -1.0f;
 #pragma unroll
                 for (int o = 0; o < NU; ++o) {
                     const int64_t uid = pL + (c - newlo) * nu + o;
                     if (!(uid >= id_begin && uid < id_end)) scs[1 + o] = -1.0f;
                 }
+            }
+            if (regs) {
+#pragma unroll
+                for (int k = 0; k < kColRegs; ++k) cur[k] = nxt[k];
             }
             if (lane == 0) {
 #pragma unroll
@@ -303,7 +334,9 @@ struct Plan {
 
 int rect_tu(int ru) { return 16 * ru; }
 
-int max_col_grid(const sisso_score_args *a) { return a->grid > 0 ? a->grid : kMaxColGrid; }
+// The stored-column pass is HBM-bound with its own launch shape; the grid
+// argument tunes the binary block's kernels only.
+int max_col_grid(const sisso_score_args *) { return kMaxColGrid; }
 int max_rect_grid(const sisso_score_args *a) { return a->grid > 0 ? a->grid : kMaxRectGrid; }
 
 void tile_shape(const sisso_score_args *a, int *ru, int *rv)

@@ -9,6 +9,7 @@ namespace sisso {
 
 constexpr int kColWaves = 4;       // waves per block of the column kernels
 constexpr int kColBatch = 16;      // columns per wave between list merges
+constexpr int kColRegs = 8;        // float4 per lane of a register-resident column (n <= 2048)
 
 // ------------------------------------------------------------ columns
 
@@ -89,6 +90,105 @@ __device__ __forceinline__ void score_column(const float *__restrict__ col, cons
             if (st.valid != 0.0f && dom && !((badu >> o) & 1))
                 scs[1 + o] = score_from_sums(Au, Bu, Cu, (double)sh[o], nd, R1, Srr);
         }
+    }
+}
+
+// Sums of a unary child of a register-resident column (see
+// score_column_regs): the shift (mean of the first 256 samples), then
+// sum g, sum g^2, sum g r of g = op(f) - shift, in the order score_column
+// takes them.  OP is a compile-time operator so the loop stays small enough
+// to unroll and the column stays in registers.
+template <int OP, int KR>
+__device__ __forceinline__ void unary_child_sums(const float4 (&fv)[KR], const float4 (&rv)[KR], int n,
+                                                 float &shift, float &au, float &bu, float &cu, bool &bad)
+{
+    const int lane = threadIdx.x & 63;
+    {
+        const int t = lane * 4;
+        const float fa[4] = {fv[0].x, fv[0].y, fv[0].z, fv[0].w};
+        const int cnt = n < 256 ? n : 256;
+        float acc = 0.f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (t + e < n) {
+                const float h = unary32(OP, fa[e]);
+                acc += fabsf(h) <= 1e15f ? h : 0.f;
+            }
+        shift = (float)(wave_sum((double)acc) / cnt);
+    }
+    au = bu = cu = 0.f;
+    bad = false;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int t = lane * 4 + 256 * k;
+        if (t < n) {
+            const float fa[4] = {fv[k].x, fv[k].y, fv[k].z, fv[k].w};
+            const float ra[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < n) {
+                    const float h = unary32(OP, fa[e]);
+                    bad |= !(fabsf(h) <= 1e15f);
+                    const float gu = h - shift;
+                    au += gu; bu = fmaf(gu, gu, bu); cu = fmaf(gu, ra[e], cu);
+                }
+        }
+    }
+}
+
+// score_column with the column's and the residual's samples already in
+// registers: float4 k of a lane holds samples lane * 4 + 256 k .. + 3
+// (zero past n), for n <= 256 * KR.  Every sum takes the same operations in
+// the same order as score_column, so the two give identical scores.
+template <int NU, int KR>
+__device__ __forceinline__ void score_column_regs(const float4 (&fv)[KR], const float4 (&rv)[KR],
+                                                  const sisso_colstat &st, int n, double nd, double R1,
+                                                  double Srr, const int (&uop)[NU > 0 ? NU : 1], int nu,
+                                                  bool do_unary, float (&scs)[1 + NU])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 0; o < 1 + NU; ++o) scs[o] = -1.0f;
+    const float f0 = st.mean;
+    float a0 = 0.f, b0s = 0.f, c0 = 0.f;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int t = lane * 4 + 256 * k;
+        if (t < n) {
+            const float fa[4] = {fv[k].x, fv[k].y, fv[k].z, fv[k].w};
+            const float ra[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < n) {
+                    const float g = fa[e] - f0;
+                    a0 += g; b0s = fmaf(g, g, b0s); c0 = fmaf(g, ra[e], c0);
+                }
+        }
+    }
+    const double A = wave_sum((double)a0), B = wave_sum((double)b0s), C = wave_sum((double)c0);
+    if (st.valid != 0.0f) scs[0] = score_from_sums(A, B, C, (double)f0, nd, R1, Srr);
+    if (NU == 0 || !do_unary) return;
+#pragma unroll
+    for (int o = 0; o < (NU > 0 ? NU : 1); ++o) {
+        if (o >= nu) continue;
+        float sh = 0.f, au = 0.f, bu = 0.f, cu = 0.f;
+        bool bad = false;
+        switch (uop[o]) {
+        case SISSO_SQ: unary_child_sums<SISSO_SQ, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        case SISSO_CUBE: unary_child_sums<SISSO_CUBE, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        case SISSO_SQRT: unary_child_sums<SISSO_SQRT, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        case SISSO_INV: unary_child_sums<SISSO_INV, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        case SISSO_EXP: unary_child_sums<SISSO_EXP, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        case SISSO_NEXP: unary_child_sums<SISSO_NEXP, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        case SISSO_LOG: unary_child_sums<SISSO_LOG, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        case SISSO_SIN: unary_child_sums<SISSO_SIN, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        default: unary_child_sums<-1, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        }
+        const bool anybad = wave_or(bad ? 1 : 0) != 0;
+        const double Au = wave_sum((double)au), Bu = wave_sum((double)bu), Cu = wave_sum((double)cu);
+        float bound;
+        const bool dom = unary_domain_bound(uop[o], st, &bound);
+        if (st.valid != 0.0f && dom && !anybad) scs[1 + o] = score_from_sums(Au, Bu, Cu, (double)sh, nd, R1, Srr);
     }
 }
 
