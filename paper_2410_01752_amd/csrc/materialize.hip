@@ -1,7 +1,7 @@
 // materialize.hip -- operand pools and FP64 feature evaluation.
 //
 // Feature expansion (Sec. 2.1, eq. feature-exp): the pool levels P_0, P_1,
-// P_2 are evaluated in FP64 from the base features, one block per column,
+// P_2 are evaluated in FP64 from the base features, one wave per column,
 // and stored column-major in FP32 (the screening operands) together with
 // per-column statistics.  Level-1 values are also kept in FP64 so that any
 // feature of the space (pool or one-sided slice) can be re-evaluated exactly
@@ -29,16 +29,50 @@ __device__ inline void block_minmax(float &mx, float &mn, float &mv, int &bad, B
     }
 }
 
-// One level of the pool: columns [c_begin, c_end).  Level 0 copies the base
-// features.  Operands of levels >= 1 are read from the FP64 level-1 pool.
+// One level of the pool: columns [c_begin, c_end), one wave per column.
+// Level 0 copies the base features; operands of levels >= 1 are read from
+// the FP64 level-1 pool.  For n <= 64 kPoolRegs the column's FP64 values stay
+// in registers between the two passes (the mean is needed before the sum of
+// squared deviations); longer columns are evaluated twice.
+constexpr int kPoolRegs = 32;
+
+// Pass 1 over the register-resident part of a column for a compile-time
+// operator OP (-1: copy of a base feature): values, domain and magnitude
+// flags, and the sums of f, x^2 and y^2.
+template <int OP>
+__device__ __forceinline__ void pool_values(const double *__restrict__ A, const double *__restrict__ B, int n,
+                                            double (&fr)[kPoolRegs], double &sum, double &sa2, double &sb2,
+                                            int &bad)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr bool binary = OP == SISSO_ADD || OP == SISSO_SUB || OP == SISSO_MUL || OP == SISSO_DIV;
+#pragma unroll
+    for (int i = 0; i < kPoolRegs; ++i) {
+        const int t = lane + 64 * i;
+        fr[i] = 0.0;
+        if (t < n) {
+            bool ok = true;
+            const double x = A[t], y = binary ? B[t] : 0.0;
+            const double f = OP < 0 ? x : apply64(OP, x, y, ok);
+            if (!ok || !(fabs(f) <= kValueCap)) bad = 1;   // also catches NaN
+            fr[i] = f;
+            sum += f;
+            sa2 += x * x;
+            sb2 += y * y;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_pool_level(sisso_space s, const double *__restrict__ X,
                                                     int n, int ldx, float *__restrict__ pool32,
                                                     int64_t ld32, double *__restrict__ p1,
                                                     int64_t ld64, sisso_colstat *__restrict__ stats,
                                                     int64_t c_begin, int64_t c_end)
 {
-    __shared__ BlockStats bs;
-    for (int64_t c = c_begin + blockIdx.x; c < c_end; c += gridDim.x) {
+    const int lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * nwv + (threadIdx.x >> 6), wstride = (int64_t)gridDim.x * nwv;
+    const bool regs = n <= 64 * kPoolRegs;
+    for (int64_t c = c_begin + wid; c < c_end; c += wstride) {
         int op;
         int64_t a, b;
         decode_id(s, c, &op, &a, &b);
@@ -49,28 +83,59 @@ __global__ void __launch_bounds__(256) k_pool_level(sisso_space s, const double 
         }
         const double *A = op < 0 ? X + (size_t)c * ldx : p1 + (size_t)a * ld64;
         const double *B = (op >= 0 && b >= 0) ? p1 + (size_t)b * ld64 : nullptr;
+        auto value = [&](int t, bool &ok, double &x, double &y) {
+            x = A[t];
+            y = B ? B[t] : 0.0;
+            return op < 0 ? x : apply64(op, x, y, ok);
+        };
         // pass 1: values, domain, magnitude, sums
+        double fr[kPoolRegs];
         double sum = 0.0, sa2 = 0.0, sb2 = 0.0;
         int bad = opok ? 0 : 1;
-        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        auto pass1 = [&](int t, double &f) {
             bool ok = true;
-            const double x = A[t], y = B ? B[t] : 0.0;
-            const double f = op < 0 ? x : apply64(op, x, y, ok);
+            double x, y;
+            f = value(t, ok, x, y);
             if (!ok || !(fabs(f) <= kValueCap)) bad = 1;   // also catches NaN
             sum += f;
             sa2 += x * x;
             sb2 += y * y;
+        };
+        switch (op < 0 ? -1 : op) {
+        case -1: pool_values<-1>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_ADD: pool_values<SISSO_ADD>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_SUB: pool_values<SISSO_SUB>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_MUL: pool_values<SISSO_MUL>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_DIV: pool_values<SISSO_DIV>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_SQ: pool_values<SISSO_SQ>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_CUBE: pool_values<SISSO_CUBE>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_SQRT: pool_values<SISSO_SQRT>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_INV: pool_values<SISSO_INV>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_EXP: pool_values<SISSO_EXP>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_NEXP: pool_values<SISSO_NEXP>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_LOG: pool_values<SISSO_LOG>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        case SISSO_SIN: pool_values<SISSO_SIN>(A, B, n, fr, sum, sa2, sb2, bad); break;
+        default:
+#pragma unroll
+            for (int i = 0; i < kPoolRegs; ++i) {
+                fr[i] = 0.0;
+                const int t = lane + 64 * i;
+                if (t < n) pass1(t, fr[i]);
+            }
         }
-        const double mean = block_sum(sum, bs.red) / n;
-        const double ra = sqrt(block_sum(sa2, bs.red) / n), rb = sqrt(block_sum(sb2, bs.red) / n);
+        if (!regs)
+            for (int t = lane + 64 * kPoolRegs; t < n; t += 64) {
+                double f;
+                pass1(t, f);
+            }
+        const double mean = wave_sum(sum) / n;
+        const double ra = sqrt(wave_sum(sa2) / n), rb = sqrt(wave_sum(sb2) / n);
         // pass 2: sum of squares, extremes, reciprocal mean, stores
         double ss = 0.0, srcp = 0.0, sf2 = 0.0;
         float mx = 0.0f, mn = INFINITY, mv = INFINITY;
         float *out32 = pool32 + (size_t)c * ld32;
         double *out64 = (c < s.pool[1 < s.levels ? 1 : s.levels]) ? p1 + (size_t)c * ld64 : nullptr;
-        for (int t = threadIdx.x; t < n; t += blockDim.x) {
-            bool ok = true;
-            const double f = op < 0 ? A[t] : apply64(op, A[t], B ? B[t] : 0.0, ok);
+        auto pass2 = [&](int t, double f) {
             const double e = f - mean;
             ss += e * e;
             sf2 += f * f;
@@ -79,13 +144,24 @@ __global__ void __launch_bounds__(256) k_pool_level(sisso_space s, const double 
             mx = fmaxf(mx, af); mn = fminf(mn, af); mv = fminf(mv, (float)f);
             out32[t] = (float)f;
             if (out64) out64[t] = f;
+        };
+#pragma unroll
+        for (int i = 0; i < kPoolRegs; ++i) {
+            const int t = lane + 64 * i;
+            if (t < n) pass2(t, fr[i]);
         }
-        for (int64_t t = n + threadIdx.x; t < ld32; t += blockDim.x) out32[t] = 0.0f;
-        const double sst = block_sum(ss, bs.red);
-        const double mrcp = block_sum(srcp, bs.red) / n;
-        const double msq = block_sum(sf2, bs.red) / n;
-        block_minmax(mx, mn, mv, bad, bs);
-        if (threadIdx.x == 0) {
+        if (!regs)
+            for (int t = lane + 64 * kPoolRegs; t < n; t += 64) {
+                bool ok = true;
+                double x, y;
+                pass2(t, value(t, ok, x, y));
+            }
+        for (int64_t t = n + lane; t < ld32; t += 64) out32[t] = 0.0f;
+        const double sst = wave_sum(ss);
+        const double mrcp = wave_sum(srcp) / n;
+        const double msq = wave_sum(sf2) / n;
+        mx = wave_max(mx); mn = wave_min(mn); mv = wave_min(mv); bad = wave_or(bad);
+        if (lane == 0) {
             const double sd = sqrt(sst / n);
             bool valid = !bad && sd != 0.0 && sd > kConstRel * fabs(mean);
             if (op == SISSO_ADD || op == SISSO_SUB) valid = valid && sd > kCancelRel * fmax(ra, rb);
@@ -100,7 +176,6 @@ __global__ void __launch_bounds__(256) k_pool_level(sisso_space s, const double 
             st.rms = (float)sqrt(msq);
             stats[c] = st;
         }
-        __syncthreads();
     }
 }
 
@@ -262,7 +337,8 @@ extern "C" sisso_status sisso_materialize_pools(const sisso_space *space, const 
     for (int lev = 0; lev <= space->levels; ++lev) {
         const int64_t lo = lev == 0 ? 0 : space->pool[lev - 1], hi = space->pool[lev];
         const int64_t cols = hi - lo;
-        const int grid = (int)(cols < 65536 ? cols : 65536);
+        const int64_t blocks = (cols + 3) / 4;   // four waves (columns) per block
+        const int grid = (int)(blocks < 16384 ? blocks : 16384);
         hipLaunchKernelGGL(k_pool_level, dim3(grid), dim3(256), 0, st, *space, X, n, ldx, pool32, ld32,
                            pool1_64, ld64, stats, lo, hi);
         if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
