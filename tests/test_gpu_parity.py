@@ -82,6 +82,31 @@ def test_pools_match_oracle(name):
     assert np.all(np.abs(got - want) <= 2e-7 * np.maximum(np.abs(want), 1e-30))
 
 
+@pytest.mark.parametrize("n", [2048, 2049, 2600])
+def test_long_columns_pools_and_column_pass(n):
+    """Columns of up to 2048 samples are held in registers by the pool and
+    stored-column kernels; longer ones take the streaming path.  Both sides of
+    the boundary against the oracle: every pool column, and SIS over the stored
+    pool plus the unary slice."""
+    p = I.tiny(17, n=n, d=4, dist="lognormal", rect=True)
+    print(f"[long columns] n={n}", flush=True)
+    eng = _engine(p)
+    sp = O.Space(4, p.unary, p.binary, 2, True)
+    p2 = sp.pool(2)
+    V, ok = sp.eval(p.X, np.arange(p2))
+    torch.cuda.synchronize()
+    pool = eng.pool32.view(p2, eng.ld32)[:, :eng.n].cpu().numpy()
+    stats = eng.stats.view(p2, 8).cpu().numpy()
+    assert np.array_equal(stats[:, 6] != 0, ok)
+    want = V[:, ok].astype(np.float32)
+    assert np.all(np.abs(pool[ok].T - want) <= 2e-7 * np.maximum(np.abs(want), 1e-30))
+    end = p2 + len(p.unary) * (p2 - sp.pool(1))
+    keep = 800
+    gi, gs = _screen(eng, p.y, keep, 0, end)
+    oi, os_ = sp.sis(p.X, p.y, keep, begin=0, end=end)
+    assert_topk_parity(sp, p.X, p.y, gi, gs, oi, os_, keep)
+
+
 # --------------------------------------------------------------- screening
 
 def test_screen_c1_full_space():
