@@ -493,6 +493,37 @@ sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, 
                              double *out_coef, double *out_resid, double *out_stats, void *ws,
                              size_t ws_bytes, void *stream);
 
+/* sisso_l0_search for many independent problems (cross-validation folds,
+ * bootstrap resamples: Sec. 3 and 4 run such fits side by side) in seven
+ * launches in all.  The table is a DEVICE array of n_problems records; every
+ * field has the meaning of the sisso_l0_search argument of the same name,
+ * ws has at least sisso_l0_workspace_size(m, n, D) bytes (ws_bytes), and all
+ * problems share D and singular_tol.  m_max and n_max [host] bound m and n
+ * of every entry and size the launch.  out_status (device, nullable,
+ * n_problems int32) receives 0, or SISSO_E_SHAPE for an entry that was
+ * skipped (a NULL pointer, m outside D..m_max, n outside 2..n_max, ld < n,
+ * or a short workspace).  Each problem's results equal those of
+ * sisso_l0_search on it.  Errors: SISSO_E_NULL, SISSO_E_SHAPE (n_problems
+ * outside 1..SISSO_MAX_BATCH, D outside 1..SISSO_MAX_D, m_max outside
+ * D..SISSO_MAX_SUBSPACE, n_max outside 2..SISSO_MAX_N), SISSO_E_RANGE
+ * (singular_tol). */
+typedef struct {
+    const double *F;       /* n x m subspace columns, ascending ids        */
+    int32_t m, ld, n, reserved;
+    const double *y;       /* n                                            */
+    int32_t *out_tuple;    /* D (0-based columns of F)                     */
+    double *out_sse;       /* 1                                            */
+    double *out_coef;      /* D + 1, intercept first                       */
+    double *out_resid;     /* n                                            */
+    double *out_stats;     /* 4: RMSE, R^2, tuples evaluated, skipped      */
+    void *ws;              /* workspace of this problem                    */
+    int64_t ws_bytes;
+} sisso_l0_problem;
+
+sisso_status sisso_l0_search_batched(const sisso_l0_problem *problems, int32_t n_problems, int32_t D,
+                                     int32_t m_max, int32_t n_max, double singular_tol, int32_t *out_status,
+                                     void *stream);
+
 /* Gather columns: dst[:, i] = src[:, perm[i]] for i < m (FP64), with ids.
  * Used to put a subspace in ascending id order before sisso_l0_search.
  * perm_out (device, m int32) receives the permutation that sorts ids. */

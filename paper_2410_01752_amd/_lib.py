@@ -60,6 +60,14 @@ class Problem(ctypes.Structure):
                 ("n_exclude", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class L0Problem(ctypes.Structure):
+    """sisso_l0_problem: one entry of a batched SO table (device array)."""
+    _fields_ = [("F", ctypes.c_void_p), ("m", ctypes.c_int32), ("ld", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("y", ctypes.c_void_p), ("out_tuple", ctypes.c_void_p),
+                ("out_sse", ctypes.c_void_p), ("out_coef", ctypes.c_void_p), ("out_resid", ctypes.c_void_p),
+                ("out_stats", ctypes.c_void_p), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_int64)]
+
+
 COLSTAT_FLOATS = 8      # sisso_colstat: 8 floats
 RESID_DOUBLES = 4       # sisso_resid_info: 4 doubles
 
@@ -94,6 +102,7 @@ def lib():
         "sisso_batch_items": (_i32, [sp]),
         "sisso_expand_score_batched": (_i32, [sp, _vp, _i32, _i32, _i32, _vp, _sz, _vp]),
         "sisso_topk_batched": (_i32, [_vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp]),
+        "sisso_l0_search_batched": (_i32, [_vp, _i32, _i32, _i32, _i32, ctypes.c_double, _vp, _vp]),
         "sisso_score_workspace_size": (_sz, [sp, ap]),
         "sisso_score_reset": (_i32, [_vp, _sz, _vp]),
         "sisso_expand_score": (_i32, [sp, ap, _i64, _i64, _vp, _sz, _vp]),
@@ -150,7 +159,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_bf16_workspace_size", "sisso_expand_score_bf16_lists", "sisso_expand_score_bf16",
             "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore",
             "sisso_materialize_ids_stored", "sisso_prepare_residual_batched", "sisso_batch_workspace_size",
-            "sisso_batch_items", "sisso_expand_score_batched", "sisso_topk_batched",
+            "sisso_batch_items", "sisso_expand_score_batched", "sisso_topk_batched", "sisso_l0_search_batched",
             "sisso_mlp_param_count", "sisso_mlp_table_count", "sisso_encode_operands", "sisso_candidate_inputs",
             "sisso_score_ids", "sisso_mlp_forward", "sisso_mlp_workspace_size", "sisso_mlp_backward",
             "sisso_adam_step", "sisso_mlp_parts", "sisso_mlp_tables", "sisso_mlp_score_ids", "sisso_select_kth",

@@ -5,9 +5,9 @@ datasets) share the operator set and rung, so one persistent launch screens
 all of them: sisso_prepare_residual_batched -> sisso_expand_score_batched ->
 sisso_topk_batched per step t of Sec. 2.3.  Each problem stores only its pool
 P_1; the level-2 features are generated in registers by the screening
-kernel.  The subspace update and the SO step then run per problem on the
-same stream (FitState), with one host synchronisation per stage for the
-whole batch.
+kernel.  The subspace update runs per problem on the same stream
+(FitState); the SO step of every problem is one sisso_l0_search_batched call,
+and the per-step results of the whole batch come back in a few copies.
 """
 from __future__ import annotations
 
@@ -195,16 +195,60 @@ class Batch:
                         keep[p] = min(2 * keep[p], L.MAX_KEEP)
                         nxt.append(p)
                 todo = nxt
-            still = []
-            for p in active:
-                nn, nc, ct = upd[p]
-                if states[p].commit(nn, t):
-                    states[p].so(self.y[p], t, singular_tol, ws_of(p), None)
-                    still.append(p)
-            for p in still:
-                nn, nc, ct = upd[p]
-                ids_p, sc_p, _ = lists[p]
-                out[p].append(states[p].result(t, ids_p, sc_p, ct, keep[p], nc))
-                r[p] = states[p].resid.clone()
+            still = [p for p in active if states[p].commit(upd[p][0], t)]
+            if still:
+                self.so_batched(still, states, t, singular_tol, ws_of, timings)
+                for p, res in zip(still, self.results(still, states, lists, upd, keep, t)):
+                    out[p].append(res)
+                    r[p] = states[p].resid.clone()
             active = still
+        return out
+
+    def so_batched(self, which, states, t: int, singular_tol: float, ws_of, timings=None):
+        """The SO step (Sec. 2.3) of every problem in `which` in one batched call."""
+        recs = (L.L0Problem * len(which))()
+        for j, p in enumerate(which):
+            recs[j] = states[p].so_record(self.y[p], t, ws_of(p))
+        tbl = torch.frombuffer(bytearray(recs), dtype=torch.uint8).to(self.dev)
+        self._l0_table = tbl                     # alive until the results are read
+        self._l0_status = torch.empty(len(which), dtype=torch.int32, device=self.dev)
+        if timings is not None:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        m_max = max(states[p].m for p in which)
+        n_max = max(self.n[p] for p in which)
+        L.check(L.lib().sisso_l0_search_batched(L.ptr(tbl), len(which), t, m_max, n_max, singular_tol,
+                                                L.ptr(self._l0_status), L.stream_handle(self.dev)),
+                "sisso_l0_search_batched")
+        if timings is not None:
+            e1.record()
+            timings.setdefault(f"l0_batched_D{t}", []).append((e0, e1))
+
+    def results(self, which, states, lists, upd, keep, t: int) -> List[StepResult]:
+        """StepResults of step t for every problem in `which`, in three copies."""
+        small = torch.cat([torch.cat([states[p].tup[:t].double(), states[p].sse, states[p].coef[:t + 1],
+                                      states[p].stats]) for p in which]).cpu().numpy()
+        ids = torch.cat([torch.cat([states[p].ids_sorted[:states[p].m], states[p].sub_ids[:states[p].m],
+                                    lists[p][0][:upd[p][2]]]) for p in which]).cpu().numpy()
+        scs = torch.cat([lists[p][1][:upd[p][2]] for p in which]).cpu().numpy()
+        st = self._l0_status.cpu().numpy()
+        if np.any(st != 0):
+            raise L.SissoError(f"sisso_l0_search_batched: entry status {st.tolist()}")
+        out, o_s, o_i, o_c = [], 0, 0, 0
+        w = 2 * t + 6
+        for p in which:
+            m, ct = states[p].m, upd[p][2]
+            v = small[o_s:o_s + w]
+            o_s += w
+            srt, sub = ids[o_i:o_i + m], ids[o_i + m:o_i + 2 * m]
+            lid = ids[o_i + 2 * m:o_i + 2 * m + ct]
+            o_i += 2 * m + ct
+            lsc = scs[o_c:o_c + ct]
+            o_c += ct
+            tp = v[:t].astype(np.int64)
+            sse, coef, stt = v[t], v[t + 1:2 * t + 2], v[2 * t + 2:2 * t + 6]
+            best = srt[tp] if (tp >= 0).all() else np.full(t, -1)
+            out.append(StepResult(t, lid, lsc, sub, best, coef, float(sse), float(stt[0]), float(stt[1]),
+                                  int(stt[2]), int(stt[3]), keep[p], upd[p][1]))
         return out

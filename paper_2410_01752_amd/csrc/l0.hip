@@ -55,7 +55,7 @@ __host__ __device__ inline L0Ws l0_ws_view(void *ws, int m, int n)
     return w;
 }
 
-__global__ void __launch_bounds__(256) k_l0_y(const double *__restrict__ y, int n, L0Ws w)
+__device__ inline void l0_y(const double *__restrict__ y, int n, L0Ws w)
 {
     __shared__ double red[16];
     double s = 0.0;
@@ -77,10 +77,9 @@ __global__ void __launch_bounds__(256) k_l0_y(const double *__restrict__ y, int 
     }
 }
 
-__global__ void __launch_bounds__(256) k_l0_columns(const double *__restrict__ F, int ld, int n, L0Ws w)
+__device__ inline void l0_column(const double *__restrict__ F, int ld, int n, L0Ws w, int j)
 {
     __shared__ double red[16];
-    const int j = blockIdx.x;
     double *z = w.Z + (size_t)j * w.ldz;
     standardize_column(F + (size_t)j * ld, n, z, &w.mean[j], &w.norm[j], nullptr, red);
     double d = 0.0;
@@ -89,11 +88,10 @@ __global__ void __launch_bounds__(256) k_l0_columns(const double *__restrict__ F
     if (threadIdx.x == 0) w.beta[j] = b;
 }
 
-__global__ void __launch_bounds__(256) k_l0_gram(int m, int n, L0Ws w)
+__device__ inline void l0_gram(int m, int n, L0Ws w, int bi, int bj)
 {
     __shared__ double As[kGK][kGT + 1];
     __shared__ double Bs[kGK][kGT + 1];
-    const int bi = blockIdx.y, bj = blockIdx.x;
     if (bj > bi) return;
     double acc[2][2];
     gemm_tile_tn(w.Z, m, w.Z, m, n, w.ldz, bi, bj, acc, As, Bs);
@@ -119,12 +117,11 @@ __device__ __forceinline__ unsigned long long sse_bits(double sse)
 // Enumerate tuples with first index i = blockIdx.x.  PASS 0: minimum SSE;
 // PASS 1: smallest lexicographic key (i, j, l) with SSE <= band.
 template <int D, int PASS>
-__global__ void __launch_bounds__(256) k_l0_enum(int m, double tol, L0Ws w)
+__device__ inline void l0_enum(int m, double tol, L0Ws w, int i)
 {
     __shared__ double inv22[SISSO_MAX_SUBSPACE], z2s[SISSO_MAX_SUBSPACE];
     __shared__ unsigned long long red64[4];
     __shared__ unsigned long long skip_s;
-    const int i = blockIdx.x;
     const double syy = w.scal[1];
     const double bi = w.beta[i];
     const double base = syy - bi * bi;
@@ -212,11 +209,11 @@ __global__ void __launch_bounds__(256) k_l0_enum(int m, double tol, L0Ws w)
 }
 
 // Decode the best tuple, solve for the coefficients, form the residual.
-__global__ void __launch_bounds__(256) k_l0_finish(const double *__restrict__ F, int ld, int n, int m, int D,
-                                                   const double *__restrict__ y, double n_tuples, L0Ws w,
-                                                   int32_t *__restrict__ out_tuple, double *__restrict__ out_sse,
-                                                   double *__restrict__ out_coef, double *__restrict__ out_resid,
-                                                   double *__restrict__ out_stats)
+__device__ inline void l0_finish(const double *__restrict__ F, int ld, int n, int m, int D,
+                                 const double *__restrict__ y, double n_tuples, L0Ws w,
+                                 int32_t *__restrict__ out_tuple, double *__restrict__ out_sse,
+                                 double *__restrict__ out_coef, double *__restrict__ out_resid,
+                                 double *__restrict__ out_stats)
 {
     __shared__ int tup[SISSO_MAX_D];
     __shared__ double coef[SISSO_MAX_D + 1];
@@ -299,6 +296,96 @@ __global__ void __launch_bounds__(256) k_l0_finish(const double *__restrict__ F,
     }
 }
 
+__host__ __device__ inline double n_choose(int m, int D)
+{
+    double r = 1.0;
+    for (int a = 0; a < D; ++a) r = r * (m - a) / (a + 1);
+    return r;
+}
+
+// ------------------------------------------------------- one problem
+
+__global__ void __launch_bounds__(256) k_l0_y(const double *__restrict__ y, int n, L0Ws w) { l0_y(y, n, w); }
+
+__global__ void __launch_bounds__(256) k_l0_columns(const double *__restrict__ F, int ld, int n, L0Ws w)
+{
+    l0_column(F, ld, n, w, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_l0_gram(int m, int n, L0Ws w) { l0_gram(m, n, w, blockIdx.y, blockIdx.x); }
+
+template <int D, int PASS>
+__global__ void __launch_bounds__(256) k_l0_enum(int m, double tol, L0Ws w)
+{
+    l0_enum<D, PASS>(m, tol, w, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_l0_finish(const double *__restrict__ F, int ld, int n, int m, int D,
+                                                   const double *__restrict__ y, double n_tuples, L0Ws w,
+                                                   int32_t *__restrict__ out_tuple, double *__restrict__ out_sse,
+                                                   double *__restrict__ out_coef, double *__restrict__ out_resid,
+                                                   double *__restrict__ out_stats)
+{
+    l0_finish(F, ld, n, m, D, y, n_tuples, w, out_tuple, out_sse, out_coef, out_resid, out_stats);
+}
+
+// ------------------------------------------------------- many problems
+//
+// The same bodies over a table of problems: blockIdx.y (gram: blockIdx.z)
+// is the problem; blocks beyond a problem's own extent return at once.
+
+__device__ inline bool l0p_ok(const sisso_l0_problem &P, int D, int m_max, int n_max)
+{
+    return P.F && P.y && P.out_tuple && P.out_sse && P.out_coef && P.out_resid && P.out_stats && P.ws &&
+           P.m >= D && P.m <= m_max && P.n >= 2 && P.n <= n_max && P.ld >= P.n &&
+           P.ws_bytes >= (int64_t)l0_ws_bytes(P.m, P.n);
+}
+
+__global__ void __launch_bounds__(256) k_l0b_y(const sisso_l0_problem *__restrict__ T, int D, int m_max, int n_max,
+                                               int32_t *__restrict__ status)
+{
+    const sisso_l0_problem P = T[blockIdx.y];
+    const bool ok = l0p_ok(P, D, m_max, n_max);
+    if (threadIdx.x == 0 && status) status[blockIdx.y] = ok ? SISSO_OK : SISSO_E_SHAPE;
+    if (!ok) return;
+    l0_y(P.y, P.n, l0_ws_view(P.ws, P.m, P.n));
+}
+
+__global__ void __launch_bounds__(256) k_l0b_columns(const sisso_l0_problem *__restrict__ T, int D, int m_max,
+                                                     int n_max)
+{
+    const sisso_l0_problem P = T[blockIdx.y];
+    if (!l0p_ok(P, D, m_max, n_max) || (int)blockIdx.x >= P.m) return;
+    l0_column(P.F, P.ld, P.n, l0_ws_view(P.ws, P.m, P.n), blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_l0b_gram(const sisso_l0_problem *__restrict__ T, int D, int m_max, int n_max)
+{
+    const sisso_l0_problem P = T[blockIdx.z];
+    const int tiles = (P.m + kGT - 1) / kGT;
+    if (!l0p_ok(P, D, m_max, n_max) || (int)blockIdx.x >= tiles || (int)blockIdx.y >= tiles) return;
+    l0_gram(P.m, P.n, l0_ws_view(P.ws, P.m, P.n), blockIdx.y, blockIdx.x);
+}
+
+template <int D, int PASS>
+__global__ void __launch_bounds__(256) k_l0b_enum(const sisso_l0_problem *__restrict__ T, int m_max, int n_max,
+                                                  double tol)
+{
+    const sisso_l0_problem P = T[blockIdx.y];
+    const int gb = D == 1 ? P.m : P.m - D + 1;
+    if (!l0p_ok(P, D, m_max, n_max) || (int)blockIdx.x >= gb) return;
+    l0_enum<D, PASS>(P.m, tol, l0_ws_view(P.ws, P.m, P.n), blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_l0b_finish(const sisso_l0_problem *__restrict__ T, int D, int m_max,
+                                                    int n_max)
+{
+    const sisso_l0_problem P = T[blockIdx.x];
+    if (!l0p_ok(P, D, m_max, n_max)) return;
+    l0_finish(P.F, P.ld, P.n, P.m, D, P.y, n_choose(P.m, D), l0_ws_view(P.ws, P.m, P.n), P.out_tuple, P.out_sse,
+              P.out_coef, P.out_resid, P.out_stats);
+}
+
 }  // namespace sisso
 
 using namespace sisso;
@@ -311,12 +398,6 @@ extern "C" size_t sisso_l0_workspace_size(int32_t m, int32_t n, int32_t D)
     return l0_ws_bytes(m, n);
 }
 
-static double n_choose(int m, int D)
-{
-    double r = 1.0;
-    for (int a = 0; a < D; ++a) r = r * (m - a) / (a + 1);
-    return r;
-}
 
 extern "C" sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, const double *y,
                                         int32_t D, double singular_tol, int32_t *out_tuple, double *out_sse,
@@ -347,5 +428,35 @@ extern "C" sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, 
     }
     hipLaunchKernelGGL(k_l0_finish, dim3(1), dim3(256), 0, st, F, ld, n, m, D, y, n_choose(m, D), w, out_tuple,
                        out_sse, out_coef, out_resid, out_stats);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_l0_search_batched(const sisso_l0_problem *problems, int32_t n_problems, int32_t D,
+                                                int32_t m_max, int32_t n_max, double singular_tol,
+                                                int32_t *out_status, void *stream)
+{
+    if (!problems) return SISSO_E_NULL;
+    if (n_problems < 1 || n_problems > SISSO_MAX_BATCH || D < 1 || D > SISSO_MAX_D || m_max < D ||
+        m_max > SISSO_MAX_SUBSPACE || n_max < 2 || n_max > SISSO_MAX_N)
+        return SISSO_E_SHAPE;
+    if (!(singular_tol >= 0.0) || singular_tol >= 1.0) return SISSO_E_RANGE;
+    hipStream_t st = as_stream(stream);
+    const unsigned P = (unsigned)n_problems;
+    hipLaunchKernelGGL(k_l0b_y, dim3(1, P), dim3(256), 0, st, problems, D, m_max, n_max, out_status);
+    hipLaunchKernelGGL(k_l0b_columns, dim3(m_max, P), dim3(256), 0, st, problems, D, m_max, n_max);
+    const int tiles = (m_max + kGT - 1) / kGT;
+    hipLaunchKernelGGL(k_l0b_gram, dim3(tiles, tiles, P), dim3(256), 0, st, problems, D, m_max, n_max);
+    const unsigned gb = (unsigned)(D == 1 ? m_max : m_max - D + 1);
+    if (D == 1) {
+        hipLaunchKernelGGL((k_l0b_enum<1, 0>), dim3(gb, P), dim3(64), 0, st, problems, m_max, n_max, singular_tol);
+        hipLaunchKernelGGL((k_l0b_enum<1, 1>), dim3(gb, P), dim3(64), 0, st, problems, m_max, n_max, singular_tol);
+    } else if (D == 2) {
+        hipLaunchKernelGGL((k_l0b_enum<2, 0>), dim3(gb, P), dim3(256), 0, st, problems, m_max, n_max, singular_tol);
+        hipLaunchKernelGGL((k_l0b_enum<2, 1>), dim3(gb, P), dim3(256), 0, st, problems, m_max, n_max, singular_tol);
+    } else {
+        hipLaunchKernelGGL((k_l0b_enum<3, 0>), dim3(gb, P), dim3(256), 0, st, problems, m_max, n_max, singular_tol);
+        hipLaunchKernelGGL((k_l0b_enum<3, 1>), dim3(gb, P), dim3(256), 0, st, problems, m_max, n_max, singular_tol);
+    }
+    hipLaunchKernelGGL(k_l0b_finish, dim3(P), dim3(256), 0, st, problems, D, m_max, n_max);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }

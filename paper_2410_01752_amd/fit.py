@@ -346,11 +346,28 @@ class FitState:
         self.m += nn
         return self.m >= t
 
-    def so(self, y, t: int, singular_tol: float, workspace, timings: Optional[dict] = None):
+    def sort(self):
+        """Put S_t in ascending id order (the SO's column order)."""
         n, m, st = self.n, self.m, L.stream_handle(self.dev)
         L.check(L.lib().sisso_sort_subspace(L.ptr(self.sub), n, L.ptr(self.sub_ids), m, n, L.ptr(self.fsorted),
                                             n, L.ptr(self.ids_sorted), L.ptr(self.perm), st),
                 "sisso_sort_subspace")
+
+    def so_record(self, y, t: int, workspace) -> "L.L0Problem":
+        """Sort S_t and return this problem's sisso_l0_problem record."""
+        self.sort()
+        n, m = self.n, self.m
+        ws = workspace("l0", L.lib().sisso_l0_workspace_size(m, n, t))
+        rec = L.L0Problem()
+        rec.F, rec.m, rec.ld, rec.n, rec.reserved = L.ptr(self.fsorted), m, n, n, 0
+        rec.y, rec.out_tuple, rec.out_sse = L.ptr(y), L.ptr(self.tup), L.ptr(self.sse)
+        rec.out_coef, rec.out_resid, rec.out_stats = L.ptr(self.coef), L.ptr(self.resid), L.ptr(self.stats)
+        rec.ws, rec.ws_bytes = L.ptr(ws), ws.numel()
+        return rec
+
+    def so(self, y, t: int, singular_tol: float, workspace, timings: Optional[dict] = None):
+        n, m, st = self.n, self.m, L.stream_handle(self.dev)
+        self.sort()
         nb = L.lib().sisso_l0_workspace_size(m, n, t)
         ws = workspace("l0", nb)
         if timings is not None:

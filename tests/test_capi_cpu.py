@@ -111,6 +111,25 @@ def test_argument_errors_before_launch():
         assert lib.sisso_status_string(st)
 
 
+def test_batched_l0_argument_errors_before_launch():
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    # the record layout matches the C struct: 8 + 4*4 + 7*8 + 8 bytes
+    assert ctypes.sizeof(L.L0Problem) == 88
+    assert lib.sisso_l0_search_batched(None, 4, 2, 100, 500, 1e-10, None, None) == 1
+    assert lib.sisso_l0_search_batched(fake, 0, 2, 100, 500, 1e-10, None, None) == 2
+    assert lib.sisso_l0_search_batched(fake, L.MAX_BATCH + 1, 2, 100, 500, 1e-10, None, None) == 2
+    assert lib.sisso_l0_search_batched(fake, 4, 0, 100, 500, 1e-10, None, None) == 2
+    assert lib.sisso_l0_search_batched(fake, 4, L.MAX_D + 1, 100, 500, 1e-10, None, None) == 2
+    assert lib.sisso_l0_search_batched(fake, 4, 3, 2, 500, 1e-10, None, None) == 2        # m_max < D
+    assert lib.sisso_l0_search_batched(fake, 4, 2, L.MAX_SUBSPACE + 1, 500, 1e-10, None, None) == 2
+    assert lib.sisso_l0_search_batched(fake, 4, 2, 100, 1, 1e-10, None, None) == 2
+    assert lib.sisso_l0_search_batched(fake, 4, 2, 100, L.MAX_N + 1, 1e-10, None, None) == 2
+    assert lib.sisso_l0_search_batched(fake, 4, 2, 100, 500, -1.0, None, None) == 3
+    assert lib.sisso_l0_search_batched(fake, 4, 2, 100, 500, 1.0, None, None) == 3
+    assert lib.sisso_l0_search_batched(fake, 4, 2, 100, 500, float("nan"), None, None) == 3
+
+
 def test_batched_argument_errors_before_launch():
     lib = L.lib()
     full = dict(unary=["sq", "sqrt", "inv"], binary=["add", "sub", "mul", "div"])

@@ -147,3 +147,54 @@ def test_batched_c4_fit_matches_oracle_on_sampled_problems():
     for j, p in enumerate(ps):
         assert len(res[j]) == p.dmax
         assert res[j][1].rmse <= res[j][0].rmse
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_l0_search_batched_equals_single_problem_calls(D):
+    """sisso_l0_search_batched runs the single-problem SO bodies over a table:
+    every entry's outputs equal sisso_l0_search on that problem bit for bit,
+    and an entry with m < D is skipped (status SISSO_E_SHAPE, outputs left
+    untouched)."""
+    import ctypes
+    from paper_2410_01752_amd import _lib as L
+    from test_gpu_parity import _l0_gpu
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(40 + D)
+    shapes = [(150, 45), (97, 12), (300, 60), (64, D - 1 if D > 1 else 0), (211, 33)]
+    print(f"[l0 batched] D={D} shapes={shapes}", flush=True)
+    recs = (L.L0Problem * len(shapes))()
+    keep, ref = [], []
+    for j, (n, m) in enumerate(shapes):
+        F = rng.lognormal(size=(n, max(m, 1)))
+        y = F[:, 0] - 0.5 * F[:, -1] + 0.2 * rng.normal(size=n)
+        Ft = torch.as_tensor(np.ascontiguousarray(F.T), device=dev)
+        yt = torch.as_tensor(y, dtype=torch.float64, device=dev)
+        out = [torch.full((3,), -7, dtype=torch.int32, device=dev), torch.full((1,), -7.0, dtype=torch.float64,
+               device=dev), torch.full((4,), -7.0, dtype=torch.float64, device=dev),
+               torch.full((n,), -7.0, dtype=torch.float64, device=dev),
+               torch.full((4,), -7.0, dtype=torch.float64, device=dev)]
+        nb = L.lib().sisso_l0_workspace_size(max(m, 1), n, D)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        r = recs[j]
+        r.F, r.m, r.ld, r.n, r.reserved, r.y = Ft.data_ptr(), m, n, n, 0, yt.data_ptr()
+        r.out_tuple, r.out_sse, r.out_coef, r.out_resid, r.out_stats = [x.data_ptr() for x in out]
+        r.ws, r.ws_bytes = ws.data_ptr(), nb
+        keep.append((Ft, yt, out, ws))
+        ref.append(_l0_gpu(F, y, D) if m >= D else None)
+    tbl = torch.frombuffer(bytearray(recs), dtype=torch.uint8).to(dev)
+    status = torch.full((len(shapes),), -1, dtype=torch.int32, device=dev)
+    m_max, n_max = max(m for _, m in shapes), max(n for n, _ in shapes)
+    L.check(L.lib().sisso_l0_search_batched(tbl.data_ptr(), len(shapes), D, m_max, n_max, 1e-10,
+                                            status.data_ptr(), L.stream_handle()), "l0 batched")
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    for j, (n, m) in enumerate(shapes):
+        tup, sse, coef, res, stt = [x.cpu().numpy() for x in keep[j][2]]
+        if m < D:
+            assert st[j] == 2
+            assert np.all(tup == -7) and np.all(sse == -7.0) and np.all(res == -7.0)
+            continue
+        assert st[j] == 0
+        rt, rs, rc, rr, rst = ref[j]
+        assert np.array_equal(tup[:D], rt) and sse[0] == rs
+        assert np.array_equal(coef[:D + 1], rc) and np.array_equal(res, rr) and np.array_equal(stt, rst)
