@@ -117,6 +117,45 @@ def train_proposal(args, log):
     return params, info
 
 
+def learned_c5(params, args, log):
+    """The learned form on its own workload: a held-out d = 30 rung-3 problem
+    (seed 509, 1.51e11 candidates in the slice's binary block), one screening
+    against y per form; top-K' recall and speedup against exhaustive FP32.
+    The proposal is measured by itself here (no tail-check fallback)."""
+    import torch
+    from paper_2410_01752_amd import inputs as I
+    from paper_2410_01752_amd import learned as LN
+    from paper_2410_01752_amd.fit import Engine
+    q = I.config5(seed=509)
+    e = Engine(q.X, q.y, q.unary, q.binary, q.rung, q.rect)
+    bb, keep = e.binary_base(), 2048
+
+    def run(form, **kw):
+        ev = {}
+        ids, sc, cnt = e.screen(e.y, keep, None, begin=bb, precision=form, events=ev, **kw)
+        torch.cuda.synchronize()
+        c = int(cnt.item())
+        return ids[:c].cpu().numpy(), sc[:c].cpu().numpy(), sum(a.elapsed_time(b) for a, b in ev["binary"])
+
+    fi, fs, fms = run("fp32")
+    log(f"C5 fp32 {fms:.0f} ms")
+    out = {"workload": "held-out rung-3 problem: n=2000, d=30 LogNormal(0,0.5), seed 509; binary block of the "
+                       "one-sided slice against y",
+           "candidates": int(e.total - bb), "keep": keep, "fp32_ms": fms}
+    for frac in (0.05, 0.01):
+        e.set_pruner(LN.Pruner(e, params), frac=frac, n_sample=1 << 20, seed=3, min_recall=0.0)
+        gi, gs, ms = run("learned")
+        out[f"learned_{frac:g}"] = {"ms": ms, "recall": LN.recall_of(fi, fs, gi), "speedup_vs_fp32": fms / ms,
+                                    "tail_check": list(e.learned_log[-1])}
+        log(f"C5 learned {frac:g}: {ms:.0f} ms, recall {out[f'learned_{frac:g}']['recall']:.4f}")
+    bi, bs, bms = run("bf16", band=4 * keep)
+    out["bf16"] = {"ms": bms, "recall": LN.recall_of(fi, fs, bi), "speedup_vs_fp32": fms / bms}
+    log(f"C5 bf16 {bms:.0f} ms, recall {out['bf16']['recall']:.4f}")
+    del e
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_fit(log):
     """The 64-problem CV / bootstrap batch: one persistent screening launch per step."""
     import torch
@@ -182,10 +221,13 @@ def parse():
     ap.add_argument("--learned-fallback", default="bf16", choices=["fp32", "bf16"],
                     help="exhaustive form of a learned pass whose proposal fails the tail check")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem fit")
+    ap.add_argument("--c5", action="store_true",
+                    help="also screen a held-out d=30 problem with every form (learned at 5%% and 1%%); ~2 min")
     ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16", "learned"],
                     help="screening form of the rung-3 slice; auto = the fastest form whose recall against "
                          "the FP32 form is >= 0.99 and whose whole fit matches an FP32 fit, both measured here")
-    ap.add_argument("--band", type=int, default=2048, help="BF16 form: candidates rescored in FP32")
+    ap.add_argument("--band", type=int, default=0,
+                    help="BF16 form: candidates rescored in FP32 (0: 4 x K', at most 8192)")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 vs FP32 recall check")
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -248,7 +290,7 @@ def main():
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
     log(f"workload {args.workload} n={n} d={p.X.shape[1]} k={p.k} D={p.dmax}")
     keep0 = args.keep0 or (2048 if p.rect else 2 * p.k)
-    band = args.band
+    band = args.band or min(4 * keep0, 8192)
 
     if args.copy_calibration:
         # an elementwise kernel that reads 1 GiB and writes 1 GiB (a copy through
@@ -465,6 +507,10 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_fit(log)
+    if args.c5:
+        if learned_params is None:
+            learned_params, forms["learned_training"] = train_proposal(args, log)
+        out["learned_c5"] = learned_c5(learned_params, args, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)

@@ -87,6 +87,7 @@ typedef enum {
 #define SISSO_MAX_LEVELS 2
 #define SISSO_MAX_N 65536          /* samples per problem                    */
 #define SISSO_MAX_KEEP 2048        /* screened-list length per call          */
+#define SISSO_MAX_BAND 8192        /* BF16 candidates rescored exactly       */
 #define SISSO_MAX_SUBSPACE 1024    /* |S_t|                                  */
 #define SISSO_MAX_D 3              /* terms per SO model                     */
 #define SISSO_MAX_BATCH 4096       /* problems per batched call              */
@@ -250,10 +251,13 @@ sisso_status sisso_expand_score(const sisso_space *space, const sisso_score_args
  * scores.  The best `band` candidates by BF16 score are then rescored exactly
  * with the FP32 path's arithmetic and written as per-block lists into `ws`
  * (list_base as in sisso_expand_score), so sisso_topk returns FP32 scores.
- *   ops       u-side BF16 operands from sisso_prepare_bf16 (size from
+ *   ops       u-side column constants from sisso_prepare_bf16 (size from
  *             sisso_bf16_operands_size; residual-independent, once per problem).
  *   bws       per-call workspace (size from sisso_bf16_workspace_size).
- *   band      candidates rescored, keep <= band <= SISSO_MAX_KEEP.
+ *   band      candidates rescored, keep <= band <= SISSO_MAX_BAND.  Each
+ *             block keeps its best min(band, SISSO_MAX_KEEP) by BF16 score;
+ *             a band wider than keep is the margin that absorbs BF16 ranking
+ *             errors near the cutoff (ties of regrouped sums, for instance).
  * [cand_begin, cand_end) must lie in the binary block of the slice.  The
  * recall of the band against the FP32 screening is measured by the tests.
  * Errors: as sisso_expand_score; SISSO_E_UNSUPPORTED without a slice. */

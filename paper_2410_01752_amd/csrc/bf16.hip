@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     const float *__restrict__ r32, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
     const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
-    int64_t ut_hi, int64_t id_begin, int64_t id_end, void *lws, int lists_total, int keep, int cap)
+    int64_t ut_hi, int64_t id_begin, int64_t id_end, void *lws, int lists_total, int keep, int cap, int publish)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // two staging buffers
@@ -206,7 +206,10 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
     float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBT;
     __shared__ int lcnt, lpend;
     __shared__ float lthr;
+    __shared__ unsigned gdummy;                   // bound of a block that must not publish (stays 0)
     WsView W = ws_view(lws, lists_total, keep);
+    if (threadIdx.x == 0) gdummy = 0u;
+    unsigned *const gb = publish ? &W.h->gthr : &gdummy;
     BlockList Lst{lsc, lid, &lcnt, &lthr, cap, keep};
     if (threadIdx.x == 0) lpend = 0;
     list_init(Lst);
@@ -430,7 +433,7 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
             // not excluded, and the block's total.  When they all fit into the
             // list, every thread reserves its slots with one atomic and writes
             // them: no per-row barriers.
-            const float tb = fmaxf(*Lst.thr, load_gthr(&W.h->gthr));
+            const float tb = fmaxf(*Lst.thr, load_gthr(gb));
             auto admit = [&](float sc, int64_t id) {
                 return sc >= 0.0f && sc >= tb && (n_excl == 0 || !in_sorted_ids(excl, n_excl, id));
             };
@@ -452,7 +455,7 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
             const int total = lpend;                  // reset after the next barrier
             if (total == 0) continue;
             if (*Lst.cnt + total > Lst.cap) {
-                list_merge(Lst, &W.h->gthr);          // block-uniform: ends with a barrier
+                list_merge(Lst, gb);          // block-uniform: ends with a barrier
             }
             if (*Lst.cnt + total <= Lst.cap) {
                 if (mine) {
@@ -484,7 +487,7 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                 const int c = *Lst.cnt;
                 __syncthreads();
                 if (c + 5 * (int)blockDim.x <= Lst.cap) {
-                    const float t = fmaxf(*Lst.thr, load_gthr(&W.h->gthr));
+                    const float t = fmaxf(*Lst.thr, load_gthr(gb));
 #pragma unroll
                     for (int k = 0; k < 5; ++k)
                         if (sc[k] >= 0.0f && sc[k] >= t && (n_excl == 0 || !in_sorted_ids(excl, n_excl, fid[k]))) {
@@ -493,12 +496,12 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                             Lst.id[slot] = fid[k];
                         }
                 } else {
-                    list_offer<5>(Lst, sc, fid, &W.h->gthr, excl, n_excl);
+                    list_offer<5>(Lst, sc, fid, gb, excl, n_excl);
                 }
             }
         }
     }
-    list_flush(Lst, &W.h->gthr, W.sc + (size_t)blockIdx.x * keep, W.id + (size_t)blockIdx.x * keep);
+    list_flush(Lst, gb, W.sc + (size_t)blockIdx.x * keep, W.id + (size_t)blockIdx.x * keep);
 }
 
 // --------------------------------------------------------------- rescore
@@ -584,6 +587,10 @@ int bf_lists_cap(const sisso_space *s) { return bf_plan(s, 0, s->total).grid; }
 
 int bf_list_cap(int keep) { return next_pow2(keep + 256); }
 
+// Per-block list length of a band: the block keeps its best min(band, K'max)
+// (the LDS list); the grid-wide merge then takes the best `band` of all lists.
+int bf_block_keep(int band) { return band < SISSO_MAX_KEEP ? band : SISSO_MAX_KEEP; }
+
 bool space_ok(const sisso_space *s)
 {
     return s && s->total > 0 && s->rect && s->levels >= 1 && s->levels <= SISSO_MAX_LEVELS &&
@@ -617,10 +624,10 @@ extern "C" sisso_status sisso_prepare_bf16(const sisso_space *space, const sisso
 
 extern "C" size_t sisso_bf16_workspace_size(const sisso_space *space, const sisso_score_args *args, int32_t band)
 {
-    if (!space_ok(space) || !args || args->n < 2 || band < 1 || band > SISSO_MAX_KEEP) return 0;
+    if (!space_ok(space) || !args || args->n < 2 || band < 1 || band > SISSO_MAX_BAND) return 0;
     const int L = space->levels;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
-    return bf_ws_bytes(ucols, vcols, band, bf_lists_cap(space), band);
+    return bf_ws_bytes(ucols, vcols, band, bf_lists_cap(space), bf_block_keep(band));
 }
 
 extern "C" int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_score_args *args,
@@ -628,7 +635,7 @@ extern "C" int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const
 {
     (void)space;
     (void)args;
-    if (band < 1 || band > SISSO_MAX_KEEP) return -1;
+    if (band < 1 || band > SISSO_MAX_BAND) return -1;
     return (band + 255) / 256;
 }
 
@@ -642,7 +649,7 @@ sisso_status bf_check(const sisso_space *space, const sisso_score_args *args, in
     const int n = args->n;
     if (n < 2 || n > SISSO_MAX_N || args->ld32 < n || (args->ld32 % 4) != 0 || args->n_exclude < 0)
         return SISSO_E_SHAPE;
-    if (args->keep < 1 || args->keep > SISSO_MAX_KEEP || band < args->keep || band > SISSO_MAX_KEEP)
+    if (args->keep < 1 || args->keep > SISSO_MAX_KEEP || band < args->keep || band > SISSO_MAX_BAND)
         return SISSO_E_RANGE;
     if (bws_bytes < sisso_bf16_workspace_size(space, args, band)) return SISSO_E_WORKSPACE;
     return SISSO_OK;
@@ -686,8 +693,12 @@ extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_
     const FormSlots fs = form_slots(space);
     const BfPlan p = bf_plan(space, cand_begin, cand_end,
                              args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid);
-    const int keep_b = band;   // every block keeps the whole band: the grid-wide bound stays valid
+    // Every block keeps min(band, K'max).  Only a block that keeps the whole
+    // band may publish its threshold as the grid-wide bound (it is then a
+    // lower bound of the band-th best score).
+    const int keep_b = bf_block_keep(band);
     const int cap_b = bf_list_cap(keep_b);
+    const int publish = keep_b >= band ? 1 : 0;
     const int lcap = bf_lists_cap(space);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
@@ -696,7 +707,7 @@ extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_
         if (!allow_dynamic_lds(k_score_rect_bf16, smem)) return SISSO_E_UNSUPPORTED;
         hipLaunchKernelGGL(k_score_rect_bf16, dim3(p.grid), dim3(256), smem, st, *space, fs, n, args->pool32,
                            args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info, args->exclude, args->n_exclude, p.ut_lo, p.ut_hi,
-                           cand_begin, cand_end, w.lists, lcap, keep_b, cap_b);
+                           cand_begin, cand_end, w.lists, lcap, keep_b, cap_b, publish);
     }
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
@@ -716,7 +727,7 @@ extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
     BfWs w = bf_ws_view(bws, ucols, vcols, band);
     const FormSlots fs = form_slots(space);
-    sisso_status rs = topk_launch(w.lists, band, w.band_ids, w.band_sc, w.band_cnt, st, false);
+    sisso_status rs = topk_launch(w.lists, band, w.band_ids, w.band_sc, w.band_cnt, st, band > bf_block_keep(band));
     if (rs != SISSO_OK) return rs;
     const int keep = args->keep, cap = next_pow2(keep + 256);
     if (args->list_base == 0)

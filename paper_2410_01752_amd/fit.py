@@ -160,7 +160,7 @@ class Engine:
             raise L.SissoError("learned screening needs a pruner (Engine.set_pruner)")
         if use_bf16:
             self.prepare_bf16()
-            band = max(min(band or 4 * keep, L.MAX_KEEP), keep)
+            band = max(min(band or 4 * keep, L.MAX_BAND), keep)
         for name, b, e in parts:
             if b >= e:
                 continue
@@ -192,7 +192,7 @@ class Engine:
                     self.prepare_residual(r64)
                     if fallback == "bf16":
                         self.prepare_bf16()
-                        band = max(min(band or 4 * keep, L.MAX_KEEP), keep)
+                        band = max(min(band or 4 * keep, L.MAX_BAND), keep)
                 else:
                     if events is not None:
                         s0 = torch.cuda.Event(enable_timing=True)

@@ -84,6 +84,21 @@ def test_bf16_recall_c3_slice():
     _check(out, 400)
 
 
+@pytest.mark.parametrize("keep,band", [(2048, 8192), (700, 3000)])
+def test_bf16_band_wider_than_block_lists(keep, band):
+    """A band above SISSO_MAX_KEEP: each block keeps its best 2048 by BF16
+    score, publishes no grid-wide bound, and the grid-wide merge takes the
+    best `band` for the exact rescore (C3 shape, 1024 u operands)."""
+    p = I.config3()
+    print(f"[bf16] C3 slice keep {keep} band {band}", flush=True)
+    eng = _engine(p)
+    sp = O.Space(20, p.unary, p.binary, 2, True)
+    bb = eng.binary_base()
+    per_u = sp.pool(1) * 5
+    out = _both(eng, p.y, keep, band, begin=bb + 500 * per_u, end=bb + 1524 * per_u)
+    assert _check(out, keep) == 1.0
+
+
 def test_bf16_rescored_scores_match_oracle():
     """The rescored list of the BF16 form is FP32-exact: within 1e-6 of the oracle."""
     p = I.tiny(9, n=300, d=6, dist="lognormal", rect=True)
