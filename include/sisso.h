@@ -497,6 +497,66 @@ sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, 
                              double *out_coef, double *out_resid, double *out_stats, void *ws,
                              size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------- batched subspace steps
+ * The per-problem steps between screening and SO for a table of problems in
+ * a fixed number of launches (the records are DEVICE arrays; every field has
+ * the meaning of the single-problem argument of the same name).  Each entry's
+ * results equal those of the single-problem call.  out_status (device,
+ * nullable, n_problems int32) receives 0, or SISSO_E_SHAPE for an entry that
+ * was skipped (a NULL pointer or a size outside its range or the bounds).
+ *
+ * sisso_materialize_ids_stored per entry; count <= count_max [host]. */
+typedef struct {
+    int32_t n, count;
+    const double *pool1_64;
+    int64_t ld64;
+    const sisso_colstat *stats;
+    const int64_t *ids;
+    double *out;
+    int32_t ldo, reserved;
+    int32_t *valid;
+} sisso_eval_problem;
+
+sisso_status sisso_materialize_ids_batched(const sisso_space *space, int32_t stored_levels,
+                                           const sisso_eval_problem *problems, int32_t n_problems,
+                                           int32_t count_max, int32_t *out_status, void *stream);
+
+/* sisso_subspace_update per entry; m_prev + count_max <= nodes_max and
+ * k <= k_max [host] (nodes_max <= SISSO_MAX_SUBSPACE + SISSO_MAX_KEEP; the
+ * duplicate-class step's LDS, 24 B per node, must fit the device). */
+typedef struct {
+    const double *cand;
+    int32_t ldc, count_max;
+    const int64_t *cand_ids;
+    const int32_t *cand_valid;
+    const int32_t *count_dev;
+    const double *r;
+    int32_t n, lds;
+    double *sub;
+    int64_t *sub_ids;
+    int32_t m_prev, k;
+    int32_t *n_new, *n_classes;
+    void *ws;               /* sisso_subspace_workspace_size(n, count_max, m_prev) */
+    int64_t ws_bytes;
+} sisso_subspace_problem;
+
+sisso_status sisso_subspace_update_batched(const sisso_subspace_problem *problems, int32_t n_problems,
+                                           int32_t nodes_max, int32_t k_max, int32_t *out_status, void *stream);
+
+/* sisso_sort_subspace per entry; m <= m_max [host]. */
+typedef struct {
+    const double *src;
+    int32_t lds, m;
+    const int64_t *ids;
+    int32_t n, ldd;
+    double *dst;
+    int64_t *ids_sorted;
+    int32_t *perm;
+} sisso_sort_problem;
+
+sisso_status sisso_sort_subspace_batched(const sisso_sort_problem *problems, int32_t n_problems, int32_t m_max,
+                                         int32_t *out_status, void *stream);
+
 /* sisso_l0_search for many independent problems (cross-validation folds,
  * bootstrap resamples: Sec. 3 and 4 run such fits side by side) in seven
  * launches in all.  The table is a DEVICE array of n_problems records; every

@@ -69,6 +69,36 @@ class L0Problem(ctypes.Structure):
                 ("out_stats", ctypes.c_void_p), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_int64)]
 
 
+class EvalProblem(ctypes.Structure):
+    """sisso_eval_problem: one entry of a batched materialisation table."""
+    _fields_ = [("n", ctypes.c_int32), ("count", ctypes.c_int32), ("pool1_64", ctypes.c_void_p),
+                ("ld64", ctypes.c_int64), ("stats", ctypes.c_void_p), ("ids", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("ldo", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("valid", ctypes.c_void_p)]
+
+
+class SubspaceProblem(ctypes.Structure):
+    """sisso_subspace_problem: one entry of a batched subspace-update table."""
+    _fields_ = [("cand", ctypes.c_void_p), ("ldc", ctypes.c_int32), ("count_max", ctypes.c_int32),
+                ("cand_ids", ctypes.c_void_p), ("cand_valid", ctypes.c_void_p), ("count_dev", ctypes.c_void_p),
+                ("r", ctypes.c_void_p), ("n", ctypes.c_int32), ("lds", ctypes.c_int32), ("sub", ctypes.c_void_p),
+                ("sub_ids", ctypes.c_void_p), ("m_prev", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("n_new", ctypes.c_void_p), ("n_classes", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_int64)]
+
+
+class SortProblem(ctypes.Structure):
+    """sisso_sort_problem: one entry of a batched subspace-sort table."""
+    _fields_ = [("src", ctypes.c_void_p), ("lds", ctypes.c_int32), ("m", ctypes.c_int32), ("ids", ctypes.c_void_p),
+                ("n", ctypes.c_int32), ("ldd", ctypes.c_int32), ("dst", ctypes.c_void_p),
+                ("ids_sorted", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
+
+
+def device_table(recs, dev) -> torch.Tensor:
+    """A ctypes record array copied to device memory (a batched call's table)."""
+    return torch.frombuffer(bytearray(recs), dtype=torch.uint8).to(dev)
+
+
 COLSTAT_FLOATS = 8      # sisso_colstat: 8 floats
 RESID_DOUBLES = 4       # sisso_resid_info: 4 doubles
 
@@ -104,6 +134,9 @@ def lib():
         "sisso_expand_score_batched": (_i32, [sp, _vp, _i32, _i32, _i32, _vp, _sz, _vp]),
         "sisso_topk_batched": (_i32, [_vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp]),
         "sisso_l0_search_batched": (_i32, [_vp, _i32, _i32, _i32, _i32, ctypes.c_double, _vp, _vp]),
+        "sisso_materialize_ids_batched": (_i32, [sp, _i32, _vp, _i32, _i32, _vp, _vp]),
+        "sisso_subspace_update_batched": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp]),
+        "sisso_sort_subspace_batched": (_i32, [_vp, _i32, _i32, _vp, _vp]),
         "sisso_score_workspace_size": (_sz, [sp, ap]),
         "sisso_score_reset": (_i32, [_vp, _sz, _vp]),
         "sisso_expand_score": (_i32, [sp, ap, _i64, _i64, _vp, _sz, _vp]),
@@ -161,6 +194,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore",
             "sisso_materialize_ids_stored", "sisso_prepare_residual_batched", "sisso_batch_workspace_size",
             "sisso_batch_items", "sisso_expand_score_batched", "sisso_topk_batched", "sisso_l0_search_batched",
+            "sisso_materialize_ids_batched", "sisso_subspace_update_batched", "sisso_sort_subspace_batched",
             "sisso_mlp_param_count", "sisso_mlp_table_count", "sisso_encode_operands", "sisso_candidate_inputs",
             "sisso_score_ids", "sisso_mlp_forward", "sisso_mlp_workspace_size", "sisso_mlp_backward",
             "sisso_adam_step", "sisso_mlp_parts", "sisso_mlp_tables", "sisso_mlp_score_ids", "sisso_select_kth",

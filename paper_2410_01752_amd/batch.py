@@ -179,14 +179,16 @@ class Batch:
             while todo:
                 ids, sc, cnt, status = self.screen(todo, [r[p] for p in todo], [keep[p] for p in todo],
                                                    [states[p].exclude() for p in todo], grid=grid, events=timings)
+                self.update_batched(todo, states, ids, cnt, keep, r, k, ws_of)
                 for j, p in enumerate(todo):
-                    cand, valid = self.materialize(p, ids[j, :keep[p]])
-                    states[p].update(cand, ids[j], valid, cnt[j:j + 1], keep[p], r[p], k, ws_of(p))
                     lists[p] = (ids[j], sc[j], cnt[j:j + 1])
                 v = torch.stack([torch.cat([states[p].n_new, states[p].n_cls]) for p in todo]).cpu().numpy()
                 cv, sv = cnt.cpu().numpy(), status.cpu().numpy()
                 if np.any(sv != 0):
                     raise L.SissoError(f"sisso_topk_batched: problem status {sv.tolist()}")
+                uv = self._upd_hold[3].cpu().numpy()
+                if np.any(uv != 0):
+                    raise L.SissoError(f"batched materialise / subspace update: entry status {uv.tolist()}")
                 nxt = []
                 for j, p in enumerate(todo):
                     nn, nc, ct = int(v[j, 0]), int(v[j, 1]), int(cv[j])
@@ -204,12 +206,57 @@ class Batch:
             active = still
         return out
 
-    def so_batched(self, which, states, t: int, singular_tol: float, ws_of, timings=None):
-        """The SO step (Sec. 2.3) of every problem in `which` in one batched call."""
-        recs = (L.L0Problem * len(which))()
+    def update_batched(self, which, states, ids, cnt, keep, r, k: int, ws_of):
+        """FP64 materialisation of every screened list and the subspace updates
+        (Sec. 2.1 duplicates, Sec. 2.3 eq. subspace-expansion) of the problems in
+        `which` (row j of ids / cnt belongs to which[j]), in two batched calls."""
+        lib, st, P = L.lib(), L.stream_handle(self.dev), len(which)
+        erecs, srecs = (L.EvalProblem * P)(), (L.SubspaceProblem * P)()
+        hold = []
         for j, p in enumerate(which):
-            recs[j] = states[p].so_record(self.y[p], t, ws_of(p))
-        tbl = torch.frombuffer(bytearray(recs), dtype=torch.uint8).to(self.dev)
+            n, kp, s = self.n[p], keep[p], states[p]
+            out = torch.empty(kp * n, dtype=torch.float64, device=self.dev)
+            valid = torch.empty(kp, dtype=torch.int32, device=self.dev)
+            e = erecs[j]
+            e.n, e.count, e.pool1_64, e.ld64, e.stats = n, kp, L.ptr(self.pool1[p]), n, L.ptr(self.stats[p])
+            e.ids, e.out, e.ldo, e.reserved, e.valid = L.ptr(ids[j]), L.ptr(out), n, 0, L.ptr(valid)
+            ws = ws_of(p)("sub", lib.sisso_subspace_workspace_size(n, kp, s.m))
+            u = srecs[j]
+            u.cand, u.ldc, u.count_max, u.cand_ids, u.cand_valid = L.ptr(out), n, kp, L.ptr(ids[j]), L.ptr(valid)
+            u.count_dev, u.r, u.n, u.lds, u.sub, u.sub_ids = L.ptr(cnt[j:j + 1]), L.ptr(r[p]), n, n, L.ptr(s.sub), \
+                L.ptr(s.sub_ids)
+            u.m_prev, u.k, u.n_new, u.n_classes = s.m, k, L.ptr(s.n_new), L.ptr(s.n_cls)
+            u.ws, u.ws_bytes = L.ptr(ws), ws.numel()
+            hold += [out, valid]
+        et, ut = L.device_table(erecs, self.dev), L.device_table(srecs, self.dev)
+        status = torch.empty(2 * P, dtype=torch.int32, device=self.dev)
+        L.check(lib.sisso_materialize_ids_batched(ctypes.byref(self.space), self.levels - 1, L.ptr(et), P,
+                                                  max(keep[p] for p in which), L.ptr(status), st),
+                "sisso_materialize_ids_batched")
+        nodes_max = max(states[p].m + keep[p] for p in which)
+        L.check(lib.sisso_subspace_update_batched(L.ptr(ut), P, nodes_max, k, L.ptr(status[P:]), st),
+                "sisso_subspace_update_batched")
+        self._upd_hold = (hold, et, ut, status)      # alive until the stream has passed the calls
+
+    def so_batched(self, which, states, t: int, singular_tol: float, ws_of, timings=None):
+        """The SO step (Sec. 2.3) of every problem in `which` in one batched call
+        (after one batched sort of their subspaces into ascending id order)."""
+        P = len(which)
+        srt = (L.SortProblem * P)()
+        for j, p in enumerate(which):
+            s, n = states[p], self.n[p]
+            q = srt[j]
+            q.src, q.lds, q.m, q.ids, q.n, q.ldd = L.ptr(s.sub), n, s.m, L.ptr(s.sub_ids), n, n
+            q.dst, q.ids_sorted, q.perm = L.ptr(s.fsorted), L.ptr(s.ids_sorted), L.ptr(s.perm)
+        stt = L.device_table(srt, self.dev)
+        sst = torch.empty(P, dtype=torch.int32, device=self.dev)
+        L.check(L.lib().sisso_sort_subspace_batched(L.ptr(stt), P, max(states[p].m for p in which), L.ptr(sst),
+                                                    L.stream_handle(self.dev)), "sisso_sort_subspace_batched")
+        recs = (L.L0Problem * P)()
+        for j, p in enumerate(which):
+            recs[j] = states[p].so_record(self.y[p], t, ws_of(p), sort=False)
+        tbl = L.device_table(recs, self.dev)
+        self._sort_hold = (stt, sst)
         self._l0_table = tbl                     # alive until the results are read
         self._l0_status = torch.empty(len(which), dtype=torch.int32, device=self.dev)
         if timings is not None:
@@ -235,6 +282,9 @@ class Batch:
         st = self._l0_status.cpu().numpy()
         if np.any(st != 0):
             raise L.SissoError(f"sisso_l0_search_batched: entry status {st.tolist()}")
+        sv = self._sort_hold[1].cpu().numpy()
+        if np.any(sv != 0):
+            raise L.SissoError(f"sisso_sort_subspace_batched: entry status {sv.tolist()}")
         out, o_s, o_i, o_c = [], 0, 0, 0
         w = 2 * t + 6
         for p in which:

@@ -206,15 +206,14 @@ __device__ __forceinline__ double eval_node(const Node &nd, const double *p1, in
     return apply64(nd.op, x, y, ok);
 }
 
-// FP64 values of arbitrary features, one block per id.
-__global__ void __launch_bounds__(256) k_eval_ids(sisso_space s, int stored, int n, const double *__restrict__ p1,
-                                                  int64_t ld64, const sisso_colstat *__restrict__ stats,
-                                                  const int64_t *__restrict__ ids, int count,
-                                                  double *__restrict__ out, int ldo,
-                                                  int32_t *__restrict__ valid)
+// FP64 values of arbitrary features, one block per id (ids q0, q0 + qstep, ..).
+__device__ inline void eval_ids(const sisso_space &s, int stored, int n, const double *__restrict__ p1,
+                                int64_t ld64, const sisso_colstat *__restrict__ stats,
+                                const int64_t *__restrict__ ids, int count, double *__restrict__ out, int ldo,
+                                int32_t *__restrict__ valid, int q0, int qstep)
 {
     __shared__ BlockStats bs;
-    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+    for (int q = q0; q < count; q += qstep) {
         const int64_t id = ids[q];
         double *o = out + (size_t)q * ldo;
         if (id < 0 || id >= s.total) {
@@ -269,6 +268,34 @@ __global__ void __launch_bounds__(256) k_eval_ids(sisso_space s, int stored, int
         if (threadIdx.x == 0) valid[q] = ok ? 1 : 0;
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(256) k_eval_ids(sisso_space s, int stored, int n, const double *__restrict__ p1,
+                                                  int64_t ld64, const sisso_colstat *__restrict__ stats,
+                                                  const int64_t *__restrict__ ids, int count,
+                                                  double *__restrict__ out, int ldo,
+                                                  int32_t *__restrict__ valid)
+{
+    eval_ids(s, stored, n, p1, ld64, stats, ids, count, out, ldo, valid, blockIdx.x, gridDim.x);
+}
+
+// The same over a table of problems (blockIdx.y = problem).
+__device__ inline bool evalp_ok(const sisso_eval_problem &P, int count_max)
+{
+    return P.pool1_64 && P.stats && P.ids && P.out && P.valid && P.n >= 2 && P.n <= SISSO_MAX_N &&
+           P.ld64 >= P.n && P.ldo >= P.n && P.count >= 0 && P.count <= count_max;
+}
+
+__global__ void __launch_bounds__(256) k_eval_ids_batch(sisso_space s, int stored,
+                                                        const sisso_eval_problem *__restrict__ T, int count_max,
+                                                        int32_t *__restrict__ status)
+{
+    const sisso_eval_problem P = T[blockIdx.y];
+    const bool ok = evalp_ok(P, count_max);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && status) status[blockIdx.y] = ok ? SISSO_OK : SISSO_E_SHAPE;
+    if (!ok) return;
+    eval_ids(s, stored, P.n, P.pool1_64, P.ld64, P.stats, P.ids, P.count, P.out, P.ldo, P.valid, blockIdx.x,
+             gridDim.x);
 }
 
 // Centre a residual, round it to FP32 and record its sums (one block).
@@ -389,5 +416,19 @@ extern "C" sisso_status sisso_prepare_residual_batched(const sisso_problem *prob
     if (!problems) return SISSO_E_NULL;
     if (n_problems < 1 || n_problems > SISSO_MAX_BATCH) return SISSO_E_SHAPE;
     hipLaunchKernelGGL(k_prepare_residual_batch, dim3(n_problems), dim3(1024), 0, as_stream(stream), problems);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_materialize_ids_batched(const sisso_space *space, int32_t stored_levels,
+                                                      const sisso_eval_problem *problems, int32_t n_problems,
+                                                      int32_t count_max, int32_t *out_status, void *stream)
+{
+    if (!space || !problems) return SISSO_E_NULL;
+    if (space->total <= 0 || stored_levels < 1 || stored_levels > space->levels || n_problems < 1 ||
+        n_problems > SISSO_MAX_BATCH || count_max < 1 || count_max > SISSO_MAX_KEEP)
+        return SISSO_E_SHAPE;
+    const int gx = count_max < 256 ? count_max : 256;
+    hipLaunchKernelGGL(k_eval_ids_batch, dim3(gx, n_problems), dim3(256), 0, as_stream(stream), *space,
+                       stored_levels, problems, count_max, out_status);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }

@@ -54,7 +54,7 @@ __host__ __device__ inline SubWs sub_ws_view(void *ws, int n, int nodes)
     return w;
 }
 
-__global__ void __launch_bounds__(256) k_sub_resid(const double *__restrict__ r, int n, SubWs w)
+__device__ inline void sub_resid(const double *__restrict__ r, int n, SubWs w)
 {
     __shared__ double red[16];
     standardize_column(r, n, w.zr, nullptr, nullptr, nullptr, red);
@@ -62,13 +62,11 @@ __global__ void __launch_bounds__(256) k_sub_resid(const double *__restrict__ r,
 }
 
 // node q < m_prev: subspace column; else candidate q - m_prev.
-__global__ void __launch_bounds__(256) k_sub_standardize(const double *__restrict__ sub, int lds, int m_prev,
-                                                         const double *__restrict__ cand, int ldc,
-                                                         const int32_t *__restrict__ cvalid,
-                                                         const int32_t *__restrict__ count_dev, int n, SubWs w)
+__device__ inline void sub_standardize(const double *__restrict__ sub, int lds, int m_prev,
+                                       const double *__restrict__ cand, int ldc, const int32_t *__restrict__ cvalid,
+                                       const int32_t *__restrict__ count_dev, int n, SubWs w, int q)
 {
     __shared__ double red[16];
-    const int q = blockIdx.x;
     const bool is_c = q >= m_prev;
     const int ci = q - m_prev;
     const double *x = is_c ? cand + (size_t)ci * ldc : sub + (size_t)q * lds;
@@ -94,11 +92,11 @@ __global__ void __launch_bounds__(256) k_sub_standardize(const double *__restric
 }
 
 // Duplicate edges between candidate rows and all earlier nodes.
-__global__ void __launch_bounds__(256) k_sub_edges(int m_prev, int nodes, int n, SubWs w)
+__device__ inline void sub_edges(int m_prev, int nodes, int n, SubWs w, int bi, int bj)
 {
     __shared__ double As[kGK][kGT + 1];
     __shared__ double Bs[kGK][kGT + 1];
-    const int bi = blockIdx.y, bj = blockIdx.x;     // rows: nodes, cols: nodes
+    // rows: nodes, cols: nodes
     if (bj > bi) return;                              // only j <= i tiles
     if ((bi + 1) * kGT <= m_prev) return;             // rows all subspace members
     double acc[2][2];
@@ -122,11 +120,10 @@ __device__ __forceinline__ bool rank64_before(double sa, int64_t ia, double sb, 
 }
 
 // Components, classes, ranking and the new members (one block).
-__global__ void __launch_bounds__(1024) k_sub_classes(int m_prev, int nodes, const int64_t *__restrict__ cand_ids,
-                                                      int64_t *__restrict__ sub_ids, int k, int32_t *n_new,
-                                                      int32_t *n_classes, int *__restrict__ new_src, SubWs w)
+__device__ inline void sub_classes(int m_prev, int nodes, const int64_t *__restrict__ cand_ids,
+                                   int64_t *__restrict__ sub_ids, int k, int32_t *n_new, int32_t *n_classes,
+                                   int *__restrict__ new_src, SubWs w, unsigned char *smem)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     int *label = (int *)smem;                                   // nodes
     unsigned long long *rep = (unsigned long long *)(label + ((nodes + 1) & ~1));   // min id per root
     unsigned long long *best = rep + nodes;                     // max score bits per root
@@ -214,11 +211,10 @@ __global__ void __launch_bounds__(1024) k_sub_classes(int m_prev, int nodes, con
     if (threadIdx.x == 0) { *n_new = take; *n_classes = nc; }
 }
 
-__global__ void __launch_bounds__(256) k_sub_gather(const double *__restrict__ cand, int ldc,
-                                                    const int *__restrict__ new_src, const int32_t *__restrict__ n_new,
-                                                    int n, double *__restrict__ sub, int lds, int m_prev)
+__device__ inline void sub_gather(const double *__restrict__ cand, int ldc, const int *__restrict__ new_src,
+                                  const int32_t *__restrict__ n_new, int n, double *__restrict__ sub, int lds,
+                                  int m_prev, int q)
 {
-    const int q = blockIdx.x;
     if (q >= *n_new) return;
     const double *src = cand + (size_t)new_src[q] * ldc;
     double *dst = sub + (size_t)(m_prev + q) * lds;
@@ -226,8 +222,8 @@ __global__ void __launch_bounds__(256) k_sub_gather(const double *__restrict__ c
 }
 
 // Sort ids ascending (one block) and record the permutation.
-__global__ void __launch_bounds__(1024) k_sort_ids(const int64_t *__restrict__ ids, int m, int64_t *__restrict__ ids_sorted,
-                                                   int32_t *__restrict__ perm)
+__device__ inline void sort_ids(const int64_t *__restrict__ ids, int m, int64_t *__restrict__ ids_sorted,
+                                int32_t *__restrict__ perm)
 {
     __shared__ int64_t key[SISSO_MAX_SUBSPACE];
     __shared__ int pos[SISSO_MAX_SUBSPACE];
@@ -253,14 +249,155 @@ __global__ void __launch_bounds__(1024) k_sort_ids(const int64_t *__restrict__ i
     for (int i = threadIdx.x; i < m; i += blockDim.x) { ids_sorted[i] = key[i]; perm[i] = pos[i]; }
 }
 
+__device__ inline void gather_perm(const double *__restrict__ src, int lds, const int32_t *__restrict__ perm, int n,
+                                   double *__restrict__ dst, int ldd, int q)
+{
+    const double *s = src + (size_t)perm[q] * lds;
+    double *d = dst + (size_t)q * ldd;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) d[t] = s[t];
+}
+
+
+// ------------------------------------------------------- one problem
+
+__global__ void __launch_bounds__(256) k_sub_resid(const double *__restrict__ r, int n, SubWs w) { sub_resid(r, n, w); }
+
+__global__ void __launch_bounds__(256) k_sub_standardize(const double *__restrict__ sub, int lds, int m_prev,
+                                                         const double *__restrict__ cand, int ldc,
+                                                         const int32_t *__restrict__ cvalid,
+                                                         const int32_t *__restrict__ count_dev, int n, SubWs w)
+{
+    sub_standardize(sub, lds, m_prev, cand, ldc, cvalid, count_dev, n, w, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_sub_edges(int m_prev, int nodes, int n, SubWs w)
+{
+    sub_edges(m_prev, nodes, n, w, blockIdx.y, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_sub_classes(int m_prev, int nodes, const int64_t *__restrict__ cand_ids,
+                                                      int64_t *__restrict__ sub_ids, int k, int32_t *n_new,
+                                                      int32_t *n_classes, int *__restrict__ new_src, SubWs w)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    sub_classes(m_prev, nodes, cand_ids, sub_ids, k, n_new, n_classes, new_src, w, smem);
+}
+
+__global__ void __launch_bounds__(256) k_sub_gather(const double *__restrict__ cand, int ldc,
+                                                    const int *__restrict__ new_src, const int32_t *__restrict__ n_new,
+                                                    int n, double *__restrict__ sub, int lds, int m_prev)
+{
+    sub_gather(cand, ldc, new_src, n_new, n, sub, lds, m_prev, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_sort_ids(const int64_t *__restrict__ ids, int m,
+                                                   int64_t *__restrict__ ids_sorted, int32_t *__restrict__ perm)
+{
+    sort_ids(ids, m, ids_sorted, perm);
+}
+
 __global__ void __launch_bounds__(256) k_gather_perm(const double *__restrict__ src, int lds,
                                                      const int32_t *__restrict__ perm, int n,
                                                      double *__restrict__ dst, int ldd)
 {
-    const int q = blockIdx.x;
-    const double *s = src + (size_t)perm[q] * lds;
-    double *d = dst + (size_t)q * ldd;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) d[t] = s[t];
+    gather_perm(src, lds, perm, n, dst, ldd, blockIdx.x);
+}
+
+// ------------------------------------------------------- many problems
+//
+// The same bodies over a table: blockIdx.y (edges: blockIdx.z) is the
+// problem; blocks beyond a problem's own extent return at once.
+
+__host__ __device__ inline size_t sub_ws_total(int n, int count_max, int m_prev)
+{
+    return sub_ws_bytes(n, m_prev + count_max) + (size_t)SISSO_MAX_SUBSPACE * sizeof(int) + 256;
+}
+
+__device__ inline bool subp_ok(const sisso_subspace_problem &P, int nodes_max, int k_max)
+{
+    return P.cand && P.cand_ids && P.cand_valid && P.count_dev && P.r && P.sub && P.sub_ids && P.n_new &&
+           P.n_classes && P.ws && P.n >= 2 && P.n <= SISSO_MAX_N && P.ldc >= P.n && P.lds >= P.n &&
+           P.count_max >= 1 && P.count_max <= SISSO_MAX_KEEP && P.m_prev >= 0 && P.k >= 1 && P.k <= k_max &&
+           P.m_prev + P.k <= SISSO_MAX_SUBSPACE && P.m_prev + P.count_max <= nodes_max &&
+           P.ws_bytes >= (int64_t)sub_ws_total(P.n, P.count_max, P.m_prev);
+}
+
+__device__ inline SubWs subp_ws(const sisso_subspace_problem &P)
+{
+    return sub_ws_view(P.ws, P.n, P.m_prev + P.count_max);
+}
+
+__device__ inline int *subp_new_src(const sisso_subspace_problem &P)
+{
+    return (int *)((char *)P.ws + sub_ws_bytes(P.n, P.m_prev + P.count_max));
+}
+
+__global__ void __launch_bounds__(256) k_subb_resid(const sisso_subspace_problem *__restrict__ T, int nodes_max,
+                                                    int k_max, int32_t *__restrict__ status)
+{
+    const sisso_subspace_problem P = T[blockIdx.y];
+    const bool ok = subp_ok(P, nodes_max, k_max);
+    if (threadIdx.x == 0 && status) status[blockIdx.y] = ok ? SISSO_OK : SISSO_E_SHAPE;
+    if (!ok) return;
+    sub_resid(P.r, P.n, subp_ws(P));
+}
+
+__global__ void __launch_bounds__(256) k_subb_standardize(const sisso_subspace_problem *__restrict__ T, int nodes_max,
+                                                          int k_max)
+{
+    const sisso_subspace_problem P = T[blockIdx.y];
+    if (!subp_ok(P, nodes_max, k_max) || (int)blockIdx.x >= P.m_prev + P.count_max) return;
+    sub_standardize(P.sub, P.lds, P.m_prev, P.cand, P.ldc, P.cand_valid, P.count_dev, P.n, subp_ws(P), blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_subb_edges(const sisso_subspace_problem *__restrict__ T, int nodes_max,
+                                                    int k_max)
+{
+    const sisso_subspace_problem P = T[blockIdx.z];
+    const int nodes = P.m_prev + P.count_max, tiles = (nodes + kGT - 1) / kGT;
+    if (!subp_ok(P, nodes_max, k_max) || (int)blockIdx.x >= tiles || (int)blockIdx.y >= tiles) return;
+    sub_edges(P.m_prev, nodes, P.n, subp_ws(P), blockIdx.y, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_subb_classes(const sisso_subspace_problem *__restrict__ T, int nodes_max,
+                                                       int k_max)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const sisso_subspace_problem P = T[blockIdx.y];
+    if (!subp_ok(P, nodes_max, k_max)) return;
+    sub_classes(P.m_prev, P.m_prev + P.count_max, P.cand_ids, P.sub_ids, P.k, P.n_new, P.n_classes,
+                subp_new_src(P), subp_ws(P), smem);
+}
+
+__global__ void __launch_bounds__(256) k_subb_gather(const sisso_subspace_problem *__restrict__ T, int nodes_max,
+                                                     int k_max)
+{
+    const sisso_subspace_problem P = T[blockIdx.y];
+    if (!subp_ok(P, nodes_max, k_max) || (int)blockIdx.x >= P.k) return;
+    sub_gather(P.cand, P.ldc, subp_new_src(P), P.n_new, P.n, P.sub, P.lds, P.m_prev, blockIdx.x);
+}
+
+__device__ inline bool sortp_ok(const sisso_sort_problem &P, int m_max)
+{
+    return P.src && P.ids && P.dst && P.ids_sorted && P.perm && P.m >= 1 && P.m <= m_max && P.n >= 1 &&
+           P.lds >= P.n && P.ldd >= P.n;
+}
+
+__global__ void __launch_bounds__(1024) k_sortb_ids(const sisso_sort_problem *__restrict__ T, int m_max,
+                                                    int32_t *__restrict__ status)
+{
+    const sisso_sort_problem P = T[blockIdx.y];
+    const bool ok = sortp_ok(P, m_max);
+    if (threadIdx.x == 0 && status) status[blockIdx.y] = ok ? SISSO_OK : SISSO_E_SHAPE;
+    if (!ok) return;
+    sort_ids(P.ids, P.m, P.ids_sorted, P.perm);
+}
+
+__global__ void __launch_bounds__(256) k_sortb_gather(const sisso_sort_problem *__restrict__ T, int m_max)
+{
+    const sisso_sort_problem P = T[blockIdx.y];
+    if (!sortp_ok(P, m_max) || (int)blockIdx.x >= P.m) return;
+    gather_perm(P.src, P.lds, P.perm, P.n, P.dst, P.ldd, blockIdx.x);
 }
 
 }  // namespace sisso
@@ -272,7 +409,13 @@ static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 extern "C" size_t sisso_subspace_workspace_size(int32_t n, int32_t count, int32_t m_prev)
 {
     if (n < 2 || count < 0 || m_prev < 0) return 0;
-    return sub_ws_bytes(n, m_prev + count) + (size_t)SISSO_MAX_SUBSPACE * sizeof(int) + 256;
+    return sub_ws_total(n, count, m_prev);
+}
+
+static size_t classes_smem(int nodes)
+{
+    return (size_t)((nodes + 1) & ~1) * sizeof(int) + (size_t)nodes * 2 * sizeof(unsigned long long) +
+           (size_t)next_pow2(nodes) * (sizeof(double) + sizeof(int64_t));
 }
 
 extern "C" sisso_status sisso_subspace_update(const double *cand, int32_t ldc, const int64_t *cand_ids,
@@ -297,8 +440,7 @@ extern "C" sisso_status sisso_subspace_update(const double *cand, int32_t ldc, c
                        count_dev, n, w);
     const int tiles = (nodes + kGT - 1) / kGT;
     hipLaunchKernelGGL(k_sub_edges, dim3(tiles, tiles), dim3(256), 0, st, m_prev, nodes, n, w);
-    const size_t smem = (size_t)((nodes + 1) & ~1) * sizeof(int) + (size_t)nodes * 2 * sizeof(unsigned long long) +
-                        (size_t)next_pow2(nodes) * (sizeof(double) + sizeof(int64_t));
+    const size_t smem = classes_smem(nodes);
     if (smem > 160 * 1024) return SISSO_E_SHAPE;
     if (!allow_dynamic_lds(k_sub_classes, smem)) return SISSO_E_UNSUPPORTED;
     hipLaunchKernelGGL(k_sub_classes, dim3(1), dim3(1024), smem, st, m_prev, nodes, cand_ids, sub_ids, k, n_new,
@@ -316,5 +458,40 @@ extern "C" sisso_status sisso_sort_subspace(const double *src, int32_t lds, cons
     hipStream_t st = as_stream(stream);
     hipLaunchKernelGGL(k_sort_ids, dim3(1), dim3(1024), 0, st, ids, m, ids_sorted, perm_out);
     hipLaunchKernelGGL(k_gather_perm, dim3(m), dim3(256), 0, st, src, lds, perm_out, n, dst, ldd);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_subspace_update_batched(const sisso_subspace_problem *problems, int32_t n_problems,
+                                                      int32_t nodes_max, int32_t k_max, int32_t *out_status,
+                                                      void *stream)
+{
+    if (!problems) return SISSO_E_NULL;
+    if (n_problems < 1 || n_problems > SISSO_MAX_BATCH || nodes_max < 1 ||
+        nodes_max > SISSO_MAX_SUBSPACE + SISSO_MAX_KEEP || k_max < 1 || k_max > SISSO_MAX_SUBSPACE)
+        return SISSO_E_SHAPE;
+    const size_t smem = classes_smem(nodes_max);
+    if (smem > 160 * 1024) return SISSO_E_SHAPE;
+    if (!allow_dynamic_lds(k_subb_classes, smem)) return SISSO_E_UNSUPPORTED;
+    hipStream_t st = as_stream(stream);
+    const unsigned P = (unsigned)n_problems;
+    const int tiles = (nodes_max + kGT - 1) / kGT;
+    hipLaunchKernelGGL(k_subb_resid, dim3(1, P), dim3(256), 0, st, problems, nodes_max, k_max, out_status);
+    hipLaunchKernelGGL(k_subb_standardize, dim3(nodes_max, P), dim3(256), 0, st, problems, nodes_max, k_max);
+    hipLaunchKernelGGL(k_subb_edges, dim3(tiles, tiles, P), dim3(256), 0, st, problems, nodes_max, k_max);
+    hipLaunchKernelGGL(k_subb_classes, dim3(1, P), dim3(1024), smem, st, problems, nodes_max, k_max);
+    hipLaunchKernelGGL(k_subb_gather, dim3(k_max, P), dim3(256), 0, st, problems, nodes_max, k_max);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_sort_subspace_batched(const sisso_sort_problem *problems, int32_t n_problems,
+                                                    int32_t m_max, int32_t *out_status, void *stream)
+{
+    if (!problems) return SISSO_E_NULL;
+    if (n_problems < 1 || n_problems > SISSO_MAX_BATCH || m_max < 1 || m_max > SISSO_MAX_SUBSPACE)
+        return SISSO_E_SHAPE;
+    hipStream_t st = as_stream(stream);
+    const unsigned P = (unsigned)n_problems;
+    hipLaunchKernelGGL(k_sortb_ids, dim3(1, P), dim3(1024), 0, st, problems, m_max, out_status);
+    hipLaunchKernelGGL(k_sortb_gather, dim3(m_max, P), dim3(256), 0, st, problems, m_max);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }

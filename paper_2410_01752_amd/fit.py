@@ -353,9 +353,11 @@ class FitState:
                                             n, L.ptr(self.ids_sorted), L.ptr(self.perm), st),
                 "sisso_sort_subspace")
 
-    def so_record(self, y, t: int, workspace) -> "L.L0Problem":
-        """Sort S_t and return this problem's sisso_l0_problem record."""
-        self.sort()
+    def so_record(self, y, t: int, workspace, sort: bool = True) -> "L.L0Problem":
+        """Sort S_t (unless done by a batched call) and return this problem's
+        sisso_l0_problem record."""
+        if sort:
+            self.sort()
         n, m = self.n, self.m
         ws = workspace("l0", L.lib().sisso_l0_workspace_size(m, n, t))
         rec = L.L0Problem()

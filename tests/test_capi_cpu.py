@@ -130,6 +130,37 @@ def test_batched_l0_argument_errors_before_launch():
     assert lib.sisso_l0_search_batched(fake, 4, 2, 100, 500, float("nan"), None, None) == 3
 
 
+def test_batched_subspace_steps_argument_errors_before_launch():
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    s2 = L.make_space(4, ["sq", "sqrt", "inv"], ["add", "sub", "mul", "div"], 2, False)
+    # record layouts match the C structs
+    assert ctypes.sizeof(L.EvalProblem) == 64
+    assert ctypes.sizeof(L.SubspaceProblem) == 112
+    assert ctypes.sizeof(L.SortProblem) == 56
+    m = lib.sisso_materialize_ids_batched
+    assert m(None, 1, fake, 4, 100, None, None) == 1
+    assert m(ctypes.byref(s2), 1, None, 4, 100, None, None) == 1
+    assert m(ctypes.byref(s2), 0, fake, 4, 100, None, None) == 2          # stored levels
+    assert m(ctypes.byref(s2), 3, fake, 4, 100, None, None) == 2
+    assert m(ctypes.byref(s2), 1, fake, 0, 100, None, None) == 2
+    assert m(ctypes.byref(s2), 1, fake, L.MAX_BATCH + 1, 100, None, None) == 2
+    assert m(ctypes.byref(s2), 1, fake, 4, 0, None, None) == 2
+    assert m(ctypes.byref(s2), 1, fake, 4, L.MAX_KEEP + 1, None, None) == 2
+    u = lib.sisso_subspace_update_batched
+    assert u(None, 4, 200, 50, None, None) == 1
+    assert u(fake, 0, 200, 50, None, None) == 2
+    assert u(fake, 4, 0, 50, None, None) == 2
+    assert u(fake, 4, L.MAX_SUBSPACE + L.MAX_KEEP + 1, 50, None, None) == 2
+    assert u(fake, 4, 200, 0, None, None) == 2
+    assert u(fake, 4, 200, L.MAX_SUBSPACE + 1, None, None) == 2
+    s = lib.sisso_sort_subspace_batched
+    assert s(None, 4, 100, None, None) == 1
+    assert s(fake, 0, 100, None, None) == 2
+    assert s(fake, 4, 0, None, None) == 2
+    assert s(fake, 4, L.MAX_SUBSPACE + 1, None, None) == 2
+
+
 def test_batched_argument_errors_before_launch():
     lib = L.lib()
     full = dict(unary=["sq", "sqrt", "inv"], binary=["add", "sub", "mul", "div"])
