@@ -5,9 +5,11 @@ datasets) share the operator set and rung, so one persistent launch screens
 all of them: sisso_prepare_residual_batched -> sisso_expand_score_batched ->
 sisso_topk_batched per step t of Sec. 2.3.  Each problem stores only its pool
 P_1; the level-2 features are generated in registers by the screening
-kernel.  The subspace update runs per problem on the same stream
-(FitState); the SO step of every problem is one sisso_l0_search_batched call,
-and the per-step results of the whole batch come back in a few copies.
+kernel.  The FP64 materialisation of the screened lists, the subspace
+updates, the subspace sorts and the SO step then run as one batched call each
+(sisso_materialize_ids_batched, sisso_subspace_update_batched,
+sisso_sort_subspace_batched, sisso_l0_search_batched) over the problems'
+FitState buffers, and the per-step results come back in a few copies.
 """
 from __future__ import annotations
 
