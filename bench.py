@@ -262,7 +262,8 @@ def cpu_baseline(p, budget_s: float):
 
 
 MI355X_BF16_TFLOPS = 2500.0               # dense MFMA
-GEMMS_PER_PAIR = 12                       # BF16 form: 12 contractions over the samples per (u, v) pair
+CONTRACTIONS_PER_PAIR = 9            # algorithmic: (u v, u (v r), u^2 v^2) for u * v, u / v and v / u
+EXECUTED_MFMA_GEMMS = 12 * 3         # the kernel: 12 centred contractions x 3 hi/lo split products
 
 
 def recall_of(fi, fs, bi, tol=1e-6):
@@ -445,12 +446,15 @@ def main():
         ks = ev_ms(timings, "bf16_screen")
         kernel_ms = sum(ks) / len(ks)
         pairs = n_bin // eng.space.n_slots
-        flops = 2.0 * GEMMS_PER_PAIR * n * pairs
+        flops = 2.0 * CONTRACTIONS_PER_PAIR * n * pairs
         achieved = flops / (kernel_ms * 1e-3) / 1e12
+        executed = 2.0 * EXECUTED_MFMA_GEMMS * n * pairs / (kernel_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "k_score_rect_bf16", "achieved": achieved,
                 "peak": MI355X_BF16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MI355X_BF16_TFLOPS,
                 "traffic": None, "avg_launch_ms": kernel_ms, "units_per_launch": pairs,
-                "per_unit": f"{GEMMS_PER_PAIR} GEMMs x 2 flops x n={n} samples per (u, v) pair"}
+                "per_unit": f"{CONTRACTIONS_PER_PAIR} contractions x 2 flops x n={n} samples per (u, v) pair "
+                            f"(= {2 * CONTRACTIONS_PER_PAIR * n / 5:.0f} flops per candidate of the 5 forms)",
+                "executed_mfma_tflops": executed, "executed_frac": executed / MI355X_BF16_TFLOPS}
     elif n_bin > 0:
         kb = ev_ms(timings, "binary")
         kernel_ms = sum(kb) / len(kb)
