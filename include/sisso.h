@@ -244,9 +244,10 @@ sisso_status sisso_expand_score(const sisso_space *space, const sisso_score_args
                                 int64_t cand_begin, int64_t cand_end, void *ws, size_t ws_bytes,
                                 void *stream);
 
-/* BF16 screening of the one-sided slice's binary block (spec form of
- * Sec. 2.2's screening on matrix cores).  With centred operands the sums of
- * every form op(u, v) are contractions over the samples; twelve GEMMs per tile
+/* BF16 screening of the one-sided slice's binary block (Sec. 2.2's screening
+ * carried out on matrix cores, an addition to the paper's method).  With
+ * centred operands the sums of every form op(u, v) are contractions over the
+ * samples; twelve GEMMs per tile
  * of (u, v) pairs run on BF16 MFMA with FP32 accumulation and give approximate
  * scores.  The best `band` candidates by BF16 score are then rescored exactly
  * with the FP32 path's arithmetic and written as per-block lists into `ws`
