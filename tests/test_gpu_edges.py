@@ -1,0 +1,66 @@
+"""Degenerate and boundary cases of the screening and fitting path against the
+FP64 oracle: the smallest sample counts (n below one float4 group, ragged
+chunks, every feature tied at |corr| = 1), lists longer than the number of
+valid candidates, K' = 1, a constant residual (no candidate has a defined
+correlation) and whole fits at small n."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2410_01752_amd import inputs as I
+
+from test_gpu_parity import _compare_fit, _engine, _screen, assert_topk_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n", [3, 5, 7])
+def test_smallest_sample_counts_full_rect_space(n):
+    p = I.tiny(21, n=n, d=3, dist="lognormal", rect=True)
+    print(f"[edges] rect space n={n}", flush=True)
+    eng = _engine(p)
+    sp = O.Space(3, p.unary, p.binary, 2, True)
+    keep = 300
+    gi, gs = _screen(eng, p.y, keep)
+    oi, os_ = sp.sis(p.X, p.y, keep)
+    assert_topk_parity(sp, p.X, p.y, gi, gs, oi, os_, keep)
+
+
+def test_list_longer_than_the_valid_candidates_and_keep_one():
+    p = I.tiny(22, n=20, d=2, dist="lognormal", rect=False, unary=("sq",), binary=("add", "mul"), rung=1)
+    print("[edges] 6 valid candidates", flush=True)
+    eng = _engine(p)
+    sp = O.Space(2, p.unary, p.binary, 1, False)
+    gi, gs = _screen(eng, p.y, 100)
+    oi, os_ = sp.sis(p.X, p.y, 100)
+    assert len(oi) < 100 and np.array_equal(gi, oi)
+    assert np.max(np.abs(gs - os_)) <= 1e-6
+    g1, s1 = _screen(eng, p.y, 1)
+    assert len(g1) == 1 and g1[0] == oi[0]
+
+
+def test_constant_residual_admits_nothing():
+    p = I.tiny(23, n=40, d=3, dist="lognormal", rect=True)
+    print("[edges] constant residual", flush=True)
+    eng = _engine(p)
+    sp = O.Space(3, p.unary, p.binary, 2, True)
+    r = np.full(40, 2.5)
+    assert len(sp.sis(p.X, r, 50)[0]) == 0
+    gi, gs = _screen(eng, r, 50)
+    assert len(gi) == 0
+    for form in ("bf16",):
+        r64 = torch.as_tensor(r, dtype=torch.float64, device=eng.dev)
+        ids, sc, cnt = eng.screen(r64, 50, None, begin=eng.binary_base(), precision=form)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == 0
+
+
+@pytest.mark.parametrize("n", [6, 9])
+def test_fit_at_small_n_matches_oracle(n):
+    p = I.tiny(24, n=n, d=3, dist="uniform", rect=False, k=3, dmax=2)
+    print(f"[edges] fit n={n}", flush=True)
+    eng = _engine(p)
+    res = eng.fit(p.k, p.dmax)
+    ref = O.fit(p.X, p.y, p.unary, p.binary, p.rung, p.rect, p.k, p.dmax)
+    _compare_fit(p, res, ref)
