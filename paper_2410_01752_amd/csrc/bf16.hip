@@ -14,13 +14,16 @@
 // need only G[U~, V~].  Twelve GEMMs over a tile of (u, v) pairs, with the
 // per-column terms folded into the v-side operands, give all five forms.
 // They run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Every operand
-// is stored as two BF16 parts, x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
-// and each product is hi*hi + hi*lo + lo*hi: BF16 alone (8-bit mantissa) cannot
-// resolve forms whose centred terms cancel (ratios of strongly related operands,
-// e.g. (x0 x1 x2)/(x0 x1)), the split form keeps about 16 bits.  Sums of single
-// columns are exact (FP64).  The BF16 scores only select a band; every
-// candidate of the band is rescored with the plain FP32 kernel's arithmetic
-// (shared functions), so reported scores are the FP32 path's scores.
+// variant enters as two BF16 parts, x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
+// formed from the FP32 pool values while a sample chunk is staged into LDS
+// (nothing BF16 is stored in HBM), and each product is hi*hi + hi*lo + lo*hi:
+// BF16 alone (8-bit mantissa) cannot resolve forms whose centred terms cancel
+// (ratios of strongly related operands, e.g. (x0 x1 x2)/(x0 x1)), the split
+// form keeps about 16 bits.  Sums of single columns are exact (FP64).  The BF16
+// scores only select a band (a margin wider than the list, since BF16 noise
+// reorders near-ties); every candidate of the band is rescored with the plain
+// FP32 kernel's arithmetic (shared functions), so reported scores are the FP32
+// path's scores.
 #include "tiles.hpp"
 
 namespace sisso {
