@@ -284,6 +284,39 @@ sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score
                                      int64_t cand_begin, int64_t cand_end, void *bws, size_t bws_bytes,
                                      void *ws, size_t ws_bytes, void *stream);
 
+/* Residual-independent moments of the BF16 screen.  The weights of Sec. 2.2
+ * take the columns of the feature matrix standardised (zero mean, unit
+ * variance); that standardisation depends on the features alone, not on the
+ * residual, so the SIS passes of one fit (one per SO dimension) share it.
+ * Likewise, of the twelve GEMMs of the BF16 screen, nine give per-pair sums
+ * that do not involve the residual.  A screen in mode SISSO_MOMENTS_WRITE runs all twelve and also
+ * stores, for every (u, v) pair of the tiles it covers, six FP32 values (sum h
+ * and the variance of u v, u/v and v/u); a screen in mode SISSO_MOMENTS_READ
+ * loads them and runs only the three residual GEMMs.  The approximate scores
+ * of a READ screen equal, bit for bit, those of a WRITE (or a plain) screen of
+ * the same residual, so the band, the rescore and the result are the same.
+ *   moments        device buffer of sisso_bf16_moments_size(space, n) bytes
+ *                  (24 bytes per pair of the padded 64 x 64 tiles: about 69 GB
+ *                  for 2.65M x 1030 operand pairs), owned by the caller.
+ *   mode           SISSO_MOMENTS_NONE (moments unused, may be NULL: the same
+ *                  as sisso_bf16_screen), SISSO_MOMENTS_WRITE or
+ *                  SISSO_MOMENTS_READ.
+ * A READ screen requires an earlier WRITE screen over the same pools, the same
+ * operands (`ops`) and a candidate range covering its own, into the same
+ * buffer; any residual, keep, band or exclusion list may differ.  The library
+ * does not track this: reading moments that were never written gives wrong
+ * scores, not an error.
+ * Errors: as sisso_bf16_screen; SISSO_E_RANGE (unknown mode), SISSO_E_NULL
+ * (moments NULL in mode WRITE or READ), SISSO_E_WORKSPACE (moments_bytes
+ * smaller than the size query). */
+typedef enum { SISSO_MOMENTS_NONE = 0, SISSO_MOMENTS_WRITE = 1, SISSO_MOMENTS_READ = 2 } sisso_moments_mode;
+size_t sisso_bf16_moments_size(const sisso_space *space, int32_t n);
+sisso_status sisso_bf16_screen_moments(const sisso_space *space, const sisso_score_args *args,
+                                       const void *ops, size_t ops_bytes, int32_t band,
+                                       int64_t cand_begin, int64_t cand_end, void *moments,
+                                       size_t moments_bytes, int32_t mode, void *bws, size_t bws_bytes,
+                                       void *stream);
+
 /* Merge the workspace's per-block lists into the global best k (score desc,
  * id asc) (Sec. 2.2, eq. sis-method).  out_ids / out_scores: k entries;
  * out_count: number written (< k when fewer valid features exist).

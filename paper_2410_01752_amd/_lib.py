@@ -21,6 +21,7 @@ OPNAME = {v: k for k, v in OPCODE.items()}
 MAX_UNARY, MAX_BINARY, MAX_LEVELS = 8, 4, 2
 MAX_N, MAX_KEEP, MAX_SUBSPACE, MAX_D = 65536, 2048, 1024, 3
 MAX_BAND = 8192
+MOMENTS_NONE, MOMENTS_WRITE, MOMENTS_READ = 0, 1, 2
 MAX_BATCH = 4096
 ENC, MLP_IN, MLP_HIDDEN = 64, 144, 256
 MLP_PARAMS = 256 * 144 + 256 + 256 + 1
@@ -157,6 +158,8 @@ def lib():
         "sisso_bf16_residual": (_i32, [sp, ap, _i32, _vp, _sz, _vp]),
         "sisso_bf16_screen": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _vp]),
         "sisso_bf16_rescore": (_i32, [sp, ap, _i32, _vp, _sz, _vp, _sz, _vp]),
+        "sisso_bf16_moments_size": (_sz, [sp, _i32]),
+        "sisso_bf16_screen_moments": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _i32, _vp, _sz, _vp]),
         "sisso_mlp_param_count": (_i32, []),
         "sisso_mlp_table_count": (_i32, []),
         "sisso_encode_operands": (_i32, [sp, ap, _i64, _i64, _vp, _vp]),
@@ -191,7 +194,8 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_subspace_update", "sisso_l0_workspace_size", "sisso_l0_search",
             "sisso_sort_subspace", "sisso_bf16_operands_size", "sisso_prepare_bf16",
             "sisso_bf16_workspace_size", "sisso_expand_score_bf16_lists", "sisso_expand_score_bf16",
-            "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore",
+            "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore", "sisso_bf16_moments_size",
+            "sisso_bf16_screen_moments",
             "sisso_materialize_ids_stored", "sisso_prepare_residual_batched", "sisso_batch_workspace_size",
             "sisso_batch_items", "sisso_expand_score_batched", "sisso_topk_batched", "sisso_l0_search_batched",
             "sisso_materialize_ids_batched", "sisso_subspace_update_batched", "sisso_sort_subspace_batched",

@@ -26,6 +26,9 @@
 // path's scores.
 #include "tiles.hpp"
 
+#include <type_traits>
+#include <utility>
+
 namespace sisso {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
@@ -33,21 +36,54 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kUVar = 4;      // U~, U~^2, Z~, Z~^2
-constexpr int kVVar = 8;      // V~, V~ r, P, Q, W~, W~ r, Pw, Qw
 constexpr int kSplit = 2;     // BF16 parts per operand (hi, lo)
 constexpr int kBT = 64;       // (u, v) pairs per block side: 2 x 2 waves of 32 x 32
 constexpr int kKC = 16;       // samples per LDS stage (one MFMA k-step)
-constexpr int kKR = kKC;       // bf16 per LDS row: one chunk of samples of one column
+constexpr int kKR = kKC;      // bf16 per LDS row: one chunk of samples of one column
 constexpr int kPlane = kBT * kKR;                   // bf16 per staged plane (64 columns)
-constexpr int kPA = kUVar * kSplit, kPB = kVVar * kSplit;   // staged planes per side
-constexpr int kStage = (kPA + kPB) * kPlane;        // bf16 per staging buffer
-constexpr int kNG = 12;       // GEMMs per tile
+constexpr int kMom = 6;       // residual-independent moments kept per (u, v) pair
+constexpr size_t kMomTile = (size_t)4 * 16 * kMom * 64;   // floats per (u tile, v tile)
 
-// GEMM g multiplies u-side variant A(g) with v-side variant B(g):
-//   g:  0   1    2   3   4   5    6    7   8   9    10   11
-//   A:  U~  U~   U~2 U~  U~  U~   U~2  U~  Z~  Z~   Z~2  Z~
-//   B:  V~  V~r  P   Q   W~  W~r  Pw   Qw  V~  V~r  P    Q
+// Moments modes of the screen.  kBfFull and kBfWrite run all twelve GEMMs;
+// kBfWrite also stores, per pair, the sums that do not involve the residual
+// (sum h of u v, u/v and v/u, the variances of u v, u/v and v/u).  kBfRead
+// loads them and runs only the three residual GEMMs.
+enum BfMode { kBfFull = 0, kBfWrite = 1, kBfRead = 2 };
+
+// GEMM g multiplies u-side variant A(g) with v-side variant B(g).
+//   full:  g:  0   1    2   3   4   5    6    7   8   9    10   11
+//          A:  U~  U~   U~2 U~  U~  U~   U~2  U~  Z~  Z~   Z~2  Z~
+//          B:  V~  V~r  P   Q   W~  W~r  Pw   Qw  V~  V~r  P    Q
+//   read:  g:  0    1    2           (= full 1, 5, 9)
+//          A:  U~   U~   Z~
+//          B:  V~r  W~r  V~r
+template <int MODE> struct BfShape {
+    static constexpr bool kRead = MODE == kBfRead;
+    static constexpr int kUVar = kRead ? 2 : 4;     // U~, [U~^2,] Z~, [Z~^2]
+    static constexpr int kVVar = kRead ? 2 : 8;     // [V~,] V~ r, [P, Q, W~,] W~ r, [Pw, Qw]
+    static constexpr int kNG = kRead ? 3 : 12;      // GEMMs per tile
+    static constexpr int kPA = kUVar * kSplit, kPB = kVVar * kSplit;   // staged planes per side
+    static constexpr int kStage = (kPA + kPB) * kPlane;                // bf16 per staging buffer
+    // chunks between the global load of a chunk and the MFMAs that use it
+    static constexpr int kAhead = 2;
+    // staging buffers: the read form's LDS (one buffer) admits two blocks per CU,
+    // whose waves overlap one another's staging, barriers and MFMAs
+    static constexpr int kNBuf = kRead ? 1 : 2, kMinBlocks = kRead ? 2 : 1;
+    // accumulator of the residual contraction of u v, u/v and v/u
+    static constexpr int kCovUV = kRead ? 0 : 1, kCovUW = kRead ? 1 : 5, kCovZV = kRead ? 2 : 9;
+};
+
+// f(std::integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
 
 __host__ __device__ inline size_t align256b(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -193,16 +229,24 @@ __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restr
 
 // -------------------------------------------------------------- screening
 
-__global__ void __launch_bounds__(256) k_score_rect_bf16(
+// mom: per (u tile, v tile, wave, row slot r, moment k) the 64 lanes' values,
+// at float offset (((ut * nvt + vt) * 4 + wave) * 16 + r) * kMom * 64 + k * 64 + lane
+// (written by kBfWrite, read by kBfRead, unused by kBfFull).
+template <int MODE>
+__global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_bf16(
     sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
     const float *__restrict__ r32, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
     const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
-    int64_t ut_hi, int64_t id_begin, int64_t id_end, void *lws, int lists_total, int keep, int cap, int publish)
+    int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, void *lws, int lists_total,
+    int keep, int cap, int publish)
 {
+    using Sh = BfShape<MODE>;
+    constexpr int kUVar = Sh::kUVar, kVVar = Sh::kVVar, kNG = Sh::kNG, kPA = Sh::kPA, kPB = Sh::kPB,
+                  kStage = Sh::kStage;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // two staging buffers
-    float *lsc = (float *)(stage + 2 * kStage);
+    __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // kNBuf staging buffers
+    float *lsc = (float *)(stage + Sh::kNBuf * kStage);
     int64_t *lid = (int64_t *)(lsc + cap);
     // u-tile column constants for the epilogue: (mean u, mean 1/u, sum u~^2,
     // sum z~^2) and (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero)
@@ -278,6 +322,9 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                 xr4 = *reinterpret_cast<const float4 *>(r32 + t0);
             };
             auto store_chunk = [&](int ch, __bf16 *buf, bool tail) {
+                // no contraction: the parts of U~, Z~, V~ r and W~ r are the same
+                // bits in every mode, so the residual GEMMs agree exactly
+#pragma clang fp contract(off)
                 const int t0 = ch * kKC + squad * 4;
                 const float xu[4] = {pu.x, pu.y, pu.z, pu.w};
                 const float xv[4] = {pv.x, pv.y, pv.z, pv.w};
@@ -292,9 +339,16 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                         uu = live ? uu : 0.f; zz = live ? zz : 0.f;
                         vv = live ? vv : 0.f; ww = live ? ww : 0.f; r = live ? r : 0.f;
                     }
-                    ua[0][e] = uu; ua[1][e] = uu * uu; ua[2][e] = zz; ua[3][e] = zz * zz;
-                    va[0][e] = vv; va[1][e] = vv * r; va[2][e] = vv * (vv + 2.f * smv); va[3][e] = vv * (vv + smv);
-                    va[4][e] = ww; va[5][e] = ww * r; va[6][e] = ww * (ww + 2.f * smw); va[7][e] = ww * (ww + smw);
+                    if constexpr (Sh::kRead) {
+                        ua[0][e] = uu; ua[1][e] = zz;
+                        va[0][e] = vv * r; va[1][e] = ww * r;
+                    } else {
+                        ua[0][e] = uu; ua[1][e] = uu * uu; ua[2][e] = zz; ua[3][e] = zz * zz;
+                        va[0][e] = vv; va[1][e] = vv * r; va[2][e] = vv * (vv + 2.f * smv);
+                        va[3][e] = vv * (vv + smv);
+                        va[4][e] = ww; va[5][e] = ww * r; va[6][e] = ww * (ww + 2.f * smw);
+                        va[7][e] = ww * (ww + smw);
+                    }
                 }
                 auto put = [&](__bf16 *plane, const float (&x)[4]) {
                     // hi = bf16(x), lo = bf16(x - hi), two values per conversion
@@ -318,8 +372,14 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                 for (int q = 0; q < kVVar; ++q) put(buf + (kPA + q * kSplit) * kPlane, va[q]);
             };
             // GEMM g: u-side variant GA[g], v-side variant GB[g]; terms hi*hi, hi*lo, lo*hi
-            constexpr int GA[kNG] = {0, 0, 1, 0, 0, 0, 1, 0, 2, 2, 3, 2};
-            constexpr int GB[kNG] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3};
+            constexpr int GAf[12] = {0, 0, 1, 0, 0, 0, 1, 0, 2, 2, 3, 2};
+            constexpr int GBf[12] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3};
+            constexpr int GAr[3] = {0, 0, 1}, GBr[3] = {0, 1, 0};
+            auto GA = [&](int g) { return Sh::kRead ? GAr[g] : GAf[g]; };
+            auto GB = [&](int g) { return Sh::kRead ? GBr[g] : GBf[g]; };
+            // Fragments of the staged chunk, then its MFMAs.  With a single staging
+            // buffer a barrier between the two frees the buffer for the next chunk
+            // (every wave holds its fragments in registers by then).
             auto mfma_chunk = [&](const __bf16 *buf) {
                 bf16x8 af[kPA], bfr[kPB];
 #pragma unroll
@@ -327,50 +387,80 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
 #pragma unroll
                 for (int q = 0; q < kPB; ++q)
                     bfr[q] = *reinterpret_cast<const bf16x8 *>(buf + (kPA + q) * kPlane + fb);
+                if constexpr (Sh::kNBuf == 1) __syncthreads();
 #pragma unroll
                 for (int term = 0; term < 3; ++term) {
                     const int pa_ = term == 2 ? 1 : 0, pb_ = term == 1 ? 1 : 0;
 #pragma unroll
                     for (int g = 0; g < kNG; ++g)
-                        acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[GA[g] * kSplit + pa_],
-                                                                         bfr[GB[g] * kSplit + pb_], acc[g], 0, 0, 0);
+                        acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[GA(g) * kSplit + pa_],
+                                                                         bfr[GB(g) * kSplit + pb_], acc[g], 0, 0, 0);
                 }
             };
             // interleave: fragment reads first, then each MFMA followed by a share of
             // the staging work of the next chunk (VALU and LDS stores)
             auto interleave = [&]() {
-                __builtin_amdgcn_sched_group_barrier(0x100, kPA + kPB, 0);   // LDS reads
+                if constexpr (Sh::kNBuf == 2)
+                    __builtin_amdgcn_sched_group_barrier(0x100, kPA + kPB, 0);   // LDS reads
                 __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);           // global loads
 #pragma unroll
                 for (int i = 0; i < 3 * kNG; ++i) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // MFMA
                     __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);       // VALU
-                    if (i % 3 == 2) __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);   // LDS stores
+                    if constexpr (Sh::kRead) {
+                        if (i < kPA + kPB) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // LDS stores
+                    } else {
+                        if (i % 3 == 2) __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);   // LDS stores
+                    }
                 }
             };
+            auto buf_of = [&](int c) { return Sh::kNBuf == 2 ? stage + (c & 1) * kStage : stage; };
             __syncthreads();                          // the previous tile's fragment reads are done
             if (tid == 0) lpend = 0;                  // every thread has read the previous total
+            // Chunks ch + 2 .. ch + kAhead - 1 wait in registers behind pu/pv/pr
+            // (chunk ch + 1); loads past the last chunk re-read its samples.
+            constexpr int kAhead = Sh::kAhead, kRing = kAhead > 2 ? kAhead - 2 : 1;
+            float4 fu[kRing], fv[kRing], fr[kRing];
             load_chunk(0, pu, pv, pr);
             store_chunk(0, stage, nch == 1);
             load_chunk(1, pu, pv, pr);
+#pragma unroll
+            for (int a = 0; a + 2 < kAhead; ++a) load_chunk(2 + a, fu[a], fv[a], fr[a]);
             __syncthreads();
             int ch = 0;
             for (; ch + 2 < nch; ++ch) {              // chunk ch + 1 is full
                 float4 qu, qv, qr;
-                load_chunk(ch + 2, qu, qv, qr);
-                mfma_chunk(stage + (ch & 1) * kStage);
-                store_chunk(ch + 1, stage + ((ch + 1) & 1) * kStage, false);
+                load_chunk(ch + kAhead, qu, qv, qr);
+                mfma_chunk(buf_of(ch));
+                store_chunk(ch + 1, buf_of(ch + 1), false);
                 interleave();
-                pu = qu; pv = qv; pr = qr;
+                if constexpr (kAhead > 2) {
+                    pu = fu[0]; pv = fv[0]; pr = fr[0];
+#pragma unroll
+                    for (int a = 0; a + 3 < kAhead; ++a) { fu[a] = fu[a + 1]; fv[a] = fv[a + 1]; fr[a] = fr[a + 1]; }
+                    fu[kRing - 1] = qu; fv[kRing - 1] = qv; fr[kRing - 1] = qr;
+                } else {
+                    pu = qu; pv = qv; pr = qr;
+                }
                 __syncthreads();
             }
             if (ch + 1 < nch) {                       // chunk ch + 1 is the last one
-                mfma_chunk(stage + (ch & 1) * kStage);
-                store_chunk(ch + 1, stage + ((ch + 1) & 1) * kStage, true);
+                mfma_chunk(buf_of(ch));
+                store_chunk(ch + 1, buf_of(ch + 1), true);
                 __syncthreads();
                 ++ch;
             }
-            mfma_chunk(stage + (ch & 1) * kStage);
+            mfma_chunk(buf_of(ch));
+
+            // this tile's moments: loaded once the chunk loop's registers are free
+            // (held across the loop they would be spilled; the other block on the
+            // CU runs meanwhile), or formed from the accumulators (write)
+            float mr[MODE != kBfFull ? 16 * kMom : 1];
+            if constexpr (Sh::kRead) {
+                const float *const mp = mom + (((size_t)ut * nvt + vt) * 4 + w) * (16 * kMom * 64) + lane;
+#pragma unroll
+                for (int q = 0; q < 16 * kMom; ++q) mr[q] = __builtin_nontemporal_load(mp + q * 64);
+            }
 
             // epilogue: lane holds column j = lane % 32 and rows
             // i = 8 (r / 4) + 4 (lane / 32) + (r % 4) of each 32 x 32 result
@@ -381,77 +471,130 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
             const float4 vs0 = vsum[2 * (vin ? v : 0)], vs1 = vsum[2 * (vin ? v : 0) + 1];
             const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w, Svr = vs1.x, Swr = vs1.y, vrm = vs1.z;
             const float fn = (float)n, rr = (float)(R1 / nd);
-            // approximate scores of the five forms of row r of this lane
-            auto row_scores = [&](int r, float (&sc)[5], int64_t (&fid)[5]) {
+            // Residual-independent moments of row r, from the accumulators: sum h
+            // of u v, its variance, then the same for u/v and v/u.  The read form
+            // takes them as the write form stored them over the same pools.
+            auto moments_acc = [&](int r, float (&m)[kMom]) {
+#pragma clang fp contract(off)
+                if constexpr (!Sh::kRead) {
+                    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const float4 us = ucon_a[wu * 32 + i];
+                    const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w;
+                    float s1 = acc[0][r];                           // u v
+                    float s2 = acc[2][r] + 2.0f * mu * acc[3][r] + mv * mv * Suu + mu * mu * Svv;
+                    m[0] = s1;
+                    m[1] = s2 - s1 * s1 / fn;
+                    s1 = acc[4][r];                                 // u / v
+                    s2 = acc[6][r] + 2.0f * mu * acc[7][r] + mw * mw * Suu + mu * mu * Sww;
+                    m[2] = s1;
+                    m[3] = s2 - s1 * s1 / fn;
+                    s1 = acc[8][r];                                 // v / u
+                    s2 = acc[10][r] + 2.0f * mz * acc[11][r] + mv * mv * Szz + mz * mz * Svv;
+                    m[4] = s1;
+                    m[5] = s2 - s1 * s1 / fn;
+                }
+            };
+            if constexpr (MODE == kBfWrite) {
+                // kept in registers for the scores below: the nine accumulators
+                // they come from are dead from here on
+                float *const mp = mom + (((size_t)ut * nvt + vt) * 4 + w) * (16 * kMom * 64) + lane;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    float m[kMom];
+                    moments_acc(r, m);
+#pragma unroll
+                    for (int k = 0; k < kMom; ++k) {
+                        mr[r * kMom + k] = m[k];
+                        __builtin_nontemporal_store(m[k], mp + (r * kMom + k) * 64);
+                    }
+                }
+            }
+            auto moments_of = [&](int r, float (&m)[kMom]) {
+                if constexpr (MODE == kBfFull) {
+                    moments_acc(r, m);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kMom; ++k) m[k] = mr[r * kMom + k];
+                }
+            };
+            // Approximate scores of the five forms of row r of this lane, -1 for
+            // a pair outside the space or a form outside its domain.  Branch-free;
+            // ids are formed only for the few candidates at the admission bound.
+            auto row_scores = [&](int r, float (&sc)[5]) {
+#pragma clang fp contract(off)
                 const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int64_t uix = u0 + wu * 32 + i;
                 const float4 us = ucon_a[wu * 32 + i], ub = ucon_b[wu * 32 + i];
-                const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w, Sur = ub.x, Szr = ub.y;
+                const float mu = us.x, mz = us.y, Suu = us.z, Sur = ub.x, Szr = ub.y;
                 const int uflags = (int)ub.w;
                 const bool ok = (uflags & 1) && vin && vst.valid != 0.0f;
-                const float g0 = acc[0][r];
+                float m[kMom];
+                moments_of(r, m);
+                const float g0 = m[0];
                 float cov[5], var[5];
                 var[0] = Suu + Svv + 2.0f * g0;                     // u + v
                 var[1] = Suu + Svv - 2.0f * g0;                     // u - v
                 cov[0] = Sur + Svr;
                 cov[1] = Sur - Svr;
-                {                                                   // u v
-                    const float s1 = g0;
-                    const float s2 = acc[2][r] + 2.0f * mu * acc[3][r] + mv * mv * Suu + mu * mu * Svv;
-                    var[2] = s2 - s1 * s1 / fn;
-                    cov[2] = acc[1][r] + mv * Sur + mu * Svr - s1 * rr;
-                }
-                {                                                   // u / v
-                    const float s1 = acc[4][r];
-                    const float s2 = acc[6][r] + 2.0f * mu * acc[7][r] + mw * mw * Suu + mu * mu * Sww;
-                    var[3] = s2 - s1 * s1 / fn;
-                    cov[3] = acc[5][r] + mw * Sur + mu * Swr - s1 * rr;
-                }
-                {                                                   // v / u
-                    const float s1 = acc[8][r];
-                    const float s2 = acc[10][r] + 2.0f * mz * acc[11][r] + mv * mv * Szz + mz * mz * Svv;
-                    var[4] = s2 - s1 * s1 / fn;
-                    cov[4] = acc[9][r] + mv * Szr + mz * Svr - s1 * rr;
-                }
+                var[2] = m[1];                                      // u v
+                cov[2] = acc[Sh::kCovUV][r] + mv * Sur + mu * Svr - m[0] * rr;
+                var[3] = m[3];                                      // u / v
+                cov[3] = acc[Sh::kCovUW][r] + mw * Sur + mu * Swr - m[2] * rr;
+                var[4] = m[5];                                      // v / u
+                cov[4] = acc[Sh::kCovZV][r] + mv * Szr + mz * Svr - m[4] * rr;
                 const bool dom[5] = {true, true, true, vst.minabs > 0.f, (uflags & 2) != 0};
+                // a sum or difference whose spread sqrt(var / n) is at most 1e-2
+                // of the operands' rms has cancelled to rounding noise (the
+                // exact rule is applied by the rescore)
                 const float scale = fmaxf(ub.z, vrm);
+                const float cth = 1e-4f * scale * scale * fn;
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    sc[k] = -1.0f;
-                    fid[k] = INT64_MAX;
-                    if (ok && dom[k] && fs.slot[k] >= 0) {
-                        fid[k] = binbase + (uix * vcount + v) * S + fs.slot[k];
-                        if (fid[k] >= id_begin && fid[k] < id_end && var[k] > 0.0f) {
-                            float q = fabsf(cov[k]) * __builtin_amdgcn_rsqf(var[k] * (float)Srr);
-                            sc[k] = q <= 1.0f ? q : (q > 1.0f ? 1.0f : -1.0f);
-                            // clear cancellation of a sum or difference (the exact
-                            // rule is applied by the rescore)
-                            if (k < 2 && !(sqrtf(var[k] / fn) > 1e-2f * scale)) sc[k] = -1.0f;
-                        }
-                    }
+                    const float q = fabsf(cov[k]) * __builtin_amdgcn_rsqf(var[k] * (float)Srr);
+                    const float sk = q <= 1.0f ? q : (q > 1.0f ? 1.0f : -1.0f);   // rounding above 1, or NaN
+                    const bool live = ok && dom[k] && fs.slot[k] >= 0 && var[k] > (k < 2 ? cth : 0.0f);
+                    sc[k] = live ? sk : -1.0f;
                 }
             };
-            // Count this lane's candidates at or above the admission bound (the
-            // bounds only rise, so a stale read admits more, never fewer) and
-            // not excluded, and the block's total.  When they all fit into the
-            // list, every thread reserves its slots with one atomic and writes
-            // them: no per-row barriers.
-            const float tb = fmaxf(*Lst.thr, load_gthr(gb));
-            auto admit = [&](float sc, int64_t id) {
-                return sc >= 0.0f && sc >= tb && (n_excl == 0 || !in_sorted_ids(excl, n_excl, id));
+            auto fid_of = [&](int r, int k) -> int64_t {
+                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                return binbase + ((u0 + wu * 32 + i) * vcount + v) * S + fs.slot[k];
             };
-            int mine = 0;
-            unsigned rows = 0;                        // bit r: row r has an admitted candidate
+            // every id of the tile inside [id_begin, id_end) (the usual case): no
+            // per-candidate range check
+            const int64_t tile_lo = binbase + (u0 * vcount + v0) * S;
+            const int64_t tile_hi = binbase + ((u0 + kBT - 1) * vcount + v0 + kBT - 1) * S + S;
+            const bool tile_in = tile_lo >= id_begin && tile_hi <= id_end;
+            auto admit_id = [&](int64_t id) {
+                return (tile_in || (id >= id_begin && id < id_end)) &&
+                       (n_excl == 0 || !in_sorted_ids(excl, n_excl, id));
+            };
+            // Count this lane's candidates at or above the admission bound (the
+            // bounds only rise, so a stale read admits more, never fewer), in
+            // range and not excluded, and the block's total.  When they all fit
+            // into the list, every thread reserves its slots with one atomic and
+            // writes them: no per-row barriers.
+            const float tb = fmaxf(*Lst.thr, load_gthr(gb));
+            unsigned rows = 0;                        // bit r: row r has a candidate at the bound
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 float sc[5];
-                int64_t fid[5];
-                row_scores(r, sc, fid);
-                int c = 0;
+                row_scores(r, sc);
+                bool hit = false;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) c += admit(sc[k], fid[k]) ? 1 : 0;
-                mine += c;
-                rows |= (c ? 1u : 0u) << r;
+                for (int k = 0; k < 5; ++k) hit = hit || (sc[k] >= 0.0f && sc[k] >= tb);
+                rows |= (hit ? 1u : 0u) << r;
+            }
+            int mine = 0;
+            if (rows) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    if (!((rows >> r) & 1u)) continue;
+                    float sc[5];
+                    row_scores(r, sc);
+#pragma unroll
+                    for (int k = 0; k < 5; ++k)
+                        if (sc[k] >= 0.0f && sc[k] >= tb && admit_id(fid_of(r, k))) ++mine;
+                }
             }
             if (mine) atomicAdd(&lpend, mine);
             __syncthreads();
@@ -467,25 +610,33 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                     for (int r = 0; r < 16; ++r) {
                         if (!((rows >> r) & 1u)) continue;
                         float sc[5];
-                        int64_t fid[5];
-                        row_scores(r, sc, fid);
+                        row_scores(r, sc);
 #pragma unroll
-                        for (int k = 0; k < 5; ++k)
-                            if (admit(sc[k], fid[k])) {
+                        for (int k = 0; k < 5; ++k) {
+                            if (!(sc[k] >= 0.0f && sc[k] >= tb)) continue;
+                            const int64_t id = fid_of(r, k);
+                            if (admit_id(id)) {
                                 Lst.sc[slot] = sc[k];
-                                Lst.id[slot] = fid[k];
+                                Lst.id[slot] = id;
                                 ++slot;
                             }
+                        }
                     }
                 }
                 continue;
             }
-            // the list is filling: row by row, merging as needed
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            // the list is filling: row by row, merging as needed (rows unrolled at
+            // compile time: the registers of row r are addressed statically)
+            static_for<16>([&](auto R) {
+                constexpr int r = decltype(R)::value;
                 float sc[5];
                 int64_t fid[5];
-                row_scores(r, sc, fid);
+                row_scores(r, sc);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    fid[k] = fid_of(r, k);
+                    if (!(tile_in || (fid[k] >= id_begin && fid[k] < id_end))) sc[k] = -1.0f;
+                }
                 __syncthreads();
                 const int c = *Lst.cnt;
                 __syncthreads();
@@ -501,7 +652,7 @@ __global__ void __launch_bounds__(256) k_score_rect_bf16(
                 } else {
                     list_offer<5>(Lst, sc, fid, gb, excl, n_excl);
                 }
-            }
+            });
         }
     }
     list_flush(Lst, gb, W.sc + (size_t)blockIdx.x * keep, W.id + (size_t)blockIdx.x * keep);
@@ -678,21 +829,16 @@ extern "C" sisso_status sisso_bf16_residual(const sisso_space *space, const siss
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 
-extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_score_args *args, const void *ops,
-                                          size_t ops_bytes, int32_t band, int64_t cand_begin, int64_t cand_end,
-                                          void *bws, size_t bws_bytes, void *stream)
+namespace {
+
+int64_t bf_tiles(int64_t cols) { return (cols + kBT - 1) / kBT; }
+
+template <int MODE>
+sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, const BfOps &o, BfWs &w,
+                       int32_t band, int64_t cand_begin, int64_t cand_end, float *mom, hipStream_t st)
 {
-    if (!ops || !bws) return SISSO_E_NULL;
-    const sisso_status c = bf_check(space, args, band, bws_bytes);
-    if (c != SISSO_OK) return c;
-    const int L = space->levels, n = args->n;
-    const int64_t bb = space->pool[L] + space->rect_unary;
-    if (cand_begin < bb || cand_end > space->total || cand_begin >= cand_end) return SISSO_E_RANGE;
-    if (ops_bytes < sisso_bf16_operands_size(space, n)) return SISSO_E_WORKSPACE;
-    hipStream_t st = as_stream(stream);
-    const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
-    const BfOps o = bf_ops_view(const_cast<void *>(ops));
-    BfWs w = bf_ws_view(bws, ucols, vcols, band);
+    using Sh = BfShape<MODE>;
+    const int n = args->n;
     const FormSlots fs = form_slots(space);
     const BfPlan p = bf_plan(space, cand_begin, cand_end,
                              args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid);
@@ -705,14 +851,72 @@ extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_
     const int lcap = bf_lists_cap(space);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)2 * kStage * sizeof(__bf16) + 2 * kBT * sizeof(float4) +
+        const size_t smem = (size_t)Sh::kNBuf * Sh::kStage * sizeof(__bf16) + 2 * kBT * sizeof(float4) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
-        if (!allow_dynamic_lds(k_score_rect_bf16, smem)) return SISSO_E_UNSUPPORTED;
-        hipLaunchKernelGGL(k_score_rect_bf16, dim3(p.grid), dim3(256), smem, st, *space, fs, n, args->pool32,
-                           args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info, args->exclude, args->n_exclude, p.ut_lo, p.ut_hi,
-                           cand_begin, cand_end, w.lists, lcap, keep_b, cap_b, publish);
+        if (!allow_dynamic_lds(k_score_rect_bf16<MODE>, smem)) return SISSO_E_UNSUPPORTED;
+        hipLaunchKernelGGL(k_score_rect_bf16<MODE>, dim3(p.grid), dim3(256), smem, st, *space, fs, n,
+                           args->pool32, args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info,
+                           args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, mom, w.lists,
+                           lcap, keep_b, cap_b, publish);
     }
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, const void *ops, size_t ops_bytes,
+                       int32_t band, int64_t cand_begin, int64_t cand_end, void *moments, size_t moments_bytes,
+                       int32_t mode, void *bws, size_t bws_bytes, void *stream)
+{
+    if (!ops || !bws) return SISSO_E_NULL;
+    const sisso_status c = bf_check(space, args, band, bws_bytes);
+    if (c != SISSO_OK) return c;
+    const int L = space->levels, n = args->n;
+    const int64_t bb = space->pool[L] + space->rect_unary;
+    if (cand_begin < bb || cand_end > space->total || cand_begin >= cand_end) return SISSO_E_RANGE;
+    if (ops_bytes < sisso_bf16_operands_size(space, n)) return SISSO_E_WORKSPACE;
+    if (mode != SISSO_MOMENTS_NONE && mode != SISSO_MOMENTS_WRITE && mode != SISSO_MOMENTS_READ)
+        return SISSO_E_RANGE;
+    if (mode != SISSO_MOMENTS_NONE) {
+        if (!moments) return SISSO_E_NULL;
+        if (moments_bytes < sisso_bf16_moments_size(space, n)) return SISSO_E_WORKSPACE;
+    }
+    hipStream_t st = as_stream(stream);
+    const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
+    const BfOps o = bf_ops_view(const_cast<void *>(ops));
+    BfWs w = bf_ws_view(bws, ucols, vcols, band);
+    float *mom = (float *)moments;
+    switch (mode) {
+    case SISSO_MOMENTS_WRITE: return bf_launch<kBfWrite>(space, args, o, w, band, cand_begin, cand_end, mom, st);
+    case SISSO_MOMENTS_READ: return bf_launch<kBfRead>(space, args, o, w, band, cand_begin, cand_end, mom, st);
+    default: return bf_launch<kBfFull>(space, args, o, w, band, cand_begin, cand_end, nullptr, st);
+    }
+}
+
+}  // namespace
+
+extern "C" size_t sisso_bf16_moments_size(const sisso_space *space, int32_t n)
+{
+    if (!space_ok(space) || n < 2 || n > SISSO_MAX_N) return 0;
+    const int L = space->levels;
+    const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
+    return (size_t)bf_tiles(ucols) * (size_t)bf_tiles(vcols) * kMomTile * sizeof(float);
+}
+
+extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_score_args *args, const void *ops,
+                                          size_t ops_bytes, int32_t band, int64_t cand_begin, int64_t cand_end,
+                                          void *bws, size_t bws_bytes, void *stream)
+{
+    return bf_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, nullptr, 0, SISSO_MOMENTS_NONE, bws,
+                     bws_bytes, stream);
+}
+
+extern "C" sisso_status sisso_bf16_screen_moments(const sisso_space *space, const sisso_score_args *args,
+                                                  const void *ops, size_t ops_bytes, int32_t band,
+                                                  int64_t cand_begin, int64_t cand_end, void *moments,
+                                                  size_t moments_bytes, int32_t mode, void *bws, size_t bws_bytes,
+                                                  void *stream)
+{
+    return bf_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, moments, moments_bytes, mode, bws,
+                     bws_bytes, stream);
 }
 
 extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso_score_args *args, int32_t band,

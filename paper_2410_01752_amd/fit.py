@@ -41,6 +41,10 @@ def _round_up(x: int, m: int) -> int:
     return (x + m - 1) // m * m
 
 
+# device memory left free beside the BF16 moments buffer
+MOMENTS_HEADROOM = 8 << 30
+
+
 class Engine:
     """Device state of one SISSO problem: base features, pools, subspace."""
 
@@ -68,6 +72,7 @@ class Engine:
             L.ptr(self.pool1), self.ld64, L.ptr(self.stats), L.stream_handle(self.dev)),
             "sisso_materialize_pools")
         self.bf16_ops: Optional[torch.Tensor] = None
+        self.bf16_moments: Optional[torch.Tensor] = None
         self.r32 = torch.zeros(self.ld32, dtype=torch.float32, device=self.dev)
         self.info = torch.zeros(L.RESID_DOUBLES, dtype=torch.float64, device=self.dev)
         self._ws: Dict[str, torch.Tensor] = {}
@@ -133,17 +138,38 @@ class Engine:
         L.check(L.lib().sisso_prepare_bf16(ctypes.byref(self.space), ctypes.byref(a), L.ptr(self.bf16_ops),
                                            nb, self.stream()), "sisso_prepare_bf16")
 
+    def bf16_moments_buffer(self) -> Optional[torch.Tensor]:
+        """Device buffer of the BF16 screen's residual-independent moments
+        (sisso_bf16_screen_moments), allocated on first use; None when the
+        space has no slice or the buffer would leave less than
+        MOMENTS_HEADROOM bytes of device memory free."""
+        if self.bf16_moments is None:
+            nb = L.lib().sisso_bf16_moments_size(ctypes.byref(self.space), self.n)
+            if nb == 0:
+                return None
+            free, _ = torch.cuda.mem_get_info(self.dev)
+            free += torch.cuda.memory_reserved(self.dev) - torch.cuda.memory_allocated(self.dev)
+            if nb + MOMENTS_HEADROOM > free:
+                return None
+            self.bf16_moments = torch.empty(nb, dtype=torch.uint8, device=self.dev)
+        return self.bf16_moments
+
     def screen(self, r64: torch.Tensor, keep: int, exclude: Optional[torch.Tensor] = None,
                begin: int = 0, end: Optional[int] = None, grid: int = 0, tile: int = 0,
                k: Optional[int] = None, events: Optional[dict] = None, precision: str = "fp32",
-               band: int = 0):
+               band: int = 0, moments: str = "none"):
         """SIS over ids [begin, end): returns device tensors (ids, scores, count).
 
         The pass is issued as one sisso_expand_score call per block of the
         space (stored pool + unary slice, then the binary slice) feeding one
         workspace; `events`, if given, collects (start, end) CUDA events per
-        call, recorded on the stream the kernels run on."""
+        call, recorded on the stream the kernels run on.  With the BF16 form,
+        `moments` "write" also stores the residual-independent moments of the
+        whole binary block into bf16_moments_buffer(), and "read" uses the
+        ones an earlier "write" over the same engine stored."""
         end = self.total if end is None else end
+        if moments not in ("none", "write", "read"):
+            raise L.SissoError(f"unknown moments mode {moments!r}")
         self.prepare_residual(r64)
         a = self.score_args(keep, exclude, grid, tile)
         nbytes = L.lib().sisso_score_workspace_size(ctypes.byref(self.space), ctypes.byref(a))
@@ -206,11 +232,18 @@ class Engine:
                 nb = L.lib().sisso_bf16_workspace_size(ctypes.byref(self.space), ctypes.byref(a), band)
                 bws = self._workspace("bf16", nb)
                 sp_, a_ = ctypes.byref(self.space), ctypes.byref(a)
+                mode = L.MOMENTS_NONE if fallback is not None else \
+                    {"none": L.MOMENTS_NONE, "write": L.MOMENTS_WRITE, "read": L.MOMENTS_READ}[moments]
+                mom = self.bf16_moments_buffer() if mode != L.MOMENTS_NONE else None
+                if mode != L.MOMENTS_NONE and (mom is None or b != bb or e != self.total):
+                    raise L.SissoError("BF16 moments need their buffer and the whole binary block")
                 steps = [("bf16_residual", lambda: L.lib().sisso_bf16_residual(sp_, a_, band, L.ptr(bws),
                                                                               bws.numel(), st)),
-                         ("bf16_screen", lambda: L.lib().sisso_bf16_screen(
-                             sp_, a_, L.ptr(self.bf16_ops), self.bf16_ops.numel(), band, b, e, L.ptr(bws),
-                             bws.numel(), st)),
+                         ("bf16_screen_read" if mode == L.MOMENTS_READ else "bf16_screen",
+                          lambda: L.lib().sisso_bf16_screen_moments(
+                             sp_, a_, L.ptr(self.bf16_ops), self.bf16_ops.numel(), band, b, e,
+                             L.ptr(mom) if mom is not None else None, mom.numel() if mom is not None else 0,
+                             mode, L.ptr(bws), bws.numel(), st)),
                          ("bf16_rescore", lambda: L.lib().sisso_bf16_rescore(sp_, a_, band, L.ptr(bws),
                                                                             bws.numel(), L.ptr(ws), ws.numel(),
                                                                             st))]
@@ -274,8 +307,18 @@ class Engine:
     # ----------------------------------------------------------------- fit
     def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10,
             grid: int = 0, tile: int = 0, timings: Optional[dict] = None, precision: str = "fp32",
-            band: int = 0) -> List[StepResult]:
+            band: int = 0, moments: str = "auto") -> List[StepResult]:
+        """SISSO fit: for t = 1..dmax, SIS against the residual, subspace
+        update, SO over the subspace.  With the BF16 form and `moments` "auto",
+        the first pass of the fit stores the residual-independent moments of
+        the binary block and the later passes read them (when the buffer fits
+        in device memory); "off" recomputes them in every pass."""
         keep0 = min(2 * k if keep0 is None else keep0, L.MAX_KEEP)
+        if moments not in ("auto", "off"):
+            raise L.SissoError(f"unknown moments policy {moments!r}")
+        use_mom = precision == "bf16" and self.rect and moments == "auto" and \
+            self.bf16_moments_buffer() is not None
+        mom_state = "write"                   # written by this fit's first pass, then read
         if dmax < 1 or dmax > L.MAX_D or k * dmax > L.MAX_SUBSPACE:
             raise L.SissoError("dmax or k out of range")
         fs = FitState(self.n, self.dev)
@@ -286,7 +329,9 @@ class Engine:
             keep = keep0
             while True:
                 ids, sc, cnt = self.screen(r, keep, fs.exclude(), grid=grid, tile=tile, events=timings,
-                                           precision=precision, band=band)
+                                           precision=precision, band=band,
+                                           moments=mom_state if use_mom else "none")
+                mom_state = "read"
                 cand, valid = self.materialize(ids)
                 fs.update(cand, ids, valid, cnt, keep, r, k, self._workspace)
                 nn, nc, ct = fs.read_update(cnt)

@@ -111,6 +111,43 @@ def test_argument_errors_before_launch():
         assert lib.sisso_status_string(st)
 
 
+def test_bf16_moments_size_and_argument_errors_before_launch():
+    """The moments buffer holds 6 floats per pair of the padded 64 x 64 tiles of
+    the slice's binary block; a bad mode, a missing or short buffer and the
+    usual range checks are reported before any launch."""
+    lib = L.lib()
+    s = L.make_space(20, I.OPS1["unary"], I.OPS1["binary"], 2, True)
+    nu, nv = int(s.pool[2] - s.pool[1]), int(s.pool[1])
+    tiles = ((nu + 63) // 64) * ((nv + 63) // 64)
+    assert lib.sisso_bf16_moments_size(ctypes.byref(s), 100) == tiles * 4 * 16 * 6 * 64 * 4
+    assert lib.sisso_bf16_moments_size(ctypes.byref(s), 1) == 0
+    plain = L.make_space(5, I.OPS1["unary"], I.OPS1["binary"], 2, False)
+    assert lib.sisso_bf16_moments_size(ctypes.byref(plain), 100) == 0      # no slice
+    a = L.ScoreArgs()
+    a.n, a.keep, a.ld32 = 100, 40, 128
+    a.pool32 = a.stats = a.r32 = a.info = 0x1000
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    band = 160
+    bws = lib.sisso_bf16_workspace_size(ctypes.byref(s), ctypes.byref(a), band)
+    ops = lib.sisso_bf16_operands_size(ctypes.byref(s), 100)
+    mom = lib.sisso_bf16_moments_size(ctypes.byref(s), 100)
+    assert bws > 0 and ops > 0
+    b0 = int(s.pool[2] + s.rect_unary)
+    sp, ap = ctypes.byref(s), ctypes.byref(a)
+
+    def call(mode, m=fake, mb=mom, lo=b0, hi=s.total):
+        return lib.sisso_bf16_screen_moments(sp, ap, fake, ops, band, lo, hi, m, mb, mode, fake, bws, None)
+
+    assert call(3) == 3                                   # unknown mode
+    assert call(-1) == 3
+    assert call(L.MOMENTS_WRITE, m=None) == 1             # no buffer
+    assert call(L.MOMENTS_READ, m=None) == 1
+    assert call(L.MOMENTS_READ, mb=mom - 1) == 4          # short buffer
+    assert call(L.MOMENTS_WRITE, lo=b0 - 1) == 3          # outside the binary block
+    assert lib.sisso_bf16_screen_moments(sp, ap, None, ops, band, b0, s.total, fake, mom, 1, fake, bws,
+                                         None) == 1       # no operands
+
+
 def test_batched_l0_argument_errors_before_launch():
     lib = L.lib()
     fake = ctypes.c_void_p(0x1000)

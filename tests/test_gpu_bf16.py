@@ -134,3 +134,83 @@ def test_autotuned_shapes_give_identical_results(tmp_path):
         b = eng.screen(r64, 300, None, precision=form, band=1200, tile=ch.tile, grid=ch.grid)
         torch.cuda.synchronize()
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def _a256(x):
+    return (x + 255) // 256 * 256
+
+
+def _band_of(eng, band):
+    """The BF16 band of the last screen (ids and BF16 scores, before the exact
+    rescore), read from the BF16 workspace: column sums of both sides, then
+    band ids (int64), band scores (float32) and the band count."""
+    s = eng.space
+    vcols, ucols = int(s.pool[eng.levels - 1]), int(s.pool[eng.levels] - s.pool[eng.levels - 1])
+    w = eng._ws["bf16"]
+    o_id = _a256(vcols * 2 * 16) + _a256(ucols * 8)
+    o_sc = o_id + _a256(band * 8)
+    o_ct = o_sc + _a256(band * 4)
+    c = int(w[o_ct:o_ct + 4].view(torch.int32).item())
+    ids = w[o_id:o_id + 8 * c].view(torch.int64).cpu().numpy()
+    sc = w[o_sc:o_sc + 4 * c].view(torch.float32).cpu().numpy()
+    order = np.lexsort((ids, -sc))
+    return ids[order], sc[order]
+
+
+@pytest.mark.parametrize("case", ["ragged_n300", "persistent_grid", "c3_shape_n2000"])
+def test_bf16_moments_read_equals_plain_screen(case):
+    """A screen that reads the stored residual-independent moments gives the
+    same BF16 band (ids and BF16 scores, bit for bit) and the same rescored
+    list as a plain screen of the same residual; so does the screen that
+    writes them.  Cases: n = 300 (a ragged last chunk of samples, ragged u and v
+    tiles), a grid of 3 blocks sweeping every u tile, and n = 2000 with d = 12."""
+    if case == "ragged_n300":
+        p, keep, band, grid = I.tiny(9, n=300, d=6, dist="lognormal", rect=True), 300, 1200, 0
+    elif case == "persistent_grid":
+        p, keep, band, grid = I.tiny(4, n=77, d=5, dist="lognormal", rect=True), 200, 800, 3
+    else:
+        p, keep, band, grid = I.tiny(21, n=2000, d=12, dist="lognormal", rect=True), 1000, 4000, 0
+    print(f"[bf16 moments] {case}", flush=True)
+    eng = _engine(p)
+    assert eng.bf16_moments_buffer() is not None
+    rng = np.random.default_rng(77)
+    y64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+    r2 = torch.as_tensor(p.y - 0.3 * p.X[:, 0] + 0.1 * rng.standard_normal(p.y.shape[0]),
+                         dtype=torch.float64, device=eng.dev)
+    excl = torch.as_tensor(np.sort(rng.choice(eng.total, 50, replace=False)), dtype=torch.int64,
+                           device=eng.dev)
+
+    def run(r, mode, ex=None):
+        ids, sc, cnt = eng.screen(r, keep, ex, precision="bf16", band=band, grid=grid, moments=mode)
+        torch.cuda.synchronize()
+        c = int(cnt.item())
+        return (ids[:c].cpu().numpy(), sc[:c].cpu().numpy()), _band_of(eng, band)
+
+    plain_y = run(y64, "none")
+    write_y = run(y64, "write")
+    plain_r = run(r2, "none", excl)
+    read_r = run(r2, "read", excl)
+    read_y = run(y64, "read")
+    for a, b in ((plain_y, write_y), (plain_r, read_r), (plain_y, read_y)):
+        (ia, sa), (ba, bsa) = a
+        (ib, sb), (bb_, bsb) = b
+        assert len(ba) > 0
+        assert np.array_equal(ba, bb_) and np.array_equal(bsa, bsb)      # the BF16 band, bit for bit
+        assert np.array_equal(ia, ib) and np.array_equal(sa, sb)         # the rescored list
+
+
+def test_bf16_fit_with_moments_equals_fit_without():
+    """A BF16 fit whose later passes read the first pass's moments gives the
+    tuples and RMSE of the BF16 fit that recomputes them and of the FP32 fit."""
+    p = I.tiny(6, n=400, d=6, dist="lognormal", rect=True, k=10, dmax=3)
+    eng = _engine(p)
+    a = eng.fit(p.k, p.dmax, precision="bf16", moments="off")
+    assert eng.bf16_moments is None
+    b = eng.fit(p.k, p.dmax, precision="bf16", moments="auto")
+    assert eng.bf16_moments is not None
+    c = eng.fit(p.k, p.dmax, precision="fp32")
+    assert len(a) == len(b) == len(c) == p.dmax
+    for x, y, z in zip(a, b, c):
+        assert list(x.best_ids) == list(y.best_ids) == list(z.best_ids)
+        assert x.rmse == y.rmse
+        assert abs(x.rmse - z.rmse) <= 1e-9 * z.rmse
