@@ -264,6 +264,8 @@ def cpu_baseline(p, budget_s: float):
 MI355X_BF16_TFLOPS = 2500.0               # dense MFMA
 CONTRACTIONS_PER_PAIR = 9            # algorithmic: (u v, u (v r), u^2 v^2) for u * v, u / v and v / u
 EXECUTED_MFMA_GEMMS = 12 * 3         # the kernel: 12 centred contractions x 3 hi/lo split products
+READ_CONTRACTIONS_PER_PAIR = 3       # read form: u (v r) for u * v, u / v and v / u
+MOMENT_BYTES_PER_PAIR = 24           # six FP32 residual-independent moments per (u, v) pair
 
 
 def recall_of(fi, fs, bi, tol=1e-6):
@@ -408,7 +410,9 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
+    eng = None
     for st in range(args.steps):
+        eng = None                               # the previous step's device state is released first
         eng, res = one_step(timings)
         results.append(res)
         torch.cuda.synchronize()
@@ -443,18 +447,36 @@ def main():
                 "per_unit": f"{NET_FLOPS_PER_CAND} network flops per candidate + {FLOPS_PER_CAND_SAMPLE} flops "
                             f"x n={n} per exactly scored candidate ({kept:.3g} per launch)"}
     elif n_bin > 0 and prec == "bf16":
+        # with the moments buffer the first pass of each fit is the write form
+        # (all 12 GEMMs + the moments' stores), the later ones the read form
+        moments = eng.bf16_moments is not None
         ks = ev_ms(timings, "bf16_screen")
         kernel_ms = sum(ks) / len(ks)
         pairs = n_bin // eng.space.n_slots
         flops = 2.0 * CONTRACTIONS_PER_PAIR * n * pairs
         achieved = flops / (kernel_ms * 1e-3) / 1e12
         executed = 2.0 * EXECUTED_MFMA_GEMMS * n * pairs / (kernel_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "k_score_rect_bf16", "achieved": achieved,
+        roof = {"bound": "mfma", "kernel": "k_score_rect_bf16_write" if moments else "k_score_rect_bf16",
+                "achieved": achieved,
                 "peak": MI355X_BF16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MI355X_BF16_TFLOPS,
                 "traffic": None, "avg_launch_ms": kernel_ms, "units_per_launch": pairs,
                 "per_unit": f"{CONTRACTIONS_PER_PAIR} contractions x 2 flops x n={n} samples per (u, v) pair "
                             f"(= {2 * CONTRACTIONS_PER_PAIR * n / 5:.0f} flops per candidate of the 5 forms)",
-                "executed_mfma_tflops": executed, "executed_frac": executed / MI355X_BF16_TFLOPS}
+                "executed_mfma_tflops": executed, "executed_frac": executed / MI355X_BF16_TFLOPS,
+                "launches_per_step": len(ks) / args.steps}
+        kr = ev_ms(timings, "bf16_screen_read")
+        if kr:
+            read_ms = sum(kr) / len(kr)
+            rflops = 2.0 * READ_CONTRACTIONS_PER_PAIR * n * pairs
+            roof["read_form"] = {
+                "kernel": "k_score_rect_bf16_read", "avg_launch_ms": read_ms, "launches_per_step": len(kr) / args.steps,
+                "achieved": rflops / (read_ms * 1e-3) / 1e12, "unit": "TFLOP/s",
+                "frac": rflops / (read_ms * 1e-3) / 1e12 / MI355X_BF16_TFLOPS,
+                "per_unit": f"{READ_CONTRACTIONS_PER_PAIR} residual contractions x 2 flops x n={n} samples per "
+                            f"(u, v) pair, plus {MOMENT_BYTES_PER_PAIR} bytes of stored moments",
+                "executed_mfma_tflops": 2.0 * 3 * 3 * n * pairs / (read_ms * 1e-3) / 1e12,
+                "moments_gb_per_s": MOMENT_BYTES_PER_PAIR * pairs / (read_ms * 1e-3) / 1e9,
+                "traffic": measured_traffic("k_score_rect_bf16_read", args.workload)}
     elif n_bin > 0:
         kb = ev_ms(timings, "binary")
         kernel_ms = sum(kb) / len(kb)
@@ -495,6 +517,7 @@ def main():
                                 "C1": "rung-2 SISSO fit: n=50, d=5, k=20, D=1..2"}[args.workload],
                    "n": n, "d": p.X.shape[1], "candidates_per_pass": total, "k": p.k, "D": p.dmax,
                    "screening_form": prec, "keep0": keep0, "band": band if prec == "bf16" else None,
+                   "bf16_moments": (eng.bf16_moments is not None) if prec == "bf16" else None,
                    "learned_frac": args.learned_frac if prec == "learned" else None},
         "sis_passes_per_step": passes_per_step,
         "sis_candidates_per_step": cands_per_step,

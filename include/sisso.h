@@ -301,6 +301,8 @@ sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score
  *   mode           SISSO_MOMENTS_NONE (moments unused, may be NULL: the same
  *                  as sisso_bf16_screen), SISSO_MOMENTS_WRITE or
  *                  SISSO_MOMENTS_READ.
+ * The READ form runs two blocks per CU and sizes its own grid (args->grid
+ * applies to the other forms).
  * A READ screen requires an earlier WRITE screen over the same pools, the same
  * operands (`ops`) and a candidate range covering its own, into the same
  * buffer; any residual, keep, band or exclusion list may differ.  The library

@@ -840,8 +840,19 @@ sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, c
     using Sh = BfShape<MODE>;
     const int n = args->n;
     const FormSlots fs = form_slots(space);
-    const BfPlan p = bf_plan(space, cand_begin, cand_end,
-                             args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid);
+    // The read form sizes its own grid: as many blocks as can be resident
+    // (kMinBlocks per CU), each sweeping its share of the u tiles.  A grid
+    // tuned for the other forms (one block per CU) would leave half its slots
+    // empty.
+    int max_grid = args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid;
+    if (Sh::kRead) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            return SISSO_E_DEVICE;
+        max_grid = Sh::kMinBlocks * cus < kMaxBfGrid ? Sh::kMinBlocks * cus : kMaxBfGrid;   // the workspace's lists
+    }
+    const BfPlan p = bf_plan(space, cand_begin, cand_end, max_grid);
     // Every block keeps min(band, K'max).  Only a block that keeps the whole
     // band may publish its threshold as the grid-wide bound (it is then a
     // lower bound of the band-th best score).
