@@ -35,12 +35,12 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSplit = 2;     // BF16 parts per operand (hi, lo)
-constexpr int kBT = 64;       // (u, v) pairs per block side: 2 x 2 waves of 32 x 32
+constexpr int kBT = 64;       // u operands per block tile (the tiling of the slice's u range)
 constexpr int kKC = 16;       // samples per LDS stage (one MFMA k-step)
 constexpr int kKR = kKC;      // bf16 per LDS row: one chunk of samples of one column
-constexpr int kPlane = kBT * kKR;                   // bf16 per staged plane (64 columns)
 constexpr int kMom = 6;       // residual-independent moments kept per (u, v) pair
 constexpr size_t kMomTile = (size_t)4 * 16 * kMom * 64;   // floats per (u tile, v tile)
 
@@ -62,13 +62,18 @@ template <int MODE> struct BfShape {
     static constexpr int kUVar = kRead ? 2 : 4;     // U~, [U~^2,] Z~, [Z~^2]
     static constexpr int kVVar = kRead ? 2 : 8;     // [V~,] V~ r, [P, Q, W~,] W~ r, [Pw, Qw]
     static constexpr int kNG = kRead ? 3 : 12;      // GEMMs per tile
+    // Block tile: kBTU u columns x kBTV v columns, one 32 x 32 sub-tile per
+    // wave.  The read form's few GEMMs leave registers for two waves per SIMD,
+    // and its wider v tile streams each u tile half as often.
+    static constexpr int kBTU = 64, kBTV = kRead ? 128 : 64;
+    static constexpr int kWV = kBTV / 32, kThreads = 64 * 2 * kWV;     // waves: 2 along u, kWV along v
+    static constexpr int kSU = kBTU * kKC / kThreads;                  // u samples staged per thread
+    static constexpr int kSV = kBTV * kKC / kThreads;                  // v samples staged per thread
+    static constexpr int kPlaneU = kBTU * kKR, kPlaneV = kBTV * kKR;   // bf16 per staged plane
     static constexpr int kPA = kUVar * kSplit, kPB = kVVar * kSplit;   // staged planes per side
-    static constexpr int kStage = (kPA + kPB) * kPlane;                // bf16 per staging buffer
-    // chunks between the global load of a chunk and the MFMAs that use it
-    static constexpr int kAhead = 2;
-    // staging buffers: the read form's LDS (one buffer) admits two blocks per CU,
-    // whose waves overlap one another's staging, barriers and MFMAs
-    static constexpr int kNBuf = kRead ? 1 : 2, kMinBlocks = kRead ? 2 : 1;
+    static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;       // bf16 per staging buffer
+    static constexpr int kNBuf = 2;                 // staging buffers
+    static constexpr int kMinBlocks = 1;            // resident blocks per CU the registers are sized for
     // accumulator of the residual contraction of u v, u/v and v/u
     static constexpr int kCovUV = kRead ? 0 : 1, kCovUW = kRead ? 1 : 5, kCovZV = kRead ? 2 : 9;
 };
@@ -108,16 +113,24 @@ struct BfWs {
     float *band_sc;
     int32_t *band_cnt;
     void *lists;      // screening workspace of the BF16 lists
+    __bf16 *vimg;     // the read form's v-side staging image (see k_bf16_v_image)
 };
-__host__ __device__ inline size_t bf_ws_bytes(int64_t ucols, int64_t vcols, int band, int lists, int keep)
+// bf16 of the read form's v-side image: per 128-column v tile and chunk of
+// samples, the staged planes of V~ r and W~ r (hi and lo) in their LDS layout
+__host__ __device__ inline size_t bf_vimg_elems(int64_t vcols, int n)
+{
+    return (size_t)((vcols + 127) / 128) * (size_t)((n + kKC - 1) / kKC) * (2 * kSplit) * (128 * kKR);
+}
+__host__ __device__ inline size_t bf_ws_bytes(int64_t ucols, int64_t vcols, int n, int band, int lists, int keep)
 {
     size_t b = align256b((size_t)vcols * 2 * sizeof(float4));
     b += align256b((size_t)ucols * sizeof(float2));
     b += align256b((size_t)band * sizeof(int64_t)) + align256b((size_t)band * sizeof(float)) + 256;
-    b += ws_bytes_for(lists, keep);
+    b += align256b(ws_bytes_for(lists, keep));
+    b += align256b(bf_vimg_elems(vcols, n) * sizeof(__bf16));
     return b;
 }
-__host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols, int band)
+__host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols, int band, int lists, int keep)
 {
     BfWs w;
     char *c = (char *)p;
@@ -126,7 +139,8 @@ __host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols
     w.band_ids = (int64_t *)c; c += align256b((size_t)band * sizeof(int64_t));
     w.band_sc = (float *)c; c += align256b((size_t)band * sizeof(float));
     w.band_cnt = (int32_t *)c; c += 256;
-    w.lists = c;
+    w.lists = c; c += align256b(ws_bytes_for(lists, keep));
+    w.vimg = (__bf16 *)c;
     return w;
 }
 
@@ -140,6 +154,43 @@ __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 __device__ __forceinline__ int lds_off(int row, int k)
 {
     return row * kKR + (k ^ ((((row >> 2) ^ (row >> 3)) & 1) << 3));
+}
+
+// N consecutive floats (N = 2 or 4, 4N-byte aligned) in one load.
+template <int N>
+__device__ __forceinline__ void load_floats(const float *p, float (&x)[N])
+{
+    static_assert(N == 2 || N == 4, "2 or 4 samples per thread");
+    if constexpr (N == 4) {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+    } else {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        x[0] = t.x; x[1] = t.y;
+    }
+}
+
+// Stores the BF16 parts of N consecutive samples: hi = bf16(x) at dst, lo =
+// bf16(x - hi) one plane further; two values per conversion.
+template <int N>
+__device__ __forceinline__ void put_split(__bf16 *dst, int plane, const float (&x)[N])
+{
+#pragma clang fp contract(off)
+    unsigned hw[N / 2], lw[N / 2];
+#pragma unroll
+    for (int e = 0; e < N; e += 2) {
+        const bf16x2 h = __builtin_convertvector((f32x2){x[e], x[e + 1]}, bf16x2);
+        const bf16x2 l = __builtin_convertvector((f32x2){x[e] - (float)h[0], x[e + 1] - (float)h[1]}, bf16x2);
+        __builtin_memcpy(&hw[e / 2], &h, 4);
+        __builtin_memcpy(&lw[e / 2], &l, 4);
+    }
+    if constexpr (N == 4) {
+        *reinterpret_cast<uint2 *>(dst) = make_uint2(hw[0], hw[1]);
+        *reinterpret_cast<uint2 *>(dst + plane) = make_uint2(lw[0], lw[1]);
+    } else {
+        *reinterpret_cast<unsigned *>(dst) = hw[0];
+        *reinterpret_cast<unsigned *>(dst + plane) = lw[0];
+    }
 }
 
 // ---------------------------------------------------------------- operands
@@ -227,30 +278,85 @@ __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restr
     }
 }
 
+// The residual-weighted centred v variants of one sample, V~ r and W~ r (0 for
+// a sample past n).  The write form forms them in its tile kernel and the read
+// form takes them from the v-side image: one function, the same bits.
+__device__ __forceinline__ void v_resid_vars(float x, float r, float smv, float smw, bool live, float &vr,
+                                             float &wr)
+{
+#pragma clang fp contract(off)
+    float vv = x - smv, ww = __builtin_amdgcn_rcpf(x) - smw;
+    vv = live ? vv : 0.f; ww = live ? ww : 0.f; r = live ? r : 0.f;
+    vr = vv * r;
+    wr = ww * r;
+}
+
+// The read form's v-side staging image for one residual: for each 128-column
+// v tile and chunk of 16 samples, the planes V~ r hi, V~ r lo, W~ r hi, W~ r lo
+// (128 rows of 16 samples each) exactly as the tile kernel lays them out in
+// LDS, so that staging them is a copy.  Block (vt, ch); thread t forms column
+// t / 2, samples 8 (t % 2) .. + 7.  Columns past |P_1| stage column 0's values
+// (their scores are discarded), samples past n zeros.
+__global__ void __launch_bounds__(256) k_bf16_v_image(int n, const float *__restrict__ pool32, int64_t ld32,
+                                                      int64_t vcols, const float *__restrict__ r32,
+                                                      const float4 *__restrict__ vsum, __bf16 *__restrict__ img)
+{
+    constexpr int kRows = 128, kPlanes = 2 * kSplit;
+    const int nch = (n + kKC - 1) / kKC;
+    const int64_t vt = blockIdx.x / nch;
+    const int ch = blockIdx.x % nch;
+    const int c = threadIdx.x >> 1, k0 = (threadIdx.x & 1) * 8;
+    const int64_t v = vt * kRows + c;
+    const int64_t vv = v < vcols ? v : 0;
+    const float4 vs = vsum[2 * vv];
+    const float *col = pool32 + (size_t)vv * ld32;
+    float vr[8], wr[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int t = ch * kKC + k0 + e;
+        const int tc = t < n ? t : n - 1;
+        v_resid_vars(col[tc], r32[tc], vs.x, vs.y, t < n, vr[e], wr[e]);
+    }
+    __bf16 *const out = img + (size_t)blockIdx.x * kPlanes * kRows * kKR + lds_off(c, k0);
+    __bf16 hv[8], lv[8], hw[8], lw[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+#pragma clang fp contract(off)
+        hv[e] = (__bf16)vr[e]; lv[e] = (__bf16)(vr[e] - (float)hv[e]);
+        hw[e] = (__bf16)wr[e]; lw[e] = (__bf16)(wr[e] - (float)hw[e]);
+    }
+    __builtin_memcpy(out, hv, 16);
+    __builtin_memcpy(out + kRows * kKR, lv, 16);
+    __builtin_memcpy(out + 2 * kRows * kKR, hw, 16);
+    __builtin_memcpy(out + 3 * kRows * kKR, lw, 16);
+}
+
 // -------------------------------------------------------------- screening
 
-// mom: per (u tile, v tile, wave, row slot r, moment k) the 64 lanes' values,
-// at float offset (((ut * nvt + vt) * 4 + wave) * 16 + r) * kMom * 64 + k * 64 + lane
-// (written by kBfWrite, read by kBfRead, unused by kBfFull).
+// mom: per 64 x 64 tile (ut, vt64) of (u, v) pairs, its four 32 x 32 sub-tiles
+// w = wu + 2 wv, row slot r and moment k, the 64 lanes' values, at float offset
+// (((ut * nvt64 + vt64) * 4 + w) * 16 + r) * kMom * 64 + k * 64 + lane
+// (written by kBfWrite, read by kBfRead, unused by kBfFull; nvt64 = ceil(|P_1| / 64)).
 template <int MODE>
-__global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_bf16(
+__global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBlocks) k_score_rect_bf16(
     sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
     const float *__restrict__ r32, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
     const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
-    int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, void *lws, int lists_total,
-    int keep, int cap, int publish)
+    int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, const __bf16 *__restrict__ vimg,
+    void *lws, int lists_total, int keep, int cap, int publish)
 {
     using Sh = BfShape<MODE>;
     constexpr int kUVar = Sh::kUVar, kVVar = Sh::kVVar, kNG = Sh::kNG, kPA = Sh::kPA, kPB = Sh::kPB,
-                  kStage = Sh::kStage;
+                  kStage = Sh::kStage, kBTU = Sh::kBTU, kBTV = Sh::kBTV, kSU = Sh::kSU, kSV = Sh::kSV,
+                  kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // kNBuf staging buffers
     float *lsc = (float *)(stage + Sh::kNBuf * kStage);
     int64_t *lid = (int64_t *)(lsc + cap);
     // u-tile column constants for the epilogue: (mean u, mean 1/u, sum u~^2,
     // sum z~^2) and (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero)
-    float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBT;
+    float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBTU;
     __shared__ int lcnt, lpend;
     __shared__ float lthr;
     __shared__ unsigned gdummy;                   // bound of a block that must not publish (stays 0)
@@ -269,24 +375,26 @@ __global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_b
     const int S = s.n_slots;
     const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
     const int nch = (n + kKC - 1) / kKC;
-    const int64_t nvt = (vcount + kBT - 1) / kBT;
-    // staging role: column scol of the u and v tiles, samples 4 squad .. 4 squad + 3 of a chunk
-    const int scol = tid >> 2, squad = tid & 3;
-    const int tmax = ((n - 1) >> 2) << 2;        // last 4-aligned sample start: loads stay inside the column
-    const int sto = lds_off(scol, squad * 4);     // staging store offset within a plane
-    // fragment role: lane reads 8 samples (koff ..) of row lane % 32 of its wave's 32-row half
+    const int64_t nvt = (vcount + kBTV - 1) / kBTV, nvt64 = (vcount + 63) / 64;
+    // staging roles: u column ucs, samples uks .. uks + kSU - 1 of a chunk; v
+    // column vcs, samples vks .. vks + kSV - 1
+    const int ucs = tid / (kKC / kSU), uks = (tid % (kKC / kSU)) * kSU;
+    const int vcs = tid / (kKC / kSV), vks = (tid % (kKC / kSV)) * kSV;
+    const int tmax_u = ((n - 1) / kSU) * kSU, tmax_v = ((n - 1) / kSV) * kSV;   // loads stay inside a column
+    const int sto_u = lds_off(ucs, uks), sto_v = lds_off(vcs, vks);              // store offsets within a plane
+    // fragment role: lane reads 8 samples (koff ..) of row lane % 32 of its wave's 32-row part
     const int koff = (lane >> 5) * 8;
     const int fa = lds_off(wu * 32 + (lane & 31), koff), fb = lds_off(wv * 32 + (lane & 31), koff);
 
     for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
-        const int64_t u0 = ut * kBT;   // index into the newest level
-        const int64_t su = u0 + scol;
+        const int64_t u0 = ut * kBTU;  // index into the newest level
+        const int64_t su = u0 + ucs;
         const bool su_ok = su < ucols;
         const float4 us_c = usum[su_ok ? su : 0];
         const float smu = us_c.x, smz = us_c.y;
         const float *ucol = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
         __syncthreads();                              // the previous tile's epilogue reads are done
-        if (tid < kBT) {
+        if (tid < kBTU) {
             const int64_t x = u0 + tid;
             const bool in = x < ucols;
             const sisso_colstat cs = stats[ulo + (in ? x : 0)];
@@ -296,8 +404,8 @@ __global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_b
                                       (in && cs.valid != 0.0f ? 1.0f : 0.0f) + (cs.minabs > 0.0f ? 2.0f : 0.0f));
         }
         for (int64_t vt = 0; vt < nvt; ++vt) {
-            const int64_t v0 = vt * kBT;
-            const int64_t sv = v0 + scol;
+            const int64_t v0 = vt * kBTV;
+            const int64_t sv = v0 + vcs;
             const bool sv_ok = sv < vcount;
             const float4 vs_c = vsum[2 * (sv_ok ? sv : 0)];
             const float smv = vs_c.x, smw = vs_c.y;
@@ -314,62 +422,70 @@ __global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_b
             // column 0 (their rows and columns are dropped by the epilogue); a
             // zero in a column gives infinite reciprocal variants, which reach
             // only the accumulators of the form whose domain excludes it.
-            float4 pu, pv, pr;
-            auto load_chunk = [&](int ch, float4 &xu4, float4 &xv4, float4 &xr4) {
-                const int t0 = min(ch * kKC + squad * 4, tmax);
-                xu4 = *reinterpret_cast<const float4 *>(ucol + t0);
-                xv4 = *reinterpret_cast<const float4 *>(vcol + t0);
-                xr4 = *reinterpret_cast<const float4 *>(r32 + t0);
+            // The read form copies its v side from the image (32 bytes per thread
+            // and chunk); the other forms form it from v and r.
+            constexpr int kRawV = Sh::kRead ? 1 : kSV;
+            struct Raw {
+                float u[kSU], v[kRawV], r[kRawV];
+                u32x4 i0, i1;                         // image bytes (read form)
+            };
+            Raw pr;                                   // the next chunk to stage
+            auto load_chunk = [&](int ch, Raw &x) {
+                const int tu = min(ch * kKC + uks, tmax_u);
+                load_floats<kSU>(ucol + tu, x.u);
+                if constexpr (Sh::kRead) {
+                    const int cc = min(ch, nch - 1);
+                    const u32x4 *src = reinterpret_cast<const u32x4 *>(vimg + (size_t)(vt * nch + cc) * kPB * kPlaneV);
+                    x.i0 = src[2 * tid];
+                    x.i1 = src[2 * tid + 1];
+                } else {
+                    const int tv = min(ch * kKC + vks, tmax_v);
+                    load_floats<kSV>(vcol + tv, x.v);
+                    load_floats<kSV>(r32 + tv, x.r);
+                }
             };
             auto store_chunk = [&](int ch, __bf16 *buf, bool tail) {
                 // no contraction: the parts of U~, Z~, V~ r and W~ r are the same
                 // bits in every mode, so the residual GEMMs agree exactly
 #pragma clang fp contract(off)
-                const int t0 = ch * kKC + squad * 4;
-                const float xu[4] = {pu.x, pu.y, pu.z, pu.w};
-                const float xv[4] = {pv.x, pv.y, pv.z, pv.w};
-                const float xr[4] = {pr.x, pr.y, pr.z, pr.w};
-                float ua[kUVar][4], va[kVVar][4];
+                float ua[kUVar][kSU], va[kVVar][kSV];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float ru = __builtin_amdgcn_rcpf(xu[e]), rv = __builtin_amdgcn_rcpf(xv[e]);
-                    float uu = xu[e] - smu, zz = ru - smz, vv = xv[e] - smv, ww = rv - smw, r = xr[e];
+                for (int e = 0; e < kSU; ++e) {
+                    float uu = pr.u[e] - smu, zz = __builtin_amdgcn_rcpf(pr.u[e]) - smz;
                     if (tail) {                       // samples past n contribute nothing
-                        const bool live = t0 + e < n;
+                        const bool live = ch * kKC + uks + e < n;
                         uu = live ? uu : 0.f; zz = live ? zz : 0.f;
-                        vv = live ? vv : 0.f; ww = live ? ww : 0.f; r = live ? r : 0.f;
                     }
                     if constexpr (Sh::kRead) {
                         ua[0][e] = uu; ua[1][e] = zz;
-                        va[0][e] = vv * r; va[1][e] = ww * r;
                     } else {
                         ua[0][e] = uu; ua[1][e] = uu * uu; ua[2][e] = zz; ua[3][e] = zz * zz;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kUVar; ++q)
+                    put_split<kSU>(buf + (q * kSplit) * kPlaneU + sto_u, kPlaneU, ua[q]);
+                if constexpr (Sh::kRead) {
+                    u32x4 *dst = reinterpret_cast<u32x4 *>(buf + kPA * kPlaneU);
+                    dst[2 * tid] = pr.i0;
+                    dst[2 * tid + 1] = pr.i1;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < kSV; ++e) {
+                        float vv = pr.v[e] - smv, ww = __builtin_amdgcn_rcpf(pr.v[e]) - smw, r = pr.r[e];
+                        if (tail) {
+                            const bool live = ch * kKC + vks + e < n;
+                            vv = live ? vv : 0.f; ww = live ? ww : 0.f; r = live ? r : 0.f;
+                        }
                         va[0][e] = vv; va[1][e] = vv * r; va[2][e] = vv * (vv + 2.f * smv);
                         va[3][e] = vv * (vv + smv);
                         va[4][e] = ww; va[5][e] = ww * r; va[6][e] = ww * (ww + 2.f * smw);
                         va[7][e] = ww * (ww + smw);
                     }
+#pragma unroll
+                    for (int q = 0; q < kVVar; ++q)
+                        put_split<kSV>(buf + kPA * kPlaneU + (q * kSplit) * kPlaneV + sto_v, kPlaneV, va[q]);
                 }
-                auto put = [&](__bf16 *plane, const float (&x)[4]) {
-                    // hi = bf16(x), lo = bf16(x - hi), two values per conversion
-                    const bf16x2 h01 = __builtin_convertvector((f32x2){x[0], x[1]}, bf16x2);
-                    const bf16x2 h23 = __builtin_convertvector((f32x2){x[2], x[3]}, bf16x2);
-                    const bf16x2 l01 = __builtin_convertvector(
-                        (f32x2){x[0] - (float)h01[0], x[1] - (float)h01[1]}, bf16x2);
-                    const bf16x2 l23 = __builtin_convertvector(
-                        (f32x2){x[2] - (float)h23[0], x[3] - (float)h23[1]}, bf16x2);
-                    uint2 ph, pl;
-                    __builtin_memcpy(&ph.x, &h01, 4);
-                    __builtin_memcpy(&ph.y, &h23, 4);
-                    __builtin_memcpy(&pl.x, &l01, 4);
-                    __builtin_memcpy(&pl.y, &l23, 4);
-                    *reinterpret_cast<uint2 *>(plane + sto) = ph;
-                    *reinterpret_cast<uint2 *>(plane + kPlane + sto) = pl;
-                };
-#pragma unroll
-                for (int q = 0; q < kUVar; ++q) put(buf + (q * kSplit) * kPlane, ua[q]);
-#pragma unroll
-                for (int q = 0; q < kVVar; ++q) put(buf + (kPA + q * kSplit) * kPlane, va[q]);
             };
             // GEMM g: u-side variant GA[g], v-side variant GB[g]; terms hi*hi, hi*lo, lo*hi
             constexpr int GAf[12] = {0, 0, 1, 0, 0, 0, 1, 0, 2, 2, 3, 2};
@@ -383,10 +499,10 @@ __global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_b
             auto mfma_chunk = [&](const __bf16 *buf) {
                 bf16x8 af[kPA], bfr[kPB];
 #pragma unroll
-                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const bf16x8 *>(buf + a * kPlane + fa);
+                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const bf16x8 *>(buf + a * kPlaneU + fa);
 #pragma unroll
                 for (int q = 0; q < kPB; ++q)
-                    bfr[q] = *reinterpret_cast<const bf16x8 *>(buf + (kPA + q) * kPlane + fb);
+                    bfr[q] = *reinterpret_cast<const bf16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb);
                 if constexpr (Sh::kNBuf == 1) __syncthreads();
 #pragma unroll
                 for (int term = 0; term < 3; ++term) {
@@ -415,33 +531,28 @@ __global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_b
                 }
             };
             auto buf_of = [&](int c) { return Sh::kNBuf == 2 ? stage + (c & 1) * kStage : stage; };
+            // this wave's 32 x 32 sub-tile in the moments' 64 x 64 tiling; a
+            // sub-tile past the last 64-column tile has no pair in the space
+            const int64_t v32 = vt * Sh::kWV + wv;
+            const bool mom_in = (v32 >> 1) < nvt64;
+            const size_t mom_off = (((size_t)ut * nvt64 + (v32 >> 1)) * 4 + wu + 2 * (int)(v32 & 1)) *
+                                   (16 * kMom * 64);
             __syncthreads();                          // the previous tile's fragment reads are done
             if (tid == 0) lpend = 0;                  // every thread has read the previous total
-            // Chunks ch + 2 .. ch + kAhead - 1 wait in registers behind pu/pv/pr
-            // (chunk ch + 1); loads past the last chunk re-read its samples.
-            constexpr int kAhead = Sh::kAhead, kRing = kAhead > 2 ? kAhead - 2 : 1;
-            float4 fu[kRing], fv[kRing], fr[kRing];
-            load_chunk(0, pu, pv, pr);
+            // pr holds chunk ch + 1 while chunk ch + 2 loads (loads past the last
+            // chunk re-read its samples)
+            load_chunk(0, pr);
             store_chunk(0, stage, nch == 1);
-            load_chunk(1, pu, pv, pr);
-#pragma unroll
-            for (int a = 0; a + 2 < kAhead; ++a) load_chunk(2 + a, fu[a], fv[a], fr[a]);
+            load_chunk(1, pr);
             __syncthreads();
             int ch = 0;
             for (; ch + 2 < nch; ++ch) {              // chunk ch + 1 is full
-                float4 qu, qv, qr;
-                load_chunk(ch + kAhead, qu, qv, qr);
+                Raw q;
+                load_chunk(ch + 2, q);
                 mfma_chunk(buf_of(ch));
                 store_chunk(ch + 1, buf_of(ch + 1), false);
                 interleave();
-                if constexpr (kAhead > 2) {
-                    pu = fu[0]; pv = fv[0]; pr = fr[0];
-#pragma unroll
-                    for (int a = 0; a + 3 < kAhead; ++a) { fu[a] = fu[a + 1]; fv[a] = fv[a + 1]; fr[a] = fr[a + 1]; }
-                    fu[kRing - 1] = qu; fv[kRing - 1] = qv; fr[kRing - 1] = qr;
-                } else {
-                    pu = qu; pv = qv; pr = qr;
-                }
+                pr = q;
                 __syncthreads();
             }
             if (ch + 1 < nch) {                       // chunk ch + 1 is the last one
@@ -457,9 +568,9 @@ __global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_b
             // CU runs meanwhile), or formed from the accumulators (write)
             float mr[MODE != kBfFull ? 16 * kMom : 1];
             if constexpr (Sh::kRead) {
-                const float *const mp = mom + (((size_t)ut * nvt + vt) * 4 + w) * (16 * kMom * 64) + lane;
+                const float *const mp = mom + mom_off + lane;
 #pragma unroll
-                for (int q = 0; q < 16 * kMom; ++q) mr[q] = __builtin_nontemporal_load(mp + q * 64);
+                for (int q = 0; q < 16 * kMom; ++q) mr[q] = mom_in ? __builtin_nontemporal_load(mp + q * 64) : 0.0f;
             }
 
             // epilogue: lane holds column j = lane % 32 and rows
@@ -497,7 +608,7 @@ __global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_b
             if constexpr (MODE == kBfWrite) {
                 // kept in registers for the scores below: the nine accumulators
                 // they come from are dead from here on
-                float *const mp = mom + (((size_t)ut * nvt + vt) * 4 + w) * (16 * kMom * 64) + lane;
+                float *const mp = mom + mom_off + lane;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     float m[kMom];
@@ -562,7 +673,7 @@ __global__ void __launch_bounds__(256, BfShape<MODE>::kMinBlocks) k_score_rect_b
             // every id of the tile inside [id_begin, id_end) (the usual case): no
             // per-candidate range check
             const int64_t tile_lo = binbase + (u0 * vcount + v0) * S;
-            const int64_t tile_hi = binbase + ((u0 + kBT - 1) * vcount + v0 + kBT - 1) * S + S;
+            const int64_t tile_hi = binbase + ((u0 + kBTU - 1) * vcount + v0 + kBTV - 1) * S + S;
             const bool tile_in = tile_lo >= id_begin && tile_hi <= id_end;
             auto admit_id = [&](int64_t id) {
                 return (tile_in || (id >= id_begin && id < id_end)) &&
@@ -739,7 +850,8 @@ BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end, int max_grid = 
 
 int bf_lists_cap(const sisso_space *s) { return bf_plan(s, 0, s->total).grid; }
 
-int bf_list_cap(int keep) { return next_pow2(keep + 256); }
+// a block list holds keep entries plus one offer per thread between merges
+int bf_list_cap(int keep, int threads) { return next_pow2(keep + threads); }
 
 // Per-block list length of a band: the block keeps its best min(band, K'max)
 // (the LDS list); the grid-wide merge then takes the best `band` of all lists.
@@ -781,7 +893,7 @@ extern "C" size_t sisso_bf16_workspace_size(const sisso_space *space, const siss
     if (!space_ok(space) || !args || args->n < 2 || band < 1 || band > SISSO_MAX_BAND) return 0;
     const int L = space->levels;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
-    return bf_ws_bytes(ucols, vcols, band, bf_lists_cap(space), bf_block_keep(band));
+    return bf_ws_bytes(ucols, vcols, args->n, band, bf_lists_cap(space), bf_block_keep(band));
 }
 
 extern "C" int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_score_args *args,
@@ -820,12 +932,15 @@ extern "C" sisso_status sisso_bf16_residual(const sisso_space *space, const siss
     hipStream_t st = as_stream(stream);
     const int L = space->levels, n = args->n;
     const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
-    BfWs w = bf_ws_view(bws, ucols, vcols, band);
+    BfWs w = bf_ws_view(bws, ucols, vcols, band, bf_lists_cap(space), bf_block_keep(band));
     const int64_t vb = (vcols + 3) / 4, ub = (ucols + 3) / 4;
     hipLaunchKernelGGL(k_bf16_v_prep, dim3((unsigned)(vb < 65536 ? vb : 65536)), dim3(256), 0, st, n, args->pool32,
                        args->ld32, args->stats, vcols, args->r32, w);
     hipLaunchKernelGGL(k_bf16_u_resid, dim3((unsigned)(ub < 65536 ? ub : 65536)), dim3(256), 0, st, n, args->pool32,
                        args->ld32, args->stats, col0, ucols, args->r32, w.ures);
+    const int64_t img_blocks = ((vcols + 127) / 128) * (int64_t)((n + kKC - 1) / kKC);
+    hipLaunchKernelGGL(k_bf16_v_image, dim3((unsigned)img_blocks), dim3(256), 0, st, n, args->pool32, args->ld32,
+                       vcols, args->r32, w.vsum, w.vimg);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 
@@ -857,18 +972,18 @@ sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, c
     // band may publish its threshold as the grid-wide bound (it is then a
     // lower bound of the band-th best score).
     const int keep_b = bf_block_keep(band);
-    const int cap_b = bf_list_cap(keep_b);
+    const int cap_b = bf_list_cap(keep_b, Sh::kThreads);
     const int publish = keep_b >= band ? 1 : 0;
     const int lcap = bf_lists_cap(space);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)Sh::kNBuf * Sh::kStage * sizeof(__bf16) + 2 * kBT * sizeof(float4) +
+        const size_t smem = (size_t)Sh::kNBuf * Sh::kStage * sizeof(__bf16) + 2 * Sh::kBTU * sizeof(float4) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16<MODE>, smem)) return SISSO_E_UNSUPPORTED;
-        hipLaunchKernelGGL(k_score_rect_bf16<MODE>, dim3(p.grid), dim3(256), smem, st, *space, fs, n,
+        hipLaunchKernelGGL(k_score_rect_bf16<MODE>, dim3(p.grid), dim3(Sh::kThreads), smem, st, *space, fs, n,
                            args->pool32, args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info,
-                           args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, mom, w.lists,
-                           lcap, keep_b, cap_b, publish);
+                           args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, mom, w.vimg,
+                           w.lists, lcap, keep_b, cap_b, publish);
     }
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
@@ -893,7 +1008,7 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     hipStream_t st = as_stream(stream);
     const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
     const BfOps o = bf_ops_view(const_cast<void *>(ops));
-    BfWs w = bf_ws_view(bws, ucols, vcols, band);
+    BfWs w = bf_ws_view(bws, ucols, vcols, band, bf_lists_cap(space), bf_block_keep(band));
     float *mom = (float *)moments;
     switch (mode) {
     case SISSO_MOMENTS_WRITE: return bf_launch<kBfWrite>(space, args, o, w, band, cand_begin, cand_end, mom, st);
@@ -943,7 +1058,7 @@ extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso
     hipStream_t st = as_stream(stream);
     const int L = space->levels, n = args->n;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
-    BfWs w = bf_ws_view(bws, ucols, vcols, band);
+    BfWs w = bf_ws_view(bws, ucols, vcols, band, bf_lists_cap(space), bf_block_keep(band));
     const FormSlots fs = form_slots(space);
     sisso_status rs = topk_launch(w.lists, band, w.band_ids, w.band_sc, w.band_cnt, st, band > bf_block_keep(band));
     if (rs != SISSO_OK) return rs;
