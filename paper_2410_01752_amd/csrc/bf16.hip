@@ -73,6 +73,9 @@ template <int MODE> struct BfShape {
     static constexpr int kPA = kUVar * kSplit, kPB = kVVar * kSplit;   // staged planes per side
     static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;       // bf16 per staging buffer
     static constexpr int kNBuf = 2;                 // staging buffers
+    // chunks between a chunk's global loads and its MFMAs (deeper rings were
+    // slower: the read form is not bound by load latency)
+    static constexpr int kAhead = 2;
     static constexpr int kMinBlocks = 1;            // resident blocks per CU the registers are sized for
     // accumulator of the residual contraction of u v, u/v and v/u
     static constexpr int kCovUV = kRead ? 0 : 1, kCovUW = kRead ? 1 : 5, kCovZV = kRead ? 2 : 9;
@@ -436,8 +439,8 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 if constexpr (Sh::kRead) {
                     const int cc = min(ch, nch - 1);
                     const u32x4 *src = reinterpret_cast<const u32x4 *>(vimg + (size_t)(vt * nch + cc) * kPB * kPlaneV);
-                    x.i0 = src[2 * tid];
-                    x.i1 = src[2 * tid + 1];
+                    x.i0 = src[tid];                  // each wave instruction: 1 KB contiguous
+                    x.i1 = src[tid + Sh::kThreads];
                 } else {
                     const int tv = min(ch * kKC + vks, tmax_v);
                     load_floats<kSV>(vcol + tv, x.v);
@@ -467,8 +470,8 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                     put_split<kSU>(buf + (q * kSplit) * kPlaneU + sto_u, kPlaneU, ua[q]);
                 if constexpr (Sh::kRead) {
                     u32x4 *dst = reinterpret_cast<u32x4 *>(buf + kPA * kPlaneU);
-                    dst[2 * tid] = pr.i0;
-                    dst[2 * tid + 1] = pr.i1;
+                    dst[tid] = pr.i0;
+                    dst[tid + Sh::kThreads] = pr.i1;
                 } else {
 #pragma unroll
                     for (int e = 0; e < kSV; ++e) {
@@ -477,10 +480,11 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                             const bool live = ch * kKC + vks + e < n;
                             vv = live ? vv : 0.f; ww = live ? ww : 0.f; r = live ? r : 0.f;
                         }
-                        va[0][e] = vv; va[1][e] = vv * r; va[2][e] = vv * (vv + 2.f * smv);
-                        va[3][e] = vv * (vv + smv);
-                        va[4][e] = ww; va[5][e] = ww * r; va[6][e] = ww * (ww + 2.f * smw);
-                        va[7][e] = ww * (ww + smw);
+                        va[0][e] = vv; va[2][e] = vv * (vv + 2.f * smv); va[3][e] = vv * (vv + smv);
+                        va[4][e] = ww; va[6][e] = ww * (ww + 2.f * smw); va[7][e] = ww * (ww + smw);
+                        // V~ r and W~ r as the read form's image has them
+                        v_resid_vars(pr.v[e], pr.r[e], smv, smw, !tail || ch * kKC + vks + e < n, va[1][e],
+                                     va[5][e]);
                     }
 #pragma unroll
                     for (int q = 0; q < kVVar; ++q)
@@ -539,20 +543,31 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                                    (16 * kMom * 64);
             __syncthreads();                          // the previous tile's fragment reads are done
             if (tid == 0) lpend = 0;                  // every thread has read the previous total
-            // pr holds chunk ch + 1 while chunk ch + 2 loads (loads past the last
-            // chunk re-read its samples)
+            // pr holds chunk ch + 1 and ring[] chunks ch + 2 .. ch + kAhead - 1
+            // while chunk ch + kAhead loads (loads past the last chunk re-read it)
+            constexpr int kAhead = Sh::kAhead, kRing = kAhead > 2 ? kAhead - 2 : 1;
+            Raw ring[kRing];
             load_chunk(0, pr);
             store_chunk(0, stage, nch == 1);
             load_chunk(1, pr);
+#pragma unroll
+            for (int a = 0; a + 2 < kAhead; ++a) load_chunk(2 + a, ring[a]);
             __syncthreads();
             int ch = 0;
             for (; ch + 2 < nch; ++ch) {              // chunk ch + 1 is full
                 Raw q;
-                load_chunk(ch + 2, q);
+                load_chunk(ch + kAhead, q);
                 mfma_chunk(buf_of(ch));
                 store_chunk(ch + 1, buf_of(ch + 1), false);
                 interleave();
-                pr = q;
+                if constexpr (kAhead > 2) {
+                    pr = ring[0];
+#pragma unroll
+                    for (int a = 0; a + 3 < kAhead; ++a) ring[a] = ring[a + 1];
+                    ring[kRing - 1] = q;
+                } else {
+                    pr = q;
+                }
                 __syncthreads();
             }
             if (ch + 1 < nch) {                       // chunk ch + 1 is the last one
@@ -631,7 +646,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // Approximate scores of the five forms of row r of this lane, -1 for
             // a pair outside the space or a form outside its domain.  Branch-free;
             // ids are formed only for the few candidates at the admission bound.
-            auto row_scores = [&](int r, float (&sc)[5]) {
+            auto row_sums = [&](int r, float (&cov)[5], float (&var)[5], bool (&live)[5]) {
 #pragma clang fp contract(off)
                 const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const float4 us = ucon_a[wu * 32 + i], ub = ucon_b[wu * 32 + i];
@@ -641,7 +656,6 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 float m[kMom];
                 moments_of(r, m);
                 const float g0 = m[0];
-                float cov[5], var[5];
                 var[0] = Suu + Svv + 2.0f * g0;                     // u + v
                 var[1] = Suu + Svv - 2.0f * g0;                     // u - v
                 cov[0] = Sur + Svr;
@@ -659,11 +673,17 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 const float scale = fmaxf(ub.z, vrm);
                 const float cth = 1e-4f * scale * scale * fn;
 #pragma unroll
+                for (int k = 0; k < 5; ++k) live[k] = ok && dom[k] && fs.slot[k] >= 0 && var[k] > (k < 2 ? cth : 0.0f);
+            };
+            auto row_scores = [&](int r, float (&sc)[5]) {
+                float cov[5], var[5];
+                bool live[5];
+                row_sums(r, cov, var, live);
+#pragma unroll
                 for (int k = 0; k < 5; ++k) {
                     const float q = fabsf(cov[k]) * __builtin_amdgcn_rsqf(var[k] * (float)Srr);
                     const float sk = q <= 1.0f ? q : (q > 1.0f ? 1.0f : -1.0f);   // rounding above 1, or NaN
-                    const bool live = ok && dom[k] && fs.slot[k] >= 0 && var[k] > (k < 2 ? cth : 0.0f);
-                    sc[k] = live ? sk : -1.0f;
+                    sc[k] = live[k] ? sk : -1.0f;
                 }
             };
             auto fid_of = [&](int r, int k) -> int64_t {
@@ -685,14 +705,22 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // into the list, every thread reserves its slots with one atomic and
             // writes them: no per-row barriers.
             const float tb = fmaxf(*Lst.thr, load_gthr(gb));
-            unsigned rows = 0;                        // bit r: row r has a candidate at the bound
+            // Rows with a candidate at the bound, by a test without the reciprocal
+            // square root: |cov| / sqrt(var Srr) >= tb as cov^2 >= var Srr tb^2,
+            // loosened by a margin above the rounding of rsq and of the squares.
+            // It may flag a row whose scores all fall below the bound (the exact
+            // test below then admits nothing from it), never the reverse.
+            const bool no_bound = !(tb > 0.0f);
+            const float k2 = (float)Srr * tb * tb * (1.0f - 1e-5f);
+            unsigned rows = 0;                        // bit r: row r may have a candidate at the bound
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                float sc[5];
-                row_scores(r, sc);
+                float cov[5], var[5];
+                bool live[5];
+                row_sums(r, cov, var, live);
                 bool hit = false;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) hit = hit || (sc[k] >= 0.0f && sc[k] >= tb);
+                for (int k = 0; k < 5; ++k) hit = hit || (live[k] && (no_bound || cov[k] * cov[k] >= var[k] * k2));
                 rows |= (hit ? 1u : 0u) << r;
             }
             int mine = 0;
