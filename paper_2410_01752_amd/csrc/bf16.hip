@@ -72,10 +72,6 @@ template <int MODE> struct BfShape {
     static constexpr int kPlaneU = kBTU * kKR, kPlaneV = kBTV * kKR;   // bf16 per staged plane
     static constexpr int kPA = kUVar * kSplit, kPB = kVVar * kSplit;   // staged planes per side
     static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;       // bf16 per staging buffer
-    static constexpr int kNBuf = 2;                 // staging buffers
-    // chunks between a chunk's global loads and its MFMAs (deeper rings were
-    // slower: the read form is not bound by load latency)
-    static constexpr int kAhead = 2;
     static constexpr int kMinBlocks = 1;            // resident blocks per CU the registers are sized for
     // accumulator of the residual contraction of u v, u/v and v/u
     static constexpr int kCovUV = kRead ? 0 : 1, kCovUW = kRead ? 1 : 5, kCovZV = kRead ? 2 : 9;
@@ -354,8 +350,8 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                   kStage = Sh::kStage, kBTU = Sh::kBTU, kBTV = Sh::kBTV, kSU = Sh::kSU, kSV = Sh::kSV,
                   kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // kNBuf staging buffers
-    float *lsc = (float *)(stage + Sh::kNBuf * kStage);
+    __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // two staging buffers
+    float *lsc = (float *)(stage + 2 * kStage);
     int64_t *lid = (int64_t *)(lsc + cap);
     // u-tile column constants for the epilogue: (mean u, mean 1/u, sum u~^2,
     // sum z~^2) and (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero)
@@ -507,7 +503,6 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
 #pragma unroll
                 for (int q = 0; q < kPB; ++q)
                     bfr[q] = *reinterpret_cast<const bf16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb);
-                if constexpr (Sh::kNBuf == 1) __syncthreads();
 #pragma unroll
                 for (int term = 0; term < 3; ++term) {
                     const int pa_ = term == 2 ? 1 : 0, pb_ = term == 1 ? 1 : 0;
@@ -520,8 +515,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // interleave: fragment reads first, then each MFMA followed by a share of
             // the staging work of the next chunk (VALU and LDS stores)
             auto interleave = [&]() {
-                if constexpr (Sh::kNBuf == 2)
-                    __builtin_amdgcn_sched_group_barrier(0x100, kPA + kPB, 0);   // LDS reads
+                __builtin_amdgcn_sched_group_barrier(0x100, kPA + kPB, 0);   // LDS reads
                 __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);           // global loads
 #pragma unroll
                 for (int i = 0; i < 3 * kNG; ++i) {
@@ -534,7 +528,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                     }
                 }
             };
-            auto buf_of = [&](int c) { return Sh::kNBuf == 2 ? stage + (c & 1) * kStage : stage; };
+            auto buf_of = [&](int c) { return stage + (c & 1) * kStage; };   // two staging buffers
             // this wave's 32 x 32 sub-tile in the moments' 64 x 64 tiling; a
             // sub-tile past the last 64-column tile has no pair in the space
             const int64_t v32 = vt * Sh::kWV + wv;
@@ -543,31 +537,20 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                                    (16 * kMom * 64);
             __syncthreads();                          // the previous tile's fragment reads are done
             if (tid == 0) lpend = 0;                  // every thread has read the previous total
-            // pr holds chunk ch + 1 and ring[] chunks ch + 2 .. ch + kAhead - 1
-            // while chunk ch + kAhead loads (loads past the last chunk re-read it)
-            constexpr int kAhead = Sh::kAhead, kRing = kAhead > 2 ? kAhead - 2 : 1;
-            Raw ring[kRing];
+            // pr holds chunk ch + 1 while chunk ch + 2 loads (loads past the last
+            // chunk re-read it); deeper load rings were slower
             load_chunk(0, pr);
             store_chunk(0, stage, nch == 1);
             load_chunk(1, pr);
-#pragma unroll
-            for (int a = 0; a + 2 < kAhead; ++a) load_chunk(2 + a, ring[a]);
             __syncthreads();
             int ch = 0;
             for (; ch + 2 < nch; ++ch) {              // chunk ch + 1 is full
                 Raw q;
-                load_chunk(ch + kAhead, q);
+                load_chunk(ch + 2, q);
                 mfma_chunk(buf_of(ch));
                 store_chunk(ch + 1, buf_of(ch + 1), false);
                 interleave();
-                if constexpr (kAhead > 2) {
-                    pr = ring[0];
-#pragma unroll
-                    for (int a = 0; a + 3 < kAhead; ++a) ring[a] = ring[a + 1];
-                    ring[kRing - 1] = q;
-                } else {
-                    pr = q;
-                }
+                pr = q;
                 __syncthreads();
             }
             if (ch + 1 < nch) {                       // chunk ch + 1 is the last one
@@ -1005,7 +988,7 @@ sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, c
     const int lcap = bf_lists_cap(space);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)Sh::kNBuf * Sh::kStage * sizeof(__bf16) + 2 * Sh::kBTU * sizeof(float4) +
+        const size_t smem = (size_t)2 * Sh::kStage * sizeof(__bf16) + 2 * Sh::kBTU * sizeof(float4) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16<MODE>, smem)) return SISSO_E_UNSUPPORTED;
         hipLaunchKernelGGL(k_score_rect_bf16<MODE>, dim3(p.grid), dim3(Sh::kThreads), smem, st, *space, fs, n,
