@@ -214,3 +214,25 @@ def test_bf16_fit_with_moments_equals_fit_without():
         assert list(x.best_ids) == list(y.best_ids) == list(z.best_ids)
         assert x.rmse == y.rmse
         assert abs(x.rmse - z.rmse) <= 1e-9 * z.rmse
+
+
+def test_bf16_moments_argument_errors():
+    """Moments need the whole binary block (a WRITE over part of it would leave
+    pairs unwritten that a later READ reads); unknown modes and policies are
+    rejected before any launch."""
+    from paper_2410_01752_amd import _lib as L
+    p = I.tiny(9, n=300, d=6, dist="lognormal", rect=True)
+    eng = _engine(p)
+    y64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+    bb = eng.binary_base()
+    with pytest.raises(L.SissoError):
+        eng.screen(y64, 100, None, begin=bb + 5, precision="bf16", band=400, moments="write")
+    with pytest.raises(L.SissoError):
+        eng.screen(y64, 100, None, precision="bf16", band=400, moments="sometimes")
+    with pytest.raises(L.SissoError):
+        eng.fit(5, 2, precision="bf16", moments="always")
+    # the plain form ignores moments="none"; a whole-block write then read works
+    a = eng.screen(y64, 100, None, precision="bf16", band=400, moments="write")
+    b = eng.screen(y64, 100, None, precision="bf16", band=400, moments="read")
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
