@@ -216,8 +216,8 @@ __global__ void __launch_bounds__(256) k_bf16_u_prep(int n, const float *__restr
             suu += (double)uu * uu;
             szz += (double)zz * zz;
         }
-        suu = wave_sum(suu);
-        szz = wave_sum(szz);
+        suu = wave_sum_dpp(suu);
+        szz = wave_sum_dpp(szz);
         if (lane == 0) ops.usum[c] = make_float4(mu, mz, (float)suu, (float)szz);
     }
 }
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(256) k_bf16_u_resid(int n, const float *__rest
             sur = fmaf(x - st.mean, r, sur);
             if (zok) szr = fmaf(__builtin_amdgcn_rcpf(x) - st.mean_rcp, r, szr);
         }
-        const double a = wave_sum((double)sur), b = wave_sum((double)szr);
+        const double a = wave_sum_dpp((double)sur), b = wave_sum_dpp((double)szr);
         if (lane == 0) ures[c] = make_float2((float)a, (float)b);
     }
 }
@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restr
             svr += (double)vv * r;
             swr += (double)ww * r;
         }
-        svv = wave_sum(svv); sww = wave_sum(sww); svr = wave_sum(svr); swr = wave_sum(swr);
+        svv = wave_sum_dpp(svv); sww = wave_sum_dpp(sww); svr = wave_sum_dpp(svr); swr = wave_sum_dpp(swr);
         if (lane == 0) {
             w.vsum[2 * c] = make_float4(mv, mw, (float)svv, (float)sww);
             w.vsum[2 * c + 1] = make_float4((float)svr, (float)swr, st.rms, 0.f);

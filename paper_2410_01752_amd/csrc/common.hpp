@@ -168,6 +168,81 @@ __device__ __forceinline__ int wave_or(int v)
     return v;
 }
 
+// Wave reductions through DPP lane moves (no LDS crossbar): quad
+// permutations, half-row and row mirrors, then the row broadcasts of lanes 15
+// and 31, after which lane 63 holds the result, read back as a wave-uniform
+// value.  All 64 lanes must be active; the order of the additions is fixed, so
+// the result is deterministic (it may differ from wave_sum in the last bits).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move(int v)
+{
+    // rows outside ROWS receive 0
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    int2 h;
+    __builtin_memcpy(&h, &v, 8);
+    h.x = dpp_move<CTRL, ROWS>(h.x);
+    h.y = dpp_move<CTRL, ROWS>(h.y);
+    double r;
+    __builtin_memcpy(&r, &h, 8);
+    return r;
+}
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_move<0xB1, 0xF>(v);     // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E, 0xF>(v);     // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141, 0xF>(v);    // row_half_mirror: sums of 8 lanes
+    v += dpp_move<0x140, 0xF>(v);    // row_mirror: sums of 16-lane rows
+    v += dpp_move<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    int2 h;
+    __builtin_memcpy(&h, &v, 8);
+    h.x = __builtin_amdgcn_readlane(h.x, 63);
+    h.y = __builtin_amdgcn_readlane(h.y, 63);
+    double r;
+    __builtin_memcpy(&r, &h, 8);
+    return r;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(dpp_move<CTRL, ROWS>(__float_as_int(v)));
+}
+// rows outside a broadcast's ROWS take 0, which never reaches lane 63
+__device__ __forceinline__ float wave_max_dpp(float v)
+{
+    v = fmaxf(v, dpp_move<0xB1, 0xF>(v));
+    v = fmaxf(v, dpp_move<0x4E, 0xF>(v));
+    v = fmaxf(v, dpp_move<0x141, 0xF>(v));
+    v = fmaxf(v, dpp_move<0x140, 0xF>(v));
+    v = fmaxf(v, dpp_move<0x142, 0xA>(v));
+    v = fmaxf(v, dpp_move<0x143, 0xC>(v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ float wave_min_dpp(float v)
+{
+    v = fminf(v, dpp_move<0xB1, 0xF>(v));
+    v = fminf(v, dpp_move<0x4E, 0xF>(v));
+    v = fminf(v, dpp_move<0x141, 0xF>(v));
+    v = fminf(v, dpp_move<0x140, 0xF>(v));
+    v = fminf(v, dpp_move<0x142, 0xA>(v));
+    v = fminf(v, dpp_move<0x143, 0xC>(v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ int wave_or_dpp(int v)
+{
+    v |= dpp_move<0xB1, 0xF>(v);
+    v |= dpp_move<0x4E, 0xF>(v);
+    v |= dpp_move<0x141, 0xF>(v);
+    v |= dpp_move<0x140, 0xF>(v);
+    v |= dpp_move<0x142, 0xA>(v);
+    v |= dpp_move<0x143, 0xC>(v);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Block-wide sum of one double per thread; result broadcast to all threads.
 // `red` must hold blockDim.x / 64 doubles of LDS.
 __device__ __forceinline__ double block_sum(double v, double *red)

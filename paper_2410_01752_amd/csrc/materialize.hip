@@ -128,8 +128,8 @@ __global__ void __launch_bounds__(256) k_pool_level(sisso_space s, const double 
                 double f;
                 pass1(t, f);
             }
-        const double mean = wave_sum(sum) / n;
-        const double ra = sqrt(wave_sum(sa2) / n), rb = sqrt(wave_sum(sb2) / n);
+        const double mean = wave_sum_dpp(sum) / n;
+        const double ra = sqrt(wave_sum_dpp(sa2) / n), rb = sqrt(wave_sum_dpp(sb2) / n);
         // pass 2: sum of squares, extremes, reciprocal mean, stores
         double ss = 0.0, srcp = 0.0, sf2 = 0.0;
         float mx = 0.0f, mn = INFINITY, mv = INFINITY;
@@ -157,10 +157,10 @@ __global__ void __launch_bounds__(256) k_pool_level(sisso_space s, const double 
                 pass2(t, value(t, ok, x, y));
             }
         for (int64_t t = n + lane; t < ld32; t += 64) out32[t] = 0.0f;
-        const double sst = wave_sum(ss);
-        const double mrcp = wave_sum(srcp) / n;
-        const double msq = wave_sum(sf2) / n;
-        mx = wave_max(mx); mn = wave_min(mn); mv = wave_min(mv); bad = wave_or(bad);
+        const double sst = wave_sum_dpp(ss);
+        const double mrcp = wave_sum_dpp(srcp) / n;
+        const double msq = wave_sum_dpp(sf2) / n;
+        mx = wave_max_dpp(mx); mn = wave_min_dpp(mn); mv = wave_min_dpp(mv); bad = wave_or_dpp(bad);
         if (lane == 0) {
             const double sd = sqrt(sst / n);
             bool valid = !bad && sd != 0.0 && sd > kConstRel * fabs(mean);

@@ -172,7 +172,7 @@ __device__ inline float score_stored_column(const float *col, const float *r32, 
                 c0 = fmaf(g, ra[e], c0);
             }
     }
-    const double A = wave_sum((double)a0), B = wave_sum((double)b0), C = wave_sum((double)c0);
+    const double A = wave_sum_dpp((double)a0), B = wave_sum_dpp((double)b0), C = wave_sum_dpp((double)c0);
     return valid ? score_from_sums(A, B, C, (double)mean, nd, R1, Srr) : -1.0f;
 }
 

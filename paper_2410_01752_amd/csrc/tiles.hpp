@@ -53,7 +53,7 @@ __device__ __forceinline__ void score_column(const float *__restrict__ col, cons
                         acc += fabsf(h) <= 1e15f ? h : 0.f;
                     }
             }
-            sh[o] = (float)(wave_sum((double)acc) / cnt);
+            sh[o] = (float)(wave_sum_dpp((double)acc) / cnt);
         }
     }
     for (int t = lane * 4; t < n; t += 256) {
@@ -78,13 +78,13 @@ __device__ __forceinline__ void score_column(const float *__restrict__ col, cons
             }
         }
     }
-    const double A = wave_sum((double)a0), B = wave_sum((double)b0s), C = wave_sum((double)c0);
+    const double A = wave_sum_dpp((double)a0), B = wave_sum_dpp((double)b0s), C = wave_sum_dpp((double)c0);
     if (st.valid != 0.0f) scs[0] = score_from_sums(A, B, C, (double)f0, nd, R1, Srr);
-    badu = wave_or(badu);
+    badu = wave_or_dpp(badu);
 #pragma unroll
     for (int o = 0; o < NU; ++o) {
         if (o < nu) {
-            const double Au = wave_sum((double)au[o]), Bu = wave_sum((double)bu[o]), Cu = wave_sum((double)cu[o]);
+            const double Au = wave_sum_dpp((double)au[o]), Bu = wave_sum_dpp((double)bu[o]), Cu = wave_sum_dpp((double)cu[o]);
             float bound;
             const bool dom = unary_domain_bound(uop[o], st, &bound);
             if (st.valid != 0.0f && dom && !((badu >> o) & 1))
@@ -114,7 +114,7 @@ __device__ __forceinline__ void unary_child_sums(const float4 (&fv)[KR], const f
                 const float h = unary32(OP, fa[e]);
                 acc += fabsf(h) <= 1e15f ? h : 0.f;
             }
-        shift = (float)(wave_sum((double)acc) / cnt);
+        shift = (float)(wave_sum_dpp((double)acc) / cnt);
     }
     au = bu = cu = 0.f;
     bad = false;
@@ -165,7 +165,7 @@ __device__ __forceinline__ void score_column_regs(const float4 (&fv)[KR], const 
                 }
         }
     }
-    const double A = wave_sum((double)a0), B = wave_sum((double)b0s), C = wave_sum((double)c0);
+    const double A = wave_sum_dpp((double)a0), B = wave_sum_dpp((double)b0s), C = wave_sum_dpp((double)c0);
     if (st.valid != 0.0f) scs[0] = score_from_sums(A, B, C, (double)f0, nd, R1, Srr);
     if (NU == 0 || !do_unary) return;
 #pragma unroll
@@ -184,8 +184,8 @@ __device__ __forceinline__ void score_column_regs(const float4 (&fv)[KR], const 
         case SISSO_SIN: unary_child_sums<SISSO_SIN, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
         default: unary_child_sums<-1, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
         }
-        const bool anybad = wave_or(bad ? 1 : 0) != 0;
-        const double Au = wave_sum((double)au), Bu = wave_sum((double)bu), Cu = wave_sum((double)cu);
+        const bool anybad = wave_or_dpp(bad ? 1 : 0) != 0;
+        const double Au = wave_sum_dpp((double)au), Bu = wave_sum_dpp((double)bu), Cu = wave_sum_dpp((double)cu);
         float bound;
         const bool dom = unary_domain_bound(uop[o], st, &bound);
         if (st.valid != 0.0f && dom && !anybad) scs[1 + o] = score_from_sums(Au, Bu, Cu, (double)sh, nd, R1, Srr);
