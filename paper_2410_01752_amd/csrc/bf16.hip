@@ -209,12 +209,17 @@ __global__ void __launch_bounds__(256) k_bf16_u_prep(int n, const float *__restr
         const float mu = st.mean, mz = st.mean_rcp;
         const bool zok = st.minabs > 0.0f;
         double suu = 0.0, szz = 0.0;
-        for (int t = lane; t < n; t += 64) {
-            const float x = col[t];
-            const float uu = x - mu;
-            const float zz = zok ? __builtin_amdgcn_rcpf(x) - mz : 0.f;
-            suu += (double)uu * uu;
-            szz += (double)zz * zz;
+        for (int t = lane * 4; t < n; t += 256) {     // 16-byte loads: samples t .. t + 3
+            const float4 x4 = *reinterpret_cast<const float4 *>(col + t);
+            const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < n) {
+                    const float uu = xs[e] - mu;
+                    const float zz = zok ? __builtin_amdgcn_rcpf(xs[e]) - mz : 0.f;
+                    suu += (double)uu * uu;
+                    szz += (double)zz * zz;
+                }
         }
         suu = wave_sum_dpp(suu);
         szz = wave_sum_dpp(szz);
@@ -236,10 +241,16 @@ __global__ void __launch_bounds__(256) k_bf16_u_resid(int n, const float *__rest
         const float *col = pool32 + (size_t)(col0 + c) * ld32;
         const bool zok = st.minabs > 0.0f;
         float sur = 0.f, szr = 0.f;
-        for (int t = lane; t < n; t += 64) {
-            const float x = col[t], r = r32[t];
-            sur = fmaf(x - st.mean, r, sur);
-            if (zok) szr = fmaf(__builtin_amdgcn_rcpf(x) - st.mean_rcp, r, szr);
+        for (int t = lane * 4; t < n; t += 256) {     // 16-byte loads: samples t .. t + 3
+            const float4 x4 = *reinterpret_cast<const float4 *>(col + t);
+            const float4 r4 = *reinterpret_cast<const float4 *>(r32 + t);
+            const float xs[4] = {x4.x, x4.y, x4.z, x4.w}, rs[4] = {r4.x, r4.y, r4.z, r4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < n) {
+                    sur = fmaf(xs[e] - st.mean, rs[e], sur);
+                    if (zok) szr = fmaf(__builtin_amdgcn_rcpf(xs[e]) - st.mean_rcp, rs[e], szr);
+                }
         }
         const double a = wave_sum_dpp((double)sur), b = wave_sum_dpp((double)szr);
         if (lane == 0) ures[c] = make_float2((float)a, (float)b);
