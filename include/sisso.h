@@ -269,9 +269,10 @@ size_t sisso_bf16_workspace_size(const sisso_space *space, const sisso_score_arg
 int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_score_args *args,
                                       int32_t band);
 /* The three steps of sisso_expand_score_bf16, for callers that time or
- * overlap them: the residual-dependent operands (v side and the u side's
- * residual sums), the MFMA screen into the band lists of `bws`, and the band
- * top-k plus exact FP32 rescore into `ws`. */
+ * overlap them: the residual-dependent operands (v-side column sums, the u
+ * side's residual sums and the v-side staging image that the READ form of
+ * sisso_bf16_screen_moments copies), the MFMA screen into the band lists of
+ * `bws`, and the band top-k plus exact FP32 rescore into `ws`. */
 sisso_status sisso_bf16_residual(const sisso_space *space, const sisso_score_args *args, int32_t band,
                                  void *bws, size_t bws_bytes, void *stream);
 sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_score_args *args, const void *ops,
