@@ -227,7 +227,7 @@ def parse():
                     help="screening form of the rung-3 slice; auto = the fastest form whose recall against "
                          "the FP32 form is >= 0.99 and whose whole fit matches an FP32 fit, both measured here")
     ap.add_argument("--band", type=int, default=0,
-                    help="BF16 form: candidates rescored in FP32 (0: 4 x K', at most 8192)")
+                    help="BF16 form: candidates rescored in FP32 (0: 4 x K', at most 7168)")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 vs FP32 recall check")
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -293,7 +293,7 @@ def main():
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
     log(f"workload {args.workload} n={n} d={p.X.shape[1]} k={p.k} D={p.dmax}")
     keep0 = args.keep0 or (2048 if p.rect else 2 * p.k)
-    band = args.band or min(4 * keep0, 8192)
+    band = args.band or min(4 * keep0, 7168)
 
     if args.copy_calibration:
         # an elementwise kernel that reads 1 GiB and writes 1 GiB (a copy through

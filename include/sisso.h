@@ -87,7 +87,7 @@ typedef enum {
 #define SISSO_MAX_LEVELS 2
 #define SISSO_MAX_N 65536          /* samples per problem                    */
 #define SISSO_MAX_KEEP 2048        /* screened-list length per call          */
-#define SISSO_MAX_BAND 8192        /* BF16 candidates rescored exactly       */
+#define SISSO_MAX_BAND 7168        /* BF16 candidates rescored exactly       */
 #define SISSO_MAX_SUBSPACE 1024    /* |S_t|                                  */
 #define SISSO_MAX_D 3              /* terms per SO model                     */
 #define SISSO_MAX_BATCH 4096       /* problems per batched call              */
@@ -323,7 +323,10 @@ sisso_status sisso_bf16_screen_moments(const sisso_space *space, const sisso_sco
 /* Merge the workspace's per-block lists into the global best k (score desc,
  * id asc) (Sec. 2.2, eq. sis-method).  out_ids / out_scores: k entries;
  * out_count: number written (< k when fewer valid features exist).
- * Deterministic: identical for any grid or tile choice.
+ * Deterministic: identical for any grid or tile choice.  The entries above the
+ * k-th score and those tied with it are gathered in a buffer of 8192; the BF16
+ * band (k <= SISSO_MAX_BAND = 8192 - 1024) thus leaves room for 1024 ties at
+ * its cutoff.
  * Errors: SISSO_E_NULL, SISSO_E_RANGE (k < 1 or k larger than the keep the
  * workspace was filled with). */
 sisso_status sisso_topk(const void *ws, size_t ws_bytes, int32_t k, int64_t *out_ids,

@@ -20,7 +20,7 @@ OPNAME = {v: k for k, v in OPCODE.items()}
 
 MAX_UNARY, MAX_BINARY, MAX_LEVELS = 8, 4, 2
 MAX_N, MAX_KEEP, MAX_SUBSPACE, MAX_D = 65536, 2048, 1024, 3
-MAX_BAND = 8192
+MAX_BAND = 7168
 MOMENTS_NONE, MOMENTS_WRITE, MOMENTS_READ = 0, 1, 2
 MAX_BATCH = 4096
 ENC, MLP_IN, MLP_HIDDEN = 64, 144, 256

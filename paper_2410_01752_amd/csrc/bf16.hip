@@ -733,10 +733,17 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             __syncthreads();
             const int total = lpend;                  // reset after the next barrier
             if (total == 0) continue;
-            if (*Lst.cnt + total > Lst.cap) {
-                list_merge(Lst, gb);          // block-uniform: ends with a barrier
+            // Every thread takes the same branch only if every thread reads the
+            // list's count before any thread reserves slots: read it, merge if
+            // the tile's candidates do not fit (block-uniform, ends with a
+            // barrier), read it again, and meet at a barrier before reserving.
+            int cnt0 = *Lst.cnt;
+            if (cnt0 + total > Lst.cap) {
+                list_merge(Lst, gb);
+                cnt0 = *Lst.cnt;
             }
-            if (*Lst.cnt + total <= Lst.cap) {
+            __syncthreads();
+            if (cnt0 + total <= Lst.cap) {
                 if (mine) {
                     int slot = atomicAdd(Lst.cnt, mine);
 #pragma unroll

@@ -270,10 +270,17 @@ __global__ void __launch_bounds__(256) k_tk_gather(void *ws)
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x) {
         const float sc = W.sc[e];
         if (!considered(sc, g)) continue;
+        // Entries above the k-th score (fewer than k of them) fill the gather
+        // buffer from the front, entries equal to it from the back: only ties
+        // at the cutoff can exceed the buffer, and only tied entries are lost
+        // then (reported as status 1).
         const unsigned u = __float_as_uint(sc);
-        if (all || u >= sstar) {
+        if (all || u > sstar) {
             const int slot = atomicAdd(&W.h->n_gt, 1);
             if (slot < kFinalCap) { W.fin_sc[slot] = sc; W.fin_id[slot] = W.id[e]; }
+        } else if (u == sstar) {
+            const int slot = kFinalCap - 1 - atomicAdd(&W.h->n_eq, 1);
+            if (slot >= 0) { W.fin_sc[slot] = sc; W.fin_id[slot] = W.id[e]; }
         }
     }
 }
@@ -290,25 +297,29 @@ __global__ void __launch_bounds__(1024) k_tk_final(void *ws, int k, int allow_ab
         if (threadIdx.x == 0) { *out_count = 0; W.h->status = 2; }
         return;
     }
-    const int m = W.h->n_gt;
-    const int cap = next_pow2(m < kFinalCap ? (m > 1 ? m : 2) : kFinalCap);
+    // front: the entries above the cutoff; back: the ties at it (as many as fit)
+    const int m_gt = W.h->n_gt < kFinalCap ? W.h->n_gt : kFinalCap;
+    const int room = kFinalCap - m_gt;
+    const int m_eq = W.h->n_eq < room ? W.h->n_eq : room;
+    const int m = m_gt + m_eq;
+    const int cap = next_pow2(m > 1 ? m : 2);
     float *sc = (float *)smem;
     int64_t *id = (int64_t *)(smem + kFinalCap * sizeof(float));
     for (int i = threadIdx.x; i < cap; i += blockDim.x) {
-        sc[i] = i < m && i < kFinalCap ? W.fin_sc[i] : -1.0f;
-        id[i] = i < m && i < kFinalCap ? W.fin_id[i] : INT64_MAX;
+        const int src = i < m_gt ? i : kFinalCap - 1 - (i - m_gt);
+        sc[i] = i < m ? W.fin_sc[src] : -1.0f;
+        id[i] = i < m ? W.fin_id[src] : INT64_MAX;
     }
     __syncthreads();
     bitonic_sort_keys(sc, id, cap);
-    int valid = m < kFinalCap ? m : kFinalCap;
-    const int take = valid < k ? valid : k;
+    const int take = m < k ? m : k;
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
         out_ids[i] = i < take ? id[i] : INT64_MAX;
         out_sc[i] = i < take ? sc[i] : -1.0f;
     }
     if (threadIdx.x == 0) {
         *out_count = take;
-        if (m > kFinalCap) W.h->status = 1;
+        if (W.h->n_gt + W.h->n_eq > kFinalCap) W.h->status = 1;
     }
 }
 

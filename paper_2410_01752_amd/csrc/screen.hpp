@@ -31,6 +31,7 @@ inline FormSlots form_slots(const sisso_space *space)
 
 constexpr int kHistBins = 4096;
 constexpr int kFinalCap = 8192;
+static_assert(SISSO_MAX_BAND + 1024 <= kFinalCap, "a BF16 band leaves room for 1024 ties at its cutoff");
 
 struct WsHeader {
     unsigned gthr;          // grid-wide admission bound (float bits)

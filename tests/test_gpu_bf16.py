@@ -84,7 +84,7 @@ def test_bf16_recall_c3_slice():
     _check(out, 400)
 
 
-@pytest.mark.parametrize("keep,band", [(2048, 8192), (700, 3000)])
+@pytest.mark.parametrize("keep,band", [(2048, 7168), (700, 3000)])
 def test_bf16_band_wider_than_block_lists(keep, band):
     """A band above SISSO_MAX_KEEP: each block keeps its best 2048 by BF16
     score, publishes no grid-wide bound, and the grid-wide merge takes the
@@ -157,19 +157,23 @@ def _band_of(eng, band):
     return ids[order], sc[order]
 
 
-@pytest.mark.parametrize("case", ["ragged_n300", "persistent_grid", "c3_shape_n2000"])
+@pytest.mark.parametrize("case", ["ragged_n300", "persistent_grid", "c3_shape_n2000", "c3_full_block"])
 def test_bf16_moments_read_equals_plain_screen(case):
     """A screen that reads the stored residual-independent moments gives the
     same BF16 band (ids and BF16 scores, bit for bit) and the same rescored
     list as a plain screen of the same residual; so does the screen that
     writes them.  Cases: n = 300 (a ragged last chunk of samples, ragged u and v
-    tiles), a grid of 3 blocks sweeping every u tile, and n = 2000 with d = 12."""
+    tiles), a grid of 3 blocks sweeping every u tile, n = 2000 with d = 12, and the
+    whole C3 binary block at the bench's keep, band and tuned grid (41,434 u tiles;
+    the read form sizes its own grid)."""
     if case == "ragged_n300":
         p, keep, band, grid = I.tiny(9, n=300, d=6, dist="lognormal", rect=True), 300, 1200, 0
     elif case == "persistent_grid":
         p, keep, band, grid = I.tiny(4, n=77, d=5, dist="lognormal", rect=True), 200, 800, 3
-    else:
+    elif case == "c3_shape_n2000":
         p, keep, band, grid = I.tiny(21, n=2000, d=12, dist="lognormal", rect=True), 1000, 4000, 0
+    else:       # the bench's workload: 1.37e10 candidates, 69 GB of moments, the bench's band
+        p, keep, band, grid = I.config3(), 2048, 7168, 256
     print(f"[bf16 moments] {case}", flush=True)
     eng = _engine(p)
     assert eng.bf16_moments_buffer() is not None
