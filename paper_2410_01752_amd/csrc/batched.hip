@@ -26,6 +26,8 @@ namespace sisso {
 constexpr int kBatchTU = 32, kBatchTV = 32;          // pair tile (RectCfg<2, 2>)
 constexpr int kBatchCols = kColWaves * kColBatch;    // stored columns per item
 constexpr int kBatchFinalCap = 4096;                 // merge buffer per problem
+static_assert(kBatchFinalCap % 1024 == 0 && SISSO_MAX_KEEP < kBatchFinalCap,
+              "the per-problem merge moves kBatchFinalCap / 1024 entries per thread, and the entries above the cutoff (fewer than keep) must fit");
 constexpr int kMaxBatch = SISSO_MAX_BATCH;
 
 struct BatchHeader {
@@ -251,7 +253,7 @@ __global__ void __launch_bounds__(1024) k_topk_batch(const sisso_problem *__rest
 {
     __shared__ unsigned hist[kHistBins];
     __shared__ unsigned s_prefix;
-    __shared__ int s_need, s_total, s_m;
+    __shared__ int s_need, s_total, s_gt, s_eq;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     float *fsc = (float *)smem;
     int64_t *fid = (int64_t *)(smem + kBatchFinalCap * sizeof(float));
@@ -285,7 +287,7 @@ __global__ void __launch_bounds__(1024) k_topk_batch(const sisso_problem *__rest
     auto entry = [&](int64_t e) -> size_t { return (size_t)(first + e / keep) * keep_max + (size_t)(e % keep); };
     auto considered = [&](float sc) { return sc >= 0.0f && __float_as_uint(sc) >= g; };
 
-    if (threadIdx.x == 0) { s_prefix = 0u; s_need = keep; s_total = 0; s_m = 0; }
+    if (threadIdx.x == 0) { s_prefix = 0u; s_need = keep; s_total = 0; s_gt = 0; s_eq = 0; }
     bool all = false;
     for (int pass = 0; pass < 3; ++pass) {
         for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) hist[i] = 0u;
@@ -320,31 +322,58 @@ __global__ void __launch_bounds__(1024) k_topk_batch(const sisso_problem *__rest
         __syncthreads();
     }
     const unsigned sstar = s_prefix;
+    // Entries above the keep-th score (fewer than keep of them) fill the
+    // buffer from the front, entries equal to it from the back: only ties at
+    // the cutoff can exceed the buffer, and only tied entries are lost then.
     for (int64_t e = threadIdx.x; e < M; e += blockDim.x) {
         const size_t x = entry(e);
         const float sc = W.sc[x];
         if (!considered(sc)) continue;
-        if (all || __float_as_uint(sc) >= sstar) {
-            const int slot = atomicAdd(&s_m, 1);
+        const unsigned u = __float_as_uint(sc);
+        if (all || u > sstar) {
+            const int slot = atomicAdd(&s_gt, 1);
             if (slot < kBatchFinalCap) { fsc[slot] = sc; fid[slot] = W.id[x]; }
+        } else if (u == sstar) {
+            const int slot = kBatchFinalCap - 1 - atomicAdd(&s_eq, 1);
+            if (slot >= 0) { fsc[slot] = sc; fid[slot] = W.id[x]; }
         }
     }
     __syncthreads();
-    const int m = s_m;
-    const int cap = next_pow2(m < kBatchFinalCap ? (m > 1 ? m : 2) : kBatchFinalCap);
+    const int n_gt = s_gt, n_eq = s_eq;
+    const int m_gt = n_gt < kBatchFinalCap ? n_gt : kBatchFinalCap;
+    const int room = kBatchFinalCap - m_gt;
+    const int m_eq = n_eq < room ? n_eq : room;
+    const int m = m_gt + m_eq;
+    // Move the ties behind the front entries.  The two ranges may overlap, so
+    // every thread reads its entries before any thread writes (1024 threads x
+    // kTiePer entries cover the buffer).
+    constexpr int kTiePer = kBatchFinalCap / 1024;
+    float tsc[kTiePer];
+    int64_t tid[kTiePer];
+#pragma unroll
+    for (int j = 0; j < kTiePer; ++j) {
+        const int i = threadIdx.x + 1024 * j;
+        if (i < m_eq) { tsc[j] = fsc[kBatchFinalCap - 1 - i]; tid[j] = fid[kBatchFinalCap - 1 - i]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kTiePer; ++j) {
+        const int i = threadIdx.x + 1024 * j;
+        if (i < m_eq) { fsc[m_gt + i] = tsc[j]; fid[m_gt + i] = tid[j]; }
+    }
+    const int cap = next_pow2(m > 1 ? m : 2);
     for (int i = threadIdx.x; i < cap; i += blockDim.x)
         if (i >= m) { fsc[i] = -1.0f; fid[i] = INT64_MAX; }
     __syncthreads();
     bitonic_sort_keys(fsc, fid, cap);
-    const int valid = m < kBatchFinalCap ? m : kBatchFinalCap;
-    const int take = valid < keep ? valid : keep;
+    const int take = m < keep ? m : keep;
     for (int i = threadIdx.x; i < keep_max; i += blockDim.x) {
         oi[i] = i < take ? fid[i] : INT64_MAX;
         os[i] = i < take ? fsc[i] : -1.0f;
     }
     if (threadIdx.x == 0) {
         out_count[p] = take;
-        if (out_status) out_status[p] = m > kBatchFinalCap ? (int)SISSO_E_RANGE : 0;
+        if (out_status) out_status[p] = n_gt + n_eq > kBatchFinalCap ? (int)SISSO_E_RANGE : 0;
     }
 }
 
