@@ -148,7 +148,7 @@ def learned_c5(params, args, log):
         out[f"learned_{frac:g}"] = {"ms": ms, "recall": LN.recall_of(fi, fs, gi), "speedup_vs_fp32": fms / ms,
                                     "tail_check": list(e.learned_log[-1])}
         log(f"C5 learned {frac:g}: {ms:.0f} ms, recall {out[f'learned_{frac:g}']['recall']:.4f}")
-    bi, bs, bms = run("bf16", band=4 * keep)
+    bi, bs, bms = run("bf16", band=min(4 * keep, 7168))
     out["bf16"] = {"ms": bms, "recall": LN.recall_of(fi, fs, bi), "speedup_vs_fp32": fms / bms}
     log(f"C5 bf16 {bms:.0f} ms, recall {out['bf16']['recall']:.4f}")
     del e
