@@ -28,7 +28,7 @@ with one persistent screening launch per step; its time and rates are
 reported under "batched".
 
 Prints one JSON line (see the fields below).  `--gpus N` with N > 1 exits:
-this build measures one GPU.
+the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -281,7 +281,7 @@ def recall_of(fi, fs, bi, tol=1e-6):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU; run with --gpus 1"}))
         sys.exit(2)
     import torch
     from paper_2410_01752_amd import inputs as I

@@ -70,7 +70,7 @@ typedef enum {
     SISSO_E_SHAPE = 2,       /* n, ld, m, d or another size is out of range       */
     SISSO_E_RANGE = 3,       /* an id, a range or k is outside the space         */
     SISSO_E_WORKSPACE = 4,   /* the workspace is smaller than its size query     */
-    SISSO_E_UNSUPPORTED = 5, /* a valid request this build does not implement    */
+    SISSO_E_UNSUPPORTED = 5, /* a valid request the library does not implement */
     SISSO_E_DEVICE = 6,      /* the HIP runtime reported an error                */
     SISSO_E_NUMERIC = 7      /* e.g. a constant residual (nothing to screen)     */
 } sisso_status;

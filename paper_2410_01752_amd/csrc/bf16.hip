@@ -25,11 +25,11 @@
 // FP32 kernel's arithmetic (shared functions), so reported scores are the FP32
 // path's scores.
 //
-// The file is compiled twice.  The second build (bf16_mfma.hip, which defines
-// SISSO_BF16_MFMA_PART) holds only the launches of the plain and write forms and
-// is compiled with the scheduler that maximises instruction-level parallelism:
-// measured 3% faster for those two forms and 2% slower for the read form, which
-// this build keeps.
+// The file is compiled twice.  The second translation unit (bf16_mfma.hip,
+// which defines SISSO_BF16_MFMA_PART) holds only the launches of the plain and
+// write forms and is compiled with the scheduler that maximises
+// instruction-level parallelism: measured 3% faster for those two forms and 2%
+// slower for the read form, which stays in this one.
 #include "tiles.hpp"
 
 #include <type_traits>
