@@ -141,3 +141,19 @@ def test_target_is_fisher_z():
     assert M.target(np.array([0.0]))[0] == 0.0
     assert math.isclose(M.target(np.array([0.5]))[0], 0.5 * math.log(3.0), rel_tol=1e-15)
     assert np.isfinite(M.target(np.array([1.0]))[0])
+
+
+def test_operand_stats_log10_mean_and_sd_hand_values():
+    """Entries 51 and 52 of an operand encoding: clip(log10|mean|, -6, 6)/6
+    and clip(log10 sd, -6, 6)/6.  x = (990, 1010): mean 1000, population sd
+    10, so the entries are 3/6 and 1/6; scaling by 1e8 clips the mean's
+    entry at 1 (sd 1e9 clips too); scaling by 1e-8 gives log10 = -5 and -7."""
+    r = np.array([0.3, -0.3])
+    st = M.operand_stats(np.array([990.0, 1010.0]), r)
+    assert math.isclose(st[9], 0.5, rel_tol=1e-15) and math.isclose(st[10], 1.0 / 6.0, rel_tol=1e-14)
+    big = M.operand_stats(np.array([990.0, 1010.0]) * 1e8, r)
+    assert big[9] == 1.0 and big[10] == 1.0
+    small = M.operand_stats(np.array([990.0, 1010.0]) * 1e-8, r)
+    assert math.isclose(small[9], -5.0 / 6.0, rel_tol=1e-14) and small[10] == -1.0
+    neg = M.operand_stats(-np.array([990.0, 1010.0]), r)
+    assert math.isclose(neg[9], 0.5, rel_tol=1e-15)

@@ -346,3 +346,95 @@ def test_cancelling_sum_or_difference_is_invalid():
     assert np.max(np.abs(V[:, 0] - X[:, 1])) < 1e-14
     feats = B.enumerate_space(X, ["sq", "sqrt"], ["sub", "add"], 2, True)
     assert feats[root][2] and not feats[bad][2] and feats[good][2]
+
+
+# ------------------------------------------------ the FULL unary operator set
+
+# Hand-computed values of the eight unary operators of eq. feature-exp
+# (Sec. 2.1; the operator list of Sec. 3.3) at x = 1, 2, 1/2, 4.  The
+# constants are the known decimal expansions of e, e^2, sqrt(2), ln 2, sin 1,
+# ... to 16-17 significant digits, typed here, not computed by a library.
+_X_HAND = [1.0, 2.0, 0.5, 4.0]
+_HAND = {
+    "sq": [1.0, 4.0, 0.25, 16.0],
+    "cube": [1.0, 8.0, 0.125, 64.0],
+    "sqrt": [1.0, 1.4142135623730951, 0.7071067811865476, 2.0],
+    "inv": [1.0, 0.5, 2.0, 0.25],
+    "exp": [2.718281828459045, 7.38905609893065, 1.6487212707001282, 54.598150033144236],
+    "nexp": [0.36787944117144233, 0.1353352832366127, 0.6065306597126334, 0.01831563888873418],
+    "log": [0.0, 0.6931471805599453, -0.6931471805599453, 1.3862943611198906],
+    "sin": [0.8414709848078965, 0.9092974268256817, 0.479425538604203, -0.7568024953079282],
+}
+
+
+@pytest.mark.parametrize("op", I.FULL["unary"])
+def test_unary_operator_values_hand_computed(op):
+    """Each unary operator of the FULL set, evaluated by the oracle, equals
+    its hand-computed value (exp(-x) is NEXP: nexp(1) = 1/e)."""
+    X = np.array(_X_HAND)[:, None]
+    sp = O.Space(1, I.FULL["unary"], [], 1)
+    fid = 1 + I.FULL["unary"].index(op)              # level 1: op(x0) in list order
+    assert sp.decode(fid) == (O.OPCODE[op], 0, -1)
+    V, ok = sp.eval(X, [fid])
+    assert ok[0]
+    want = np.array(_HAND[op])
+    assert np.allclose(V[:, 0], want, rtol=2e-16, atol=1e-300), (op, V[:, 0], want)
+    # and the independent NumPy brute force agrees with the same constants
+    feats = B.enumerate_space(X, I.FULL["unary"], [], 1)
+    assert np.allclose(feats[fid][1], want, rtol=2e-16, atol=1e-300)
+
+
+def test_binary_operator_values_hand_computed():
+    """x0 = (3, 1.5), x1 = (2, 0.5): level 1 holds, per binary slot, x1 op x0
+    (ADD, SUB, MUL, then DIV both orders)."""
+    X = np.array([[3.0, 2.0], [1.5, 0.5], [2.0, 5.0]])
+    sp = O.Space(2, [], I.FULL["binary"], 1)
+    V, ok = sp.eval(X, range(2, 7))
+    assert ok.all()
+    want = [[5.0, 2.0, 7.0], [-1.0, -1.0, 3.0], [6.0, 0.75, 10.0], [2.0 / 3.0, 1.0 / 3.0, 2.5],
+            [1.5, 3.0, 0.4]]
+    for c in range(5):
+        assert np.allclose(V[:, c], want[c], rtol=2e-16), (c, V[:, c])
+
+
+@pytest.mark.parametrize("lo,hi", [(0.2, 3.0), (-2.0, 40.0)])
+def test_values_match_brute_force_full_operators(lo, hi):
+    """Every feature of a FULL-operator level-2 space (d = 3, 4,644 features)
+    and of a rung-3 slice with all eight unary operators (d = 2, 55,000
+    features): identical validity flags and values to 1e-13.  The second range
+    puts negative values under sqrt and log and overflows exp beyond the 1e15
+    cap, so every domain rule is exercised."""
+    rng = np.random.default_rng(17)
+    X = rng.uniform(lo, hi, size=(9, 3))
+    for d, binary, rect in ((3, I.FULL["binary"], False), (2, ["sub", "div"], True)):
+        Xd = X[:, :d]
+        feats = B.enumerate_space(Xd, I.FULL["unary"], binary, 2, rect)
+        sp = O.Space(d, I.FULL["unary"], binary, 2, rect)
+        assert len(feats) == sp.total
+        V, ok = sp.eval(Xd, np.arange(sp.total))
+        okb = np.array([f[2] for f in feats])
+        assert np.array_equal(ok, okb)
+        assert 0 < ok.sum() < sp.total
+        Vb = np.column_stack([f[1] for f in feats])
+        assert np.allclose(V[:, ok], Vb[:, ok], rtol=1e-13, atol=0)
+        # every unary operator appears among the valid features
+        ops_seen = {sp.decode(int(f))[0] for f in np.flatnonzero(ok)}
+        assert {O.OPCODE[u] for u in I.FULL["unary"]} <= ops_seen
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_r2_is_squared_correlation_of_the_fit(seed):
+    """R^2 of the reported model (Sec. 2.3) equals corr(y, y_hat)^2 of the
+    NumPy least-squares fit with an intercept on the selected features, and
+    1 - SSE/S_yy of that fit."""
+    p = I.tiny(seed, n=14, d=3, k=5, dmax=3)
+    ro = O.fit(p.X, p.y, p.unary, p.binary, 2, False, p.k, p.dmax)
+    sp = O.Space(3, p.unary, p.binary, 2)
+    for st in ro:
+        F, _ = sp.eval(p.X, st.best_ids)
+        A = np.column_stack([np.ones(len(p.y)), F])
+        c, *_ = np.linalg.lstsq(A, p.y, rcond=None)
+        yh = A @ c
+        rho = np.corrcoef(p.y, yh)[0, 1]
+        assert math.isclose(st.r2, rho * rho, rel_tol=1e-10)
+        assert math.isclose(st.rmse, math.sqrt(np.mean((p.y - yh) ** 2)), rel_tol=1e-9)
