@@ -321,7 +321,11 @@ sisso_status sisso_bf16_screen_moments(const sisso_space *space, const sisso_sco
                                        void *stream);
 
 /* Merge the workspace's per-block lists into the global best k (score desc,
- * id asc) (Sec. 2.2, eq. sis-method).  out_ids / out_scores: k entries;
+ * id asc) (Sec. 2.2, eq. sis-method).  The merge takes no exclusion list:
+ * the ids of S_{t-1} are excluded when candidates enter the per-block lists
+ * (sisso_score_args.exclude), so that an excluded feature never occupies a
+ * list slot that a screened candidate needs; filtering them at the merge
+ * would need lists longer by |S_{t-1}|.  out_ids / out_scores: k entries;
  * out_count: number written (< k when fewer valid features exist).
  * Deterministic: identical for any grid or tile choice.  The entries above the
  * k-th score and those tied with it are gathered in a buffer of 8192; the BF16
@@ -331,6 +335,17 @@ sisso_status sisso_bf16_screen_moments(const sisso_space *space, const sisso_sco
  * workspace was filled with). */
 sisso_status sisso_topk(const void *ws, size_t ws_bytes, int32_t k, int64_t *out_ids,
                         float *out_scores, int32_t *out_count, void *stream);
+
+/* Outcome of the last sisso_topk on a workspace, copied on `stream` into
+ * *out_status (device int32): 0 = exact result; 1 = more entries tie at the
+ * k-th score than the gather buffer holds behind the entries above it (every
+ * entry above the cutoff is still returned, and every returned score is
+ * correct, but the tied entries returned need not be those of smallest id);
+ * 2 = k was larger than the keep the workspace was filled with (nothing
+ * returned).  A caller that needs the (score desc, id asc) order exactly
+ * checks it once the stream has passed the call.
+ * Errors: SISSO_E_NULL, SISSO_E_WORKSPACE. */
+sisso_status sisso_topk_status(const void *ws, size_t ws_bytes, int32_t *out_status, void *stream);
 
 /* ---------------------------------------------------------------- batches
  * Many independent problems over one space: cross-validation folds and
@@ -450,6 +465,12 @@ sisso_status sisso_mlp_backward(const float *params, const float *X, const float
                                 const float *t, const float *w, int32_t batch, float *grads, float *loss, void *ws,
                                 size_t ws_bytes, void *stream);
 
+/* Training target of the network for count screening scores (|corr| in
+ * [0, 1]): out[i] = atanh(min(|scores[i]|, 1 - 1e-6)), the Fisher z-transform,
+ * which spreads the top of the score range the proposal has to rank.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE (count < 1). */
+sisso_status sisso_mlp_target(const float *scores, int32_t count, float *out, void *stream);
+
 /* Adam update of count parameters with bias-corrected moments m, v (step >= 1
  * is the update's number).  Errors: SISSO_E_NULL, SISSO_E_SHAPE. */
 sisso_status sisso_adam_step(float *params, const float *grads, float *m, float *v, int64_t count, int32_t step,
@@ -506,7 +527,10 @@ sisso_status sisso_expand_score_pruned(const sisso_space *space, const sisso_sco
  * |corr| of its members; the best k classes (score desc, id asc) are
  * appended to the subspace (ids to sub_ids[m_prev..], columns to sub).
  * *n_new (device int32) receives the number appended (<= k) and *n_classes
- * the number of surviving classes.
+ * the number of surviving classes.  If more than 2^20 pairs of the list and
+ * subspace are duplicates, the classes cannot be formed: nothing is appended,
+ * *n_new = 0 and *n_classes = -1 (the caller checks this once the stream has
+ * passed the call).
  * Errors: SISSO_E_NULL, SISSO_E_SHAPE (m_prev + k > SISSO_MAX_SUBSPACE,
  * count > SISSO_MAX_KEEP). */
 size_t sisso_subspace_workspace_size(int32_t n, int32_t count, int32_t m_prev);
@@ -516,6 +540,12 @@ sisso_status sisso_subspace_update(const double *cand, int32_t ldc, const int64_
                                    int32_t lds, int64_t *sub_ids, int32_t m_prev, int32_t k,
                                    int32_t *n_new, int32_t *n_classes, void *ws, size_t ws_bytes,
                                    void *stream);
+
+/* Outcome of a finished SO search from its stats record [host]: `stats` is
+ * a host copy of the 4 doubles out_stats received.  SISSO_OK when a model was
+ * found; SISSO_E_NUMERIC when every tuple was singular (no model exists: the
+ * call wrote tuple -1, SSE +inf and the residual y); SISSO_E_NULL. */
+sisso_status sisso_l0_outcome(const double *stats);
 
 /* SO: exhaustive l0 search (Sec. 2.3, eq. residual read with an inverse;
  * all C(m, D) models, best by residual norm).  F: n x m FP64 columns (ld)
@@ -530,7 +560,9 @@ sisso_status sisso_subspace_update(const double *cand, int32_t ldc, const int64_
  * out_stats 4 doubles (rmse, r2, tuples evaluated, tuples skipped).
  * Errors: SISSO_E_NULL, SISSO_E_SHAPE (D outside 1..SISSO_MAX_D, m < D,
  * m > SISSO_MAX_SUBSPACE), SISSO_E_WORKSPACE.  If every tuple is singular
- * the stats record tuples skipped == tuples evaluated and out_sse = +inf. */
+ * the stats record tuples skipped == tuples evaluated and out_sse = +inf;
+ * the search runs asynchronously, so this outcome is read from the stats
+ * record by sisso_l0_outcome (SISSO_E_NUMERIC). */
 size_t sisso_l0_workspace_size(int32_t m, int32_t n, int32_t D);
 sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, const double *y,
                              int32_t D, double singular_tol, int32_t *out_tuple, double *out_sse,

@@ -143,10 +143,12 @@ def lib():
         "sisso_expand_score": (_i32, [sp, ap, _i64, _i64, _vp, _sz, _vp]),
         "sisso_expand_score_lists": (_i32, [sp, ap, _i64, _i64]),
         "sisso_topk": (_i32, [_vp, _sz, _i32, _vp, _vp, _vp, _vp]),
+        "sisso_topk_status": (_i32, [_vp, _sz, _vp, _vp]),
         "sisso_subspace_workspace_size": (_sz, [_i32, _i32, _i32]),
         "sisso_subspace_update": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp,
                                          _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
         "sisso_l0_workspace_size": (_sz, [_i32, _i32, _i32]),
+        "sisso_l0_outcome": (_i32, [_vp]),
         "sisso_l0_search": (_i32, [_vp, _i32, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
                                    _vp, _vp, _vp, _sz, _vp]),
         "sisso_sort_subspace": (_i32, [_vp, _i32, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
@@ -168,6 +170,7 @@ def lib():
         "sisso_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp]),
         "sisso_mlp_workspace_size": (_sz, [_i32]),
         "sisso_mlp_backward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp]),
+        "sisso_mlp_target": (_i32, [_vp, _i32, _vp, _vp]),
         "sisso_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, ctypes.c_float, _vp]),
         "sisso_mlp_parts": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
@@ -190,8 +193,9 @@ def lib():
 
 EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "sisso_materialize_ids",
             "sisso_prepare_residual", "sisso_score_workspace_size", "sisso_score_reset",
-            "sisso_expand_score", "sisso_expand_score_lists", "sisso_topk", "sisso_subspace_workspace_size",
-            "sisso_subspace_update", "sisso_l0_workspace_size", "sisso_l0_search",
+            "sisso_expand_score", "sisso_expand_score_lists", "sisso_topk", "sisso_topk_status",
+            "sisso_subspace_workspace_size",
+            "sisso_subspace_update", "sisso_l0_workspace_size", "sisso_l0_search", "sisso_l0_outcome",
             "sisso_sort_subspace", "sisso_bf16_operands_size", "sisso_prepare_bf16",
             "sisso_bf16_workspace_size", "sisso_expand_score_bf16_lists", "sisso_expand_score_bf16",
             "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore", "sisso_bf16_moments_size",
@@ -201,7 +205,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_materialize_ids_batched", "sisso_subspace_update_batched", "sisso_sort_subspace_batched",
             "sisso_mlp_param_count", "sisso_mlp_table_count", "sisso_encode_operands", "sisso_candidate_inputs",
             "sisso_score_ids", "sisso_mlp_forward", "sisso_mlp_workspace_size", "sisso_mlp_backward",
-            "sisso_adam_step", "sisso_mlp_parts", "sisso_mlp_tables", "sisso_mlp_score_ids", "sisso_select_kth",
+            "sisso_mlp_target", "sisso_adam_step", "sisso_mlp_parts", "sisso_mlp_tables", "sisso_mlp_score_ids", "sisso_select_kth",
             "sisso_expand_score_pruned_lists", "sisso_expand_score_pruned", "sisso_count_pass",
             "sisso_status_string", "sisso_version"]
 

@@ -192,6 +192,8 @@ class Batch:
                 if np.any(uv != 0):
                     raise L.SissoError(f"batched materialise / subspace update: entry status {uv.tolist()}")
                 nxt = []
+                if np.any(v[:, 1] < 0):
+                    raise L.SissoError("batched subspace update: more duplicate pairs than the edge list holds")
                 for j, p in enumerate(todo):
                     nn, nc, ct = int(v[j, 0]), int(v[j, 1]), int(cv[j])
                     upd[p] = (nn, nc, ct)
@@ -299,7 +301,8 @@ class Batch:
             lsc = scs[o_c:o_c + ct]
             o_c += ct
             tp = v[:t].astype(np.int64)
-            sse, coef, stt = v[t], v[t + 1:2 * t + 2], v[2 * t + 2:2 * t + 6]
+            sse, coef, stt = v[t], v[t + 1:2 * t + 2], np.ascontiguousarray(v[2 * t + 2:2 * t + 6])
+            L.check(L.lib().sisso_l0_outcome(stt.ctypes.data), f"sisso_l0_search_batched (problem {p})")
             best = srt[tp] if (tp >= 0).all() else np.full(t, -1)
             out.append(StepResult(t, lid, lsc, sub, best, coef, float(sse), float(stt[0]), float(stt[1]),
                                   int(stt[2]), int(stt[3]), keep[p], upd[p][1]))

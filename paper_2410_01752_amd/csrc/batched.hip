@@ -322,9 +322,11 @@ __global__ void __launch_bounds__(1024) k_topk_batch(const sisso_problem *__rest
         __syncthreads();
     }
     const unsigned sstar = s_prefix;
-    // Entries above the keep-th score (fewer than keep of them) fill the
-    // buffer from the front, entries equal to it from the back: only ties at
-    // the cutoff can exceed the buffer, and only tied entries are lost then.
+    // Entries above the keep-th score (keep - need < keep of them) fill the
+    // buffer from the front, entries equal to it from the back down to the
+    // front's end: only ties at the cutoff can exceed the buffer, and only
+    // tied entries are lost then.
+    const int front = all ? kBatchFinalCap : keep - s_need;
     for (int64_t e = threadIdx.x; e < M; e += blockDim.x) {
         const size_t x = entry(e);
         const float sc = W.sc[x];
@@ -335,7 +337,7 @@ __global__ void __launch_bounds__(1024) k_topk_batch(const sisso_problem *__rest
             if (slot < kBatchFinalCap) { fsc[slot] = sc; fid[slot] = W.id[x]; }
         } else if (u == sstar) {
             const int slot = kBatchFinalCap - 1 - atomicAdd(&s_eq, 1);
-            if (slot >= 0) { fsc[slot] = sc; fid[slot] = W.id[x]; }
+            if (slot >= front) { fsc[slot] = sc; fid[slot] = W.id[x]; }
         }
     }
     __syncthreads();

@@ -392,6 +392,13 @@ using namespace sisso;
 
 static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+extern "C" sisso_status sisso_l0_outcome(const double *stats)
+{
+    if (!stats) return SISSO_E_NULL;
+    // tuples evaluated == tuples skipped: no admissible model
+    return stats[2] >= 1.0 && stats[3] >= stats[2] ? SISSO_E_NUMERIC : SISSO_OK;
+}
+
 extern "C" size_t sisso_l0_workspace_size(int32_t m, int32_t n, int32_t D)
 {
     if (m < 1 || n < 2 || D < 1) return 0;

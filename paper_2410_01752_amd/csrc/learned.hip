@@ -983,6 +983,27 @@ extern "C" sisso_status sisso_mlp_backward(const float *params, const float *X, 
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 
+namespace sisso {
+// Regression target of the proposal network: the Fisher z-transform of a
+// |correlation|, atanh(min(|c|, 1 - 1e-6)) (finite at |c| = 1), in FP64.
+__global__ void __launch_bounds__(256) k_mlp_target(const float *__restrict__ sc, int count, float *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const double c = fmin(fabs((double)sc[i]), 0.999999);
+    out[i] = (float)atanh(c);
+}
+}  // namespace sisso
+
+extern "C" sisso_status sisso_mlp_target(const float *scores, int32_t count, float *out, void *stream)
+{
+    if (!scores || !out) return SISSO_E_NULL;
+    if (count < 1) return SISSO_E_SHAPE;
+    hipLaunchKernelGGL(k_mlp_target, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, as_stream(stream), scores,
+                       count, out);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
 extern "C" sisso_status sisso_adam_step(float *params, const float *grads, float *m, float *v, int64_t count,
                                         int32_t step, float lr, float beta1, float beta2, float eps, void *stream)
 {

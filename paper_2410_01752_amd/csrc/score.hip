@@ -260,27 +260,30 @@ __global__ void k_tk_select(WsHeader *h, int pass)
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) h->hist[i] = 0u;
 }
 
-__global__ void __launch_bounds__(256) k_tk_gather(void *ws)
+__global__ void __launch_bounds__(256) k_tk_gather(void *ws, int k)
 {
     WsView W = ws_view_dev(ws);
     const int keep = W.h->keep;
     const unsigned g = W.h->gthr, sstar = W.h->prefix;
     const bool all = W.h->need < 0;
+    // after the select passes exactly k - need entries lie above the cutoff:
+    // the front of the buffer holds them, ties may use the slots behind them
+    const int front = all ? kFinalCap : k - W.h->need;
     const int64_t M = (int64_t)W.h->n_lists * keep;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x) {
         const float sc = W.sc[e];
         if (!considered(sc, g)) continue;
-        // Entries above the k-th score (fewer than k of them) fill the gather
-        // buffer from the front, entries equal to it from the back: only ties
-        // at the cutoff can exceed the buffer, and only tied entries are lost
-        // then (reported as status 1).
+        // Entries above the k-th score (k - need < k of them) fill the gather
+        // buffer from the front, entries equal to it from the back down to the
+        // front's end: only ties at the cutoff can exceed the buffer, and only
+        // tied entries are lost then (reported as status 1).
         const unsigned u = __float_as_uint(sc);
         if (all || u > sstar) {
             const int slot = atomicAdd(&W.h->n_gt, 1);
             if (slot < kFinalCap) { W.fin_sc[slot] = sc; W.fin_id[slot] = W.id[e]; }
         } else if (u == sstar) {
             const int slot = kFinalCap - 1 - atomicAdd(&W.h->n_eq, 1);
-            if (slot >= 0) { W.fin_sc[slot] = sc; W.fin_id[slot] = W.id[e]; }
+            if (slot >= front) { W.fin_sc[slot] = sc; W.fin_id[slot] = W.id[e]; }
         }
     }
 }
@@ -537,7 +540,7 @@ sisso_status topk_launch(void *ws, int k, int64_t *out_ids, float *out_scores, i
         hipLaunchKernelGGL(k_tk_hist, dim3(512), dim3(256), 0, st, ws, pass);
         hipLaunchKernelGGL(k_tk_select, dim3(1), dim3(256), 0, st, h, pass);
     }
-    hipLaunchKernelGGL(k_tk_gather, dim3(512), dim3(256), 0, st, ws);
+    hipLaunchKernelGGL(k_tk_gather, dim3(512), dim3(256), 0, st, ws, k);
     const size_t smem = (size_t)kFinalCap * (sizeof(float) + sizeof(int64_t));
     if (!allow_dynamic_lds(k_tk_final, smem)) return SISSO_E_UNSUPPORTED;
     hipLaunchKernelGGL(k_tk_final, dim3(1), dim3(1024), smem, st, ws, k, allow_above_keep ? 1 : 0, out_ids,
@@ -554,4 +557,19 @@ extern "C" sisso_status sisso_topk(const void *ws_c, size_t ws_bytes, int32_t k,
     if (k < 1 || k > SISSO_MAX_KEEP) return SISSO_E_RANGE;
     if (ws_bytes < ws_bytes_for(0, 1)) return SISSO_E_WORKSPACE;
     return topk_launch(ws, k, out_ids, out_scores, out_count, as_stream(stream), false);
+}
+
+namespace sisso {
+__global__ void k_tk_status(const WsHeader *h, int32_t *out)
+{
+    if (threadIdx.x == 0) *out = h->status;
+}
+}  // namespace sisso
+
+extern "C" sisso_status sisso_topk_status(const void *ws, size_t ws_bytes, int32_t *out_status, void *stream)
+{
+    if (!ws || !out_status) return SISSO_E_NULL;
+    if (ws_bytes < ws_bytes_for(0, 1)) return SISSO_E_WORKSPACE;
+    hipLaunchKernelGGL(k_tk_status, dim3(1), dim3(64), 0, as_stream(stream), (const WsHeader *)ws, out_status);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }

@@ -130,7 +130,13 @@ __device__ inline void sub_classes(int m_prev, int nodes, const int64_t *__restr
     double *ksc = (double *)(best + nodes);                     // class list (pow2)
     int64_t *kid = (int64_t *)(ksc + next_pow2(nodes));
     __shared__ int changed, ncls;
-    const int ne = min(*w.n_edges, kEdgeCap);
+    if (*w.n_edges > kEdgeCap) {
+        // more duplicate pairs than the edge list holds: the classes cannot be
+        // formed exactly, so the update fails (nothing appended, n_classes -1)
+        if (threadIdx.x == 0) { *n_new = 0; *n_classes = -1; }
+        return;
+    }
+    const int ne = *w.n_edges;
     for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
         label[i] = i;
         rep[i] = ~0ull;

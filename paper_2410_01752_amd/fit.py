@@ -73,6 +73,7 @@ class Engine:
             "sisso_materialize_pools")
         self.bf16_ops: Optional[torch.Tensor] = None
         self.bf16_moments: Optional[torch.Tensor] = None
+        self.tk_status = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.r32 = torch.zeros(self.ld32, dtype=torch.float32, device=self.dev)
         self.info = torch.zeros(L.RESID_DOUBLES, dtype=torch.float64, device=self.dev)
         self._ws: Dict[str, torch.Tensor] = {}
@@ -275,6 +276,7 @@ class Engine:
             ev0.record()
         L.check(L.lib().sisso_topk(L.ptr(ws), ws.numel(), k, L.ptr(ids), L.ptr(sc), L.ptr(cnt), st),
                 "sisso_topk")
+        L.check(L.lib().sisso_topk_status(L.ptr(ws), ws.numel(), L.ptr(self.tk_status), st), "sisso_topk_status")
         if events is not None:
             ev1.record()
             events.setdefault("topk", []).append((ev0, ev1))
@@ -334,7 +336,7 @@ class Engine:
                 mom_state = "read"
                 cand, valid = self.materialize(ids)
                 fs.update(cand, ids, valid, cnt, keep, r, k, self._workspace)
-                nn, nc, ct = fs.read_update(cnt)
+                nn, nc, ct = fs.read_update(cnt, self.tk_status)
                 if nn >= k or ct < keep or keep >= L.MAX_KEEP:
                     break
                 keep = min(2 * keep, L.MAX_KEEP)
@@ -382,8 +384,15 @@ class FitState:
             L.ptr(self.sub), n, L.ptr(self.sub_ids), self.m, k, L.ptr(self.n_new), L.ptr(self.n_cls),
             L.ptr(ws), ws.numel(), st), "sisso_subspace_update")
 
-    def read_update(self, cnt):
-        v = torch.cat([self.n_new, self.n_cls, cnt]).cpu().numpy()
+    def read_update(self, cnt, tk_status=None):
+        """(appended, classes, screened count) of the last update; raises if
+        the top-k merge or the duplicate classes could not be formed exactly."""
+        parts = [self.n_new, self.n_cls, cnt] + ([tk_status] if tk_status is not None else [])
+        v = torch.cat(parts).cpu().numpy()
+        if tk_status is not None and int(v[3]) != 0:
+            raise L.SissoError(f"sisso_topk: status {int(v[3])} (more ties at the cutoff than the gather holds)")
+        if int(v[1]) < 0:
+            raise L.SissoError("sisso_subspace_update: more duplicate pairs than the edge list holds")
         return int(v[0]), int(v[1]), int(v[2])
 
     def commit(self, nn: int, t: int) -> bool:
@@ -433,7 +442,8 @@ class FitState:
         m = self.m
         tp = self.tup[:t].cpu().numpy()
         srt = self.ids_sorted[:m].cpu().numpy()
-        stt = self.stats.cpu().numpy()
+        stt = np.ascontiguousarray(self.stats.cpu().numpy())
+        L.check(L.lib().sisso_l0_outcome(stt.ctypes.data), "sisso_l0_search")
         best = srt[tp] if (tp >= 0).all() else np.full(t, -1)
         return StepResult(t, ids[:ct].cpu().numpy(), sc[:ct].cpu().numpy(), self.sub_ids[:m].cpu().numpy(),
                           best, self.coef[:t + 1].cpu().numpy(), float(self.sse.item()), float(stt[0]),

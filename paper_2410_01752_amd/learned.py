@@ -96,8 +96,10 @@ def dataset(eng, r64: torch.Tensor, ids: np.ndarray, scores: np.ndarray):
     """Device tensors X (inputs), t = atanh(|corr|) and unit weights."""
     enc = encode(eng, r64)
     X = inputs(eng, enc, torch.from_numpy(np.ascontiguousarray(ids)).to(eng.dev))
-    t = np.arctanh(np.minimum(scores.astype(np.float64), 0.999999)).astype(np.float32)
-    return X, torch.from_numpy(t).to(eng.dev), torch.ones(len(ids), dtype=torch.float32, device=eng.dev)
+    sc = torch.from_numpy(np.ascontiguousarray(scores, dtype=np.float32)).to(eng.dev)
+    t = torch.empty_like(sc)
+    L.check(L.lib().sisso_mlp_target(L.ptr(sc), sc.numel(), L.ptr(t), L.stream_handle(eng.dev)), "sisso_mlp_target")
+    return X, t, torch.ones(len(ids), dtype=torch.float32, device=eng.dev)
 
 
 # ------------------------------------------------------------------ training

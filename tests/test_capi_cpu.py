@@ -109,6 +109,21 @@ def test_argument_errors_before_launch():
     assert lib.sisso_sort_subspace(fake, 50, fake, 0, 50, fake, 50, fake, fake, None) == 2
     for st in range(8):
         assert lib.sisso_status_string(st)
+    assert lib.sisso_topk_status(None, ws, fake, None) == 1
+    assert lib.sisso_topk_status(fake, ws, None, None) == 1
+    assert lib.sisso_topk_status(fake, 8, fake, None) == 4
+
+
+def test_l0_outcome_reports_all_singular_searches():
+    """sisso_l0_outcome reads a finished search's stats record (RMSE, R^2,
+    tuples evaluated, tuples skipped): SISSO_E_NUMERIC (7) when every tuple
+    was singular, SISSO_OK otherwise."""
+    lib = L.lib()
+    ok = np.array([0.1, 0.9, 79800.0, 12.0])
+    none = np.array([np.nan, np.nan, 79800.0, 79800.0])
+    assert lib.sisso_l0_outcome(ok.ctypes.data) == 0
+    assert lib.sisso_l0_outcome(none.ctypes.data) == 7
+    assert lib.sisso_l0_outcome(None) == 1
 
 
 def test_bf16_moments_size_and_argument_errors_before_launch():

@@ -64,3 +64,39 @@ def test_fit_at_small_n_matches_oracle(n):
     res = eng.fit(p.k, p.dmax)
     ref = O.fit(p.X, p.y, p.unary, p.binary, p.rung, p.rect, p.k, p.dmax)
     _compare_fit(p, res, ref)
+
+
+def test_topk_tie_overflow_keeps_every_entry_above_the_cutoff():
+    """More entries tie exactly at the k-th score than the top-k gather buffer
+    (8192) holds behind the entries above it.  x0 carries the target; x1..x130
+    are copies of one column z, so z's copies and every x_j + x_i = 2z (i, j
+    >= 1) tie exactly (8,515 features), and the x_j + x0 tie at a higher
+    score.  The merge must return every entry above the cutoff (x0 and the 130
+    sums with x0), fill the rest with tied entries, and report the overflow."""
+    from paper_2410_01752_amd import _lib as L
+    rng = np.random.default_rng(31)
+    n, d = 64, 131
+    x0 = rng.lognormal(0.0, 0.5, n)
+    z = rng.lognormal(0.0, 0.5, n)
+    X = np.column_stack([x0] + [z] * (d - 1))
+    y = x0 + 0.2 * z + rng.normal(0.0, 0.05, n)
+    p = I.Problem("ties", X, y, [], ["add"], 1, False, 10, 1, [], [], 0)
+    print("[edges] tie overflow at the top-k cutoff", flush=True)
+    eng = _engine(p)
+    sp = O.Space(d, [], ["add"], 1, False)
+    keep = 2048
+    oi, os_ = sp.sis(X, y, keep)
+    n_above = int(np.sum(os_ > os_[-1]))
+    assert n_above == 131 and np.sum(os_ == os_[-1]) == keep - n_above
+    gi, gs = _screen(eng, y, keep)
+    assert len(gi) == keep
+    assert set(gi[:n_above].tolist()) == set(oi[:n_above].tolist())
+    assert np.all(gs[n_above:] == gs[n_above])
+    assert gs[n_above - 1] > gs[n_above]
+    ties = set(np.flatnonzero(np.isclose(sp.score_range(X, y, 0, sp.total), os_[-1], rtol=0, atol=1e-15)).tolist())
+    assert len(ties) == 8515 and set(gi[n_above:].tolist()) <= ties
+    torch.cuda.synchronize()
+    assert int(eng.tk_status.item()) == 1
+    # the fit driver refuses a merge whose tie order is not exact
+    with pytest.raises(L.SissoError):
+        eng.fit(10, 1, keep0=keep)

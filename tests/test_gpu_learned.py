@@ -315,3 +315,16 @@ def test_learned_falls_back_when_the_proposal_misses_the_top():
     c = int(fc.item())
     assert int(gc.item()) == c
     assert torch.equal(gi[:c], fi[:c]) and torch.equal(gs[:c], fs[:c])
+
+
+def test_training_target_kernel_matches_reference():
+    """sisso_mlp_target against the FP64 reference's Fisher z-transform."""
+    L = _lib()
+    sc = np.array([0.0, 1e-7, 0.1, 0.5, 0.9, 0.99, 0.999999, 1.0], dtype=np.float32)
+    sc = np.concatenate([sc, np.random.default_rng(4).uniform(0, 1, 1000).astype(np.float32)])
+    s = _dev(sc)
+    out = torch.empty_like(s)
+    L.check(L.lib().sisso_mlp_target(L.ptr(s), s.numel(), L.ptr(out), L.stream_handle(s.device)), "target")
+    torch.cuda.synchronize()
+    ref = M.target(sc.astype(np.float64))
+    assert np.allclose(out.cpu().numpy(), ref, rtol=2e-7, atol=1e-7)
