@@ -569,6 +569,24 @@ sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, 
                              double *out_coef, double *out_resid, double *out_stats, void *ws,
                              size_t ws_bytes, void *stream);
 
+/* sisso_l0_search for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same search with its workspace in a fixed device array of
+ * the library (sisso_l0_scratch_capacity() bytes, 32 MiB, held on every
+ * device the library runs on until the process ends) instead of a `ws`
+ * argument.  Arguments and outputs as sisso_l0_search.  The call allocates
+ * nothing.  Every call on one device shares that device's array: calls that
+ * overlap on one device (concurrent streams, threads) race and must be
+ * serialised by the caller; each call re-initialises what it reads.
+ * Errors: as sisso_l0_search; SISSO_E_WORKSPACE when the search needs more
+ * than the array holds (sisso_l0_workspace_size(m, n, D) > capacity: e.g.
+ * m = 1024 columns hold n <= 3000 samples, m = 600 hold n <= 5000);
+ * SISSO_E_DEVICE if the array's device address cannot be obtained. */
+size_t sisso_l0_scratch_capacity(void);
+sisso_status sisso_l0_search_noalloc(const double *F, int32_t m, int32_t ld, int32_t n, const double *y,
+                                     int32_t D, double singular_tol, int32_t *out_tuple, double *out_sse,
+                                     double *out_coef, double *out_resid, double *out_stats, void *stream);
+
 /* ------------------------------------------------- batched subspace steps
  * The per-problem steps between screening and SO for a table of problems in
  * a fixed number of launches (the records are DEVICE arrays; every field has

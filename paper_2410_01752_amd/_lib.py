@@ -149,6 +149,9 @@ def lib():
                                          _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
         "sisso_l0_workspace_size": (_sz, [_i32, _i32, _i32]),
         "sisso_l0_outcome": (_i32, [_vp]),
+        "sisso_l0_scratch_capacity": (_sz, []),
+        "sisso_l0_search_noalloc": (_i32, [_vp, _i32, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
+                                           _vp, _vp, _vp]),
         "sisso_l0_search": (_i32, [_vp, _i32, _i32, _i32, _vp, _i32, ctypes.c_double, _vp, _vp, _vp,
                                    _vp, _vp, _vp, _sz, _vp]),
         "sisso_sort_subspace": (_i32, [_vp, _i32, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
@@ -196,6 +199,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_expand_score", "sisso_expand_score_lists", "sisso_topk", "sisso_topk_status",
             "sisso_subspace_workspace_size",
             "sisso_subspace_update", "sisso_l0_workspace_size", "sisso_l0_search", "sisso_l0_outcome",
+            "sisso_l0_scratch_capacity", "sisso_l0_search_noalloc",
             "sisso_sort_subspace", "sisso_bf16_operands_size", "sisso_prepare_bf16",
             "sisso_bf16_workspace_size", "sisso_expand_score_bf16_lists", "sisso_expand_score_bf16",
             "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore", "sisso_bf16_moments_size",

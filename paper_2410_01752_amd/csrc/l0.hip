@@ -16,6 +16,8 @@
 // SSE is within 1e-12 S_yy of it (columns arrive in ascending id order).
 #include "linalg.hpp"
 
+#include <mutex>
+
 namespace sisso {
 
 struct L0Ws {
@@ -436,6 +438,57 @@ extern "C" sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, 
     hipLaunchKernelGGL(k_l0_finish, dim3(1), dim3(256), 0, st, F, ld, n, m, D, y, n_choose(m, D), w, out_tuple,
                        out_sse, out_coef, out_resid, out_stats);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+// ------------------------------------------------- allocation-free search
+//
+// sisso_l0_search with its workspace in a file-scope device array instead of
+// a caller-provided buffer.  The array's host-side name is not a device
+// address: its address on each device is taken once with hipGetSymbolAddress
+// (with that device current) and only that pointer is passed to kernels.
+
+namespace {
+constexpr size_t kL0ScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kL0ScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device), or nullptr if the runtime reports an error.
+void *scratch_on_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" size_t sisso_l0_scratch_capacity(void) { return kL0ScratchBytes; }
+
+extern "C" sisso_status sisso_l0_search_noalloc(const double *F, int32_t m, int32_t ld, int32_t n, const double *y,
+                                                int32_t D, double singular_tol, int32_t *out_tuple, double *out_sse,
+                                                double *out_coef, double *out_resid, double *out_stats,
+                                                void *stream)
+{
+    if (!F || !y || !out_tuple || !out_sse || !out_coef || !out_resid || !out_stats) return SISSO_E_NULL;
+    if (D < 1 || D > SISSO_MAX_D || m < D || m > SISSO_MAX_SUBSPACE || n < 2 || n > SISSO_MAX_N || ld < n)
+        return SISSO_E_SHAPE;
+    if (l0_ws_bytes(m, n) > kL0ScratchBytes) return SISSO_E_WORKSPACE;
+    void *ws = scratch_on_current_device();
+    if (!ws) return SISSO_E_DEVICE;
+    return sisso_l0_search(F, m, ld, n, y, D, singular_tol, out_tuple, out_sse, out_coef, out_resid, out_stats, ws,
+                           kL0ScratchBytes, stream);
 }
 
 extern "C" sisso_status sisso_l0_search_batched(const sisso_l0_problem *problems, int32_t n_problems, int32_t D,

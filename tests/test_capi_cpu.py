@@ -126,6 +126,19 @@ def test_l0_outcome_reports_all_singular_searches():
     assert lib.sisso_l0_outcome(None) == 1
 
 
+def test_noalloc_l0_argument_errors_before_launch():
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    cap = lib.sisso_l0_scratch_capacity()
+    assert cap >= lib.sisso_l0_workspace_size(600, 2000, 3)
+    assert lib.sisso_l0_search_noalloc(None, 10, 10, 10, fake, 2, 1e-10, fake, fake, fake, fake, fake, None) == 1
+    assert lib.sisso_l0_search_noalloc(fake, 2, 10, 10, fake, 3, 1e-10, fake, fake, fake, fake, fake, None) == 2
+    assert lib.sisso_l0_search_noalloc(fake, 10, 10, 10, fake, 4, 1e-10, fake, fake, fake, fake, fake, None) == 2
+    assert lib.sisso_l0_workspace_size(1024, 4096, 3) > cap
+    assert lib.sisso_l0_search_noalloc(fake, 1024, 4096, 4096, fake, 3, 1e-10, fake, fake, fake, fake, fake,
+                                       None) == 4
+
+
 def test_bf16_moments_size_and_argument_errors_before_launch():
     """The moments buffer holds 6 floats per pair of the padded 64 x 64 tiles of
     the slice's binary block; a bad mode, a missing or short buffer and the
