@@ -1,4 +1,4 @@
-// bf16.hip -- BF16 MFMA screening of the one-sided rung-3 slice, followed by
+// bf16.hip -- 16-bit MFMA screening of the one-sided rung-3 slice, followed by
 // an exact FP32 rescore of a band of candidates around the cutoff (Sec. 2.2,
 // eq. sis-weight: the correlation of every candidate with the residual).
 //
@@ -13,23 +13,29 @@
 // and likewise u/v (with W~) and v/u (with Z~ against V~); u + v and u - v
 // need only G[U~, V~].  Twelve GEMMs over a tile of (u, v) pairs, with the
 // per-column terms folded into the v-side operands, give all five forms.
-// They run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Every operand
-// variant enters as two BF16 parts, x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
-// formed from the FP32 pool values while a sample chunk is staged into LDS
-// (nothing BF16 is stored in HBM), and each product is hi*hi + hi*lo + lo*hi:
-// BF16 alone (8-bit mantissa) cannot resolve forms whose centred terms cancel
-// (ratios of strongly related operands, e.g. (x0 x1 x2)/(x0 x1)), the split
-// form keeps about 16 bits.  Sums of single columns are exact (FP64).  The BF16
-// scores only select a band (a margin wider than the list, since BF16 noise
-// reorders near-ties); every candidate of the band is rescored with the plain
-// FP32 kernel's arithmetic (shared functions), so reported scores are the FP32
-// path's scores.
+//
+// The operands are IEEE half precision (11-bit significand): every variant
+// column is scaled by a power of two near the inverse of its root-mean-square
+// (exact, undone on the FP32 accumulators), rounded to FP16 while a sample
+// chunk is staged into LDS (nothing 16-bit is stored in HBM), and each GEMM is
+// one v_mfma_f32_32x32x16_f16 per 16 samples with FP32 accumulation.  A single
+// 16-bit product cannot resolve a variance whose expansion terms cancel (a
+// ratio of strongly related operands, a sum or difference of nearly opposite
+// operands): such a candidate is recognised per pair and form by a
+// conditioning test -- its approximate variance is below kCondRel of the sum
+// of the magnitudes of the terms it was formed from, where the rounding error
+// of those terms is no longer negligible -- and is scored exactly instead
+// (about 3 in 10^4 candidates at n = 2000, d = 20).  Every other candidate
+// keeps its approximate score.  The approximate scores and the exact scores of
+// the flagged candidates select a band (a margin wider than the list, since
+// 16-bit noise reorders near-ties); every candidate of the band is rescored
+// with the plain FP32 kernel's arithmetic (shared functions), so reported
+// scores are the FP32 path's scores.
 //
 // The file is compiled twice.  The second translation unit (bf16_mfma.hip,
 // which defines SISSO_BF16_MFMA_PART) holds only the launches of the plain and
 // write forms and is compiled with the scheduler that maximises
-// instruction-level parallelism: measured 3% faster for those two forms and 2%
-// slower for the read form, which stays in this one.
+// instruction-level parallelism.
 #include "tiles.hpp"
 
 #include <type_traits>
@@ -37,16 +43,21 @@
 
 namespace sisso {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef _Float16 h16;
+typedef h16 h16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef h16 h16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kSplit = 2;     // BF16 parts per operand (hi, lo)
 constexpr int kBT = 64;       // u operands per block tile (the tiling of the slice's u range)
+// A form's approximate variance is trusted when it is at least kCondRel of the
+// sum of the magnitudes of its expansion terms (each carries a relative
+// rounding error of about 2^-12 from the FP16 operands); below it the
+// candidate is scored exactly.
+constexpr float kCondRel = 1e-2f;
 constexpr int kKC = 16;       // samples per LDS stage (one MFMA k-step)
-constexpr int kKR = kKC;      // bf16 per LDS row: one chunk of samples of one column
+constexpr int kKR = kKC;      // 16-bit values per LDS row: one chunk of samples of one column
 constexpr int kMom = 6;       // residual-independent moments kept per (u, v) pair
 constexpr size_t kMomTile = (size_t)4 * 16 * kMom * 64;   // floats per (u tile, v tile)
 
@@ -75,9 +86,9 @@ template <int MODE> struct BfShape {
     static constexpr int kWV = kBTV / 32, kThreads = 64 * 2 * kWV;     // waves: 2 along u, kWV along v
     static constexpr int kSU = kBTU * kKC / kThreads;                  // u samples staged per thread
     static constexpr int kSV = kBTV * kKC / kThreads;                  // v samples staged per thread
-    static constexpr int kPlaneU = kBTU * kKR, kPlaneV = kBTV * kKR;   // bf16 per staged plane
-    static constexpr int kPA = kUVar * kSplit, kPB = kVVar * kSplit;   // staged planes per side
-    static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;       // bf16 per staging buffer
+    static constexpr int kPlaneU = kBTU * kKR, kPlaneV = kBTV * kKR;   // 16-bit values per staged plane
+    static constexpr int kPA = kUVar, kPB = kVVar;                     // staged planes per side
+    static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;       // 16-bit values per staging buffer
     static constexpr int kMinBlocks = 1;            // resident blocks per CU the registers are sized for
     // accumulator of the residual contraction of u v, u/v and v/u
     static constexpr int kCovUV = kRead ? 0 : 1, kCovUW = kRead ? 1 : 5, kCovZV = kRead ? 2 : 9;
@@ -109,33 +120,62 @@ __host__ __device__ inline BfOps bf_ops_view(void *p)
     return o;
 }
 
-// per-pass BF16 workspace: v-side column sums, u-side residual sums, band
-// lists (a screening workspace of its own) and the band ids.
+// Candidates the conditioning test flags, kept for exact scoring: a counter
+// (which may exceed the capacity: the excess was not stored) and their ids.
+// The capacity is proportional to the binary block (one in 1024 candidates).
+struct BfSide {
+    unsigned long long *cnt;
+    int64_t *ids;
+    int64_t cap;
+};
+__host__ __device__ inline int64_t bf_side_cap(const sisso_space &s)
+{
+    const int64_t c = s.rect_binary / 1024;
+    return c < ((int64_t)1 << 16) ? ((int64_t)1 << 16) : (c > ((int64_t)1 << 26) ? ((int64_t)1 << 26) : c);
+}
+__host__ __device__ inline size_t bf_side_bytes(const sisso_space &s) { return 256 + (size_t)bf_side_cap(s) * 8; }
+__host__ __device__ inline BfSide bf_side_view(void *p, const sisso_space &s)
+{
+    BfSide d;
+    d.cnt = (unsigned long long *)p;
+    d.ids = (int64_t *)((char *)p + 256);
+    d.cap = bf_side_cap(s);
+    return d;
+}
+
+// per-pass workspace of the 16-bit screen: v-side column sums, u-side residual
+// sums, band lists (a screening workspace of its own, whose lists are those of
+// the screen followed by the exact scores of the flagged candidates), the
+// band ids, the read form's v-side image and the flagged candidates of a
+// screen that stores no moments.
 struct BfWs {
     float4 *vsum;     // 2 per column: (mean v, mean 1/v, sum v~^2, sum w~^2), (sum v~ r, sum w~ r, rms, 0)
     float2 *ures;     // per u column: sum u~ r, sum z~ r
     int64_t *band_ids;
     float *band_sc;
     int32_t *band_cnt;
-    void *lists;      // screening workspace of the BF16 lists
-    __bf16 *vimg;     // the read form's v-side staging image (see k_bf16_v_image)
+    void *lists;      // screening workspace of the band lists
+    h16 *vimg;        // the read form's v-side staging image (see k_bf16_v_image)
+    void *side;       // BfSide storage of a screen without moments
 };
-// bf16 of the read form's v-side image: per 128-column v tile and chunk of
-// samples, the staged planes of V~ r and W~ r (hi and lo) in their LDS layout
+// the read form's v-side image: per 128-column v tile and chunk of samples,
+// the staged planes of V~ r and W~ r in their LDS layout
 __host__ __device__ inline size_t bf_vimg_elems(int64_t vcols, int n)
 {
-    return (size_t)((vcols + 127) / 128) * (size_t)((n + kKC - 1) / kKC) * (2 * kSplit) * (128 * kKR);
+    return (size_t)((vcols + 127) / 128) * (size_t)((n + kKC - 1) / kKC) * 2 * (128 * kKR);
 }
-__host__ __device__ inline size_t bf_ws_bytes(int64_t ucols, int64_t vcols, int n, int band, int lists, int keep)
+__host__ __device__ inline size_t bf_ws_bytes(const sisso_space &s, int64_t ucols, int64_t vcols, int n, int band,
+                                              int lists, int keep)
 {
     size_t b = align256b((size_t)vcols * 2 * sizeof(float4));
     b += align256b((size_t)ucols * sizeof(float2));
     b += align256b((size_t)band * sizeof(int64_t)) + align256b((size_t)band * sizeof(float)) + 256;
     b += align256b(ws_bytes_for(lists, keep));
-    b += align256b(bf_vimg_elems(vcols, n) * sizeof(__bf16));
+    b += align256b(bf_vimg_elems(vcols, n) * sizeof(h16));
+    b += align256b(bf_side_bytes(s));
     return b;
 }
-__host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols, int band, int lists, int keep)
+__host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols, int n, int band, int lists, int keep)
 {
     BfWs w;
     char *c = (char *)p;
@@ -145,11 +185,70 @@ __host__ __device__ inline BfWs bf_ws_view(void *p, int64_t ucols, int64_t vcols
     w.band_sc = (float *)c; c += align256b((size_t)band * sizeof(float));
     w.band_cnt = (int32_t *)c; c += 256;
     w.lists = c; c += align256b(ws_bytes_for(lists, keep));
-    w.vimg = (__bf16 *)c;
+    w.vimg = (h16 *)c; c += align256b(bf_vimg_elems(vcols, n) * sizeof(h16));
+    w.side = c;
     return w;
 }
 
-__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+// Power of two nearest to 1 / x for x in [2^-56, 2^56], 1 otherwise: x times
+// it lies in [2^-1/2, 2^1/2).  Every operand variant is scaled by such a
+// factor of its root-mean-square (products of them by the product of the
+// factors, which stays inside FP32's exponent range), so that FP16 holds it
+// without overflow (|value| <= sqrt(n) times its rms) and with full relative
+// precision; the FP32 accumulators are scaled back exactly.  A column whose
+// rms lies outside that range is not scalable: the screen scores its
+// candidates exactly.
+__device__ __forceinline__ bool scalable(float x) { return x >= 0x1p-56f && x <= 0x1p56f; }
+__device__ __forceinline__ float pow2_inv(float x)
+{
+    if (!scalable(x)) return 1.0f;
+    int e;
+    const float f = frexpf(x, &e);                // x = f 2^e, f in [1/2, 1)
+    return ldexpf(1.0f, f < 0.70710678f ? 1 - e : -e);
+}
+// the root-mean-squares of a column's centred variants x~ and 1/x - mean(1/x)
+// (the latter only when the column has no zero) are scalable
+__device__ __forceinline__ bool col_scalable(float sxx, float srr, float fn, bool rcp)
+{
+    return scalable(sqrtf(sxx / fn)) && (!rcp || scalable(sqrtf(srr / fn)));
+}
+
+// Extra factor of the variants that are products of two centred values (their
+// magnitude can reach 2n times the product of the factors): keeps them under
+// 2^15 for any n.
+__device__ __forceinline__ float sq_shift(int n)
+{
+    int e;
+    frexpf((float)(2 * n), &e);                   // 2n < 2^e
+    return e > 15 ? ldexpf(1.0f, 15 - e) : 1.0f;
+}
+
+// Scale factors of a u column (U~, Z~; U~^2 and Z~^2 take the squares times
+// sq_shift) from its sums of squares.
+struct UScale { float u, z; };
+__device__ __forceinline__ UScale u_scales(float suu, float szz, float fn)
+{
+    return UScale{pow2_inv(sqrtf(suu / fn)), pow2_inv(sqrtf(szz / fn))};
+}
+// Scale factors of a v column: V~, P = V~ (V~ + 2 mean v), Q = V~ (V~ + mean v),
+// V~ r; the same for W~ = 1/v - mean(1/v).  rs: the residual's factor.
+struct VScale { float v, p, q, vr, w, pw, qw, wr; };
+__device__ __forceinline__ VScale v_scales(float mv, float mw, float svv, float sww, float fn, float rs, float sh)
+{
+    const float sv = sqrtf(svv / fn), sw = sqrtf(sww / fn);
+    VScale c;
+    c.v = pow2_inv(sv);
+    c.p = c.v * pow2_inv(sv + 2.0f * fabsf(mv)) * sh;
+    c.q = c.v * pow2_inv(sv + fabsf(mv)) * sh;
+    c.vr = c.v * rs * sh;
+    c.w = pow2_inv(sw);
+    c.pw = c.w * pow2_inv(sw + 2.0f * fabsf(mw)) * sh;
+    c.qw = c.w * pow2_inv(sw + fabsf(mw)) * sh;
+    c.wr = c.w * rs * sh;
+    return c;
+}
+// the residual's factor from its sum of squares
+__device__ __forceinline__ float r_scale(double srr, double n) { return pow2_inv((float)sqrt(srr / n)); }
 
 // Element offset of samples k .. k + 3 (k % 4 == 0) of column `row` in a staged
 // plane.  The two 8-sample halves of a row are swapped on rows whose bits 2 and
@@ -175,27 +274,18 @@ __device__ __forceinline__ void load_floats(const float *p, float (&x)[N])
     }
 }
 
-// Stores the BF16 parts of N consecutive samples: hi = bf16(x) at dst, lo =
-// bf16(x - hi) one plane further; two values per conversion.
+// Stores N consecutive samples rounded to FP16 (two per conversion).
 template <int N>
-__device__ __forceinline__ void put_split(__bf16 *dst, int plane, const float (&x)[N])
+__device__ __forceinline__ void put_h16(h16 *dst, const float (&x)[N])
 {
-#pragma clang fp contract(off)
-    unsigned hw[N / 2], lw[N / 2];
+    unsigned hw[N / 2];
 #pragma unroll
     for (int e = 0; e < N; e += 2) {
-        const bf16x2 h = __builtin_convertvector((f32x2){x[e], x[e + 1]}, bf16x2);
-        const bf16x2 l = __builtin_convertvector((f32x2){x[e] - (float)h[0], x[e + 1] - (float)h[1]}, bf16x2);
+        const h16x2 h = __builtin_convertvector((f32x2){x[e], x[e + 1]}, h16x2);
         __builtin_memcpy(&hw[e / 2], &h, 4);
-        __builtin_memcpy(&lw[e / 2], &l, 4);
     }
-    if constexpr (N == 4) {
-        *reinterpret_cast<uint2 *>(dst) = make_uint2(hw[0], hw[1]);
-        *reinterpret_cast<uint2 *>(dst + plane) = make_uint2(lw[0], lw[1]);
-    } else {
-        *reinterpret_cast<unsigned *>(dst) = hw[0];
-        *reinterpret_cast<unsigned *>(dst + plane) = lw[0];
-    }
+    if constexpr (N == 4) *reinterpret_cast<uint2 *>(dst) = make_uint2(hw[0], hw[1]);
+    else *reinterpret_cast<unsigned *>(dst) = hw[0];
 }
 
 #ifndef SISSO_BF16_MFMA_PART
@@ -296,31 +386,33 @@ __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restr
 }
 #endif  // SISSO_BF16_MFMA_PART
 
-// The residual-weighted centred v variants of one sample, V~ r and W~ r (0 for
-// a sample past n).  The write form forms them in its tile kernel and the read
-// form takes them from the v-side image: one function, the same bits.
-__device__ __forceinline__ void v_resid_vars(float x, float r, float smv, float smw, bool live, float &vr,
-                                             float &wr)
+// The residual-weighted centred v variants of one sample, V~ r and W~ r,
+// scaled (0 for a sample past n).  The write form forms them in its tile
+// kernel and the read form takes them from the v-side image: one function, the
+// same bits.
+__device__ __forceinline__ void v_resid_vars(float x, float r, float smv, float smw, float cvr, float cwr, bool live,
+                                             float &vr, float &wr)
 {
 #pragma clang fp contract(off)
     float vv = x - smv, ww = __builtin_amdgcn_rcpf(x) - smw;
     vv = live ? vv : 0.f; ww = live ? ww : 0.f; r = live ? r : 0.f;
-    vr = vv * r;
-    wr = ww * r;
+    vr = (vv * r) * cvr;
+    wr = (ww * r) * cwr;
 }
 
 #ifndef SISSO_BF16_MFMA_PART
 // The read form's v-side staging image for one residual: for each 128-column
-// v tile and chunk of 16 samples, the planes V~ r hi, V~ r lo, W~ r hi, W~ r lo
-// (128 rows of 16 samples each) exactly as the tile kernel lays them out in
-// LDS, so that staging them is a copy.  Block (vt, ch); thread t forms column
-// t / 2, samples 8 (t % 2) .. + 7.  Columns past |P_1| stage column 0's values
+// v tile and chunk of 16 samples, the planes V~ r and W~ r (128 rows of 16
+// samples each, FP16) exactly as the tile kernel lays them out in LDS, so that
+// staging them is a copy.  Block (vt, ch); thread t forms column t / 2,
+// samples 8 (t % 2) .. + 7.  Columns past |P_1| stage column 0's values
 // (their scores are discarded), samples past n zeros.
 __global__ void __launch_bounds__(256) k_bf16_v_image(int n, const float *__restrict__ pool32, int64_t ld32,
                                                       int64_t vcols, const float *__restrict__ r32,
-                                                      const float4 *__restrict__ vsum, __bf16 *__restrict__ img)
+                                                      const sisso_resid_info *__restrict__ info,
+                                                      const float4 *__restrict__ vsum, h16 *__restrict__ img)
 {
-    constexpr int kRows = 128, kPlanes = 2 * kSplit;
+    constexpr int kRows = 128, kPlanes = 2;
     const int nch = (n + kKC - 1) / kKC;
     const int64_t vt = blockIdx.x / nch;
     const int ch = blockIdx.x % nch;
@@ -328,26 +420,24 @@ __global__ void __launch_bounds__(256) k_bf16_v_image(int n, const float *__rest
     const int64_t v = vt * kRows + c;
     const int64_t vv = v < vcols ? v : 0;
     const float4 vs = vsum[2 * vv];
+    const VScale sc = v_scales(vs.x, vs.y, vs.z, vs.w, (float)n, r_scale(info->s_rr, (double)n), sq_shift(n));
     const float *col = pool32 + (size_t)vv * ld32;
     float vr[8], wr[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int t = ch * kKC + k0 + e;
         const int tc = t < n ? t : n - 1;
-        v_resid_vars(col[tc], r32[tc], vs.x, vs.y, t < n, vr[e], wr[e]);
+        v_resid_vars(col[tc], r32[tc], vs.x, vs.y, sc.vr, sc.wr, t < n, vr[e], wr[e]);
     }
-    __bf16 *const out = img + (size_t)blockIdx.x * kPlanes * kRows * kKR + lds_off(c, k0);
-    __bf16 hv[8], lv[8], hw[8], lw[8];
+    h16 *const out = img + (size_t)blockIdx.x * kPlanes * kRows * kKR + lds_off(c, k0);
+    h16 hv[8], hw[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-#pragma clang fp contract(off)
-        hv[e] = (__bf16)vr[e]; lv[e] = (__bf16)(vr[e] - (float)hv[e]);
-        hw[e] = (__bf16)wr[e]; lw[e] = (__bf16)(wr[e] - (float)hw[e]);
+        hv[e] = (h16)vr[e];
+        hw[e] = (h16)wr[e];
     }
     __builtin_memcpy(out, hv, 16);
-    __builtin_memcpy(out + kRows * kKR, lv, 16);
-    __builtin_memcpy(out + 2 * kRows * kKR, hw, 16);
-    __builtin_memcpy(out + 3 * kRows * kKR, lw, 16);
+    __builtin_memcpy(out + kRows * kKR, hw, 16);
 }
 
 // -------------------------------------------------------------- screening
@@ -363,20 +453,21 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     const float *__restrict__ r32, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
     const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
-    int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, const __bf16 *__restrict__ vimg,
-    void *lws, int lists_total, int keep, int cap, int publish)
+    int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, const h16 *__restrict__ vimg,
+    BfSide side, void *lws, int lists_total, int keep, int cap, int publish)
 {
     using Sh = BfShape<MODE>;
     constexpr int kUVar = Sh::kUVar, kVVar = Sh::kVVar, kNG = Sh::kNG, kPA = Sh::kPA, kPB = Sh::kPB,
                   kStage = Sh::kStage, kBTU = Sh::kBTU, kBTV = Sh::kBTV, kSU = Sh::kSU, kSV = Sh::kSV,
                   kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __bf16 *const stage = reinterpret_cast<__bf16 *>(smem);   // two staging buffers
+    h16 *const stage = reinterpret_cast<h16 *>(smem);   // two staging buffers
     float *lsc = (float *)(stage + 2 * kStage);
     int64_t *lid = (int64_t *)(lsc + cap);
     // u-tile column constants for the epilogue: (mean u, mean 1/u, sum u~^2,
-    // sum z~^2) and (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero)
-    float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBTU;
+    // sum z~^2), (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero) and the
+    // inverse scale factors of U~, U~^2, Z~, Z~^2
+    float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBTU, *ucon_c = ucon_b + kBTU;
     __shared__ int lcnt, lpend;
     __shared__ float lthr;
     __shared__ unsigned gdummy;                   // bound of a block that must not publish (stays 0)
@@ -394,6 +485,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     const int64_t binbase = s.pool[Lv] + s.rect_unary;
     const int S = s.n_slots;
     const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
+    const float fn = (float)n, rsc = r_scale(Srr, nd), shs = sq_shift(n);
     const int nch = (n + kKC - 1) / kKC;
     const int64_t nvt = (vcount + kBTV - 1) / kBTV, nvt64 = (vcount + 63) / 64;
     // staging roles: u column ucs, samples uks .. uks + kSU - 1 of a chunk; v
@@ -412,6 +504,8 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
         const bool su_ok = su < ucols;
         const float4 us_c = usum[su_ok ? su : 0];
         const float smu = us_c.x, smz = us_c.y;
+        const UScale usc = u_scales(us_c.z, us_c.w, fn);
+        const float cu = usc.u, cz = usc.z, cu2 = usc.u * usc.u * shs, cz2 = usc.z * usc.z * shs;
         const float *ucol = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
         __syncthreads();                              // the previous tile's epilogue reads are done
         if (tid < kBTU) {
@@ -419,9 +513,13 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             const bool in = x < ucols;
             const sisso_colstat cs = stats[ulo + (in ? x : 0)];
             const float2 b = ures[in ? x : 0];
-            ucon_a[tid] = usum[in ? x : 0];
+            const float4 ua = usum[in ? x : 0];
+            ucon_a[tid] = ua;
             ucon_b[tid] = make_float4(b.x, b.y, cs.rms,
                                       (in && cs.valid != 0.0f ? 1.0f : 0.0f) + (cs.minabs > 0.0f ? 2.0f : 0.0f));
+            const UScale c = u_scales(ua.z, ua.w, fn);
+            ucon_c[tid] = make_float4(1.0f / c.u, 1.0f / (c.u * c.u * shs), 1.0f / c.z, 1.0f / (c.z * c.z * shs));
+            if (!col_scalable(ua.z, ua.w, fn, cs.minabs > 0.0f)) ucon_b[tid].w += 4.0f;
         }
         for (int64_t vt = 0; vt < nvt; ++vt) {
             const int64_t v0 = vt * kBTV;
@@ -429,6 +527,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             const bool sv_ok = sv < vcount;
             const float4 vs_c = vsum[2 * (sv_ok ? sv : 0)];
             const float smv = vs_c.x, smw = vs_c.y;
+            const VScale vsc = v_scales(smv, smw, vs_c.z, vs_c.w, fn, rsc, shs);
             const float *vcol = pool32 + (size_t)(sv_ok ? sv : 0) * ld32;
             f32x16 acc[kNG];
 #pragma unroll
@@ -436,7 +535,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
             // Raw FP32 values of one chunk are loaded two chunks ahead into
-            // registers; the centred variants and their BF16 hi/lo parts are formed
+            // registers; the centred, scaled variants are formed, rounded to FP16
             // and stored into the other staging buffer while the MFMAs of the
             // current chunk run.  Out-of-range columns stage finite values of
             // column 0 (their rows and columns are dropped by the epilogue); a
@@ -445,9 +544,12 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // The read form copies its v side from the image (32 bytes per thread
             // and chunk); the other forms form it from v and r.
             constexpr int kRawV = Sh::kRead ? 1 : kSV;
+            // the read form's image chunk: kPB planes of kPlaneV values, one
+            // 16-byte vector per thread
+            static_assert(!Sh::kRead || kPB * kPlaneV * sizeof(h16) == 16 * Sh::kThreads, "image chunk per thread");
             struct Raw {
                 float u[kSU], v[kRawV], r[kRawV];
-                u32x4 i0, i1;                         // image bytes (read form)
+                u32x4 i0;                             // image bytes (read form)
             };
             Raw pr;                                   // the next chunk to stage
             auto load_chunk = [&](int ch, Raw &x) {
@@ -457,16 +559,15 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                     const int cc = min(ch, nch - 1);
                     const u32x4 *src = reinterpret_cast<const u32x4 *>(vimg + (size_t)(vt * nch + cc) * kPB * kPlaneV);
                     x.i0 = src[tid];                  // each wave instruction: 1 KB contiguous
-                    x.i1 = src[tid + Sh::kThreads];
                 } else {
                     const int tv = min(ch * kKC + vks, tmax_v);
                     load_floats<kSV>(vcol + tv, x.v);
                     load_floats<kSV>(r32 + tv, x.r);
                 }
             };
-            auto store_chunk = [&](int ch, __bf16 *buf, bool tail) {
-                // no contraction: the parts of U~, Z~, V~ r and W~ r are the same
-                // bits in every mode, so the residual GEMMs agree exactly
+            auto store_chunk = [&](int ch, h16 *buf, bool tail) {
+                // no contraction: U~, Z~, V~ r and W~ r are the same bits in
+                // every mode, so the residual GEMMs agree exactly
 #pragma clang fp contract(off)
                 float ua[kUVar][kSU], va[kVVar][kSV];
 #pragma unroll
@@ -477,18 +578,16 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                         uu = live ? uu : 0.f; zz = live ? zz : 0.f;
                     }
                     if constexpr (Sh::kRead) {
-                        ua[0][e] = uu; ua[1][e] = zz;
+                        ua[0][e] = uu * cu; ua[1][e] = zz * cz;
                     } else {
-                        ua[0][e] = uu; ua[1][e] = uu * uu; ua[2][e] = zz; ua[3][e] = zz * zz;
+                        ua[0][e] = uu * cu; ua[1][e] = (uu * uu) * cu2; ua[2][e] = zz * cz; ua[3][e] = (zz * zz) * cz2;
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < kUVar; ++q)
-                    put_split<kSU>(buf + (q * kSplit) * kPlaneU + sto_u, kPlaneU, ua[q]);
+                for (int q = 0; q < kUVar; ++q) put_h16<kSU>(buf + q * kPlaneU + sto_u, ua[q]);
                 if constexpr (Sh::kRead) {
                     u32x4 *dst = reinterpret_cast<u32x4 *>(buf + kPA * kPlaneU);
                     dst[tid] = pr.i0;
-                    dst[tid + Sh::kThreads] = pr.i1;
                 } else {
 #pragma unroll
                     for (int e = 0; e < kSV; ++e) {
@@ -497,18 +596,19 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                             const bool live = ch * kKC + vks + e < n;
                             vv = live ? vv : 0.f; ww = live ? ww : 0.f; r = live ? r : 0.f;
                         }
-                        va[0][e] = vv; va[2][e] = vv * (vv + 2.f * smv); va[3][e] = vv * (vv + smv);
-                        va[4][e] = ww; va[6][e] = ww * (ww + 2.f * smw); va[7][e] = ww * (ww + smw);
+                        va[0][e] = vv * vsc.v; va[2][e] = (vv * (vv + 2.f * smv)) * vsc.p;
+                        va[3][e] = (vv * (vv + smv)) * vsc.q;
+                        va[4][e] = ww * vsc.w; va[6][e] = (ww * (ww + 2.f * smw)) * vsc.pw;
+                        va[7][e] = (ww * (ww + smw)) * vsc.qw;
                         // V~ r and W~ r as the read form's image has them
-                        v_resid_vars(pr.v[e], pr.r[e], smv, smw, !tail || ch * kKC + vks + e < n, va[1][e],
-                                     va[5][e]);
+                        v_resid_vars(pr.v[e], pr.r[e], smv, smw, vsc.vr, vsc.wr, !tail || ch * kKC + vks + e < n,
+                                     va[1][e], va[5][e]);
                     }
 #pragma unroll
-                    for (int q = 0; q < kVVar; ++q)
-                        put_split<kSV>(buf + kPA * kPlaneU + (q * kSplit) * kPlaneV + sto_v, kPlaneV, va[q]);
+                    for (int q = 0; q < kVVar; ++q) put_h16<kSV>(buf + kPA * kPlaneU + q * kPlaneV + sto_v, va[q]);
                 }
             };
-            // GEMM g: u-side variant GA[g], v-side variant GB[g]; terms hi*hi, hi*lo, lo*hi
+            // GEMM g: u-side variant GA[g], v-side variant GB[g]
             constexpr int GAf[12] = {0, 0, 1, 0, 0, 0, 1, 0, 2, 2, 3, 2};
             constexpr int GBf[12] = {0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3};
             constexpr int GAr[3] = {0, 0, 1}, GBr[3] = {0, 1, 0};
@@ -517,21 +617,16 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // Fragments of the staged chunk, then its MFMAs.  With a single staging
             // buffer a barrier between the two frees the buffer for the next chunk
             // (every wave holds its fragments in registers by then).
-            auto mfma_chunk = [&](const __bf16 *buf) {
-                bf16x8 af[kPA], bfr[kPB];
+            auto mfma_chunk = [&](const h16 *buf) {
+                h16x8 af[kPA], bfr[kPB];
 #pragma unroll
-                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const bf16x8 *>(buf + a * kPlaneU + fa);
+                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const h16x8 *>(buf + a * kPlaneU + fa);
 #pragma unroll
                 for (int q = 0; q < kPB; ++q)
-                    bfr[q] = *reinterpret_cast<const bf16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb);
+                    bfr[q] = *reinterpret_cast<const h16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb);
 #pragma unroll
-                for (int term = 0; term < 3; ++term) {
-                    const int pa_ = term == 2 ? 1 : 0, pb_ = term == 1 ? 1 : 0;
-#pragma unroll
-                    for (int g = 0; g < kNG; ++g)
-                        acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[GA(g) * kSplit + pa_],
-                                                                         bfr[GB(g) * kSplit + pb_], acc[g], 0, 0, 0);
-                }
+                for (int g = 0; g < kNG; ++g)
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[GA(g)], bfr[GB(g)], acc[g], 0, 0, 0);
             };
             // interleave: fragment reads first, then each MFMA followed by a share of
             // the staging work of the next chunk (VALU and LDS stores)
@@ -539,14 +634,10 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 __builtin_amdgcn_sched_group_barrier(0x100, kPA + kPB, 0);   // LDS reads
                 __builtin_amdgcn_sched_group_barrier(0x020, 3, 0);           // global loads
 #pragma unroll
-                for (int i = 0; i < 3 * kNG; ++i) {
+                for (int i = 0; i < kNG; ++i) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // MFMA
-                    __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);       // VALU
-                    if constexpr (Sh::kRead) {
-                        if (i < kPA + kPB) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // LDS stores
-                    } else {
-                        if (i % 3 == 2) __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);   // LDS stores
-                    }
+                    __builtin_amdgcn_sched_group_barrier(0x002, Sh::kRead ? 6 : 12, 0);   // VALU
+                    if (i < kPA + kPB) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0); // LDS stores
                 }
             };
             auto buf_of = [&](int c) { return stage + (c & 1) * kStage; };   // two staging buffers
@@ -599,29 +690,38 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             const bool vin = v < vcount;
             const sisso_colstat vst = stats[vin ? v : 0];
             const float4 vs0 = vsum[2 * (vin ? v : 0)], vs1 = vsum[2 * (vin ? v : 0) + 1];
-            const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w, Svr = vs1.x, Swr = vs1.y, vrm = vs1.z;
-            const float fn = (float)n, rr = (float)(R1 / nd);
+            const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w, Svr = vs1.x, Swr = vs1.y;
+            const float rr = (float)(R1 / nd);
+            // inverse scale factors of this lane's v column: the accumulator of
+            // GEMM g times iu(row) iv(column) is the unscaled contraction
+            const VScale vc = v_scales(mv, mw, Svv, Sww, fn, rsc, shs);
+            const float iv = 1.0f / vc.v, ip = 1.0f / vc.p, iq = 1.0f / vc.q, ivr = 1.0f / vc.vr, iw = 1.0f / vc.w,
+                        ipw = 1.0f / vc.pw, iqw = 1.0f / vc.qw, iwr = 1.0f / vc.wr;
+            const bool vscal = col_scalable(Svv, Sww, fn, vst.minabs > 0.0f);
             // Residual-independent moments of row r, from the accumulators: sum h
-            // of u v, its variance, then the same for u/v and v/u.  The read form
-            // takes them as the write form stored them over the same pools.
+            // of u v, its variance, then the same for u/v and v/u.  A variance
+            // below kCondRel of the magnitude of its terms is not resolved by the
+            // FP16 operands: it is stored as -1 (the candidate is scored exactly).
+            // The read form takes the moments as the write form stored them over
+            // the same pools.
             auto moments_acc = [&](int r, float (&m)[kMom]) {
 #pragma clang fp contract(off)
                 if constexpr (!Sh::kRead) {
                     const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    const float4 us = ucon_a[wu * 32 + i];
+                    const float4 us = ucon_a[wu * 32 + i], ui = ucon_c[wu * 32 + i];
                     const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w;
-                    float s1 = acc[0][r];                           // u v
-                    float s2 = acc[2][r] + 2.0f * mu * acc[3][r] + mv * mv * Suu + mu * mu * Svv;
-                    m[0] = s1;
-                    m[1] = s2 - s1 * s1 / fn;
-                    s1 = acc[4][r];                                 // u / v
-                    s2 = acc[6][r] + 2.0f * mu * acc[7][r] + mw * mw * Suu + mu * mu * Sww;
-                    m[2] = s1;
-                    m[3] = s2 - s1 * s1 / fn;
-                    s1 = acc[8][r];                                 // v / u
-                    s2 = acc[10][r] + 2.0f * mz * acc[11][r] + mv * mv * Szz + mz * mz * Svv;
-                    m[4] = s1;
-                    m[5] = s2 - s1 * s1 / fn;
+                    auto var_of = [&](float s1, float g2, float g3, float ma, float mb, float sa, float sb) {
+                        const float t2 = 2.0f * ma * g3, t3 = mb * mb * sa, t4 = ma * ma * sb;
+                        const float var = (g2 + t2 + t3 + t4) - s1 * s1 / fn;
+                        const float mag = fabsf(g2) + fabsf(t2) + t3 + t4;
+                        return var >= kCondRel * mag && var < INFINITY ? var : -1.0f;
+                    };
+                    m[0] = (acc[0][r] * ui.x) * iv;                 // u v
+                    m[1] = var_of(m[0], (acc[2][r] * ui.y) * ip, (acc[3][r] * ui.x) * iq, mu, mv, Suu, Svv);
+                    m[2] = (acc[4][r] * ui.x) * iw;                 // u / v
+                    m[3] = var_of(m[2], (acc[6][r] * ui.y) * ipw, (acc[7][r] * ui.x) * iqw, mu, mw, Suu, Sww);
+                    m[4] = (acc[8][r] * ui.z) * iv;                 // v / u
+                    m[5] = var_of(m[4], (acc[10][r] * ui.w) * ip, (acc[11][r] * ui.z) * iq, mz, mv, Szz, Svv);
                 }
             };
             if constexpr (MODE == kBfWrite) {
@@ -650,13 +750,16 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // Approximate scores of the five forms of row r of this lane, -1 for
             // a pair outside the space or a form outside its domain.  Branch-free;
             // ids are formed only for the few candidates at the admission bound.
-            auto row_sums = [&](int r, float (&cov)[5], float (&var)[5], bool (&live)[5]) {
+            // flag[k]: a candidate of the space whose approximate variance fails
+            // the conditioning test (scored exactly instead; never live).
+            auto row_sums = [&](int r, float (&cov)[5], float (&var)[5], bool (&live)[5], bool (&flag)[5]) {
 #pragma clang fp contract(off)
                 const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const float4 us = ucon_a[wu * 32 + i], ub = ucon_b[wu * 32 + i];
+                const float4 us = ucon_a[wu * 32 + i], ub = ucon_b[wu * 32 + i], ui = ucon_c[wu * 32 + i];
                 const float mu = us.x, mz = us.y, Suu = us.z, Sur = ub.x, Szr = ub.y;
                 const int uflags = (int)ub.w;
                 const bool ok = (uflags & 1) && vin && vst.valid != 0.0f;
+                const bool unscal = (uflags & 4) != 0 || !vscal;
                 float m[kMom];
                 moments_of(r, m);
                 const float g0 = m[0];
@@ -665,24 +768,28 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 cov[0] = Sur + Svr;
                 cov[1] = Sur - Svr;
                 var[2] = m[1];                                      // u v
-                cov[2] = acc[Sh::kCovUV][r] + mv * Sur + mu * Svr - m[0] * rr;
+                cov[2] = (acc[Sh::kCovUV][r] * ui.x) * ivr + mv * Sur + mu * Svr - m[0] * rr;
                 var[3] = m[3];                                      // u / v
-                cov[3] = acc[Sh::kCovUW][r] + mw * Sur + mu * Swr - m[2] * rr;
+                cov[3] = (acc[Sh::kCovUW][r] * ui.x) * iwr + mw * Sur + mu * Swr - m[2] * rr;
                 var[4] = m[5];                                      // v / u
-                cov[4] = acc[Sh::kCovZV][r] + mv * Szr + mz * Svr - m[4] * rr;
+                cov[4] = (acc[Sh::kCovZV][r] * ui.z) * ivr + mv * Szr + mz * Svr - m[4] * rr;
                 const bool dom[5] = {true, true, true, vst.minabs > 0.f, (uflags & 2) != 0};
-                // a sum or difference whose spread sqrt(var / n) is at most 1e-2
-                // of the operands' rms has cancelled to rounding noise (the
-                // exact rule is applied by the rescore)
-                const float scale = fmaxf(ub.z, vrm);
-                const float cth = 1e-4f * scale * scale * fn;
+                // u + v and u - v: trusted when the variance is at least kCondRel
+                // of Suu + Svv (the error of 2 g0 is a fraction of it); the
+                // product forms carry -1 when their test failed
+                const float cth = kCondRel * (Suu + Svv);
 #pragma unroll
-                for (int k = 0; k < 5; ++k) live[k] = ok && dom[k] && fs.slot[k] >= 0 && var[k] > (k < 2 ? cth : 0.0f);
+                for (int k = 0; k < 5; ++k) {
+                    const bool cand = ok && dom[k] && fs.slot[k] >= 0;
+                    const bool good = !unscal && (k < 2 ? var[k] >= cth : var[k] > 0.0f) && var[k] < INFINITY;
+                    live[k] = cand && good && var[k] > 0.0f;
+                    flag[k] = cand && !good;
+                }
             };
             auto row_scores = [&](int r, float (&sc)[5]) {
                 float cov[5], var[5];
-                bool live[5];
-                row_sums(r, cov, var, live);
+                bool live[5], flag[5];
+                row_sums(r, cov, var, live, flag);
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
                     const float q = fabsf(cov[k]) * __builtin_amdgcn_rsqf(var[k] * (float)Srr);
@@ -720,12 +827,29 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 float cov[5], var[5];
-                bool live[5];
-                row_sums(r, cov, var, live);
-                bool hit = false;
+                bool live[5], flag[5];
+                row_sums(r, cov, var, live, flag);
+                bool hit = false, fl = false;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) hit = hit || (live[k] && (no_bound || cov[k] * cov[k] >= var[k] * k2));
+                for (int k = 0; k < 5; ++k) {
+                    hit = hit || (live[k] && (no_bound || cov[k] * cov[k] >= var[k] * k2));
+                    fl = fl || flag[k];
+                }
                 rows |= (hit ? 1u : 0u) << r;
+                if constexpr (!Sh::kRead) {
+                    // flagged candidates in range join the list of exact scoring
+                    // (the exclusion list is applied when they are scored)
+                    if (fl) {
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) {
+                            const int64_t id = fid_of(r, k);
+                            if (flag[k] && (tile_in || (id >= id_begin && id < id_end))) {
+                                const unsigned long long q = atomicAdd(side.cnt, 1ull);
+                                if (q < (unsigned long long)side.cap) side.ids[q] = id;
+                            }
+                        }
+                    }
+                }
             }
             int mine = 0;
             if (rows) {
@@ -844,6 +968,111 @@ __global__ void __launch_bounds__(256) k_rescore_ids(sisso_space s, FormSlots fs
     list_flush(L, &W.h->gthr, W.sc + (size_t)list * keep, W.id + (size_t)list * keep);
 }
 
+// Score of binary slice candidate `id` by one wave (lanes over the samples,
+// FP32 partial sums per lane, FP64 wave sums), with the validity, magnitude and
+// cancellation rules of the exact kernels; -1 if invalid.  Used for the
+// candidates the 16-bit screen cannot rank; the band rescore then gives every
+// reported candidate its exact FP32 score.
+__device__ inline float score_slice_id_wave(const sisso_space &s, const FormSlots &fs, int n,
+                                            const float *__restrict__ pool32, int64_t ld32,
+                                            const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
+                                            double nd, double R1, double Srr, int64_t id)
+{
+    const int lane = threadIdx.x & 63;
+    const int Lv = s.levels;
+    const int64_t binbase = s.pool[Lv] + s.rect_unary;
+    if (s.rect != 1 || id < binbase || id >= s.total) return -1.0f;
+    const int64_t loc = id - binbase, vcount = s.pool[Lv - 1];
+    const int slot = (int)(loc % s.n_slots);
+    const int64_t pair = loc / s.n_slots;
+    const int64_t u = s.pool[Lv - 1] + pair / vcount, v = pair % vcount;
+    int k = -1;
+    for (int f = 0; f < 5; ++f)
+        if (fs.slot[f] == slot) k = f;
+    const sisso_colstat ust = stats[u], vst = stats[v];
+    if (k < 0 || ust.valid == 0.0f || vst.valid == 0.0f) return -1.0f;
+    if ((k == 3 && !(vst.minabs > 0.0f)) || (k == 4 && !(ust.minabs > 0.0f))) return -1.0f;
+    const float *cu = pool32 + (size_t)u * ld32, *cv = pool32 + (size_t)v * ld32;
+    const float cm = ust.mean * vst.mean, c3 = ust.mean * vst.mean_rcp, c4 = vst.mean * ust.mean_rcp;
+    float fA = 0.f, fB = 0.f, fC = 0.f;
+    for (int t = lane * 4; t < n; t += 256) {     // 16-byte loads: samples t .. t + 3
+        const float4 a4 = *reinterpret_cast<const float4 *>(cu + t);
+        const float4 b4 = *reinterpret_cast<const float4 *>(cv + t);
+        const float4 r4 = *reinterpret_cast<const float4 *>(r32 + t);
+        const float ua[4] = {a4.x, a4.y, a4.z, a4.w}, va[4] = {b4.x, b4.y, b4.z, b4.w};
+        const float ra[4] = {r4.x, r4.y, r4.z, r4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (t + e < n) {
+                const float ur = ua[e], vr = va[e];
+                const float g = binary_form(k, ur, ur - ust.mean, __builtin_amdgcn_rcpf(ur), vr, vr - vst.mean,
+                                            __builtin_amdgcn_rcpf(vr), cm, c3, c4);
+                fA += g;
+                fB = fmaf(g, g, fB);
+                fC = fmaf(g, ra[e], fC);
+            }
+    }
+    const double A = wave_sum_dpp((double)fA), B = wave_sum_dpp((double)fB), C = wave_sum_dpp((double)fC);
+    const double shifts[5] = {(double)ust.mean + (double)vst.mean, (double)ust.mean - (double)vst.mean,
+                              (double)cm, (double)c3, (double)c4};
+    return form_score(k, (float)A, B, C, shifts[k], cu, cv, n, ust.maxabs, ust.minabs, ust.rms, vst.maxabs,
+                      vst.minabs, vst.rms, nd, R1, Srr);
+}
+
+// Scores of the flagged candidates, one wave per candidate, written as extra
+// lists of the band workspace after the screen's l0 lists: entry e at list
+// l0 + e / keep, slot e % keep (-1 for an entry outside [id_begin, id_end)
+// or excluded, and for the padding of the last list).  Every flagged
+// candidate is kept, so the band's merge does not depend on the order in
+// which the screen stored them.  An overflowing list is reported (3).
+__global__ void __launch_bounds__(256) k_bf_side(sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32,
+                                                 int64_t ld32, const sisso_colstat *__restrict__ stats,
+                                                 const float *__restrict__ r32,
+                                                 const sisso_resid_info *__restrict__ info,
+                                                 const int64_t *__restrict__ excl, int n_excl, int64_t id_begin,
+                                                 int64_t id_end, BfSide side, void *lws, int lists_total, int keep,
+                                                 int l0)
+{
+    WsView W = ws_view(lws, lists_total, keep);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const unsigned long long c = *side.cnt;
+    const int64_t cnt = c < (unsigned long long)side.cap ? (int64_t)c : side.cap;
+    const int64_t nl = (cnt + keep - 1) / keep;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        W.h->n_lists = l0 + (int)nl;
+        if (c > (unsigned long long)side.cap) W.h->scr_status = 3;
+    }
+    const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
+    float *const osc = W.sc + (size_t)l0 * keep;
+    int64_t *const oid = W.id + (size_t)l0 * keep;
+    for (int64_t e = wave; e < nl * keep; e += nw) {
+        float sc = -1.0f;
+        int64_t id = INT64_MAX;
+        if (e < cnt) {
+            id = side.ids[e];
+            if (id >= id_begin && id < id_end && (n_excl == 0 || !in_sorted_ids(excl, n_excl, id)))
+                sc = score_slice_id_wave(s, fs, n, pool32, ld32, stats, r32, nd, R1, Srr, id);
+        }
+        if (lane == 0) {
+            osc[e] = sc;
+            oid[e] = id;
+        }
+    }
+}
+
+__global__ void k_bf_side_reset(BfSide side)
+{
+    if (threadIdx.x == 0) *side.cnt = 0ull;
+}
+
+// the screening status of the band workspace joins the main workspace's
+__global__ void k_bf_status(WsHeader *h, const WsHeader *band)
+{
+    if (threadIdx.x == 0 && band->scr_status != 0) h->scr_status = band->scr_status;
+}
+
 __global__ void k_bf_append(WsHeader *h, int n_lists)
 {
     if (threadIdx.x == 0) h->n_lists = n_lists;
@@ -853,6 +1082,7 @@ __global__ void k_bf_reset(WsHeader *h, int keep, int n_lists, int lists_cap)
 {
     if (threadIdx.x == 0) {
         h->gthr = 0u; h->keep = keep; h->n_lists = n_lists; h->lists_cap = lists_cap; h->status = 0;
+        h->scr_status = 0;
     }
 }
 #else
@@ -891,7 +1121,13 @@ BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end, int max_grid = 
     return p;
 }
 
+// band lists: those of the screen (one per block) and those of the exact
+// scores of the flagged candidates
 int bf_lists_cap(const sisso_space *s) { return bf_plan(s, 0, s->total).grid; }
+int bf_lists_total(const sisso_space *s, int keep_b)
+{
+    return bf_lists_cap(s) + (int)((bf_side_cap(*s) + keep_b - 1) / keep_b);
+}
 
 // a block list holds keep entries plus one offer per thread between merges
 int bf_list_cap(int keep, int threads) { return next_pow2(keep + threads); }
@@ -902,7 +1138,7 @@ int bf_block_keep(int band) { return band < SISSO_MAX_KEEP ? band : SISSO_MAX_KE
 
 bool space_ok(const sisso_space *s)
 {
-    return s && s->total > 0 && s->rect && s->levels >= 1 && s->levels <= SISSO_MAX_LEVELS &&
+    return s && s->total > 0 && s->rect == 1 && s->levels >= 1 && s->levels <= SISSO_MAX_LEVELS &&
            s->pool[s->levels - 1] > 0;
 }
 
@@ -937,7 +1173,8 @@ extern "C" size_t sisso_bf16_workspace_size(const sisso_space *space, const siss
     if (!space_ok(space) || !args || args->n < 2 || band < 1 || band > SISSO_MAX_BAND) return 0;
     const int L = space->levels;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
-    return bf_ws_bytes(ucols, vcols, args->n, band, bf_lists_cap(space), bf_block_keep(band));
+    return bf_ws_bytes(*space, ucols, vcols, args->n, band, bf_lists_total(space, bf_block_keep(band)),
+                       bf_block_keep(band));
 }
 
 extern "C" int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_score_args *args,
@@ -976,7 +1213,7 @@ extern "C" sisso_status sisso_bf16_residual(const sisso_space *space, const siss
     hipStream_t st = as_stream(stream);
     const int L = space->levels, n = args->n;
     const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
-    BfWs w = bf_ws_view(bws, ucols, vcols, band, bf_lists_cap(space), bf_block_keep(band));
+    BfWs w = bf_ws_view(bws, ucols, vcols, n, band, bf_lists_total(space, bf_block_keep(band)), bf_block_keep(band));
     const int64_t vb = (vcols + 3) / 4, ub = (ucols + 3) / 4;
     hipLaunchKernelGGL(k_bf16_v_prep, dim3((unsigned)(vb < 65536 ? vb : 65536)), dim3(256), 0, st, n, args->pool32,
                        args->ld32, args->stats, vcols, args->r32, w);
@@ -984,7 +1221,7 @@ extern "C" sisso_status sisso_bf16_residual(const sisso_space *space, const siss
                        args->ld32, args->stats, col0, ucols, args->r32, w.ures);
     const int64_t img_blocks = ((vcols + 127) / 128) * (int64_t)((n + kKC - 1) / kKC);
     hipLaunchKernelGGL(k_bf16_v_image, dim3((unsigned)img_blocks), dim3(256), 0, st, n, args->pool32, args->ld32,
-                       vcols, args->r32, w.vsum, w.vimg);
+                       vcols, args->r32, args->info, w.vsum, w.vimg);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 
@@ -996,7 +1233,7 @@ namespace sisso {
 // and write forms are instantiated by the second build only.
 template <int MODE>
 sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, const BfOps &o, BfWs &w,
-                       int32_t band, int64_t cand_begin, int64_t cand_end, float *mom, hipStream_t st)
+                       int32_t band, int64_t cand_begin, int64_t cand_end, float *mom, BfSide side, hipStream_t st)
 {
     using Sh = BfShape<MODE>;
     const int n = args->n;
@@ -1020,37 +1257,57 @@ sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, c
     const int keep_b = bf_block_keep(band);
     const int cap_b = bf_list_cap(keep_b, Sh::kThreads);
     const int publish = keep_b >= band ? 1 : 0;
-    const int lcap = bf_lists_cap(space);
+    const int lcap = bf_lists_total(space, keep_b);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)2 * Sh::kStage * sizeof(__bf16) + 2 * Sh::kBTU * sizeof(float4) +
+        const size_t smem = (size_t)2 * Sh::kStage * sizeof(h16) + 3 * Sh::kBTU * sizeof(float4) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16<MODE>, smem)) return SISSO_E_UNSUPPORTED;
         hipLaunchKernelGGL(k_score_rect_bf16<MODE>, dim3(p.grid), dim3(Sh::kThreads), smem, st, *space, fs, n,
                            args->pool32, args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info,
                            args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, mom, w.vimg,
-                           w.lists, lcap, keep_b, cap_b, publish);
+                           side, w.lists, lcap, keep_b, cap_b, publish);
     }
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+// The screen's lists come first in the band workspace: the number it writes.
+template <int MODE>
+int bf_screen_lists(const sisso_space *space, const sisso_score_args *args, int64_t cand_begin, int64_t cand_end,
+                    int cus)
+{
+    int max_grid = args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid;
+    if (BfShape<MODE>::kRead) max_grid = BfShape<MODE>::kMinBlocks * cus < kMaxBfGrid ? BfShape<MODE>::kMinBlocks * cus
+                                                                                       : kMaxBfGrid;
+    return bf_plan(space, cand_begin, cand_end, max_grid).grid;
 }
 
 }  // namespace sisso
 
 #ifdef SISSO_BF16_MFMA_PART
 template sisso_status sisso::bf_launch<kBfFull>(const sisso_space *, const sisso_score_args *, const BfOps &,
-                                                BfWs &, int32_t, int64_t, int64_t, float *, hipStream_t);
+                                                BfWs &, int32_t, int64_t, int64_t, float *, BfSide, hipStream_t);
 template sisso_status sisso::bf_launch<kBfWrite>(const sisso_space *, const sisso_score_args *, const BfOps &,
-                                                 BfWs &, int32_t, int64_t, int64_t, float *, hipStream_t);
+                                                 BfWs &, int32_t, int64_t, int64_t, float *, BfSide, hipStream_t);
 #else
 extern template sisso_status sisso::bf_launch<kBfFull>(const sisso_space *, const sisso_score_args *, const BfOps &,
-                                                       BfWs &, int32_t, int64_t, int64_t, float *, hipStream_t);
+                                                       BfWs &, int32_t, int64_t, int64_t, float *, BfSide,
+                                                       hipStream_t);
 extern template sisso_status sisso::bf_launch<kBfWrite>(const sisso_space *, const sisso_score_args *,
                                                         const BfOps &, BfWs &, int32_t, int64_t, int64_t, float *,
-                                                        hipStream_t);
+                                                        BfSide, hipStream_t);
 
 namespace {
 
 int64_t bf_tiles(int64_t cols) { return (cols + kBT - 1) / kBT; }
+
+// the moments of every pair, 256-byte aligned (the flagged candidates follow)
+size_t bf_moments_bytes(const sisso_space *space)
+{
+    const int L = space->levels;
+    const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
+    return align256b((size_t)bf_tiles(ucols) * (size_t)bf_tiles(vcols) * kMomTile * sizeof(float));
+}
 
 sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, const void *ops, size_t ops_bytes,
                        int32_t band, int64_t cand_begin, int64_t cand_end, void *moments, size_t moments_bytes,
@@ -1072,13 +1329,39 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     hipStream_t st = as_stream(stream);
     const int64_t col0 = space->pool[L - 1], ucols = space->pool[L] - col0, vcols = space->pool[L - 1];
     const BfOps o = bf_ops_view(const_cast<void *>(ops));
-    BfWs w = bf_ws_view(bws, ucols, vcols, band, bf_lists_cap(space), bf_block_keep(band));
+    const int keep_b = bf_block_keep(band);
+    BfWs w = bf_ws_view(bws, ucols, vcols, n, band, bf_lists_total(space, keep_b), keep_b);
     float *mom = (float *)moments;
+    // the flagged candidates: beside the moments (the READ form scores those a
+    // WRITE form stored), else in the workspace
+    const BfSide side = bf_side_view(mode == SISSO_MOMENTS_NONE ? w.side : (char *)moments + bf_moments_bytes(space),
+                                     *space);
+    if (mode != SISSO_MOMENTS_READ) hipLaunchKernelGGL(k_bf_side_reset, dim3(1), dim3(64), 0, st, side);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return SISSO_E_DEVICE;
+    sisso_status rc;
+    int l0;
     switch (mode) {
-    case SISSO_MOMENTS_WRITE: return bf_launch<kBfWrite>(space, args, o, w, band, cand_begin, cand_end, mom, st);
-    case SISSO_MOMENTS_READ: return bf_launch<kBfRead>(space, args, o, w, band, cand_begin, cand_end, mom, st);
-    default: return bf_launch<kBfFull>(space, args, o, w, band, cand_begin, cand_end, nullptr, st);
+    case SISSO_MOMENTS_WRITE:
+        rc = bf_launch<kBfWrite>(space, args, o, w, band, cand_begin, cand_end, mom, side, st);
+        l0 = bf_screen_lists<kBfWrite>(space, args, cand_begin, cand_end, cus);
+        break;
+    case SISSO_MOMENTS_READ:
+        rc = bf_launch<kBfRead>(space, args, o, w, band, cand_begin, cand_end, mom, side, st);
+        l0 = bf_screen_lists<kBfRead>(space, args, cand_begin, cand_end, cus);
+        break;
+    default:
+        rc = bf_launch<kBfFull>(space, args, o, w, band, cand_begin, cand_end, nullptr, side, st);
+        l0 = bf_screen_lists<kBfFull>(space, args, cand_begin, cand_end, cus);
     }
+    if (rc != SISSO_OK) return rc;
+    const FormSlots fs = form_slots(space);
+    hipLaunchKernelGGL(k_bf_side, dim3(1024), dim3(256), 0, st, *space, fs, n, args->pool32, args->ld32, args->stats,
+                       args->r32, args->info, args->exclude, args->n_exclude, cand_begin, cand_end, side, w.lists,
+                       bf_lists_total(space, keep_b), keep_b, l0);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 
 }  // namespace
@@ -1086,9 +1369,7 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
 extern "C" size_t sisso_bf16_moments_size(const sisso_space *space, int32_t n)
 {
     if (!space_ok(space) || n < 2 || n > SISSO_MAX_N) return 0;
-    const int L = space->levels;
-    const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
-    return (size_t)bf_tiles(ucols) * (size_t)bf_tiles(vcols) * kMomTile * sizeof(float);
+    return bf_moments_bytes(space) + bf_side_bytes(*space);
 }
 
 extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_score_args *args, const void *ops,
@@ -1122,7 +1403,7 @@ extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso
     hipStream_t st = as_stream(stream);
     const int L = space->levels, n = args->n;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
-    BfWs w = bf_ws_view(bws, ucols, vcols, band, bf_lists_cap(space), bf_block_keep(band));
+    BfWs w = bf_ws_view(bws, ucols, vcols, n, band, bf_lists_total(space, bf_block_keep(band)), bf_block_keep(band));
     const FormSlots fs = form_slots(space);
     sisso_status rs = topk_launch(w.lists, band, w.band_ids, w.band_sc, w.band_cnt, st, band > bf_block_keep(band));
     if (rs != SISSO_OK) return rs;
@@ -1131,6 +1412,7 @@ extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso
         hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)ws, keep, n_resc, lists_main);
     else
         hipLaunchKernelGGL(k_bf_append, dim3(1), dim3(64), 0, st, (WsHeader *)ws, args->list_base + n_resc);
+    hipLaunchKernelGGL(k_bf_status, dim3(1), dim3(64), 0, st, (WsHeader *)ws, (const WsHeader *)w.lists);
     const size_t smem = (size_t)cap * (sizeof(float) + sizeof(int64_t));
     hipLaunchKernelGGL(k_rescore_ids, dim3(n_resc), dim3(256), smem, st, *space, fs, n, args->pool32, args->ld32,
                        args->stats, args->r32, args->info, w.band_ids, w.band_cnt, args->exclude, args->n_exclude,

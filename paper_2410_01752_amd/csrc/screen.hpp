@@ -43,7 +43,9 @@ struct WsHeader {
     int total;              // entries considered by the select
     int n_gt, n_eq;         // gather counters
     int lists_cap;          // list slots the workspace was laid out for
-    int pad[6];
+    int scr_status;         // 0 ok; 3 = a 16-bit screen could not keep every flagged candidate
+    int thr_count;          // threshold selection: entries at or above the threshold
+    int pad[4];
     unsigned hist[kHistBins];
 };
 

@@ -7,19 +7,20 @@
 // 1 - |corr(f, g)| <= 1e-9 over list + current subspace; a class touching the
 // subspace is dropped; a class is represented by its smallest id and scored by
 // its best member; the best k classes (score desc, id asc) are appended.
+// The components are formed by a lock-free union-find over the duplicate
+// pairs as the pair kernel finds them (a root is hooked under the smaller of
+// two roots, so every root is the smallest node of its component), which
+// holds any number of duplicate pairs.
 #include "linalg.hpp"
 
 namespace sisso {
-
-constexpr int kEdgeCap = 1 << 20;
 
 struct SubWs {
     double *Z;        // n x nodes, standardised (ld = ldz)
     double *zr;       // standardised residual
     double *score;    // FP64 score per node (candidates)
     int *ok;          // per node
-    int2 *edges;
-    int *n_edges;
+    int *parent;      // union-find forest over the nodes
     int ldz;
 };
 
@@ -32,7 +33,7 @@ __host__ __device__ inline size_t sub_ws_bytes(int n, int nodes)
     b += (size_t)nodes * sizeof(double);
     b += (size_t)nodes * sizeof(int);
     b = (b + 255) & ~(size_t)255;
-    b += (size_t)kEdgeCap * sizeof(int2);
+    b += (size_t)nodes * sizeof(int);
     b += 256;
     return b;
 }
@@ -49,8 +50,7 @@ __host__ __device__ inline SubWs sub_ws_view(void *ws, int n, int nodes)
     size_t off = (size_t)(p - (char *)ws);
     off = (off + 255) & ~(size_t)255;
     p = (char *)ws + off;
-    w.edges = (int2 *)p; p += (size_t)kEdgeCap * sizeof(int2);
-    w.n_edges = (int *)p;
+    w.parent = (int *)p;
     return w;
 }
 
@@ -58,7 +58,6 @@ __device__ inline void sub_resid(const double *__restrict__ r, int n, SubWs w)
 {
     __shared__ double red[16];
     standardize_column(r, n, w.zr, nullptr, nullptr, nullptr, red);
-    if (threadIdx.x == 0) *w.n_edges = 0;
 }
 
 // node q < m_prev: subspace column; else candidate q - m_prev.
@@ -71,6 +70,7 @@ __device__ inline void sub_standardize(const double *__restrict__ sub, int lds, 
     const int ci = q - m_prev;
     const double *x = is_c ? cand + (size_t)ci * ldc : sub + (size_t)q * lds;
     double *z = w.Z + (size_t)q * w.ldz;
+    if (threadIdx.x == 0) w.parent[q] = q;
     int ok_live = 1;
     if (is_c) ok_live = (ci < *count_dev) && cvalid[ci] != 0;
     if (!ok_live) {
@@ -91,7 +91,35 @@ __device__ inline void sub_standardize(const double *__restrict__ sub, int lds, 
     }
 }
 
-// Duplicate edges between candidate rows and all earlier nodes.
+// Root of node a (loads bypass the non-coherent caches: other blocks hook
+// roots while this one walks).
+__device__ __forceinline__ int uf_root(int *par, int a)
+{
+    int p = __hip_atomic_load(par + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (p != a) {
+        a = p;
+        p = __hip_atomic_load(par + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return a;
+}
+
+// Join the components of a and b: the larger root is hooked under the smaller
+// one by compare-and-swap; a failed swap means another thread changed that
+// root, and the walk starts again.  Hooks only point to smaller nodes, so no
+// cycle forms and every loop ends.
+__device__ inline void uf_join(int *par, int a, int b)
+{
+    for (;;) {
+        a = uf_root(par, a);
+        b = uf_root(par, b);
+        if (a == b) return;
+        if (a < b) { const int t = a; a = b; b = t; }
+        if (atomicCAS(par + a, a, b) == a) return;
+    }
+}
+
+// Duplicate pairs between candidate rows and all earlier nodes, joined in the
+// union-find forest.
 __device__ inline void sub_edges(int m_prev, int nodes, int n, SubWs w, int bi, int bj)
 {
     __shared__ double As[kGK][kGT + 1];
@@ -107,10 +135,8 @@ __device__ inline void sub_edges(int m_prev, int nodes, int n, SubWs w, int bi, 
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int i = bi * kGT + ty * 2 + a, j = bj * kGT + tx * 2 + b;
-            if (i < nodes && j < i && i >= m_prev && w.ok[i] && w.ok[j] && 1.0 - fabs(acc[a][b]) <= kDupTol) {
-                const int e = atomicAdd(w.n_edges, 1);
-                if (e < kEdgeCap) w.edges[e] = make_int2(i, j);
-            }
+            if (i < nodes && j < i && i >= m_prev && w.ok[i] && w.ok[j] && 1.0 - fabs(acc[a][b]) <= kDupTol)
+                uf_join(w.parent, i, j);
         }
 }
 
@@ -129,45 +155,16 @@ __device__ inline void sub_classes(int m_prev, int nodes, const int64_t *__restr
     unsigned long long *best = rep + nodes;                     // max score bits per root
     double *ksc = (double *)(best + nodes);                     // class list (pow2)
     int64_t *kid = (int64_t *)(ksc + next_pow2(nodes));
-    __shared__ int changed, ncls;
-    if (*w.n_edges > kEdgeCap) {
-        // more duplicate pairs than the edge list holds: the classes cannot be
-        // formed exactly, so the update fails (nothing appended, n_classes -1)
-        if (threadIdx.x == 0) { *n_new = 0; *n_classes = -1; }
-        return;
-    }
-    const int ne = *w.n_edges;
+    __shared__ int ncls;
+    // component label: the root, which is the component's smallest node
     for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
-        label[i] = i;
+        int r = i;
+        while (w.parent[r] != r) r = w.parent[r];
+        label[i] = r;
         rep[i] = ~0ull;
         best[i] = 0ull;
     }
     __syncthreads();
-    // min-label propagation over the edges until stable
-    for (;;) {
-        if (threadIdx.x == 0) changed = 0;
-        __syncthreads();
-        for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-            const int2 ed = w.edges[e];
-            const int la = label[ed.x], lb = label[ed.y];
-            if (la != lb) {
-                const int m = la < lb ? la : lb;
-                atomicMin(&label[ed.x], m);
-                atomicMin(&label[ed.y], m);
-                changed = 1;
-            }
-        }
-        __syncthreads();
-        // pointer jumping
-        for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
-            int l = label[i];
-            while (label[l] != l) l = label[l];
-            if (l != label[i]) { atomicMin(&label[i], l); }
-        }
-        __syncthreads();
-        if (!changed) break;
-        __syncthreads();
-    }
     // per root: min candidate id and max FP64 score over valid candidates
     for (int i = threadIdx.x; i < nodes; i += blockDim.x) {
         if (i >= m_prev && w.ok[i]) {

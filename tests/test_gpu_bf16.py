@@ -240,3 +240,37 @@ def test_bf16_moments_argument_errors():
     b = eng.screen(y64, 100, None, precision="bf16", band=400, moments="read")
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_small_spread_differences_reach_the_list():
+    """Valid differences whose spread is about 1e-3 of their operands' rms fill
+    the top of the list: x1 = 1 + 1e-3 N(0, 1) and y = x0 (x1^2 - 1) + noise,
+    so (x1 x0) x1 - x0, x1 x0 - x0 and their regroupings all correlate with y
+    to 0.9999.  Their 16-bit variance is rounding noise (the conditioning test
+    flags them) and they are scored exactly: the 16-bit form's list equals the
+    FP32 form's list id for id and bit for bit (the exact rules call them
+    valid, their sd being above 1e-5 of the operands' rms; a screen that cut
+    them at 1e-2 lost them)."""
+    rng = np.random.default_rng(41)
+    n, d = 500, 4
+    X = rng.lognormal(0.0, 0.5, size=(n, d))
+    X[:, 1] = 1.0 + 1e-3 * rng.normal(size=n)
+    target = X[:, 0] * (X[:, 1] ** 2 - 1.0)
+    y = 3.0 * target / target.std() + 0.05 * rng.normal(size=n)
+    p = I.Problem("spread", X, y, list(I.OPS1["unary"]), list(I.OPS1["binary"]), 2, True, 10, 1, [], [], 0)
+    print("[bf16] small-spread differences", flush=True)
+    eng = _engine(p)
+    sp = O.Space(d, p.unary, p.binary, 2, True)
+    out = _both(eng, p.y, 200, 800)
+    fi, fs = out["fp32"]
+    bi, bs = out["bf16"]
+    gap = 0
+    for i in fi[:50]:
+        op, a, b = sp.decode(int(i))
+        if op != O.OPCODE["sub"]:
+            continue
+        V, ok = sp.eval(X, [int(i), a, b])
+        ratio = V[:, 0].std() / np.sqrt(np.mean(V[:, 1:] ** 2, axis=0)).max()
+        gap += int(ok.all() and 1e-5 < ratio < 1e-2)
+    assert gap >= 10, gap
+    assert np.array_equal(bi, fi) and np.array_equal(bs, fs)

@@ -100,3 +100,25 @@ def test_topk_tie_overflow_keeps_every_entry_above_the_cutoff():
     # the fit driver refuses a merge whose tie order is not exact
     with pytest.raises(L.SissoError):
         eng.fit(10, 1, keep0=keep)
+
+
+def test_duplicate_class_with_millions_of_pairs():
+    """The screened list holds 1,977 duplicates of one feature (copies of z and
+    sums of two copies, 2z), so one duplicate class has about 1.95 million
+    pairs: the classes (Sec. 2.1's non-unique combinations) must still be
+    exact -- the subspace equals the oracle's."""
+    rng = np.random.default_rng(32)
+    n, d = 64, 71
+    x0 = rng.lognormal(0.0, 0.5, n)
+    z = rng.lognormal(0.0, 0.5, n)
+    X = np.column_stack([x0] + [z] * (d - 1))
+    y = x0 + 0.2 * z + rng.normal(0.0, 0.05, n)
+    p = I.Problem("dups", X, y, [], ["add"], 1, False, 3, 1, [], [], 0)
+    print("[edges] duplicate class of ~2e6 pairs", flush=True)
+    eng = _engine(p)
+    res = eng.fit(3, 1, keep0=2048)
+    ref = O.fit(X, y, [], ["add"], 1, False, 3, 1, keep0=2048)
+    assert list(res[0].list_ids) == list(ref[0].list_ids)
+    assert list(res[0].sub_ids) == list(ref[0].sub_ids)
+    assert res[0].n_classes == 3
+    assert list(res[0].best_ids) == list(ref[0].best_ids)
