@@ -36,6 +36,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -235,9 +236,23 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(p, budget_s: float):
-    """The FP64 oracle on a bounded sample of the same workload: the binary
-    rung-3 block for the first u operands (all v, all slots), single thread."""
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:                          # noqa: BLE001 - lscpu is optional
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, budget_s: float, sub=None):
+    """The FP64 oracle on bounded samples of the same workload: the binary
+    rung-3 block for consecutive u operands (all v, all slots) on one thread,
+    then the same rate from one single-threaded process per core (at most 16,
+    the host share of one GPU), then the SO step on the fit's 600-column
+    subspace at D = 3 (C(600, 3) tuples)."""
     from oracle import oracle as O
     sp = O.Space(p.X.shape[1], p.unary, p.binary, p.rung, p.rect)
     if p.rect:
@@ -256,9 +271,42 @@ def cpu_baseline(p, budget_s: float):
     sp.score_range(p.X, p.y, base + per_u, base + per_u * (1 + n_u))
     dt = time.perf_counter() - t0
     cands = per_u * n_u
-    return {"value": cands / dt, "unit": "candidates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cands} candidates ({n_u} u operands x {per_u} (v, op) pairs of the "
-                      f"binary rung-3 block) scored in FP64, one thread, {dt:.1f} s"}
+    out = {"value": cands / dt, "unit": "candidates/s", "cores": 1, "kind": "oracle",
+           "sample": f"{cands} candidates ({n_u} u operands x {per_u} (v, op) pairs of the "
+                     f"binary rung-3 block) scored in FP64, one thread, {dt:.1f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    # all cores: independent single-threaded processes on disjoint slices
+    if p.rect and p.name == "C3":
+        procs = max(1, min(os.cpu_count() or 1, 16))
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        per_proc = max(1, n_u // 2)
+        start = base + per_u * (1 + n_u)
+        t0 = time.perf_counter()
+        workers = []
+        for i in range(procs):
+            b = start + i * per_proc * per_u
+            workers.append(subprocess.Popen(
+                [sys.executable, "-m", "oracle.slice_worker", str(p.seed), str(b), str(b + per_proc * per_u)],
+                cwd=ROOT, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+        done = 0
+        for w in workers:
+            o, _ = w.communicate()
+            if w.returncode == 0:
+                done += int(o.split()[0])
+        wall = time.perf_counter() - t0
+        out["all_core"] = {"value": done / wall, "unit": "candidates/s", "cores": procs,
+                           "sample": f"{procs} single-threaded processes x {per_proc * per_u} candidates "
+                                     f"(disjoint u ranges of the binary block), {wall:.1f} s wall including "
+                                     f"each process's start-up"}
+    if sub is not None:
+        F, y, D = sub
+        t0 = time.perf_counter()
+        r = O.l0(F, y, D)
+        dt = time.perf_counter() - t0
+        out["so"] = {"value": r.n_tuples / dt, "unit": "tuples/s", "cores": 1,
+                     "sample": f"oracle SO over the fit's {F.shape[1]}-column subspace at D = {D} "
+                               f"({r.n_tuples} tuples, Gram + Gaussian elimination per tuple), {dt:.2f} s"}
+    return out
 
 
 MI355X_BF16_TFLOPS = 2500.0               # dense MFMA
@@ -540,7 +588,13 @@ def main():
         out["learned_c5"] = learned_c5(learned_params, args, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        sub = None
+        if p.rect and len(last) == p.dmax:
+            from oracle import oracle as O
+            sp = O.Space(p.X.shape[1], p.unary, p.binary, p.rung, p.rect)
+            F, ok = sp.eval(p.X, np.sort(last[-1].sub_ids))
+            sub = (F, p.y, p.dmax)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds, sub)
     print(json.dumps(out))
 
 

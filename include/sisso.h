@@ -42,10 +42,13 @@
  *      P[j] / P[i], then P[i] / P[j].
  * Pairs are never a feature with itself and need an operand new at the
  * previous level, which reproduces the paper's worked example of Sec. 2.1
- * (|phi_1| = 4, |phi_2| = 14 for d = 2 and {I, +, x}).  If `rect` is set, the
+ * (|phi_1| = 4, |phi_2| = 14 for d = 2 and {I, +, x}).  If `rect` is 1, the
  * SIS space adds the one-sided slice of the next level: for each u in N_L,
  * each unary op(u); then for each u in N_L, each v in P_{L-1}, each binary
- * slot: op(u, v) (DIV: u/v then v/u).
+ * slot: op(u, v) (DIV: u/v then v/u).  If `rect` is 2, it adds the whole next
+ * level N_{L+1} of eq. feature-exp, numbered as every level above (unary
+ * block, then pairs v < u with u in N_L ordered by (u, v)) but not stored:
+ * its features are generated in registers like the slice's.
  *
  * Validity: a feature is invalid if an operand is invalid, a domain is
  * violated (sqrt of a negative, log of a non-positive, division by zero,
@@ -99,7 +102,8 @@ typedef enum {
 typedef struct {
     int32_t d;                         /* base features, >= 1                  */
     int32_t levels;                    /* full levels stored as pools, 1..2    */
-    int32_t rect;                      /* 1: add the one-sided next-level slice */
+    int32_t rect;                      /* 1: add the one-sided next-level slice;
+                                          2: add the whole next level (generated) */
     int32_t n_unary, n_binary;
     int32_t unary[SISSO_MAX_UNARY];    /* sisso_op codes 4..11, distinct       */
     int32_t binary[SISSO_MAX_BINARY];  /* sisso_op codes 0..3, distinct        */
@@ -125,8 +129,8 @@ typedef struct {
 } sisso_colstat;
 
 /* Validate a space and fill its derived fields [host].  Errors:
- * SISSO_E_NULL, SISSO_E_SHAPE (d < 1, levels outside 1..2, rect without a
- * level, operator lists too long or with wrong or repeated codes),
+ * SISSO_E_NULL, SISSO_E_SHAPE (d < 1, levels outside 1..2, rect outside
+ * 0..2, operator lists too long or with wrong or repeated codes),
  * SISSO_E_RANGE (total size overflows 2^62). */
 sisso_status sisso_space_init(sisso_space *space);
 
@@ -261,7 +265,8 @@ sisso_status sisso_expand_score(const sisso_space *space, const sisso_score_args
  *             errors near the cutoff (ties of regrouped sums, for instance).
  * [cand_begin, cand_end) must lie in the binary block of the slice.  The
  * recall of the band against the FP32 screening is measured by the tests.
- * Errors: as sisso_expand_score; SISSO_E_UNSUPPORTED without a slice. */
+ * Errors: as sisso_expand_score; SISSO_E_UNSUPPORTED without a one-sided
+ * slice (rect 1). */
 size_t sisso_bf16_operands_size(const sisso_space *space, int32_t n);
 sisso_status sisso_prepare_bf16(const sisso_space *space, const sisso_score_args *args, void *ops,
                                 size_t ops_bytes, void *stream);
@@ -336,13 +341,29 @@ sisso_status sisso_bf16_screen_moments(const sisso_space *space, const sisso_sco
 sisso_status sisso_topk(const void *ws, size_t ws_bytes, int32_t k, int64_t *out_ids,
                         float *out_scores, int32_t *out_count, void *stream);
 
+/* Threshold alternative of Sec. 2.2: instead of the best k, every screened
+ * candidate whose score is at least tau (0 <= tau <= 1), by (score desc, id
+ * asc), at most max_out of them (1..SISSO_MAX_BAND): out_ids / out_scores
+ * (device, max_out entries), *out_count (device) the number returned.  The
+ * per-block lists of the screening pass hold K' entries each, so the list is
+ * complete only if no block filled its list with candidates at or above tau:
+ * sisso_topk_status reports 4 when one did (screen again with a larger K'), 5
+ * when more than max_out candidates reach tau (the best max_out are
+ * returned).  A workspace filled by the BF16 form holds the rescored band
+ * only: its threshold list is complete for the candidates the band reached.
+ * Errors: SISSO_E_NULL, SISSO_E_RANGE (max_out or tau), SISSO_E_WORKSPACE. */
+sisso_status sisso_select_threshold(const void *ws, size_t ws_bytes, float tau, int32_t max_out,
+                                    int64_t *out_ids, float *out_scores, int32_t *out_count, void *stream);
+
 /* Outcome of the last sisso_topk on a workspace, copied on `stream` into
  * *out_status (device int32): 0 = exact result; 1 = more entries tie at the
  * k-th score than the gather buffer holds behind the entries above it (every
  * entry above the cutoff is still returned, and every returned score is
  * correct, but the tied entries returned need not be those of smallest id);
  * 2 = k was larger than the keep the workspace was filled with (nothing
- * returned).  A caller that needs the (score desc, id asc) order exactly
+ * returned); 3 = a BF16-form screen into this workspace could not keep every
+ * candidate it had to score exactly (the band may lack some); 4, 5: see
+ * sisso_select_threshold.  A caller that needs the (score desc, id asc) order exactly
  * checks it once the stream has passed the call.
  * Errors: SISSO_E_NULL, SISSO_E_WORKSPACE. */
 sisso_status sisso_topk_status(const void *ws, size_t ws_bytes, int32_t *out_status, void *stream);
@@ -508,7 +529,7 @@ sisso_status sisso_count_pass(const float *exact, const float *net, int32_t coun
  * and keep of args; sisso_topk merges).  *kept (device, nullable) is
  * increased by the number of candidates scored exactly.  Exact scores are
  * bit-identical to those of sisso_expand_score.  Errors: as
- * sisso_expand_score; SISSO_E_UNSUPPORTED without a slice. */
+ * sisso_expand_score; SISSO_E_UNSUPPORTED without a one-sided slice (rect 1). */
 int32_t sisso_expand_score_pruned_lists(const sisso_space *space, const sisso_score_args *args, int64_t cand_begin,
                                         int64_t cand_end);
 sisso_status sisso_expand_score_pruned(const sisso_space *space, const sisso_score_args *args, const float *Au,
@@ -527,10 +548,8 @@ sisso_status sisso_expand_score_pruned(const sisso_space *space, const sisso_sco
  * |corr| of its members; the best k classes (score desc, id asc) are
  * appended to the subspace (ids to sub_ids[m_prev..], columns to sub).
  * *n_new (device int32) receives the number appended (<= k) and *n_classes
- * the number of surviving classes.  If more than 2^20 pairs of the list and
- * subspace are duplicates, the classes cannot be formed: nothing is appended,
- * *n_new = 0 and *n_classes = -1 (the caller checks this once the stream has
- * passed the call).
+ * the number of surviving classes.  Any number of duplicate pairs is handled
+ * (the components are formed by union-find as the pairs are found).
  * Errors: SISSO_E_NULL, SISSO_E_SHAPE (m_prev + k > SISSO_MAX_SUBSPACE,
  * count > SISSO_MAX_KEEP). */
 size_t sisso_subspace_workspace_size(int32_t n, int32_t count, int32_t m_prev);
@@ -684,6 +703,37 @@ sisso_status sisso_l0_search_batched(const sisso_l0_problem *problems, int32_t n
 sisso_status sisso_sort_subspace(const double *src, int32_t lds, const int64_t *ids, int32_t m,
                                  int32_t n, double *dst, int32_t ldd, int64_t *ids_sorted,
                                  int32_t *perm_out, void *stream);
+
+/* ------------------------------------------------------- pre-screening
+ * Ranking of the base features before expansion, for problems with many
+ * primary features (Sec. 3.1, eq. mi-exact, and the initial screening option
+ * of Sec. 3.3 with its methods "mi" and "spearman").
+ *   SISSO_PRESCREEN_MI        mutual information of eq. mi-exact estimated by
+ *                             Gaussian kernel densities: x and y standardised
+ *                             (population sd), bandwidths h_k = (4 / (k + 2))^
+ *                             (1 / (k + 4)) n^(-1 / (k + 4)) (k = 1 for each
+ *                             marginal, k = 2 for the joint product kernel),
+ *                             the integral replaced by the mean over the n
+ *                             observations of log(p(x, y) / (p(x) p(y))) with
+ *                             every density the kernel average over all n
+ *                             observations; 0 for a constant column.
+ *   SISSO_PRESCREEN_SPEARMAN  |Pearson correlation| of the ranks (ties share
+ *                             their average rank); 0 for a constant column.
+ * sisso_prescreen_scores: X n x d FP64 (leading dim ldx), y n FP64, out d
+ * FP64 scores (device); ws of sisso_prescreen_workspace_size(n, d) bytes.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE (n < 2, d < 1, ldx < n), SISSO_E_RANGE
+ * (unknown method), SISSO_E_UNSUPPORTED (Spearman with n > 4096),
+ * SISSO_E_WORKSPACE.
+ * sisso_prescreen_select: the indices of the best ceil(quantile d) features by
+ * (score desc, index asc) into out_idx (device, that many int32), their number
+ * into *out_count (device).  Errors: SISSO_E_NULL, SISSO_E_SHAPE (d outside
+ * 1..8192), SISSO_E_RANGE (quantile outside (0, 1]). */
+typedef enum { SISSO_PRESCREEN_MI = 0, SISSO_PRESCREEN_SPEARMAN = 1 } sisso_prescreen_method;
+size_t sisso_prescreen_workspace_size(int32_t n, int32_t d);
+sisso_status sisso_prescreen_scores(const double *X, int32_t n, int32_t ldx, int32_t d, const double *y,
+                                    int32_t method, double *out, void *ws, size_t ws_bytes, void *stream);
+sisso_status sisso_prescreen_select(const double *scores, int32_t d, double quantile, int32_t *out_idx,
+                                    int32_t *out_count, void *stream);
 
 /* Human-readable name of a status. */
 const char *sisso_status_string(sisso_status status);

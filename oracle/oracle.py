@@ -79,6 +79,25 @@ def lib():
         L.or_fit.restype = ctypes.c_int
         L.or_fit.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
                              ctypes.c_int, ctypes.c_int64, ctypes.POINTER(_Step)]
+        L.or_abs_corr_w.restype = ctypes.c_double
+        L.or_abs_corr_w.argtypes = [_dp, _dp, _dp, ctypes.c_int]
+        L.or_score_range_w.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                       ctypes.c_int64, ctypes.c_int64, _dp]
+        L.or_sis_w.restype = ctypes.c_int64
+        L.or_sis_w.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                               ctypes.c_int64, ctypes.c_int64, _i64p, ctypes.c_int64,
+                               ctypes.c_int64, _i64p, _dp]
+        L.or_dup_components_w.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp, _i64p]
+        L.or_dedup_w.restype = ctypes.c_int64
+        L.or_dedup_w.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, _dp, _i64p, _dp,
+                                 ctypes.c_int64, _i64p, ctypes.c_int64, ctypes.c_int64,
+                                 _i64p, _dp, _i64p]
+        L.or_l0_w.restype = ctypes.c_int
+        L.or_l0_w.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp, _dp, ctypes.c_int,
+                              _i64p, _dp, _dp, _dp, _i64p, _i64p]
+        L.or_fit_w.restype = ctypes.c_int
+        L.or_fit_w.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_int64, ctypes.POINTER(_Step)]
         L.or_step_size.restype = ctypes.c_int
         assert L.or_step_size() == ctypes.sizeof(_Step)
         _lib = L
@@ -87,6 +106,18 @@ def lib():
 
 def _p(a, t):
     return a.ctypes.data_as(t)
+
+
+def _wp(w, n: int):
+    """Sample weights (Sec. 2.4: w_s = 1 / sigma_s^2 for a diagonal noise
+    covariance) as a C pointer, or NULL for the unweighted method; the array
+    is returned too so that it outlives the call."""
+    if w is None:
+        return None, None
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    if w.shape != (n,) or not np.all(np.isfinite(w)) or np.any(w <= 0.0):
+        raise ValueError("oracle: weights must be n positive finite values")
+    return w, _p(w, _dp)
 
 
 def _colmajor(X: np.ndarray) -> np.ndarray:
@@ -139,52 +170,57 @@ class Space:
                            _p(valid, _i32p))
         return out.T.copy(), valid.astype(bool)
 
-    def score_range(self, X, r, begin: int, end: int) -> np.ndarray:
+    def score_range(self, X, r, begin: int, end: int, w=None) -> np.ndarray:
         Xc = _colmajor(X)
         r = np.ascontiguousarray(r, dtype=np.float64)
         out = np.empty(end - begin, dtype=np.float64)
-        lib().or_score_range(self._h, _p(Xc, _dp), X.shape[0], X.shape[0], _p(r, _dp), begin,
-                             end, _p(out, _dp))
+        w, wp = _wp(w, X.shape[0])
+        lib().or_score_range_w(self._h, _p(Xc, _dp), X.shape[0], X.shape[0], _p(r, _dp), wp, begin,
+                               end, _p(out, _dp))
         return out
 
     def sis(self, X, r, keep: int, exclude: Sequence[int] = (), begin: int = 0,
-            end: int | None = None):
+            end: int | None = None, w=None):
         Xc = _colmajor(X)
         r = np.ascontiguousarray(r, dtype=np.float64)
         ex = np.ascontiguousarray(np.asarray(list(exclude) or [0], dtype=np.int64))
         ids = np.empty(max(keep, 1), dtype=np.int64)
         sc = np.empty(max(keep, 1), dtype=np.float64)
         end = self.total if end is None else end
-        c = lib().or_sis(self._h, _p(Xc, _dp), X.shape[0], X.shape[0], _p(r, _dp), begin, end,
-                         _p(ex, _i64p), len(exclude), keep, _p(ids, _i64p), _p(sc, _dp))
+        w, wp = _wp(w, X.shape[0])
+        c = lib().or_sis_w(self._h, _p(Xc, _dp), X.shape[0], X.shape[0], _p(r, _dp), wp, begin, end,
+                           _p(ex, _i64p), len(exclude), keep, _p(ids, _i64p), _p(sc, _dp))
         return ids[:c].copy(), sc[:c].copy()
 
-    def dedup(self, X, list_ids, list_scores, prev: Sequence[int], k: int):
+    def dedup(self, X, list_ids, list_scores, prev: Sequence[int], k: int, w=None):
         Xc = _colmajor(X)
+        w, wp = _wp(w, X.shape[0])
         li = np.ascontiguousarray(np.asarray(list_ids, dtype=np.int64))
         ls = np.ascontiguousarray(np.asarray(list_scores, dtype=np.float64))
         pv = np.ascontiguousarray(np.asarray(list(prev) or [0], dtype=np.int64))
         oi = np.empty(max(k, 1), dtype=np.int64)
         os_ = np.empty(max(k, 1), dtype=np.float64)
         ncls = ctypes.c_int64()
-        c = lib().or_dedup(self._h, _p(Xc, _dp), X.shape[0], X.shape[0], _p(li, _i64p),
-                           _p(ls, _dp), len(li), _p(pv, _i64p), len(prev), k, _p(oi, _i64p),
-                           _p(os_, _dp), ctypes.byref(ncls))
+        c = lib().or_dedup_w(self._h, _p(Xc, _dp), X.shape[0], X.shape[0], wp, _p(li, _i64p),
+                             _p(ls, _dp), len(li), _p(pv, _i64p), len(prev), k, _p(oi, _i64p),
+                             _p(os_, _dp), ctypes.byref(ncls))
         return oi[:c].copy(), os_[:c].copy(), ncls.value
 
 
-def abs_corr(f, r) -> float:
+def abs_corr(f, r, w=None) -> float:
     f = np.ascontiguousarray(f, dtype=np.float64)
     r = np.ascontiguousarray(r, dtype=np.float64)
-    return float(lib().or_abs_corr(_p(f, _dp), _p(r, _dp), len(f)))
+    w, wp = _wp(w, len(f))
+    return float(lib().or_abs_corr_w(_p(f, _dp), _p(r, _dp), wp, len(f)))
 
 
-def dup_components(F: np.ndarray) -> np.ndarray:
+def dup_components(F: np.ndarray, w=None) -> np.ndarray:
     """F: n x m FP64; returns the component label (min member index) per column."""
     Fc = np.ascontiguousarray(np.asarray(F, dtype=np.float64).T)
     m = Fc.shape[0]
     comp = np.empty(max(m, 1), dtype=np.int64)
-    lib().or_dup_components(_p(Fc, _dp), F.shape[0], F.shape[0], m, _p(comp, _i64p))
+    w, wp = _wp(w, F.shape[0])
+    lib().or_dup_components_w(_p(Fc, _dp), F.shape[0], F.shape[0], m, wp, _p(comp, _i64p))
     return comp[:m]
 
 
@@ -199,9 +235,10 @@ class L0Result:
     status: int
 
 
-def l0(F: np.ndarray, y: np.ndarray, D: int) -> L0Result:
+def l0(F: np.ndarray, y: np.ndarray, D: int, w=None) -> L0Result:
     """Exhaustive D-term least squares over the columns of F (n x m), whose
-    order must be ascending in feature id."""
+    order must be ascending in feature id; weighted least squares (the SSE is
+    sum_s w_s e_s^2) when sample weights w are given."""
     Fc = np.ascontiguousarray(np.asarray(F, dtype=np.float64).T)
     n, m = F.shape
     y = np.ascontiguousarray(y, dtype=np.float64)
@@ -209,8 +246,9 @@ def l0(F: np.ndarray, y: np.ndarray, D: int) -> L0Result:
     sse = ctypes.c_double(); ru = ctypes.c_double()
     coef = np.zeros(9, dtype=np.float64)
     nt = ctypes.c_int64(); ns = ctypes.c_int64()
-    st = lib().or_l0(_p(Fc, _dp), n, n, m, _p(y, _dp), D, _p(best, _i64p), ctypes.byref(sse),
-                     ctypes.byref(ru), _p(coef, _dp), ctypes.byref(nt), ctypes.byref(ns))
+    w, wp = _wp(w, n)
+    st = lib().or_l0_w(_p(Fc, _dp), n, n, m, _p(y, _dp), wp, D, _p(best, _i64p), ctypes.byref(sse),
+                       ctypes.byref(ru), _p(coef, _dp), ctypes.byref(nt), ctypes.byref(ns))
     return L0Result(best[:D].copy(), sse.value, ru.value, coef[:D + 1].copy(), nt.value,
                     ns.value, st)
 
@@ -232,15 +270,18 @@ class StepResult:
 
 
 def fit(X: np.ndarray, y: np.ndarray, unary, binary, levels: int, rect: bool, k: int,
-        dmax: int, keep0: int | None = None) -> List[StepResult]:
-    """Oracle SISSO fit; one StepResult per dimension t = 1..dmax."""
+        dmax: int, keep0: int | None = None, w=None) -> List[StepResult]:
+    """Oracle SISSO fit; one StepResult per dimension t = 1..dmax (weighted
+    screening, duplicate classes and least squares when sample weights w are
+    given)."""
     sp = Space(X.shape[1], unary, binary, levels, rect)
     Xc = _colmajor(X)
     y = np.ascontiguousarray(y, dtype=np.float64)
     steps = (_Step * dmax)()
     keep0 = 2 * k if keep0 is None else keep0
-    done = lib().or_fit(sp._h, _p(Xc, _dp), X.shape[0], X.shape[0], _p(y, _dp), k, dmax, keep0,
-                        steps)
+    w, wp = _wp(w, X.shape[0])
+    done = lib().or_fit_w(sp._h, _p(Xc, _dp), X.shape[0], X.shape[0], _p(y, _dp), wp, k, dmax, keep0,
+                          steps)
     out = []
     for t in range(done):
         s = steps[t]
@@ -248,4 +289,31 @@ def fit(X: np.ndarray, y: np.ndarray, unary, binary, levels: int, rect: bool, k:
                               np.array(s.sub_ids[:s.n_sub]), np.array(s.best_ids[:t + 1]),
                               np.array(s.coef[:t + 2]), s.sse, s.runner_up, s.rmse, s.r2,
                               s.n_tuples, s.n_singular, s.status))
+    return out
+
+
+def fit_threshold(X: np.ndarray, y: np.ndarray, unary, binary, levels: int, rect, tau: float, keep: int,
+                  k: int, dmax: int):
+    """Oracle SISSO fit with Sec. 2.2's threshold alternative: each pass keeps
+    every candidate whose |corr| with the residual is at least tau (searched
+    among the best `keep`), forms their duplicate classes against S_{t-1} and
+    appends at most k of them; the SO of Sec. 2.3 then fits y on S_t.  Built
+    from the oracle's own screening, duplicate-class and l0 functions.
+    Returns per t: (appended ids, S_t, best ids, SSE)."""
+    sp = Space(X.shape[1], unary, binary, levels, rect)
+    r = np.asarray(y, dtype=np.float64).copy()
+    sub: List[int] = []
+    out = []
+    for t in range(1, dmax + 1):
+        ids, sc = sp.sis(X, r, keep, exclude=sorted(sub))
+        sel = sc >= tau
+        new, nsc, _ = sp.dedup(X, ids[sel], sc[sel], sub, k)
+        sub.extend(int(i) for i in new)
+        srt = np.array(sorted(sub), dtype=np.int64)
+        F, ok = sp.eval(X, srt)
+        res = l0(F, y, t)
+        best = srt[res.best]
+        A = np.column_stack([np.ones(len(y)), F[:, res.best]])
+        r = y - A @ res.coef
+        out.append((np.array(new), np.array(sub), best, res.sse))
     return out

@@ -28,10 +28,13 @@
  *     then for each unordered pair (i < j) with j new at level l-1, ordered by
  *     (j, i), each binary slot.  Slots: ADD, SUB, MUL give op(P[j], P[i]);
  *     DIV gives P[j]/P[i] then P[i]/P[j].
- *   - one-sided next-level slice (used at rung 3): after the last pool level
- *     L, for each u new at level L: each unary op of u; then for each u new
- *     at level L, each v in P_{L-1}, each binary slot: op(u, v) (DIV: u/v,
- *     v/u).
+ *   - one-sided next-level slice (used at rung 3, rect = 1): after the last
+ *     pool level L, for each u new at level L: each unary op of u; then for
+ *     each u new at level L, each v in P_{L-1}, each binary slot: op(u, v)
+ *     (DIV: u/v, v/u).
+ *   - the whole next level (rect = 2): level L + 1 numbered as every TRI
+ *     level, without stored tables (its ids are decoded by searching the pair
+ *     counts), so that a rung-3 space of 10^13 features can be sliced.
  *   - validity: a feature is invalid if an operand is invalid, a domain is
  *     violated (sqrt of a negative, log of a non-positive, division by zero,
  *     1/0), a value is non-finite or exceeds 1e15 in magnitude, the feature
@@ -45,6 +48,11 @@
  *     the screened list plus the previous subspace; representative = min id,
  *     class score = max member score; classes touching the previous subspace
  *     are dropped.
+ *   - per-sample weights (optional; Sec. 2.4's whitening for noise with a
+ *     known diagonal covariance, w_s = 1 / sigma_s^2, the intercept whitened
+ *     with the features): every mean, variance and covariance is the
+ *     weighted one (sum_s w_s (.)), so the score is the weighted |corr| and
+ *     SO is weighted least squares; unit weights give the plain method.
  *   - SO fits y (not the residual) with an intercept that is not counted in
  *     the t terms; eq. residual is read with an inverse (normal equations);
  *     a tuple is rank deficient when a Gaussian-elimination pivot of the unit-
@@ -93,7 +101,7 @@ or_space *or_space_new(int d, const int *unary, int n_unary, const int *binary, 
                        int levels, int rect)
 {
     if (d < 1 || levels < 0 || levels > OR_MAX_LEVELS || n_unary < 0 || n_unary > 16 ||
-        n_binary < 0 || n_binary > 8 || (rect && levels < 1))
+        n_binary < 0 || n_binary > 8 || (rect && levels < 1) || rect < 0 || rect > 2)
         return NULL;
     or_space *s = (or_space *)calloc(1, sizeof(or_space));
     s->d = d; s->n_unary = n_unary; s->n_binary = n_binary; s->levels = levels; s->rect = rect;
@@ -141,7 +149,13 @@ or_space *or_space_new(int d, const int *unary, int n_unary, const int *binary, 
     if (rect) {
         int64_t nlast = s->p[levels] - s->p[levels - 1];
         s->rect_unary = (int64_t)n_unary * nlast;
-        s->rect_binary = (int64_t)s->n_slots * nlast * s->p[levels - 1];
+        if (rect == 1) {
+            s->rect_binary = (int64_t)s->n_slots * nlast * s->p[levels - 1];
+        } else {                       /* pairs i < j with j new at level L */
+            int64_t pairs = 0;
+            for (int64_t j = s->p[levels - 1]; j < s->p[levels]; j++) pairs += j;
+            s->rect_binary = (int64_t)s->n_slots * pairs;
+        }
         s->total += s->rect_unary + s->rect_binary;
     }
     return s;
@@ -165,7 +179,21 @@ int or_decode(const or_space *s, int64_t id, int32_t *op, int64_t *left, int64_t
     loc -= s->rect_unary;
     int sl = (int)(loc % s->n_slots);
     int64_t pair = loc / s->n_slots;
-    int64_t u = lo + pair / lo, v = pair % lo;   /* v in P_{L-1} = [0, lo) */
+    int64_t u, v;
+    if (s->rect == 1) {
+        u = lo + pair / lo; v = pair % lo;       /* v in P_{L-1} = [0, lo) */
+    } else {
+        /* pairs (j, i), i < j, j from lo upwards: j is the largest index whose
+           first pair number (the pairs of all smaller j) is <= pair; found by
+           bisection on that count */
+        int64_t a = lo, b = s->p[s->levels] - 1;
+        while (a < b) {
+            int64_t m = a + (b - a + 1) / 2;
+            int64_t first = (m * (m - 1) - lo * (lo - 1)) / 2;
+            if (first <= pair) a = m; else b = m - 1;
+        }
+        u = a; v = pair - (a * (a - 1) - lo * (lo - 1)) / 2;
+    }
     *op = s->slot_op[sl];
     if (s->slot_rev[sl]) { *left = v; *right = u; } else { *left = u; *right = v; }
     return 0;
@@ -270,31 +298,44 @@ void or_eval_many(const or_space *s, const double *X, int n, int ldx, const int6
     }
 }
 
-/* |Pearson correlation| by the two-pass definition. */
-double or_abs_corr(const double *f, const double *r, int n)
+/* |Pearson correlation| by the two-pass definition, with sample weights w
+ * (NULL: all 1): weighted means, then weighted sums of squares and products. */
+double or_abs_corr_w(const double *f, const double *r, const double *w, int n)
 {
-    double mf = 0.0, mr = 0.0;
-    for (int s = 0; s < n; s++) { mf += f[s]; mr += r[s]; }
-    mf /= n; mr /= n;
+    double mf = 0.0, mr = 0.0, sw = 0.0;
+    for (int s = 0; s < n; s++) {
+        double ws = w ? w[s] : 1.0;
+        mf += ws * f[s]; mr += ws * r[s]; sw += ws;
+    }
+    mf /= sw; mr /= sw;
     double sff = 0.0, srr = 0.0, sfr = 0.0;
     for (int s = 0; s < n; s++) {
+        double ws = w ? w[s] : 1.0;
         double a = f[s] - mf, b = r[s] - mr;
-        sff += a * a; srr += b * b; sfr += a * b;
+        sff += ws * a * a; srr += ws * b * b; sfr += ws * a * b;
     }
     if (sff <= 0.0 || srr <= 0.0) return NAN;
     return fabs(sfr) / sqrt(sff * srr);
 }
 
+double or_abs_corr(const double *f, const double *r, int n) { return or_abs_corr_w(f, r, NULL, n); }
+
 /* Scores for every id in [begin, end): NaN for invalid features. */
-void or_score_range(const or_space *s, const double *X, int n, int ldx, const double *r,
-                    int64_t begin, int64_t end, double *scores)
+void or_score_range_w(const or_space *s, const double *X, int n, int ldx, const double *r, const double *w,
+                      int64_t begin, int64_t end, double *scores)
 {
     double *f = (double *)malloc(sizeof(double) * n);
     for (int64_t id = begin; id < end; id++) {
-        if (eval_rec(s, X, n, ldx, id, f)) scores[id - begin] = or_abs_corr(f, r, n);
+        if (eval_rec(s, X, n, ldx, id, f)) scores[id - begin] = or_abs_corr_w(f, r, w, n);
         else scores[id - begin] = NAN;
     }
     free(f);
+}
+
+void or_score_range(const or_space *s, const double *X, int n, int ldx, const double *r,
+                    int64_t begin, int64_t end, double *scores)
+{
+    or_score_range_w(s, X, n, ldx, r, NULL, begin, end, scores);
 }
 
 /* ------------------------------------------------------------------ SIS */
@@ -319,9 +360,9 @@ static int cmp_i64(const void *a, const void *b)
 
 /* Best `keep` valid features over [begin, end) by (score desc, id asc),
  * skipping excluded ids.  Returns the number kept (<= keep), sorted. */
-int64_t or_sis(const or_space *s, const double *X, int n, int ldx, const double *r,
-               int64_t begin, int64_t end, const int64_t *exclude, int64_t n_exclude,
-               int64_t keep, int64_t *out_ids, double *out_scores)
+int64_t or_sis_w(const or_space *s, const double *X, int n, int ldx, const double *r, const double *w,
+                 int64_t begin, int64_t end, const int64_t *exclude, int64_t n_exclude,
+                 int64_t keep, int64_t *out_ids, double *out_scores)
 {
     int64_t *ex = (int64_t *)malloc(sizeof(int64_t) * (n_exclude > 0 ? n_exclude : 1));
     if (n_exclude > 0) memcpy(ex, exclude, sizeof(int64_t) * n_exclude);
@@ -331,7 +372,7 @@ int64_t or_sis(const or_space *s, const double *X, int n, int ldx, const double 
     for (int64_t id = begin; id < end; id++) {
         if (n_exclude > 0 && in_sorted(ex, n_exclude, id)) continue;
         if (!eval_rec(s, X, n, ldx, id, f)) continue;
-        double sc = or_abs_corr(f, r, n);
+        double sc = or_abs_corr_w(f, r, w, n);
         if (isnan(sc)) continue;
         if (cnt < keep) {
             out_ids[cnt] = id; out_scores[cnt] = sc; cnt++;
@@ -359,6 +400,13 @@ int64_t or_sis(const or_space *s, const double *X, int n, int ldx, const double 
     return cnt;
 }
 
+int64_t or_sis(const or_space *s, const double *X, int n, int ldx, const double *r,
+               int64_t begin, int64_t end, const int64_t *exclude, int64_t n_exclude,
+               int64_t keep, int64_t *out_ids, double *out_scores)
+{
+    return or_sis_w(s, X, n, ldx, r, NULL, begin, end, exclude, n_exclude, keep, out_ids, out_scores);
+}
+
 /* ---------------------------------------------------------------- dedup */
 
 static int64_t uf_find(int64_t *par, int64_t a)
@@ -370,13 +418,13 @@ static int64_t uf_find(int64_t *par, int64_t a)
 /* Duplicate classes over m columns F (n x m, leading dim ldf): connected
  * components of 1 - |corr| <= 1e-9.  comp[i] = smallest column index of
  * the component of column i. */
-void or_dup_components(const double *F, int n, int ldf, int64_t m, int64_t *comp)
+void or_dup_components_w(const double *F, int n, int ldf, int64_t m, const double *w, int64_t *comp)
 {
     int64_t *par = (int64_t *)malloc(sizeof(int64_t) * (m > 0 ? m : 1));
     for (int64_t i = 0; i < m; i++) par[i] = i;
     for (int64_t i = 0; i < m; i++)
         for (int64_t j = i + 1; j < m; j++) {
-            double c = or_abs_corr(F + (size_t)i * ldf, F + (size_t)j * ldf, n);
+            double c = or_abs_corr_w(F + (size_t)i * ldf, F + (size_t)j * ldf, w, n);
             if (1.0 - c <= DUP_TOL) {
                 int64_t a = uf_find(par, i), b = uf_find(par, j);
                 if (a != b) { if (a < b) par[b] = a; else par[a] = b; }
@@ -386,14 +434,19 @@ void or_dup_components(const double *F, int n, int ldf, int64_t m, int64_t *comp
     free(par);
 }
 
+void or_dup_components(const double *F, int n, int ldf, int64_t m, int64_t *comp)
+{
+    or_dup_components_w(F, n, ldf, m, NULL, comp);
+}
+
 /* New subspace members from a screened list.
  *   list: ids/scores (count), prev: previous subspace ids (n_prev).
  * Writes up to k representatives (ids, class scores) in rank order and
  * returns how many.  *n_classes gets the number of surviving classes. */
-int64_t or_dedup(const or_space *s, const double *X, int n, int ldx,
-                 const int64_t *list_ids, const double *list_scores, int64_t count,
-                 const int64_t *prev, int64_t n_prev, int64_t k,
-                 int64_t *out_ids, double *out_scores, int64_t *n_classes)
+int64_t or_dedup_w(const or_space *s, const double *X, int n, int ldx, const double *w,
+                   const int64_t *list_ids, const double *list_scores, int64_t count,
+                   const int64_t *prev, int64_t n_prev, int64_t k,
+                   int64_t *out_ids, double *out_scores, int64_t *n_classes)
 {
     int64_t m = count + n_prev;
     double *F = (double *)malloc(sizeof(double) * (size_t)n * (m > 0 ? m : 1));
@@ -403,7 +456,7 @@ int64_t or_dedup(const or_space *s, const double *X, int n, int ldx,
     for (int64_t i = 0; i < count; i++) ids[n_prev + i] = list_ids[i];
     or_eval_many(s, X, n, ldx, ids, m, F, n, valid);
     int64_t *comp = (int64_t *)malloc(sizeof(int64_t) * (m > 0 ? m : 1));
-    or_dup_components(F, n, n, m, comp);
+    or_dup_components_w(F, n, n, m, w, comp);
     /* per component: excluded?, representative id, class score */
     int64_t *rep = (int64_t *)malloc(sizeof(int64_t) * (m > 0 ? m : 1));
     double *csc = (double *)malloc(sizeof(double) * (m > 0 ? m : 1));
@@ -432,6 +485,15 @@ int64_t or_dedup(const or_space *s, const double *X, int n, int ldx,
     *n_classes = nc;
     free(F); free(valid); free(ids); free(comp); free(rep); free(csc); free(excl); free(cls);
     return take;
+}
+
+int64_t or_dedup(const or_space *s, const double *X, int n, int ldx,
+                 const int64_t *list_ids, const double *list_scores, int64_t count,
+                 const int64_t *prev, int64_t n_prev, int64_t k,
+                 int64_t *out_ids, double *out_scores, int64_t *n_classes)
+{
+    return or_dedup_w(s, X, n, ldx, NULL, list_ids, list_scores, count, prev, n_prev, k, out_ids, out_scores,
+                      n_classes);
 }
 
 /* ------------------------------------------------------------------- SO */
@@ -504,31 +566,32 @@ static int next_comb(int64_t *t, int D, int64_t m)
  * Outputs: best tuple (positions), its SSE, the runner-up SSE (best SSE over
  * the other tuples), coefficients (intercept first), and counts.
  * Returns 0 on success, 1 if every tuple is rank deficient. */
-int or_l0(const double *F, int n, int ldf, int64_t m, const double *y, int D,
-          int64_t *best, double *best_sse, double *runner_up, double *coef,
-          int64_t *n_tuples, int64_t *n_singular)
+int or_l0_w(const double *F, int n, int ldf, int64_t m, const double *y, const double *w, int D,
+            int64_t *best, double *best_sse, double *runner_up, double *coef,
+            int64_t *n_tuples, int64_t *n_singular)
 {
     if (D < 1 || D > 8 || m < D) return 2;
-    double ym = 0.0;
-    for (int s = 0; s < n; s++) ym += y[s];
-    ym /= n;
+    double ym = 0.0, sw = 0.0;
+    for (int s = 0; s < n; s++) { double ws = w ? w[s] : 1.0; ym += ws * y[s]; sw += ws; }
+    ym /= sw;
     double *mu = (double *)malloc(sizeof(double) * m);
     for (int64_t i = 0; i < m; i++) {
         double a = 0.0;
-        for (int s = 0; s < n; s++) a += F[(size_t)i * ldf + s];
-        mu[i] = a / n;
+        for (int s = 0; s < n; s++) a += (w ? w[s] : 1.0) * F[(size_t)i * ldf + s];
+        mu[i] = a / sw;
     }
     double syy = 0.0;
-    for (int s = 0; s < n; s++) syy += (y[s] - ym) * (y[s] - ym);
+    for (int s = 0; s < n; s++) syy += (w ? w[s] : 1.0) * (y[s] - ym) * (y[s] - ym);
     double *G = (double *)malloc(sizeof(double) * m * m);
     double *bv = (double *)malloc(sizeof(double) * m);
     for (int64_t i = 0; i < m; i++) {
         double bb = 0.0;
-        for (int s = 0; s < n; s++) bb += (F[(size_t)i * ldf + s] - mu[i]) * (y[s] - ym);
+        for (int s = 0; s < n; s++) bb += (w ? w[s] : 1.0) * (F[(size_t)i * ldf + s] - mu[i]) * (y[s] - ym);
         bv[i] = bb;
         for (int64_t j = 0; j <= i; j++) {
             double g = 0.0;
-            for (int s = 0; s < n; s++) g += (F[(size_t)i * ldf + s] - mu[i]) * (F[(size_t)j * ldf + s] - mu[j]);
+            for (int s = 0; s < n; s++)
+                g += (w ? w[s] : 1.0) * (F[(size_t)i * ldf + s] - mu[i]) * (F[(size_t)j * ldf + s] - mu[j]);
             G[i * m + j] = g; G[j * m + i] = g;
         }
     }
@@ -564,6 +627,13 @@ int or_l0(const double *F, int n, int ldf, int64_t m, const double *y, int D,
     return 0;
 }
 
+int or_l0(const double *F, int n, int ldf, int64_t m, const double *y, int D,
+          int64_t *best, double *best_sse, double *runner_up, double *coef,
+          int64_t *n_tuples, int64_t *n_singular)
+{
+    return or_l0_w(F, n, ldf, m, y, NULL, D, best, best_sse, runner_up, coef, n_tuples, n_singular);
+}
+
 /* --------------------------------------------------------------- driver */
 
 /* Residual of a fitted model: r = y - (c0 + sum c_a F[:, tup[a]]). */
@@ -594,8 +664,8 @@ typedef struct {
  * size (k + slack); the slack doubles while duplicate removal leaves fewer
  * than k classes and the space is not exhausted.  Writes one or_step per t.
  * Returns the number of completed steps. */
-int or_fit(const or_space *s, const double *X, int n, int ldx, const double *y, int k, int dmax,
-           int64_t keep0, or_step *steps)
+int or_fit_w(const or_space *s, const double *X, int n, int ldx, const double *y, const double *w, int k,
+             int dmax, int64_t keep0, or_step *steps)
 {
     double *r = (double *)malloc(sizeof(double) * n);
     memcpy(r, y, sizeof(double) * n);
@@ -610,8 +680,8 @@ int or_fit(const or_space *s, const double *X, int n, int ldx, const double *y, 
         for (;;) {
             lids = (int64_t *)realloc(lids, sizeof(int64_t) * keep);
             lsc = (double *)realloc(lsc, sizeof(double) * keep);
-            cnt = or_sis(s, X, n, ldx, r, 0, s->total, sub, nsub, keep, lids, lsc);
-            nnew = or_dedup(s, X, n, ldx, lids, lsc, cnt, sub, nsub, k, newids, newsc, &ncls);
+            cnt = or_sis_w(s, X, n, ldx, r, w, 0, s->total, sub, nsub, keep, lids, lsc);
+            nnew = or_dedup_w(s, X, n, ldx, w, lids, lsc, cnt, sub, nsub, k, newids, newsc, &ncls);
             if (nnew >= k || cnt < keep || keep >= 4096) break;
             keep *= 2;
             if (keep > 4096) keep = 4096;
@@ -631,22 +701,31 @@ int or_fit(const or_space *s, const double *X, int n, int ldx, const double *y, 
         int32_t *valid = (int32_t *)malloc(sizeof(int32_t) * nsub);
         or_eval_many(s, X, n, ldx, sorted, nsub, F, n, valid);
         int64_t bt[8];
-        int rc = or_l0(F, n, n, nsub, y, t, bt, &st->sse, &st->runner_up, st->coef,
-                       &st->n_tuples, &st->n_singular);
+        int rc = or_l0_w(F, n, n, nsub, y, w, t, bt, &st->sse, &st->runner_up, st->coef,
+                         &st->n_tuples, &st->n_singular);
         if (rc) { st->status = 4; free(F); free(valid); break; }
         for (int a = 0; a < t; a++) st->best_ids[a] = sorted[bt[a]];
         or_residual(F, n, n, bt, t, st->coef, y, r);
-        double ss = 0.0, ym = 0.0, syy = 0.0;
-        for (int q = 0; q < n; q++) { ss += r[q] * r[q]; ym += y[q]; }
-        ym /= n;
-        for (int q = 0; q < n; q++) syy += (y[q] - ym) * (y[q] - ym);
-        st->rmse = sqrt(ss / n);
+        double ss = 0.0, ym = 0.0, syy = 0.0, sw = 0.0;
+        for (int q = 0; q < n; q++) {
+            double wq = w ? w[q] : 1.0;
+            ss += wq * r[q] * r[q]; ym += wq * y[q]; sw += wq;
+        }
+        ym /= sw;
+        for (int q = 0; q < n; q++) syy += (w ? w[q] : 1.0) * (y[q] - ym) * (y[q] - ym);
+        st->rmse = sqrt(ss / sw);
         st->r2 = 1.0 - st->sse / syy;
         free(F); free(valid);
         done = t;
     }
     free(r);
     return done;
+}
+
+int or_fit(const or_space *s, const double *X, int n, int ldx, const double *y, int k, int dmax,
+           int64_t keep0, or_step *steps)
+{
+    return or_fit_w(s, X, n, ldx, y, NULL, k, dmax, keep0, steps);
 }
 
 int or_step_size(void) { return (int)sizeof(or_step); }

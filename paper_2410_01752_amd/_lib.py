@@ -27,6 +27,7 @@ ENC, MLP_IN, MLP_HIDDEN = 64, 144, 256
 MLP_PARAMS = 256 * 144 + 256 + 256 + 1
 MLP_TABLES = 5 * 256 + 256 + 1
 FP32, BF16 = 0, 1
+PRESCREEN = {"mi": 0, "spearman": 1}
 
 
 class SissoError(RuntimeError):
@@ -144,6 +145,7 @@ def lib():
         "sisso_expand_score_lists": (_i32, [sp, ap, _i64, _i64]),
         "sisso_topk": (_i32, [_vp, _sz, _i32, _vp, _vp, _vp, _vp]),
         "sisso_topk_status": (_i32, [_vp, _sz, _vp, _vp]),
+        "sisso_select_threshold": (_i32, [_vp, _sz, ctypes.c_float, _i32, _vp, _vp, _vp, _vp]),
         "sisso_subspace_workspace_size": (_sz, [_i32, _i32, _i32]),
         "sisso_subspace_update": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp,
                                          _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
@@ -183,6 +185,9 @@ def lib():
         "sisso_expand_score_pruned_lists": (_i32, [sp, ap, _i64, _i64]),
         "sisso_count_pass": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
         "sisso_expand_score_pruned": (_i32, [sp, ap, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _sz, _vp, _vp]),
+        "sisso_prescreen_workspace_size": (_sz, [_i32, _i32]),
+        "sisso_prescreen_scores": (_i32, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp]),
+        "sisso_prescreen_select": (_i32, [_vp, _i32, ctypes.c_double, _vp, _vp, _vp]),
         "sisso_status_string": (ctypes.c_char_p, [_i32]),
         "sisso_version": (ctypes.c_char_p, []),
     }
@@ -196,7 +201,7 @@ def lib():
 
 EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "sisso_materialize_ids",
             "sisso_prepare_residual", "sisso_score_workspace_size", "sisso_score_reset",
-            "sisso_expand_score", "sisso_expand_score_lists", "sisso_topk", "sisso_topk_status",
+            "sisso_expand_score", "sisso_expand_score_lists", "sisso_topk", "sisso_topk_status", "sisso_select_threshold",
             "sisso_subspace_workspace_size",
             "sisso_subspace_update", "sisso_l0_workspace_size", "sisso_l0_search", "sisso_l0_outcome",
             "sisso_l0_scratch_capacity", "sisso_l0_search_noalloc",
@@ -211,6 +216,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_score_ids", "sisso_mlp_forward", "sisso_mlp_workspace_size", "sisso_mlp_backward",
             "sisso_mlp_target", "sisso_adam_step", "sisso_mlp_parts", "sisso_mlp_tables", "sisso_mlp_score_ids", "sisso_select_kth",
             "sisso_expand_score_pruned_lists", "sisso_expand_score_pruned", "sisso_count_pass",
+            "sisso_prescreen_workspace_size", "sisso_prescreen_scores", "sisso_prescreen_select",
             "sisso_status_string", "sisso_version"]
 
 

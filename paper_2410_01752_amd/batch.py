@@ -192,8 +192,6 @@ class Batch:
                 if np.any(uv != 0):
                     raise L.SissoError(f"batched materialise / subspace update: entry status {uv.tolist()}")
                 nxt = []
-                if np.any(v[:, 1] < 0):
-                    raise L.SissoError("batched subspace update: more duplicate pairs than the edge list holds")
                 for j, p in enumerate(todo):
                     nn, nc, ct = int(v[j, 0]), int(v[j, 1]), int(cv[j])
                     upd[p] = (nn, nc, ct)

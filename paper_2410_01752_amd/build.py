@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsisso.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["capi.hip", "materialize.hip", "score.hip", "bf16.hip", "bf16_mfma.hip", "batched.hip", "learned.hip",
-           "subspace.hip", "l0.hip"]
+           "subspace.hip", "l0.hip", "prescreen.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -7,7 +7,7 @@ using namespace sisso;
 extern "C" sisso_status sisso_space_init(sisso_space *s)
 {
     if (!s) return SISSO_E_NULL;
-    if (s->d < 1 || s->levels < 1 || s->levels > SISSO_MAX_LEVELS || (s->rect != 0 && s->rect != 1))
+    if (s->d < 1 || s->levels < 1 || s->levels > SISSO_MAX_LEVELS || s->rect < 0 || s->rect > 2)
         return SISSO_E_SHAPE;
     if (s->n_unary < 0 || s->n_unary > SISSO_MAX_UNARY || s->n_binary < 0 || s->n_binary > SISSO_MAX_BINARY)
         return SISSO_E_SHAPE;
@@ -53,12 +53,15 @@ extern "C" sisso_status sisso_space_init(sisso_space *s)
     s->total = s->pool[s->levels];
     s->rect_unary = s->rect_binary = 0;
     if (s->rect) {
-        const int64_t nlast = s->pool[s->levels] - s->pool[s->levels - 1];
-        const double sz = (double)s->total + (double)s->n_unary * nlast +
-                          (double)s->n_slots * (double)nlast * (double)s->pool[s->levels - 1];
+        // rect 1: the one-sided slice (u new at level L, v in P_{L-1});
+        // rect 2: the whole next TRI level (u new at level L, v < u)
+        const int64_t lo = s->pool[s->levels - 1], hi = s->pool[s->levels];
+        const int64_t nlast = hi - lo;
+        const double pairs = s->rect == 1 ? (double)nlast * (double)lo : (double)choose2(hi) - (double)choose2(lo);
+        const double sz = (double)s->total + (double)s->n_unary * nlast + (double)s->n_slots * pairs;
         if (sz > lim) return SISSO_E_RANGE;
         s->rect_unary = (int64_t)s->n_unary * nlast;
-        s->rect_binary = (int64_t)s->n_slots * nlast * s->pool[s->levels - 1];
+        s->rect_binary = (int64_t)s->n_slots * (s->rect == 1 ? nlast * lo : choose2(hi) - choose2(lo));
         s->total += s->rect_unary + s->rect_binary;
     }
     if (s->total < 1) return SISSO_E_SHAPE;

@@ -76,7 +76,12 @@ SISSO_HD int decode_id(const sisso_space &s, int64_t id, int *op, int64_t *l, in
     loc -= s.rect_unary;
     const int64_t pair = loc / s.n_slots;
     const int slot = (int)(loc % s.n_slots);
-    const int64_t u = lo + pair / lo, v = pair % lo;
+    int64_t u, v;
+    if (s.rect == 1) {
+        u = lo + pair / lo; v = pair % lo;            // v in P_{L-1}
+    } else {
+        pair_from_index(pair + choose2(lo), &u, &v);  // the next TRI level: v < u
+    }
     *op = s.slot_op[slot];
     if (s.slot_rev[slot]) { *l = v; *r = u; } else { *l = u; *r = v; }
     return 0;

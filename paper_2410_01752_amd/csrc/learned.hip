@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(256) k_inputs(sisso_space s, FormSlots fs, con
     float *row = X + (size_t)q * kIn;
     int k = -1;
     int64_t u = 0, v = 0;
-    if (s.rect && id >= binbase && id < s.total) {
+    if (s.rect == 1 && id >= binbase && id < s.total) {
         const int64_t loc = id - binbase, pair = loc / s.n_slots;
         const int slot = (int)(loc % s.n_slots);
         u = s.pool[Lv - 1] + pair / vcount;
@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(256) k_mlp_score_ids(sisso_space s, FormSlots 
     const int64_t binbase = s.pool[Lv] + s.rect_unary, vcount = s.pool[Lv - 1];
     const int64_t id = ids[q];
     float sc = -INFINITY;
-    if (s.rect && id >= binbase && id < s.total) {
+    if (s.rect == 1 && id >= binbase && id < s.total) {
         const int64_t loc = id - binbase, pair = loc / s.n_slots;
         const int slot = (int)(loc % s.n_slots);
         const int64_t ui = pair / vcount, v = pair % vcount;
@@ -862,7 +862,7 @@ bool args_ok(const sisso_score_args *a)
 
 bool slice_ok(const sisso_space *s)
 {
-    return s && s->total > 0 && s->rect && s->levels >= 1 && s->levels <= SISSO_MAX_LEVELS &&
+    return s && s->total > 0 && s->rect == 1 && s->levels >= 1 && s->levels <= SISSO_MAX_LEVELS &&
            s->pool[s->levels - 1] >= 1;
 }
 

@@ -42,21 +42,22 @@ constexpr int kGT = 32;    // output tile
 constexpr int kGK = 16;    // samples per LDS chunk
 
 // Tile (bi, bj) of Z_a^T Z_b (a: ma columns, b: mb columns, both n x *,
-// leading dim ldz).  256 threads, 2 x 2 outputs each.  Returns the four
-// dot products in acc; rows i = bi*32 + ty*2 + {0,1}, cols j = bj*32 + tx*2 + {0,1}.
-__device__ inline void gemm_tile_tn(const double *Za, int ma, const double *Zb, int mb, int n, int ldz,
-                                    int bi, int bj, double (&acc)[2][2], double (*As)[kGT + 1],
-                                    double (*Bs)[kGT + 1])
+// leading dim ldz) over the samples [kb, ke).  256 threads, 2 x 2 outputs
+// each.  Returns the four dot products in acc; rows i = bi*32 + ty*2 + {0,1},
+// cols j = bj*32 + tx*2 + {0,1}.
+__device__ inline void gemm_tile_tn_range(const double *Za, int ma, const double *Zb, int mb, int kb, int ke,
+                                          int ldz, int bi, int bj, double (&acc)[2][2], double (*As)[kGT + 1],
+                                          double (*Bs)[kGT + 1])
 {
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     acc[0][0] = acc[0][1] = acc[1][0] = acc[1][1] = 0.0;
-    for (int k0 = 0; k0 < n; k0 += kGK) {
+    for (int k0 = kb; k0 < ke; k0 += kGK) {
         // load 32 columns x 16 samples of each operand: 512 values, 2 per thread
         for (int e = tid; e < kGT * kGK; e += blockDim.x) {
             const int c = e / kGK, t = e % kGK;
             const int ia = bi * kGT + c, ib = bj * kGT + c;
-            As[t][c] = (ia < ma && k0 + t < n) ? Za[(size_t)ia * ldz + k0 + t] : 0.0;
-            Bs[t][c] = (ib < mb && k0 + t < n) ? Zb[(size_t)ib * ldz + k0 + t] : 0.0;
+            As[t][c] = (ia < ma && k0 + t < ke) ? Za[(size_t)ia * ldz + k0 + t] : 0.0;
+            Bs[t][c] = (ib < mb && k0 + t < ke) ? Zb[(size_t)ib * ldz + k0 + t] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -70,6 +71,14 @@ __device__ inline void gemm_tile_tn(const double *Za, int ma, const double *Zb, 
         }
         __syncthreads();
     }
+}
+
+// The same over all n samples.
+__device__ inline void gemm_tile_tn(const double *Za, int ma, const double *Zb, int mb, int n, int ldz,
+                                    int bi, int bj, double (&acc)[2][2], double (*As)[kGT + 1],
+                                    double (*Bs)[kGT + 1])
+{
+    gemm_tile_tn_range(Za, ma, Zb, mb, 0, n, ldz, bi, bj, acc, As, Bs);
 }
 
 }  // namespace sisso

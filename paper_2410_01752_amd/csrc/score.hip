@@ -32,6 +32,7 @@ __global__ void k_ws_reset(WsHeader *h, int keep, int n_lists, int lists_cap)
         h->n_lists = n_lists;
         h->lists_cap = lists_cap;
         h->status = 0;
+        h->scr_status = 0;
     }
 }
 
@@ -171,17 +172,21 @@ __global__ void __launch_bounds__(256) k_score_rect(
     BlockList L{lsc, lid, &lcnt, &lthr, cap, keep};
     list_init(L);
 
+    // one-sided slice (rect 1): v in P_{L-1}; whole next TRI level (rect 2):
+    // v < u over P_L, the u tile's v range ending at its last u
     const int Lv = s.levels;
-    const int64_t vcount = s.pool[Lv - 1];          // v in P_{L-1}
+    const bool tri = s.rect == 2;
     const int64_t ulo = s.pool[Lv - 1], uhi = s.pool[Lv];
-    const PairIds ids{s.pool[Lv] + s.rect_unary, ulo, vcount, s.n_slots, false};
+    const int64_t vcount = tri ? uhi : ulo;
+    const PairIds ids{s.pool[Lv] + s.rect_unary, ulo, ulo, s.n_slots, tri};
     const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
-    const int64_t nvt = (vcount + TV - 1) / TV;
 
     for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
         const int64_t u0 = ulo + ut * TU;
         USide<RU, RV> U;
         load_uside<RU, RV>(U, stats, ids, u0, uhi);
+        const int64_t vlim = tri ? (u0 + TU < uhi ? u0 + TU : uhi) : vcount;
+        const int64_t nvt = (vlim + TV - 1) / TV;
         for (int64_t vt = 0; vt < nvt; ++vt) {
             float osc[RU * RV * 5];
             int64_t oid[RU * RV * 5];
@@ -391,8 +396,18 @@ Plan make_plan(const sisso_space *s, const sisso_score_args *a, int64_t begin, i
         const int64_t bb = pL + s->rect_unary, be = s->total;
         const int64_t b = begin > bb ? begin : bb, e = end < be ? end : be;
         if (b < e) {
-            const int64_t per_u = newlo * s->n_slots;
-            const int64_t ul = (b - bb) / per_u, uh = (e - 1 - bb) / per_u + 1;
+            int64_t ul, uh;                  // u range (from the first u of N_L) of the ids
+            if (s->rect == 1) {
+                const int64_t per_u = newlo * s->n_slots;
+                ul = (b - bb) / per_u;
+                uh = (e - 1 - bb) / per_u + 1;
+            } else {
+                int64_t jb, je, ib, ie;
+                pair_from_index((b - bb) / s->n_slots + choose2(newlo), &jb, &ib);
+                pair_from_index((e - 1 - bb) / s->n_slots + choose2(newlo), &je, &ie);
+                ul = jb - newlo;
+                uh = je - newlo + 1;
+            }
             const int tu = rect_tu(p.ru);
             p.ut_lo = ul / tu;
             p.ut_hi = (uh + tu - 1) / tu;
@@ -560,11 +575,64 @@ extern "C" sisso_status sisso_topk(const void *ws_c, size_t ws_bytes, int32_t k,
 }
 
 namespace sisso {
+// Threshold selection (Sec. 2.2's alternative to a fixed k): count the list
+// entries at or above tau, then keep that prefix of the merged list.
+__global__ void k_thr_reset(WsHeader *h)
+{
+    if (threadIdx.x == 0) h->thr_count = 0;
+}
+
+__global__ void __launch_bounds__(256) k_thr_count(void *ws, float tau)
+{
+    WsView W = ws_view_dev(ws);
+    const int64_t M = (int64_t)W.h->n_lists * W.h->keep;
+    int c = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < M; e += (int64_t)gridDim.x * blockDim.x) {
+        const float sc = W.sc[e];
+        c += (sc >= 0.0f && sc >= tau) ? 1 : 0;
+    }
+    c = (int)wave_sum_dpp((double)c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&W.h->thr_count, c);
+}
+
+// *out_count = the merged entries at or above tau; status 4 when a block's
+// list was full with its last entry at or above tau (it may have dropped
+// candidates that reach tau), 5 when more than max_out candidates reach it.
+__global__ void k_thr_final(WsHeader *h, float tau, int max_out, int32_t *out_count)
+{
+    if (threadIdx.x == 0) {
+        const int c = h->thr_count;
+        const int take = *out_count;
+        *out_count = c < take ? c : take;
+        if (h->status == 0) {
+            if (__uint_as_float(h->gthr) >= tau && h->gthr != 0u) h->status = 4;
+            else if (c > max_out) h->status = 5;
+        }
+    }
+}
+
 __global__ void k_tk_status(const WsHeader *h, int32_t *out)
 {
-    if (threadIdx.x == 0) *out = h->status;
+    if (threadIdx.x == 0) *out = h->status != 0 ? h->status : h->scr_status;
 }
 }  // namespace sisso
+
+extern "C" sisso_status sisso_select_threshold(const void *ws_c, size_t ws_bytes, float tau, int32_t max_out,
+                                               int64_t *out_ids, float *out_scores, int32_t *out_count,
+                                               void *stream)
+{
+    void *ws = const_cast<void *>(ws_c);
+    if (!ws || !out_ids || !out_scores || !out_count) return SISSO_E_NULL;
+    if (max_out < 1 || max_out > SISSO_MAX_BAND || !(tau >= 0.0f) || tau > 1.0f) return SISSO_E_RANGE;
+    if (ws_bytes < ws_bytes_for(0, 1)) return SISSO_E_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    const sisso_status rs = topk_launch(ws, max_out, out_ids, out_scores, out_count, st, true);
+    if (rs != SISSO_OK) return rs;
+    hipLaunchKernelGGL(k_thr_reset, dim3(1), dim3(64), 0, st, (WsHeader *)ws);
+    hipLaunchKernelGGL(k_thr_count, dim3(512), dim3(256), 0, st, ws, tau);
+    hipLaunchKernelGGL(k_thr_final, dim3(1), dim3(64), 0, st, (WsHeader *)ws, tau, max_out, out_count);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
 
 extern "C" sisso_status sisso_topk_status(const void *ws, size_t ws_bytes, int32_t *out_status, void *stream)
 {

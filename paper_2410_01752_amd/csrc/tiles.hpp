@@ -481,7 +481,7 @@ __device__ inline float score_slice_id(const sisso_space &s, const FormSlots &fs
 {
     const int Lv = s.levels;
     const int64_t binbase = s.pool[Lv] + s.rect_unary;
-    if (!s.rect || id < binbase || id >= s.total) return -1.0f;
+    if (s.rect != 1 || id < binbase || id >= s.total) return -1.0f;
     const int64_t loc = id - binbase, vcount = s.pool[Lv - 1];
     const int slot = (int)(loc % s.n_slots);
     const int64_t pair = loc / s.n_slots;

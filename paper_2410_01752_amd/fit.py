@@ -282,6 +282,31 @@ class Engine:
             events.setdefault("topk", []).append((ev0, ev1))
         return ids, sc, cnt
 
+    def select_threshold(self, tau: float, max_out: int):
+        """Every candidate of the last screening pass whose score is at least
+        tau (Sec. 2.2's threshold alternative to a fixed k), best first, at
+        most max_out: device tensors (ids, scores, count).  Raises if the
+        pass's per-block lists may have dropped candidates that reach tau, or
+        more than max_out do."""
+        ws = self._ws.get("score")
+        if ws is None:
+            raise L.SissoError("select_threshold needs a screening pass first")
+        ids = torch.empty(max_out, dtype=torch.int64, device=self.dev)
+        sc = torch.empty(max_out, dtype=torch.float32, device=self.dev)
+        cnt = torch.empty(1, dtype=torch.int32, device=self.dev)
+        st = self.stream()
+        L.check(L.lib().sisso_select_threshold(L.ptr(ws), ws.numel(), float(tau), max_out, L.ptr(ids), L.ptr(sc),
+                                               L.ptr(cnt), st), "sisso_select_threshold")
+        L.check(L.lib().sisso_topk_status(L.ptr(ws), ws.numel(), L.ptr(self.tk_status), st), "sisso_topk_status")
+        status = int(self.tk_status.item())
+        if status == 4:
+            raise L.SissoError("threshold selection: a block's list filled above the threshold (raise keep)")
+        if status == 5:
+            raise L.SissoError(f"threshold selection: more than {max_out} candidates reach {tau}")
+        if status != 0:
+            raise L.SissoError(f"threshold selection: status {status}")
+        return ids, sc, cnt
+
     def materialize(self, ids: torch.Tensor):
         """FP64 values (count x n, row q = feature ids[q]) and validity."""
         count = ids.numel()
@@ -309,12 +334,16 @@ class Engine:
     # ----------------------------------------------------------------- fit
     def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10,
             grid: int = 0, tile: int = 0, timings: Optional[dict] = None, precision: str = "fp32",
-            band: int = 0, moments: str = "auto") -> List[StepResult]:
+            band: int = 0, moments: str = "auto", threshold: Optional[float] = None) -> List[StepResult]:
         """SISSO fit: for t = 1..dmax, SIS against the residual, subspace
         update, SO over the subspace.  With the BF16 form and `moments` "auto",
         the first pass of the fit stores the residual-independent moments of
         the binary block and the later passes read them (when the buffer fits
-        in device memory); "off" recomputes them in every pass."""
+        in device memory); "off" recomputes them in every pass.  With a
+        `threshold`, each pass keeps every candidate whose score reaches it
+        (Sec. 2.2's alternative) instead of the best k: S_t grows by all their
+        duplicate classes, at most k per pass (the screen keeps keep0 per
+        block; a pass whose lists filled above the threshold raises)."""
         keep0 = min(2 * k if keep0 is None else keep0, L.MAX_KEEP)
         if moments not in ("auto", "off"):
             raise L.SissoError(f"unknown moments policy {moments!r}")
@@ -334,6 +363,13 @@ class Engine:
                                            precision=precision, band=band,
                                            moments=mom_state if use_mom else "none")
                 mom_state = "read"
+                if threshold is not None:
+                    fs.read_update(cnt, self.tk_status)         # the merge's own status
+                    ids, sc, cnt = self.select_threshold(threshold, keep)
+                    cand, valid = self.materialize(ids)
+                    fs.update(cand, ids, valid, cnt, keep, r, k, self._workspace)
+                    nn, nc, ct = fs.read_update(cnt)
+                    break
                 cand, valid = self.materialize(ids)
                 fs.update(cand, ids, valid, cnt, keep, r, k, self._workspace)
                 nn, nc, ct = fs.read_update(cnt, self.tk_status)
@@ -386,13 +422,11 @@ class FitState:
 
     def read_update(self, cnt, tk_status=None):
         """(appended, classes, screened count) of the last update; raises if
-        the top-k merge or the duplicate classes could not be formed exactly."""
+        the top-k merge could not order its ties exactly."""
         parts = [self.n_new, self.n_cls, cnt] + ([tk_status] if tk_status is not None else [])
         v = torch.cat(parts).cpu().numpy()
         if tk_status is not None and int(v[3]) != 0:
             raise L.SissoError(f"sisso_topk: status {int(v[3])} (more ties at the cutoff than the gather holds)")
-        if int(v[1]) < 0:
-            raise L.SissoError("sisso_subspace_update: more duplicate pairs than the edge list holds")
         return int(v[0]), int(v[1]), int(v[2])
 
     def commit(self, nn: int, t: int) -> bool:
