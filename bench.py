@@ -309,9 +309,9 @@ def cpu_baseline(p, budget_s: float, sub=None):
     return out
 
 
-MI355X_BF16_TFLOPS = 2500.0               # dense MFMA
+MI355X_FP16_TFLOPS = 2500.0               # dense MFMA, FP16 and BF16 alike
 CONTRACTIONS_PER_PAIR = 9            # algorithmic: (u v, u (v r), u^2 v^2) for u * v, u / v and v / u
-EXECUTED_MFMA_GEMMS = 12 * 3         # the kernel: 12 centred contractions x 3 hi/lo split products
+EXECUTED_MFMA_GEMMS = 12             # the kernel: 12 centred contractions, one FP16 product each
 READ_CONTRACTIONS_PER_PAIR = 3       # read form: u (v r) for u * v, u / v and v / u
 MOMENT_BYTES_PER_PAIR = 24           # six FP32 residual-independent moments per (u, v) pair
 
@@ -506,11 +506,11 @@ def main():
         executed = 2.0 * EXECUTED_MFMA_GEMMS * n * pairs / (kernel_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "k_score_rect_bf16_write" if moments else "k_score_rect_bf16",
                 "achieved": achieved,
-                "peak": MI355X_BF16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MI355X_BF16_TFLOPS,
+                "peak": MI355X_FP16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MI355X_FP16_TFLOPS,
                 "traffic": None, "avg_launch_ms": kernel_ms, "units_per_launch": pairs,
                 "per_unit": f"{CONTRACTIONS_PER_PAIR} contractions x 2 flops x n={n} samples per (u, v) pair "
                             f"(= {2 * CONTRACTIONS_PER_PAIR * n / 5:.0f} flops per candidate of the 5 forms)",
-                "executed_mfma_tflops": executed, "executed_frac": executed / MI355X_BF16_TFLOPS,
+                "executed_mfma_tflops": executed, "executed_frac": executed / MI355X_FP16_TFLOPS,
                 "launches_per_step": len(ks) / args.steps}
         kr = ev_ms(timings, "bf16_screen_read")
         if kr:
@@ -519,10 +519,10 @@ def main():
             roof["read_form"] = {
                 "kernel": "k_score_rect_bf16_read", "avg_launch_ms": read_ms, "launches_per_step": len(kr) / args.steps,
                 "achieved": rflops / (read_ms * 1e-3) / 1e12, "unit": "TFLOP/s",
-                "frac": rflops / (read_ms * 1e-3) / 1e12 / MI355X_BF16_TFLOPS,
+                "frac": rflops / (read_ms * 1e-3) / 1e12 / MI355X_FP16_TFLOPS,
                 "per_unit": f"{READ_CONTRACTIONS_PER_PAIR} residual contractions x 2 flops x n={n} samples per "
                             f"(u, v) pair, plus {MOMENT_BYTES_PER_PAIR} bytes of stored moments",
-                "executed_mfma_tflops": 2.0 * 3 * 3 * n * pairs / (read_ms * 1e-3) / 1e12,
+                "executed_mfma_tflops": 2.0 * READ_CONTRACTIONS_PER_PAIR * n * pairs / (read_ms * 1e-3) / 1e12,
                 "moments_gb_per_s": MOMENT_BYTES_PER_PAIR * pairs / (read_ms * 1e-3) / 1e9,
                 "traffic": measured_traffic("k_score_rect_bf16_read", args.workload)}
     elif n_bin > 0:
@@ -556,7 +556,7 @@ def main():
         "metric": "SIS candidates scored/s + SO tuples/s at rung 3; learned/BF16 vs plain @99% recall",
         "value": value, "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if prec == "bf16" else "f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp16" if prec == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": {"C3": "rung-3 SISSO fit: n=2000, d=20 LogNormal(0,0.5), ops {+,-,*,/,^2,sqrt,1/x}, "
                                       "pool levels 0-2 + one-sided rung-3 slice (13,667,146,300 candidates), "

@@ -194,6 +194,25 @@ typedef struct {
 sisso_status sisso_prepare_residual(const double *r, int32_t n, float *r32,
                                     sisso_resid_info *info, void *stream);
 
+/* Weighted form of sisso_prepare_residual for a pass under sample weights
+ * (Sec. 2.4: whitening by W = Sigma^(-1/2) when the noise covariance Sigma is
+ * diagonal and known; w_s = 1 / sigma_s^2).  The model keeps its intercept,
+ * so the whitened problem is weighted least squares and the screening score
+ * of a candidate is its weighted |Pearson correlation| with the residual.
+ *   r, w   n FP64 inputs (device); every w_s must be finite and > 0.
+ *   r32    n FP32 output: wn_s (r_s - mu), with wn = w n / sum(w) (weights
+ *          scaled to mean 1) and mu the weighted mean of r.
+ *   w32    n FP32 output: wn (the screening kernels read it from
+ *          sisso_score_args.w32).  Both buffers are read as float4 by the
+ *          kernels: allocate n rounded up to a multiple of 4 floats.
+ *   info   record: sum_r32 = sum of r32, s_rr = sum wn (r - mu)^2, mean_r = mu,
+ *          n = n.
+ * Errors: SISSO_E_NULL, SISSO_E_SHAPE.  Weights that are not positive and
+ * finite give a record with s_rr = NaN, and every score of the pass is then
+ * -1 (no candidate is admitted). */
+sisso_status sisso_prepare_residual_weighted(const double *r, const double *w, int32_t n, float *r32, float *w32,
+                                             sisso_resid_info *info, void *stream);
+
 /* Screening precision. */
 typedef enum { SISSO_FP32 = 0, SISSO_BF16 = 1 } sisso_precision;
 
@@ -216,6 +235,11 @@ typedef struct {
     int32_t list_base;            /* first list slot this call writes: 0 starts a
                                      new pass (resets the workspace); > 0 appends
                                      to the lists of earlier calls of the pass   */
+    const float *w32;             /* NULL, or the sample weights of a weighted
+                                     pass (sisso_prepare_residual_weighted; r32
+                                     and info must come from the same call):
+                                     scores are weighted |corr| (Sec. 2.4).
+                                     FP32 precision only                        */
 } sisso_score_args;
 
 /* Workspace of a screening pass: per-block candidate lists plus a header.
@@ -248,14 +272,20 @@ sisso_status sisso_expand_score(const sisso_space *space, const sisso_score_args
                                 int64_t cand_begin, int64_t cand_end, void *ws, size_t ws_bytes,
                                 void *stream);
 
-/* BF16 screening of the one-sided slice's binary block (Sec. 2.2's screening
- * carried out on matrix cores, an addition to the paper's method).  With
- * centred operands the sums of every form op(u, v) are contractions over the
- * samples; twelve GEMMs per tile
- * of (u, v) pairs run on BF16 MFMA with FP32 accumulation and give approximate
- * scores.  The best `band` candidates by BF16 score are then rescored exactly
- * with the FP32 path's arithmetic and written as per-block lists into `ws`
- * (list_base as in sisso_expand_score), so sisso_topk returns FP32 scores.
+/* 16-bit screening of the one-sided slice's binary block (Sec. 2.2's
+ * screening carried out on matrix cores, an addition to the paper's method;
+ * the entry points keep the name bf16 of their first form).  With centred
+ * operands the sums of every form op(u, v) are contractions over the samples;
+ * twelve GEMMs per tile of (u, v) pairs run on FP16 MFMA (operands scaled by
+ * powers of two near their inverse RMS) with FP32 accumulation and give
+ * approximate scores.  A candidate whose approximate variance is too
+ * ill-conditioned for 16-bit operands (below 1e-2 of the magnitude of the
+ * terms it is formed from) is scored exactly instead.  The best `band`
+ * candidates by approximate score, and the exactly scored ones, are then
+ * rescored with the FP32 path's arithmetic and written as per-block lists
+ * into `ws` (list_base as in sisso_expand_score), so sisso_topk returns FP32
+ * scores.  A list of flagged candidates that overflows its capacity is
+ * reported by sisso_topk_status (3).
  *   ops       u-side column constants from sisso_prepare_bf16 (size from
  *             sisso_bf16_operands_size; residual-independent, once per problem).
  *   bws       per-call workspace (size from sisso_bf16_workspace_size).
@@ -275,8 +305,8 @@ int32_t sisso_expand_score_bf16_lists(const sisso_space *space, const sisso_scor
                                       int32_t band);
 /* The three steps of sisso_expand_score_bf16, for callers that time or
  * overlap them: the residual-dependent operands (v-side column sums, the u
- * side's residual sums and the v-side staging image that the READ form of
- * sisso_bf16_screen_moments copies), the MFMA screen into the band lists of
+ * side's residual sums and the v-side staging image that the moments screens
+ * of sisso_bf16_screen_moments copy), the MFMA screen into the band lists of
  * `bws`, and the band top-k plus exact FP32 rescore into `ws`. */
 sisso_status sisso_bf16_residual(const sisso_space *space, const sisso_score_args *args, int32_t band,
                                  void *bws, size_t bws_bytes, void *stream);
@@ -290,25 +320,29 @@ sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score
                                      int64_t cand_begin, int64_t cand_end, void *bws, size_t bws_bytes,
                                      void *ws, size_t ws_bytes, void *stream);
 
-/* Residual-independent moments of the BF16 screen.  The weights of Sec. 2.2
- * take the columns of the feature matrix standardised (zero mean, unit
- * variance); that standardisation depends on the features alone, not on the
- * residual, so the SIS passes of one fit (one per SO dimension) share it.
- * Likewise, of the twelve GEMMs of the BF16 screen, nine give per-pair sums
- * that do not involve the residual.  A screen in mode SISSO_MOMENTS_WRITE runs all twelve and also
- * stores, for every (u, v) pair of the tiles it covers, six FP32 values (sum h
- * and the variance of u v, u/v and v/u); a screen in mode SISSO_MOMENTS_READ
- * loads them and runs only the three residual GEMMs.  The approximate scores
- * of a READ screen equal, bit for bit, those of a WRITE (or a plain) screen of
- * the same residual, so the band, the rescore and the result are the same.
- *   moments        device buffer of sisso_bf16_moments_size(space, n) bytes
- *                  (24 bytes per pair of the padded 64 x 64 tiles: about 69 GB
- *                  for 2.65M x 1030 operand pairs), owned by the caller.
+/* Residual-independent moments of the 16-bit screen.  The weights of
+ * Sec. 2.2 take the columns of the feature matrix standardised (zero mean,
+ * unit variance); that standardisation depends on the features alone, not on
+ * the residual, so the SIS passes of one fit (one per SO dimension) share it.
+ * Likewise, of the twelve GEMMs of the 16-bit screen, nine give per-pair sums
+ * that do not involve the residual.  A screen in mode SISSO_MOMENTS_WRITE
+ * first runs those nine and stores, for every (u, v) pair of the tiles it
+ * covers, six FP32 values (sum h and the variance of u v, u/v and v/u), the
+ * candidates the conditioning test flags, and the u side's FP16 operands;
+ * then, like a screen in mode SISSO_MOMENTS_READ, it loads them and runs only
+ * the three residual GEMMs.  The approximate scores of these screens equal,
+ * bit for bit, those of a plain screen of the same residual, so the band, the
+ * rescore and the result are the same.
+ *   moments        device buffer of sisso_bf16_moments_size(space, n) bytes,
+ *                  owned by the caller: 24 bytes per pair of the padded
+ *                  64 x 64 tiles (about 69 GB for 2.65M x 1030 operand
+ *                  pairs), the flagged candidates, and 4 bytes per sample of
+ *                  each newest-level operand (about 21 GB at n = 2000).
  *   mode           SISSO_MOMENTS_NONE (moments unused, may be NULL: the same
  *                  as sisso_bf16_screen), SISSO_MOMENTS_WRITE or
  *                  SISSO_MOMENTS_READ.
- * The READ form runs two blocks per CU and sizes its own grid (args->grid
- * applies to the other forms).
+ * The moments screens size their own grids (args->grid applies to the plain
+ * form).
  * A READ screen requires an earlier WRITE screen over the same pools, the same
  * operands (`ops`) and a candidate range covering its own, into the same
  * buffer; any residual, keep, band or exclusion list may differ.  The library
@@ -560,6 +594,18 @@ sisso_status sisso_subspace_update(const double *cand, int32_t ldc, const int64_
                                    int32_t *n_new, int32_t *n_classes, void *ws, size_t ws_bytes,
                                    void *stream);
 
+/* sisso_subspace_update under sample weights w (device, n FP64, positive;
+ * NULL: the unweighted call): every correlation (the FP64 re-score of the
+ * list and the duplicate test) is the weighted one (Sec. 2.4 whitening with a
+ * diagonal covariance, intercept whitened).  A non-finite weight makes every
+ * column invalid. */
+sisso_status sisso_subspace_update_weighted(const double *cand, int32_t ldc, const int64_t *cand_ids,
+                                            const int32_t *cand_valid, const int32_t *count_dev,
+                                            int32_t count_max, const double *r, const double *w, int32_t n,
+                                            double *sub, int32_t lds, int64_t *sub_ids, int32_t m_prev, int32_t k,
+                                            int32_t *n_new, int32_t *n_classes, void *ws, size_t ws_bytes,
+                                            void *stream);
+
 /* Outcome of a finished SO search from its stats record [host]: `stats` is
  * a host copy of the 4 doubles out_stats received.  SISSO_OK when a model was
  * found; SISSO_E_NUMERIC when every tuple was singular (no model exists: the
@@ -588,6 +634,18 @@ sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, 
                              double *out_coef, double *out_resid, double *out_stats, void *ws,
                              size_t ws_bytes, void *stream);
 
+/* sisso_l0_search under sample weights w (device, n FP64, positive; NULL:
+ * the unweighted call): weighted least squares, i.e. least squares on the
+ * whitened problem W y, W [1, F] with W = diag(sqrt(w)) (Sec. 2.4 with a
+ * diagonal noise covariance, w_s = 1 / sigma_s^2).  out_sse is
+ * sum w_s e_s^2, out_resid the plain residual y - fit, out_stats[0] the
+ * weighted RMSE sqrt(sum w e^2 / sum w) and out_stats[1] the weighted R^2.
+ * Workspace and errors as sisso_l0_search. */
+sisso_status sisso_l0_search_weighted(const double *F, int32_t m, int32_t ld, int32_t n, const double *y,
+                                      const double *w, int32_t D, double singular_tol, int32_t *out_tuple,
+                                      double *out_sse, double *out_coef, double *out_resid, double *out_stats,
+                                      void *ws, size_t ws_bytes, void *stream);
+
 /* sisso_l0_search for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same search with its workspace in a fixed device array of
@@ -599,7 +657,7 @@ sisso_status sisso_l0_search(const double *F, int32_t m, int32_t ld, int32_t n, 
  * serialised by the caller; each call re-initialises what it reads.
  * Errors: as sisso_l0_search; SISSO_E_WORKSPACE when the search needs more
  * than the array holds (sisso_l0_workspace_size(m, n, D) > capacity: e.g.
- * m = 1024 columns hold n <= 3000 samples, m = 600 hold n <= 5000);
+ * m = 600 columns hold n <= 4400 samples, m = 1024 hold n <= 2000);
  * SISSO_E_DEVICE if the array's device address cannot be obtained. */
 size_t sisso_l0_scratch_capacity(void);
 sisso_status sisso_l0_search_noalloc(const double *F, int32_t m, int32_t ld, int32_t n, const double *y,

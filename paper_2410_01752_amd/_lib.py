@@ -52,7 +52,7 @@ class ScoreArgs(ctypes.Structure):
                 ("exclude", ctypes.c_void_p), ("n_exclude", ctypes.c_int32),
                 ("keep", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("list_base", ctypes.c_int32)]
+                ("list_base", ctypes.c_int32), ("w32", ctypes.c_void_p)]
 
 
 class Problem(ctypes.Structure):
@@ -130,6 +130,7 @@ def lib():
         "sisso_materialize_ids_stored": (_i32, [sp, _i32, _i32, _vp, _i64, _vp, _vp, _i32, _vp, _i32, _vp,
                                                 _vp]),
         "sisso_prepare_residual": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+        "sisso_prepare_residual_weighted": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
         "sisso_prepare_residual_batched": (_i32, [_vp, _i32, _vp]),
         "sisso_batch_workspace_size": (_sz, [sp, _i32, _i32]),
         "sisso_batch_items": (_i32, [sp]),
@@ -149,6 +150,10 @@ def lib():
         "sisso_subspace_workspace_size": (_sz, [_i32, _i32, _i32]),
         "sisso_subspace_update": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp,
                                          _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+        "sisso_subspace_update_weighted": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _i32,
+                                                  _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+        "sisso_l0_search_weighted": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _i32, ctypes.c_double, _vp, _vp,
+                                            _vp, _vp, _vp, _vp, _sz, _vp]),
         "sisso_l0_workspace_size": (_sz, [_i32, _i32, _i32]),
         "sisso_l0_outcome": (_i32, [_vp]),
         "sisso_l0_scratch_capacity": (_sz, []),
@@ -217,6 +222,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_mlp_target", "sisso_adam_step", "sisso_mlp_parts", "sisso_mlp_tables", "sisso_mlp_score_ids", "sisso_select_kth",
             "sisso_expand_score_pruned_lists", "sisso_expand_score_pruned", "sisso_count_pass",
             "sisso_prescreen_workspace_size", "sisso_prescreen_scores", "sisso_prescreen_select",
+            "sisso_prepare_residual_weighted", "sisso_subspace_update_weighted", "sisso_l0_search_weighted",
             "sisso_status_string", "sisso_version"]
 
 

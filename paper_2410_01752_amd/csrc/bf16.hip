@@ -33,8 +33,8 @@
 // scores are the FP32 path's scores.
 //
 // The file is compiled twice.  The second translation unit (bf16_mfma.hip,
-// which defines SISSO_BF16_MFMA_PART) holds only the launches of the plain and
-// write forms and is compiled with the scheduler that maximises
+// which defines SISSO_BF16_MFMA_PART) holds only the plain form and the
+// moments pass and is compiled with the scheduler that maximises
 // instruction-level parallelism.
 #include "tiles.hpp"
 
@@ -61,11 +61,13 @@ constexpr int kKR = kKC;      // 16-bit values per LDS row: one chunk of samples
 constexpr int kMom = 6;       // residual-independent moments kept per (u, v) pair
 constexpr size_t kMomTile = (size_t)4 * 16 * kMom * 64;   // floats per (u tile, v tile)
 
-// Moments modes of the screen.  kBfFull and kBfWrite run all twelve GEMMs;
-// kBfWrite also stores, per pair, the sums that do not involve the residual
-// (sum h of u v, u/v and v/u, the variances of u v, u/v and v/u).  kBfRead
-// loads them and runs only the three residual GEMMs.
-enum BfMode { kBfFull = 0, kBfWrite = 1, kBfRead = 2 };
+// Forms of the screening kernel.  kBfFull runs all twelve GEMMs.  Within a
+// fit, the first pass runs the moments pass (k_bf_moments below: the nine
+// residual-independent GEMMs, reduced per pair to sum h of u v, u/v and v/u
+// and their variances, stored with the u side's FP16 image), and every pass
+// scores with kBfRead, which loads them and runs only the three residual
+// GEMMs.
+enum BfMode { kBfFull = 0, kBfRead = 2 };
 
 // GEMM g multiplies u-side variant A(g) with v-side variant B(g).
 //   full:  g:  0   1    2   3   4   5    6    7   8   9    10   11
@@ -82,14 +84,15 @@ template <int MODE> struct BfShape {
     // Block tile: kBTU u columns x kBTV v columns, one 32 x 32 sub-tile per
     // wave.  The read form's few GEMMs leave registers for two waves per SIMD,
     // and its wider v tile streams each u tile half as often.
-    static constexpr int kBTU = 64, kBTV = kRead ? 128 : 64;
-    static constexpr int kWV = kBTV / 32, kThreads = 64 * 2 * kWV;     // waves: 2 along u, kWV along v
+    static constexpr int kWU = 2, kWV = kRead ? 4 : 2;                 // waves along u and along v
+    static constexpr int kBTU = 32 * kWU, kBTV = 32 * kWV, kThreads = 64 * kWU * kWV;
     static constexpr int kSU = kBTU * kKC / kThreads;                  // u samples staged per thread
     static constexpr int kSV = kBTV * kKC / kThreads;                  // v samples staged per thread
     static constexpr int kPlaneU = kBTU * kKR, kPlaneV = kBTV * kKR;   // 16-bit values per staged plane
     static constexpr int kPA = kUVar, kPB = kVVar;                     // staged planes per side
     static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;       // 16-bit values per staging buffer
     static constexpr int kMinBlocks = 1;            // resident blocks per CU the registers are sized for
+    static constexpr int kNStage = kRead ? 4 : 2;   // staging buffers: double buffer, or the read form's ring
     // accumulator of the residual contraction of u v, u/v and v/u
     static constexpr int kCovUV = kRead ? 0 : 1, kCovUW = kRead ? 1 : 5, kCovZV = kRead ? 2 : 9;
 };
@@ -163,6 +166,12 @@ struct BfWs {
 __host__ __device__ inline size_t bf_vimg_elems(int64_t vcols, int n)
 {
     return (size_t)((vcols + 127) / 128) * (size_t)((n + kKC - 1) / kKC) * 2 * (128 * kKR);
+}
+// the u side's image (written by the moments pass, read by the read form):
+// per 64-column u tile and chunk of samples, the staged planes U~ and Z~
+__host__ __device__ inline size_t bf_uimg_elems(int64_t ucols, int n)
+{
+    return (size_t)((ucols + 63) / 64) * (size_t)((n + kKC - 1) / kKC) * 2 * (64 * kKR);
 }
 __host__ __device__ inline size_t bf_ws_bytes(const sisso_space &s, int64_t ucols, int64_t vcols, int n, int band,
                                               int lists, int keep)
@@ -258,6 +267,18 @@ __device__ __forceinline__ float r_scale(double srr, double n) { return pow2_inv
 __device__ __forceinline__ int lds_off(int row, int k)
 {
     return row * kKR + (k ^ ((((row >> 2) ^ (row >> 3)) & 1) << 3));
+}
+
+// s_waitcnt immediate that waits until at most n vector memory operations of
+// this wave are outstanding, leaving the other counters free (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt in 6:4, lgkmcnt in 11:8).
+constexpr int vm_wait(int n) { return (n & 0xF) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8); }
+
+// An LDS address for the direct global-to-LDS loads (wave-uniform: each lane
+// of the load writes its 16 bytes at this address + 16 x lane).
+__device__ __forceinline__ __attribute__((address_space(3))) void *lds_ptr(h16 *p)
+{
+    return (__attribute__((address_space(3))) void *)p;
 }
 
 // N consecutive floats (N = 2 or 4, 4N-byte aligned) in one load.
@@ -387,7 +408,7 @@ __global__ void __launch_bounds__(256) k_bf16_v_prep(int n, const float *__restr
 #endif  // SISSO_BF16_MFMA_PART
 
 // The residual-weighted centred v variants of one sample, V~ r and W~ r,
-// scaled (0 for a sample past n).  The write form forms them in its tile
+// scaled (0 for a sample past n).  The plain form forms them in its tile
 // kernel and the read form takes them from the v-side image: one function, the
 // same bits.
 __device__ __forceinline__ void v_resid_vars(float x, float r, float smv, float smw, float cvr, float cwr, bool live,
@@ -443,10 +464,12 @@ __global__ void __launch_bounds__(256) k_bf16_v_image(int n, const float *__rest
 // -------------------------------------------------------------- screening
 #endif  // SISSO_BF16_MFMA_PART
 
-// mom: per 64 x 64 tile (ut, vt64) of (u, v) pairs, its four 32 x 32 sub-tiles
-// w = wu + 2 wv, row slot r and moment k, the 64 lanes' values, at float offset
-// (((ut * nvt64 + vt64) * 4 + w) * 16 + r) * kMom * 64 + k * 64 + lane
-// (written by kBfWrite, read by kBfRead, unused by kBfFull; nvt64 = ceil(|P_1| / 64)).
+// mom: per 64 x 64 tile (ut64, vt64) of (u, v) pairs, its four 32 x 32
+// sub-tiles w = su + 2 sv (su, sv: the 32-column half of the tile along u and
+// along v), row slot r and moment k, the 64 lanes' values, at float offset
+// (((ut64 * nvt64 + vt64) * 4 + w) * 16 + r) * kMom * 64 + k * 64 + lane
+// (written by the moments pass, read by kBfRead, unused by kBfFull; nvt64 = ceil(|P_1| / 64)).
+// The layout does not depend on a form's block tile.
 template <int MODE>
 __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBlocks) k_score_rect_bf16(
     sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
@@ -454,15 +477,15 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
     int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, const h16 *__restrict__ vimg,
-    BfSide side, void *lws, int lists_total, int keep, int cap, int publish)
+    const h16 *__restrict__ uimg, BfSide side, void *lws, int lists_total, int keep, int cap, int publish)
 {
     using Sh = BfShape<MODE>;
     constexpr int kUVar = Sh::kUVar, kVVar = Sh::kVVar, kNG = Sh::kNG, kPA = Sh::kPA, kPB = Sh::kPB,
                   kStage = Sh::kStage, kBTU = Sh::kBTU, kBTV = Sh::kBTV, kSU = Sh::kSU, kSV = Sh::kSV,
                   kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    h16 *const stage = reinterpret_cast<h16 *>(smem);   // two staging buffers
-    float *lsc = (float *)(stage + 2 * kStage);
+    h16 *const stage = reinterpret_cast<h16 *>(smem);   // staging buffers (two; the read form's ring: kNStage)
+    float *lsc = (float *)(stage + Sh::kNStage * kStage);
     int64_t *lid = (int64_t *)(lsc + cap);
     // u-tile column constants for the epilogue: (mean u, mean 1/u, sum u~^2,
     // sum z~^2), (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero) and the
@@ -479,7 +502,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     list_init(Lst);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wu = w & 1, wv = w >> 1;
+    const int wu = w % Sh::kWU, wv = w / Sh::kWU;
     const int Lv = s.levels;
     const int64_t vcount = s.pool[Lv - 1], ulo = s.pool[Lv - 1], ucols = s.pool[Lv] - ulo;
     const int64_t binbase = s.pool[Lv] + s.rect_unary;
@@ -487,7 +510,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
     const float fn = (float)n, rsc = r_scale(Srr, nd), shs = sq_shift(n);
     const int nch = (n + kKC - 1) / kKC;
-    const int64_t nvt = (vcount + kBTV - 1) / kBTV, nvt64 = (vcount + 63) / 64;
+    const int64_t nvt = (vcount + kBTV - 1) / kBTV, nvt64 = (vcount + 63) / 64, nut64 = (ucols + 63) / 64;
     // staging roles: u column ucs, samples uks .. uks + kSU - 1 of a chunk; v
     // column vcs, samples vks .. vks + kSV - 1
     const int ucs = tid / (kKC / kSU), uks = (tid % (kKC / kSU)) * kSU;
@@ -644,39 +667,74 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // this wave's 32 x 32 sub-tile in the moments' 64 x 64 tiling; a
             // sub-tile past the last 64-column tile has no pair in the space
             const int64_t v32 = vt * Sh::kWV + wv;
-            const bool mom_in = (v32 >> 1) < nvt64;
-            const size_t mom_off = (((size_t)ut * nvt64 + (v32 >> 1)) * 4 + wu + 2 * (int)(v32 & 1)) *
+            const int64_t u64 = (u0 + wu * 32) / 64;
+            const bool mom_in = (v32 >> 1) < nvt64 && u64 < nut64;
+            const size_t mom_off = (((size_t)u64 * nvt64 + (v32 >> 1)) * 4 + (wu & 1) + 2 * (int)(v32 & 1)) *
                                    (16 * kMom * 64);
+            __builtin_amdgcn_s_waitcnt(vm_wait(0));   // the ring's load counts below are exact
             __syncthreads();                          // the previous tile's fragment reads are done
             if (tid == 0) lpend = 0;                  // every thread has read the previous total
-            // pr holds chunk ch + 1 while chunk ch + 2 loads (loads past the last
-            // chunk re-read it); deeper load rings were slower
-            load_chunk(0, pr);
-            store_chunk(0, stage, nch == 1);
-            load_chunk(1, pr);
-            __syncthreads();
-            int ch = 0;
-            for (; ch + 2 < nch; ++ch) {              // chunk ch + 1 is full
-                Raw q;
-                load_chunk(ch + 2, q);
-                mfma_chunk(buf_of(ch));
-                store_chunk(ch + 1, buf_of(ch + 1), false);
-                interleave();
-                pr = q;
+            if constexpr (Sh::kRead) {
+                // Both sides are copies of FP16 images already in the staged
+                // layout (u: written by the moments pass; v: per residual), moved
+                // by direct global-to-LDS loads into a ring of kNS stages, kNS - 1
+                // chunks ahead: no registers hold data in flight.  Chunk c's 4 KB
+                // of u are four 1 KB wave loads (waves 0..3), its 8 KB of v eight
+                // (one per wave).  Loads past the last chunk re-read it into the
+                // free stage.
+                constexpr int kNS = Sh::kNStage;
+                const h16 *const ub = uimg + (size_t)(u0 / 64) * nch * (kPA * kPlaneU) + w * 512 + lane * 8;
+                const h16 *const vb = vimg + (size_t)vt * nch * (kPB * kPlaneV) + w * 512 + lane * 8;
+                auto issue = [&](int c) {
+                    h16 *const stg = stage + (c % kNS) * kStage;
+                    const size_t cc = (size_t)(c < nch ? c : nch - 1);
+                    if (w < 4) __builtin_amdgcn_global_load_lds(ub + cc * (kPA * kPlaneU), lds_ptr(stg + w * 512), 16, 0, 0);
+                    __builtin_amdgcn_global_load_lds(vb + cc * (kPB * kPlaneV), lds_ptr(stg + kPA * kPlaneU + w * 512), 16, 0,
+                                                     0);
+                };
+#pragma unroll
+                for (int c = 0; c < kNS - 1; ++c) issue(c);
+                for (int ch = 0; ch < nch; ++ch) {
+                    // this wave's loads of chunk ch are done when at most the
+                    // kNS - 2 later chunks' are outstanding; the barrier makes
+                    // every wave's part visible and frees the stage read last
+                    if (w < 4) __builtin_amdgcn_s_waitcnt(vm_wait(2 * (kNS - 2)));
+                    else __builtin_amdgcn_s_waitcnt(vm_wait(kNS - 2));
+                    __builtin_amdgcn_s_barrier();
+                    issue(ch + kNS - 1);
+                    mfma_chunk(stage + (ch % kNS) * kStage);
+                }
+                __builtin_amdgcn_s_waitcnt(vm_wait(0));
+            } else {
+                // pr holds chunk ch + 1 while chunk ch + 2 loads (loads past the last
+                // chunk re-read it); deeper load rings were slower
+                load_chunk(0, pr);
+                store_chunk(0, stage, nch == 1);
+                load_chunk(1, pr);
                 __syncthreads();
-            }
-            if (ch + 1 < nch) {                       // chunk ch + 1 is the last one
+                int ch = 0;
+                for (; ch + 2 < nch; ++ch) {              // chunk ch + 1 is full
+                    Raw q;
+                    load_chunk(ch + 2, q);
+                    mfma_chunk(buf_of(ch));
+                    store_chunk(ch + 1, buf_of(ch + 1), false);
+                    interleave();
+                    pr = q;
+                    __syncthreads();
+                }
+                if (ch + 1 < nch) {                       // chunk ch + 1 is the last one
+                    mfma_chunk(buf_of(ch));
+                    store_chunk(ch + 1, buf_of(ch + 1), true);
+                    __syncthreads();
+                    ++ch;
+                }
                 mfma_chunk(buf_of(ch));
-                store_chunk(ch + 1, buf_of(ch + 1), true);
-                __syncthreads();
-                ++ch;
             }
-            mfma_chunk(buf_of(ch));
 
             // this tile's moments: loaded once the chunk loop's registers are free
             // (held across the loop they would be spilled; the other block on the
-            // CU runs meanwhile), or formed from the accumulators (write)
-            float mr[MODE != kBfFull ? 16 * kMom : 1];
+            // CU runs meanwhile)
+            float mr[Sh::kRead ? 16 * kMom : 1];
             if constexpr (Sh::kRead) {
                 const float *const mp = mom + mom_off + lane;
 #pragma unroll
@@ -702,8 +760,8 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // of u v, its variance, then the same for u/v and v/u.  A variance
             // below kCondRel of the magnitude of its terms is not resolved by the
             // FP16 operands: it is stored as -1 (the candidate is scored exactly).
-            // The read form takes the moments as the write form stored them over
-            // the same pools.
+            // The read form takes the moments as the moments pass stored them
+            // over the same pools (the same operations on the same bits).
             auto moments_acc = [&](int r, float (&m)[kMom]) {
 #pragma clang fp contract(off)
                 if constexpr (!Sh::kRead) {
@@ -724,21 +782,6 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                     m[5] = var_of(m[4], (acc[10][r] * ui.w) * ip, (acc[11][r] * ui.z) * iq, mz, mv, Szz, Svv);
                 }
             };
-            if constexpr (MODE == kBfWrite) {
-                // kept in registers for the scores below: the nine accumulators
-                // they come from are dead from here on
-                float *const mp = mom + mom_off + lane;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    float m[kMom];
-                    moments_acc(r, m);
-#pragma unroll
-                    for (int k = 0; k < kMom; ++k) {
-                        mr[r * kMom + k] = m[k];
-                        __builtin_nontemporal_store(m[k], mp + (r * kMom + k) * 64);
-                    }
-                }
-            }
             auto moments_of = [&](int r, float (&m)[kMom]) {
                 if constexpr (MODE == kBfFull) {
                     moments_acc(r, m);
@@ -932,6 +975,249 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     list_flush(Lst, gb, W.sc + (size_t)blockIdx.x * keep, W.id + (size_t)blockIdx.x * keep);
 }
 
+#ifdef SISSO_BF16_MFMA_PART
+// ----------------------------------------------------------- moments pass
+//
+// The first pass of a fit: per (u, v) pair of the binary block, the six
+// residual-independent moments the read form loads (sum h and the variance of
+// u v, u/v and v/u), from the nine residual-independent contractions of the
+// full form; the conditioning flags of the five forms (the flagged candidates
+// join the list of exact scoring); and the u side's FP16 image (U~ and Z~ in
+// the read form's staged layout).  The read form then scores the pass.  No
+// residual is involved, so nine accumulators per wave fit two waves per SIMD:
+// block tile 128 u x 64 v, eight waves (four along u, two along v), one
+// 32 x 32 sub-tile each.  Every staged value and every accumulator takes the
+// full form's operations, so the moments, flags and images are the bits the
+// full form computes.
+//   g:  0   1    2   3   4    5    6   7    8
+//   A:  U~  U~2  U~  U~  U~2  U~   Z~  Z~2  Z~
+//   B:  V~  P    Q   W~  Pw   Qw   V~  P    Q
+struct MomShape {
+    static constexpr int kWU = 4, kWV = 2, kBTU = 32 * kWU, kBTV = 32 * kWV, kThreads = 64 * kWU * kWV;
+    static constexpr int kSU = kBTU * kKC / kThreads, kSV = kBTV * kKC / kThreads;
+    static constexpr int kPA = 4, kPB = 6, kNG = 9;
+    static constexpr int kPlaneU = kBTU * kKR, kPlaneV = kBTV * kKR;
+    static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;
+};
+
+__global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
+    sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
+    const float4 *__restrict__ usum, const float4 *__restrict__ vsum, const sisso_colstat *__restrict__ stats,
+    int64_t ut_lo, int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, h16 *__restrict__ uimg,
+    BfSide side)
+{
+    using Sh = MomShape;
+    constexpr int kPA = Sh::kPA, kPB = Sh::kPB, kNG = Sh::kNG, kStage = Sh::kStage, kBTU = Sh::kBTU,
+                  kBTV = Sh::kBTV, kSU = Sh::kSU, kSV = Sh::kSV, kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV;
+    __shared__ __attribute__((aligned(16))) h16 stage[2 * kStage];
+    // u-tile constants: (mean u, mean 1/u, sum u~^2, sum z~^2), the inverse
+    // scale factors of U~, U~^2, Z~, Z~^2, flags (1 valid, 2 no zero, 4 not
+    // scalable)
+    __shared__ float4 ucon_a[kBTU], ucon_c[kBTU];
+    __shared__ int ucon_f[kBTU];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wu = w % Sh::kWU, wv = w / Sh::kWU;
+    const int Lv = s.levels;
+    const int64_t vcount = s.pool[Lv - 1], ulo = s.pool[Lv - 1], ucols = s.pool[Lv] - ulo;
+    const int64_t binbase = s.pool[Lv] + s.rect_unary;
+    const int S = s.n_slots;
+    const float fn = (float)n, shs = sq_shift(n);
+    const int nch = (n + kKC - 1) / kKC;
+    const int64_t nvt = (vcount + kBTV - 1) / kBTV, nvt64 = (vcount + 63) / 64, nut64 = (ucols + 63) / 64;
+    const int ucs = tid / (kKC / kSU), uks = (tid % (kKC / kSU)) * kSU;
+    const int vcs = tid / (kKC / kSV), vks = (tid % (kKC / kSV)) * kSV;
+    const int tmax_u = ((n - 1) / kSU) * kSU, tmax_v = ((n - 1) / kSV) * kSV;
+    const int sto_u = lds_off(ucs, uks), sto_v = lds_off(vcs, vks);
+    const int koff = (lane >> 5) * 8;
+    const int fa = lds_off(wu * 32 + (lane & 31), koff), fb = lds_off(wv * 32 + (lane & 31), koff);
+    const int img_off = lds_off(ucs & 63, uks);   // this thread's samples in its 64-column image tile
+
+    for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
+        const int64_t u0 = ut * kBTU;
+        const int64_t su = u0 + ucs;
+        const bool su_ok = su < ucols;
+        const float4 us_c = usum[su_ok ? su : 0];
+        const float smu = us_c.x, smz = us_c.y;
+        const UScale usc = u_scales(us_c.z, us_c.w, fn);
+        const float cu = usc.u, cz = usc.z, cu2 = usc.u * usc.u * shs, cz2 = usc.z * usc.z * shs;
+        const float *ucol = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
+        // the image has 64-column tiles up to the one holding the last column
+        // (its rows past the last column stage column 0, like the tiles)
+        h16 *const img = su / 64 < nut64 ? uimg + (size_t)(su / 64) * nch * (2 * 64 * kKR) + img_off : nullptr;
+        __syncthreads();                              // the previous tile's epilogue reads are done
+        if (tid < kBTU) {
+            const int64_t x = u0 + tid;
+            const bool in = x < ucols;
+            const sisso_colstat cs = stats[ulo + (in ? x : 0)];
+            const float4 ua = usum[in ? x : 0];
+            ucon_a[tid] = ua;
+            const UScale c = u_scales(ua.z, ua.w, fn);
+            ucon_c[tid] = make_float4(1.0f / c.u, 1.0f / (c.u * c.u * shs), 1.0f / c.z, 1.0f / (c.z * c.z * shs));
+            ucon_f[tid] = (in && cs.valid != 0.0f ? 1 : 0) + (cs.minabs > 0.0f ? 2 : 0) +
+                          (col_scalable(ua.z, ua.w, fn, cs.minabs > 0.0f) ? 0 : 4);
+        }
+        for (int64_t vt = 0; vt < nvt; ++vt) {
+            const int64_t v0 = vt * kBTV;
+            const int64_t sv = v0 + vcs;
+            const bool sv_ok = sv < vcount;
+            const float4 vs_c = vsum[2 * (sv_ok ? sv : 0)];
+            const float smv = vs_c.x, smw = vs_c.y;
+            const VScale vsc = v_scales(smv, smw, vs_c.z, vs_c.w, fn, 1.0f, shs);
+            const float *vcol = pool32 + (size_t)(sv_ok ? sv : 0) * ld32;
+            const bool wimg = vt == 0 && img != nullptr;
+            f32x16 acc[kNG];
+#pragma unroll
+            for (int g = 0; g < kNG; ++g)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
+            struct Raw {
+                float u[kSU], v[kSV];
+            };
+            Raw pr;
+            auto load_chunk = [&](int ch, Raw &x) {
+                load_floats<kSU>(ucol + min(ch * kKC + uks, tmax_u), x.u);
+                load_floats<kSV>(vcol + min(ch * kKC + vks, tmax_v), x.v);
+            };
+            auto store_chunk = [&](int ch, h16 *buf, bool tail) {
+                // the full form's operations, uncontracted
+#pragma clang fp contract(off)
+                float ua[kPA][kSU], va[kPB][kSV];
+#pragma unroll
+                for (int e = 0; e < kSU; ++e) {
+                    float uu = pr.u[e] - smu, zz = __builtin_amdgcn_rcpf(pr.u[e]) - smz;
+                    if (tail) {
+                        const bool live = ch * kKC + uks + e < n;
+                        uu = live ? uu : 0.f; zz = live ? zz : 0.f;
+                    }
+                    ua[0][e] = uu * cu; ua[1][e] = (uu * uu) * cu2; ua[2][e] = zz * cz; ua[3][e] = (zz * zz) * cz2;
+                }
+#pragma unroll
+                for (int q = 0; q < kPA; ++q) put_h16<kSU>(buf + q * kPlaneU + sto_u, ua[q]);
+                if (wimg) {
+                    h16 *const dst = img + (size_t)ch * (2 * 64 * kKR);
+                    put_h16<kSU>(dst, ua[0]);
+                    put_h16<kSU>(dst + 64 * kKR, ua[2]);
+                }
+#pragma unroll
+                for (int e = 0; e < kSV; ++e) {
+                    float vv = pr.v[e] - smv, ww = __builtin_amdgcn_rcpf(pr.v[e]) - smw;
+                    if (tail) {
+                        const bool live = ch * kKC + vks + e < n;
+                        vv = live ? vv : 0.f; ww = live ? ww : 0.f;
+                    }
+                    va[0][e] = vv * vsc.v; va[1][e] = (vv * (vv + 2.f * smv)) * vsc.p;
+                    va[2][e] = (vv * (vv + smv)) * vsc.q;
+                    va[3][e] = ww * vsc.w; va[4][e] = (ww * (ww + 2.f * smw)) * vsc.pw;
+                    va[5][e] = (ww * (ww + smw)) * vsc.qw;
+                }
+#pragma unroll
+                for (int q = 0; q < kPB; ++q) put_h16<kSV>(buf + kPA * kPlaneU + q * kPlaneV + sto_v, va[q]);
+            };
+            constexpr int GA[kNG] = {0, 1, 0, 0, 1, 0, 2, 3, 2};
+            constexpr int GB[kNG] = {0, 1, 2, 3, 4, 5, 0, 1, 2};
+            auto mfma_chunk = [&](const h16 *buf) {
+                h16x8 af[kPA], bfr[kPB];
+#pragma unroll
+                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const h16x8 *>(buf + a * kPlaneU + fa);
+#pragma unroll
+                for (int q = 0; q < kPB; ++q)
+                    bfr[q] = *reinterpret_cast<const h16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb);
+#pragma unroll
+                for (int g = 0; g < kNG; ++g)
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[GA[g]], bfr[GB[g]], acc[g], 0, 0, 0);
+            };
+            auto buf_of = [&](int c) { return stage + (c & 1) * kStage; };
+            __syncthreads();                          // the previous tile's fragment reads are done
+            load_chunk(0, pr);
+            store_chunk(0, stage, nch == 1);
+            load_chunk(1, pr);
+            __syncthreads();
+            int ch = 0;
+            for (; ch + 2 < nch; ++ch) {
+                Raw q;
+                load_chunk(ch + 2, q);
+                mfma_chunk(buf_of(ch));
+                store_chunk(ch + 1, buf_of(ch + 1), false);
+                pr = q;
+                __syncthreads();
+            }
+            if (ch + 1 < nch) {
+                mfma_chunk(buf_of(ch));
+                store_chunk(ch + 1, buf_of(ch + 1), true);
+                __syncthreads();
+                ++ch;
+            }
+            mfma_chunk(buf_of(ch));
+
+            // epilogue: lane holds column j = lane % 32 and rows
+            // i = 8 (r / 4) + 4 (lane / 32) + (r % 4) of each 32 x 32 result
+            const int j = lane & 31;
+            const int64_t v = v0 + wv * 32 + j;
+            const bool vin = v < vcount;
+            const sisso_colstat vst = stats[vin ? v : 0];
+            const float4 vs0 = vsum[2 * (vin ? v : 0)];
+            const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w;
+            const VScale vc = v_scales(mv, mw, Svv, Sww, fn, 1.0f, shs);
+            const float iv = 1.0f / vc.v, ip = 1.0f / vc.p, iq = 1.0f / vc.q, iw = 1.0f / vc.w, ipw = 1.0f / vc.pw,
+                        iqw = 1.0f / vc.qw;
+            const bool vscal = col_scalable(Svv, Sww, fn, vst.minabs > 0.0f);
+            const int64_t v32 = vt * Sh::kWV + wv;
+            const int64_t u64 = (u0 + wu * 32) / 64;
+            const bool mom_in = (v32 >> 1) < nvt64 && u64 < nut64;
+            float *const mp = mom + (((size_t)u64 * nvt64 + (v32 >> 1)) * 4 + (wu & 1) + 2 * (int)(v32 & 1)) *
+                                        (16 * kMom * 64) + lane;
+            const int64_t tile_lo = binbase + (u0 * vcount + v0) * S;
+            const int64_t tile_hi = binbase + ((u0 + kBTU - 1) * vcount + v0 + kBTV - 1) * S + S;
+            const bool tile_in = tile_lo >= id_begin && tile_hi <= id_end;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+#pragma clang fp contract(off)
+                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const float4 us = ucon_a[wu * 32 + i], ui = ucon_c[wu * 32 + i];
+                const int uf = ucon_f[wu * 32 + i];
+                const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w;
+                auto var_of = [&](float s1, float g2, float g3, float ma, float mb, float sa, float sb) {
+                    const float t2 = 2.0f * ma * g3, t3 = mb * mb * sa, t4 = ma * ma * sb;
+                    const float var = (g2 + t2 + t3 + t4) - s1 * s1 / fn;
+                    const float mag = fabsf(g2) + fabsf(t2) + t3 + t4;
+                    return var >= kCondRel * mag && var < INFINITY ? var : -1.0f;
+                };
+                float m[kMom];
+                m[0] = (acc[0][r] * ui.x) * iv;                 // u v
+                m[1] = var_of(m[0], (acc[1][r] * ui.y) * ip, (acc[2][r] * ui.x) * iq, mu, mv, Suu, Svv);
+                m[2] = (acc[3][r] * ui.x) * iw;                 // u / v
+                m[3] = var_of(m[2], (acc[4][r] * ui.y) * ipw, (acc[5][r] * ui.x) * iqw, mu, mw, Suu, Sww);
+                m[4] = (acc[6][r] * ui.z) * iv;                 // v / u
+                m[5] = var_of(m[4], (acc[7][r] * ui.w) * ip, (acc[8][r] * ui.z) * iq, mz, mv, Szz, Svv);
+                if (mom_in) {
+#pragma unroll
+                    for (int k = 0; k < kMom; ++k) __builtin_nontemporal_store(m[k], mp + (r * kMom + k) * 64);
+                }
+                // the read form's conditioning decision, from the same values
+                const bool ok = (uf & 1) && vin && vst.valid != 0.0f;
+                const bool unscal = (uf & 4) != 0 || !vscal;
+                const float var[5] = {Suu + Svv + 2.0f * m[0], Suu + Svv - 2.0f * m[0], m[1], m[3], m[5]};
+                const bool dom[5] = {true, true, true, vst.minabs > 0.f, (uf & 2) != 0};
+                const float cth = kCondRel * (Suu + Svv);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const bool cand = ok && dom[k] && fs.slot[k] >= 0;
+                    const bool good = !unscal && (k < 2 ? var[k] >= cth : var[k] > 0.0f) && var[k] < INFINITY;
+                    if (cand && !good) {
+                        const int64_t id = binbase + ((u0 + wu * 32 + i) * vcount + v) * S + fs.slot[k];
+                        if (tile_in || (id >= id_begin && id < id_end)) {
+                            const unsigned long long q = atomicAdd(side.cnt, 1ull);
+                            if (q < (unsigned long long)side.cap) side.ids[q] = id;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+#endif  // SISSO_BF16_MFMA_PART
+
 #ifndef SISSO_BF16_MFMA_PART
 // --------------------------------------------------------------- rescore
 
@@ -1105,7 +1391,8 @@ struct BfPlan {
 
 constexpr int kMaxBfGrid = 1024;
 
-BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end, int max_grid = kMaxBfGrid)
+// u tiles of `tile` columns (the form's kBTU) covering the ids [begin, end)
+BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end, int max_grid = kMaxBfGrid, int tile = kBT)
 {
     BfPlan p;
     const int L = s->levels;
@@ -1114,8 +1401,8 @@ BfPlan bf_plan(const sisso_space *s, int64_t begin, int64_t end, int max_grid = 
     if (b >= e) return p;
     const int64_t per_u = s->pool[L - 1] * s->n_slots;
     const int64_t ul = (b - bb) / per_u, uh = (e - 1 - bb) / per_u + 1;
-    p.ut_lo = ul / kBT;
-    p.ut_hi = (uh + kBT - 1) / kBT;
+    p.ut_lo = ul / tile;
+    p.ut_hi = (uh + tile - 1) / tile;
     const int64_t tiles = p.ut_hi - p.ut_lo;
     p.grid = (int)(tiles < max_grid ? tiles : max_grid);
     return p;
@@ -1155,6 +1442,7 @@ extern "C" size_t sisso_bf16_operands_size(const sisso_space *space, int32_t n)
 extern "C" sisso_status sisso_prepare_bf16(const sisso_space *space, const sisso_score_args *args, void *ops,
                                            size_t ops_bytes, void *stream)
 {
+    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
     if (!space || !args || !ops || !args->pool32 || !args->stats) return SISSO_E_NULL;
     if (!space_ok(space)) return SISSO_E_UNSUPPORTED;
     if (args->n < 2 || args->n > SISSO_MAX_N || args->ld32 < args->n || (args->ld32 % 4) != 0) return SISSO_E_SHAPE;
@@ -1207,6 +1495,7 @@ sisso_status bf_check(const sisso_space *space, const sisso_score_args *args, in
 extern "C" sisso_status sisso_bf16_residual(const sisso_space *space, const sisso_score_args *args, int32_t band,
                                             void *bws, size_t bws_bytes, void *stream)
 {
+    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
     if (!bws) return SISSO_E_NULL;
     const sisso_status c = bf_check(space, args, band, bws_bytes);
     if (c != SISSO_OK) return c;
@@ -1229,11 +1518,12 @@ extern "C" sisso_status sisso_bf16_residual(const sisso_space *space, const siss
 
 namespace sisso {
 
-// One launch of a BF16 screening form (after the workspace reset).  The plain
-// and write forms are instantiated by the second build only.
+// One launch of a 16-bit screening form (after the workspace reset).  The
+// plain form is instantiated by the second build only.
 template <int MODE>
 sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, const BfOps &o, BfWs &w,
-                       int32_t band, int64_t cand_begin, int64_t cand_end, float *mom, BfSide side, hipStream_t st)
+                       int32_t band, int64_t cand_begin, int64_t cand_end, float *mom, const h16 *uimg, BfSide side,
+                       hipStream_t st)
 {
     using Sh = BfShape<MODE>;
     const int n = args->n;
@@ -1250,7 +1540,7 @@ sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, c
             return SISSO_E_DEVICE;
         max_grid = Sh::kMinBlocks * cus < kMaxBfGrid ? Sh::kMinBlocks * cus : kMaxBfGrid;   // the workspace's lists
     }
-    const BfPlan p = bf_plan(space, cand_begin, cand_end, max_grid);
+    const BfPlan p = bf_plan(space, cand_begin, cand_end, max_grid, Sh::kBTU);
     // Every block keeps min(band, K'max).  Only a block that keeps the whole
     // band may publish its threshold as the grid-wide bound (it is then a
     // lower bound of the band-th best score).
@@ -1260,13 +1550,13 @@ sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, c
     const int lcap = bf_lists_total(space, keep_b);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)2 * Sh::kStage * sizeof(h16) + 3 * Sh::kBTU * sizeof(float4) +
+        const size_t smem = (size_t)Sh::kNStage * Sh::kStage * sizeof(h16) + 3 * Sh::kBTU * sizeof(float4) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16<MODE>, smem)) return SISSO_E_UNSUPPORTED;
         hipLaunchKernelGGL(k_score_rect_bf16<MODE>, dim3(p.grid), dim3(Sh::kThreads), smem, st, *space, fs, n,
                            args->pool32, args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info,
                            args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, mom, w.vimg,
-                           side, w.lists, lcap, keep_b, cap_b, publish);
+                           uimg, side, w.lists, lcap, keep_b, cap_b, publish);
     }
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
@@ -1279,34 +1569,61 @@ int bf_screen_lists(const sisso_space *space, const sisso_score_args *args, int6
     int max_grid = args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid;
     if (BfShape<MODE>::kRead) max_grid = BfShape<MODE>::kMinBlocks * cus < kMaxBfGrid ? BfShape<MODE>::kMinBlocks * cus
                                                                                        : kMaxBfGrid;
-    return bf_plan(space, cand_begin, cand_end, max_grid).grid;
+    return bf_plan(space, cand_begin, cand_end, max_grid, BfShape<MODE>::kBTU).grid;
 }
 
 }  // namespace sisso
 
+namespace sisso {
+// The moments pass over the u tiles covering [cand_begin, cand_end): one
+// block per CU (its registers allow no more), each sweeping its share.
+sisso_status bf_launch_moments(const sisso_space *space, const sisso_score_args *args, const BfOps &o, BfWs &w,
+                               int64_t cand_begin, int64_t cand_end, float *mom, h16 *uimg, BfSide side,
+                               hipStream_t st)
+#ifdef SISSO_BF16_MFMA_PART
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return SISSO_E_DEVICE;
+    const BfPlan p = bf_plan(space, cand_begin, cand_end, cus, MomShape::kBTU);
+    if (p.grid > 0)
+        hipLaunchKernelGGL(k_bf_moments, dim3(p.grid), dim3(MomShape::kThreads), 0, st, *space, form_slots(space),
+                           args->n, args->pool32, args->ld32, o.usum, w.vsum, args->stats, p.ut_lo, p.ut_hi,
+                           cand_begin, cand_end, mom, uimg, side);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+#else
+    ;
+#endif
+}  // namespace sisso
+
 #ifdef SISSO_BF16_MFMA_PART
 template sisso_status sisso::bf_launch<kBfFull>(const sisso_space *, const sisso_score_args *, const BfOps &,
-                                                BfWs &, int32_t, int64_t, int64_t, float *, BfSide, hipStream_t);
-template sisso_status sisso::bf_launch<kBfWrite>(const sisso_space *, const sisso_score_args *, const BfOps &,
-                                                 BfWs &, int32_t, int64_t, int64_t, float *, BfSide, hipStream_t);
+                                                BfWs &, int32_t, int64_t, int64_t, float *, const h16 *, BfSide,
+                                                hipStream_t);
 #else
 extern template sisso_status sisso::bf_launch<kBfFull>(const sisso_space *, const sisso_score_args *, const BfOps &,
-                                                       BfWs &, int32_t, int64_t, int64_t, float *, BfSide,
-                                                       hipStream_t);
-extern template sisso_status sisso::bf_launch<kBfWrite>(const sisso_space *, const sisso_score_args *,
-                                                        const BfOps &, BfWs &, int32_t, int64_t, int64_t, float *,
-                                                        BfSide, hipStream_t);
+                                                       BfWs &, int32_t, int64_t, int64_t, float *, const h16 *,
+                                                       BfSide, hipStream_t);
 
 namespace {
 
 int64_t bf_tiles(int64_t cols) { return (cols + kBT - 1) / kBT; }
 
-// the moments of every pair, 256-byte aligned (the flagged candidates follow)
+// the moments of every pair, 256-byte aligned (the flagged candidates and
+// the u side's image follow)
 size_t bf_moments_bytes(const sisso_space *space)
 {
     const int L = space->levels;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
     return align256b((size_t)bf_tiles(ucols) * (size_t)bf_tiles(vcols) * kMomTile * sizeof(float));
+}
+size_t bf_uimg_offset(const sisso_space *space) { return bf_moments_bytes(space) + align256b(bf_side_bytes(*space)); }
+size_t bf_moments_total(const sisso_space *space, int n)
+{
+    const int L = space->levels;
+    return bf_uimg_offset(space) + align256b(bf_uimg_elems(space->pool[L] - space->pool[L - 1], n) * sizeof(h16));
 }
 
 sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, const void *ops, size_t ops_bytes,
@@ -1332,8 +1649,9 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     const int keep_b = bf_block_keep(band);
     BfWs w = bf_ws_view(bws, ucols, vcols, n, band, bf_lists_total(space, keep_b), keep_b);
     float *mom = (float *)moments;
-    // the flagged candidates: beside the moments (the READ form scores those a
-    // WRITE form stored), else in the workspace
+    h16 *const uimg = mode == SISSO_MOMENTS_NONE ? nullptr : (h16 *)((char *)moments + bf_uimg_offset(space));
+    // the flagged candidates: beside the moments (every pass of a fit scores
+    // those its first pass stored), else in the workspace
     const BfSide side = bf_side_view(mode == SISSO_MOMENTS_NONE ? w.side : (char *)moments + bf_moments_bytes(space),
                                      *space);
     if (mode != SISSO_MOMENTS_READ) hipLaunchKernelGGL(k_bf_side_reset, dim3(1), dim3(64), 0, st, side);
@@ -1345,15 +1663,18 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     int l0;
     switch (mode) {
     case SISSO_MOMENTS_WRITE:
-        rc = bf_launch<kBfWrite>(space, args, o, w, band, cand_begin, cand_end, mom, side, st);
-        l0 = bf_screen_lists<kBfWrite>(space, args, cand_begin, cand_end, cus);
+        // the moments pass stores the moments, the flagged candidates and the
+        // u side's image; the read form then scores the pass from them
+        rc = bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, side, st);
+        if (rc == SISSO_OK) rc = bf_launch<kBfRead>(space, args, o, w, band, cand_begin, cand_end, mom, uimg, side, st);
+        l0 = bf_screen_lists<kBfRead>(space, args, cand_begin, cand_end, cus);
         break;
     case SISSO_MOMENTS_READ:
-        rc = bf_launch<kBfRead>(space, args, o, w, band, cand_begin, cand_end, mom, side, st);
+        rc = bf_launch<kBfRead>(space, args, o, w, band, cand_begin, cand_end, mom, uimg, side, st);
         l0 = bf_screen_lists<kBfRead>(space, args, cand_begin, cand_end, cus);
         break;
     default:
-        rc = bf_launch<kBfFull>(space, args, o, w, band, cand_begin, cand_end, nullptr, side, st);
+        rc = bf_launch<kBfFull>(space, args, o, w, band, cand_begin, cand_end, nullptr, nullptr, side, st);
         l0 = bf_screen_lists<kBfFull>(space, args, cand_begin, cand_end, cus);
     }
     if (rc != SISSO_OK) return rc;
@@ -1369,13 +1690,14 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
 extern "C" size_t sisso_bf16_moments_size(const sisso_space *space, int32_t n)
 {
     if (!space_ok(space) || n < 2 || n > SISSO_MAX_N) return 0;
-    return bf_moments_bytes(space) + bf_side_bytes(*space);
+    return bf_moments_total(space, n);
 }
 
 extern "C" sisso_status sisso_bf16_screen(const sisso_space *space, const sisso_score_args *args, const void *ops,
                                           size_t ops_bytes, int32_t band, int64_t cand_begin, int64_t cand_end,
                                           void *bws, size_t bws_bytes, void *stream)
 {
+    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
     return bf_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, nullptr, 0, SISSO_MOMENTS_NONE, bws,
                      bws_bytes, stream);
 }
@@ -1386,6 +1708,7 @@ extern "C" sisso_status sisso_bf16_screen_moments(const sisso_space *space, cons
                                                   size_t moments_bytes, int32_t mode, void *bws, size_t bws_bytes,
                                                   void *stream)
 {
+    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
     return bf_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, moments, moments_bytes, mode, bws,
                      bws_bytes, stream);
 }
@@ -1393,6 +1716,7 @@ extern "C" sisso_status sisso_bf16_screen_moments(const sisso_space *space, cons
 extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso_score_args *args, int32_t band,
                                            void *bws, size_t bws_bytes, void *ws, size_t ws_bytes, void *stream)
 {
+    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
     if (!bws || !ws) return SISSO_E_NULL;
     const sisso_status c = bf_check(space, args, band, bws_bytes);
     if (c != SISSO_OK) return c;
@@ -1425,6 +1749,7 @@ extern "C" sisso_status sisso_expand_score_bf16(const sisso_space *space, const 
                                                 int64_t cand_end, void *bws, size_t bws_bytes, void *ws,
                                                 size_t ws_bytes, void *stream)
 {
+    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
     sisso_status st = sisso_bf16_residual(space, args, band, bws, bws_bytes, stream);
     if (st != SISSO_OK) return st;
     st = sisso_bf16_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, bws, bws_bytes, stream);

@@ -38,6 +38,48 @@ __device__ inline void standardize_column(const double *x, int n, double *z, dou
     __syncthreads();
 }
 
+// standardize_column under sample weights wt (nullable: the unweighted
+// form): weighted mean mu = sum w x / sum w and
+// z = sqrt(w) (x - mu) / sqrt(sum w (x - mu)^2), so that z_a . z_b is the
+// weighted correlation of two columns (Sec. 2.4: whitening by
+// W = Sigma^(-1/2) with the intercept whitened too).  norm_out receives
+// sqrt(sum w (x - mu)^2).  Weights must be positive; `ok` also fails for a
+// non-finite weight.
+__device__ inline void standardize_column_w(const double *x, const double *wt, int n, double *z, double *mean_out,
+                                            double *norm_out, int *ok_out, double *red)
+{
+    if (!wt) {
+        standardize_column(x, n, z, mean_out, norm_out, ok_out, red);
+        return;
+    }
+    double s = 0.0, sw = 0.0;
+    int bad = 0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double v = x[t], w = wt[t];
+        if (!isfinite(v) || !isfinite(w)) bad = 1;
+        s += w * v;
+        sw += w;
+    }
+    bad = __syncthreads_or(bad);
+    const double W = block_sum(sw, red);
+    const double mean = block_sum(s, red) / W;
+    double ss = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double e = x[t] - mean;
+        ss += wt[t] * e * e;
+    }
+    const double sst = block_sum(ss, red);
+    const bool ok = !bad && sst > 0.0;
+    const double inv = ok ? 1.0 / sqrt(sst) : 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) z[t] = ok ? sqrt(wt[t]) * (x[t] - mean) * inv : 0.0;
+    if (threadIdx.x == 0) {
+        if (mean_out) *mean_out = mean;
+        if (norm_out) *norm_out = ok ? sqrt(sst) : 0.0;
+        if (ok_out) *ok_out = ok ? 1 : 0;
+    }
+    __syncthreads();
+}
+
 constexpr int kGT = 32;    // output tile
 constexpr int kGK = 16;    // samples per LDS chunk
 

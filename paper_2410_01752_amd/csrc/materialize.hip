@@ -335,6 +335,49 @@ __global__ void __launch_bounds__(1024) k_prepare_residual(const double *__restr
     prepare_residual_block(r, n, r32, info, red);
 }
 
+// Weighted residual of a pass under sample weights (Sec. 2.4, whitening with
+// a diagonal covariance): weights scaled to mean 1 (wn = w n / sum w), the
+// weighted mean mu of r, r32 = wn (r - mu) in FP32 and its sums (one block).
+// A weight that is not positive and finite poisons s_rr with NaN.
+__global__ void __launch_bounds__(1024) k_prepare_residual_weighted(const double *__restrict__ r,
+                                                                    const double *__restrict__ w, int n,
+                                                                    float *__restrict__ r32,
+                                                                    float *__restrict__ w32,
+                                                                    sisso_resid_info *__restrict__ info)
+{
+    __shared__ double red[16];
+    double sw = 0.0, swr = 0.0;
+    int bad = 0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double wt = w[t];
+        if (!(wt > 0.0) || !isfinite(wt)) bad = 1;
+        sw += wt;
+        swr += wt * r[t];
+    }
+    bad = __syncthreads_or(bad);
+    const double W = block_sum(sw, red);
+    const double mean = block_sum(swr, red) / W;
+    const double scale = (double)n / W;
+    double s32 = 0.0, ss = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double wn = w[t] * scale;
+        const double e = r[t] - mean;
+        const float v = (float)(wn * e);
+        r32[t] = v;
+        w32[t] = (float)wn;
+        s32 += (double)v;
+        ss += wn * e * e;
+    }
+    const double sum32 = block_sum(s32, red);
+    const double srr = block_sum(ss, red);
+    if (threadIdx.x == 0) {
+        info->sum_r32 = sum32;
+        info->s_rr = bad ? NAN : srr;
+        info->mean_r = mean;
+        info->n = (double)n;
+    }
+}
+
 // One block per problem of a batch; entries with a bad n or a null pointer
 // are left untouched (the batched screening flags them).
 __global__ void __launch_bounds__(1024) k_prepare_residual_batch(const sisso_problem *__restrict__ probs)
@@ -407,6 +450,16 @@ extern "C" sisso_status sisso_prepare_residual(const double *r, int32_t n, float
     if (!r || !r32 || !info) return SISSO_E_NULL;
     if (n < 2 || n > SISSO_MAX_N) return SISSO_E_SHAPE;
     hipLaunchKernelGGL(k_prepare_residual, dim3(1), dim3(1024), 0, as_stream(stream), r, n, r32, info);
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_prepare_residual_weighted(const double *r, const double *w, int32_t n, float *r32,
+                                                        float *w32, sisso_resid_info *info, void *stream)
+{
+    if (!r || !w || !r32 || !w32 || !info) return SISSO_E_NULL;
+    if (n < 2 || n > SISSO_MAX_N) return SISSO_E_SHAPE;
+    hipLaunchKernelGGL(k_prepare_residual_weighted, dim3(1), dim3(1024), 0, as_stream(stream), r, w, n, r32, w32,
+                       info);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 

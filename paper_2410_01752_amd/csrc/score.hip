@@ -43,13 +43,13 @@ __global__ void k_ws_append(WsHeader *h, int n_lists)
 
 // ------------------------------------------------------ pool columns kernel
 
-template <int NU>
+template <int NU, bool WT>
 __global__ void __launch_bounds__(256) k_score_columns(
     sisso_space s, int n, const float *__restrict__ pool32, int64_t ld32,
     const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl,
     int64_t c_lo, int64_t c_hi, int64_t id_begin, int64_t id_end, int list_base, void *ws,
-    int lists_total, int keep, int cap)
+    int lists_total, int keep, int cap, const float *__restrict__ w32)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     WsView W = ws_view(ws, lists_total, keep);
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_score_columns(
     // n <= 256 kColRegs: the residual stays in registers and each column is
     // loaded whole, one column ahead of the one being scored
     const bool regs = n <= 256 * kColRegs;
-    float4 rv[kColRegs], cur[kColRegs], nxt[kColRegs];
+    float4 rv[kColRegs], wv[kColRegs], cur[kColRegs], nxt[kColRegs];
     auto load_col = [&](int64_t c, float4 (&dst)[kColRegs]) {
         const float *col = pool32 + (size_t)c * ld32;
 #pragma unroll
@@ -93,6 +93,8 @@ __global__ void __launch_bounds__(256) k_score_columns(
         for (int k = 0; k < kColRegs; ++k) {
             const int t = lane * 4 + 256 * k;
             rv[k] = t < n ? *reinterpret_cast<const float4 *>(r32 + t) : make_float4(0.f, 0.f, 0.f, 0.f);
+            wv[k] = make_float4(1.f, 1.f, 1.f, 1.f);
+            if (WT && t < n) wv[k] = *reinterpret_cast<const float4 *>(w32 + t);
         }
     }
 
@@ -109,11 +111,11 @@ __global__ void __launch_bounds__(256) k_score_columns(
             if (c < c_hi) {
                 const sisso_colstat st = stats[c];
                 if (regs)
-                    score_column_regs<NU, kColRegs>(cur, rv, st, n, nd, R1, Srr, uop, nu,
-                                                    NU > 0 && rect && c >= newlo, scs);
+                    score_column_regs<NU, kColRegs, WT>(cur, rv, wv, st, n, nd, R1, Srr, uop, nu,
+                                                        NU > 0 && rect && c >= newlo, scs);
                 else
-                    score_column<NU>(pool32 + (size_t)c * ld32, st, r32, n, nd, R1, Srr, uop, nu,
-                                     NU > 0 && rect && c >= newlo, scs);
+                    score_column<NU, WT>(pool32 + (size_t)c * ld32, st, r32, n, nd, R1, Srr, uop, nu,
+                                         NU > 0 && rect && c >= newlo, scs, w32);
                 if (!(c >= id_begin && c < id_end)) scs[0] = -1.0f;
 #pragma unroll
                 for (int o = 0; o < NU; ++o) {
@@ -151,13 +153,13 @@ __global__ void __launch_bounds__(256) k_score_columns(
 
 // --------------------------------------------------------- binary slice
 
-template <int RU, int RV>
+template <int RU, int RV, bool WT>
 __global__ void __launch_bounds__(256) k_score_rect(
     sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
     const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl,
     int64_t ut_lo, int64_t ut_hi, int64_t id_begin, int64_t id_end, int list_base, void *ws,
-    int lists_total, int keep, int cap)
+    int lists_total, int keep, int cap, const float *__restrict__ w32)
 {
     using Cfg = RectCfg<RU, RV>;
     constexpr int TU = Cfg::TU, TV = Cfg::TV;
@@ -190,8 +192,8 @@ __global__ void __launch_bounds__(256) k_score_rect(
         for (int64_t vt = 0; vt < nvt; ++vt) {
             float osc[RU * RV * 5];
             int64_t oid[RU * RV * 5];
-            score_pair_tile<RU, RV>(pool32, ld32, stats, r32, n, nd, R1, Srr, fs, ids, u0, U, vt * TV, vcount,
-                                    id_begin, id_end, buf0, buf1, osc, oid);
+            score_pair_tile<RU, RV, WT>(pool32, ld32, stats, r32, n, nd, R1, Srr, fs, ids, u0, U, vt * TV,
+                                        vcount, id_begin, id_end, buf0, buf1, osc, oid, w32);
             list_offer<RU * RV * 5>(L, osc, oid, &W.h->gthr, excl, n_excl);
         }
     }
@@ -497,6 +499,7 @@ extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso
 
     const Plan p = make_plan(space, args, cand_begin, cand_end);
     if (args->list_base < 0 || args->list_base + p.g_cols + p.g_rect > lists) return SISSO_E_WORKSPACE;
+    const bool weighted = args->w32 != nullptr;
     hipStream_t st = as_stream(stream);
     const int keep = args->keep, cap = list_cap(keep);
     const int base = args->list_base;
@@ -508,18 +511,20 @@ extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso
     const size_t lsmem = (size_t)cap * (sizeof(float) + sizeof(int64_t));
     if (p.g_cols > 0) {
         const int nu = space->rect ? space->n_unary : 0;
-        if (nu == 0)
-            hipLaunchKernelGGL(k_score_columns<0>, dim3(p.g_cols), dim3(256), lsmem, st, *space, args->n,
-                               args->pool32, args->ld32, args->stats, args->r32, args->info, args->exclude,
-                               args->n_exclude, p.c_lo, p.c_hi, cand_begin, cand_end, base, ws, lists, keep, cap);
-        else if (nu <= 3)
-            hipLaunchKernelGGL(k_score_columns<3>, dim3(p.g_cols), dim3(256), lsmem, st, *space, args->n,
-                               args->pool32, args->ld32, args->stats, args->r32, args->info, args->exclude,
-                               args->n_exclude, p.c_lo, p.c_hi, cand_begin, cand_end, base, ws, lists, keep, cap);
-        else
-            hipLaunchKernelGGL(k_score_columns<8>, dim3(p.g_cols), dim3(256), lsmem, st, *space, args->n,
-                               args->pool32, args->ld32, args->stats, args->r32, args->info, args->exclude,
-                               args->n_exclude, p.c_lo, p.c_hi, cand_begin, cand_end, base, ws, lists, keep, cap);
+        auto launch_cols = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(p.g_cols), dim3(256), lsmem, st, *space, args->n, args->pool32, args->ld32,
+                               args->stats, args->r32, args->info, args->exclude, args->n_exclude, p.c_lo, p.c_hi,
+                               cand_begin, cand_end, base, ws, lists, keep, cap, args->w32);
+        };
+        if (!weighted) {
+            if (nu == 0) launch_cols(k_score_columns<0, false>);
+            else if (nu <= 3) launch_cols(k_score_columns<3, false>);
+            else launch_cols(k_score_columns<8, false>);
+        } else {
+            if (nu == 0) launch_cols(k_score_columns<0, true>);
+            else if (nu <= 3) launch_cols(k_score_columns<3, true>);
+            else launch_cols(k_score_columns<8, true>);
+        }
         if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
     }
     if (p.g_rect > 0) {
@@ -529,13 +534,20 @@ extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso
             if (!allow_dynamic_lds(kern, smem)) return SISSO_E_UNSUPPORTED;
             hipLaunchKernelGGL(kern, dim3(p.g_rect), dim3(256), smem, st, *space, fs, args->n, args->pool32,
                                args->ld32, args->stats, args->r32, args->info, args->exclude, args->n_exclude,
-                               p.ut_lo, p.ut_hi, cand_begin, cand_end, base + p.g_cols, ws, lists, keep, cap);
+                               p.ut_lo, p.ut_hi, cand_begin, cand_end, base + p.g_cols, ws, lists, keep, cap,
+                               args->w32);
             return SISSO_OK;
         };
         sisso_status rs;
-        if (p.ru == 2 && p.rv == 2) rs = launch(k_score_rect<2, 2>);
-        else if (p.ru == 2 && p.rv == 1) rs = launch(k_score_rect<2, 1>);
-        else rs = launch(k_score_rect<1, 2>);
+        if (!weighted) {
+            if (p.ru == 2 && p.rv == 2) rs = launch(k_score_rect<2, 2, false>);
+            else if (p.ru == 2 && p.rv == 1) rs = launch(k_score_rect<2, 1, false>);
+            else rs = launch(k_score_rect<1, 2, false>);
+        } else {
+            if (p.ru == 2 && p.rv == 2) rs = launch(k_score_rect<2, 2, true>);
+            else if (p.ru == 2 && p.rv == 1) rs = launch(k_score_rect<2, 1, true>);
+            else rs = launch(k_score_rect<1, 2, true>);
+        }
         if (rs != SISSO_OK) return rs;
         if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
     }

@@ -156,27 +156,40 @@ __device__ inline float form_score(int k, float fA, double dB, double dC, double
 // returns the score, -1 if the column is invalid).  Lane l accumulates the
 // samples l*4 + 256 j in FP32; the wave sum is taken in FP64.  The single-
 // problem and batched screening kernels use this same sequence of operations.
-__device__ inline float score_stored_column(const float *col, const float *r32, int n, float mean, bool valid,
-                                            double nd, double R1, double Srr)
+// WT: A and B are weighted by the sample weights w32 (Sec. 2.4 whitening with
+// a diagonal covariance; the residual of such a pass carries its weights).
+template <bool WT>
+__device__ inline float score_stored_column_t(const float *col, const float *r32, const float *w32, int n,
+                                              float mean, bool valid, double nd, double R1, double Srr)
 {
     const int lane = threadIdx.x & 63;
     float a0 = 0.f, b0 = 0.f, c0 = 0.f;
     for (int t = lane * 4; t < n; t += 256) {
         const float4 fv = *reinterpret_cast<const float4 *>(col + t);
         const float4 rv = *reinterpret_cast<const float4 *>(r32 + t);
+        float4 wv = make_float4(1.f, 1.f, 1.f, 1.f);
+        if (WT) wv = *reinterpret_cast<const float4 *>(w32 + t);
         const float fa[4] = {fv.x, fv.y, fv.z, fv.w};
         const float ra[4] = {rv.x, rv.y, rv.z, rv.w};
+        const float wa[4] = {wv.x, wv.y, wv.z, wv.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             if (t + e < n) {
                 const float g = fa[e] - mean;
-                a0 += g;
-                b0 = fmaf(g, g, b0);
+                const float wg = WT ? wa[e] * g : g;
+                a0 += wg;
+                b0 = fmaf(wg, g, b0);
                 c0 = fmaf(g, ra[e], c0);
             }
     }
     const double A = wave_sum_dpp((double)a0), B = wave_sum_dpp((double)b0), C = wave_sum_dpp((double)c0);
     return valid ? score_from_sums(A, B, C, (double)mean, nd, R1, Srr) : -1.0f;
+}
+
+__device__ inline float score_stored_column(const float *col, const float *r32, int n, float mean, bool valid,
+                                            double nd, double R1, double Srr)
+{
+    return score_stored_column_t<false>(col, r32, nullptr, n, mean, valid, nd, R1, Srr);
 }
 
 int score_lists_capacity(const sisso_space *s, const sisso_score_args *a);

@@ -21,6 +21,7 @@ struct SubWs {
     double *score;    // FP64 score per node (candidates)
     int *ok;          // per node
     int *parent;      // union-find forest over the nodes
+    const double *wt; // sample weights (nullable: unweighted)
     int ldz;
 };
 
@@ -51,13 +52,14 @@ __host__ __device__ inline SubWs sub_ws_view(void *ws, int n, int nodes)
     off = (off + 255) & ~(size_t)255;
     p = (char *)ws + off;
     w.parent = (int *)p;
+    w.wt = nullptr;
     return w;
 }
 
 __device__ inline void sub_resid(const double *__restrict__ r, int n, SubWs w)
 {
     __shared__ double red[16];
-    standardize_column(r, n, w.zr, nullptr, nullptr, nullptr, red);
+    standardize_column_w(r, w.wt, n, w.zr, nullptr, nullptr, nullptr, red);
 }
 
 // node q < m_prev: subspace column; else candidate q - m_prev.
@@ -80,7 +82,7 @@ __device__ inline void sub_standardize(const double *__restrict__ sub, int lds, 
     }
     int okc;
     __shared__ int okc_s;
-    standardize_column(x, n, z, nullptr, nullptr, &okc_s, red);
+    standardize_column_w(x, w.wt, n, z, nullptr, nullptr, &okc_s, red);
     okc = okc_s;
     double d = 0.0;
     for (int t = threadIdx.x; t < n; t += blockDim.x) d += z[t] * w.zr[t];
@@ -421,12 +423,12 @@ static size_t classes_smem(int nodes)
            (size_t)next_pow2(nodes) * (sizeof(double) + sizeof(int64_t));
 }
 
-extern "C" sisso_status sisso_subspace_update(const double *cand, int32_t ldc, const int64_t *cand_ids,
-                                              const int32_t *cand_valid, const int32_t *count_dev,
-                                              int32_t count_max, const double *r, int32_t n, double *sub,
-                                              int32_t lds, int64_t *sub_ids, int32_t m_prev, int32_t k,
-                                              int32_t *n_new, int32_t *n_classes, void *ws, size_t ws_bytes,
-                                              void *stream)
+extern "C" sisso_status sisso_subspace_update_weighted(const double *cand, int32_t ldc, const int64_t *cand_ids,
+                                                       const int32_t *cand_valid, const int32_t *count_dev,
+                                                       int32_t count_max, const double *r, const double *wts,
+                                                       int32_t n, double *sub, int32_t lds, int64_t *sub_ids,
+                                                       int32_t m_prev, int32_t k, int32_t *n_new, int32_t *n_classes,
+                                                       void *ws, size_t ws_bytes, void *stream)
 {
     if (!cand || !cand_ids || !cand_valid || !count_dev || !r || !sub || !sub_ids || !n_new || !n_classes || !ws)
         return SISSO_E_NULL;
@@ -437,6 +439,7 @@ extern "C" sisso_status sisso_subspace_update(const double *cand, int32_t ldc, c
     if (ws_bytes < sisso_subspace_workspace_size(n, count_max, m_prev)) return SISSO_E_WORKSPACE;
     hipStream_t st = as_stream(stream);
     SubWs w = sub_ws_view(ws, n, nodes);
+    w.wt = wts;
     int *new_src = (int *)((char *)ws + sub_ws_bytes(n, nodes));
     hipLaunchKernelGGL(k_sub_resid, dim3(1), dim3(256), 0, st, r, n, w);
     hipLaunchKernelGGL(k_sub_standardize, dim3(nodes), dim3(256), 0, st, sub, lds, m_prev, cand, ldc, cand_valid,
@@ -450,6 +453,17 @@ extern "C" sisso_status sisso_subspace_update(const double *cand, int32_t ldc, c
                        n_classes, new_src, w);
     hipLaunchKernelGGL(k_sub_gather, dim3(k), dim3(256), 0, st, cand, ldc, new_src, n_new, n, sub, lds, m_prev);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+
+extern "C" sisso_status sisso_subspace_update(const double *cand, int32_t ldc, const int64_t *cand_ids,
+                                              const int32_t *cand_valid, const int32_t *count_dev,
+                                              int32_t count_max, const double *r, int32_t n, double *sub,
+                                              int32_t lds, int64_t *sub_ids, int32_t m_prev, int32_t k,
+                                              int32_t *n_new, int32_t *n_classes, void *ws, size_t ws_bytes,
+                                              void *stream)
+{
+    return sisso_subspace_update_weighted(cand, ldc, cand_ids, cand_valid, count_dev, count_max, r, nullptr, n, sub,
+                                          lds, sub_ids, m_prev, k, n_new, n_classes, ws, ws_bytes, stream);
 }
 
 extern "C" sisso_status sisso_sort_subspace(const double *src, int32_t lds, const int64_t *ids, int32_t m,

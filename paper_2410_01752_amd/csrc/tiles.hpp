@@ -16,18 +16,21 @@ constexpr int kColRegs = 8;        // float4 per lane of a register-resident col
 // Score of a stored column (scs[0]) and of its unary children (scs[1 + o] for
 // the o-th unary operator, when do_unary), -1 where invalid.  One wave per
 // column; every lane returns the same values.  The column's shift is its mean;
-// a unary child's shift is its mean over the first 256 samples.
-template <int NU>
+// a unary child's shift is its mean over the first 256 samples.  WT: sample
+// weights w32 (mean 1) enter the sums A and B (the residual of a weighted
+// pass already carries them).
+template <int NU, bool WT = false>
 __device__ __forceinline__ void score_column(const float *__restrict__ col, const sisso_colstat &st,
                                              const float *__restrict__ r32, int n, double nd, double R1,
                                              double Srr, const int (&uop)[NU > 0 ? NU : 1], int nu,
-                                             bool do_unary, float (&scs)[1 + NU])
+                                             bool do_unary, float (&scs)[1 + NU],
+                                             const float *__restrict__ w32 = nullptr)
 {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int o = 0; o < 1 + NU; ++o) scs[o] = -1.0f;
     if (NU == 0 || !do_unary) {
-        scs[0] = score_stored_column(col, r32, n, st.mean, st.valid != 0.0f, nd, R1, Srr);
+        scs[0] = score_stored_column_t<WT>(col, r32, w32, n, st.mean, st.valid != 0.0f, nd, R1, Srr);
         return;
     }
     const float f0 = st.mean;
@@ -59,20 +62,25 @@ __device__ __forceinline__ void score_column(const float *__restrict__ col, cons
     for (int t = lane * 4; t < n; t += 256) {
         const float4 fv = *reinterpret_cast<const float4 *>(col + t);
         const float4 rv = *reinterpret_cast<const float4 *>(r32 + t);
+        float4 wv = make_float4(1.f, 1.f, 1.f, 1.f);
+        if (WT) wv = *reinterpret_cast<const float4 *>(w32 + t);
         const float fa[4] = {fv.x, fv.y, fv.z, fv.w};
         const float ra[4] = {rv.x, rv.y, rv.z, rv.w};
+        const float wa[4] = {wv.x, wv.y, wv.z, wv.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             if (t + e < n) {
                 const float g = fa[e] - f0;
-                a0 += g; b0s = fmaf(g, g, b0s); c0 = fmaf(g, ra[e], c0);
+                const float wg = WT ? wa[e] * g : g;
+                a0 += wg; b0s = fmaf(wg, g, b0s); c0 = fmaf(g, ra[e], c0);
 #pragma unroll
                 for (int o = 0; o < NU; ++o) {
                     if (o < nu) {
                         const float h = unary32(uop[o], fa[e]);
                         badu |= (!(fabsf(h) <= 1e15f)) << o;
                         const float gu = h - sh[o];
-                        au[o] += gu; bu[o] = fmaf(gu, gu, bu[o]); cu[o] = fmaf(gu, ra[e], cu[o]);
+                        const float wgu = WT ? wa[e] * gu : gu;
+                        au[o] += wgu; bu[o] = fmaf(wgu, gu, bu[o]); cu[o] = fmaf(gu, ra[e], cu[o]);
                     }
                 }
             }
@@ -98,9 +106,10 @@ __device__ __forceinline__ void score_column(const float *__restrict__ col, cons
 // sum g, sum g^2, sum g r of g = op(f) - shift, in the order score_column
 // takes them.  OP is a compile-time operator so the loop stays small enough
 // to unroll and the column stays in registers.
-template <int OP, int KR>
-__device__ __forceinline__ void unary_child_sums(const float4 (&fv)[KR], const float4 (&rv)[KR], int n,
-                                                 float &shift, float &au, float &bu, float &cu, bool &bad)
+template <int OP, int KR, bool WT = false>
+__device__ __forceinline__ void unary_child_sums(const float4 (&fv)[KR], const float4 (&rv)[KR],
+                                                 const float4 (&wv)[KR], int n, float &shift, float &au, float &bu,
+                                                 float &cu, bool &bad)
 {
     const int lane = threadIdx.x & 63;
     {
@@ -124,13 +133,15 @@ __device__ __forceinline__ void unary_child_sums(const float4 (&fv)[KR], const f
         if (t < n) {
             const float fa[4] = {fv[k].x, fv[k].y, fv[k].z, fv[k].w};
             const float ra[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
+            const float wa[4] = {wv[k].x, wv[k].y, wv[k].z, wv[k].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 if (t + e < n) {
                     const float h = unary32(OP, fa[e]);
                     bad |= !(fabsf(h) <= 1e15f);
                     const float gu = h - shift;
-                    au += gu; bu = fmaf(gu, gu, bu); cu = fmaf(gu, ra[e], cu);
+                    const float wgu = WT ? wa[e] * gu : gu;
+                    au += wgu; bu = fmaf(wgu, gu, bu); cu = fmaf(gu, ra[e], cu);
                 }
         }
     }
@@ -140,11 +151,12 @@ __device__ __forceinline__ void unary_child_sums(const float4 (&fv)[KR], const f
 // registers: float4 k of a lane holds samples lane * 4 + 256 k .. + 3
 // (zero past n), for n <= 256 * KR.  Every sum takes the same operations in
 // the same order as score_column, so the two give identical scores.
-template <int NU, int KR>
+template <int NU, int KR, bool WT = false>
 __device__ __forceinline__ void score_column_regs(const float4 (&fv)[KR], const float4 (&rv)[KR],
-                                                  const sisso_colstat &st, int n, double nd, double R1,
-                                                  double Srr, const int (&uop)[NU > 0 ? NU : 1], int nu,
-                                                  bool do_unary, float (&scs)[1 + NU])
+                                                  const float4 (&wv)[KR], const sisso_colstat &st, int n,
+                                                  double nd, double R1, double Srr,
+                                                  const int (&uop)[NU > 0 ? NU : 1], int nu, bool do_unary,
+                                                  float (&scs)[1 + NU])
 {
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -157,11 +169,13 @@ __device__ __forceinline__ void score_column_regs(const float4 (&fv)[KR], const 
         if (t < n) {
             const float fa[4] = {fv[k].x, fv[k].y, fv[k].z, fv[k].w};
             const float ra[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
+            const float wa[4] = {wv[k].x, wv[k].y, wv[k].z, wv[k].w};
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 if (t + e < n) {
                     const float g = fa[e] - f0;
-                    a0 += g; b0s = fmaf(g, g, b0s); c0 = fmaf(g, ra[e], c0);
+                    const float wg = WT ? wa[e] * g : g;
+                    a0 += wg; b0s = fmaf(wg, g, b0s); c0 = fmaf(g, ra[e], c0);
                 }
         }
     }
@@ -174,15 +188,15 @@ __device__ __forceinline__ void score_column_regs(const float4 (&fv)[KR], const 
         float sh = 0.f, au = 0.f, bu = 0.f, cu = 0.f;
         bool bad = false;
         switch (uop[o]) {
-        case SISSO_SQ: unary_child_sums<SISSO_SQ, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
-        case SISSO_CUBE: unary_child_sums<SISSO_CUBE, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
-        case SISSO_SQRT: unary_child_sums<SISSO_SQRT, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
-        case SISSO_INV: unary_child_sums<SISSO_INV, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
-        case SISSO_EXP: unary_child_sums<SISSO_EXP, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
-        case SISSO_NEXP: unary_child_sums<SISSO_NEXP, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
-        case SISSO_LOG: unary_child_sums<SISSO_LOG, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
-        case SISSO_SIN: unary_child_sums<SISSO_SIN, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
-        default: unary_child_sums<-1, KR>(fv, rv, n, sh, au, bu, cu, bad); break;
+        case SISSO_SQ: unary_child_sums<SISSO_SQ, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
+        case SISSO_CUBE: unary_child_sums<SISSO_CUBE, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
+        case SISSO_SQRT: unary_child_sums<SISSO_SQRT, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
+        case SISSO_INV: unary_child_sums<SISSO_INV, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
+        case SISSO_EXP: unary_child_sums<SISSO_EXP, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
+        case SISSO_NEXP: unary_child_sums<SISSO_NEXP, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
+        case SISSO_LOG: unary_child_sums<SISSO_LOG, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
+        case SISSO_SIN: unary_child_sums<SISSO_SIN, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
+        default: unary_child_sums<-1, KR, WT>(fv, rv, wv, n, sh, au, bu, cu, bad); break;
         }
         const bool anybad = wave_or_dpp(bad ? 1 : 0) != 0;
         const double Au = wave_sum_dpp((double)au), Bu = wave_sum_dpp((double)bu), Cu = wave_sum_dpp((double)cu);
@@ -198,7 +212,7 @@ template <int RU, int RV>
 struct RectCfg {
     static constexpr int TU = 16 * RU, TV = 16 * RV;
     static constexpr int TUP = TU + 4, TVP = TV + 4;
-    static constexpr int BUF = kSC * (3 * TUP + 3 * TVP) + kSC;   // floats per buffer
+    static constexpr int BUF = kSC * (3 * TUP + 3 * TVP) + 2 * kSC;   // floats per buffer (+ r, w chunks)
 };
 
 // Canonical id of binary candidate (u, v, slot) of a pair block.
@@ -256,12 +270,13 @@ __device__ __forceinline__ void load_uside(USide<RU, RV> &U, const sisso_colstat
 // TRI mode only v < u is a candidate.  Sample chunks of kSC samples of both
 // operand tiles and of r are staged through LDS (buf0/buf1, double
 // buffered); the forms are evaluated in registers.  Block-uniform call.
-template <int RU, int RV>
+template <int RU, int RV, bool WT = false>
 __device__ __forceinline__ void score_pair_tile(
     const float *__restrict__ pool32, int64_t ld32, const sisso_colstat *__restrict__ stats,
     const float *__restrict__ r32, int n, double nd, double R1, double Srr, const FormSlots &fs,
     const PairIds &ids, int64_t u0, const USide<RU, RV> &U, int64_t v0, int64_t vcount, int64_t id_begin,
-    int64_t id_end, float *buf0, float *buf1, float (&osc)[RU * RV * 5], int64_t (&oid)[RU * RV * 5])
+    int64_t id_end, float *buf0, float *buf1, float (&osc)[RU * RV * 5], int64_t (&oid)[RU * RV * 5],
+    const float *__restrict__ w32 = nullptr)
 {
     using Cfg = RectCfg<RU, RV>;
     constexpr int TU = Cfg::TU, TV = Cfg::TV, TUP = Cfg::TUP, TVP = Cfg::TVP;
@@ -304,6 +319,7 @@ __device__ __forceinline__ void score_pair_tile(
 
     // register prefetch of one chunk
     float4 pu = make_float4(0, 0, 0, 0), pv = make_float4(0, 0, 0, 0), pr = make_float4(0, 0, 0, 0);
+    float4 pw = make_float4(0, 0, 0, 0);
     auto load_chunk = [&](int ch) {
         const int t0 = ch * kSC + squad * 4;
         pu = make_float4(0, 0, 0, 0);
@@ -315,6 +331,7 @@ __device__ __forceinline__ void score_pair_tile(
         if (tid < kSC / 4) {
             const int tr = ch * kSC + tid * 4;
             pr = tr < n ? *reinterpret_cast<const float4 *>(r32 + tr) : make_float4(0, 0, 0, 0);
+            if (WT) pw = tr < n ? *reinterpret_cast<const float4 *>(w32 + tr) : make_float4(0, 0, 0, 0);
         }
     };
     auto store_chunk = [&](float *bf) {
@@ -340,6 +357,11 @@ __device__ __forceinline__ void score_pair_tile(
         if (tid < kSC / 4) {
             R[tid * 4 + 0] = pr.x; R[tid * 4 + 1] = pr.y;
             R[tid * 4 + 2] = pr.z; R[tid * 4 + 3] = pr.w;
+            if (WT) {
+                float *Wc = R + kSC;
+                Wc[tid * 4 + 0] = pw.x; Wc[tid * 4 + 1] = pw.y;
+                Wc[tid * 4 + 2] = pw.z; Wc[tid * 4 + 3] = pw.w;
+            }
         }
     };
 
@@ -402,6 +424,7 @@ __device__ __forceinline__ void score_pair_tile(
                 vq[b] = Vq[t * TVP + tx * RV + b];
             }
             const float r = R[t];
+            const float wt = WT ? R[kSC + t] : 1.0f;
 #pragma unroll
             for (int a = 0; a < RU; ++a)
 #pragma unroll
@@ -413,8 +436,9 @@ __device__ __forceinline__ void score_pair_tile(
                                            c4[a][b]);
 #pragma unroll
                     for (int k = 0; k < 5; ++k) {
-                        fA[a][b][k] += g[k];
-                        fB[a][b][k] = fmaf(g[k], g[k], fB[a][b][k]);
+                        const float wg = WT ? wt * g[k] : g[k];
+                        fA[a][b][k] += wg;
+                        fB[a][b][k] = fmaf(wg, g[k], fB[a][b][k]);
                         fC[a][b][k] = fmaf(g[k], r, fC[a][b][k]);
                     }
                 }

@@ -49,7 +49,11 @@ class Engine:
     """Device state of one SISSO problem: base features, pools, subspace."""
 
     def __init__(self, X: np.ndarray, y: np.ndarray, unary: Sequence[str], binary: Sequence[str],
-                 levels: int, rect: bool = False, device: str = "cuda:0"):
+                 levels: int, rect: bool = False, device: str = "cuda:0", weights: Optional[np.ndarray] = None):
+        """`weights`: optional per-sample weights w_s = 1 / sigma_s^2 for noise
+        with a known diagonal covariance (Sec. 2.4's whitening): screening,
+        duplicate classes and SO then use the weighted correlation and weighted
+        least squares (FP32 screening form only)."""
         L.lib()
         self.dev = torch.device(device)
         X = np.asarray(X, dtype=np.float64)
@@ -76,6 +80,14 @@ class Engine:
         self.tk_status = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.r32 = torch.zeros(self.ld32, dtype=torch.float32, device=self.dev)
         self.info = torch.zeros(L.RESID_DOUBLES, dtype=torch.float64, device=self.dev)
+        self.w64: Optional[torch.Tensor] = None
+        self.w32: Optional[torch.Tensor] = None
+        if weights is not None:
+            w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+            if w.shape != (n,) or not np.all(np.isfinite(w)) or np.any(w <= 0.0):
+                raise L.SissoError("weights must be n positive finite values")
+            self.w64 = torch.from_numpy(w).to(self.dev)
+            self.w32 = torch.zeros(self.ld32, dtype=torch.float32, device=self.dev)
         self._ws: Dict[str, torch.Tensor] = {}
 
     # ---------------------------------------------------------------- utils
@@ -109,6 +121,11 @@ class Engine:
 
     # ----------------------------------------------------------------- SIS
     def prepare_residual(self, r64: torch.Tensor):
+        if self.w64 is not None:
+            L.check(L.lib().sisso_prepare_residual_weighted(L.ptr(r64), L.ptr(self.w64), self.n, L.ptr(self.r32),
+                                                            L.ptr(self.w32), L.ptr(self.info), self.stream()),
+                    "sisso_prepare_residual_weighted")
+            return
         L.check(L.lib().sisso_prepare_residual(L.ptr(r64), self.n, L.ptr(self.r32), L.ptr(self.info),
                                                self.stream()), "sisso_prepare_residual")
 
@@ -120,6 +137,7 @@ class Engine:
         a.exclude = L.ptr(exclude) if exclude is not None and exclude.numel() else None
         a.n_exclude = int(exclude.numel()) if exclude is not None else 0
         a.keep, a.precision, a.grid, a.tile = keep, precision, grid, tile
+        a.w32 = L.ptr(self.w32) if self.w32 is not None else None
         return a
 
     def binary_base(self) -> int:
@@ -171,6 +189,8 @@ class Engine:
         end = self.total if end is None else end
         if moments not in ("none", "write", "read"):
             raise L.SissoError(f"unknown moments mode {moments!r}")
+        if self.w64 is not None and precision != "fp32":
+            raise L.SissoError("weighted screening runs in the FP32 form only")
         self.prepare_residual(r64)
         a = self.score_args(keep, exclude, grid, tile)
         nbytes = L.lib().sisso_score_workspace_size(ctypes.byref(self.space), ctypes.byref(a))
@@ -352,7 +372,7 @@ class Engine:
         mom_state = "write"                   # written by this fit's first pass, then read
         if dmax < 1 or dmax > L.MAX_D or k * dmax > L.MAX_SUBSPACE:
             raise L.SissoError("dmax or k out of range")
-        fs = FitState(self.n, self.dev)
+        fs = FitState(self.n, self.dev, self.w64)
         out: List[StepResult] = []
         r = self.y
         self.residuals = [self.y]
@@ -392,8 +412,9 @@ class FitState:
     sort and the l0 search; neither synchronises.  read_update() and
     result() copy the few scalars the loop needs to the host."""
 
-    def __init__(self, n: int, dev: torch.device):
+    def __init__(self, n: int, dev: torch.device, w64: Optional[torch.Tensor] = None):
         self.n, self.dev, self.m = n, dev, 0
+        self.w64 = w64                           # sample weights (None: unweighted)
         M = L.MAX_SUBSPACE
         self.sub = torch.empty(M * n, dtype=torch.float64, device=dev)
         self.sub_ids = torch.empty(M, dtype=torch.int64, device=dev)
@@ -415,8 +436,8 @@ class FitState:
         n, st = self.n, L.stream_handle(self.dev)
         nb = L.lib().sisso_subspace_workspace_size(n, keep, self.m)
         ws = workspace("sub", nb)
-        L.check(L.lib().sisso_subspace_update(
-            L.ptr(cand), n, L.ptr(ids), L.ptr(valid), L.ptr(cnt), keep, L.ptr(r), n,
+        L.check(L.lib().sisso_subspace_update_weighted(
+            L.ptr(cand), n, L.ptr(ids), L.ptr(valid), L.ptr(cnt), keep, L.ptr(r), L.ptr(self.w64), n,
             L.ptr(self.sub), n, L.ptr(self.sub_ids), self.m, k, L.ptr(self.n_new), L.ptr(self.n_cls),
             L.ptr(ws), ws.numel(), st), "sisso_subspace_update")
 
@@ -464,9 +485,10 @@ class FitState:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-        L.check(L.lib().sisso_l0_search(L.ptr(self.fsorted), m, n, n, L.ptr(y), t, singular_tol,
-                                        L.ptr(self.tup), L.ptr(self.sse), L.ptr(self.coef), L.ptr(self.resid),
-                                        L.ptr(self.stats), L.ptr(ws), ws.numel(), st), "sisso_l0_search")
+        L.check(L.lib().sisso_l0_search_weighted(L.ptr(self.fsorted), m, n, n, L.ptr(y), L.ptr(self.w64), t,
+                                                 singular_tol, L.ptr(self.tup), L.ptr(self.sse), L.ptr(self.coef),
+                                                 L.ptr(self.resid), L.ptr(self.stats), L.ptr(ws), ws.numel(), st),
+                "sisso_l0_search")
         if timings is not None:
             e1.record()
             timings.setdefault(f"l0_D{t}", []).append((e0, e1))

@@ -85,6 +85,7 @@ class Problem:
     seed: int = 0
     base: Optional[str] = None      # batched problems: name of the base dataset
     rows: Optional[np.ndarray] = None  # batched problems: row indices into the base
+    w: Optional[np.ndarray] = None  # per-sample weights 1 / sigma_s^2 (heteroscedastic noise)
 
 
 def _well_conditioned(vals: Sequence[np.ndarray]) -> bool:
@@ -207,6 +208,25 @@ def config5(seed: int = 501, n: int = 2000, d: int = 30) -> Problem:
     p = config3(seed=seed, n=n, d=d)
     p.name = "C5"
     return p
+
+
+def heteroscedastic(seed: int = 211, n: int = 500, d: int = 10, rect: bool = False,
+                    spread: float = 1.0) -> Problem:
+    """A problem for Sec. 2.4's whitening: like config2 (LogNormal(0, 0.5)
+    features, three planted rung-2 terms, full operator set) but with noise of
+    known per-sample sd sigma_s = 0.05 sd(signal) exp(spread z_s), z_s ~ N(0, 1),
+    so sigma_s spans about a factor exp(4 spread) over the samples; the
+    weights are w_s = 1 / sigma_s^2.  With rect the space adds the one-sided
+    rung-3 slice (operator set OPS1 then, as config3)."""
+    rng = np.random.default_rng(seed)
+    X = rng.lognormal(0.0, 0.5, size=(n, d))
+    ops = OPS1 if rect else FULL
+    clean, trees, coef = _planted_target(rng, X, ops, 3 if not rect else 2,
+                                         _rand_rung2 if not rect else _rand_rung3_binary, 0.0)
+    sigma = 0.05 * clean.std() * np.exp(spread * rng.normal(size=n))
+    y = clean + sigma * rng.normal(size=n)
+    return Problem("het", X, y, list(ops["unary"]), list(ops["binary"]), 2, rect, 20, 3, trees, coef, seed,
+                   w=1.0 / sigma ** 2)
 
 
 def config4(seeds: Sequence[int] = tuple(range(401, 409)), d: int = 12,
