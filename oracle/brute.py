@@ -14,7 +14,8 @@ from __future__ import annotations
 
 import itertools
 import math
-from typing import List, Sequence, Tuple
+from fractions import Fraction
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -79,14 +80,54 @@ def _slots(binary):
     return out
 
 
+# Units as {dimension name: Fraction exponent} (dimensionless: {}), None for a
+# feature that breaks dimensional analysis (Sec. 2.1; Sec. 3.3's
+# dimensionality option): sums and differences need equal units, products and
+# quotients add and subtract exponents, powers scale them, and exp, exp(-x),
+# ln, sin take a dimensionless argument.
+_UNIT_POW = {"sq": Fraction(2), "cube": Fraction(3), "sqrt": Fraction(1, 2), "inv": Fraction(-1)}
+
+
+def _unit_unary(op: str, ua: Optional[Dict[str, Fraction]]):
+    if ua is None:
+        return None
+    if op in _UNIT_POW:
+        return {k: e * _UNIT_POW[op] for k, e in ua.items()}
+    return {} if not ua else None
+
+
+def _unit_binary(op: str, ul, ur):
+    if ul is None or ur is None:
+        return None
+    if op in ("add", "sub"):
+        return dict(ul) if ul == ur else None
+    sign = 1 if op == "mul" else -1
+    out = dict(ul)
+    for k, e in ur.items():
+        out[k] = out.get(k, Fraction(0)) + sign * e
+    return {k: e for k, e in out.items() if e != 0}
+
+
 def enumerate_space(X: np.ndarray, unary: Sequence[str], binary: Sequence[str], levels: int,
-                    rect: bool = False):
+                    rect: bool = False, dimensionality: Optional[Sequence[str]] = None):
     """All features in canonical order: list of (expr, values, valid)."""
+    return enumerate_space_units(X, unary, binary, levels, rect, dimensionality)[0]
+
+
+def enumerate_space_units(X: np.ndarray, unary: Sequence[str], binary: Sequence[str], levels: int,
+                          rect: bool = False, dimensionality: Optional[Sequence[str]] = None):
+    """(features, units): the features as enumerate_space gives them and, per
+    feature, its units (None if not physical; all {} without dimensionality).
+    With dimensionality (one unit string per base feature, "" or "1" for a
+    dimensionless one) a non-physical feature is invalid."""
     n, d = X.shape
     feats: List[Tuple[str, np.ndarray, bool]] = []
+    units: List[Optional[Dict[str, Fraction]]] = []
     for i in range(d):
         v = X[:, i].astype(np.float64)
         feats.append((f"x{i}", v, _ok(v)))
+        u = dimensionality[i] if dimensionality is not None else ""
+        units.append({} if u in ("", "1") else {u: Fraction(1)})
     sizes = [0, d]            # P_{-1}, P_0
     slots = _slots(binary)
 
@@ -116,30 +157,42 @@ def enumerate_space(X: np.ndarray, unary: Sequence[str], binary: Sequence[str], 
             ok = bool(np.sqrt(np.mean((v - v.mean()) ** 2)) > 1e-5 * scale)
         return (e, v, ok)
 
+    def physical(f, u):
+        e, v, ok = f
+        return (e, v, ok and u is not None) if dimensionality is not None else f
+
     for _ in range(levels):
         lo, hi = sizes[-2], sizes[-1]
-        new = []
+        new, nu = [], []
         for a in range(lo, hi):
             for op in unary:
-                new.append(unary_feat(a, op))
+                ua = _unit_unary(op, units[a])
+                new.append(physical(unary_feat(a, op), ua)); nu.append(ua)
         for j in range(lo, hi):
             for i in range(j):
                 for op, rev in slots:
-                    new.append(binary_feat(i, j, op) if rev else binary_feat(j, i, op))
+                    l, r = (i, j) if rev else (j, i)
+                    ub = _unit_binary(op, units[l], units[r])
+                    new.append(physical(binary_feat(l, r, op), ub)); nu.append(ub)
         feats.extend(new)
+        units.extend(nu)
         sizes.append(len(feats))
     if rect:
         lo, hi = sizes[-2], sizes[-1]
-        new = []
+        new, nu = [], []
         for u in range(lo, hi):
             for op in unary:
-                new.append(unary_feat(u, op))
+                ua = _unit_unary(op, units[u])
+                new.append(physical(unary_feat(u, op), ua)); nu.append(ua)
         for u in range(lo, hi):
             for v in range(0, lo):
                 for op, rev in slots:
-                    new.append(binary_feat(v, u, op) if rev else binary_feat(u, v, op))
+                    l, r = (v, u) if rev else (u, v)
+                    ub = _unit_binary(op, units[l], units[r])
+                    new.append(physical(binary_feat(l, r, op), ub)); nu.append(ub)
         feats.extend(new)
-    return feats
+        units.extend(nu)
+    return feats, units
 
 
 def abs_corr(f, r) -> float:
@@ -207,9 +260,9 @@ def l0(F: np.ndarray, y: np.ndarray, D: int):
     raise AssertionError
 
 
-def fit(X, y, unary, binary, levels, rect, k, dmax, keep0=None):
+def fit(X, y, unary, binary, levels, rect, k, dmax, keep0=None, dimensionality=None):
     """Brute-force SISSO loop (same readings as the oracle)."""
-    feats = enumerate_space(X, unary, binary, levels, rect)
+    feats = enumerate_space(X, unary, binary, levels, rect, dimensionality)
     keep0 = 2 * k if keep0 is None else keep0
     sub: List[int] = []
     r = np.asarray(y, dtype=np.float64).copy()

@@ -98,6 +98,10 @@ def lib():
         L.or_fit_w.restype = ctypes.c_int
         L.or_fit_w.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
                                ctypes.c_int, ctypes.c_int64, ctypes.POINTER(_Step)]
+        L.or_space_set_units.restype = ctypes.c_int
+        L.or_space_set_units.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int]
+        L.or_units.restype = ctypes.c_int
+        L.or_units.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp]
         L.or_step_size.restype = ctypes.c_int
         assert L.or_step_size() == ctypes.sizeof(_Step)
         _lib = L
@@ -125,12 +129,29 @@ def _colmajor(X: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(X, dtype=np.float64).T)
 
 
+def unit_matrix(dimensionality: Sequence[str]) -> np.ndarray:
+    """Exponent matrix (d x n_dim) of the base features from their unit
+    strings (the dimensionality option of Sec. 3.3): every distinct string
+    names a base dimension in order of first appearance and gives its feature
+    exponent 1 there; "" and "1" mark a dimensionless feature."""
+    names: List[str] = []
+    for u in dimensionality:
+        if u not in ("", "1") and u not in names:
+            names.append(u)
+    M = np.zeros((len(dimensionality), len(names)), dtype=np.float64)
+    for i, u in enumerate(dimensionality):
+        if u not in ("", "1"):
+            M[i, names.index(u)] = 1.0
+    return M
+
+
 class Space:
     """The expanded feature space: `levels` full levels plus, if `rect`, the
-    one-sided next-level slice."""
+    one-sided next-level slice; with `dimensionality` (one unit string per
+    base feature), features that break dimensional analysis are invalid."""
 
     def __init__(self, d: int, unary: Sequence[str], binary: Sequence[str], levels: int,
-                 rect: bool = False):
+                 rect: bool = False, dimensionality: Sequence[str] | None = None):
         self.d, self.levels, self.rect = d, levels, rect
         self.unary, self.binary = list(unary), list(binary)
         u = np.array([OPCODE[o] for o in unary] or [0], dtype=np.int32)
@@ -140,6 +161,15 @@ class Space:
         if not h:
             raise ValueError("oracle: invalid space")
         self._h = ctypes.c_void_p(h)
+        self.n_dim = 0
+        if dimensionality is not None:
+            if len(dimensionality) != d:
+                raise ValueError("oracle: one unit string per base feature")
+            M = np.ascontiguousarray(unit_matrix(dimensionality))
+            self.n_dim = M.shape[1]
+            # no named dimension: every feature is dimensionless, no rule applies
+            if self.n_dim and lib().or_space_set_units(self._h, _p(M, _dp), self.n_dim):
+                raise ValueError("oracle: too many base dimensions")
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
@@ -158,6 +188,13 @@ class Space:
         if lib().or_decode(self._h, fid, ctypes.byref(op), ctypes.byref(l), ctypes.byref(r)):
             raise IndexError(fid)
         return op.value, l.value, r.value
+
+    def units(self, fid: int):
+        """(physical, exponents) of feature fid (exponents over the base
+        dimensions in order of first appearance)."""
+        u = np.zeros(max(self.n_dim, 1), dtype=np.float64)
+        ok = lib().or_units(self._h, int(fid), _p(u, _dp))
+        return bool(ok), u[:self.n_dim].copy()
 
     def eval(self, X: np.ndarray, ids: Sequence[int]):
         """FP64 values (n x len(ids)) and validity flags of features `ids`."""
@@ -270,11 +307,11 @@ class StepResult:
 
 
 def fit(X: np.ndarray, y: np.ndarray, unary, binary, levels: int, rect: bool, k: int,
-        dmax: int, keep0: int | None = None, w=None) -> List[StepResult]:
+        dmax: int, keep0: int | None = None, w=None, dimensionality=None) -> List[StepResult]:
     """Oracle SISSO fit; one StepResult per dimension t = 1..dmax (weighted
     screening, duplicate classes and least squares when sample weights w are
     given)."""
-    sp = Space(X.shape[1], unary, binary, levels, rect)
+    sp = Space(X.shape[1], unary, binary, levels, rect, dimensionality)
     Xc = _colmajor(X)
     y = np.ascontiguousarray(y, dtype=np.float64)
     steps = (_Step * dmax)()

@@ -86,6 +86,8 @@ typedef struct {
     int64_t total;
     int32_t *op;                    /* per pool id: op (-1 for base) */
     int64_t *left, *right;          /* per pool id: operand ids (-1 if none) */
+    int n_dim;                      /* base dimensions of the units (0: no units) */
+    double *units;                  /* d x n_dim exponents of the base features */
 } or_space;
 
 static int is_binary(int op) { return op >= OP_ADD && op <= OP_DIV; }
@@ -93,7 +95,7 @@ static int is_binary(int op) { return op >= OP_ADD && op <= OP_DIV; }
 void or_space_free(or_space *s)
 {
     if (!s) return;
-    free(s->op); free(s->left); free(s->right); free(s);
+    free(s->op); free(s->left); free(s->right); free(s->units); free(s);
 }
 
 /* Build the pool tables by enumerating the levels with nested loops. */
@@ -260,10 +262,69 @@ static double sd_of(const double *f, int n)
     return sqrt(ss / n);
 }
 
+/* Dimensional analysis (Sec. 2.1; the dimensionality option of Sec. 3.3):
+ * units are vectors of exponents over base dimensions.  A sum or difference
+ * needs equal units; a product adds them, a quotient subtracts them; x^2,
+ * x^3, sqrt(x), 1/x scale them by 2, 3, 1/2, -1; exp, exp(-x), ln and sin
+ * need a dimensionless argument and give a dimensionless result.  Returns 0
+ * for a feature that breaks a rule (not physical), else its units in u. */
+int or_space_set_units(or_space *s, const double *units, int n_dim)
+{
+    if (!s || n_dim < 0 || n_dim > 16 || (n_dim > 0 && !units)) return 1;
+    free(s->units);
+    s->units = NULL;
+    s->n_dim = n_dim;
+    if (n_dim > 0) {
+        s->units = (double *)malloc(sizeof(double) * s->d * n_dim);
+        memcpy(s->units, units, sizeof(double) * s->d * n_dim);
+    }
+    return 0;
+}
+
+static int unit_rec(const or_space *s, int64_t id, double *u)
+{
+    int32_t op; int64_t l, r;
+    if (or_decode(s, id, &op, &l, &r)) return 0;
+    const int k = s->n_dim;
+    if (op < 0) {
+        for (int q = 0; q < k; q++) u[q] = s->units[(size_t)id * k + q];
+        return 1;
+    }
+    double a[16], b[16];
+    if (!unit_rec(s, l, a)) return 0;
+    if (is_binary(op) && !unit_rec(s, r, b)) return 0;
+    int dimless = 1;
+    for (int q = 0; q < k; q++) if (a[q] != 0.0) dimless = 0;
+    for (int q = 0; q < k; q++) {
+        switch (op) {
+        case OP_ADD: case OP_SUB: if (a[q] != b[q]) return 0; u[q] = a[q]; break;
+        case OP_MUL: u[q] = a[q] + b[q]; break;
+        case OP_DIV: u[q] = a[q] - b[q]; break;
+        case OP_SQ: u[q] = 2.0 * a[q]; break;
+        case OP_CUBE: u[q] = 3.0 * a[q]; break;
+        case OP_SQRT: u[q] = 0.5 * a[q]; break;
+        case OP_INV: u[q] = -a[q]; break;
+        default: if (!dimless) return 0; u[q] = 0.0; break;   /* exp, exp(-x), ln, sin */
+        }
+    }
+    return 1;
+}
+
+/* Units of feature `id` (n_dim values) and whether it is physical. */
+int or_units(const or_space *s, int64_t id, double *u)
+{
+    if (!s->units) return 1;
+    return unit_rec(s, id, u);
+}
+
 static int eval_rec(const or_space *s, const double *X, int n, int ldx, int64_t id, double *out)
 {
     int32_t op; int64_t l, r;
     if (or_decode(s, id, &op, &l, &r)) return 0;
+    if (s->units) {
+        double u[16];
+        if (!unit_rec(s, id, u)) return 0;
+    }
     if (op < 0) {
         memcpy(out, X + (size_t)id * ldx, sizeof(double) * n);
         return check_values(out, n);
