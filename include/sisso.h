@@ -94,6 +94,8 @@ typedef enum {
 #define SISSO_MAX_SUBSPACE 1024    /* |S_t|                                  */
 #define SISSO_MAX_D 3              /* terms per SO model                     */
 #define SISSO_MAX_BATCH 4096       /* problems per batched call              */
+#define SISSO_UNIT_DIMS 8          /* base dimensions of feature units        */
+#define SISSO_UNIT_SCALE 16        /* unit exponents are stored times this    */
 
 /* Feature space description (host struct).  Fill d, levels, rect and the
  * operator lists, then call sisso_space_init, which validates them and fills
@@ -177,6 +179,28 @@ sisso_status sisso_materialize_ids_stored(const sisso_space *space, int32_t stor
                                           const int64_t *ids, int32_t count, double *out, int32_t ldo,
                                           int32_t *valid, void *stream);
 
+/* Dimensional analysis (Sec. 2.1, last paragraph; the dimensionality option
+ * of Sec. 3.3).  The units of a feature are its exponents over up to
+ * SISSO_UNIT_DIMS base dimensions, stored as int16 times SISSO_UNIT_SCALE
+ * (exact through four nested square roots); a feature that breaks a rule
+ * carries INT16_MIN as its first exponent.  The rules (a reading of the
+ * paper, which names the first): a sum or difference needs operands of
+ * equal units and keeps them; a product adds the exponents, a quotient
+ * subtracts them; x^2, x^3, sqrt(x), 1/x scale them by 2, 3, 1/2, -1; exp,
+ * exp(-x), ln and sin need a dimensionless operand and are dimensionless.
+ * A feature that breaks a rule is not generated: sisso_pool_units computes
+ * the units of every pool column from those of the base features and clears
+ * `valid` in the stats of the columns that break a rule (so they are neither
+ * scored nor combined further), and with sisso_score_args.units set the
+ * screening kernels apply the same rules to the slice candidates they form.
+ *   base_units  device, d rows of SISSO_UNIT_DIMS int16 (base features).
+ *   units       device output, |P_levels| rows of SISSO_UNIT_DIMS int16.
+ *   stats       device in/out, as sisso_materialize_pools wrote them.
+ * Exponents whose magnitude would exceed 2^14 are reported as breaking a
+ * rule.  Errors: SISSO_E_NULL, SISSO_E_SHAPE. */
+sisso_status sisso_pool_units(const sisso_space *space, const int16_t *base_units, int16_t *units,
+                              sisso_colstat *stats, void *stream);
+
 /* Residual record used by the screening kernels (device, 4 doubles). */
 typedef struct {
     double sum_r32;   /* sum of the FP32 centred residual values            */
@@ -240,6 +264,10 @@ typedef struct {
                                      and info must come from the same call):
                                      scores are weighted |corr| (Sec. 2.4).
                                      FP32 precision only                        */
+    const int16_t *units;         /* NULL, or the pool columns' units from
+                                     sisso_pool_units: slice candidates that
+                                     break dimensional analysis are invalid.
+                                     FP32 and 16-bit screening forms only       */
 } sisso_score_args;
 
 /* Workspace of a screening pass: per-block candidate lists plus a header.

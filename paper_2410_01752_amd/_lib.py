@@ -21,6 +21,7 @@ OPNAME = {v: k for k, v in OPCODE.items()}
 MAX_UNARY, MAX_BINARY, MAX_LEVELS = 8, 4, 2
 MAX_N, MAX_KEEP, MAX_SUBSPACE, MAX_D = 65536, 2048, 1024, 3
 MAX_BAND = 7168
+UNIT_DIMS, UNIT_SCALE = 8, 16          # SISSO_UNIT_DIMS, SISSO_UNIT_SCALE
 MOMENTS_NONE, MOMENTS_WRITE, MOMENTS_READ = 0, 1, 2
 MAX_BATCH = 4096
 ENC, MLP_IN, MLP_HIDDEN = 64, 144, 256
@@ -52,7 +53,7 @@ class ScoreArgs(ctypes.Structure):
                 ("exclude", ctypes.c_void_p), ("n_exclude", ctypes.c_int32),
                 ("keep", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("list_base", ctypes.c_int32), ("w32", ctypes.c_void_p)]
+                ("list_base", ctypes.c_int32), ("w32", ctypes.c_void_p), ("units", ctypes.c_void_p)]
 
 
 class Problem(ctypes.Structure):
@@ -131,6 +132,7 @@ def lib():
                                                 _vp]),
         "sisso_prepare_residual": (_i32, [_vp, _i32, _vp, _vp, _vp]),
         "sisso_prepare_residual_weighted": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+        "sisso_pool_units": (_i32, [sp, _vp, _vp, _vp, _vp]),
         "sisso_prepare_residual_batched": (_i32, [_vp, _i32, _vp]),
         "sisso_batch_workspace_size": (_sz, [sp, _i32, _i32]),
         "sisso_batch_items": (_i32, [sp]),
@@ -223,6 +225,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_expand_score_pruned_lists", "sisso_expand_score_pruned", "sisso_count_pass",
             "sisso_prescreen_workspace_size", "sisso_prescreen_scores", "sisso_prescreen_select",
             "sisso_prepare_residual_weighted", "sisso_subspace_update_weighted", "sisso_l0_search_weighted",
+            "sisso_pool_units",
             "sisso_status_string", "sisso_version"]
 
 
@@ -230,6 +233,25 @@ def check(status: int, what: str = ""):
     if status != 0:
         msg = lib().sisso_status_string(status).decode()
         raise SissoError(f"{what}: status {status} ({msg})")
+
+
+def base_units(dimensionality) -> "np.ndarray":
+    """int16 rows of SISSO_UNIT_DIMS exponents (times SISSO_UNIT_SCALE) for
+    the base features from their unit strings (the dimensionality option of
+    Sec. 3.3): every distinct string names a base dimension, in order of first
+    appearance; "" or "1" marks a dimensionless feature."""
+    import numpy as np
+    names = []
+    for u in dimensionality:
+        if u not in ("", "1") and u not in names:
+            names.append(u)
+    if len(names) > UNIT_DIMS:
+        raise SissoError(f"at most {UNIT_DIMS} distinct units")
+    M = np.zeros((len(dimensionality), UNIT_DIMS), dtype=np.int16)
+    for i, u in enumerate(dimensionality):
+        if u not in ("", "1"):
+            M[i, names.index(u)] = UNIT_SCALE
+    return M
 
 
 def ptr(t) -> int:

@@ -477,7 +477,8 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
     int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, const h16 *__restrict__ vimg,
-    const h16 *__restrict__ uimg, BfSide side, void *lws, int lists_total, int keep, int cap, int publish)
+    const h16 *__restrict__ uimg, const int16_t *__restrict__ units, BfSide side, void *lws, int lists_total,
+    int keep, int cap, int publish)
 {
     using Sh = BfShape<MODE>;
     constexpr int kUVar = Sh::kUVar, kVVar = Sh::kVVar, kNG = Sh::kNG, kPA = Sh::kPA, kPB = Sh::kPB,
@@ -491,6 +492,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     // sum z~^2), (sum u~ r, sum z~ r, rms, flags: 1 valid, 2 no zero) and the
     // inverse scale factors of U~, U~^2, Z~, Z~^2
     float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBTU, *ucon_c = ucon_b + kBTU;
+    uint4 *ucon_u = reinterpret_cast<uint4 *>(ucon_c + kBTU);      // the u columns' units (zero without units)
     __shared__ int lcnt, lpend;
     __shared__ float lthr;
     __shared__ unsigned gdummy;                   // bound of a block that must not publish (stays 0)
@@ -543,6 +545,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             const UScale c = u_scales(ua.z, ua.w, fn);
             ucon_c[tid] = make_float4(1.0f / c.u, 1.0f / (c.u * c.u * shs), 1.0f / c.z, 1.0f / (c.z * c.z * shs));
             if (!col_scalable(ua.z, ua.w, fn, cs.minabs > 0.0f)) ucon_b[tid].w += 4.0f;
+            ucon_u[tid] = units ? unit_of(units, ulo + (in ? x : 0)) : make_uint4(0u, 0u, 0u, 0u);
         }
         for (int64_t vt = 0; vt < nvt; ++vt) {
             const int64_t v0 = vt * kBTV;
@@ -750,6 +753,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             const float4 vs0 = vsum[2 * (vin ? v : 0)], vs1 = vsum[2 * (vin ? v : 0) + 1];
             const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w, Svr = vs1.x, Swr = vs1.y;
             const float rr = (float)(R1 / nd);
+            const uint4 vunit = units ? unit_of(units, vin ? v : 0) : make_uint4(0u, 0u, 0u, 0u);
             // inverse scale factors of this lane's v column: the accumulator of
             // GEMM g times iu(row) iv(column) is the unscaled contraction
             const VScale vc = v_scales(mv, mw, Svv, Sww, fn, rsc, shs);
@@ -816,7 +820,9 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 cov[3] = (acc[Sh::kCovUW][r] * ui.x) * iwr + mw * Sur + mu * Swr - m[2] * rr;
                 var[4] = m[5];                                      // v / u
                 cov[4] = (acc[Sh::kCovZV][r] * ui.z) * ivr + mv * Szr + mz * Svr - m[4] * rr;
-                const bool dom[5] = {true, true, true, vst.minabs > 0.f, (uflags & 2) != 0};
+                // a sum or difference needs operands of equal units
+                const bool same_u = unit_eq(ucon_u[wu * 32 + i], vunit);
+                const bool dom[5] = {same_u, same_u, true, vst.minabs > 0.f, (uflags & 2) != 0};
                 // u + v and u - v: trusted when the variance is at least kCondRel
                 // of Suu + Svv (the error of 2 g0 is a fraction of it); the
                 // product forms carry -1 when their test failed
@@ -1004,7 +1010,7 @@ __global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
     sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
     const float4 *__restrict__ usum, const float4 *__restrict__ vsum, const sisso_colstat *__restrict__ stats,
     int64_t ut_lo, int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, h16 *__restrict__ uimg,
-    BfSide side)
+    const int16_t *__restrict__ units, BfSide side)
 {
     using Sh = MomShape;
     constexpr int kPA = Sh::kPA, kPB = Sh::kPB, kNG = Sh::kNG, kStage = Sh::kStage, kBTU = Sh::kBTU,
@@ -1014,6 +1020,7 @@ __global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
     // scale factors of U~, U~^2, Z~, Z~^2, flags (1 valid, 2 no zero, 4 not
     // scalable)
     __shared__ float4 ucon_a[kBTU], ucon_c[kBTU];
+    __shared__ uint4 ucon_u[kBTU];                // units (zero without units)
     __shared__ int ucon_f[kBTU];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -1056,6 +1063,7 @@ __global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
             ucon_c[tid] = make_float4(1.0f / c.u, 1.0f / (c.u * c.u * shs), 1.0f / c.z, 1.0f / (c.z * c.z * shs));
             ucon_f[tid] = (in && cs.valid != 0.0f ? 1 : 0) + (cs.minabs > 0.0f ? 2 : 0) +
                           (col_scalable(ua.z, ua.w, fn, cs.minabs > 0.0f) ? 0 : 4);
+            ucon_u[tid] = units ? unit_of(units, ulo + (in ? x : 0)) : make_uint4(0u, 0u, 0u, 0u);
         }
         for (int64_t vt = 0; vt < nvt; ++vt) {
             const int64_t v0 = vt * kBTV;
@@ -1162,6 +1170,7 @@ __global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
             const float iv = 1.0f / vc.v, ip = 1.0f / vc.p, iq = 1.0f / vc.q, iw = 1.0f / vc.w, ipw = 1.0f / vc.pw,
                         iqw = 1.0f / vc.qw;
             const bool vscal = col_scalable(Svv, Sww, fn, vst.minabs > 0.0f);
+            const uint4 vunit = units ? unit_of(units, vin ? v : 0) : make_uint4(0u, 0u, 0u, 0u);
             const int64_t v32 = vt * Sh::kWV + wv;
             const int64_t u64 = (u0 + wu * 32) / 64;
             const bool mom_in = (v32 >> 1) < nvt64 && u64 < nut64;
@@ -1198,7 +1207,8 @@ __global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
                 const bool ok = (uf & 1) && vin && vst.valid != 0.0f;
                 const bool unscal = (uf & 4) != 0 || !vscal;
                 const float var[5] = {Suu + Svv + 2.0f * m[0], Suu + Svv - 2.0f * m[0], m[1], m[3], m[5]};
-                const bool dom[5] = {true, true, true, vst.minabs > 0.f, (uf & 2) != 0};
+                const bool same_u = unit_eq(ucon_u[wu * 32 + i], vunit);   // sums and differences
+                const bool dom[5] = {same_u, same_u, true, vst.minabs > 0.f, (uf & 2) != 0};
                 const float cth = kCondRel * (Suu + Svv);
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
@@ -1550,13 +1560,13 @@ sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, c
     const int lcap = bf_lists_total(space, keep_b);
     hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, keep_b, p.grid, lcap);
     if (p.grid > 0) {
-        const size_t smem = (size_t)Sh::kNStage * Sh::kStage * sizeof(h16) + 3 * Sh::kBTU * sizeof(float4) +
+        const size_t smem = (size_t)Sh::kNStage * Sh::kStage * sizeof(h16) + 4 * Sh::kBTU * sizeof(float4) +
                             (size_t)cap_b * (sizeof(float) + sizeof(int64_t));
         if (!allow_dynamic_lds(k_score_rect_bf16<MODE>, smem)) return SISSO_E_UNSUPPORTED;
         hipLaunchKernelGGL(k_score_rect_bf16<MODE>, dim3(p.grid), dim3(Sh::kThreads), smem, st, *space, fs, n,
                            args->pool32, args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info,
                            args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, mom, w.vimg,
-                           uimg, side, w.lists, lcap, keep_b, cap_b, publish);
+                           uimg, args->units, side, w.lists, lcap, keep_b, cap_b, publish);
     }
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
@@ -1590,7 +1600,7 @@ sisso_status bf_launch_moments(const sisso_space *space, const sisso_score_args 
     if (p.grid > 0)
         hipLaunchKernelGGL(k_bf_moments, dim3(p.grid), dim3(MomShape::kThreads), 0, st, *space, form_slots(space),
                            args->n, args->pool32, args->ld32, o.usum, w.vsum, args->stats, p.ut_lo, p.ut_hi,
-                           cand_begin, cand_end, mom, uimg, side);
+                           cand_begin, cand_end, mom, uimg, args->units, side);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 #else

@@ -127,6 +127,25 @@ __device__ __forceinline__ float unary32(int op, float a)
     }
 }
 
+// ----------------------------------------------------------------- units
+
+// One column's units (SISSO_UNIT_DIMS int16 exponents times SISSO_UNIT_SCALE)
+// as one 16-byte word; kUnitNone as the first exponent marks a feature that
+// breaks dimensional analysis.
+static_assert(SISSO_UNIT_DIMS * sizeof(int16_t) == sizeof(uint4), "units of a column are one 16-byte word");
+constexpr int kUnitNone = -32768;
+__device__ __forceinline__ uint4 unit_of(const int16_t *units, int64_t c)
+{
+    return reinterpret_cast<const uint4 *>(units)[c];
+}
+__device__ __forceinline__ bool unit_eq(uint4 a, uint4 b) { return a.x == b.x && a.y == b.y && a.z == b.z && a.w == b.w; }
+__device__ __forceinline__ bool unit_dimless(uint4 a) { return (a.x | a.y | a.z | a.w) == 0u; }
+// exp, exp(-x), ln and sin take a dimensionless argument
+__device__ __forceinline__ bool unary_needs_dimless(int op)
+{
+    return op == SISSO_EXP || op == SISSO_NEXP || op == SISSO_LOG || op == SISSO_SIN;
+}
+
 // Domain check and magnitude bound of a unary op applied to a column with
 // the given statistics.  Returns false if the domain is violated; *bound
 // receives an upper bound of |op(f)| (or +inf when no cheap bound exists).

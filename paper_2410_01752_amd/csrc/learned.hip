@@ -912,7 +912,7 @@ extern "C" int32_t sisso_mlp_table_count(void) { return kTab; }
 extern "C" sisso_status sisso_encode_operands(const sisso_space *space, const sisso_score_args *args,
                                               int64_t c_begin, int64_t c_end, float *enc, void *stream)
 {
-    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
+    if (args && (args->w32 || args->units)) return SISSO_E_UNSUPPORTED;   // weights, units: FP32 / 16-bit forms
     if (!space || !args || !enc || !args->pool32 || !args->stats || !args->r32 || !args->info) return SISSO_E_NULL;
     if (space->total <= 0 || !args_ok(args)) return SISSO_E_SHAPE;
     const int64_t pL = space->pool[space->levels];
@@ -940,7 +940,7 @@ extern "C" sisso_status sisso_candidate_inputs(const sisso_space *space, const f
 extern "C" sisso_status sisso_score_ids(const sisso_space *space, const sisso_score_args *args, const int64_t *ids,
                                         int32_t count, float *out, void *stream)
 {
-    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
+    if (args && (args->w32 || args->units)) return SISSO_E_UNSUPPORTED;   // weights, units: FP32 / 16-bit forms
     if (!space || !args || !ids || !out || !args->pool32 || !args->stats || !args->r32 || !args->info)
         return SISSO_E_NULL;
     if (!slice_ok(space)) return SISSO_E_UNSUPPORTED;
@@ -1072,7 +1072,7 @@ extern "C" sisso_status sisso_expand_score_pruned(const sisso_space *space, cons
                                                   const float *tau, int64_t cand_begin, int64_t cand_end, void *ws,
                                                   size_t ws_bytes, unsigned long long *kept, void *stream)
 {
-    if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
+    if (args && (args->w32 || args->units)) return SISSO_E_UNSUPPORTED;   // weights, units: FP32 / 16-bit forms
     if (!space || !args || !Au || !Bv || !tables || !tau || !ws || !args->pool32 || !args->stats || !args->r32 ||
         !args->info)
         return SISSO_E_NULL;

@@ -392,7 +392,69 @@ __global__ void __launch_bounds__(1024) k_prepare_residual_batch(const sisso_pro
 
 using namespace sisso;
 
+namespace sisso {
+// Units of the pool columns [lo, hi) of one level from those of the earlier
+// levels (level 0: copied from the base features); a column that breaks a
+// rule gets kUnitNone and loses its validity.  One thread per column.
+__global__ void __launch_bounds__(256) k_pool_units(sisso_space s, const int16_t *__restrict__ base,
+                                                    int16_t *__restrict__ units, sisso_colstat *__restrict__ stats,
+                                                    int64_t lo, int64_t hi)
+{
+    constexpr int K = SISSO_UNIT_DIMS;
+    for (int64_t c = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < hi;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int32_t e[K];
+        bool ok = true;
+        int op;
+        int64_t a, b;
+        if (c < s.d) {
+            for (int q = 0; q < K; ++q) e[q] = base[c * K + q];
+            ok = e[0] != kUnitNone;
+        } else {
+            decode_id(s, c, &op, &a, &b);
+            const int16_t *ua = units + a * K, *ub = b >= 0 ? units + b * K : nullptr;
+            ok = ua[0] != kUnitNone && (!ub || ub[0] != kUnitNone);
+            bool dimless = true;
+            for (int q = 0; q < K; ++q) dimless = dimless && ua[q] == 0;
+            for (int q = 0; q < K && ok; ++q) {
+                const int x = ua[q];
+                switch (op) {
+                case SISSO_ADD: case SISSO_SUB: ok = x == ub[q]; e[q] = x; break;
+                case SISSO_MUL: e[q] = x + ub[q]; break;
+                case SISSO_DIV: e[q] = x - ub[q]; break;
+                case SISSO_SQ: e[q] = 2 * x; break;
+                case SISSO_CUBE: e[q] = 3 * x; break;
+                case SISSO_SQRT: ok = (x & 1) == 0; e[q] = x / 2; break;
+                case SISSO_INV: e[q] = -x; break;
+                default: ok = dimless; e[q] = 0; break;       // exp, exp(-x), ln, sin
+                }
+                ok = ok && e[q] >= -(1 << 14) && e[q] <= (1 << 14);
+            }
+        }
+        int16_t *out = units + c * K;
+        for (int q = 0; q < K; ++q) out[q] = ok ? (int16_t)e[q] : (q == 0 ? (int16_t)kUnitNone : (int16_t)0);
+        if (!ok) stats[c].valid = 0.0f;
+    }
+}
+}  // namespace sisso
+
 static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" sisso_status sisso_pool_units(const sisso_space *space, const int16_t *base_units, int16_t *units,
+                                         sisso_colstat *stats, void *stream)
+{
+    if (!space || !base_units || !units || !stats) return SISSO_E_NULL;
+    if (space->total <= 0 || space->levels < 1 || space->levels > SISSO_MAX_LEVELS) return SISSO_E_SHAPE;
+    hipStream_t st = as_stream(stream);
+    for (int lev = 0; lev <= space->levels; ++lev) {
+        const int64_t lo = lev == 0 ? 0 : space->pool[lev - 1], hi = space->pool[lev];
+        const int64_t blocks = (hi - lo + 255) / 256;
+        const int grid = (int)(blocks < 16384 ? blocks : 16384);
+        hipLaunchKernelGGL(k_pool_units, dim3(grid), dim3(256), 0, st, *space, base_units, units, stats, lo, hi);
+        if (hipGetLastError() != hipSuccess) return SISSO_E_DEVICE;
+    }
+    return SISSO_OK;
+}
 
 extern "C" sisso_status sisso_materialize_pools(const sisso_space *space, const double *X, int32_t n,
                                                 int32_t ldx, float *pool32, int64_t ld32,

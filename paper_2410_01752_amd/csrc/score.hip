@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(256) k_score_columns(
     const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl,
     int64_t c_lo, int64_t c_hi, int64_t id_begin, int64_t id_end, int list_base, void *ws,
-    int lists_total, int keep, int cap, const float *__restrict__ w32)
+    int lists_total, int keep, int cap, const float *__restrict__ w32, const int16_t *__restrict__ units)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     WsView W = ws_view(ws, lists_total, keep);
@@ -117,10 +117,13 @@ __global__ void __launch_bounds__(256) k_score_columns(
                     score_column<NU, WT>(pool32 + (size_t)c * ld32, st, r32, n, nd, R1, Srr, uop, nu,
                                          NU > 0 && rect && c >= newlo, scs, w32);
                 if (!(c >= id_begin && c < id_end)) scs[0] = -1.0f;
+                // dimensional analysis: exp, exp(-x), ln, sin of a dimensionless column only
+                const bool dimless = !units || unit_dimless(unit_of(units, c));
 #pragma unroll
                 for (int o = 0; o < NU; ++o) {
                     const int64_t uid = pL + (c - newlo) * nu + o;
-                    if (!(uid >= id_begin && uid < id_end)) scs[1 + o] = -1.0f;
+                    if (!(uid >= id_begin && uid < id_end) || (!dimless && o < nu && unary_needs_dimless(uop[o])))
+                        scs[1 + o] = -1.0f;
                 }
             }
             if (regs) {
@@ -159,7 +162,7 @@ __global__ void __launch_bounds__(256) k_score_rect(
     const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl,
     int64_t ut_lo, int64_t ut_hi, int64_t id_begin, int64_t id_end, int list_base, void *ws,
-    int lists_total, int keep, int cap, const float *__restrict__ w32)
+    int lists_total, int keep, int cap, const float *__restrict__ w32, const int16_t *__restrict__ units)
 {
     using Cfg = RectCfg<RU, RV>;
     constexpr int TU = Cfg::TU, TV = Cfg::TV;
@@ -193,7 +196,7 @@ __global__ void __launch_bounds__(256) k_score_rect(
             float osc[RU * RV * 5];
             int64_t oid[RU * RV * 5];
             score_pair_tile<RU, RV, WT>(pool32, ld32, stats, r32, n, nd, R1, Srr, fs, ids, u0, U, vt * TV,
-                                        vcount, id_begin, id_end, buf0, buf1, osc, oid, w32);
+                                        vcount, id_begin, id_end, buf0, buf1, osc, oid, w32, units);
             list_offer<RU * RV * 5>(L, osc, oid, &W.h->gthr, excl, n_excl);
         }
     }
@@ -514,7 +517,7 @@ extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso
         auto launch_cols = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(p.g_cols), dim3(256), lsmem, st, *space, args->n, args->pool32, args->ld32,
                                args->stats, args->r32, args->info, args->exclude, args->n_exclude, p.c_lo, p.c_hi,
-                               cand_begin, cand_end, base, ws, lists, keep, cap, args->w32);
+                               cand_begin, cand_end, base, ws, lists, keep, cap, args->w32, args->units);
         };
         if (!weighted) {
             if (nu == 0) launch_cols(k_score_columns<0, false>);
@@ -535,7 +538,7 @@ extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso
             hipLaunchKernelGGL(kern, dim3(p.g_rect), dim3(256), smem, st, *space, fs, args->n, args->pool32,
                                args->ld32, args->stats, args->r32, args->info, args->exclude, args->n_exclude,
                                p.ut_lo, p.ut_hi, cand_begin, cand_end, base + p.g_cols, ws, lists, keep, cap,
-                               args->w32);
+                               args->w32, args->units);
             return SISSO_OK;
         };
         sisso_status rs;

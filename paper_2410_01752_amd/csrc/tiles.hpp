@@ -276,7 +276,7 @@ __device__ __forceinline__ void score_pair_tile(
     const float *__restrict__ r32, int n, double nd, double R1, double Srr, const FormSlots &fs,
     const PairIds &ids, int64_t u0, const USide<RU, RV> &U, int64_t v0, int64_t vcount, int64_t id_begin,
     int64_t id_end, float *buf0, float *buf1, float (&osc)[RU * RV * 5], int64_t (&oid)[RU * RV * 5],
-    const float *__restrict__ w32 = nullptr)
+    const float *__restrict__ w32 = nullptr, const int16_t *__restrict__ units = nullptr)
 {
     using Cfg = RectCfg<RU, RV>;
     constexpr int TU = Cfg::TU, TV = Cfg::TV, TUP = Cfg::TUP, TVP = Cfg::TVP;
@@ -472,6 +472,8 @@ __device__ __forceinline__ void score_pair_tile(
             const int64_t v = v0 + tx * RV + b;
             const int64_t u = u0 + ty * RU + a;
             const bool ok = U.val[a] && vval[b] && (!ids.tri || v < u);
+            // dimensional analysis: a sum or difference needs equal units
+            const bool same_units = !units || unit_eq(unit_of(units, ok ? u : 0), unit_of(units, ok ? v : 0));
             const double shifts[5] = {(double)U.fo[a] + (double)vfo[b], (double)U.fo[a] - (double)vfo[b],
                                       (double)cm[a][b], (double)c3[a][b], (double)c4[a][b]};
             const float *cu = pool32 + (size_t)(ok ? u : 0) * ld32;
@@ -481,7 +483,7 @@ __device__ __forceinline__ void score_pair_tile(
                 const int e = (a * RV + b) * 5 + k;
                 float sc = -1.0f;
                 int64_t fid = INT64_MAX;
-                if (fs.slot[k] >= 0 && ok) {
+                if (fs.slot[k] >= 0 && ok && (k >= 2 || same_units)) {
                     fid = ids.base + (U.row[a] + v) * ids.S + fs.slot[k];
                     if (fid >= id_begin && fid < id_end)
                         sc = form_score(k, fA[a][b][k], dB[a][b][k], dC[a][b][k], shifts[k], cu, cv, n, U.mx[a],
@@ -501,7 +503,8 @@ __device__ __forceinline__ void score_pair_tile(
 __device__ inline float score_slice_id(const sisso_space &s, const FormSlots &fs, int n,
                                        const float *__restrict__ pool32, int64_t ld32,
                                        const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
-                                       const sisso_resid_info *__restrict__ info, int64_t id)
+                                       const sisso_resid_info *__restrict__ info, int64_t id,
+                                       const int16_t *__restrict__ units = nullptr)
 {
     const int Lv = s.levels;
     const int64_t binbase = s.pool[Lv] + s.rect_unary;
@@ -515,6 +518,7 @@ __device__ inline float score_slice_id(const sisso_space &s, const FormSlots &fs
         if (fs.slot[f] == slot) k = f;
     const sisso_colstat ust = stats[u], vst = stats[v];
     if (k < 0 || ust.valid == 0.0f || vst.valid == 0.0f) return -1.0f;
+    if (units && k < 2 && !unit_eq(unit_of(units, u), unit_of(units, v))) return -1.0f;
     const float *cu = pool32 + (size_t)u * ld32, *cv = pool32 + (size_t)v * ld32;
     const int c0 = n < kSC ? n : kSC;
     float pm = 0.f, p3 = 0.f, p4 = 0.f;

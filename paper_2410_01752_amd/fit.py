@@ -49,11 +49,14 @@ class Engine:
     """Device state of one SISSO problem: base features, pools, subspace."""
 
     def __init__(self, X: np.ndarray, y: np.ndarray, unary: Sequence[str], binary: Sequence[str],
-                 levels: int, rect: bool = False, device: str = "cuda:0", weights: Optional[np.ndarray] = None):
+                 levels: int, rect: bool = False, device: str = "cuda:0", weights: Optional[np.ndarray] = None,
+                 dimensionality: Optional[Sequence[str]] = None):
         """`weights`: optional per-sample weights w_s = 1 / sigma_s^2 for noise
         with a known diagonal covariance (Sec. 2.4's whitening): screening,
         duplicate classes and SO then use the weighted correlation and weighted
-        least squares (FP32 screening form only)."""
+        least squares (FP32 screening form only).  `dimensionality`: optional
+        unit string per base feature (Sec. 3.3): features that break
+        dimensional analysis are not generated (FP32 and 16-bit forms)."""
         L.lib()
         self.dev = torch.device(device)
         X = np.asarray(X, dtype=np.float64)
@@ -75,6 +78,15 @@ class Engine:
             ctypes.byref(self.space), L.ptr(self.X), n, n, L.ptr(self.pool32), self.ld32,
             L.ptr(self.pool1), self.ld64, L.ptr(self.stats), L.stream_handle(self.dev)),
             "sisso_materialize_pools")
+        self.units: Optional[torch.Tensor] = None
+        if dimensionality is not None:
+            if len(dimensionality) != self.d:
+                raise L.SissoError("one unit string per base feature")
+            bu = torch.from_numpy(L.base_units(dimensionality)).to(self.dev)
+            self.units = torch.empty(pL * L.UNIT_DIMS, dtype=torch.int16, device=self.dev)
+            L.check(L.lib().sisso_pool_units(ctypes.byref(self.space), L.ptr(bu), L.ptr(self.units),
+                                             L.ptr(self.stats), L.stream_handle(self.dev)), "sisso_pool_units")
+            torch.cuda.synchronize(self.dev)          # bu is released on return
         self.bf16_ops: Optional[torch.Tensor] = None
         self.bf16_moments: Optional[torch.Tensor] = None
         self.tk_status = torch.zeros(1, dtype=torch.int32, device=self.dev)
@@ -138,6 +150,7 @@ class Engine:
         a.n_exclude = int(exclude.numel()) if exclude is not None else 0
         a.keep, a.precision, a.grid, a.tile = keep, precision, grid, tile
         a.w32 = L.ptr(self.w32) if self.w32 is not None else None
+        a.units = L.ptr(self.units) if self.units is not None else None
         return a
 
     def binary_base(self) -> int:
