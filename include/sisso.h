@@ -317,10 +317,12 @@ sisso_status sisso_expand_score(const sisso_space *space, const sisso_score_args
  *   ops       u-side column constants from sisso_prepare_bf16 (size from
  *             sisso_bf16_operands_size; residual-independent, once per problem).
  *   bws       per-call workspace (size from sisso_bf16_workspace_size).
- *   band      candidates rescored, keep <= band <= SISSO_MAX_BAND.  Each
- *             block keeps its best min(band, SISSO_MAX_KEEP) by BF16 score;
- *             a band wider than keep is the margin that absorbs BF16 ranking
- *             errors near the cutoff (ties of regrouped sums, for instance).
+ *   band      candidates rescored, keep <= band <= SISSO_MAX_BAND: the
+ *             band best approximate scores of the slice (score desc, id asc;
+ *             every block keeps its best band and the grid shares the running
+ *             bound, so the band does not depend on the grid).  A band wider
+ *             than keep is the margin that absorbs 16-bit ranking errors near
+ *             the cutoff.
  * [cand_begin, cand_end) must lie in the binary block of the slice.  The
  * recall of the band against the FP32 screening is measured by the tests.
  * Errors: as sisso_expand_score; SISSO_E_UNSUPPORTED without a one-sided
@@ -357,15 +359,18 @@ sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score
  * first runs those nine and stores, for every (u, v) pair of the tiles it
  * covers, six FP32 values (sum h and the variance of u v, u/v and v/u), the
  * candidates the conditioning test flags, and the u side's FP16 operands;
- * then, like a screen in mode SISSO_MOMENTS_READ, it loads them and runs only
- * the three residual GEMMs.  The approximate scores of these screens equal,
- * bit for bit, those of a plain screen of the same residual, so the band, the
- * rescore and the result are the same.
+ * then, like a screen in mode SISSO_MOMENTS_READ, it runs only the three
+ * residual GEMMs, stores their per-pair results, and scores every pair from
+ * them and the stored moments.  The approximate scores of these screens
+ * equal, bit for bit, those of a plain screen of the same residual, so the
+ * band, the rescore and the result are the same.
  *   moments        device buffer of sisso_bf16_moments_size(space, n) bytes,
  *                  owned by the caller: 24 bytes per pair of the padded
  *                  64 x 64 tiles (about 69 GB for 2.65M x 1030 operand
- *                  pairs), the flagged candidates, and 4 bytes per sample of
- *                  each newest-level operand (about 21 GB at n = 2000).
+ *                  pairs), the flagged candidates, 4 bytes per sample of each
+ *                  newest-level operand (about 21 GB at n = 2000), and 12
+ *                  bytes per pair of scratch for a pass's residual GEMMs
+ *                  (about 35 GB).
  *   mode           SISSO_MOMENTS_NONE (moments unused, may be NULL: the same
  *                  as sisso_bf16_screen), SISSO_MOMENTS_WRITE or
  *                  SISSO_MOMENTS_READ.

@@ -81,18 +81,24 @@ template <int MODE> struct BfShape {
     static constexpr int kUVar = kRead ? 2 : 4;     // U~, [U~^2,] Z~, [Z~^2]
     static constexpr int kVVar = kRead ? 2 : 8;     // [V~,] V~ r, [P, Q, W~,] W~ r, [Pw, Qw]
     static constexpr int kNG = kRead ? 3 : 12;      // GEMMs per tile
-    // Block tile: kBTU u columns x kBTV v columns, one 32 x 32 sub-tile per
-    // wave.  The read form's few GEMMs leave registers for two waves per SIMD,
-    // and its wider v tile streams each u tile half as often.
-    static constexpr int kWU = 2, kWV = kRead ? 4 : 2;                 // waves along u and along v
-    static constexpr int kBTU = 32 * kWU, kBTV = 32 * kWV, kThreads = 64 * kWU * kWV;
+    // Block tile: kBTU u columns x kBTV v columns; each wave owns kSubV
+    // 32 x 32 sub-tiles along v.  The read form's few GEMMs leave registers for
+    // two sub-tiles per wave at two waves per SIMD: its 128 x 128 block streams
+    // each image once per 128 columns of the other side.
+    static constexpr int kWU = kRead ? 4 : 2, kWV = 2;                 // waves along u and along v
+    static constexpr int kSubV = kRead ? 2 : 1;                        // 32 x 32 sub-tiles per wave (along v)
+    static constexpr int kBTU = 32 * kWU, kBTV = 32 * kWV * kSubV, kThreads = 64 * kWU * kWV;
     static constexpr int kSU = kBTU * kKC / kThreads;                  // u samples staged per thread
     static constexpr int kSV = kBTV * kKC / kThreads;                  // v samples staged per thread
     static constexpr int kPlaneU = kBTU * kKR, kPlaneV = kBTV * kKR;   // 16-bit values per staged plane
     static constexpr int kPA = kUVar, kPB = kVVar;                     // staged planes per side
     static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;       // 16-bit values per staging buffer
+    // The read form stages its u side as the image's 64-column tiles, each
+    // with its planes: the stride of a u plane within a tile.
+    static constexpr int kAPlane = kRead ? 64 * kKR : kPlaneU;
     static constexpr int kMinBlocks = 1;            // resident blocks per CU the registers are sized for
-    static constexpr int kNStage = kRead ? 4 : 2;   // staging buffers: double buffer, or the read form's ring
+    static constexpr int kNStage = 2;               // staging buffers (double buffer)
+    static constexpr int kRing = 8;                 // the read form: chunks held in registers (loads in flight)
     // accumulator of the residual contraction of u v, u/v and v/u
     static constexpr int kCovUV = kRead ? 0 : 1, kCovUW = kRead ? 1 : 5, kCovZV = kRead ? 2 : 9;
 };
@@ -269,17 +275,10 @@ __device__ __forceinline__ int lds_off(int row, int k)
     return row * kKR + (k ^ ((((row >> 2) ^ (row >> 3)) & 1) << 3));
 }
 
-// s_waitcnt immediate that waits until at most n vector memory operations of
-// this wave are outstanding, leaving the other counters free (gfx9 encoding:
-// vmcnt in bits 3:0 and 15:14, expcnt in 6:4, lgkmcnt in 11:8).
-constexpr int vm_wait(int n) { return (n & 0xF) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8); }
-
-// An LDS address for the direct global-to-LDS loads (wave-uniform: each lane
-// of the load writes its 16 bytes at this address + 16 x lane).
-__device__ __forceinline__ __attribute__((address_space(3))) void *lds_ptr(h16 *p)
-{
-    return (__attribute__((address_space(3))) void *)p;
-}
+// A workgroup barrier after this wave's LDS stores have completed, which
+// leaves its vector memory loads in flight (__syncthreads would wait for
+// them); the clobber keeps the compiler from moving memory accesses across.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // N consecutive floats (N = 2 or 4, 4N-byte aligned) in one load.
 template <int N>
@@ -464,26 +463,196 @@ __global__ void __launch_bounds__(256) k_bf16_v_image(int n, const float *__rest
 // -------------------------------------------------------------- screening
 #endif  // SISSO_BF16_MFMA_PART
 
+// The v column of a pair as the five forms use it.
+struct BfVCol {
+    float mv, mw, Svv, Svr, Swr;   // mean v, mean 1/v, sum v~^2, sum v~ r, sum w~ r
+    bool ok;                       // in the pool and valid
+    bool nonzero;                  // no zero (v/u, u/v defined)
+    bool scalable;                 // the column's variants fit the 16-bit operands
+    uint4 unit;
+};
+
+// The five forms of one (u, v) pair from its column constants, the
+// residual-independent moments m (sum h and variance of u v, u/v and v/u)
+// and the three residual contractions c0, c1, c2 (of u v, u/v and v/u,
+// unscaled): residual covariance, variance, whether the candidate is live
+// (in the space and its form's domain, its variance resolved) and whether it
+// is flagged (in the space, its variance not resolved by the 16-bit
+// operands: scored exactly instead, never live).  ua = (mean u, mean 1/u,
+// sum u~^2, .), ub = (sum u~ r, sum z~ r, ., flags: 1 valid, 2 no zero, 4 not
+// scalable).  The plain form's epilogue and the scorer of stored
+// contractions both call it: the same operations on the same bits.
+__device__ __forceinline__ void bf_forms(float4 ua, float4 ub, uint4 uunit, const BfVCol &vc, const float (&m)[kMom],
+                                         float c0, float c1, float c2, float rr, const FormSlots &fs,
+                                         float (&cov)[5], float (&var)[5], bool (&live)[5], bool (&flag)[5])
+{
+#pragma clang fp contract(off)
+    const float mu = ua.x, mz = ua.y, Suu = ua.z, Sur = ub.x, Szr = ub.y;
+    // (the conditions combine with & and |, not && and ||: evaluated in full,
+    // they stay lane masks instead of becoming branches)
+    const int uflags = (int)ub.w;
+    const bool ok = ((uflags & 1) != 0) & vc.ok;
+    const bool unscal = ((uflags & 4) != 0) | !vc.scalable;
+    const float g0 = m[0];
+    var[0] = Suu + vc.Svv + 2.0f * g0;                  // u + v
+    var[1] = Suu + vc.Svv - 2.0f * g0;                  // u - v
+    cov[0] = Sur + vc.Svr;
+    cov[1] = Sur - vc.Svr;
+    var[2] = m[1];                                      // u v
+    cov[2] = c0 + vc.mv * Sur + mu * vc.Svr - m[0] * rr;
+    var[3] = m[3];                                      // u / v
+    cov[3] = c1 + vc.mw * Sur + mu * vc.Swr - m[2] * rr;
+    var[4] = m[5];                                      // v / u
+    cov[4] = c2 + vc.mv * Szr + mz * vc.Svr - m[4] * rr;
+    // a sum or difference needs operands of equal units
+    const bool same_u = unit_eq(uunit, vc.unit);
+    const bool dom[5] = {same_u, same_u, true, vc.nonzero, (uflags & 2) != 0};
+    // u + v and u - v: trusted when the variance is at least kCondRel of
+    // Suu + Svv (the error of 2 g0 is a fraction of it); the product forms
+    // carry -1 when their test failed
+    const float cth = kCondRel * (Suu + vc.Svv);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const bool cand = ok & dom[k] & (fs.slot[k] >= 0);
+        const bool good = !unscal & (k < 2 ? var[k] >= cth : var[k] > 0.0f) & (var[k] < INFINITY);
+        live[k] = cand & good & (var[k] > 0.0f);
+        flag[k] = cand & !good;
+    }
+}
+
+// Approximate scores of the five forms of a pair, -1 for a candidate that is
+// not live; |cov| / sqrt(var Srr), clamped to 1 when rounding exceeds it.
+__device__ __forceinline__ void bf_scores(const float (&cov)[5], const float (&var)[5], const bool (&live)[5],
+                                          double Srr, float (&sc)[5])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const float q = fabsf(cov[k]) * __builtin_amdgcn_rsqf(var[k] * (float)Srr);
+        const float sk = q <= 1.0f ? q : (q > 1.0f ? 1.0f : -1.0f);   // rounding above 1, or NaN
+        sc[k] = live[k] ? sk : -1.0f;
+    }
+}
+
+// Admission of one 32 x 32 sub-tile's candidates into the block list, after
+// each lane has tested its 16 rows (bit r of `rows`: row r may have a
+// candidate at the bound tb).  Block-uniform: every wave of the block calls it
+// with its own sub-tile (rows = 0 for none) and `pend` a shared counter that
+// is zero on entry.  row_scores(r, sc) gives row r's scores, fid_of(r, k) a
+// candidate's id, in_range(id) whether the id is in the slice.
+template <class RowScores, class FidOf, class InRange>
+__device__ __forceinline__ void bf_admit(BlockList &Lst, unsigned *gb, int *pend, unsigned rows, float tb,
+                                         const int64_t *__restrict__ excl, int n_excl, RowScores &&row_scores,
+                                         FidOf &&fid_of, InRange &&in_range)
+{
+    auto admit_id = [&](int64_t id) { return in_range(id) && (n_excl == 0 || !in_sorted_ids(excl, n_excl, id)); };
+    // Count this lane's candidates at or above the admission bound (the
+    // bounds only rise, so a stale read admits more, never fewer), in range
+    // and not excluded, and the block's total.  When they all fit into the
+    // list, every thread reserves its slots with one atomic and writes them:
+    // no per-row barriers.
+    int mine = 0;
+    if (rows) {
+#pragma unroll 1
+        for (int r = 0; r < 16; ++r) {
+            if (!((rows >> r) & 1u)) continue;
+            float sc[5];
+            row_scores(r, sc);
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                if (sc[k] >= 0.0f && sc[k] >= tb && admit_id(fid_of(r, k))) ++mine;
+        }
+    }
+    if (mine) atomicAdd(pend, mine);
+    __syncthreads();
+    const int total = *pend;                  // the caller resets it after a later barrier
+    if (total == 0) return;
+    // Every thread takes the same branch only if every thread reads the
+    // list's count before any thread reserves slots: read it, merge if the
+    // candidates do not fit (block-uniform, ends with a barrier), read it
+    // again, and meet at a barrier before reserving.
+    int cnt0 = *Lst.cnt;
+    if (cnt0 + total > Lst.cap) {
+        list_merge(Lst, gb);
+        cnt0 = *Lst.cnt;
+    }
+    __syncthreads();
+    if (cnt0 + total <= Lst.cap) {
+        if (mine) {
+            int slot = atomicAdd(Lst.cnt, mine);
+#pragma unroll 1
+            for (int r = 0; r < 16; ++r) {
+                if (!((rows >> r) & 1u)) continue;
+                float sc[5];
+                row_scores(r, sc);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    if (!(sc[k] >= 0.0f && sc[k] >= tb)) continue;
+                    const int64_t id = fid_of(r, k);
+                    if (admit_id(id)) {
+                        Lst.sc[slot] = sc[k];
+                        Lst.id[slot] = id;
+                        ++slot;
+                    }
+                }
+            }
+        }
+        return;
+    }
+    // the list is filling: row by row, merging as needed
+#pragma unroll 1
+    for (int r = 0; r < 16; ++r) {
+        float sc[5];
+        int64_t fid[5];
+        row_scores(r, sc);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            fid[k] = fid_of(r, k);
+            if (!in_range(fid[k])) sc[k] = -1.0f;
+        }
+        __syncthreads();
+        const int c = *Lst.cnt;
+        __syncthreads();
+        if (c + 5 * (int)blockDim.x <= Lst.cap) {
+            const float t = fmaxf(*Lst.thr, load_gthr(gb));
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                if (sc[k] >= 0.0f && sc[k] >= t && (n_excl == 0 || !in_sorted_ids(excl, n_excl, fid[k]))) {
+                    const int slot = atomicAdd(Lst.cnt, 1);
+                    Lst.sc[slot] = sc[k];
+                    Lst.id[slot] = fid[k];
+                }
+        } else {
+            list_offer<5>(Lst, sc, fid, gb, excl, n_excl);
+        }
+    }
+}
+
 // mom: per 64 x 64 tile (ut64, vt64) of (u, v) pairs, its four 32 x 32
 // sub-tiles w = su + 2 sv (su, sv: the 32-column half of the tile along u and
 // along v), row slot r and moment k, the 64 lanes' values, at float offset
 // (((ut64 * nvt64 + vt64) * 4 + w) * 16 + r) * kMom * 64 + k * 64 + lane
-// (written by the moments pass, read by kBfRead, unused by kBfFull; nvt64 = ceil(|P_1| / 64)).
-// The layout does not depend on a form's block tile.
+// (written by the moments pass, read by the scorer of stored contractions;
+// nvt64 = ceil(|P_1| / 64)).  cst: the residual contractions of a pass in the
+// same tiling, three per pair: (((ut64 * nvt64 + vt64) * 4 + w) * 16 + r) *
+// 3 * 64 + k * 64 + lane (written by kBfRead).  Lane l holds column l % 32
+// and row 8 (r / 4) + 4 (l / 32) + (r % 4) of its 32 x 32 sub-tile.
 template <int MODE>
 __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBlocks) k_score_rect_bf16(
     sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
     const float *__restrict__ r32, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
     const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t ut_lo,
-    int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, const h16 *__restrict__ vimg,
-    const h16 *__restrict__ uimg, const int16_t *__restrict__ units, BfSide side, void *lws, int lists_total,
+    int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ cst, const h16 *__restrict__ vimg,
+    const h16 *uimg, const int16_t *__restrict__ units, BfSide side, void *lws, int lists_total,
     int keep, int cap, int publish)
 {
+    // (uimg is not restrict-qualified: the read form's loads of a u tile's
+    // first chunks, the same for every v tile, must not be hoisted out of the
+    // v-tile loop into registers the chunk loop needs)
     using Sh = BfShape<MODE>;
     constexpr int kUVar = Sh::kUVar, kVVar = Sh::kVVar, kNG = Sh::kNG, kPA = Sh::kPA, kPB = Sh::kPB,
                   kStage = Sh::kStage, kBTU = Sh::kBTU, kBTV = Sh::kBTV, kSU = Sh::kSU, kSV = Sh::kSV,
-                  kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV;
+                  kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV, kAPlane = Sh::kAPlane, kSubV = Sh::kSubV;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     h16 *const stage = reinterpret_cast<h16 *>(smem);   // staging buffers (two; the read form's ring: kNStage)
     float *lsc = (float *)(stage + Sh::kNStage * kStage);
@@ -493,14 +662,14 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     // inverse scale factors of U~, U~^2, Z~, Z~^2
     float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + kBTU, *ucon_c = ucon_b + kBTU;
     uint4 *ucon_u = reinterpret_cast<uint4 *>(ucon_c + kBTU);      // the u columns' units (zero without units)
-    __shared__ int lcnt, lpend;
+    __shared__ int lcnt, lpend[kSubV];            // lpend: candidates of each sub-tile's epilogue
     __shared__ float lthr;
     __shared__ unsigned gdummy;                   // bound of a block that must not publish (stays 0)
     WsView W = ws_view(lws, lists_total, keep);
     if (threadIdx.x == 0) gdummy = 0u;
     unsigned *const gb = publish ? &W.h->gthr : &gdummy;
     BlockList Lst{lsc, lid, &lcnt, &lthr, cap, keep};
-    if (threadIdx.x == 0) lpend = 0;
+    if (threadIdx.x < kSubV) lpend[threadIdx.x] = 0;
     list_init(Lst);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -519,9 +688,15 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
     const int vcs = tid / (kKC / kSV), vks = (tid % (kKC / kSV)) * kSV;
     const int tmax_u = ((n - 1) / kSU) * kSU, tmax_v = ((n - 1) / kSV) * kSV;   // loads stay inside a column
     const int sto_u = lds_off(ucs, uks), sto_v = lds_off(vcs, vks);              // store offsets within a plane
-    // fragment role: lane reads 8 samples (koff ..) of row lane % 32 of its wave's 32-row part
+    // fragment role: lane reads 8 samples (koff ..) of row lane % 32 of its
+    // wave's 32-row part (the read form: of its 64-column u tile), and of each
+    // of its v sub-tiles
     const int koff = (lane >> 5) * 8;
-    const int fa = lds_off(wu * 32 + (lane & 31), koff), fb = lds_off(wv * 32 + (lane & 31), koff);
+    const int fa = Sh::kRead ? (wu >> 1) * (kPA * kAPlane) + lds_off((wu & 1) * 32 + (lane & 31), koff)
+                             : lds_off(wu * 32 + (lane & 31), koff);
+    int fb[kSubV];
+#pragma unroll
+    for (int s2 = 0; s2 < kSubV; ++s2) fb[s2] = lds_off((wv * kSubV + s2) * 32 + (lane & 31), koff);
 
     for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
         const int64_t u0 = ut * kBTU;  // index into the newest level
@@ -555,11 +730,13 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             const float smv = vs_c.x, smw = vs_c.y;
             const VScale vsc = v_scales(smv, smw, vs_c.z, vs_c.w, fn, rsc, shs);
             const float *vcol = pool32 + (size_t)(sv_ok ? sv : 0) * ld32;
-            f32x16 acc[kNG];
+            f32x16 acc[kSubV][kNG];
 #pragma unroll
-            for (int g = 0; g < kNG; ++g)
+            for (int s2 = 0; s2 < kSubV; ++s2)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
+                for (int g = 0; g < kNG; ++g)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) acc[s2][g][e] = 0.0f;
             // Raw FP32 values of one chunk are loaded two chunks ahead into
             // registers; the centred, scaled variants are formed, rounded to FP16
             // and stored into the other staging buffer while the MFMAs of the
@@ -644,15 +821,20 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             // buffer a barrier between the two frees the buffer for the next chunk
             // (every wave holds its fragments in registers by then).
             auto mfma_chunk = [&](const h16 *buf) {
-                h16x8 af[kPA], bfr[kPB];
+                h16x8 af[kPA], bfr[kSubV][kPB];
 #pragma unroll
-                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const h16x8 *>(buf + a * kPlaneU + fa);
+                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const h16x8 *>(buf + a * kAPlane + fa);
 #pragma unroll
-                for (int q = 0; q < kPB; ++q)
-                    bfr[q] = *reinterpret_cast<const h16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb);
+                for (int s2 = 0; s2 < kSubV; ++s2)
 #pragma unroll
-                for (int g = 0; g < kNG; ++g)
-                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[GA(g)], bfr[GB(g)], acc[g], 0, 0, 0);
+                    for (int q = 0; q < kPB; ++q)
+                        bfr[s2][q] = *reinterpret_cast<const h16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb[s2]);
+#pragma unroll
+                for (int s2 = 0; s2 < kSubV; ++s2)
+#pragma unroll
+                    for (int g = 0; g < kNG; ++g)
+                        acc[s2][g] =
+                            __builtin_amdgcn_mfma_f32_32x32x16_f16(af[GA(g)], bfr[s2][GB(g)], acc[s2][g], 0, 0, 0);
             };
             // interleave: fragment reads first, then each MFMA followed by a share of
             // the staging work of the next chunk (VALU and LDS stores)
@@ -667,47 +849,61 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 }
             };
             auto buf_of = [&](int c) { return stage + (c & 1) * kStage; };   // two staging buffers
-            // this wave's 32 x 32 sub-tile in the moments' 64 x 64 tiling; a
-            // sub-tile past the last 64-column tile has no pair in the space
-            const int64_t v32 = vt * Sh::kWV + wv;
-            const int64_t u64 = (u0 + wu * 32) / 64;
-            const bool mom_in = (v32 >> 1) < nvt64 && u64 < nut64;
-            const size_t mom_off = (((size_t)u64 * nvt64 + (v32 >> 1)) * 4 + (wu & 1) + 2 * (int)(v32 & 1)) *
-                                   (16 * kMom * 64);
-            __builtin_amdgcn_s_waitcnt(vm_wait(0));   // the ring's load counts below are exact
             __syncthreads();                          // the previous tile's fragment reads are done
-            if (tid == 0) lpend = 0;                  // every thread has read the previous total
+            if (tid < kSubV) lpend[tid] = 0;          // every thread has read the previous totals
             if constexpr (Sh::kRead) {
                 // Both sides are copies of FP16 images already in the staged
-                // layout (u: written by the moments pass; v: per residual), moved
-                // by direct global-to-LDS loads into a ring of kNS stages, kNS - 1
-                // chunks ahead: no registers hold data in flight.  Chunk c's 4 KB
-                // of u are four 1 KB wave loads (waves 0..3), its 8 KB of v eight
-                // (one per wave).  Loads past the last chunk re-read it into the
-                // free stage.
-                constexpr int kNS = Sh::kNStage;
-                const h16 *const ub = uimg + (size_t)(u0 / 64) * nch * (kPA * kPlaneU) + w * 512 + lane * 8;
+                // layout (u: written by the moments pass; v: per residual).
+                // Chunk c's 8 KB of u (two 64-column image tiles of 4 KB) and
+                // its 8 KB of v are 1 KB pieces, one of each per wave: wave w's
+                // u piece is piece w % 4 of tile w / 4, at stage offset 512 w
+                // either way.  A tile past the last one re-reads the last (its
+                // columns are outside the space).  The pieces travel through a
+                // ring of kRing chunks in registers (the loads of kRing - 1
+                // chunks stay in flight while a chunk is computed: the reads
+                // come from L2 and the MALL, and their latency is hidden only by
+                // many bytes in flight), then into the two staging buffers.
+                constexpr int kR = Sh::kRing;
+                static_assert(!Sh::kRead || (kPA * kPlaneU == 8 * 512 && kPB * kPlaneV == 8 * 512 &&
+                                             Sh::kThreads == 512 && kPA * kAPlane == 4 * 512),
+                              "one 1 KB u piece and one v piece per wave");
+                const int64_t utile = u0 / 64 + (w >> 2) < nut64 ? u0 / 64 + (w >> 2) : nut64 - 1;
+                const h16 *const ub = uimg + (size_t)utile * nch * (kPA * kAPlane) + (w & 3) * 512 + lane * 8;
                 const h16 *const vb = vimg + (size_t)vt * nch * (kPB * kPlaneV) + w * 512 + lane * 8;
-                auto issue = [&](int c) {
-                    h16 *const stg = stage + (c % kNS) * kStage;
+                u32x4 ru[kR], rv[kR];
+                auto fetch = [&](int c, u32x4 &a, u32x4 &b) {
                     const size_t cc = (size_t)(c < nch ? c : nch - 1);
-                    if (w < 4) __builtin_amdgcn_global_load_lds(ub + cc * (kPA * kPlaneU), lds_ptr(stg + w * 512), 16, 0, 0);
-                    __builtin_amdgcn_global_load_lds(vb + cc * (kPB * kPlaneV), lds_ptr(stg + kPA * kPlaneU + w * 512), 16, 0,
-                                                     0);
+                    a = *reinterpret_cast<const u32x4 *>(ub + cc * (kPA * kAPlane));
+                    b = *reinterpret_cast<const u32x4 *>(vb + cc * (kPB * kPlaneV));
                 };
-#pragma unroll
-                for (int c = 0; c < kNS - 1; ++c) issue(c);
-                for (int ch = 0; ch < nch; ++ch) {
-                    // this wave's loads of chunk ch are done when at most the
-                    // kNS - 2 later chunks' are outstanding; the barrier makes
-                    // every wave's part visible and frees the stage read last
-                    if (w < 4) __builtin_amdgcn_s_waitcnt(vm_wait(2 * (kNS - 2)));
-                    else __builtin_amdgcn_s_waitcnt(vm_wait(kNS - 2));
-                    __builtin_amdgcn_s_barrier();
-                    issue(ch + kNS - 1);
-                    mfma_chunk(stage + (ch % kNS) * kStage);
-                }
-                __builtin_amdgcn_s_waitcnt(vm_wait(0));
+                // chunk ch: registers to staging buffer ch % 2, the load of
+                // chunk ch + kR into the freed registers, a barrier (the stores of
+                // every wave are visible, and every wave is past the fragment
+                // reads of chunk ch - 2, the buffer's previous user), the MFMAs
+                auto step = [&](int ch, u32x4 &a, u32x4 &b, bool refill) {
+                    h16 *const buf = stage + (ch & 1) * kStage;
+                    *reinterpret_cast<u32x4 *>(buf + w * 512 + lane * 8) = a;
+                    *reinterpret_cast<u32x4 *>(buf + kPA * kPlaneU + w * 512 + lane * 8) = b;
+                    if (refill) fetch(ch + kR, a, b);
+                    lds_barrier();
+                    mfma_chunk(buf);
+                };
+                // the first kR chunks, in order (the compiler's waits in the
+                // loop assume the oldest load is the one needed first)
+                static_for<kR>([&](auto S) {
+                    fetch(decltype(S)::value, ru[S], rv[S]);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+                // whole groups of kR chunks without a branch, so that the load
+                // counts are the same in every group (the compiler's waits then
+                // leave kR - 1 chunks in flight); loads past the last chunk
+                // re-read it
+                int c0 = 0;
+                for (; c0 + kR <= nch; c0 += kR)
+                    static_for<kR>([&](auto S) { step(c0 + decltype(S)::value, ru[S], rv[S], true); });
+                static_for<kR>([&](auto S) {
+                    if (c0 + decltype(S)::value < nch) step(c0 + decltype(S)::value, ru[S], rv[S], false);
+                });
             } else {
                 // pr holds chunk ch + 1 while chunk ch + 2 loads (loads past the last
                 // chunk re-read it); deeper load rings were slower
@@ -734,41 +930,71 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 mfma_chunk(buf_of(ch));
             }
 
-            // this tile's moments: loaded once the chunk loop's registers are free
-            // (held across the loop they would be spilled; the other block on the
-            // CU runs meanwhile)
-            float mr[Sh::kRead ? 16 * kMom : 1];
             if constexpr (Sh::kRead) {
-                const float *const mp = mom + mom_off + lane;
-#pragma unroll
-                for (int q = 0; q < 16 * kMom; ++q) mr[q] = mom_in ? __builtin_nontemporal_load(mp + q * 64) : 0.0f;
-            }
-
-            // epilogue: lane holds column j = lane % 32 and rows
-            // i = 8 (r / 4) + 4 (lane / 32) + (r % 4) of each 32 x 32 result
-            const int j = lane & 31;
-            const int64_t v = v0 + wv * 32 + j;
-            const bool vin = v < vcount;
-            const sisso_colstat vst = stats[vin ? v : 0];
-            const float4 vs0 = vsum[2 * (vin ? v : 0)], vs1 = vsum[2 * (vin ? v : 0) + 1];
-            const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w, Svr = vs1.x, Swr = vs1.y;
-            const float rr = (float)(R1 / nd);
-            const uint4 vunit = units ? unit_of(units, vin ? v : 0) : make_uint4(0u, 0u, 0u, 0u);
-            // inverse scale factors of this lane's v column: the accumulator of
-            // GEMM g times iu(row) iv(column) is the unscaled contraction
-            const VScale vc = v_scales(mv, mw, Svv, Sww, fn, rsc, shs);
-            const float iv = 1.0f / vc.v, ip = 1.0f / vc.p, iq = 1.0f / vc.q, ivr = 1.0f / vc.vr, iw = 1.0f / vc.w,
-                        ipw = 1.0f / vc.pw, iqw = 1.0f / vc.qw, iwr = 1.0f / vc.wr;
-            const bool vscal = col_scalable(Svv, Sww, fn, vst.minabs > 0.0f);
-            // Residual-independent moments of row r, from the accumulators: sum h
-            // of u v, its variance, then the same for u/v and v/u.  A variance
-            // below kCondRel of the magnitude of its terms is not resolved by the
-            // FP16 operands: it is stored as -1 (the candidate is scored exactly).
-            // The read form takes the moments as the moments pass stored them
-            // over the same pools (the same operations on the same bits).
-            auto moments_acc = [&](int r, float (&m)[kMom]) {
+                // The pass's three residual contractions of every pair of this
+                // wave's sub-tiles, unscaled, into the moments' tiling (the
+                // scorer of stored contractions reads them beside the moments);
+                // a sub-tile past the last 64-column tile has no pair in the space
+                static_for<kSubV>([&](auto SV) {
 #pragma clang fp contract(off)
-                if constexpr (!Sh::kRead) {
+                    constexpr int sv = decltype(SV)::value;
+                    const int64_t v32 = vt * (Sh::kWV * kSubV) + wv * kSubV + sv;
+                    const int64_t u64 = (u0 + wu * 32) / 64;
+                    if ((v32 >> 1) < nvt64 && u64 < nut64) {
+                        const int64_t v = v0 + (wv * kSubV + sv) * 32 + (lane & 31);
+                        const float4 vs0 = vsum[2 * (v < vcount ? v : 0)];
+                        const VScale vc = v_scales(vs0.x, vs0.y, vs0.z, vs0.w, fn, rsc, shs);
+                        const float ivr = 1.0f / vc.vr, iwr = 1.0f / vc.wr;
+                        float *const cp =
+                            cst + (((size_t)u64 * nvt64 + (v32 >> 1)) * 4 + (wu & 1) + 2 * (int)(v32 & 1)) * (16 * 3 * 64) +
+                            lane;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                            const float4 ui = ucon_c[wu * 32 + i];
+                            __builtin_nontemporal_store((acc[sv][Sh::kCovUV][r] * ui.x) * ivr, cp + (r * 3 + 0) * 64);
+                            __builtin_nontemporal_store((acc[sv][Sh::kCovUW][r] * ui.x) * iwr, cp + (r * 3 + 1) * 64);
+                            __builtin_nontemporal_store((acc[sv][Sh::kCovZV][r] * ui.z) * ivr, cp + (r * 3 + 2) * 64);
+                        }
+                    }
+                });
+                continue;
+            } else {
+                // The plain form's epilogue.  Its code is kept small (runtime
+                // loops over the rows, a row's accumulator values taken by a
+                // uniform register index): unrolled, it outgrows the instruction
+                // cache and is fetched again for every tile.
+                auto &acs = acc[0];
+                // lane holds column j = lane % 32 and rows
+                // i = 8 (r / 4) + 4 (lane / 32) + (r % 4) of each 32 x 32 result
+                const int j = lane & 31;
+                const int64_t v = v0 + wv * 32 + j;
+                const bool vin = v < vcount;
+                const sisso_colstat vst = stats[vin ? v : 0];
+                const float4 vs0 = vsum[2 * (vin ? v : 0)], vs1 = vsum[2 * (vin ? v : 0) + 1];
+                const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w;
+                const float rr = (float)(R1 / nd);
+                const BfVCol vcol{mv,
+                                  mw,
+                                  Svv,
+                                  vs1.x,
+                                  vs1.y,
+                                  vin && vst.valid != 0.0f,
+                                  vst.minabs > 0.0f,
+                                  col_scalable(Svv, Sww, fn, vst.minabs > 0.0f),
+                                  units ? unit_of(units, vin ? v : 0) : make_uint4(0u, 0u, 0u, 0u)};
+                // inverse scale factors of this lane's v column: the accumulator of
+                // GEMM g times iu(row) iv(column) is the unscaled contraction
+                const VScale vc = v_scales(mv, mw, Svv, Sww, fn, rsc, shs);
+                const float iv = 1.0f / vc.v, ip = 1.0f / vc.p, iq = 1.0f / vc.q, ivr = 1.0f / vc.vr, iw = 1.0f / vc.w,
+                            ipw = 1.0f / vc.pw, iqw = 1.0f / vc.qw, iwr = 1.0f / vc.wr;
+                // Residual-independent moments of row r, from the accumulators: sum h
+                // of u v, its variance, then the same for u/v and v/u.  A variance
+                // below kCondRel of the magnitude of its terms is not resolved by the
+                // FP16 operands: it is -1 (the candidate is scored exactly).  The
+                // moments pass stores exactly these values.
+                auto moments_acc = [&](int r, float (&m)[kMom]) {
+#pragma clang fp contract(off)
                     const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                     const float4 us = ucon_a[wu * 32 + i], ui = ucon_c[wu * 32 + i];
                     const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w;
@@ -778,208 +1004,343 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                         const float mag = fabsf(g2) + fabsf(t2) + t3 + t4;
                         return var >= kCondRel * mag && var < INFINITY ? var : -1.0f;
                     };
-                    m[0] = (acc[0][r] * ui.x) * iv;                 // u v
-                    m[1] = var_of(m[0], (acc[2][r] * ui.y) * ip, (acc[3][r] * ui.x) * iq, mu, mv, Suu, Svv);
-                    m[2] = (acc[4][r] * ui.x) * iw;                 // u / v
-                    m[3] = var_of(m[2], (acc[6][r] * ui.y) * ipw, (acc[7][r] * ui.x) * iqw, mu, mw, Suu, Sww);
-                    m[4] = (acc[8][r] * ui.z) * iv;                 // v / u
-                    m[5] = var_of(m[4], (acc[10][r] * ui.w) * ip, (acc[11][r] * ui.z) * iq, mz, mv, Szz, Svv);
-                }
-            };
-            auto moments_of = [&](int r, float (&m)[kMom]) {
-                if constexpr (MODE == kBfFull) {
-                    moments_acc(r, m);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < kMom; ++k) m[k] = mr[r * kMom + k];
-                }
-            };
-            // Approximate scores of the five forms of row r of this lane, -1 for
-            // a pair outside the space or a form outside its domain.  Branch-free;
-            // ids are formed only for the few candidates at the admission bound.
-            // flag[k]: a candidate of the space whose approximate variance fails
-            // the conditioning test (scored exactly instead; never live).
-            auto row_sums = [&](int r, float (&cov)[5], float (&var)[5], bool (&live)[5], bool (&flag)[5]) {
+                    m[0] = (acs[0][r] * ui.x) * iv;                 // u v
+                    m[1] = var_of(m[0], (acs[2][r] * ui.y) * ip, (acs[3][r] * ui.x) * iq, mu, mv, Suu, Svv);
+                    m[2] = (acs[4][r] * ui.x) * iw;                 // u / v
+                    m[3] = var_of(m[2], (acs[6][r] * ui.y) * ipw, (acs[7][r] * ui.x) * iqw, mu, mw, Suu, Sww);
+                    m[4] = (acs[8][r] * ui.z) * iv;                 // v / u
+                    m[5] = var_of(m[4], (acs[10][r] * ui.w) * ip, (acs[11][r] * ui.z) * iq, mz, mv, Szz, Svv);
+                };
+                // the five forms of row r (see bf_forms)
+                auto row_sums = [&](int r, float (&cov)[5], float (&var)[5], bool (&live)[5], bool (&flag)[5]) {
 #pragma clang fp contract(off)
-                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const float4 us = ucon_a[wu * 32 + i], ub = ucon_b[wu * 32 + i], ui = ucon_c[wu * 32 + i];
-                const float mu = us.x, mz = us.y, Suu = us.z, Sur = ub.x, Szr = ub.y;
-                const int uflags = (int)ub.w;
-                const bool ok = (uflags & 1) && vin && vst.valid != 0.0f;
-                const bool unscal = (uflags & 4) != 0 || !vscal;
-                float m[kMom];
-                moments_of(r, m);
-                const float g0 = m[0];
-                var[0] = Suu + Svv + 2.0f * g0;                     // u + v
-                var[1] = Suu + Svv - 2.0f * g0;                     // u - v
-                cov[0] = Sur + Svr;
-                cov[1] = Sur - Svr;
-                var[2] = m[1];                                      // u v
-                cov[2] = (acc[Sh::kCovUV][r] * ui.x) * ivr + mv * Sur + mu * Svr - m[0] * rr;
-                var[3] = m[3];                                      // u / v
-                cov[3] = (acc[Sh::kCovUW][r] * ui.x) * iwr + mw * Sur + mu * Swr - m[2] * rr;
-                var[4] = m[5];                                      // v / u
-                cov[4] = (acc[Sh::kCovZV][r] * ui.z) * ivr + mv * Szr + mz * Svr - m[4] * rr;
-                // a sum or difference needs operands of equal units
-                const bool same_u = unit_eq(ucon_u[wu * 32 + i], vunit);
-                const bool dom[5] = {same_u, same_u, true, vst.minabs > 0.f, (uflags & 2) != 0};
-                // u + v and u - v: trusted when the variance is at least kCondRel
-                // of Suu + Svv (the error of 2 g0 is a fraction of it); the
-                // product forms carry -1 when their test failed
-                const float cth = kCondRel * (Suu + Svv);
+                    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const float4 ui = ucon_c[wu * 32 + i];
+                    float m[kMom];
+                    moments_acc(r, m);
+                    const float c0 = (acs[Sh::kCovUV][r] * ui.x) * ivr, c1 = (acs[Sh::kCovUW][r] * ui.x) * iwr,
+                                c2 = (acs[Sh::kCovZV][r] * ui.z) * ivr;
+                    bf_forms(ucon_a[wu * 32 + i], ucon_b[wu * 32 + i], ucon_u[wu * 32 + i], vcol, m, c0, c1, c2, rr, fs,
+                             cov, var, live, flag);
+                };
+                auto row_scores = [&](int r, float (&sc)[5]) {
+                    float cov[5], var[5];
+                    bool live[5], flag[5];
+                    row_sums(r, cov, var, live, flag);
+                    bf_scores(cov, var, live, Srr, sc);
+                };
+                auto fid_of = [&](int r, int k) -> int64_t {
+                    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    return binbase + ((u0 + wu * 32 + i) * vcount + v) * S + fs.slot[k];
+                };
+                // every id of the tile inside [id_begin, id_end) (the usual case): no
+                // per-candidate range check
+                const int64_t tile_lo = binbase + (u0 * vcount + v0) * S;
+                const int64_t tile_hi = binbase + ((u0 + kBTU - 1) * vcount + v0 + kBTV - 1) * S + S;
+                const bool tile_in = tile_lo >= id_begin && tile_hi <= id_end;
+                auto in_range = [&](int64_t id) { return tile_in || (id >= id_begin && id < id_end); };
+                const float tb = fmaxf(*Lst.thr, load_gthr(gb));
+                // Rows with a candidate at the bound, by a test without the reciprocal
+                // square root: |cov| / sqrt(var Srr) >= tb as cov^2 >= var Srr tb^2,
+                // loosened by a margin above the rounding of rsq and of the squares.
+                // It may flag a row whose scores all fall below the bound (the exact
+                // test then admits nothing from it), never the reverse.
+                const bool no_bound = !(tb > 0.0f);
+                const float k2 = (float)Srr * tb * tb * (1.0f - 1e-5f);
+                unsigned rows = 0;                        // bit r: row r may have a candidate at the bound
+#pragma unroll 1
+                for (int r = 0; r < 16; ++r) {
+                    float cov[5], var[5];
+                    bool live[5], flag[5];
+                    row_sums(r, cov, var, live, flag);
+                    bool hit = false, fl = false;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    const bool cand = ok && dom[k] && fs.slot[k] >= 0;
-                    const bool good = !unscal && (k < 2 ? var[k] >= cth : var[k] > 0.0f) && var[k] < INFINITY;
-                    live[k] = cand && good && var[k] > 0.0f;
-                    flag[k] = cand && !good;
-                }
-            };
-            auto row_scores = [&](int r, float (&sc)[5]) {
-                float cov[5], var[5];
-                bool live[5], flag[5];
-                row_sums(r, cov, var, live, flag);
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    const float q = fabsf(cov[k]) * __builtin_amdgcn_rsqf(var[k] * (float)Srr);
-                    const float sk = q <= 1.0f ? q : (q > 1.0f ? 1.0f : -1.0f);   // rounding above 1, or NaN
-                    sc[k] = live[k] ? sk : -1.0f;
-                }
-            };
-            auto fid_of = [&](int r, int k) -> int64_t {
-                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                return binbase + ((u0 + wu * 32 + i) * vcount + v) * S + fs.slot[k];
-            };
-            // every id of the tile inside [id_begin, id_end) (the usual case): no
-            // per-candidate range check
-            const int64_t tile_lo = binbase + (u0 * vcount + v0) * S;
-            const int64_t tile_hi = binbase + ((u0 + kBTU - 1) * vcount + v0 + kBTV - 1) * S + S;
-            const bool tile_in = tile_lo >= id_begin && tile_hi <= id_end;
-            auto admit_id = [&](int64_t id) {
-                return (tile_in || (id >= id_begin && id < id_end)) &&
-                       (n_excl == 0 || !in_sorted_ids(excl, n_excl, id));
-            };
-            // Count this lane's candidates at or above the admission bound (the
-            // bounds only rise, so a stale read admits more, never fewer), in
-            // range and not excluded, and the block's total.  When they all fit
-            // into the list, every thread reserves its slots with one atomic and
-            // writes them: no per-row barriers.
-            const float tb = fmaxf(*Lst.thr, load_gthr(gb));
-            // Rows with a candidate at the bound, by a test without the reciprocal
-            // square root: |cov| / sqrt(var Srr) >= tb as cov^2 >= var Srr tb^2,
-            // loosened by a margin above the rounding of rsq and of the squares.
-            // It may flag a row whose scores all fall below the bound (the exact
-            // test below then admits nothing from it), never the reverse.
-            const bool no_bound = !(tb > 0.0f);
-            const float k2 = (float)Srr * tb * tb * (1.0f - 1e-5f);
-            unsigned rows = 0;                        // bit r: row r may have a candidate at the bound
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                float cov[5], var[5];
-                bool live[5], flag[5];
-                row_sums(r, cov, var, live, flag);
-                bool hit = false, fl = false;
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    hit = hit || (live[k] && (no_bound || cov[k] * cov[k] >= var[k] * k2));
-                    fl = fl || flag[k];
-                }
-                rows |= (hit ? 1u : 0u) << r;
-                if constexpr (!Sh::kRead) {
+                    for (int k = 0; k < 5; ++k) {
+                        hit = hit | (live[k] & (no_bound | (cov[k] * cov[k] >= var[k] * k2)));
+                        fl = fl | flag[k];
+                    }
+                    rows |= (hit ? 1u : 0u) << r;
                     // flagged candidates in range join the list of exact scoring
                     // (the exclusion list is applied when they are scored)
                     if (fl) {
 #pragma unroll
                         for (int k = 0; k < 5; ++k) {
                             const int64_t id = fid_of(r, k);
-                            if (flag[k] && (tile_in || (id >= id_begin && id < id_end))) {
+                            if (flag[k] && in_range(id)) {
                                 const unsigned long long q = atomicAdd(side.cnt, 1ull);
                                 if (q < (unsigned long long)side.cap) side.ids[q] = id;
                             }
                         }
                     }
                 }
+                bf_admit(Lst, gb, &lpend[0], rows, tb, excl, n_excl, row_scores, fid_of, in_range);
             }
-            int mine = 0;
-            if (rows) {
+        }
+    }
+    if constexpr (!Sh::kRead)
+        list_flush(Lst, gb, W.sc + (size_t)blockIdx.x * keep, W.id + (size_t)blockIdx.x * keep);
+}
+
+#ifndef SISSO_BF16_MFMA_PART
+// ------------------------------------------- scorer of stored contractions
+//
+// The second kernel of a pass that reads the moments: the five forms of every
+// pair from the stored moments and the pass's three residual contractions
+// (written by kBfRead), through bf_forms as the plain form scores them.  No
+// accumulators are held, so a block of sixteen waves (four per SIMD) hides
+// the loads' latency.  A block stages the row constants of kScU 64-column u
+// tiles in LDS, then each wave takes 32 x 32 sub-tiles of them.  Three modes:
+//   0 lists    every block keeps its best `keep` candidates in its LDS list
+//              (rounds of sixteen sub-tiles, one per wave, then bf_admit), as
+//              the plain form does;
+//   1 append   every candidate at or above a bound tau (read from the device:
+//              tau_sc[tau_k - 1] when tau_cnt >= tau_k, else 0) is appended to
+//              the flat array of the workspace's lists, no per-round barrier;
+//              past app_cap entries the workspace reports scr_status 6;
+//   2 maxima   the best candidate of each sub-tile (if in the slice and not
+//              excluded) is appended, while room lasts (a lower bound for
+//              mode 1: the band-th best of any set of the slice's candidates
+//              is at most the slice's band-th best).
+// Only u tiles u64_lo + t u64_step (t = 0, 1, ...) below u64_hi are scored.
+constexpr int kScWaves = 16, kScThreads = 64 * kScWaves, kScU = 4;
+
+__global__ void __launch_bounds__(kScThreads, 1) k_bf_score_stored(
+    sisso_space s, FormSlots fs, int n, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
+    const float2 *__restrict__ ures, const sisso_colstat *__restrict__ stats,
+    const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl, int64_t u64_lo,
+    int64_t u64_hi, int64_t u64_step, int64_t id_begin, int64_t id_end, const float *__restrict__ mom,
+    const float *__restrict__ cst, const int16_t *__restrict__ units, void *lws, int lists_total, int keep, int cap,
+    int mode, const float *__restrict__ tau_sc, const int32_t *__restrict__ tau_cnt, int tau_k,
+    unsigned long long *__restrict__ app_cnt, int64_t app_cap)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const bool append = mode != 0;
+    float *lsc = (float *)smem;
+    int64_t *lid = (int64_t *)(lsc + cap);
+    // the staged u tiles' row constants (as bf_forms takes them) and units
+    float4 *ucon_a = reinterpret_cast<float4 *>(lid + cap), *ucon_b = ucon_a + 64 * kScU;
+    uint4 *ucon_u = reinterpret_cast<uint4 *>(ucon_b + 64 * kScU);
+    __shared__ int lcnt, lpend[2];                // lpend: candidates of a round (two, alternating)
+    __shared__ float lthr;
+    WsView W = ws_view(lws, lists_total, keep);
+    if (threadIdx.x == 0) { lpend[0] = 0; lpend[1] = 0; }
+    BlockList Lst{lsc, lid, &lcnt, &lthr, cap, keep};
+    list_init(Lst);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, j = lane & 31;
+    const int Lv = s.levels;
+    const int64_t vcount = s.pool[Lv - 1], ulo = s.pool[Lv - 1], ucols = s.pool[Lv] - ulo;
+    const int64_t binbase = s.pool[Lv] + s.rect_unary;
+    const int S = s.n_slots;
+    const double nd = (double)n, R1 = info->sum_r32, Srr = info->s_rr;
+    const float fn = (float)n, rr = (float)(R1 / nd);
+    const int64_t nvt64 = (vcount + 63) / 64;
+    const int nsub = (int)(nvt64 * 4);
+    const int64_t n_u = u64_hi > u64_lo ? (u64_hi - u64_lo + u64_step - 1) / u64_step : 0;
+    const float tau = mode == 1 ? (*tau_cnt >= tau_k ? tau_sc[tau_k - 1] : 0.0f) : 0.0f;
+    int round = 0;
+    for (int64_t g0 = (int64_t)blockIdx.x * kScU; g0 < n_u; g0 += (int64_t)gridDim.x * kScU) {
+        const int nt = n_u - g0 < kScU ? (int)(n_u - g0) : kScU;      // u tiles of this step
+        __syncthreads();                              // the previous step's reads of the row constants are done
+        if (tid < 64 * kScU) {
+            const int t = tid >> 6;
+            const int64_t x = (u64_lo + (g0 + t) * u64_step) * 64 + (tid & 63);
+            const bool in = t < nt && x < ucols;
+            const sisso_colstat cs = stats[ulo + (in ? x : 0)];
+            const float2 b = ures[in ? x : 0];
+            const float4 ua = usum[in ? x : 0];
+            float flags = (in && cs.valid != 0.0f ? 1.0f : 0.0f) + (cs.minabs > 0.0f ? 2.0f : 0.0f);
+            if (!col_scalable(ua.z, ua.w, fn, cs.minabs > 0.0f)) flags += 4.0f;
+            ucon_a[tid] = ua;
+            ucon_b[tid] = make_float4(b.x, b.y, cs.rms, flags);
+            ucon_u[tid] = units ? unit_of(units, ulo + (in ? x : 0)) : make_uint4(0u, 0u, 0u, 0u);
+        }
+        __syncthreads();
+        const int nq = nt * nsub;
+        // sub-tile q of the step: u tile t = q / nsub, then 4 vt64 + su + 2 sv;
+        // rows: bit r of the result, row r may have a candidate at the bound tb
+        auto sub_tile = [&](int q, float tb, auto MX, auto &&emit) -> unsigned {
+            constexpr bool kMax = decltype(MX)::value;
+            const bool act = q >= 0;
+            const int qa = act ? q : 0;
+            const int t = qa / nsub, qq = qa - t * nsub;
+            const int64_t u64 = u64_lo + (g0 + t) * u64_step;
+            const int64_t vt64 = qq >> 2;
+            const int su = qq & 1, svh = (qq >> 1) & 1;
+            const int64_t v = vt64 * 64 + svh * 32 + j;
+            const bool vin = act && v < vcount;
+            const sisso_colstat vst = stats[vin ? v : 0];
+            const float4 vs0 = vsum[2 * (vin ? v : 0)], vs1 = vsum[2 * (vin ? v : 0) + 1];
+            const BfVCol vcol{vs0.x,
+                              vs0.y,
+                              vs0.z,
+                              vs1.x,
+                              vs1.y,
+                              vin && vst.valid != 0.0f,
+                              vst.minabs > 0.0f,
+                              col_scalable(vs0.z, vs0.w, fn, vst.minabs > 0.0f),
+                              units ? unit_of(units, vin ? v : 0) : make_uint4(0u, 0u, 0u, 0u)};
+            const size_t sub = ((size_t)u64 * nvt64 + vt64) * 4 + (qq & 3);
+            const float *const mp = mom + sub * (16 * kMom * 64) + lane;
+            const float *const cp = cst + sub * (16 * 3 * 64) + lane;
+            const int64_t ub0 = u64 * 64 + su * 32, vb0 = vt64 * 64 + svh * 32;
+            const int ucb = t * 64 + su * 32;
+            auto forms = [&](int r, const float (&m)[kMom], float c0, float c1, float c2, float (&cov)[5],
+                             float (&var)[5], bool (&live)[5], bool (&flag)[5]) {
+                const int i = ucb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                bf_forms(ucon_a[i], ucon_b[i], ucon_u[i], vcol, m, c0, c1, c2, rr, fs, cov, var, live, flag);
+            };
+            auto row_scores = [&](int r, float (&sc)[5]) {
+                float m[kMom];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    if (!((rows >> r) & 1u)) continue;
-                    float sc[5];
-                    row_scores(r, sc);
+                for (int k = 0; k < kMom; ++k) m[k] = __builtin_nontemporal_load(mp + (r * kMom + k) * 64);
+                const float c0 = __builtin_nontemporal_load(cp + (r * 3 + 0) * 64),
+                            c1 = __builtin_nontemporal_load(cp + (r * 3 + 1) * 64),
+                            c2 = __builtin_nontemporal_load(cp + (r * 3 + 2) * 64);
+                float cov[5], var[5];
+                bool live[5], flag[5];
+                forms(r, m, c0, c1, c2, cov, var, live, flag);
+                bf_scores(cov, var, live, Srr, sc);
+            };
+            auto fid_of = [&](int r, int k) -> int64_t {
+                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                return binbase + ((ub0 + i) * vcount + v) * S + fs.slot[k];
+            };
+            const int64_t tile_lo = binbase + (ub0 * vcount + vb0) * S;
+            const int64_t tile_hi = binbase + ((ub0 + 31) * vcount + vb0 + 31) * S + S;
+            const bool tile_in = tile_lo >= id_begin && tile_hi <= id_end;
+            auto in_range = [&](int64_t id) { return tile_in || (id >= id_begin && id < id_end); };
+            // the test of the plain form: cov^2 >= var Srr tb^2, loosened
+            const bool no_bound = !(tb > 0.0f);
+            const float k2 = (float)Srr * tb * tb * (1.0f - 1e-5f);
+            unsigned rows = 0;
+            float best = -1.0f;                       // maxima: this lane's best live score, row, form
+            int best_r = 0, best_k = 0;
+            if (act) {
+                // four rows at a time, the next four rows' loads in flight
+                constexpr int kG = 4 * (kMom + 3);
+                float cur[kG], nxt[kG];
+                auto load4 = [&](int g, float (&d)[kG]) {
 #pragma unroll
-                    for (int k = 0; k < 5; ++k)
-                        if (sc[k] >= 0.0f && sc[k] >= tb && admit_id(fid_of(r, k))) ++mine;
+                    for (int q2 = 0; q2 < 4 * kMom; ++q2) d[q2] = __builtin_nontemporal_load(mp + (g * 4 * kMom + q2) * 64);
+#pragma unroll
+                    for (int q2 = 0; q2 < 12; ++q2) d[4 * kMom + q2] = __builtin_nontemporal_load(cp + (g * 12 + q2) * 64);
+                };
+                load4(0, nxt);
+                static_for<4>([&](auto G) {
+                    constexpr int g = decltype(G)::value;
+#pragma unroll
+                    for (int e = 0; e < kG; ++e) cur[e] = nxt[e];
+                    if constexpr (g + 1 < 4) load4(g + 1, nxt);
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4) {
+                        const int r = 4 * g + r4;
+                        float m[kMom];
+#pragma unroll
+                        for (int k = 0; k < kMom; ++k) m[k] = cur[r4 * kMom + k];
+                        float cov[5], var[5];
+                        bool live[5], flag[5];
+                        forms(r, m, cur[4 * kMom + r4 * 3], cur[4 * kMom + r4 * 3 + 1], cur[4 * kMom + r4 * 3 + 2],
+                              cov, var, live, flag);
+                        if constexpr (kMax) {
+                            float sc[5];
+                            bf_scores(cov, var, live, Srr, sc);
+#pragma unroll
+                            for (int k = 0; k < 5; ++k) {
+                                const bool b = sc[k] > best;
+                                best = b ? sc[k] : best;
+                                best_r = b ? r : best_r;
+                                best_k = b ? k : best_k;
+                            }
+                        } else {
+                            bool hit = false;
+#pragma unroll
+                            for (int k = 0; k < 5; ++k)
+                                hit = hit | (live[k] & (no_bound | (cov[k] * cov[k] >= var[k] * k2)));
+                            rows |= (hit ? 1u : 0u) << r;
+                        }
+                    }
+                });
+            }
+            if constexpr (kMax) {
+                // the sub-tile's best: the lowest lane holding the wave's maximum
+                const float wm = wave_max(best);
+                const unsigned long long who = __ballot(best == wm && wm >= 0.0f);
+                if (who != 0ull && lane == __builtin_ctzll(who)) {
+                    const int64_t id = fid_of(best_r, best_k);
+                    if (in_range(id) && (n_excl == 0 || !in_sorted_ids(excl, n_excl, id))) {
+                        const unsigned long long slot = atomicAdd(app_cnt, 1ull);
+                        if (slot < (unsigned long long)app_cap) {
+                            W.sc[slot] = wm;
+                            W.id[slot] = id;
+                        }
+                    }
                 }
+            } else {
+                emit(rows, row_scores, fid_of, in_range);
             }
-            if (mine) atomicAdd(&lpend, mine);
-            __syncthreads();
-            const int total = lpend;                  // reset after the next barrier
-            if (total == 0) continue;
-            // Every thread takes the same branch only if every thread reads the
-            // list's count before any thread reserves slots: read it, merge if
-            // the tile's candidates do not fit (block-uniform, ends with a
-            // barrier), read it again, and meet at a barrier before reserving.
-            int cnt0 = *Lst.cnt;
-            if (cnt0 + total > Lst.cap) {
-                list_merge(Lst, gb);
-                cnt0 = *Lst.cnt;
-            }
-            __syncthreads();
-            if (cnt0 + total <= Lst.cap) {
-                if (mine) {
-                    int slot = atomicAdd(Lst.cnt, mine);
-#pragma unroll
+            return rows;
+        };
+        if (append) {
+            // every candidate at or above tau, in range and not excluded, to
+            // the flat array; waves take the step's sub-tiles independently
+            for (int q = w; q < nq; q += kScWaves) {
+                if (mode == 2) {
+                    sub_tile(q, 0.0f, std::true_type{}, [](unsigned, auto &, auto &, auto &) {});
+                    continue;
+                }
+                sub_tile(q, tau, std::false_type{}, [&](unsigned rows, auto &row_scores, auto &fid_of, auto &in_range) {
+#pragma unroll 1
                     for (int r = 0; r < 16; ++r) {
                         if (!((rows >> r) & 1u)) continue;
                         float sc[5];
                         row_scores(r, sc);
 #pragma unroll
                         for (int k = 0; k < 5; ++k) {
-                            if (!(sc[k] >= 0.0f && sc[k] >= tb)) continue;
+                            if (!(sc[k] >= 0.0f && sc[k] >= tau)) continue;
                             const int64_t id = fid_of(r, k);
-                            if (admit_id(id)) {
-                                Lst.sc[slot] = sc[k];
-                                Lst.id[slot] = id;
-                                ++slot;
+                            if (!in_range(id) || (n_excl != 0 && in_sorted_ids(excl, n_excl, id))) continue;
+                            const unsigned long long slot = atomicAdd(app_cnt, 1ull);
+                            if (slot < (unsigned long long)app_cap) {
+                                W.sc[slot] = sc[k];
+                                W.id[slot] = id;
+                            } else {
+                                W.h->scr_status = 6;
                             }
                         }
                     }
-                }
-                continue;
+                });
             }
-            // the list is filling: row by row, merging as needed (rows unrolled at
-            // compile time: the registers of row r are addressed statically)
-            static_for<16>([&](auto R) {
-                constexpr int r = decltype(R)::value;
-                float sc[5];
-                int64_t fid[5];
-                row_scores(r, sc);
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    fid[k] = fid_of(r, k);
-                    if (!(tile_in || (fid[k] >= id_begin && fid[k] < id_end))) sc[k] = -1.0f;
-                }
+        } else {
+            // rounds of sixteen sub-tiles, one per wave, each ending in bf_admit
+            for (int q0 = 0; q0 < nq; q0 += kScWaves, ++round) {
+                const int q = q0 + w < nq ? q0 + w : -1;
+                const float tb = fmaxf(*Lst.thr, load_gthr(&W.h->gthr));
+                sub_tile(q, tb, std::false_type{}, [&](unsigned rows, auto &row_scores, auto &fid_of, auto &in_range) {
+                    bf_admit(Lst, &W.h->gthr, &lpend[round & 1], rows, tb, excl, n_excl, row_scores, fid_of,
+                             in_range);
+                });
+                // every thread read this round's count before the barrier below;
+                // the next round's counter was last read before the previous round's
+                if (tid == 0) lpend[(round + 1) & 1] = 0;
                 __syncthreads();
-                const int c = *Lst.cnt;
-                __syncthreads();
-                if (c + 5 * (int)blockDim.x <= Lst.cap) {
-                    const float t = fmaxf(*Lst.thr, load_gthr(gb));
-#pragma unroll
-                    for (int k = 0; k < 5; ++k)
-                        if (sc[k] >= 0.0f && sc[k] >= t && (n_excl == 0 || !in_sorted_ids(excl, n_excl, fid[k]))) {
-                            const int slot = atomicAdd(Lst.cnt, 1);
-                            Lst.sc[slot] = sc[k];
-                            Lst.id[slot] = fid[k];
-                        }
-                } else {
-                    list_offer<5>(Lst, sc, fid, gb, excl, n_excl);
-                }
-            });
+            }
         }
     }
-    list_flush(Lst, gb, W.sc + (size_t)blockIdx.x * keep, W.id + (size_t)blockIdx.x * keep);
+    if (!append) list_flush(Lst, &W.h->gthr, W.sc + (size_t)blockIdx.x * keep, W.id + (size_t)blockIdx.x * keep);
 }
+
+// Fill of a workspace's first n_entries list entries with empty slots (score
+// -1, id INT64_MAX) before an append-mode scorer writes into them.
+__global__ void k_bf_lists_clear(void *lws, int lists_total, int keep, int64_t n_entries)
+{
+    WsView W = ws_view(lws, lists_total, keep);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_entries; e += (int64_t)gridDim.x * blockDim.x) {
+        W.sc[e] = -1.0f;
+        W.id[e] = INT64_MAX;
+    }
+}
+#endif  // SISSO_BF16_MFMA_PART
 
 #ifdef SISSO_BF16_MFMA_PART
 // ----------------------------------------------------------- moments pass
@@ -1378,7 +1739,7 @@ __global__ void k_bf_reset(WsHeader *h, int keep, int n_lists, int lists_cap)
 {
     if (threadIdx.x == 0) {
         h->gthr = 0u; h->keep = keep; h->n_lists = n_lists; h->lists_cap = lists_cap; h->status = 0;
-        h->scr_status = 0;
+        h->scr_status = 0; h->app = 0ull;
     }
 }
 #else
@@ -1429,9 +1790,10 @@ int bf_lists_total(const sisso_space *s, int keep_b)
 // a block list holds keep entries plus one offer per thread between merges
 int bf_list_cap(int keep, int threads) { return next_pow2(keep + threads); }
 
-// Per-block list length of a band: the block keeps its best min(band, K'max)
-// (the LDS list); the grid-wide merge then takes the best `band` of all lists.
-int bf_block_keep(int band) { return band < SISSO_MAX_KEEP ? band : SISSO_MAX_KEEP; }
+// Per-block list length of a band: every block keeps its best `band` (the
+// LDS list) and publishes its bound, so the grid-wide merge takes the exact
+// `band` best approximate scores of the slice, whatever the grid and tiles.
+int bf_block_keep(int band) { return band; }
 
 bool space_ok(const sisso_space *s)
 {
@@ -1538,22 +1900,11 @@ sisso_status bf_launch(const sisso_space *space, const sisso_score_args *args, c
     using Sh = BfShape<MODE>;
     const int n = args->n;
     const FormSlots fs = form_slots(space);
-    // The read form sizes its own grid: as many blocks as can be resident
-    // (kMinBlocks per CU), each sweeping its share of the u tiles.  A grid
-    // tuned for the other forms (one block per CU) would leave half its slots
-    // empty.
-    int max_grid = args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid;
-    if (Sh::kRead) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            return SISSO_E_DEVICE;
-        max_grid = Sh::kMinBlocks * cus < kMaxBfGrid ? Sh::kMinBlocks * cus : kMaxBfGrid;   // the workspace's lists
-    }
+    static_assert(!Sh::kRead, "the read form launches through bf_launch_read");
+    const int max_grid = args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid;
     const BfPlan p = bf_plan(space, cand_begin, cand_end, max_grid, Sh::kBTU);
-    // Every block keeps min(band, K'max).  Only a block that keeps the whole
-    // band may publish its threshold as the grid-wide bound (it is then a
-    // lower bound of the band-th best score).
+    // Every block keeps the whole band and may publish its threshold as the
+    // grid-wide bound (a lower bound of the band-th best score).
     const int keep_b = bf_block_keep(band);
     const int cap_b = bf_list_cap(keep_b, Sh::kThreads);
     const int publish = keep_b >= band ? 1 : 0;
@@ -1576,11 +1927,88 @@ template <int MODE>
 int bf_screen_lists(const sisso_space *space, const sisso_score_args *args, int64_t cand_begin, int64_t cand_end,
                     int cus)
 {
-    int max_grid = args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid;
-    if (BfShape<MODE>::kRead) max_grid = BfShape<MODE>::kMinBlocks * cus < kMaxBfGrid ? BfShape<MODE>::kMinBlocks * cus
-                                                                                       : kMaxBfGrid;
+    if (BfShape<MODE>::kRead)   // the scorer of stored contractions: one block per CU, 64-column u tiles
+        return bf_plan(space, cand_begin, cand_end, cus < kMaxBfGrid ? cus : kMaxBfGrid, 64).grid;
+    const int max_grid = args->grid > 0 && args->grid < kMaxBfGrid ? args->grid : kMaxBfGrid;
     return bf_plan(space, cand_begin, cand_end, max_grid, BfShape<MODE>::kBTU).grid;
 }
+
+#ifndef SISSO_BF16_MFMA_PART
+// A pass that reads the moments: the residual contractions of the u tiles
+// covering [cand_begin, cand_end) (kBfRead, 128 x 128 block tiles, one block
+// per CU sweeping its share), then their scores from the stored moments and
+// contractions into the band lists (one block per CU).
+sisso_status bf_launch_read(const sisso_space *space, const sisso_score_args *args, const BfOps &o, BfWs &w,
+                            int32_t band, int64_t cand_begin, int64_t cand_end, const float *mom, float *cst,
+                            const h16 *uimg, BfSide side, hipStream_t st)
+{
+    using Sh = BfShape<kBfRead>;
+    const int n = args->n;
+    const FormSlots fs = form_slots(space);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return SISSO_E_DEVICE;
+    const int grid_max = cus < kMaxBfGrid ? cus : kMaxBfGrid;
+    const BfPlan p = bf_plan(space, cand_begin, cand_end, grid_max, Sh::kBTU);
+    if (p.grid > 0) {
+        const size_t smem = (size_t)Sh::kNStage * Sh::kStage * sizeof(h16) + 4 * Sh::kBTU * sizeof(float4);
+        if (!allow_dynamic_lds(k_score_rect_bf16<kBfRead>, smem)) return SISSO_E_UNSUPPORTED;
+        hipLaunchKernelGGL(k_score_rect_bf16<kBfRead>, dim3(p.grid), dim3(Sh::kThreads), smem, st, *space, fs, n,
+                           args->pool32, args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info,
+                           args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, cst, w.vimg,
+                           uimg, args->units, side, w.lists, 0, 1, 0, 0);
+    }
+    // The scores.  Over a large slice: first the exact band of a sample (every
+    // sixteenth u tile, in lists), whose band-th best score tau is a lower
+    // bound of the slice's band-th best (the sample is part of the slice);
+    // then every candidate at or above tau appended, without lists.  The band
+    // of the appended candidates is the slice's band, whatever the sample.
+    // Over a small slice: lists (every block keeps the whole band).
+    const BfPlan q = bf_plan(space, cand_begin, cand_end, grid_max, 64);
+    if (q.grid == 0) {
+        hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, bf_block_keep(band), 0,
+                           bf_lists_total(space, bf_block_keep(band)));
+        return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+    }
+    const int keep_b = bf_block_keep(band);
+    const int cap_b = bf_list_cap(keep_b, kScThreads);
+    const int lcap = bf_lists_total(space, keep_b);
+    WsHeader *const wh = (WsHeader *)w.lists;
+    const size_t smem = (size_t)cap_b * (sizeof(float) + sizeof(int64_t)) + 64 * kScU * (2 * sizeof(float4) + sizeof(uint4));
+    if (!allow_dynamic_lds(k_bf_score_stored, smem)) return SISSO_E_UNSUPPORTED;
+    const int64_t n_u = q.ut_hi - q.ut_lo, step = 4;
+    const int64_t nsub = 4 * ((space->pool[space->levels - 1] + 63) / 64);   // sub-tiles per u tile
+    const bool sampled = (n_u / step) * nsub >= (int64_t)4 * band;
+    auto score = [&](int grid, int64_t u_step, int mode) {
+        hipLaunchKernelGGL(k_bf_score_stored, dim3(grid), dim3(kScThreads), smem, st, *space, fs, n, o.usum, w.vsum,
+                           w.ures, args->stats, args->info, args->exclude, args->n_exclude, q.ut_lo, q.ut_hi, u_step,
+                           cand_begin, cand_end, mom, cst, args->units, w.lists, lcap, keep_b, cap_b, mode,
+                           w.band_sc, w.band_cnt, band, &wh->app, (int64_t)q.grid * keep_b);
+    };
+    if (sampled) {
+        // tau: the band-th best of the sub-tile maxima of every fourth u tile
+        const int64_t n_s = (n_u + step - 1) / step;
+        const int g_s = (int)((n_s + kScU - 1) / kScU < grid_max ? (n_s + kScU - 1) / kScU : grid_max);
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, wh, keep_b, q.grid, lcap);
+            hipLaunchKernelGGL(k_bf_lists_clear, dim3(1024), dim3(256), 0, st, w.lists, lcap, keep_b,
+                               (int64_t)q.grid * keep_b);
+            if (pass == 0) {
+                score(g_s, step, 2);
+                const sisso_status rs = topk_launch(w.lists, band, w.band_ids, w.band_sc, w.band_cnt, st, false);
+                if (rs != SISSO_OK) return rs;
+            } else {
+                score(q.grid, 1, 1);
+            }
+        }
+    } else {
+        hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, wh, keep_b, q.grid, lcap);
+        score(q.grid, 1, 0);
+    }
+    return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+}
+#endif  // SISSO_BF16_MFMA_PART
 
 }  // namespace sisso
 
@@ -1630,10 +2058,18 @@ size_t bf_moments_bytes(const sisso_space *space)
     return align256b((size_t)bf_tiles(ucols) * (size_t)bf_tiles(vcols) * kMomTile * sizeof(float));
 }
 size_t bf_uimg_offset(const sisso_space *space) { return bf_moments_bytes(space) + align256b(bf_side_bytes(*space)); }
-size_t bf_moments_total(const sisso_space *space, int n)
+// the pass's residual contractions (three per pair, the moments' tiling)
+size_t bf_cst_offset(const sisso_space *space, int n)
 {
     const int L = space->levels;
     return bf_uimg_offset(space) + align256b(bf_uimg_elems(space->pool[L] - space->pool[L - 1], n) * sizeof(h16));
+}
+size_t bf_moments_total(const sisso_space *space, int n)
+{
+    const int L = space->levels;
+    const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
+    return bf_cst_offset(space, n) + align256b((size_t)bf_tiles(ucols) * (size_t)bf_tiles(vcols) * (kMomTile / kMom) *
+                                               3 * sizeof(float));
 }
 
 sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, const void *ops, size_t ops_bytes,
@@ -1660,6 +2096,7 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     BfWs w = bf_ws_view(bws, ucols, vcols, n, band, bf_lists_total(space, keep_b), keep_b);
     float *mom = (float *)moments;
     h16 *const uimg = mode == SISSO_MOMENTS_NONE ? nullptr : (h16 *)((char *)moments + bf_uimg_offset(space));
+    float *const cst = mode == SISSO_MOMENTS_NONE ? nullptr : (float *)((char *)moments + bf_cst_offset(space, n));
     // the flagged candidates: beside the moments (every pass of a fit scores
     // those its first pass stored), else in the workspace
     const BfSide side = bf_side_view(mode == SISSO_MOMENTS_NONE ? w.side : (char *)moments + bf_moments_bytes(space),
@@ -1676,11 +2113,11 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
         // the moments pass stores the moments, the flagged candidates and the
         // u side's image; the read form then scores the pass from them
         rc = bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, side, st);
-        if (rc == SISSO_OK) rc = bf_launch<kBfRead>(space, args, o, w, band, cand_begin, cand_end, mom, uimg, side, st);
+        if (rc == SISSO_OK) rc = bf_launch_read(space, args, o, w, band, cand_begin, cand_end, mom, cst, uimg, side, st);
         l0 = bf_screen_lists<kBfRead>(space, args, cand_begin, cand_end, cus);
         break;
     case SISSO_MOMENTS_READ:
-        rc = bf_launch<kBfRead>(space, args, o, w, band, cand_begin, cand_end, mom, uimg, side, st);
+        rc = bf_launch_read(space, args, o, w, band, cand_begin, cand_end, mom, cst, uimg, side, st);
         l0 = bf_screen_lists<kBfRead>(space, args, cand_begin, cand_end, cus);
         break;
     default:

@@ -138,7 +138,10 @@ __device__ __forceinline__ uint4 unit_of(const int16_t *units, int64_t c)
 {
     return reinterpret_cast<const uint4 *>(units)[c];
 }
-__device__ __forceinline__ bool unit_eq(uint4 a, uint4 b) { return a.x == b.x && a.y == b.y && a.z == b.z && a.w == b.w; }
+__device__ __forceinline__ bool unit_eq(uint4 a, uint4 b)   // branch-free
+{
+    return ((a.x ^ b.x) | (a.y ^ b.y) | (a.z ^ b.z) | (a.w ^ b.w)) == 0u;
+}
 __device__ __forceinline__ bool unit_dimless(uint4 a) { return (a.x | a.y | a.z | a.w) == 0u; }
 // exp, exp(-x), ln and sin take a dimensionless argument
 __device__ __forceinline__ bool unary_needs_dimless(int op)

@@ -45,7 +45,8 @@ struct WsHeader {
     int lists_cap;          // list slots the workspace was laid out for
     int scr_status;         // 0 ok; 3 = a 16-bit screen could not keep every flagged candidate
     int thr_count;          // threshold selection: entries at or above the threshold
-    int pad[4];
+    unsigned long long app; // entries appended by a 16-bit scorer in append mode
+    int pad[2];
     unsigned hist[kHistBins];
 };
 

@@ -144,7 +144,8 @@ def test_bf16_moments_size_and_argument_errors_before_launch():
     the slice's binary block, then the list of the candidates the screen
     scores exactly (a counter and one id per 1024 candidates of the block, at
     least 2^16 and at most 2^26), then the u side's FP16 image (two planes of
-    64 columns x 16 samples per 64-column tile and chunk of 16 samples); a bad
+    64 columns x 16 samples per 64-column tile and chunk of 16 samples), then
+    3 floats per pair of the same tiles (a pass's residual contractions); a bad
     mode, a missing or short buffer and the usual range checks are reported
     before any launch."""
     lib = L.lib()
@@ -155,7 +156,8 @@ def test_bf16_moments_size_and_argument_errors_before_launch():
     a256 = lambda x: (x + 255) // 256 * 256
     mom = a256(tiles * 4 * 16 * 6 * 64 * 4)
     uimg = a256(((nu + 63) // 64) * ((100 + 15) // 16) * 2 * 64 * 16 * 2)
-    assert lib.sisso_bf16_moments_size(ctypes.byref(s), 100) == mom + a256(256 + 8 * side) + uimg
+    cst = a256(tiles * 4 * 16 * 3 * 64 * 4)
+    assert lib.sisso_bf16_moments_size(ctypes.byref(s), 100) == mom + a256(256 + 8 * side) + uimg + cst
     assert lib.sisso_bf16_moments_size(ctypes.byref(s), 1) == 0
     plain = L.make_space(5, I.OPS1["unary"], I.OPS1["binary"], 2, False)
     assert lib.sisso_bf16_moments_size(ctypes.byref(plain), 100) == 0      # no slice
