@@ -97,8 +97,8 @@ template <int MODE> struct BfShape {
     // with its planes: the stride of a u plane within a tile.
     static constexpr int kAPlane = kRead ? 64 * kKR : kPlaneU;
     static constexpr int kMinBlocks = 1;            // resident blocks per CU the registers are sized for
-    static constexpr int kNStage = 2;               // staging buffers (double buffer)
-    static constexpr int kRing = 8;                 // the read form: chunks held in registers (loads in flight)
+    static constexpr int kNStage = kRead ? 3 : 2;   // staging buffers
+    static constexpr int kRing = 6;                 // the read form: chunks held in registers (loads in flight)
     // accumulator of the residual contraction of u v, u/v and v/u
     static constexpr int kCovUV = kRead ? 0 : 1, kCovUW = kRead ? 1 : 5, kCovZV = kRead ? 2 : 9;
 };
@@ -698,7 +698,20 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
 #pragma unroll
     for (int s2 = 0; s2 < kSubV; ++s2) fb[s2] = lds_off((wv * kSubV + s2) * 32 + (lane & 31), koff);
 
-    for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
+    // Tile order.  The plain form: a block owns u tiles (strided over the
+    // grid) and sweeps every v tile.  The read form: (u, v) tiles, v fastest,
+    // in turns of eight consecutive runs of gridDim.x / 8 tiles, one run per
+    // XCD (consecutive blocks are dispatched to the XCDs in turn): the blocks
+    // of an XCD then work on few u tiles at a time and share their images in
+    // that XCD's L2, where a block per u tile would stream its own from HBM.
+    const int64_t T = Sh::kRead ? (ut_hi - ut_lo) * nvt : ut_hi - ut_lo;
+    const bool by_xcd = Sh::kRead && gridDim.x % 8 == 0;
+    const int64_t gx = blockIdx.x % 8, gk = blockIdx.x / 8, gn = gridDim.x / 8;
+    for (int64_t it = 0;; ++it) {
+        const int64_t t = by_xcd ? (it * 8 + gx) * gn + gk : it * gridDim.x + blockIdx.x;
+        if (t >= T) break;
+        const int64_t ut = Sh::kRead ? ut_lo + t / nvt : ut_lo + t;
+        const int64_t vt_first = Sh::kRead ? t % nvt : 0, vt_end = Sh::kRead ? vt_first + 1 : nvt;
         const int64_t u0 = ut * kBTU;  // index into the newest level
         const int64_t su = u0 + ucs;
         const bool su_ok = su < ucols;
@@ -722,7 +735,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             if (!col_scalable(ua.z, ua.w, fn, cs.minabs > 0.0f)) ucon_b[tid].w += 4.0f;
             ucon_u[tid] = units ? unit_of(units, ulo + (in ? x : 0)) : make_uint4(0u, 0u, 0u, 0u);
         }
-        for (int64_t vt = 0; vt < nvt; ++vt) {
+        for (int64_t vt = vt_first; vt < vt_end; ++vt) {
             const int64_t v0 = vt * kBTV;
             const int64_t sv = v0 + vcs;
             const bool sv_ok = sv < vcount;
@@ -862,7 +875,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 // ring of kRing chunks in registers (the loads of kRing - 1
                 // chunks stay in flight while a chunk is computed: the reads
                 // come from L2 and the MALL, and their latency is hidden only by
-                // many bytes in flight), then into the two staging buffers.
+                // many bytes in flight), then into the staging buffers.
                 constexpr int kR = Sh::kRing;
                 static_assert(!Sh::kRead || (kPA * kPlaneU == 8 * 512 && kPB * kPlaneV == 8 * 512 &&
                                              Sh::kThreads == 512 && kPA * kAPlane == 4 * 512),
@@ -871,39 +884,74 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                 const h16 *const ub = uimg + (size_t)utile * nch * (kPA * kAPlane) + (w & 3) * 512 + lane * 8;
                 const h16 *const vb = vimg + (size_t)vt * nch * (kPB * kPlaneV) + w * 512 + lane * 8;
                 u32x4 ru[kR], rv[kR];
+                // (a chunk past the last loads the last one again; it is staged
+                // as zeros, so its MFMAs add nothing)
                 auto fetch = [&](int c, u32x4 &a, u32x4 &b) {
                     const size_t cc = (size_t)(c < nch ? c : nch - 1);
                     a = *reinterpret_cast<const u32x4 *>(ub + cc * (kPA * kAPlane));
                     b = *reinterpret_cast<const u32x4 *>(vb + cc * (kPB * kPlaneV));
                 };
-                // chunk ch: registers to staging buffer ch % 2, the load of
-                // chunk ch + kR into the freed registers, a barrier (the stores of
-                // every wave are visible, and every wave is past the fragment
-                // reads of chunk ch - 2, the buffer's previous user), the MFMAs
-                auto step = [&](int ch, u32x4 &a, u32x4 &b, bool refill) {
-                    h16 *const buf = stage + (ch & 1) * kStage;
-                    *reinterpret_cast<u32x4 *>(buf + w * 512 + lane * 8) = a;
-                    *reinterpret_cast<u32x4 *>(buf + kPA * kPlaneU + w * 512 + lane * 8) = b;
-                    if (refill) fetch(ch + kR, a, b);
-                    lds_barrier();
-                    mfma_chunk(buf);
+                // Three staging buffers and two fragment sets: in the turn of
+                // chunk ch, the fragments of chunk ch + 1 are read, the MFMAs of
+                // chunk ch run on the fragments read in the previous turn, and
+                // chunk ch + 2 goes from its ring slot to its buffer (that of
+                // chunk ch - 1, whose fragments every wave has read: each turn
+                // ends in a barrier after this wave's LDS operations are done);
+                // the slot is refilled with chunk ch + 2 + kR.  The LDS traffic
+                // of a turn overlaps its MFMAs.
+                struct Frags {
+                    h16x8 a[kPA], b[kSubV][kPB];
                 };
+                auto read_frags = [&](const h16 *buf, Frags &f) {
+#pragma unroll
+                    for (int q = 0; q < kPA; ++q) f.a[q] = *reinterpret_cast<const h16x8 *>(buf + q * kAPlane + fa);
+#pragma unroll
+                    for (int s2 = 0; s2 < kSubV; ++s2)
+#pragma unroll
+                        for (int q = 0; q < kPB; ++q)
+                            f.b[s2][q] = *reinterpret_cast<const h16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb[s2]);
+                };
+                auto mfma_frags = [&](const Frags &f) {
+#pragma unroll
+                    for (int s2 = 0; s2 < kSubV; ++s2)
+#pragma unroll
+                        for (int g = 0; g < kNG; ++g)
+                            acc[s2][g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.a[GA(g)], f.b[s2][GB(g)], acc[s2][g],
+                                                                               0, 0, 0);
+                };
+                auto put = [&](h16 *buf, const u32x4 &x, const u32x4 &y, bool past) {
+                    const u32x4 zero = {0u, 0u, 0u, 0u};
+                    *reinterpret_cast<u32x4 *>(buf + w * 512 + lane * 8) = past ? zero : x;
+                    *reinterpret_cast<u32x4 *>(buf + kPA * kPlaneU + w * 512 + lane * 8) = past ? zero : y;
+                };
+                static_assert(!Sh::kRead || (kR % 6 == 0 && Sh::kNStage == 3), "ring slot, fragment set and buffer "
+                                                                               "of a chunk fixed within a group");
                 // the first kR chunks, in order (the compiler's waits in the
                 // loop assume the oldest load is the one needed first)
                 static_for<kR>([&](auto S) {
                     fetch(decltype(S)::value, ru[S], rv[S]);
                     __builtin_amdgcn_sched_barrier(0);
                 });
-                // whole groups of kR chunks without a branch, so that the load
-                // counts are the same in every group (the compiler's waits then
-                // leave kR - 1 chunks in flight); loads past the last chunk
-                // re-read it
-                int c0 = 0;
-                for (; c0 + kR <= nch; c0 += kR)
-                    static_for<kR>([&](auto S) { step(c0 + decltype(S)::value, ru[S], rv[S], true); });
-                static_for<kR>([&](auto S) {
-                    if (c0 + decltype(S)::value < nch) step(c0 + decltype(S)::value, ru[S], rv[S], false);
-                });
+                Frags F[2];
+                put(stage, ru[0], rv[0], false);
+                fetch(kR, ru[0], rv[0]);
+                put(stage + kStage, ru[1], rv[1], nch < 2);
+                fetch(kR + 1, ru[1], rv[1]);
+                lds_barrier();
+                read_frags(stage, F[0]);
+                // whole groups of kR chunks without a branch (the compiler's
+                // waits then leave the ring's chunks in flight): turns past the
+                // last chunk compute on zeros
+                for (int c0 = 0; c0 < nch; c0 += kR)
+                    static_for<kR>([&](auto S) {
+                        constexpr int sc = decltype(S)::value;
+                        constexpr int sl = (sc + 2) % kR;
+                        read_frags(stage + ((sc + 1) % 3) * kStage, F[(sc + 1) & 1]);
+                        mfma_frags(F[sc & 1]);
+                        put(stage + ((sc + 2) % 3) * kStage, ru[sl], rv[sl], c0 + sc + 2 >= nch);
+                        fetch(c0 + sc + 2 + kR, ru[sl], rv[sl]);
+                        lds_barrier();
+                    });
             } else {
                 // pr holds chunk ch + 1 while chunk ch + 2 loads (loads past the last
                 // chunk re-read it); deeper load rings were slower
@@ -1952,9 +2000,13 @@ sisso_status bf_launch_read(const sisso_space *space, const sisso_score_args *ar
     const int grid_max = cus < kMaxBfGrid ? cus : kMaxBfGrid;
     const BfPlan p = bf_plan(space, cand_begin, cand_end, grid_max, Sh::kBTU);
     if (p.grid > 0) {
+        // one block per CU over the (u, v) tiles, a multiple of the eight XCDs
+        const int64_t tiles = (p.ut_hi - p.ut_lo) * ((space->pool[space->levels - 1] + Sh::kBTV - 1) / Sh::kBTV);
+        int g = (int)(tiles < grid_max ? tiles : grid_max);
+        if (g >= 8) g -= g % 8;
         const size_t smem = (size_t)Sh::kNStage * Sh::kStage * sizeof(h16) + 4 * Sh::kBTU * sizeof(float4);
         if (!allow_dynamic_lds(k_score_rect_bf16<kBfRead>, smem)) return SISSO_E_UNSUPPORTED;
-        hipLaunchKernelGGL(k_score_rect_bf16<kBfRead>, dim3(p.grid), dim3(Sh::kThreads), smem, st, *space, fs, n,
+        hipLaunchKernelGGL(k_score_rect_bf16<kBfRead>, dim3(g), dim3(Sh::kThreads), smem, st, *space, fs, n,
                            args->pool32, args->ld32, args->r32, o.usum, w.vsum, w.ures, args->stats, args->info,
                            args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, cst, w.vimg,
                            uimg, args->units, side, w.lists, 0, 1, 0, 0);
