@@ -367,10 +367,11 @@ sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score
  *   moments        device buffer of sisso_bf16_moments_size(space, n) bytes,
  *                  owned by the caller: 24 bytes per pair of the padded
  *                  64 x 64 tiles (about 69 GB for 2.65M x 1030 operand
- *                  pairs), the flagged candidates, 4 bytes per sample of each
- *                  newest-level operand (about 21 GB at n = 2000), and 12
- *                  bytes per pair of scratch for a pass's residual GEMMs
- *                  (about 35 GB).
+ *                  pairs), the flagged candidates, 8 bytes per sample of each
+ *                  newest-level operand (its FP16 operands, about 42 GB at
+ *                  n = 2000), 12 bytes per pair of scratch for a pass's
+ *                  residual GEMMs (about 35 GB), and 12 bytes per sample of
+ *                  each previous-level operand.
  *   mode           SISSO_MOMENTS_NONE (moments unused, may be NULL: the same
  *                  as sisso_bf16_screen), SISSO_MOMENTS_WRITE or
  *                  SISSO_MOMENTS_READ.

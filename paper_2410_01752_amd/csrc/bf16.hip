@@ -173,11 +173,20 @@ __host__ __device__ inline size_t bf_vimg_elems(int64_t vcols, int n)
 {
     return (size_t)((vcols + 127) / 128) * (size_t)((n + kKC - 1) / kKC) * 2 * (128 * kKR);
 }
-// the u side's image (written by the moments pass, read by the read form):
-// per 64-column u tile and chunk of samples, the staged planes U~ and Z~
+// the u side's image (written before the moments pass, read by it and by the
+// read form): per 64-column u tile and chunk of samples, the staged planes
+// U~, Z~, U~^2 and Z~^2 (64 rows of 16 samples each, FP16, in their LDS layout)
+constexpr int kUImgPlanes = 4;
 __host__ __device__ inline size_t bf_uimg_elems(int64_t ucols, int n)
 {
-    return (size_t)((ucols + 63) / 64) * (size_t)((n + kKC - 1) / kKC) * 2 * (64 * kKR);
+    return (size_t)((ucols + 63) / 64) * (size_t)((n + kKC - 1) / kKC) * kUImgPlanes * (64 * kKR);
+}
+// the v side's residual-independent image for the moments pass: per 128-column
+// v tile and chunk, the staged planes V~, P, Q, W~, Pw, Qw (128 rows each)
+constexpr int kVmPlanes = 6;
+__host__ __device__ inline size_t bf_vmimg_elems(int64_t vcols, int n)
+{
+    return (size_t)((vcols + 127) / 128) * (size_t)((n + kKC - 1) / kKC) * kVmPlanes * (128 * kKR);
 }
 __host__ __device__ inline size_t bf_ws_bytes(const sisso_space &s, int64_t ucols, int64_t vcols, int n, int band,
                                               int lists, int keep)
@@ -866,8 +875,9 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
             if (tid < kSubV) lpend[tid] = 0;          // every thread has read the previous totals
             if constexpr (Sh::kRead) {
                 // Both sides are copies of FP16 images already in the staged
-                // layout (u: written by the moments pass; v: per residual).
-                // Chunk c's 8 KB of u (two 64-column image tiles of 4 KB) and
+                // layout (u: written for the moments pass, of which the read
+                // form takes the first two planes, U~ and Z~; v: per residual).
+                // Chunk c's 8 KB of u (4 KB of two 64-column image tiles) and
                 // its 8 KB of v are 1 KB pieces, one of each per wave: wave w's
                 // u piece is piece w % 4 of tile w / 4, at stage offset 512 w
                 // either way.  A tile past the last one re-reads the last (its
@@ -881,14 +891,14 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
                                              Sh::kThreads == 512 && kPA * kAPlane == 4 * 512),
                               "one 1 KB u piece and one v piece per wave");
                 const int64_t utile = u0 / 64 + (w >> 2) < nut64 ? u0 / 64 + (w >> 2) : nut64 - 1;
-                const h16 *const ub = uimg + (size_t)utile * nch * (kPA * kAPlane) + (w & 3) * 512 + lane * 8;
+                const h16 *const ub = uimg + (size_t)utile * nch * (kUImgPlanes * kAPlane) + (w & 3) * 512 + lane * 8;
                 const h16 *const vb = vimg + (size_t)vt * nch * (kPB * kPlaneV) + w * 512 + lane * 8;
                 u32x4 ru[kR], rv[kR];
                 // (a chunk past the last loads the last one again; it is staged
                 // as zeros, so its MFMAs add nothing)
                 auto fetch = [&](int c, u32x4 &a, u32x4 &b) {
                     const size_t cc = (size_t)(c < nch ? c : nch - 1);
-                    a = *reinterpret_cast<const u32x4 *>(ub + cc * (kPA * kAPlane));
+                    a = *reinterpret_cast<const u32x4 *>(ub + cc * (kUImgPlanes * kAPlane));
                     b = *reinterpret_cast<const u32x4 *>(vb + cc * (kPB * kPlaneV));
                 };
                 // Three staging buffers and two fragment sets: in the turn of
@@ -1394,43 +1404,123 @@ __global__ void k_bf_lists_clear(void *lws, int lists_total, int keep, int64_t n
 // ----------------------------------------------------------- moments pass
 //
 // The first pass of a fit: per (u, v) pair of the binary block, the six
-// residual-independent moments the read form loads (sum h and the variance of
-// u v, u/v and v/u), from the nine residual-independent contractions of the
-// full form; the conditioning flags of the five forms (the flagged candidates
-// join the list of exact scoring); and the u side's FP16 image (U~ and Z~ in
-// the read form's staged layout).  The read form then scores the pass.  No
-// residual is involved, so nine accumulators per wave fit two waves per SIMD:
-// block tile 128 u x 64 v, eight waves (four along u, two along v), one
-// 32 x 32 sub-tile each.  Every staged value and every accumulator takes the
-// full form's operations, so the moments, flags and images are the bits the
-// full form computes.
+// residual-independent moments the read form's scorer loads (sum h and the
+// variance of u v, u/v and v/u), from the nine residual-independent
+// contractions of the full form, and the conditioning flags of the five forms
+// (the flagged candidates join the list of exact scoring).  Both sides'
+// operands are first written once as FP16 images in the staged layout (the u
+// side's four planes, which the read form reuses, and the v side's six), so
+// that the pass itself only copies chunks into LDS and runs MFMAs: block tile
+// 64 u x 128 v (one u image tile, one v image tile), eight waves (two along u,
+// four along v), one 32 x 32 sub-tile each.  Every staged value takes the
+// full form's operations and every accumulator its order, so the moments and
+// flags are the bits the full form computes.
 //   g:  0   1    2   3   4    5    6   7    8
 //   A:  U~  U~2  U~  U~  U~2  U~   Z~  Z~2  Z~
 //   B:  V~  P    Q   W~  Pw   Qw   V~  P    Q
+
+// The u side's image over the 64-column tiles [ut_lo, ut_hi): per tile and
+// chunk, the planes U~, Z~, U~^2, Z~^2 as the full form stages them (columns
+// past the last take column 0's values, samples past n zeros).  Block: one
+// tile at a time; thread t: column t / 4, samples 4 (t % 4) .. + 3 of a chunk.
+__global__ void __launch_bounds__(256) k_bf16_u_image(int n, const float *__restrict__ pool32, int64_t ld32,
+                                                      int64_t ulo, int64_t ucols, const float4 *__restrict__ usum,
+                                                      int64_t ut_lo, int64_t ut_hi, h16 *__restrict__ uimg)
+{
+#pragma clang fp contract(off)
+    const int c = threadIdx.x >> 2, k0 = (threadIdx.x & 3) * 4;
+    const int nch = (n + kKC - 1) / kKC, tmax = ((n - 1) / 4) * 4;
+    const float fn = (float)n, shs = sq_shift(n);
+    const int off = lds_off(c, k0);
+    for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
+        const int64_t su = ut * 64 + c;
+        const bool su_ok = su < ucols;
+        const float4 us = usum[su_ok ? su : 0];
+        const float smu = us.x, smz = us.y;
+        const UScale usc = u_scales(us.z, us.w, fn);
+        const float cu = usc.u, cz = usc.z, cu2 = usc.u * usc.u * shs, cz2 = usc.z * usc.z * shs;
+        const float *col = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
+        h16 *const dst = uimg + (size_t)ut * nch * (kUImgPlanes * 64 * kKR) + off;
+        for (int ch = 0; ch < nch; ++ch) {
+            float x[4], ua[kUImgPlanes][4];
+            load_floats<4>(col + min(ch * kKC + k0, tmax), x);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float uu = x[e] - smu, zz = __builtin_amdgcn_rcpf(x[e]) - smz;
+                const bool live = ch * kKC + k0 + e < n;
+                uu = live ? uu : 0.f; zz = live ? zz : 0.f;
+                ua[0][e] = uu * cu; ua[1][e] = zz * cz; ua[2][e] = (uu * uu) * cu2; ua[3][e] = (zz * zz) * cz2;
+            }
+#pragma unroll
+            for (int q = 0; q < kUImgPlanes; ++q) put_h16<4>(dst + (size_t)ch * (kUImgPlanes * 64 * kKR) + q * (64 * kKR), ua[q]);
+        }
+    }
+}
+
+// The v side's image for the moments pass: per 128-column tile and chunk, the
+// planes V~, P, Q, W~, Pw, Qw.  Block (vt, ch); thread t: column t / 2,
+// samples 8 (t % 2) .. + 7.
+__global__ void __launch_bounds__(256) k_bf16_vm_image(int n, const float *__restrict__ pool32, int64_t ld32,
+                                                       int64_t vcols, const float4 *__restrict__ vsum,
+                                                       h16 *__restrict__ img)
+{
+#pragma clang fp contract(off)
+    const int nch = (n + kKC - 1) / kKC;
+    const int64_t vt = blockIdx.x / nch;
+    const int ch = blockIdx.x % nch;
+    const int c = threadIdx.x >> 1, k0 = (threadIdx.x & 1) * 8;
+    const int64_t v = vt * 128 + c;
+    const int64_t vv = v < vcols ? v : 0;
+    const float4 vs = vsum[2 * vv];
+    const float smv = vs.x, smw = vs.y;
+    const VScale vsc = v_scales(smv, smw, vs.z, vs.w, (float)n, 1.0f, sq_shift(n));
+    const float *col = pool32 + (size_t)vv * ld32;
+    float va[kVmPlanes][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int t = ch * kKC + k0 + e;
+        const float x = col[t < n ? t : n - 1];
+        float d = x - smv, w = __builtin_amdgcn_rcpf(x) - smw;
+        const bool live = t < n;
+        d = live ? d : 0.f; w = live ? w : 0.f;
+        va[0][e] = d * vsc.v; va[1][e] = (d * (d + 2.f * smv)) * vsc.p; va[2][e] = (d * (d + smv)) * vsc.q;
+        va[3][e] = w * vsc.w; va[4][e] = (w * (w + 2.f * smw)) * vsc.pw; va[5][e] = (w * (w + smw)) * vsc.qw;
+    }
+    h16 *const out = img + (size_t)blockIdx.x * (kVmPlanes * 128 * kKR) + lds_off(c, k0);
+#pragma unroll
+    for (int q = 0; q < kVmPlanes; ++q) {
+        h16 hv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) hv[e] = (h16)va[q][e];
+        __builtin_memcpy(out + q * (128 * kKR), hv, 16);
+    }
+}
+
 struct MomShape {
-    static constexpr int kWU = 4, kWV = 2, kBTU = 32 * kWU, kBTV = 32 * kWV, kThreads = 64 * kWU * kWV;
-    static constexpr int kSU = kBTU * kKC / kThreads, kSV = kBTV * kKC / kThreads;
-    static constexpr int kPA = 4, kPB = 6, kNG = 9;
+    static constexpr int kWU = 2, kWV = 4, kBTU = 32 * kWU, kBTV = 32 * kWV, kThreads = 64 * kWU * kWV;
+    static constexpr int kPA = kUImgPlanes, kPB = kVmPlanes, kNG = 9;
     static constexpr int kPlaneU = kBTU * kKR, kPlaneV = kBTV * kKR;
-    static constexpr int kStage = kPA * kPlaneU + kPB * kPlaneV;
+    static constexpr int kStage = kPA * kPlaneU;                   // the u image's tile-chunk (LDS)
+    static constexpr int kRing = 2;                                // chunks held in registers
 };
+static_assert(8 * MomShape::kThreads == MomShape::kStage, "one 16-byte u piece per thread and chunk");
 
 __global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
-    sisso_space s, FormSlots fs, int n, const float *__restrict__ pool32, int64_t ld32,
-    const float4 *__restrict__ usum, const float4 *__restrict__ vsum, const sisso_colstat *__restrict__ stats,
-    int64_t ut_lo, int64_t ut_hi, int64_t id_begin, int64_t id_end, float *__restrict__ mom, h16 *__restrict__ uimg,
-    const int16_t *__restrict__ units, BfSide side)
+    sisso_space s, FormSlots fs, int n, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
+    const sisso_colstat *__restrict__ stats, int64_t ut_lo, int64_t ut_hi, int64_t id_begin, int64_t id_end,
+    float *__restrict__ mom, const h16 *uimg, const h16 *vmimg, const int16_t *__restrict__ units, BfSide side)
 {
     using Sh = MomShape;
     constexpr int kPA = Sh::kPA, kPB = Sh::kPB, kNG = Sh::kNG, kStage = Sh::kStage, kBTU = Sh::kBTU,
-                  kBTV = Sh::kBTV, kSU = Sh::kSU, kSV = Sh::kSV, kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV;
-    __shared__ __attribute__((aligned(16))) h16 stage[2 * kStage];
+                  kBTV = Sh::kBTV, kPlaneU = Sh::kPlaneU, kPlaneV = Sh::kPlaneV, kR = Sh::kRing;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    h16 *const stage = reinterpret_cast<h16 *>(smem);            // two staging buffers
     // u-tile constants: (mean u, mean 1/u, sum u~^2, sum z~^2), the inverse
     // scale factors of U~, U~^2, Z~, Z~^2, flags (1 valid, 2 no zero, 4 not
-    // scalable)
-    __shared__ float4 ucon_a[kBTU], ucon_c[kBTU];
-    __shared__ uint4 ucon_u[kBTU];                // units (zero without units)
-    __shared__ int ucon_f[kBTU];
+    // scalable), units (zero without units)
+    float4 *ucon_a = reinterpret_cast<float4 *>(stage + 2 * kStage), *ucon_c = ucon_a + kBTU;
+    uint4 *ucon_u = reinterpret_cast<uint4 *>(ucon_c + kBTU);
+    int *ucon_f = reinterpret_cast<int *>(ucon_u + kBTU);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wu = w % Sh::kWU, wv = w / Sh::kWU;
@@ -1440,29 +1530,25 @@ __global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
     const int S = s.n_slots;
     const float fn = (float)n, shs = sq_shift(n);
     const int nch = (n + kKC - 1) / kKC;
-    const int64_t nvt = (vcount + kBTV - 1) / kBTV, nvt64 = (vcount + 63) / 64, nut64 = (ucols + 63) / 64;
-    const int ucs = tid / (kKC / kSU), uks = (tid % (kKC / kSU)) * kSU;
-    const int vcs = tid / (kKC / kSV), vks = (tid % (kKC / kSV)) * kSV;
-    const int tmax_u = ((n - 1) / kSU) * kSU, tmax_v = ((n - 1) / kSV) * kSV;
-    const int sto_u = lds_off(ucs, uks), sto_v = lds_off(vcs, vks);
+    const int64_t nvt = (vcount + kBTV - 1) / kBTV, nvt64 = (vcount + 63) / 64;
     const int koff = (lane >> 5) * 8;
     const int fa = lds_off(wu * 32 + (lane & 31), koff), fb = lds_off(wv * 32 + (lane & 31), koff);
-    const int img_off = lds_off(ucs & 63, uks);   // this thread's samples in its 64-column image tile
-
-    for (int64_t ut = ut_lo + blockIdx.x; ut < ut_hi; ut += gridDim.x) {
-        const int64_t u0 = ut * kBTU;
-        const int64_t su = u0 + ucs;
-        const bool su_ok = su < ucols;
-        const float4 us_c = usum[su_ok ? su : 0];
-        const float smu = us_c.x, smz = us_c.y;
-        const UScale usc = u_scales(us_c.z, us_c.w, fn);
-        const float cu = usc.u, cz = usc.z, cu2 = usc.u * usc.u * shs, cz2 = usc.z * usc.z * shs;
-        const float *ucol = pool32 + (size_t)(ulo + (su_ok ? su : 0)) * ld32;
-        // the image has 64-column tiles up to the one holding the last column
-        // (its rows past the last column stage column 0, like the tiles)
-        h16 *const img = su / 64 < nut64 ? uimg + (size_t)(su / 64) * nch * (2 * 64 * kKR) + img_off : nullptr;
-        __syncthreads();                              // the previous tile's epilogue reads are done
-        if (tid < kBTU) {
+    // A plane of GEMM g in the image's order (U~, Z~, U~^2, Z~^2); B plane
+    constexpr int GA[kNG] = {0, 2, 0, 0, 2, 0, 1, 3, 1};
+    constexpr int GB[kNG] = {0, 1, 2, 3, 4, 5, 0, 1, 2};
+    // (u, v) tiles, v fastest, in turns of eight runs of gridDim.x / 8, one
+    // run per XCD (the blocks of an XCD share their u images in its L2)
+    const int64_t T = (ut_hi - ut_lo) * nvt;
+    const bool by_xcd = gridDim.x % 8 == 0;
+    const int64_t gx = blockIdx.x % 8, gk = blockIdx.x / 8, gn = gridDim.x / 8;
+    int64_t ut_cur = -1;
+    for (int64_t it = 0;; ++it) {
+        const int64_t t = by_xcd ? (it * 8 + gx) * gn + gk : it * gridDim.x + blockIdx.x;
+        if (t >= T) break;
+        const int64_t ut = ut_lo + t / nvt, vt = t % nvt;
+        const int64_t u0 = ut * kBTU, v0 = vt * kBTV;
+        __syncthreads();                              // the previous tile's reads of LDS are done
+        if (ut != ut_cur && tid < kBTU) {
             const int64_t x = u0 + tid;
             const bool in = x < ucols;
             const sisso_colstat cs = stats[ulo + (in ? x : 0)];
@@ -1474,161 +1560,123 @@ __global__ void __launch_bounds__(MomShape::kThreads, 1) k_bf_moments(
                           (col_scalable(ua.z, ua.w, fn, cs.minabs > 0.0f) ? 0 : 4);
             ucon_u[tid] = units ? unit_of(units, ulo + (in ? x : 0)) : make_uint4(0u, 0u, 0u, 0u);
         }
-        for (int64_t vt = 0; vt < nvt; ++vt) {
-            const int64_t v0 = vt * kBTV;
-            const int64_t sv = v0 + vcs;
-            const bool sv_ok = sv < vcount;
-            const float4 vs_c = vsum[2 * (sv_ok ? sv : 0)];
-            const float smv = vs_c.x, smw = vs_c.y;
-            const VScale vsc = v_scales(smv, smw, vs_c.z, vs_c.w, fn, 1.0f, shs);
-            const float *vcol = pool32 + (size_t)(sv_ok ? sv : 0) * ld32;
-            const bool wimg = vt == 0 && img != nullptr;
-            f32x16 acc[kNG];
+        ut_cur = ut;
+        f32x16 acc[kNG];
 #pragma unroll
-            for (int g = 0; g < kNG; ++g)
+        for (int g = 0; g < kNG; ++g)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
-            struct Raw {
-                float u[kSU], v[kSV];
-            };
-            Raw pr;
-            auto load_chunk = [&](int ch, Raw &x) {
-                load_floats<kSU>(ucol + min(ch * kKC + uks, tmax_u), x.u);
-                load_floats<kSV>(vcol + min(ch * kKC + vks, tmax_v), x.v);
-            };
-            auto store_chunk = [&](int ch, h16 *buf, bool tail) {
-                // the full form's operations, uncontracted
-#pragma clang fp contract(off)
-                float ua[kPA][kSU], va[kPB][kSV];
+            for (int e = 0; e < 16; ++e) acc[g][e] = 0.0f;
+        // Chunks.  The u side (shared by the four waves along v) goes through
+        // LDS: its image tile-chunk, one 16-byte piece per thread, through a
+        // ring of kR chunks in registers into two staging buffers (a chunk
+        // past the last is staged as zeros: its MFMAs add nothing; no branch
+        // around a load).  The v side (shared by two waves only) is loaded by
+        // each wave as its own MFMA fragments straight from the image, whose
+        // layout is the staged one: no LDS traffic for it.
+        const h16 *const ub = uimg + (size_t)ut * nch * kStage + tid * 8;
+        const h16 *const vb = vmimg + (size_t)vt * nch * (kPB * kPlaneV) + fb;
+        struct Slot {
+            u32x4 u;
+            h16x8 b[kPB];
+        };
+        Slot ring[kR];
+        auto fetch = [&](int c, Slot &d) {
+            const size_t cc = (size_t)(c < nch ? c : nch - 1);
+            d.u = *reinterpret_cast<const u32x4 *>(ub + cc * kStage);
 #pragma unroll
-                for (int e = 0; e < kSU; ++e) {
-                    float uu = pr.u[e] - smu, zz = __builtin_amdgcn_rcpf(pr.u[e]) - smz;
-                    if (tail) {
-                        const bool live = ch * kKC + uks + e < n;
-                        uu = live ? uu : 0.f; zz = live ? zz : 0.f;
-                    }
-                    ua[0][e] = uu * cu; ua[1][e] = (uu * uu) * cu2; ua[2][e] = zz * cz; ua[3][e] = (zz * zz) * cz2;
-                }
+            for (int q = 0; q < kPB; ++q)
+                d.b[q] = *reinterpret_cast<const h16x8 *>(vb + cc * (kPB * kPlaneV) + q * kPlaneV);
+        };
+        static_for<kR>([&](auto S2) {
+            fetch(decltype(S2)::value, ring[S2]);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        static_assert(kR == 2, "ring slot and buffer of a chunk fixed within a group");
+        for (int c0 = 0; c0 < nch; c0 += kR)
+            static_for<kR>([&](auto S2) {
+                constexpr int sc = decltype(S2)::value;
+                h16 *const buf = stage + sc * kStage;
+                const u32x4 zero = {0u, 0u, 0u, 0u};
+                *reinterpret_cast<u32x4 *>(buf + tid * 8) = c0 + sc >= nch ? zero : ring[sc].u;
+                // this wave's store is done and every wave is past the
+                // fragment reads of chunk c - 2 (the buffer's previous user)
+                lds_barrier();
+                h16x8 af[kPA];
 #pragma unroll
-                for (int q = 0; q < kPA; ++q) put_h16<kSU>(buf + q * kPlaneU + sto_u, ua[q]);
-                if (wimg) {
-                    h16 *const dst = img + (size_t)ch * (2 * 64 * kKR);
-                    put_h16<kSU>(dst, ua[0]);
-                    put_h16<kSU>(dst + 64 * kKR, ua[2]);
-                }
-#pragma unroll
-                for (int e = 0; e < kSV; ++e) {
-                    float vv = pr.v[e] - smv, ww = __builtin_amdgcn_rcpf(pr.v[e]) - smw;
-                    if (tail) {
-                        const bool live = ch * kKC + vks + e < n;
-                        vv = live ? vv : 0.f; ww = live ? ww : 0.f;
-                    }
-                    va[0][e] = vv * vsc.v; va[1][e] = (vv * (vv + 2.f * smv)) * vsc.p;
-                    va[2][e] = (vv * (vv + smv)) * vsc.q;
-                    va[3][e] = ww * vsc.w; va[4][e] = (ww * (ww + 2.f * smw)) * vsc.pw;
-                    va[5][e] = (ww * (ww + smw)) * vsc.qw;
-                }
-#pragma unroll
-                for (int q = 0; q < kPB; ++q) put_h16<kSV>(buf + kPA * kPlaneU + q * kPlaneV + sto_v, va[q]);
-            };
-            constexpr int GA[kNG] = {0, 1, 0, 0, 1, 0, 2, 3, 2};
-            constexpr int GB[kNG] = {0, 1, 2, 3, 4, 5, 0, 1, 2};
-            auto mfma_chunk = [&](const h16 *buf) {
-                h16x8 af[kPA], bfr[kPB];
-#pragma unroll
-                for (int a = 0; a < kPA; ++a) af[a] = *reinterpret_cast<const h16x8 *>(buf + a * kPlaneU + fa);
-#pragma unroll
-                for (int q = 0; q < kPB; ++q)
-                    bfr[q] = *reinterpret_cast<const h16x8 *>(buf + kPA * kPlaneU + q * kPlaneV + fb);
+                for (int q = 0; q < kPA; ++q) af[q] = *reinterpret_cast<const h16x8 *>(buf + q * kPlaneU + fa);
 #pragma unroll
                 for (int g = 0; g < kNG; ++g)
-                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[GA[g]], bfr[GB[g]], acc[g], 0, 0, 0);
-            };
-            auto buf_of = [&](int c) { return stage + (c & 1) * kStage; };
-            __syncthreads();                          // the previous tile's fragment reads are done
-            load_chunk(0, pr);
-            store_chunk(0, stage, nch == 1);
-            load_chunk(1, pr);
-            __syncthreads();
-            int ch = 0;
-            for (; ch + 2 < nch; ++ch) {
-                Raw q;
-                load_chunk(ch + 2, q);
-                mfma_chunk(buf_of(ch));
-                store_chunk(ch + 1, buf_of(ch + 1), false);
-                pr = q;
-                __syncthreads();
-            }
-            if (ch + 1 < nch) {
-                mfma_chunk(buf_of(ch));
-                store_chunk(ch + 1, buf_of(ch + 1), true);
-                __syncthreads();
-                ++ch;
-            }
-            mfma_chunk(buf_of(ch));
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[GA[g]], ring[sc].b[GB[g]], acc[g], 0, 0, 0);
+                fetch(c0 + sc + kR, ring[sc]);
+            });
 
-            // epilogue: lane holds column j = lane % 32 and rows
-            // i = 8 (r / 4) + 4 (lane / 32) + (r % 4) of each 32 x 32 result
-            const int j = lane & 31;
-            const int64_t v = v0 + wv * 32 + j;
-            const bool vin = v < vcount;
-            const sisso_colstat vst = stats[vin ? v : 0];
-            const float4 vs0 = vsum[2 * (vin ? v : 0)];
-            const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w;
-            const VScale vc = v_scales(mv, mw, Svv, Sww, fn, 1.0f, shs);
-            const float iv = 1.0f / vc.v, ip = 1.0f / vc.p, iq = 1.0f / vc.q, iw = 1.0f / vc.w, ipw = 1.0f / vc.pw,
-                        iqw = 1.0f / vc.qw;
-            const bool vscal = col_scalable(Svv, Sww, fn, vst.minabs > 0.0f);
-            const uint4 vunit = units ? unit_of(units, vin ? v : 0) : make_uint4(0u, 0u, 0u, 0u);
-            const int64_t v32 = vt * Sh::kWV + wv;
-            const int64_t u64 = (u0 + wu * 32) / 64;
-            const bool mom_in = (v32 >> 1) < nvt64 && u64 < nut64;
-            float *const mp = mom + (((size_t)u64 * nvt64 + (v32 >> 1)) * 4 + (wu & 1) + 2 * (int)(v32 & 1)) *
-                                        (16 * kMom * 64) + lane;
-            const int64_t tile_lo = binbase + (u0 * vcount + v0) * S;
-            const int64_t tile_hi = binbase + ((u0 + kBTU - 1) * vcount + v0 + kBTV - 1) * S + S;
-            const bool tile_in = tile_lo >= id_begin && tile_hi <= id_end;
+        // epilogue: lane holds column j = lane % 32 and rows
+        // i = 8 (r / 4) + 4 (lane / 32) + (r % 4) of each 32 x 32 result
+        const int j = lane & 31;
+        const int64_t v = v0 + wv * 32 + j;
+        const bool vin = v < vcount;
+        const sisso_colstat vst = stats[vin ? v : 0];
+        const float4 vs0 = vsum[2 * (vin ? v : 0)];
+        const float mv = vs0.x, mw = vs0.y, Svv = vs0.z, Sww = vs0.w;
+        const VScale vc = v_scales(mv, mw, Svv, Sww, fn, 1.0f, shs);
+        const float iv = 1.0f / vc.v, ip = 1.0f / vc.p, iq = 1.0f / vc.q, iw = 1.0f / vc.w, ipw = 1.0f / vc.pw,
+                    iqw = 1.0f / vc.qw;
+        const bool vscal = col_scalable(Svv, Sww, fn, vst.minabs > 0.0f);
+        const uint4 vunit = units ? unit_of(units, vin ? v : 0) : make_uint4(0u, 0u, 0u, 0u);
+        const int64_t v32 = vt * Sh::kWV + wv;
+        const int64_t u64 = ut;
+        const bool mom_in = (v32 >> 1) < nvt64;
+        float *const mp = mom + (((size_t)u64 * nvt64 + (v32 >> 1)) * 4 + wu + 2 * (int)(v32 & 1)) *
+                                    (16 * kMom * 64) + lane;
+        const int64_t tile_lo = binbase + (u0 * vcount + v0) * S;
+        const int64_t tile_hi = binbase + ((u0 + kBTU - 1) * vcount + v0 + kBTV - 1) * S + S;
+        const bool tile_in = tile_lo >= id_begin && tile_hi <= id_end;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < 16; ++r) {
 #pragma clang fp contract(off)
-                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const float4 us = ucon_a[wu * 32 + i], ui = ucon_c[wu * 32 + i];
-                const int uf = ucon_f[wu * 32 + i];
-                const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w;
-                auto var_of = [&](float s1, float g2, float g3, float ma, float mb, float sa, float sb) {
-                    const float t2 = 2.0f * ma * g3, t3 = mb * mb * sa, t4 = ma * ma * sb;
-                    const float var = (g2 + t2 + t3 + t4) - s1 * s1 / fn;
-                    const float mag = fabsf(g2) + fabsf(t2) + t3 + t4;
-                    return var >= kCondRel * mag && var < INFINITY ? var : -1.0f;
-                };
-                float m[kMom];
-                m[0] = (acc[0][r] * ui.x) * iv;                 // u v
-                m[1] = var_of(m[0], (acc[1][r] * ui.y) * ip, (acc[2][r] * ui.x) * iq, mu, mv, Suu, Svv);
-                m[2] = (acc[3][r] * ui.x) * iw;                 // u / v
-                m[3] = var_of(m[2], (acc[4][r] * ui.y) * ipw, (acc[5][r] * ui.x) * iqw, mu, mw, Suu, Sww);
-                m[4] = (acc[6][r] * ui.z) * iv;                 // v / u
-                m[5] = var_of(m[4], (acc[7][r] * ui.w) * ip, (acc[8][r] * ui.z) * iq, mz, mv, Szz, Svv);
-                if (mom_in) {
+            const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const float4 us = ucon_a[wu * 32 + i], ui = ucon_c[wu * 32 + i];
+            const int uf = ucon_f[wu * 32 + i];
+            const float mu = us.x, mz = us.y, Suu = us.z, Szz = us.w;
+            auto var_of = [&](float s1, float g2, float g3, float ma, float mb, float sa, float sb) {
+                const float t2 = 2.0f * ma * g3, t3 = mb * mb * sa, t4 = ma * ma * sb;
+                const float var = (g2 + t2 + t3 + t4) - s1 * s1 / fn;
+                const float mag = fabsf(g2) + fabsf(t2) + t3 + t4;
+                return var >= kCondRel * mag && var < INFINITY ? var : -1.0f;
+            };
+            float m[kMom];
+            m[0] = (acc[0][r] * ui.x) * iv;                 // u v
+            m[1] = var_of(m[0], (acc[1][r] * ui.y) * ip, (acc[2][r] * ui.x) * iq, mu, mv, Suu, Svv);
+            m[2] = (acc[3][r] * ui.x) * iw;                 // u / v
+            m[3] = var_of(m[2], (acc[4][r] * ui.y) * ipw, (acc[5][r] * ui.x) * iqw, mu, mw, Suu, Sww);
+            m[4] = (acc[6][r] * ui.z) * iv;                 // v / u
+            m[5] = var_of(m[4], (acc[7][r] * ui.w) * ip, (acc[8][r] * ui.z) * iq, mz, mv, Szz, Svv);
+            if (mom_in) {
 #pragma unroll
-                    for (int k = 0; k < kMom; ++k) __builtin_nontemporal_store(m[k], mp + (r * kMom + k) * 64);
-                }
-                // the read form's conditioning decision, from the same values
-                const bool ok = (uf & 1) && vin && vst.valid != 0.0f;
-                const bool unscal = (uf & 4) != 0 || !vscal;
-                const float var[5] = {Suu + Svv + 2.0f * m[0], Suu + Svv - 2.0f * m[0], m[1], m[3], m[5]};
-                const bool same_u = unit_eq(ucon_u[wu * 32 + i], vunit);   // sums and differences
-                const bool dom[5] = {same_u, same_u, true, vst.minabs > 0.f, (uf & 2) != 0};
-                const float cth = kCondRel * (Suu + Svv);
+                for (int k = 0; k < kMom; ++k) __builtin_nontemporal_store(m[k], mp + (r * kMom + k) * 64);
+            }
+            // the read form's conditioning decision, from the same values
+            const bool ok = ((uf & 1) != 0) & vin & (vst.valid != 0.0f);
+            const bool unscal = ((uf & 4) != 0) | !vscal;
+            const float var[5] = {Suu + Svv + 2.0f * m[0], Suu + Svv - 2.0f * m[0], m[1], m[3], m[5]};
+            const bool same_u = unit_eq(ucon_u[wu * 32 + i], vunit);   // sums and differences
+            const bool dom[5] = {same_u, same_u, true, vst.minabs > 0.f, (uf & 2) != 0};
+            const float cth = kCondRel * (Suu + Svv);
+            bool any = false, flag[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const bool cand = ok & dom[k] & (fs.slot[k] >= 0);
+                const bool good = !unscal & (k < 2 ? var[k] >= cth : var[k] > 0.0f) & (var[k] < INFINITY);
+                flag[k] = cand & !good;
+                any = any | flag[k];
+            }
+            if (any) {
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    const bool cand = ok && dom[k] && fs.slot[k] >= 0;
-                    const bool good = !unscal && (k < 2 ? var[k] >= cth : var[k] > 0.0f) && var[k] < INFINITY;
-                    if (cand && !good) {
-                        const int64_t id = binbase + ((u0 + wu * 32 + i) * vcount + v) * S + fs.slot[k];
-                        if (tile_in || (id >= id_begin && id < id_end)) {
-                            const unsigned long long q = atomicAdd(side.cnt, 1ull);
-                            if (q < (unsigned long long)side.cap) side.ids[q] = id;
-                        }
+                    const int64_t id = binbase + ((u0 + wu * 32 + i) * vcount + v) * S + fs.slot[k];
+                    if (flag[k] && (tile_in || (id >= id_begin && id < id_end))) {
+                        const unsigned long long q = atomicAdd(side.cnt, 1ull);
+                        if (q < (unsigned long long)side.cap) side.ids[q] = id;
                     }
                 }
             }
@@ -2068,7 +2116,7 @@ namespace sisso {
 // The moments pass over the u tiles covering [cand_begin, cand_end): one
 // block per CU (its registers allow no more), each sweeping its share.
 sisso_status bf_launch_moments(const sisso_space *space, const sisso_score_args *args, const BfOps &o, BfWs &w,
-                               int64_t cand_begin, int64_t cand_end, float *mom, h16 *uimg, BfSide side,
+                               int64_t cand_begin, int64_t cand_end, float *mom, h16 *uimg, h16 *vmimg, BfSide side,
                                hipStream_t st)
 #ifdef SISSO_BF16_MFMA_PART
 {
@@ -2076,11 +2124,29 @@ sisso_status bf_launch_moments(const sisso_space *space, const sisso_score_args 
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         return SISSO_E_DEVICE;
+    const int n = args->n, L = space->levels, nch = (n + kKC - 1) / kKC;
+    const int64_t ulo = space->pool[L - 1], ucols = space->pool[L] - ulo, vcols = space->pool[L - 1];
     const BfPlan p = bf_plan(space, cand_begin, cand_end, cus, MomShape::kBTU);
-    if (p.grid > 0)
-        hipLaunchKernelGGL(k_bf_moments, dim3(p.grid), dim3(MomShape::kThreads), 0, st, *space, form_slots(space),
-                           args->n, args->pool32, args->ld32, o.usum, w.vsum, args->stats, p.ut_lo, p.ut_hi,
-                           cand_begin, cand_end, mom, uimg, args->units, side);
+    if (p.grid == 0) return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+    // the images: the u tiles of the pass, widened to the read form's 128-column
+    // tiles; every v tile
+    const int64_t nut64 = (ucols + 63) / 64, ilo = p.ut_lo & ~(int64_t)1,
+                  ihi = ((p.ut_hi + 1) & ~(int64_t)1) < nut64 ? ((p.ut_hi + 1) & ~(int64_t)1) : nut64;
+    hipLaunchKernelGGL(k_bf16_u_image, dim3((unsigned)(ihi - ilo < 8192 ? ihi - ilo : 8192)), dim3(256), 0, st, n,
+                       args->pool32, args->ld32, ulo, ucols, o.usum, ilo, ihi, uimg);
+    const int64_t nvt = (vcols + MomShape::kBTV - 1) / MomShape::kBTV;
+    hipLaunchKernelGGL(k_bf16_vm_image, dim3((unsigned)(nvt * nch)), dim3(256), 0, st, n, args->pool32, args->ld32,
+                       vcols, w.vsum, vmimg);
+    // one block per CU over the (u, v) tiles, a multiple of the eight XCDs
+    const int64_t tiles = (p.ut_hi - p.ut_lo) * nvt;
+    int g = (int)(tiles < cus ? tiles : cus);
+    if (g >= 8) g -= g % 8;
+    const size_t smem = 2 * (size_t)MomShape::kStage * sizeof(h16) +
+                        MomShape::kBTU * (2 * sizeof(float4) + sizeof(uint4) + sizeof(int));   // staging, u constants
+    if (!allow_dynamic_lds(k_bf_moments, smem)) return SISSO_E_UNSUPPORTED;
+    hipLaunchKernelGGL(k_bf_moments, dim3(g), dim3(MomShape::kThreads), smem, st, *space, form_slots(space), n, o.usum,
+                       w.vsum, args->stats, p.ut_lo, p.ut_hi, cand_begin, cand_end, mom, uimg, vmimg, args->units,
+                       side);
     return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
 }
 #else
@@ -2116,12 +2182,18 @@ size_t bf_cst_offset(const sisso_space *space, int n)
     const int L = space->levels;
     return bf_uimg_offset(space) + align256b(bf_uimg_elems(space->pool[L] - space->pool[L - 1], n) * sizeof(h16));
 }
-size_t bf_moments_total(const sisso_space *space, int n)
+// the moments pass's v image
+size_t bf_vmimg_offset(const sisso_space *space, int n)
 {
     const int L = space->levels;
     const int64_t ucols = space->pool[L] - space->pool[L - 1], vcols = space->pool[L - 1];
     return bf_cst_offset(space, n) + align256b((size_t)bf_tiles(ucols) * (size_t)bf_tiles(vcols) * (kMomTile / kMom) *
                                                3 * sizeof(float));
+}
+size_t bf_moments_total(const sisso_space *space, int n)
+{
+    const int L = space->levels;
+    return bf_vmimg_offset(space, n) + align256b(bf_vmimg_elems(space->pool[L - 1], n) * sizeof(h16));
 }
 
 sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, const void *ops, size_t ops_bytes,
@@ -2149,6 +2221,7 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     float *mom = (float *)moments;
     h16 *const uimg = mode == SISSO_MOMENTS_NONE ? nullptr : (h16 *)((char *)moments + bf_uimg_offset(space));
     float *const cst = mode == SISSO_MOMENTS_NONE ? nullptr : (float *)((char *)moments + bf_cst_offset(space, n));
+    h16 *const vmimg = mode == SISSO_MOMENTS_NONE ? nullptr : (h16 *)((char *)moments + bf_vmimg_offset(space, n));
     // the flagged candidates: beside the moments (every pass of a fit scores
     // those its first pass stored), else in the workspace
     const BfSide side = bf_side_view(mode == SISSO_MOMENTS_NONE ? w.side : (char *)moments + bf_moments_bytes(space),
@@ -2164,7 +2237,7 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     case SISSO_MOMENTS_WRITE:
         // the moments pass stores the moments, the flagged candidates and the
         // u side's image; the read form then scores the pass from them
-        rc = bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, side, st);
+        rc = bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, vmimg, side, st);
         if (rc == SISSO_OK) rc = bf_launch_read(space, args, o, w, band, cand_begin, cand_end, mom, cst, uimg, side, st);
         l0 = bf_screen_lists<kBfRead>(space, args, cand_begin, cand_end, cus);
         break;

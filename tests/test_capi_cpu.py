@@ -143,9 +143,11 @@ def test_bf16_moments_size_and_argument_errors_before_launch():
     """The moments buffer holds 6 floats per pair of the padded 64 x 64 tiles of
     the slice's binary block, then the list of the candidates the screen
     scores exactly (a counter and one id per 1024 candidates of the block, at
-    least 2^16 and at most 2^26), then the u side's FP16 image (two planes of
-    64 columns x 16 samples per 64-column tile and chunk of 16 samples), then
-    3 floats per pair of the same tiles (a pass's residual contractions); a bad
+    least 2^16 and at most 2^26), then the u side's FP16 image (four planes
+    of 64 columns x 16 samples per 64-column tile and chunk of 16 samples),
+    then 3 floats per pair of the same tiles (a pass's residual contractions),
+    then the v side's FP16 image for the moments pass (six planes of 128
+    columns x 16 samples per 128-column tile and chunk); a bad
     mode, a missing or short buffer and the usual range checks are reported
     before any launch."""
     lib = L.lib()
@@ -155,9 +157,10 @@ def test_bf16_moments_size_and_argument_errors_before_launch():
     side = min(max(int(s.rect_binary) // 1024, 1 << 16), 1 << 26)
     a256 = lambda x: (x + 255) // 256 * 256
     mom = a256(tiles * 4 * 16 * 6 * 64 * 4)
-    uimg = a256(((nu + 63) // 64) * ((100 + 15) // 16) * 2 * 64 * 16 * 2)
+    uimg = a256(((nu + 63) // 64) * ((100 + 15) // 16) * 4 * 64 * 16 * 2)
+    vmimg = a256(((nv + 127) // 128) * ((100 + 15) // 16) * 6 * 128 * 16 * 2)
     cst = a256(tiles * 4 * 16 * 3 * 64 * 4)
-    assert lib.sisso_bf16_moments_size(ctypes.byref(s), 100) == mom + a256(256 + 8 * side) + uimg + cst
+    assert lib.sisso_bf16_moments_size(ctypes.byref(s), 100) == mom + a256(256 + 8 * side) + uimg + cst + vmimg
     assert lib.sisso_bf16_moments_size(ctypes.byref(s), 1) == 0
     plain = L.make_space(5, I.OPS1["unary"], I.OPS1["binary"], 2, False)
     assert lib.sisso_bf16_moments_size(ctypes.byref(plain), 100) == 0      # no slice
