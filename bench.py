@@ -311,9 +311,11 @@ def cpu_baseline(p, budget_s: float, sub=None):
 
 MI355X_FP16_TFLOPS = 2500.0               # dense MFMA, FP16 and BF16 alike
 CONTRACTIONS_PER_PAIR = 9            # algorithmic: (u v, u (v r), u^2 v^2) for u * v, u / v and v / u
-EXECUTED_MFMA_GEMMS = 12             # the kernel: 12 centred contractions, one FP16 product each
-READ_CONTRACTIONS_PER_PAIR = 3       # read form: u (v r) for u * v, u / v and v / u
+EXECUTED_MFMA_GEMMS = 12             # the plain kernel: 12 centred contractions, one FP16 product each
+MOMENT_CONTRACTIONS_PER_PAIR = 9     # moments pass: the residual-independent ones of the plain kernel's 12
+READ_CONTRACTIONS_PER_PAIR = 3       # read pass: u (v r) for u * v, u / v and v / u
 MOMENT_BYTES_PER_PAIR = 24           # six FP32 residual-independent moments per (u, v) pair
+CONTRACTION_BYTES_PER_PAIR = 12      # three FP32 residual contractions per (u, v) pair
 
 
 def recall_of(fi, fs, bi, tol=1e-6):
@@ -495,36 +497,49 @@ def main():
                 "per_unit": f"{NET_FLOPS_PER_CAND} network flops per candidate + {FLOPS_PER_CAND_SAMPLE} flops "
                             f"x n={n} per exactly scored candidate ({kept:.3g} per launch)"}
     elif n_bin > 0 and prec == "bf16":
-        # with the moments buffer the first pass of each fit is the write form
-        # (all 12 GEMMs + the moments' stores), the later ones the read form
-        moments = eng.bf16_moments is not None
-        ks = ev_ms(timings, "bf16_screen")
-        kernel_ms = sum(ks) / len(ks)
         pairs = n_bin // eng.space.n_slots
-        flops = 2.0 * CONTRACTIONS_PER_PAIR * n * pairs
-        achieved = flops / (kernel_ms * 1e-3) / 1e12
-        executed = 2.0 * EXECUTED_MFMA_GEMMS * n * pairs / (kernel_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "k_score_rect_bf16_write" if moments else "k_score_rect_bf16",
-                "achieved": achieved,
-                "peak": MI355X_FP16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MI355X_FP16_TFLOPS,
-                "traffic": None, "avg_launch_ms": kernel_ms, "units_per_launch": pairs,
-                "per_unit": f"{CONTRACTIONS_PER_PAIR} contractions x 2 flops x n={n} samples per (u, v) pair "
-                            f"(= {2 * CONTRACTIONS_PER_PAIR * n / 5:.0f} flops per candidate of the 5 forms)",
-                "executed_mfma_tflops": executed, "executed_frac": executed / MI355X_FP16_TFLOPS,
-                "launches_per_step": len(ks) / args.steps}
+        km = ev_ms(timings, "bf16_moments")
         kr = ev_ms(timings, "bf16_screen_read")
+        if km:
+            # a fit's first pass runs the moments pass (nine residual-independent
+            # GEMMs per pair, the dominant kernel), every pass a read pass (three
+            # residual GEMMs, then the scorer of the stored contractions)
+            kernel_ms = sum(km) / len(km)
+            flops = 2.0 * MOMENT_CONTRACTIONS_PER_PAIR * n * pairs
+            achieved = flops / (kernel_ms * 1e-3) / 1e12
+            roof = {"bound": "mfma", "kernel": "k_bf_moments", "achieved": achieved,
+                    "peak": MI355X_FP16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MI355X_FP16_TFLOPS,
+                    "traffic": measured_traffic("k_bf_moments", args.workload), "avg_launch_ms": kernel_ms,
+                    "units_per_launch": pairs, "launches_per_step": len(km) / args.steps,
+                    "per_unit": f"{MOMENT_CONTRACTIONS_PER_PAIR} residual-independent contractions x 2 flops x "
+                                f"n={n} samples per (u, v) pair"}
+            ki = ev_ms(timings, "bf16_images")
+            if ki:
+                roof["images"] = {"kernels": "k_bf16_u_image, k_bf16_vm_image", "avg_ms": sum(ki) / len(ki),
+                                  "launches_per_step": len(ki) / args.steps}
+        else:
+            ks = ev_ms(timings, "bf16_screen")
+            kernel_ms = sum(ks) / len(ks)
+            flops = 2.0 * CONTRACTIONS_PER_PAIR * n * pairs
+            achieved = flops / (kernel_ms * 1e-3) / 1e12
+            executed = 2.0 * EXECUTED_MFMA_GEMMS * n * pairs / (kernel_ms * 1e-3) / 1e12
+            roof = {"bound": "mfma", "kernel": "k_score_rect_bf16", "achieved": achieved,
+                    "peak": MI355X_FP16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / MI355X_FP16_TFLOPS,
+                    "traffic": None, "avg_launch_ms": kernel_ms, "units_per_launch": pairs,
+                    "per_unit": f"{CONTRACTIONS_PER_PAIR} contractions x 2 flops x n={n} samples per (u, v) pair",
+                    "executed_mfma_tflops": executed, "executed_frac": executed / MI355X_FP16_TFLOPS,
+                    "launches_per_step": len(ks) / args.steps}
         if kr:
             read_ms = sum(kr) / len(kr)
             rflops = 2.0 * READ_CONTRACTIONS_PER_PAIR * n * pairs
-            roof["read_form"] = {
-                "kernel": "k_score_rect_bf16_read", "avg_launch_ms": read_ms, "launches_per_step": len(kr) / args.steps,
+            roof["read_pass"] = {
+                "kernels": "k_score_rect_bf16<read> (residual GEMMs), k_bf_score_stored (bound, then scores)",
+                "avg_ms": read_ms, "launches_per_step": len(kr) / args.steps,
                 "achieved": rflops / (read_ms * 1e-3) / 1e12, "unit": "TFLOP/s",
                 "frac": rflops / (read_ms * 1e-3) / 1e12 / MI355X_FP16_TFLOPS,
                 "per_unit": f"{READ_CONTRACTIONS_PER_PAIR} residual contractions x 2 flops x n={n} samples per "
-                            f"(u, v) pair, plus {MOMENT_BYTES_PER_PAIR} bytes of stored moments",
-                "executed_mfma_tflops": 2.0 * READ_CONTRACTIONS_PER_PAIR * n * pairs / (read_ms * 1e-3) / 1e12,
-                "moments_gb_per_s": MOMENT_BYTES_PER_PAIR * pairs / (read_ms * 1e-3) / 1e9,
-                "traffic": measured_traffic("k_score_rect_bf16_read", args.workload)}
+                            f"(u, v) pair, plus {MOMENT_BYTES_PER_PAIR} bytes of stored moments and "
+                            f"{CONTRACTION_BYTES_PER_PAIR} of contractions written and read"}
     elif n_bin > 0:
         kb = ev_ms(timings, "binary")
         kernel_ms = sum(kb) / len(kb)

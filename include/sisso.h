@@ -392,6 +392,22 @@ sisso_status sisso_bf16_screen_moments(const sisso_space *space, const sisso_sco
                                        int64_t cand_begin, int64_t cand_end, void *moments,
                                        size_t moments_bytes, int32_t mode, void *bws, size_t bws_bytes,
                                        void *stream);
+/* The moments work of a WRITE screen in two steps, for callers that time or
+ * overlap them: sisso_bf16_moments_images writes both sides' FP16 operand
+ * images into `moments` (residual-independent), sisso_bf16_moments_pass then
+ * runs the nine residual-independent GEMMs and stores the moments and the
+ * flagged candidates.  images, pass, then a READ screen of the same call
+ * arguments equal a WRITE screen, bit for bit.  Both need the call's
+ * sisso_bf16_residual step first (they read the v-side column sums in `bws`).
+ * Arguments and errors as sisso_bf16_screen_moments (no mode). */
+sisso_status sisso_bf16_moments_images(const sisso_space *space, const sisso_score_args *args,
+                                       const void *ops, size_t ops_bytes, int32_t band,
+                                       int64_t cand_begin, int64_t cand_end, void *moments,
+                                       size_t moments_bytes, void *bws, size_t bws_bytes, void *stream);
+sisso_status sisso_bf16_moments_pass(const sisso_space *space, const sisso_score_args *args,
+                                     const void *ops, size_t ops_bytes, int32_t band,
+                                     int64_t cand_begin, int64_t cand_end, void *moments,
+                                     size_t moments_bytes, void *bws, size_t bws_bytes, void *stream);
 
 /* Merge the workspace's per-block lists into the global best k (score desc,
  * id asc) (Sec. 2.2, eq. sis-method).  The merge takes no exclusion list:

@@ -174,6 +174,8 @@ def lib():
         "sisso_bf16_rescore": (_i32, [sp, ap, _i32, _vp, _sz, _vp, _sz, _vp]),
         "sisso_bf16_moments_size": (_sz, [sp, _i32]),
         "sisso_bf16_screen_moments": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _i32, _vp, _sz, _vp]),
+        "sisso_bf16_moments_images": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _vp, _sz, _vp]),
+        "sisso_bf16_moments_pass": (_i32, [sp, ap, _vp, _sz, _i32, _i64, _i64, _vp, _sz, _vp, _sz, _vp]),
         "sisso_mlp_param_count": (_i32, []),
         "sisso_mlp_table_count": (_i32, []),
         "sisso_encode_operands": (_i32, [sp, ap, _i64, _i64, _vp, _vp]),
@@ -215,7 +217,7 @@ EXPORTED = ["sisso_space_init", "sisso_decode", "sisso_materialize_pools", "siss
             "sisso_sort_subspace", "sisso_bf16_operands_size", "sisso_prepare_bf16",
             "sisso_bf16_workspace_size", "sisso_expand_score_bf16_lists", "sisso_expand_score_bf16",
             "sisso_bf16_residual", "sisso_bf16_screen", "sisso_bf16_rescore", "sisso_bf16_moments_size",
-            "sisso_bf16_screen_moments",
+            "sisso_bf16_screen_moments", "sisso_bf16_moments_images", "sisso_bf16_moments_pass",
             "sisso_materialize_ids_stored", "sisso_prepare_residual_batched", "sisso_batch_workspace_size",
             "sisso_batch_items", "sisso_expand_score_batched", "sisso_topk_batched", "sisso_l0_search_batched",
             "sisso_materialize_ids_batched", "sisso_subspace_update_batched", "sisso_sort_subspace_batched",

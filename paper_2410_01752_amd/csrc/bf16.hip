@@ -2115,9 +2115,10 @@ sisso_status bf_launch_read(const sisso_space *space, const sisso_score_args *ar
 namespace sisso {
 // The moments pass over the u tiles covering [cand_begin, cand_end): one
 // block per CU (its registers allow no more), each sweeping its share.
+// images: the operand images of the pass (before it), else the pass itself
 sisso_status bf_launch_moments(const sisso_space *space, const sisso_score_args *args, const BfOps &o, BfWs &w,
                                int64_t cand_begin, int64_t cand_end, float *mom, h16 *uimg, h16 *vmimg, BfSide side,
-                               hipStream_t st)
+                               bool images, hipStream_t st)
 #ifdef SISSO_BF16_MFMA_PART
 {
     int dev = 0, cus = 0;
@@ -2128,15 +2129,18 @@ sisso_status bf_launch_moments(const sisso_space *space, const sisso_score_args 
     const int64_t ulo = space->pool[L - 1], ucols = space->pool[L] - ulo, vcols = space->pool[L - 1];
     const BfPlan p = bf_plan(space, cand_begin, cand_end, cus, MomShape::kBTU);
     if (p.grid == 0) return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
-    // the images: the u tiles of the pass, widened to the read form's 128-column
-    // tiles; every v tile
-    const int64_t nut64 = (ucols + 63) / 64, ilo = p.ut_lo & ~(int64_t)1,
-                  ihi = ((p.ut_hi + 1) & ~(int64_t)1) < nut64 ? ((p.ut_hi + 1) & ~(int64_t)1) : nut64;
-    hipLaunchKernelGGL(k_bf16_u_image, dim3((unsigned)(ihi - ilo < 8192 ? ihi - ilo : 8192)), dim3(256), 0, st, n,
-                       args->pool32, args->ld32, ulo, ucols, o.usum, ilo, ihi, uimg);
     const int64_t nvt = (vcols + MomShape::kBTV - 1) / MomShape::kBTV;
-    hipLaunchKernelGGL(k_bf16_vm_image, dim3((unsigned)(nvt * nch)), dim3(256), 0, st, n, args->pool32, args->ld32,
-                       vcols, w.vsum, vmimg);
+    if (images) {
+        // the u tiles of the pass, widened to the read form's 128-column
+        // tiles; every v tile
+        const int64_t nut64 = (ucols + 63) / 64, ilo = p.ut_lo & ~(int64_t)1,
+                      ihi = ((p.ut_hi + 1) & ~(int64_t)1) < nut64 ? ((p.ut_hi + 1) & ~(int64_t)1) : nut64;
+        hipLaunchKernelGGL(k_bf16_u_image, dim3((unsigned)(ihi - ilo < 8192 ? ihi - ilo : 8192)), dim3(256), 0, st,
+                           n, args->pool32, args->ld32, ulo, ucols, o.usum, ilo, ihi, uimg);
+        hipLaunchKernelGGL(k_bf16_vm_image, dim3((unsigned)(nvt * nch)), dim3(256), 0, st, n, args->pool32,
+                           args->ld32, vcols, w.vsum, vmimg);
+        return hipGetLastError() == hipSuccess ? SISSO_OK : SISSO_E_DEVICE;
+    }
     // one block per CU over the (u, v) tiles, a multiple of the eight XCDs
     const int64_t tiles = (p.ut_hi - p.ut_lo) * nvt;
     int g = (int)(tiles < cus ? tiles : cus);
@@ -2196,6 +2200,10 @@ size_t bf_moments_total(const sisso_space *space, int n)
     return bf_vmimg_offset(space, n) + align256b(bf_vmimg_elems(space->pool[L - 1], n) * sizeof(h16));
 }
 
+// internal modes of bf_screen beside the public three: the two halves of the
+// moments work of a WRITE screen, for callers that time them
+constexpr int32_t kMomentsImages = 100, kMomentsPass = 101;
+
 sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, const void *ops, size_t ops_bytes,
                        int32_t band, int64_t cand_begin, int64_t cand_end, void *moments, size_t moments_bytes,
                        int32_t mode, void *bws, size_t bws_bytes, void *stream)
@@ -2207,7 +2215,8 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     const int64_t bb = space->pool[L] + space->rect_unary;
     if (cand_begin < bb || cand_end > space->total || cand_begin >= cand_end) return SISSO_E_RANGE;
     if (ops_bytes < sisso_bf16_operands_size(space, n)) return SISSO_E_WORKSPACE;
-    if (mode != SISSO_MOMENTS_NONE && mode != SISSO_MOMENTS_WRITE && mode != SISSO_MOMENTS_READ)
+    if (mode != SISSO_MOMENTS_NONE && mode != SISSO_MOMENTS_WRITE && mode != SISSO_MOMENTS_READ &&
+        mode != kMomentsImages && mode != kMomentsPass)
         return SISSO_E_RANGE;
     if (mode != SISSO_MOMENTS_NONE) {
         if (!moments) return SISSO_E_NULL;
@@ -2226,7 +2235,8 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     // those its first pass stored), else in the workspace
     const BfSide side = bf_side_view(mode == SISSO_MOMENTS_NONE ? w.side : (char *)moments + bf_moments_bytes(space),
                                      *space);
-    if (mode != SISSO_MOMENTS_READ) hipLaunchKernelGGL(k_bf_side_reset, dim3(1), dim3(64), 0, st, side);
+    if (mode != SISSO_MOMENTS_READ && mode != kMomentsImages)
+        hipLaunchKernelGGL(k_bf_side_reset, dim3(1), dim3(64), 0, st, side);
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
@@ -2237,10 +2247,15 @@ sisso_status bf_screen(const sisso_space *space, const sisso_score_args *args, c
     case SISSO_MOMENTS_WRITE:
         // the moments pass stores the moments, the flagged candidates and the
         // u side's image; the read form then scores the pass from them
-        rc = bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, vmimg, side, st);
+        rc = bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, vmimg, side, true, st);
+        if (rc == SISSO_OK) rc = bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, vmimg, side, false, st);
         if (rc == SISSO_OK) rc = bf_launch_read(space, args, o, w, band, cand_begin, cand_end, mom, cst, uimg, side, st);
         l0 = bf_screen_lists<kBfRead>(space, args, cand_begin, cand_end, cus);
         break;
+    case kMomentsImages:
+        return bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, vmimg, side, true, st);
+    case kMomentsPass:
+        return bf_launch_moments(space, args, o, w, cand_begin, cand_end, mom, uimg, vmimg, side, false, st);
     case SISSO_MOMENTS_READ:
         rc = bf_launch_read(space, args, o, w, band, cand_begin, cand_end, mom, cst, uimg, side, st);
         l0 = bf_screen_lists<kBfRead>(space, args, cand_begin, cand_end, cus);
@@ -2283,6 +2298,26 @@ extern "C" sisso_status sisso_bf16_screen_moments(const sisso_space *space, cons
     if (args && args->w32) return SISSO_E_UNSUPPORTED;   // weighted passes run in the FP32 form
     return bf_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, moments, moments_bytes, mode, bws,
                      bws_bytes, stream);
+}
+
+extern "C" sisso_status sisso_bf16_moments_images(const sisso_space *space, const sisso_score_args *args,
+                                                  const void *ops, size_t ops_bytes, int32_t band,
+                                                  int64_t cand_begin, int64_t cand_end, void *moments,
+                                                  size_t moments_bytes, void *bws, size_t bws_bytes, void *stream)
+{
+    if (args && args->w32) return SISSO_E_UNSUPPORTED;
+    return bf_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, moments, moments_bytes, kMomentsImages,
+                     bws, bws_bytes, stream);
+}
+
+extern "C" sisso_status sisso_bf16_moments_pass(const sisso_space *space, const sisso_score_args *args,
+                                                const void *ops, size_t ops_bytes, int32_t band, int64_t cand_begin,
+                                                int64_t cand_end, void *moments, size_t moments_bytes, void *bws,
+                                                size_t bws_bytes, void *stream)
+{
+    if (args && args->w32) return SISSO_E_UNSUPPORTED;
+    return bf_screen(space, args, ops, ops_bytes, band, cand_begin, cand_end, moments, moments_bytes, kMomentsPass,
+                     bws, bws_bytes, stream);
 }
 
 extern "C" sisso_status sisso_bf16_rescore(const sisso_space *space, const sisso_score_args *args, int32_t band,

@@ -197,10 +197,12 @@ class Engine:
         workspace; `events`, if given, collects (start, end) CUDA events per
         call, recorded on the stream the kernels run on.  With the BF16 form,
         `moments` "write" also stores the residual-independent moments of the
-        whole binary block into bf16_moments_buffer(), and "read" uses the
-        ones an earlier "write" over the same engine stored."""
+        whole binary block into bf16_moments_buffer() (as three calls: the
+        operand images, the moments pass, a "read" screen; "write_whole" issues
+        the one-call WRITE screen instead), and "read" uses the ones an earlier
+        "write" over the same engine stored."""
         end = self.total if end is None else end
-        if moments not in ("none", "write", "read"):
+        if moments not in ("none", "write", "read", "write_whole"):
             raise L.SissoError(f"unknown moments mode {moments!r}")
         if self.w64 is not None and precision != "fp32":
             raise L.SissoError("weighted screening runs in the FP32 form only")
@@ -267,20 +269,32 @@ class Engine:
                 bws = self._workspace("bf16", nb)
                 sp_, a_ = ctypes.byref(self.space), ctypes.byref(a)
                 mode = L.MOMENTS_NONE if fallback is not None else \
-                    {"none": L.MOMENTS_NONE, "write": L.MOMENTS_WRITE, "read": L.MOMENTS_READ}[moments]
+                    {"none": L.MOMENTS_NONE, "write": L.MOMENTS_WRITE, "read": L.MOMENTS_READ,
+                     "write_whole": L.MOMENTS_WRITE}[moments]
+                split = moments == "write"            # "write_whole": the one-call WRITE screen
                 mom = self.bf16_moments_buffer() if mode != L.MOMENTS_NONE else None
                 if mode != L.MOMENTS_NONE and (mom is None or b != bb or e != self.total):
                     raise L.SissoError("BF16 moments need their buffer and the whole binary block")
+                ops_, mp_ = L.ptr(self.bf16_ops), (L.ptr(mom) if mom is not None else None)
+                mb_ = mom.numel() if mom is not None else 0
                 steps = [("bf16_residual", lambda: L.lib().sisso_bf16_residual(sp_, a_, band, L.ptr(bws),
-                                                                              bws.numel(), st)),
-                         ("bf16_screen_read" if mode == L.MOMENTS_READ else "bf16_screen",
-                          lambda: L.lib().sisso_bf16_screen_moments(
-                             sp_, a_, L.ptr(self.bf16_ops), self.bf16_ops.numel(), band, b, e,
-                             L.ptr(mom) if mom is not None else None, mom.numel() if mom is not None else 0,
-                             mode, L.ptr(bws), bws.numel(), st)),
-                         ("bf16_rescore", lambda: L.lib().sisso_bf16_rescore(sp_, a_, band, L.ptr(bws),
-                                                                            bws.numel(), L.ptr(ws), ws.numel(),
-                                                                            st))]
+                                                                              bws.numel(), st))]
+                if mode == L.MOMENTS_WRITE and split:
+                    # a WRITE screen as its three parts (timed apart): the operand
+                    # images, the moments pass, then a READ screen
+                    steps += [("bf16_images", lambda: L.lib().sisso_bf16_moments_images(
+                                  sp_, a_, ops_, self.bf16_ops.numel(), band, b, e, mp_, mb_, L.ptr(bws), bws.numel(),
+                                  st)),
+                              ("bf16_moments", lambda: L.lib().sisso_bf16_moments_pass(
+                                  sp_, a_, ops_, self.bf16_ops.numel(), band, b, e, mp_, mb_, L.ptr(bws), bws.numel(),
+                                  st))]
+                smode = L.MOMENTS_READ if (mode == L.MOMENTS_WRITE and split) else mode
+                steps += [("bf16_screen_read" if smode == L.MOMENTS_READ else "bf16_screen",
+                           lambda: L.lib().sisso_bf16_screen_moments(sp_, a_, ops_, self.bf16_ops.numel(), band, b, e,
+                                                                     mp_, mb_, smode, L.ptr(bws), bws.numel(), st)),
+                          ("bf16_rescore", lambda: L.lib().sisso_bf16_rescore(sp_, a_, band, L.ptr(bws),
+                                                                             bws.numel(), L.ptr(ws), ws.numel(),
+                                                                             st))]
                 for sname, call in steps:
                     if events is not None:
                         s0 = torch.cuda.Event(enable_timing=True)

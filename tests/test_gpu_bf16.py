@@ -191,11 +191,12 @@ def test_bf16_moments_read_equals_plain_screen(case):
         return (ids[:c].cpu().numpy(), sc[:c].cpu().numpy()), _band_of(eng, band)
 
     plain_y = run(y64, "none")
-    write_y = run(y64, "write")
+    whole_y = run(y64, "write_whole")          # the one-call WRITE screen
+    write_y = run(y64, "write")                # images, moments pass, READ screen
     plain_r = run(r2, "none", excl)
     read_r = run(r2, "read", excl)
     read_y = run(y64, "read")
-    for a, b in ((plain_y, write_y), (plain_r, read_r), (plain_y, read_y)):
+    for a, b in ((plain_y, whole_y), (plain_y, write_y), (plain_r, read_r), (plain_y, read_y)):
         (ia, sa), (ba, bsa) = a
         (ib, sb), (bb_, bsb) = b
         assert len(ba) > 0
