@@ -376,7 +376,14 @@ sisso_status sisso_expand_score_bf16(const sisso_space *space, const sisso_score
  *                  as sisso_bf16_screen), SISSO_MOMENTS_WRITE or
  *                  SISSO_MOMENTS_READ.
  * The moments screens size their own grids (args->grid applies to the plain
- * form).
+ * form).  Over a large range the scores are taken in two steps: the best
+ * candidate of every 32 x 32 pair sub-tile of every eighth 64-column u tile
+ * gives a bound tau (their band-th best score, a lower bound of the range's
+ * band-th best), then every candidate scoring at least tau is appended to the
+ * workspace; if more reach tau than the workspace holds, the range is scored
+ * again with per-block band lists (same band, more time).  The environment
+ * variable SISSO_BF16_BOUND_STEP (1 .. 1024, read at each call) replaces the
+ * sampling step 8.
  * A READ screen requires an earlier WRITE screen over the same pools, the same
  * operands (`ops`) and a candidate range covering its own, into the same
  * buffer; any residual, keep, band or exclusion list may differ.  The library

@@ -38,6 +38,7 @@
 // instruction-level parallelism.
 #include "tiles.hpp"
 
+#include <cstdlib>
 #include <type_traits>
 #include <utility>
 
@@ -1158,7 +1159,9 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
 //   2 maxima   the best candidate of each sub-tile (if in the slice and not
 //              excluded) is appended, while room lasts (a lower bound for
 //              mode 1: the band-th best of any set of the slice's candidates
-//              is at most the slice's band-th best).
+//              is at most the slice's band-th best);
+//   3 redo     mode 0 if the workspace's redo flag is set (an append that
+//              overflowed), else nothing.
 // Only u tiles u64_lo + t u64_step (t = 0, 1, ...) below u64_hi are scored.
 constexpr int kScWaves = 16, kScThreads = 64 * kScWaves, kScU = 4;
 
@@ -1172,6 +1175,10 @@ __global__ void __launch_bounds__(kScThreads, 1) k_bf_score_stored(
     unsigned long long *__restrict__ app_cnt, int64_t app_cap)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    if (mode == 3) {
+        if (reinterpret_cast<const WsHeader *>(lws)->redo == 0) return;   // uniform: every thread leaves
+        mode = 0;
+    }
     const bool append = mode != 0;
     float *lsc = (float *)smem;
     int64_t *lid = (int64_t *)(lsc + cap);
@@ -1835,11 +1842,22 @@ __global__ void k_bf_reset(WsHeader *h, int keep, int n_lists, int lists_cap)
 {
     if (threadIdx.x == 0) {
         h->gthr = 0u; h->keep = keep; h->n_lists = n_lists; h->lists_cap = lists_cap; h->status = 0;
-        h->scr_status = 0; h->app = 0ull;
+        h->scr_status = 0; h->app = 0ull; h->redo = 0;
+    }
+}
+
+// After an append pass: if it overflowed app_cap entries, the workspace is
+// reset for a pass in lists and flagged for it (k_bf_score_stored mode 3).
+__global__ void k_bf_redo_reset(WsHeader *h, int keep, int n_lists, int lists_cap, int64_t app_cap)
+{
+    if (threadIdx.x == 0 && h->app > (unsigned long long)app_cap) {
+        h->gthr = 0u; h->keep = keep; h->n_lists = n_lists; h->lists_cap = lists_cap; h->status = 0;
+        h->scr_status = 0; h->app = 0ull; h->redo = 1;
     }
 }
 #else
 __global__ void k_bf_reset(WsHeader *h, int keep, int n_lists, int lists_cap);   // defined in the main build
+__global__ void k_bf_redo_reset(WsHeader *h, int keep, int n_lists, int lists_cap, int64_t app_cap);
 #endif  // SISSO_BF16_MFMA_PART
 
 }  // namespace sisso
@@ -2034,6 +2052,17 @@ int bf_screen_lists(const sisso_space *space, const sisso_score_args *args, int6
 // covering [cand_begin, cand_end) (kBfRead, 128 x 128 block tiles, one block
 // per CU sweeping its share), then their scores from the stored moments and
 // contractions into the band lists (one block per CU).
+// Sampling step of the read pass's bound: every step-th u tile (default 8;
+// SISSO_BF16_BOUND_STEP in the environment, 1 .. 1024, overrides it).  A
+// sparser sample costs less but gives a lower bound, so more candidates are
+// appended.
+inline int64_t bf_bound_step()
+{
+    const char *e = getenv("SISSO_BF16_BOUND_STEP");
+    const long v = e ? strtol(e, nullptr, 10) : 8;
+    return v >= 1 && v <= 1024 ? v : 8;
+}
+
 sisso_status bf_launch_read(const sisso_space *space, const sisso_score_args *args, const BfOps &o, BfWs &w,
                             int32_t band, int64_t cand_begin, int64_t cand_end, const float *mom, float *cst,
                             const h16 *uimg, BfSide side, hipStream_t st)
@@ -2059,12 +2088,15 @@ sisso_status bf_launch_read(const sisso_space *space, const sisso_score_args *ar
                            args->exclude, args->n_exclude, p.ut_lo, p.ut_hi, cand_begin, cand_end, cst, w.vimg,
                            uimg, args->units, side, w.lists, 0, 1, 0, 0);
     }
-    // The scores.  Over a large slice: first the exact band of a sample (every
-    // sixteenth u tile, in lists), whose band-th best score tau is a lower
-    // bound of the slice's band-th best (the sample is part of the slice);
-    // then every candidate at or above tau appended, without lists.  The band
-    // of the appended candidates is the slice's band, whatever the sample.
-    // Over a small slice: lists (every block keeps the whole band).
+    // The scores.  Over a large slice: first the best candidate of every
+    // 32 x 32 sub-tile of a sample of the u tiles (every step-th), whose
+    // band-th best score tau is a lower bound of the slice's band-th best (the
+    // sample is part of the slice); then every candidate at or above tau
+    // appended, without lists.  The band of the appended candidates is the
+    // slice's band, whatever the sample.  If more candidates reach tau than
+    // the workspace holds, the pass is scored again in lists (the redo
+    // kernels do nothing otherwise).  Over a small slice: lists (every block
+    // keeps the whole band).
     const BfPlan q = bf_plan(space, cand_begin, cand_end, grid_max, 64);
     if (q.grid == 0) {
         hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, (WsHeader *)w.lists, bf_block_keep(band), 0,
@@ -2077,7 +2109,7 @@ sisso_status bf_launch_read(const sisso_space *space, const sisso_score_args *ar
     WsHeader *const wh = (WsHeader *)w.lists;
     const size_t smem = (size_t)cap_b * (sizeof(float) + sizeof(int64_t)) + 64 * kScU * (2 * sizeof(float4) + sizeof(uint4));
     if (!allow_dynamic_lds(k_bf_score_stored, smem)) return SISSO_E_UNSUPPORTED;
-    const int64_t n_u = q.ut_hi - q.ut_lo, step = 4;
+    const int64_t n_u = q.ut_hi - q.ut_lo, step = bf_bound_step();
     const int64_t nsub = 4 * ((space->pool[space->levels - 1] + 63) / 64);   // sub-tiles per u tile
     const bool sampled = (n_u / step) * nsub >= (int64_t)4 * band;
     auto score = [&](int grid, int64_t u_step, int mode) {
@@ -2087,7 +2119,7 @@ sisso_status bf_launch_read(const sisso_space *space, const sisso_score_args *ar
                            w.band_sc, w.band_cnt, band, &wh->app, (int64_t)q.grid * keep_b);
     };
     if (sampled) {
-        // tau: the band-th best of the sub-tile maxima of every fourth u tile
+        // tau: the band-th best of the sub-tile maxima of every step-th u tile
         const int64_t n_s = (n_u + step - 1) / step;
         const int g_s = (int)((n_s + kScU - 1) / kScU < grid_max ? (n_s + kScU - 1) / kScU : grid_max);
         for (int pass = 0; pass < 2; ++pass) {
@@ -2102,6 +2134,9 @@ sisso_status bf_launch_read(const sisso_space *space, const sisso_score_args *ar
                 score(q.grid, 1, 1);
             }
         }
+        hipLaunchKernelGGL(k_bf_redo_reset, dim3(1), dim3(64), 0, st, wh, keep_b, q.grid, lcap,
+                           (int64_t)q.grid * keep_b);
+        score(q.grid, 1, 3);
     } else {
         hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, wh, keep_b, q.grid, lcap);
         score(q.grid, 1, 0);

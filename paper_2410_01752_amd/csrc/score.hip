@@ -10,7 +10,8 @@
 // in FP32 over short sample chunks and are carried in FP64.
 //
 // Two kernels cover the space:
-//   k_score_columns  stored pool columns (one wave per column, HBM-bound),
+//   k_score_columns  stored pool columns (one wave per column; bound by the
+//                    VALU work of the unary children),
 //                    plus the one-sided slice's unary block on the newest
 //                    pool level, evaluated while the column streams by;
 //   k_score_rect     the slice's binary block op(u, v): a block owns a tile of
@@ -44,7 +45,7 @@ __global__ void k_ws_append(WsHeader *h, int n_lists)
 // ------------------------------------------------------ pool columns kernel
 
 template <int NU, bool WT>
-__global__ void __launch_bounds__(256) k_score_columns(
+__global__ void __launch_bounds__(256, 3) k_score_columns(
     sisso_space s, int n, const float *__restrict__ pool32, int64_t ld32,
     const sisso_colstat *__restrict__ stats, const float *__restrict__ r32,
     const sisso_resid_info *__restrict__ info, const int64_t *__restrict__ excl, int n_excl,
@@ -77,9 +78,10 @@ __global__ void __launch_bounds__(256) k_score_columns(
     constexpr int NC = (kColWaves * kColBatch * PER + 255) / 256;
 
     // n <= 256 kColRegs: the residual stays in registers and each column is
-    // loaded whole, one column ahead of the one being scored
+    // loaded whole before it is scored (three waves per SIMD overlap one
+    // wave's loads with the others' arithmetic)
     const bool regs = n <= 256 * kColRegs;
-    float4 rv[kColRegs], wv[kColRegs], cur[kColRegs], nxt[kColRegs];
+    float4 rv[kColRegs], wv[kColRegs], cur[kColRegs];
     auto load_col = [&](int64_t c, float4 (&dst)[kColRegs]) {
         const float *col = pool32 + (size_t)c * ld32;
 #pragma unroll
@@ -100,14 +102,13 @@ __global__ void __launch_bounds__(256) k_score_columns(
 
     for (int64_t b0 = (int64_t)blockIdx.x * per_batch; b0 < ncols; b0 += (int64_t)gridDim.x * per_batch) {
         const int64_t cw = c_lo + b0 + w * kColBatch;     // this wave's first column
-        if (regs && cw < c_hi) load_col(cw, cur);
         for (int j = 0; j < kColBatch; ++j) {
             const int slot_base = (w * kColBatch + j) * PER;
             const int64_t c = cw + j;
             float scs[PER];
 #pragma unroll
             for (int o = 0; o < PER; ++o) scs[o] = -1.0f;
-            if (regs && c + 1 < c_hi && j + 1 < kColBatch) load_col(c + 1, nxt);
+            if (regs && c < c_hi) load_col(c, cur);
             if (c < c_hi) {
                 const sisso_colstat st = stats[c];
                 if (regs)
@@ -125,10 +126,6 @@ __global__ void __launch_bounds__(256) k_score_columns(
                     if (!(uid >= id_begin && uid < id_end) || (!dimless && o < nu && unary_needs_dimless(uop[o])))
                         scs[1 + o] = -1.0f;
                 }
-            }
-            if (regs) {
-#pragma unroll
-                for (int k = 0; k < kColRegs; ++k) cur[k] = nxt[k];
             }
             if (lane == 0) {
 #pragma unroll

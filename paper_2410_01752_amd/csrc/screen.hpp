@@ -46,7 +46,8 @@ struct WsHeader {
     int scr_status;         // 0 ok; 3 = a 16-bit screen could not keep every flagged candidate
     int thr_count;          // threshold selection: entries at or above the threshold
     unsigned long long app; // entries appended by a 16-bit scorer in append mode
-    int pad[2];
+    int redo;               // 1: the append overflowed and the pass is scored again in lists
+    int pad;
     unsigned hist[kHistBins];
 };
 

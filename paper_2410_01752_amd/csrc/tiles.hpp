@@ -127,22 +127,26 @@ __device__ __forceinline__ void unary_child_sums(const float4 (&fv)[KR], const f
     }
     au = bu = cu = 0.f;
     bad = false;
+    auto step = [&](float f, float r, float w) {
+        const float h = unary32(OP, f);
+        bad |= !(fabsf(h) <= 1e15f);
+        const float gu = h - shift;
+        const float wgu = WT ? w * gu : gu;
+        au += wgu; bu = fmaf(wgu, gu, bu); cu = fmaf(gu, r, cu);
+    };
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
         const int t = lane * 4 + 256 * k;
-        if (t < n) {
-            const float fa[4] = {fv[k].x, fv[k].y, fv[k].z, fv[k].w};
-            const float ra[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
-            const float wa[4] = {wv[k].x, wv[k].y, wv[k].z, wv[k].w};
+        const float fa[4] = {fv[k].x, fv[k].y, fv[k].z, fv[k].w};
+        const float ra[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
+        const float wa[4] = {wv[k].x, wv[k].y, wv[k].z, wv[k].w};
+        if (t + 3 < n) {            // the lane's four samples all lie below n
+#pragma unroll
+            for (int e = 0; e < 4; ++e) step(fa[e], ra[e], wa[e]);
+        } else if (t < n) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (t + e < n) {
-                    const float h = unary32(OP, fa[e]);
-                    bad |= !(fabsf(h) <= 1e15f);
-                    const float gu = h - shift;
-                    const float wgu = WT ? wa[e] * gu : gu;
-                    au += wgu; bu = fmaf(wgu, gu, bu); cu = fmaf(gu, ra[e], cu);
-                }
+                if (t + e < n) step(fa[e], ra[e], wa[e]);
         }
     }
 }
@@ -163,20 +167,24 @@ __device__ __forceinline__ void score_column_regs(const float4 (&fv)[KR], const 
     for (int o = 0; o < 1 + NU; ++o) scs[o] = -1.0f;
     const float f0 = st.mean;
     float a0 = 0.f, b0s = 0.f, c0 = 0.f;
+    auto step = [&](float f, float r, float w) {
+        const float g = f - f0;
+        const float wg = WT ? w * g : g;
+        a0 += wg; b0s = fmaf(wg, g, b0s); c0 = fmaf(g, r, c0);
+    };
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
         const int t = lane * 4 + 256 * k;
-        if (t < n) {
-            const float fa[4] = {fv[k].x, fv[k].y, fv[k].z, fv[k].w};
-            const float ra[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
-            const float wa[4] = {wv[k].x, wv[k].y, wv[k].z, wv[k].w};
+        const float fa[4] = {fv[k].x, fv[k].y, fv[k].z, fv[k].w};
+        const float ra[4] = {rv[k].x, rv[k].y, rv[k].z, rv[k].w};
+        const float wa[4] = {wv[k].x, wv[k].y, wv[k].z, wv[k].w};
+        if (t + 3 < n) {            // the lane's four samples all lie below n
+#pragma unroll
+            for (int e = 0; e < 4; ++e) step(fa[e], ra[e], wa[e]);
+        } else if (t < n) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (t + e < n) {
-                    const float g = fa[e] - f0;
-                    const float wg = WT ? wa[e] * g : g;
-                    a0 += wg; b0s = fmaf(wg, g, b0s); c0 = fmaf(g, ra[e], c0);
-                }
+                if (t + e < n) step(fa[e], ra[e], wa[e]);
         }
     }
     const double A = wave_sum_dpp((double)a0), B = wave_sum_dpp((double)b0s), C = wave_sum_dpp((double)c0);

@@ -7,6 +7,8 @@ path's score of that id, bit for bit (the band is rescored with the FP32
 kernel's arithmetic).  The FP32 path itself is checked against the oracle in
 test_gpu_parity.py.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -157,6 +159,16 @@ def _band_of(eng, band):
     return ids[order], sc[order]
 
 
+def _redo_flag(eng, band):
+    """1 if the last read screen's append overflowed its workspace and the
+    pass was scored again in lists: the band lists' header follows the band
+    count; its redo flag sits after the 64-bit append counter (byte 48)."""
+    s = eng.space
+    vcols, ucols = int(s.pool[eng.levels - 1]), int(s.pool[eng.levels] - s.pool[eng.levels - 1])
+    o = _a256(vcols * 2 * 16) + _a256(ucols * 8) + _a256(band * 8) + _a256(band * 4) + 256
+    return int(eng._ws["bf16"][o + 56:o + 60].view(torch.int32).item())
+
+
 @pytest.mark.parametrize("case", ["ragged_n300", "persistent_grid", "c3_shape_n2000", "c3_full_block"])
 def test_bf16_moments_read_equals_plain_screen(case):
     """A screen that reads the stored residual-independent moments gives the
@@ -196,7 +208,21 @@ def test_bf16_moments_read_equals_plain_screen(case):
     plain_r = run(r2, "none", excl)
     read_r = run(r2, "read", excl)
     read_y = run(y64, "read")
-    for a, b in ((plain_y, whole_y), (plain_y, write_y), (plain_r, read_r), (plain_y, read_y)):
+    redo_default = _redo_flag(eng, band)
+    # the bound's sampling step: every u tile (the tightest bound), and every
+    # sixteenth (at C3 more candidates reach that bound than the workspace
+    # holds, and the pass is scored again in lists)
+    steps = {}
+    try:
+        for step in ("1", "16"):
+            os.environ["SISSO_BF16_BOUND_STEP"] = step
+            steps[step] = run(y64, "read"), _redo_flag(eng, band)
+    finally:
+        os.environ.pop("SISSO_BF16_BOUND_STEP", None)
+    if case == "c3_full_block":
+        assert redo_default == 0 and steps["1"][1] == 0 and steps["16"][1] == 1
+    for a, b in ((plain_y, whole_y), (plain_y, write_y), (plain_r, read_r), (plain_y, read_y),
+                 (plain_y, steps["1"][0]), (plain_y, steps["16"][0])):
         (ia, sa), (ba, bsa) = a
         (ib, sb), (bb_, bsb) = b
         assert len(ba) > 0
