@@ -157,16 +157,26 @@ def learned_c5(params, args, log):
     return out
 
 
-def batched_fit(log):
+def batched_fit(log, autotune: bool = True):
     """The 64-problem CV / bootstrap batch: one persistent screening launch per step."""
     import torch
     from paper_2410_01752_amd import inputs as I
     from paper_2410_01752_amd.batch import Batch
     ps = I.config4()
+    grid, tuned = 0, None
+    if autotune:
+        from paper_2410_01752_amd import autotune as AT
+        b0 = Batch([(q.X, q.y) for q in ps], ps[0].unary, ps[0].binary, 2)
+        ch = AT.tune_batched(b0, keep=2 * ps[0].k)
+        grid = ch.grid
+        tuned = {"kernel": "k_score_batch", "grid": grid, "ms": ch.ms, "timings_ms": ch.timings}
+        log(f"autotune batched: grid {grid}")
+        del b0
+        torch.cuda.empty_cache()
 
     def step(tm=None):
         b = Batch([(q.X, q.y) for q in ps], ps[0].unary, ps[0].binary, 2)
-        res = b.fit(ps[0].k, ps[0].dmax, timings=tm)
+        res = b.fit(ps[0].k, ps[0].dmax, grid=grid, timings=tm)
         return b, res
 
     step()
@@ -197,7 +207,8 @@ def batched_fit(log):
                          "frac": flops / (kern_ms * 1e-3) / 1e12 / MI355X_FP32_NONPACKED_TFLOPS,
                          "per_unit": f"{BATCH_FLOPS_PER_CAND_SAMPLE} flops per (candidate, sample), "
                                      f"{total} candidates x sum_n={sum_n} per launch"},
-            "rmse_D2": [r[-1].rmse for r in res[:4]]}
+            "rmse_D2": [r[-1].rmse for r in res[:4]],
+            "autotune": tuned}
     log(f"batched: {len(ps)} problems, {wall * 1e3:.1f} ms per step, screen {kern_ms:.2f} ms per launch")
     return info
 
@@ -430,14 +441,18 @@ def main():
         learned_params, forms["learned_training"] = train_proposal(args, log)
 
     # ---- autotuned launch shape of the slice kernel for the chosen form
-    tile, grid, tuned = args.tile, args.grid, None
+    tile, grid, col_grid, tuned = args.tile, args.grid, 0, None
     if p.rect and prec in ("fp32", "bf16") and not args.no_autotune and not (args.tile or args.grid):
         from paper_2410_01752_amd import autotune as AT
         eng = Engine(p.X, p.y, p.unary, p.binary, p.rung, p.rect)
         ch = AT.tune_engine(eng, form=prec, keep=keep0, band=band, sample_tiles=1024)
         tile, grid = ch.tile, ch.grid
-        tuned = {"tile": tile, "grid": grid, "sample_ms": ch.ms, "timings_ms": ch.timings}
-        log(f"autotune {prec}: tile {tile} grid {grid}")
+        cc = AT.tune_columns(eng, keep=keep0)
+        col_grid = cc.grid
+        tuned = {"tile": tile, "grid": grid, "sample_ms": ch.ms, "timings_ms": ch.timings,
+                 "columns": {"kernel": "k_score_columns", "col_grid": col_grid, "ms": cc.ms,
+                             "timings_ms": cc.timings}}
+        log(f"autotune {prec}: tile {tile} grid {grid}; stored columns: col_grid {col_grid}")
         del eng
         torch.cuda.empty_cache()
 
@@ -447,6 +462,7 @@ def main():
             from paper_2410_01752_amd import learned as LN
             eng.set_pruner(LN.Pruner(eng, learned_params), frac=args.learned_frac, n_sample=1 << 20, seed=3,
                            fallback=args.learned_fallback)
+        eng.col_grid = col_grid
         res = eng.fit(p.k, p.dmax, keep0=keep0, grid=grid, tile=tile, timings=timings,
                       precision=prec, band=band)
         return eng, res
@@ -596,7 +612,7 @@ def main():
                 "keep": [r.keep for r in last]},
     }
     if not args.no_batched:
-        out["batched"] = batched_fit(log)
+        out["batched"] = batched_fit(log, autotune=not args.no_autotune)
     if args.c5:
         if learned_params is None:
             learned_params, forms["learned_training"] = train_proposal(args, log)

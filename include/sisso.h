@@ -254,7 +254,7 @@ typedef struct {
     int32_t precision;            /* SISSO_FP32 (SISSO_BF16: see below)          */
     int32_t grid;                 /* persistent blocks of the binary block's
                                      kernels, 0 = default (the stored-column pass
-                                     always uses its own default)                */
+                                     takes col_grid)                             */
     int32_t tile;                 /* tile-shape variant, 0 = default             */
     int32_t list_base;            /* first list slot this call writes: 0 starts a
                                      new pass (resets the workspace); > 0 appends
@@ -268,6 +268,8 @@ typedef struct {
                                      sisso_pool_units: slice candidates that
                                      break dimensional analysis are invalid.
                                      FP32 and 16-bit screening forms only       */
+    int32_t col_grid;             /* blocks of the stored-column pass, 0 =
+                                     default (2048), at most 16384              */
 } sisso_score_args;
 
 /* Workspace of a screening pass: per-block candidate lists plus a header.

@@ -53,7 +53,8 @@ class ScoreArgs(ctypes.Structure):
                 ("exclude", ctypes.c_void_p), ("n_exclude", ctypes.c_int32),
                 ("keep", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("list_base", ctypes.c_int32), ("w32", ctypes.c_void_p), ("units", ctypes.c_void_p)]
+                ("list_base", ctypes.c_int32), ("w32", ctypes.c_void_p), ("units", ctypes.c_void_p),
+                ("col_grid", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):

@@ -1,12 +1,19 @@
 """Autotuner of the screening kernels' launch shapes.
 
-For a kernel (the FP32 slice kernel or the BF16-MFMA slice kernel), a
-screening form and a bucket of sample counts n, it times each candidate
-launch shape -- tile variant and persistent grid size -- on a sample of the
-real workload (a contiguous block of operand tiles of the rung-3 slice, so
-the timed work is the production work) with HIP events on the stream the
-kernel runs on, and keeps the fastest.  Choices are cached in a JSON file
-keyed by (GPU architecture, HIP runtime version, kernel, form, n bucket).
+For a kernel, a screening form and a bucket of sample counts n, it times each
+candidate launch shape on the real workload with HIP events on the stream the
+kernel runs on, and keeps the fastest:
+  * the FP32 slice kernel (k_score_rect): register-tile variant x persistent
+    grid, on a contiguous block of operand tiles of the rung-3 slice;
+  * the plain 16-bit slice kernel (k_score_rect_bf16): persistent grid;
+  * the stored-column pass (k_score_columns): its block count (col_grid), on
+    the stored pools and the unary slice;
+  * the batched persistent kernel (k_score_batch): its grid, on one screening
+    call over every problem of the batch (keyed also by the batch size).
+Choices are cached in a JSON file keyed by (GPU architecture, HIP runtime
+version, kernel, form, n bucket).  The moments pass and the read pass of the
+16-bit form size their grids from the CU count, and their tile shapes,
+waves per block and K-chunk are compile-time constants of their kernels.
 
 Launch shapes never change results: every block keeps its best K' by
 (score desc, id asc) and the merge is exact, so any shape returns the same
@@ -25,6 +32,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sisso_mi355x", 
 # candidate launch shapes per kernel: (tile variant, grid); grid 0 = library default
 FP32_SHAPES: List[Tuple[int, int]] = [(t, g) for t in (0, 1, 2) for g in (0, 256, 512, 768)]
 BF16_SHAPES: List[Tuple[int, int]] = [(0, g) for g in (0, 256, 512, 768)]
+COL_SHAPES: List[Tuple[int, int]] = [(0, g) for g in (0, 1024, 4096, 8192)]
+BATCH_SHAPES: List[Tuple[int, int]] = [(0, g) for g in (0, 256, 512, 1024, 2048)]
 
 
 def n_bucket(n: int) -> str:
@@ -126,3 +135,74 @@ def tune_engine(eng, form: str = "fp32", keep: int = 1024, band: int = 2048, sam
                     {f"tile{t}_grid{g}": ms for (t, g), ms in timings.items()})
     cache.put(key, choice)
     return choice
+
+
+def _time_shapes(shapes, run, repeats: int) -> Dict[Tuple[int, int], float]:
+    """Best of `repeats` timings (ms) of run(tile, grid) per shape."""
+    timings: Dict[Tuple[int, int], float] = {}
+    for tile, grid in shapes:
+        timings[(tile, grid)] = min(run(tile, grid) for _ in range(repeats))
+    return timings
+
+
+def _choice(cache: Cache, key: str, timings: Dict[Tuple[int, int], float]) -> Choice:
+    tile, grid = pick(timings)
+    choice = Choice(tile, grid, timings[(tile, grid)],
+                    {f"tile{t}_grid{g}": ms for (t, g), ms in timings.items()})
+    cache.put(key, choice)
+    return choice
+
+
+def tune_columns(eng, keep: int = 1024, cache: Optional[Cache] = None, force: bool = False,
+                 shapes: Optional[Sequence] = None, repeats: int = 2) -> Choice:
+    """Tune the stored-column pass of an Engine (its block count, col_grid):
+    times the screen of the stored pools and the unary slice against y, and
+    sets eng.col_grid to the choice."""
+    import torch
+    cache = cache or Cache()
+    arch, rt = device_key()
+    key = cache_key(arch, rt, "k_score_columns", "fp32", eng.n)
+    hit = None if force else cache.get(key)
+    if hit is None:
+        end = eng.binary_base()
+        saved = eng.col_grid
+
+        def run(tile, grid):
+            eng.col_grid = grid
+            ev = {}
+            eng.screen(eng.y, keep, None, begin=0, end=end, events=ev)
+            torch.cuda.synchronize()
+            return sum(a.elapsed_time(b) for a, b in ev["pool"])
+        try:
+            hit = _choice(cache, key, _time_shapes(list(shapes or COL_SHAPES), run, repeats))
+        finally:
+            eng.col_grid = saved
+    eng.col_grid = hit.grid
+    return hit
+
+
+def tune_batched(batch, keep: int = 100, cache: Optional[Cache] = None, force: bool = False,
+                 shapes: Optional[Sequence] = None, repeats: int = 2) -> Choice:
+    """Tune the batched persistent kernel for a Batch (its grid): times one
+    screening call over every problem against its y, and sets batch.grid to
+    the choice (Batch.fit takes it)."""
+    import torch
+    cache = cache or Cache()
+    arch, rt = device_key()
+    P = batch.P
+    pb = 1
+    while pb < P:
+        pb *= 2
+    key = cache_key(arch, rt, "k_score_batch", f"fp32_P<={pb}", max(batch.n))
+    hit = None if force else cache.get(key)
+    if hit is None:
+        which = list(range(P))
+
+        def run(tile, grid):
+            ev = {}
+            batch.screen(which, [batch.y[p] for p in which], [keep] * P, grid=grid, events=ev)
+            torch.cuda.synchronize()
+            return sum(a.elapsed_time(b) for a, b in ev["batch_screen"])
+        hit = _choice(cache, key, _time_shapes(list(shapes or BATCH_SHAPES), run, repeats))
+    batch.grid = hit.grid
+    return hit

@@ -39,6 +39,7 @@ class Batch:
         self.store = L.make_space(d, list(unary), list(binary), levels - 1, False)
         self.levels, self.d = levels, d
         self.P = len(problems)
+        self.grid = 0               # persistent blocks of the screening kernel (0: the library's default)
         p1 = int(self.store.pool[1])
         st = L.stream_handle(self.dev)
         self.n: List[int] = []
@@ -151,9 +152,13 @@ class Batch:
                                                      L.stream_handle(self.dev)), "sisso_materialize_ids_stored")
         return out.view(count, n), valid
 
-    def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10, grid: int = 0,
-            timings: Optional[dict] = None) -> List[List[StepResult]]:
-        """SISSO (Sec. 2.3) for every problem; result[p][t-1] as Engine.fit."""
+    def fit(self, k: int, dmax: int, keep0: Optional[int] = None, singular_tol: float = 1e-10,
+            grid: Optional[int] = None, timings: Optional[dict] = None) -> List[List[StepResult]]:
+        """SISSO (Sec. 2.3) for every problem; result[p][t-1] as Engine.fit.
+        grid: persistent blocks of the batched screening kernel (None: the
+        batch's `grid`, which autotune.tune_batched sets; 0: the library's
+        default)."""
+        grid = self.grid if grid is None else grid
         keep0 = min(2 * k if keep0 is None else keep0, L.MAX_KEEP)
         if dmax < 1 or dmax > L.MAX_D or k * dmax > L.MAX_SUBSPACE:
             raise L.SissoError("dmax or k out of range")

@@ -343,7 +343,7 @@ namespace {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-constexpr int kMaxColGrid = 2048;
+constexpr int kColGrid = 2048, kMaxColGrid = 16384;
 constexpr int kMaxRectGrid = 1024;
 
 struct Plan {
@@ -355,9 +355,9 @@ struct Plan {
 
 int rect_tu(int ru) { return 16 * ru; }
 
-// The stored-column pass is HBM-bound with its own launch shape; the grid
+// The stored-column pass has its own launch shape (col_grid); the grid
 // argument tunes the binary block's kernels only.
-int max_col_grid(const sisso_score_args *) { return kMaxColGrid; }
+int max_col_grid(const sisso_score_args *a) { return a->col_grid > 0 ? a->col_grid : kColGrid; }
 int max_rect_grid(const sisso_score_args *a) { return a->grid > 0 ? a->grid : kMaxRectGrid; }
 
 void tile_shape(const sisso_score_args *a, int *ru, int *rv)
@@ -456,7 +456,9 @@ bool ws_begin_call(void *ws, int keep, int base, int lists_this_call, int lists_
 
 extern "C" size_t sisso_score_workspace_size(const sisso_space *space, const sisso_score_args *args)
 {
-    if (!space || !args || args->keep < 1 || args->keep > SISSO_MAX_KEEP || space->total <= 0) return 0;
+    if (!space || !args || args->keep < 1 || args->keep > SISSO_MAX_KEEP || space->total <= 0 ||
+        args->col_grid < 0 || args->col_grid > kMaxColGrid)
+        return 0;
     return ws_bytes_for(lists_capacity(space, args), args->keep);
 }
 
@@ -464,7 +466,8 @@ extern "C" int32_t sisso_expand_score_lists(const sisso_space *space, const siss
                                             int64_t cand_begin, int64_t cand_end)
 {
     if (!space || !args || space->total <= 0 || cand_begin < 0 || cand_end > space->total ||
-        cand_begin >= cand_end || args->tile < 0 || args->tile > 2 || args->grid < 0)
+        cand_begin >= cand_end || args->tile < 0 || args->tile > 2 || args->grid < 0 ||
+        args->col_grid < 0 || args->col_grid > kMaxColGrid)
         return -1;
     const Plan p = make_plan(space, args, cand_begin, cand_end);
     return p.g_cols + p.g_rect;
@@ -492,7 +495,8 @@ extern "C" sisso_status sisso_expand_score(const sisso_space *space, const sisso
     if (args->keep < 1 || args->keep > SISSO_MAX_KEEP) return SISSO_E_RANGE;
     if (cand_begin < 0 || cand_end > space->total || cand_begin >= cand_end) return SISSO_E_RANGE;
     if (args->precision != SISSO_FP32) return SISSO_E_UNSUPPORTED;
-    if (args->tile < 0 || args->tile > 2 || args->grid < 0) return SISSO_E_RANGE;
+    if (args->tile < 0 || args->tile > 2 || args->grid < 0 || args->col_grid < 0 || args->col_grid > kMaxColGrid)
+        return SISSO_E_RANGE;
     const int lists = lists_capacity(space, args);
     if (ws_bytes < ws_bytes_for(lists, args->keep)) return SISSO_E_WORKSPACE;
     if (space->rect && space->pool[space->levels - 1] < 1) return SISSO_E_SHAPE;

@@ -89,6 +89,7 @@ class Engine:
             torch.cuda.synchronize(self.dev)          # bu is released on return
         self.bf16_ops: Optional[torch.Tensor] = None
         self.bf16_moments: Optional[torch.Tensor] = None
+        self.col_grid = 0           # blocks of the stored-column pass (0: the library's default)
         self.tk_status = torch.zeros(1, dtype=torch.int32, device=self.dev)
         self.r32 = torch.zeros(self.ld32, dtype=torch.float32, device=self.dev)
         self.info = torch.zeros(L.RESID_DOUBLES, dtype=torch.float64, device=self.dev)
@@ -151,6 +152,7 @@ class Engine:
         a.keep, a.precision, a.grid, a.tile = keep, precision, grid, tile
         a.w32 = L.ptr(self.w32) if self.w32 is not None else None
         a.units = L.ptr(self.units) if self.units is not None else None
+        a.col_grid = self.col_grid
         return a
 
     def binary_base(self) -> int:

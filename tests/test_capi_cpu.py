@@ -103,6 +103,15 @@ def test_argument_errors_before_launch():
     assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 0, 10, fake, ws, None) == 3
     a.keep, a.precision = 40, 7
     assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 0, 10, fake, ws, None) == 5
+    a.precision = 0
+    for bad in (-1, 16385):                      # the stored-column pass's block count
+        a.col_grid = bad
+        assert lib.sisso_score_workspace_size(ctypes.byref(s), ctypes.byref(a)) == 0
+        assert lib.sisso_expand_score(ctypes.byref(s), ctypes.byref(a), 0, 10, fake, ws, None) == 3
+        assert lib.sisso_expand_score_lists(ctypes.byref(s), ctypes.byref(a), 0, 10) == -1
+    a.col_grid = 16384
+    assert lib.sisso_score_workspace_size(ctypes.byref(s), ctypes.byref(a)) >= ws
+    a.col_grid = 0
     assert lib.sisso_topk(fake, ws, 0, fake, fake, fake, None) == 3
     assert lib.sisso_subspace_update(fake, 50, fake, fake, fake, 40, fake, 50, fake, 50, fake, 1020, 20,
                                      fake, fake, fake, 1 << 30, None) == 2             # m_prev + k > 1024

@@ -149,6 +149,31 @@ def test_batched_c4_fit_matches_oracle_on_sampled_problems():
         assert res[j][1].rmse <= res[j][0].rmse
 
 
+def test_autotuned_batched_grid_gives_default_lists(tmp_path):
+    """The batched kernel's tuned grid returns the default grid's lists bit
+    for bit, and the default lists match the oracle's; a fit with the tuned
+    grid (Batch.fit takes batch.grid) equals the oracle's fits."""
+    from paper_2410_01752_amd import autotune as A
+    ps = _tiny_batch([61, 62, 63, 64, 65, 66], [48, 130, 77, 256, 101, 190])
+    print("[batched] autotuned grid, 6 tiny problems", flush=True)
+    b = _batch(ps)
+    cache = A.Cache(str(tmp_path / "at.json"))
+    ch = A.tune_batched(b, keep=300, cache=cache, shapes=[(0, g) for g in (0, 3, 64, 512)])
+    assert b.grid == ch.grid and len(ch.timings) == 4
+    assert cache.get(A.cache_key(*A.device_key(), "k_score_batch", "fp32_P<=8", 256)) is not None
+    default = _screen(b, 300, grid=0)
+    tuned = _screen(b, 300, grid=ch.grid)
+    for (di, ds), (ti, ts) in zip(default, tuned):
+        assert np.array_equal(di, ti) and np.array_equal(ds, ts)
+    for p, (gi, gs) in zip(ps, default):
+        sp = O.Space(p.X.shape[1], p.unary, p.binary, 2)
+        oi, os_ = sp.sis(p.X, p.y, 300)
+        assert_topk_parity(sp, p.X, p.y, gi, gs, oi, os_, 300)
+    res = b.fit(8, 2)
+    for p, rg in zip(ps, res):
+        _compare_fit(p, rg, O.fit(p.X, p.y, p.unary, p.binary, 2, False, 8, 2))
+
+
 @pytest.mark.parametrize("D", [1, 2, 3])
 def test_l0_search_batched_equals_single_problem_calls(D):
     """sisso_l0_search_batched runs the single-problem SO bodies over a table:

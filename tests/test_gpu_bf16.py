@@ -136,6 +136,20 @@ def test_autotuned_shapes_give_identical_results(tmp_path):
         b = eng.screen(r64, 300, None, precision=form, band=1200, tile=ch.tile, grid=ch.grid)
         torch.cuda.synchronize()
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # the stored-column pass: its tuned block count gives the default list
+    r64 = torch.as_tensor(p.y, dtype=torch.float64, device=eng.dev)
+    bb = eng.binary_base()
+    a = eng.screen(r64, 300, None, begin=0, end=bb)
+    torch.cuda.synchronize()
+    a = (a[0].clone(), a[1].clone())
+    cc = A.tune_columns(eng, keep=300, cache=cache, shapes=[(0, g) for g in (0, 1, 7, 4096)])
+    assert eng.col_grid == cc.grid and len(cc.timings) == 4
+    for g in (1, 7, 4096):
+        eng.col_grid = g
+        b = eng.screen(r64, 300, None, begin=0, end=bb)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    eng.col_grid = 0
 
 
 def _a256(x):
