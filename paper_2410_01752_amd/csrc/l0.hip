@@ -165,24 +165,74 @@ __device__ __forceinline__ void gram_tile(int t, int &bi, int &bj)
     bj = t - b * (b + 1) / 2;
 }
 
-// Split Gram, one block per (tile, part of the samples): the part's dot
-// products of the tile into its slot of the partial buffer.
-__device__ inline void l0_gram_part(int m, int n, L0Ws w, int split, int t, int sp)
+// Split Gram: one block per lower-triangle 64 x 64 tile and part of the
+// samples writes the part's dot products into the partial slots of the
+// tile's 32 x 32 tiles (those above the diagonal of a diagonal 64 x 64 tile
+// are not stored); each thread computes a 4 x 4 block of dot products.  Every
+// dot product takes the part's samples in order, one fma each from 0.0, as
+// gemm_tile_tn_range does, so the sums equal those of l0_gram bit for bit.
+constexpr int kGT4 = 2 * kGT;
+__host__ __device__ inline int l0_gram_tiles64(int m) { const int t = (m + kGT4 - 1) / kGT4; return t * (t + 1) / 2; }
+__device__ inline void l0_gram_part64(int m, int n, L0Ws w, int split, int T, int sp)
 {
-    __shared__ double As[kGK][kGT + 1];
-    __shared__ double Bs[kGK][kGT + 1];
-    int bi, bj;
-    gram_tile(t, bi, bj);
+    constexpr int KK = 16;
+    __shared__ __attribute__((aligned(16))) double As[KK][kGT4 + 2];
+    __shared__ __attribute__((aligned(16))) double Bs[KK][kGT4 + 2];
+    int BI, BJ;
+    gram_tile(T, BI, BJ);
     const int chunk = ((n + split - 1) / split + kGK - 1) / kGK * kGK;
-    const int k0 = sp * chunk, k1 = k0 + chunk < n ? k0 + chunk : n;
-    double acc[2][2];
-    gemm_tile_tn_range(w.Z, m, w.Z, m, k0, k1, w.ldz, bi, bj, acc, As, Bs);
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double *out = w.part + ((size_t)t * split + sp) * (kGT * kGT);
+    const int kb = sp * chunk, ke = kb + chunk < n ? kb + chunk : n;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    constexpr int Q = KK * kGT4 / 256;              // values of each operand per thread and chunk
+    double acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) out[(ty * 2 + a) * kGT + tx * 2 + b] = acc[a][b];
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    double ra[Q], rb[Q];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = tid + 256 * q, c = e / KK, t = e % KK;
+            const int ia = BI * kGT4 + c, ib = BJ * kGT4 + c;
+            ra[q] = (ia < m && k0 + t < ke) ? w.Z[(size_t)ia * w.ldz + k0 + t] : 0.0;
+            rb[q] = (ib < m && k0 + t < ke) ? w.Z[(size_t)ib * w.ldz + k0 + t] : 0.0;
+        }
+    };
+    load(kb);
+    for (int k0 = kb; k0 < ke; k0 += KK) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = tid + 256 * q, c = e / KK, t = e % KK;
+            As[t][c] = ra[q];
+            Bs[t][c] = rb[q];
+        }
+        __syncthreads();
+        if (k0 + KK < ke) load(k0 + KK);             // the next chunk's loads overlap this chunk's products
+#pragma unroll
+        for (int t = 0; t < KK; ++t) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) { av[a] = As[t][ty * 4 + a]; bv[a] = Bs[t][tx * 4 + a]; }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+    const int nt = (m + kGT - 1) / kGT;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = BI * kGT4 + ty * 4 + a, j = BJ * kGT4 + tx * 4 + b;
+            const int bi = i / kGT, bj = j / kGT;
+            if (bi < nt && bj <= bi) {
+                const int t32 = bi * (bi + 1) / 2 + bj;
+                w.part[((size_t)t32 * split + sp) * (kGT * kGT) + (i % kGT) * kGT + j % kGT] = acc[a][b];
+            }
+        }
 }
 
 // The parts of each tile summed in their order into the symmetric Gram (unit
@@ -272,7 +322,9 @@ __device__ inline void block_min_to(unsigned long long mine, unsigned long long 
     if (threadIdx.x == 0) {
         unsigned long long v = red64[0];
         for (int q = 1; q < (int)(blockDim.x >> 6); ++q) v = red64[q] < v ? red64[q] : v;
-        atomicMin(dst, v);
+        // most blocks hold no improvement by the time they finish: they
+        // leave the shared minimum alone (fewer atomics on one address)
+        if (v < __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(dst, v);
         if (skipped && skip_s) atomicAdd(skipped, skip_s);
     }
 }
@@ -594,12 +646,12 @@ __global__ void __launch_bounds__(256) k_l0_columns(const double *__restrict__ F
     l0_column(F, ld, n, w, blockIdx.x);
 }
 
-__global__ void __launch_bounds__(256) k_l0_gram_part(int m, int n, L0Ws w, int split)
-{
-    l0_gram_part(m, n, w, split, blockIdx.x, blockIdx.y);
-}
 
 __global__ void __launch_bounds__(256) k_l0_gram_sum(int m, L0Ws w, int split) { l0_gram_sum(m, w, split, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_l0_gram_part64(int m, int n, L0Ws w, int split)
+{
+    l0_gram_part64(m, n, w, split, blockIdx.x, blockIdx.y);
+}
 
 template <int D, int PASS>
 __global__ void __launch_bounds__(256) k_l0_enum(int m, double tol, L0Ws w)
@@ -710,7 +762,7 @@ extern "C" sisso_status sisso_l0_search_weighted(const double *F, int32_t m, int
     hipLaunchKernelGGL(k_l0_y, dim3(1), dim3(256), 0, st, y, n, w);
     hipLaunchKernelGGL(k_l0_columns, dim3(m), dim3(256), 0, st, F, ld, n, w);
     const int split = l0_gram_split(m, n), gtiles = l0_gram_tiles(m);
-    hipLaunchKernelGGL(k_l0_gram_part, dim3(gtiles, split), dim3(256), 0, st, m, n, w, split);
+    hipLaunchKernelGGL(k_l0_gram_part64, dim3(l0_gram_tiles64(m), split), dim3(256), 0, st, m, n, w, split);
     hipLaunchKernelGGL(k_l0_gram_sum, dim3(gtiles), dim3(256), 0, st, m, w, split);
     const int64_t npairs = (int64_t)m * (m - 1) / 2;
     if (D == 1) {
@@ -722,7 +774,9 @@ extern "C" sisso_status sisso_l0_search_weighted(const double *F, int32_t m, int
         hipLaunchKernelGGL(k_l0_pairs2<1>, dim3(g), dim3(256), 0, st, m, singular_tol, w);
     } else {
         const int64_t items = l0_items3(m);
-        const unsigned g = (unsigned)((items + 3) / 4 < 8192 ? (items + 3) / 4 : 8192);
+        // both passes over the items in 2048 persistent blocks (the tie pass
+        // revisits only the few items whose minimum lies within the band)
+        const unsigned g = (unsigned)((items + 3) / 4 < 2048 ? (items + 3) / 4 : 2048);
         hipLaunchKernelGGL(k_l0_cols3<0>, dim3(g), dim3(256), 0, st, m, singular_tol, w);
         hipLaunchKernelGGL(k_l0_cols3<1>, dim3(g), dim3(256), 0, st, m, singular_tol, w);
     }
