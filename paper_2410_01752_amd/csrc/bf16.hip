@@ -1755,22 +1755,27 @@ __device__ inline float score_slice_id_wave(const sisso_space &s, const FormSlot
     const float *cu = pool32 + (size_t)u * ld32, *cv = pool32 + (size_t)v * ld32;
     const float cm = ust.mean * vst.mean, c3 = ust.mean * vst.mean_rcp, c4 = vst.mean * ust.mean_rcp;
     float fA = 0.f, fB = 0.f, fC = 0.f;
+    auto step = [&](float ur, float vr, float r) {
+        const float g = binary_form(k, ur, ur - ust.mean, __builtin_amdgcn_rcpf(ur), vr, vr - vst.mean,
+                                    __builtin_amdgcn_rcpf(vr), cm, c3, c4);
+        fA += g;
+        fB = fmaf(g, g, fB);
+        fC = fmaf(g, r, fC);
+    };
     for (int t = lane * 4; t < n; t += 256) {     // 16-byte loads: samples t .. t + 3
         const float4 a4 = *reinterpret_cast<const float4 *>(cu + t);
         const float4 b4 = *reinterpret_cast<const float4 *>(cv + t);
         const float4 r4 = *reinterpret_cast<const float4 *>(r32 + t);
         const float ua[4] = {a4.x, a4.y, a4.z, a4.w}, va[4] = {b4.x, b4.y, b4.z, b4.w};
         const float ra[4] = {r4.x, r4.y, r4.z, r4.w};
+        if (t + 3 < n) {                           // the lane's four samples all lie below n
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (t + e < n) {
-                const float ur = ua[e], vr = va[e];
-                const float g = binary_form(k, ur, ur - ust.mean, __builtin_amdgcn_rcpf(ur), vr, vr - vst.mean,
-                                            __builtin_amdgcn_rcpf(vr), cm, c3, c4);
-                fA += g;
-                fB = fmaf(g, g, fB);
-                fC = fmaf(g, ra[e], fC);
-            }
+            for (int e = 0; e < 4; ++e) step(ua[e], va[e], ra[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < n) step(ua[e], va[e], ra[e]);
+        }
     }
     const double A = wave_sum_dpp((double)fA), B = wave_sum_dpp((double)fB), C = wave_sum_dpp((double)fC);
     const double shifts[5] = {(double)ust.mean + (double)vst.mean, (double)ust.mean - (double)vst.mean,
@@ -1811,7 +1816,10 @@ __global__ void __launch_bounds__(256) k_bf_side(sisso_space s, FormSlots fs, in
         float sc = -1.0f;
         int64_t id = INT64_MAX;
         if (e < cnt) {
-            id = side.ids[e];
+            // one id per wave: decoded on the scalar unit
+            const int64_t raw = side.ids[e];
+            id = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(raw >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)raw));
             if (id >= id_begin && id < id_end && (n_excl == 0 || !in_sorted_ids(excl, n_excl, id)))
                 sc = score_slice_id_wave(s, fs, n, pool32, ld32, stats, r32, nd, R1, Srr, id);
         }
