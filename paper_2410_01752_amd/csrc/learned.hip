@@ -357,18 +357,33 @@ __global__ void __launch_bounds__(256) k_mlp_colsums(const float *__restrict__ Z
 {
     const int j = threadIdx.x;
     const float *dz = mlp_dz(ws, batch), *ds = mlp_ds(ws);
-    double sb = 0.0, sw = 0.0;
-    for (int i = 0; i < batch; ++i) {
+    double sb = 0.0, sw = 0.0, s2 = 0.0;
+    // the rows in order; each group's loads are issued before its sums
+    constexpr int U = 16;
+    int i = 0;
+    for (; i + U <= batch; i += U) {
+        float a[U], b[U], c[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            a[q] = dz[(size_t)(i + q) * kH + j];
+            b[q] = ds[i + q];
+            c[q] = Z[(size_t)(i + q) * kH + j];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            sb += (double)a[q];
+            sw += (double)b[q] * (double)fmaxf(c[q], 0.f);
+            s2 += (double)b[q];
+        }
+    }
+    for (; i < batch; ++i) {
         sb += (double)dz[(size_t)i * kH + j];
         sw += (double)ds[i] * (double)fmaxf(Z[(size_t)i * kH + j], 0.f);
+        s2 += (double)ds[i];
     }
     G[kOffB1 + j] = (float)sb;
     G[kOffW2 + j] = (float)sw;
-    if (j == 0) {
-        double s2 = 0.0;
-        for (int i = 0; i < batch; ++i) s2 += (double)ds[i];
-        G[kOffB2] = (float)s2;
-    }
+    if (j == 0) G[kOffB2] = (float)s2;
 }
 
 // Adam with bias-corrected moments (element per thread).
