@@ -1146,11 +1146,12 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
 // The second kernel of a pass that reads the moments: the five forms of every
 // pair from the stored moments and the pass's three residual contractions
 // (written by kBfRead), through bf_forms as the plain form scores them.  No
-// accumulators are held, so a block of sixteen waves (four per SIMD) hides
-// the loads' latency.  A block stages the row constants of kScU 64-column u
-// tiles in LDS, then each wave takes 32 x 32 sub-tiles of them.  Three modes:
+// accumulators are held; a block of eight waves (two per SIMD: at four per
+// SIMD the 128-register budget spills) keeps several rows' loads in flight
+// per wave.  A block stages the row constants of kScU 64-column u tiles in
+// LDS, then each wave takes 32 x 32 sub-tiles of them.  Modes:
 //   0 lists    every block keeps its best `keep` candidates in its LDS list
-//              (rounds of sixteen sub-tiles, one per wave, then bf_admit), as
+//              (rounds of kScWaves sub-tiles, one per wave, then bf_admit), as
 //              the plain form does;
 //   1 append   every candidate at or above a bound tau (read from the device:
 //              tau_sc[tau_k - 1] when tau_cnt >= tau_k, else 0) is appended to
@@ -1163,7 +1164,7 @@ __global__ void __launch_bounds__(BfShape<MODE>::kThreads, BfShape<MODE>::kMinBl
 //   3 redo     mode 0 if the workspace's redo flag is set (an append that
 //              overflowed), else nothing.
 // Only u tiles u64_lo + t u64_step (t = 0, 1, ...) below u64_hi are scored.
-constexpr int kScWaves = 16, kScThreads = 64 * kScWaves, kScU = 4;
+constexpr int kScWaves = 8, kScThreads = 64 * kScWaves, kScU = 4;
 
 __global__ void __launch_bounds__(kScThreads, 1) k_bf_score_stored(
     sisso_space s, FormSlots fs, int n, const float4 *__restrict__ usum, const float4 *__restrict__ vsum,
