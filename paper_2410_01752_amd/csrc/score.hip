@@ -245,7 +245,11 @@ __global__ void __launch_bounds__(256) k_tk_hist(void *ws, int pass)
 
 __global__ void k_tk_select(WsHeader *h, int pass)
 {
-    // single thread scan from the top bin; then clear the histogram
+    // the histogram into LDS (coalesced), a single-thread scan from the top
+    // bin there; then clear the histogram
+    __shared__ unsigned hs[kHistBins];
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) hs[i] = h->hist[i];
+    __syncthreads();
     if (threadIdx.x == 0) {
         const int bins = pass == 2 ? 256 : kHistBins;
         const int shift = pass == 0 ? 20 : (pass == 1 ? 8 : 0);
@@ -255,7 +259,7 @@ __global__ void k_tk_select(WsHeader *h, int pass)
         } else if (need > 0) {
             int b = bins - 1;
             for (; b > 0; --b) {
-                const int c = (int)h->hist[b];
+                const int c = (int)hs[b];
                 if (c >= need) break;
                 need -= c;
             }
